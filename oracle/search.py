@@ -1,0 +1,263 @@
+"""Greedy graph search on primary vectors, then re-ranking with secondaries.
+
+Follows Section 2 ("Search"): primary vectors quant(Bx) drive the graph
+traversal with the approximation <q, x> ~ <Aq, quant(Bx)> (Eq. 1); more than
+k candidates are kept and their inner products are recomputed with the
+secondary vectors, whose top-k is returned.  Appendix C names the traversal
+"greedy traversal with backtracking"; the reading used here is the
+best-first beam with window L:
+
+  list <- [(s(entry), entry)], visited <- {entry}
+  repeat: p <- best not-yet-expanded entry of the list under the total
+          order (score descending, id ascending); stop if there is none;
+          mark p expanded; for each out-neighbour n of p not visited yet:
+          mark visited, compute s(n), insert into the list and keep the
+          best L entries.
+  re-rank: s2(n) = <q, secondary(n)> for every entry of the final list;
+           return the best k under (s2 descending, id ascending).
+
+Scores are float64.  The primary score is the plain definition
+<q', y^_n> with y^_n the LVQ reconstruction (mu + lo + delta * c).
+
+Pinned by: brute force when L >= N on a connected graph, the exhaustive
+"flat" variant, and the top-L-of-visited invariant (tests/test_oracle_search.py).
+"""
+from __future__ import annotations
+
+import bisect
+import os
+import tempfile
+from dataclasses import dataclass
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+SENTINEL = 0xFFFFFFFF
+
+
+@dataclass
+class Index:
+    """Everything the search reads; arrays may be numpy memmaps."""
+
+    adj: np.ndarray        # uint32 [N, R]
+    entry: int
+    codes: np.ndarray      # uint8 [N, d]   (one code per component)
+    delta: np.ndarray      # float32 [N]
+    lo: np.ndarray         # float32 [N]
+    mu: np.ndarray         # float32 [d]
+    sec: np.ndarray        # float16 or float32 [N, D]
+
+    @property
+    def N(self) -> int:
+        return self.adj.shape[0]
+
+
+def rowdot(M: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Row-wise inner products in float64 with one fixed summation tree.
+
+    Every row is summed in the same order whatever the number of rows, so a
+    vector scored twice gets the same bits (a BLAS matrix-vector product may
+    round a row differently depending on the batch it sits in).
+    """
+    P = np.asarray(M, np.float64) * np.asarray(v, np.float64)[None, :]
+    w = 1
+    while w < P.shape[1]:
+        w *= 2
+    if w != P.shape[1]:
+        P = np.concatenate([P, np.zeros((P.shape[0], w - P.shape[1]))], axis=1)
+    while w > 1:
+        w //= 2
+        P = P[:, :w] + P[:, w:]
+    return P[:, 0]
+
+
+def primary_scores(index: Index, qp64: np.ndarray, ids) -> np.ndarray:
+    """<q', y^_n> in float64 for the given ids (Eq. 1 with LVQ reconstruction)."""
+    ids = np.asarray(ids, dtype=np.int64)
+    yhat = (index.mu.astype(np.float64)[None, :]
+            + index.lo[ids].astype(np.float64)[:, None]
+            + index.delta[ids].astype(np.float64)[:, None]
+            * index.codes[ids].astype(np.float64))
+    return rowdot(yhat, qp64)
+
+
+def secondary_scores(index: Index, q64: np.ndarray, ids) -> np.ndarray:
+    """<q, secondary(n)> in float64 (Section 2, re-ranking)."""
+    ids = np.asarray(ids, dtype=np.int64)
+    return rowdot(index.sec[ids], q64)
+
+
+@dataclass
+class Trace:
+    n_exp: int = 0          # expansions (adjacency rows read)
+    n_dist: int = 0         # primary score evaluations
+    n_rescored: int = 0     # evaluations of already-visited ids (bounded visited set)
+    scored: Optional[dict] = None   # id -> score of every evaluation, when a dict is given
+
+
+def beam(index: Index, qp, L: int, visited_cap: Optional[int] = None,
+         trace: Optional[Trace] = None) -> List[Tuple[float, int]]:
+    """Best-first traversal; returns the final list as (score, id), best first.
+
+    visited_cap bounds the visited set (oldest entries forgotten first).  A
+    forgotten node that is met again is scored again and merged only if it
+    is not in the list already; the final list is the same as with an exact
+    visited set (a node dropped earlier was worse than L others, and the
+    L-th best score never decreases).
+    """
+    qp64 = np.asarray(qp, dtype=np.float32).astype(np.float64)
+    tr = trace if trace is not None else Trace()
+    adj = index.adj
+    e = int(index.entry)
+    s0 = float(primary_scores(index, qp64, [e])[0])
+    keys = [(-s0, e)]          # sorted ascending == score desc, id asc
+    in_list = {e}
+    expanded = set()
+    visited = {e: None}        # dict keeps insertion order for the bounded variant
+    tr.n_dist += 1
+    if tr.scored is not None:
+        tr.scored[e] = s0
+    while True:
+        p = None
+        for _, i in keys:
+            if i not in expanded:
+                p = i
+                break
+        if p is None:
+            break
+        expanded.add(p)
+        tr.n_exp += 1
+        fresh = []
+        rescored = []
+        for n in adj[p]:
+            n = int(n)
+            if n == SENTINEL:
+                continue
+            if n in visited:
+                continue
+            if n in in_list:       # only reachable when the visited set forgot n
+                rescored.append(n)
+            elif visited_cap is not None and n in expanded:
+                rescored.append(n)
+            else:
+                fresh.append(n)
+        newly = fresh + rescored
+        for n in newly:
+            visited[n] = None
+        if visited_cap is not None:
+            while len(visited) > visited_cap:
+                visited.pop(next(iter(visited)))
+        if not newly:
+            continue
+        tr.n_dist += len(newly)
+        tr.n_rescored += len(rescored)
+        sc = primary_scores(index, qp64, newly)
+        for s, n in zip(sc.tolist(), newly):
+            if tr.scored is not None:
+                tr.scored[n] = s
+            if n in in_list:
+                continue
+            key = (-s, n)
+            if len(keys) >= L and key > keys[-1]:
+                continue
+            bisect.insort(keys, key)
+            in_list.add(n)
+            if len(keys) > L:
+                _, gone = keys.pop()
+                in_list.discard(gone)
+    return [(-k, i) for k, i in keys]
+
+
+def rerank(index: Index, q, cand_ids, k: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Top-k of the candidates by secondary score (ties: smaller id)."""
+    q64 = np.asarray(q, dtype=np.float32).astype(np.float64)
+    ids = np.asarray(cand_ids, dtype=np.int64)
+    out_i = np.full(k, SENTINEL, dtype=np.int64)
+    out_s = np.full(k, -np.inf)
+    if ids.size:
+        s2 = secondary_scores(index, q64, ids)
+        order = np.lexsort((ids, -s2))[:k]
+        out_i[:len(order)] = ids[order]
+        out_s[:len(order)] = s2[order]
+    return out_i, out_s
+
+
+def search_one(index: Index, q, qp, k: int, L: int, visited_cap=None, trace=None):
+    """Full query: traversal with window L, then re-rank to k (requires L >= k)."""
+    if L < k:
+        raise ValueError("window L must be at least k")
+    lst = beam(index, qp, L, visited_cap=visited_cap, trace=trace)
+    return rerank(index, q, [i for _, i in lst], k)
+
+
+def flat_search(index: Index, q, qp, k: int, L: int):
+    """Exhaustive variant: primary top-L over all vectors, then re-rank."""
+    qp64 = np.asarray(qp, dtype=np.float32).astype(np.float64)
+    s = primary_scores(index, qp64, np.arange(index.N))
+    order = np.lexsort((np.arange(index.N), -s))[:L]
+    return rerank(index, q, order, k)
+
+
+# ---------------------------------------------------------------------------
+# Many queries, optionally over several processes (fresh interpreters that
+# memory-map the index, so nothing but numpy runs in them).
+
+_G = {}
+
+
+def _init_worker(paths, entry):
+    arrs = {k: np.load(v, mmap_mode="r") for k, v in paths.items()}
+    _G["index"] = Index(arrs["adj"], entry, arrs["codes"], arrs["delta"], arrs["lo"],
+                        arrs["mu"], arrs["sec"])
+
+
+def _run_chunk(args):
+    Q, Qp, k, L, lo = args
+    index = _G["index"]
+    ids = np.empty((len(Q), k), dtype=np.int64)
+    sc = np.empty((len(Q), k))
+    cnt = np.zeros((len(Q), 2), dtype=np.int64)
+    for i in range(len(Q)):
+        tr = Trace()
+        ids[i], sc[i] = search_one(index, Q[i], Qp[i], k, L, trace=tr)
+        cnt[i] = (tr.n_exp, tr.n_dist)
+    return lo, ids, sc, cnt
+
+
+def search_many(index: Index, Q, Qp, k: int, L: int, procs: int = 1,
+                chunk: int = 64, workdir: Optional[str] = None):
+    """Search every query; returns (ids [m,k], scores [m,k], counts [m,2])."""
+    Q = np.asarray(Q, dtype=np.float32)
+    Qp = np.asarray(Qp, dtype=np.float32)
+    m = len(Q)
+    ids = np.empty((m, k), dtype=np.int64)
+    sc = np.empty((m, k))
+    cnt = np.zeros((m, 2), dtype=np.int64)
+    if procs <= 1:
+        _G["index"] = index
+        for lo in range(0, m, chunk):
+            _, a, b, c = _run_chunk((Q[lo:lo + chunk], Qp[lo:lo + chunk], k, L, lo))
+            ids[lo:lo + len(a)], sc[lo:lo + len(a)], cnt[lo:lo + len(a)] = a, b, c
+        return ids, sc, cnt
+    import multiprocessing as mp
+    own = workdir is None
+    wd = workdir or tempfile.mkdtemp(prefix="lv_oracle_")
+    paths = {}
+    for name in ("adj", "codes", "delta", "lo", "mu", "sec"):
+        arr = getattr(index, name)
+        p = os.path.join(wd, name + ".npy")
+        if not os.path.exists(p):
+            np.save(p, np.ascontiguousarray(arr))
+        paths[name] = p
+    try:
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(procs, initializer=_init_worker, initargs=(paths, int(index.entry))) as pool:
+            jobs = [(Q[lo:lo + chunk], Qp[lo:lo + chunk], k, L, lo) for lo in range(0, m, chunk)]
+            for lo, a, b, c in pool.imap_unordered(_run_chunk, jobs):
+                ids[lo:lo + len(a)], sc[lo:lo + len(a)], cnt[lo:lo + len(a)] = a, b, c
+    finally:
+        if own:
+            for p in paths.values():
+                os.unlink(p)
+            os.rmdir(wd)
+    return ids, sc, cnt

@@ -1,0 +1,125 @@
+"""Pins for the graph-search oracle: hand-traced example, brute force, invariants."""
+import json
+import os
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import exact, lvq, search
+from oracle import fit as ofit
+from synth import gen, graph
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "beam_hand.json")
+SENT = search.SENTINEL
+
+
+def _hand_index():
+    g = json.load(open(GOLDEN))
+    n = len(g["v"])
+    codes = np.zeros((n, 4), dtype=np.uint8)
+    codes[:, 0] = g["v"]
+    adj = np.array([[SENT if a < 0 else a for a in row] for row in g["adj"]], dtype=np.uint32)
+    sec = np.zeros((n, 2), dtype=np.float32)
+    sec[:, 0] = g["w"]
+    idx = search.Index(adj, g["entry"], codes, np.ones(n, np.float32), np.zeros(n, np.float32),
+                       np.zeros(4, np.float32), sec)
+    return g, idx
+
+
+def test_hand_traced_traversal():
+    g, idx = _hand_index()
+    qp = np.array([1, 0, 0, 0], np.float32)
+    q = np.array([1, 0], np.float32)
+    for case in g["cases"]:
+        tr = search.Trace()
+        lst = search.beam(idx, qp, case["L"], trace=tr)
+        assert [i for _, i in lst] == case["list_ids"], case["why"]
+        assert (tr.n_exp, tr.n_dist) == (case["n_exp"], case["n_dist"]), case["why"]
+        ids, sc = search.search_one(idx, q, qp, case["k"], case["L"])
+        assert ids.tolist() == case["topk_ids"] and sc.tolist() == case["topk_scores"]
+
+
+def test_window_smaller_than_k_rejected():
+    _, idx = _hand_index()
+    with pytest.raises(ValueError):
+        search.search_one(idx, np.zeros(2, np.float32), np.zeros(4, np.float32), 5, 3)
+
+
+TINY = gen.Workload("tiny", D=48, d=12, N=1200, K=20, spectrum="inv", sigma=0.3, seed_basis=11,
+                    seed_data=12, seed_test=13, seed_learn=14, m_test=6, m_learn=200, bits=8,
+                    sec_dtype="f16", R=16, L_list=(24,), k=5)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    wl = TINY
+    mix = gen.mixture(wl)
+    X = gen.database(wl, mix)
+    Q = gen.queries(wl, "test", mix=mix)
+    P = ofit.fit_id(ofit.second_moment(X), wl.d)
+    Y = ofit.project(X, P).astype(np.float32)
+    Qp = ofit.project(Q, P).astype(np.float32)
+    mu = ofit.mean_reduced(X, P).astype(np.float32)
+    codes, delta, lo = lvq.encode(Y, mu, wl.bits)
+    adj, entry = graph.build_graph(X, wl.R)
+    assert graph.reachable(adj, entry).all()
+    idx = search.Index(adj, entry, codes, delta, lo, mu, X.astype(np.float16))
+    return wl, idx, Q, Qp
+
+
+def test_full_window_equals_brute_force(tiny):
+    wl, idx, Q, Qp = tiny
+    k = wl.k
+    S = idx.sec.astype(np.float64) @ Q.astype(np.float64).T
+    for i in range(3):
+        ids, sc = search.search_one(idx, Q[i], Qp[i], k, idx.N)
+        truth = sorted(range(idx.N), key=lambda j: (-S[j, i], j))[:k]
+        assert ids.tolist() == truth
+        fids, fsc = search.flat_search(idx, Q[i], Qp[i], k, idx.N)
+        assert fids.tolist() == truth and np.array_equal(fsc, sc)
+
+
+def test_final_list_is_top_L_of_scored_set(tiny):
+    wl, idx, Q, Qp = tiny
+    for i in range(len(Q)):
+        tr = search.Trace(scored={})
+        lst = search.beam(idx, Qp[i], 24, trace=tr)
+        best = sorted(tr.scored.items(), key=lambda t: (-t[1], t[0]))[:24]
+        assert [i for _, i in lst] == [i for i, _ in best]
+        assert tr.n_dist == len(tr.scored)
+
+
+def test_bounded_visited_set_gives_identical_lists(tiny):
+    wl, idx, Q, Qp = tiny
+    for i in range(len(Q)):
+        ref = search.beam(idx, Qp[i], 24)
+        for cap in (4, 16, 64):
+            tr = search.Trace()
+            assert search.beam(idx, Qp[i], 24, visited_cap=cap, trace=tr) == ref
+
+
+def test_primary_score_equals_factored_form(tiny):
+    wl, idx, Q, Qp = tiny
+    ids = np.arange(50)
+    qp = Qp[0].astype(np.float64)
+    plain = search.primary_scores(idx, qp, ids)
+    fact = (idx.delta[ids].astype(np.float64) * (idx.codes[ids].astype(np.float64) @ qp)
+            + idx.lo[ids].astype(np.float64) * qp.sum() + idx.mu.astype(np.float64) @ qp)
+    assert np.allclose(plain, fact, rtol=1e-12, atol=1e-12)
+
+
+def test_parallel_search_matches_serial(tiny):
+    wl, idx, Q, Qp = tiny
+    a = search.search_many(idx, Q, Qp, wl.k, 24, procs=1)
+    b = search.search_many(idx, Q, Qp, wl.k, 24, procs=2, chunk=2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_recall_reasonable_on_tiny(tiny):
+    wl, idx, Q, Qp = tiny
+    ids, _, _ = search.search_many(idx, Q, Qp, wl.k, 48)
+    X64 = idx.sec.astype(np.float32)
+    truth = exact.ground_truth(Q, X64, wl.k)
+    assert exact.recall_at_k(ids, truth, wl.k) >= 0.8
