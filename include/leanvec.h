@@ -1,0 +1,265 @@
+/*
+ * leanvec.h -- C ABI of the MI355X (gfx950) LeanVec search library.
+ *
+ * LeanVec (Tepper et al., "LeanVec: Searching vectors faster by making them
+ * fit") answers maximum-inner-product queries (Section 2, notation) with the
+ * approximation <q, x> ~ <A q, quant(B x)> (Eq. 1): a greedy graph traversal
+ * scores candidates against quantised d-dimensional "primary" vectors, and
+ * the surviving candidates are re-ranked against full-dimension "secondary"
+ * vectors (Section 2, "Search").  The projections A, B come from LeanVec-ID
+ * (Section 2.1) or LeanVec-OOD (Sections 2.2-2.4).
+ *
+ * Conventions for every call:
+ *  - Return value: LV_OK (0) on success, LV_WNOTCONVERGED (1) as a warning,
+ *    a negative LV_E* code on error.  lv_last_error() then returns a
+ *    thread-local message.  No C++ exception crosses this interface.
+ *  - All argument validation happens on the host before any device work, so
+ *    a rejected call has enqueued nothing.
+ *  - Matrices are row-major; vectors are rows.  Projections are [d][D].
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are ordinary host memory owned by the caller.  The library
+ *    keeps no pointer beyond the call except where a handle says it borrows.
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream).  Device
+ *    calls are asynchronous on that stream; a kernel fault surfaces at the
+ *    caller's next synchronising call.
+ *  - Integer sizes are int64_t for element counts, int32_t for dimensions.
+ */
+#ifndef LEANVEC_H
+#define LEANVEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LV_OK 0
+#define LV_WNOTCONVERGED 1
+#define LV_EINVAL (-1)
+#define LV_ENOMEM (-2)
+#define LV_EDEVICE (-3)
+#define LV_EUNSUPPORTED (-4)
+
+#define LV_SENTINEL 0xFFFFFFFFu /* padding id in adjacency rows and results */
+#define LV_MAX_L 1024           /* largest search window */
+#define LV_MAX_K 1024
+
+/* Secondary-vector element types. */
+#define LV_F32 0
+#define LV_F16 1
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int lv_version(void);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *lv_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Projection learning (host, float64, synchronous).
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Second moment accumulation, K += sum_i v_i v_i^T (the matrices K_Q = Q Q^T
+ * and K_X = X X^T of Problem leanvec_efficient, with vectors as columns of
+ * Q and X).  Accumulating lets the caller sample or stream chunks (the
+ * paper subsamples m = 1e4 queries and n = 1e5 database vectors).
+ *   V:   host float32 [n][D]
+ *   K:   host float64 [D][D], accumulated in place (symmetric)
+ *   sum: host float64 [D] or NULL; if given, sum += sum_i v_i (for the LVQ
+ *        centring vector)
+ * Errors: LV_EINVAL for NULL V/K, n < 0 or D < 1.
+ */
+int lv_second_moment(const float *V, int64_t n, int32_t D, double *K, double *sum);
+
+/*
+ * LeanVec-ID (Section 2.1, Problem pca): P = the d leading eigenvectors of
+ * K_X, as rows, so that A = B = P.  Rows are ordered by decreasing
+ * eigenvalue and signed so that each row's largest-magnitude entry is
+ * positive.
+ *   KX:    host float64 [D][D], symmetric
+ *   P:     host float64 [d][D] out
+ *   evals: host float64 [D] out (all eigenvalues, decreasing) or NULL
+ * Errors: LV_EINVAL unless 1 <= d <= D.
+ */
+int lv_fit_id(const double *KX, int32_t D, int32_t d, double *P, double *evals);
+
+/* Options of lv_fit_ood. */
+typedef struct {
+  double alpha;     /* step-size exponent, gamma_t = (t+1)^-alpha; 0 < alpha < 1 */
+  double tol;       /* stop when |f_{t+1} - f_t| / f_t <= tol */
+  int32_t max_iter; /* at most this many iterations */
+  int32_t init;     /* LV_FW_INIT_* */
+} lv_fw_params;
+
+#define LV_FW_INIT_ES 0    /* eigenvectors of K_Q/m + K_X/n (eigenvector search at beta = 1/2) */
+#define LV_FW_INIT_ZERO 1  /* A = B = 0 as suggested in Algorithm 1 */
+#define LV_FW_INIT_GIVEN 2 /* start from the A and B passed in */
+
+/* Progress of lv_fit_ood. */
+typedef struct {
+  int32_t iters;     /* iterations performed */
+  int32_t converged; /* 1 if the stop rule fired */
+  double f_first;    /* f(A_0, B_0) on the normalised moments */
+  double f_last;     /* f at the returned A, B */
+  double *f_hist;    /* caller array of max_iter + 1 entries, or NULL */
+  double *gap_hist;  /* caller array of max_iter entries (FW gap of the A and B steps summed), or NULL */
+} lv_fw_report;
+
+/*
+ * LeanVec-OOD by Frank-Wolfe block coordinate descent (Algorithm 1) on the
+ * relaxed problem (Problem leanvec) over the spectral-norm ball C (Eq.
+ * stiefel_convex_hull), with the partial gradients of Eq. leanvec_gradients
+ * and the linear step S = U V^T from the SVD of the negative gradient
+ * (Section 2.3).  K_Q / m and K_X / n are used (this leaves the iterates
+ * unchanged).
+ *   KQ, KX: host float64 [D][D]; m, n: the sample counts behind them
+ *   p:      options (NULL = alpha 0.9, tol 1e-3, 500 iterations, ES start)
+ *   A, B:   host float64 [d][D] out (inputs too with LV_FW_INIT_GIVEN)
+ *   r:      report or NULL
+ * Returns LV_OK, or LV_WNOTCONVERGED if max_iter was reached first.
+ * Errors: LV_EINVAL for bad sizes or options.
+ */
+int lv_fit_ood(const double *KQ, int64_t m, const double *KX, int64_t n, int32_t D,
+               int32_t d, const lv_fw_params *p, double *A, double *B, lv_fw_report *r);
+
+/*
+ * LeanVec-OOD by eigenvector search (Section 2.4, Algorithm 2): A = B = P,
+ * the d leading eigenvectors of K_beta = (1-beta)/m K_Q + beta/n K_X, with
+ * beta in [0, 1] minimising the equalised loss (Problem
+ * leanvec_loss_same_proj_equalized) by golden-section/parabolic (Brent)
+ * search to within xtol.
+ *   P:    host float64 [d][D] out;  beta: host double out (may be NULL)
+ * Errors: LV_EINVAL for bad sizes or xtol <= 0.
+ */
+int lv_fit_es(const double *KQ, int64_t m, const double *KX, int64_t n, int32_t D, int32_t d,
+              double xtol, double *P, double *beta);
+
+/*
+ * The LeanVec-OOD objective f(A, B) in its trace form (Problem
+ * leanvec_efficient) on K_Q / m and K_X / n, in float64.
+ */
+int lv_ood_loss(const double *KQ, int64_t m, const double *KX, int64_t n, int32_t D, int32_t d,
+                const double *A, const double *B, double *f);
+
+/* Host float64 -> bfloat16 (round to nearest even), for the device projections. */
+int lv_to_bf16(const double *src, int64_t count, uint16_t *dst);
+
+/* ------------------------------------------------------------------------
+ * Index construction (device).
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Reduced vectors out[i] = M v_i (Eq. 1: B x for the database, A q for the
+ * queries) on the matrix cores: bfloat16 operands (V is rounded to
+ * bfloat16 on load), float32 accumulation.
+ *   V:   device float32 [rows][D]
+ *   M:   device bfloat16 bits [d][D]
+ *   out: device float32 [rows][d]
+ * Errors: LV_EINVAL for NULL pointers, rows < 0, D < 1, D % 8 != 0,
+ *         d < 1, d > 1024.
+ */
+int lv_project(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32_t d,
+               float *out, void *stream);
+
+/*
+ * Record stride the search kernels support for d components at 4 or 8
+ * bits: code bytes + 8, rounded up to 64, 128, 192, 256, 512, 768 or 1024
+ * (0 if none fits).
+ */
+int32_t lv_record_stride(int32_t d, int32_t bits);
+
+/*
+ * LVQ encoding of primary vectors (quant in Eq. 1; LVQ is a per-vector
+ * scale-and-bias scalar quantiser).  With r = y - mu computed in float64:
+ * l = min r, u = max r, delta = float32((u - l)/(2^bits - 1)),
+ * lo = float32(l), code_j = clamp(floor((r_j - lo)/delta + 0.5), 0,
+ * 2^bits - 1) (all zero when delta = 0).  Record layout per vector:
+ * code bytes (bits = 8: one per component; bits = 4: component 2i in the
+ * low nibble of byte i, 2i+1 in the high nibble), float32 delta, float32
+ * lo, zero padding to record_stride.  Results are bit-exact (IEEE float64
+ * division and floor, no contraction).
+ *   Y:       device float32 [n][d];  mu: device float32 [d]
+ *   records: device [n][record_stride] bytes out
+ * Errors: LV_EINVAL unless bits is 4 or 8, d % 8 == 0, 8 <= d <= 2048 and
+ *         record_stride >= d*bits/8 + 8 is a multiple of 4.
+ */
+int lv_lvq_encode(const float *Y, int64_t n, int32_t d, const float *mu, int32_t bits,
+                  void *records, int32_t record_stride, void *stream);
+
+/* Secondary vectors (Section 2: quant(x), here float16): float32 -> float16,
+ * round to nearest even.  X: device float32 [count]; out: device [count]. */
+int lv_to_f16(const float *X, int64_t count, uint16_t *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Search (device).
+ * ---------------------------------------------------------------------- */
+
+/* Everything a search reads.  All pointers are device memory BORROWED by
+ * the index handle: they must stay valid and unchanged while it lives. */
+typedef struct {
+  int64_t N;               /* database size (< 2^31) */
+  int32_t D;               /* full dimension */
+  int32_t d;               /* reduced dimension */
+  int32_t bits;            /* LVQ bits of the primary records: 4 or 8 */
+  int32_t record_stride;   /* bytes per primary record (lv_record_stride) */
+  const void *records;     /* [N][record_stride] LVQ records */
+  const float *mu;         /* [d] LVQ centring vector */
+  int32_t sec_dtype;       /* LV_F32 or LV_F16 */
+  const void *secondaries; /* [N][D] secondary vectors */
+  int32_t R;               /* graph out-degree, 1..1024 */
+  const uint32_t *adjacency; /* [N][R]; valid ids first, then LV_SENTINEL */
+  uint32_t entry;          /* traversal start node */
+  const uint16_t *A;       /* [d][D] bfloat16 query projection, or NULL */
+} lv_index_desc;
+
+typedef struct lv_index lv_index;
+
+/* Validate desc and make a handle (host memory only; borrows the device
+ * pointers).  Errors: LV_EINVAL for inconsistent sizes or NULL data,
+ * LV_EUNSUPPORTED for a record stride or dimension the kernels lack. */
+int lv_index_create(const lv_index_desc *desc, lv_index **out);
+int lv_index_destroy(lv_index *index);
+
+/* Performance knobs.  They never change results. */
+typedef struct {
+  int32_t hash_slots;      /* visited-set slots per query (power of 2, 256..65536; 0 = 4096) */
+  int32_t waves_per_group; /* queries per workgroup (1..4; 0 = 1) */
+} lv_search_params;
+
+/* Bytes of device workspace lv_search needs for m queries. */
+size_t lv_search_workspace_size(const lv_index *index, int64_t m);
+
+/*
+ * Search m queries (Section 2 "Search"): q' = A q on the matrix cores, then
+ * one wavefront per query runs the best-first traversal with window L on
+ * the primary records (expand the best unexpanded candidate under the
+ * order (score descending, id ascending), score its unvisited
+ * out-neighbours, keep the best L), then re-ranks every candidate left in
+ * the window with <q, secondary> and returns the best k (ties: smaller id).
+ * Primary and secondary scores are accumulated in float64.
+ *   Q:        device float32 [m][D]
+ *   ids:      device uint32 [m][k] out;  scores: device float32 [m][k] out
+ *   counters: device uint32 [m][2] out (expansions, primary scorings) or NULL
+ *   ws:       device workspace of lv_search_workspace_size bytes
+ * If fewer than k nodes were reached, the tail is LV_SENTINEL / -inf.
+ * Errors: LV_EINVAL for k < 1, L < k, L > LV_MAX_L, k > LV_MAX_K, m < 0,
+ *         missing A, small workspace or NULL pointers.
+ */
+int lv_search(const lv_index *index, const float *Q, int64_t m, int32_t k, int32_t L,
+              uint32_t *ids, float *scores, uint32_t *counters, void *ws, size_t ws_bytes,
+              const lv_search_params *params, void *stream);
+
+/*
+ * The same search with the projected queries supplied by the caller
+ * (Qp: device float32 [m][d]); Q is still needed for the re-ranking.
+ */
+int lv_search_projected(const lv_index *index, const float *Q, const float *Qp, int64_t m,
+                        int32_t k, int32_t L, uint32_t *ids, float *scores, uint32_t *counters,
+                        const lv_search_params *params, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LEANVEC_H */

@@ -1,0 +1,298 @@
+"""ctypes binding of ``liblv.so`` (the C ABI in include/leanvec.h).
+
+Argument marshalling only: device arrays are torch tensors on the GPU (their
+``data_ptr()`` is passed), host arrays are numpy arrays, streams default to
+torch's current stream.  Every computation runs in the library.  A missing
+library is an error: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "liblv.so")
+
+LV_OK, LV_WNOTCONVERGED = 0, 1
+LV_EINVAL, LV_ENOMEM, LV_EDEVICE, LV_EUNSUPPORTED = -1, -2, -3, -4
+LV_F32, LV_F16 = 0, 1
+LV_SENTINEL = 0xFFFFFFFF
+LV_FW_INIT_ES, LV_FW_INIT_ZERO, LV_FW_INIT_GIVEN = 0, 1, 2
+
+_c_i32, _c_i64, _c_u32, _c_dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+_vp = ctypes.c_void_p
+
+
+class LVError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"leanvec error {code}: {msg}")
+        self.code = code
+
+
+class IndexDesc(ctypes.Structure):
+    _fields_ = [("N", _c_i64), ("D", _c_i32), ("d", _c_i32), ("bits", _c_i32),
+                ("record_stride", _c_i32), ("records", _vp), ("mu", _vp), ("sec_dtype", _c_i32),
+                ("secondaries", _vp), ("R", _c_i32), ("adjacency", _vp), ("entry", _c_u32),
+                ("A", _vp)]
+
+
+class SearchParams(ctypes.Structure):
+    _fields_ = [("hash_slots", _c_i32), ("waves_per_group", _c_i32)]
+
+
+class FWParams(ctypes.Structure):
+    _fields_ = [("alpha", _c_dbl), ("tol", _c_dbl), ("max_iter", _c_i32), ("init", _c_i32)]
+
+
+class FWReport(ctypes.Structure):
+    _fields_ = [("iters", _c_i32), ("converged", _c_i32), ("f_first", _c_dbl),
+                ("f_last", _c_dbl), ("f_hist", _vp), ("gap_hist", _vp)]
+
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "lv_version": (_c_i32, []),
+    "lv_last_error": (ctypes.c_char_p, []),
+    "lv_second_moment": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _vp]),
+    "lv_fit_id": (_c_i32, [_vp, _c_i32, _c_i32, _vp, _vp]),
+    "lv_fit_ood": (_c_i32, [_vp, _c_i64, _vp, _c_i64, _c_i32, _c_i32, _vp, _vp, _vp, _vp]),
+    "lv_fit_es": (_c_i32, [_vp, _c_i64, _vp, _c_i64, _c_i32, _c_i32, _c_dbl, _vp, _vp]),
+    "lv_ood_loss": (_c_i32, [_vp, _c_i64, _vp, _c_i64, _c_i32, _c_i32, _vp, _vp, _vp]),
+    "lv_to_bf16": (_c_i32, [_vp, _c_i64, _vp]),
+    "lv_project": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _vp]),
+    "lv_record_stride": (_c_i32, [_c_i32, _c_i32]),
+    "lv_lvq_encode": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _c_i32, _vp]),
+    "lv_to_f16": (_c_i32, [_vp, _c_i64, _vp, _vp]),
+    "lv_index_create": (_c_i32, [ctypes.POINTER(IndexDesc), ctypes.POINTER(_vp)]),
+    "lv_index_destroy": (_c_i32, [_vp]),
+    "lv_search_workspace_size": (ctypes.c_size_t, [_vp, _c_i64]),
+    "lv_search": (_c_i32, [_vp, _vp, _c_i64, _c_i32, _c_i32, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                           ctypes.POINTER(SearchParams), _vp]),
+    "lv_search_projected": (_c_i32, [_vp, _vp, _vp, _c_i64, _c_i32, _c_i32, _vp, _vp, _vp,
+                                     ctypes.POINTER(SearchParams), _vp]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load liblv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2312_16335_amd/build.py "
+                              "(or __graft_entry__.build())")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def _check(rc: int, allow_warn: bool = False) -> int:
+    if rc == LV_OK or (allow_warn and rc == LV_WNOTCONVERGED):
+        return rc
+    raise LVError(rc, load().lv_last_error().decode())
+
+
+def _host(a: np.ndarray, dtype) -> np.ndarray:
+    if not (isinstance(a, np.ndarray) and a.dtype == dtype and a.flags.c_contiguous):
+        raise TypeError(f"expected a C-contiguous numpy {np.dtype(dtype)} array")
+    return a
+
+
+def _dev(t, dtype=None):
+    """data_ptr of a contiguous CUDA tensor (or 0 for None)."""
+    if t is None:
+        return None
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise TypeError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+# ---------------------------------------------------------------- host fit
+
+def lv_version() -> int:
+    return load().lv_version()
+
+
+def lv_second_moment(V: np.ndarray, K: np.ndarray, sum_: Optional[np.ndarray] = None) -> None:
+    V = _host(V, np.float32)
+    _host(K, np.float64)
+    n, D = V.shape
+    _check(load().lv_second_moment(V.ctypes.data, n, D, K.ctypes.data,
+                                   None if sum_ is None else _host(sum_, np.float64).ctypes.data))
+
+
+def lv_fit_id(KX: np.ndarray, d: int, with_evals: bool = False):
+    KX = _host(KX, np.float64)
+    D = KX.shape[0]
+    P = np.empty((d, D), np.float64)
+    ev = np.empty(D, np.float64) if with_evals else None
+    _check(load().lv_fit_id(KX.ctypes.data, D, d, P.ctypes.data,
+                            None if ev is None else ev.ctypes.data))
+    return (P, ev) if with_evals else P
+
+
+def lv_fit_ood(KQ, m, KX, n, d, alpha=0.9, tol=1e-3, max_iter=500, init=LV_FW_INIT_ES,
+               A0=None, B0=None):
+    KQ = _host(KQ, np.float64)
+    KX = _host(KX, np.float64)
+    D = KQ.shape[0]
+    A = np.zeros((d, D)) if A0 is None else np.array(A0, np.float64, order="C")
+    B = np.zeros((d, D)) if B0 is None else np.array(B0, np.float64, order="C")
+    fh = np.zeros(max_iter + 1)
+    gh = np.zeros(max_iter)
+    rep = FWReport(0, 0, 0.0, 0.0, fh.ctypes.data, gh.ctypes.data)
+    prm = FWParams(alpha, tol, max_iter, init)
+    rc = _check(load().lv_fit_ood(KQ.ctypes.data, m, KX.ctypes.data, n, D, d, ctypes.byref(prm),
+                                  A.ctypes.data, B.ctypes.data, ctypes.byref(rep)),
+                allow_warn=True)
+    info = {"iters": rep.iters, "converged": bool(rep.converged), "f_first": rep.f_first,
+            "f_last": rep.f_last, "f": fh[:rep.iters + 1].copy(), "gap": gh[:rep.iters].copy(),
+            "status": rc}
+    return A, B, info
+
+
+def lv_fit_es(KQ, m, KX, n, d, xtol=1e-4):
+    KQ = _host(KQ, np.float64)
+    KX = _host(KX, np.float64)
+    D = KQ.shape[0]
+    P = np.empty((d, D))
+    beta = ctypes.c_double(0.0)
+    _check(load().lv_fit_es(KQ.ctypes.data, m, KX.ctypes.data, n, D, d, xtol, P.ctypes.data,
+                            ctypes.byref(beta)))
+    return P, beta.value
+
+
+def lv_ood_loss(KQ, m, KX, n, A, B) -> float:
+    KQ, KX = _host(KQ, np.float64), _host(KX, np.float64)
+    A = np.ascontiguousarray(A, np.float64)
+    B = np.ascontiguousarray(B, np.float64)
+    f = ctypes.c_double(0.0)
+    _check(load().lv_ood_loss(KQ.ctypes.data, m, KX.ctypes.data, n, KQ.shape[0], A.shape[0],
+                              A.ctypes.data, B.ctypes.data, ctypes.byref(f)))
+    return f.value
+
+
+def lv_to_bf16(M: np.ndarray) -> np.ndarray:
+    M = np.ascontiguousarray(M, np.float64)
+    out = np.empty(M.shape, np.uint16)
+    _check(load().lv_to_bf16(M.ctypes.data, M.size, out.ctypes.data))
+    return out
+
+
+# ------------------------------------------------------------ device calls
+
+def lv_project(V, M_bf16, out, stream=None) -> None:
+    """out[rows, d] = V[rows, D] @ M^T with M given as bfloat16 bits (int16 tensor)."""
+    import torch
+
+    rows, D = V.shape
+    d = M_bf16.shape[0]
+    _check(load().lv_project(_dev(V, torch.float32), rows, D, _dev(M_bf16), d,
+                             _dev(out, torch.float32), _stream(stream)))
+
+
+def lv_record_stride(d: int, bits: int) -> int:
+    return load().lv_record_stride(d, bits)
+
+
+def lv_lvq_encode(Y, mu, bits: int, records, stream=None) -> None:
+    import torch
+
+    n, d = Y.shape
+    _check(load().lv_lvq_encode(_dev(Y, torch.float32), n, d, _dev(mu, torch.float32), bits,
+                                _dev(records, torch.uint8), records.shape[1], _stream(stream)))
+
+
+def lv_to_f16(X, out, stream=None) -> None:
+    import torch
+
+    _check(load().lv_to_f16(_dev(X, torch.float32), X.numel(), _dev(out, torch.float16),
+                            _stream(stream)))
+
+
+class Index:
+    """Handle over device arrays (borrowed: keep the tensors alive)."""
+
+    def __init__(self, records, mu, secondaries, adjacency, entry: int, bits: int, d: int,
+                 A_bf16=None):
+        import torch
+
+        N, D = secondaries.shape
+        self._keep = (records, mu, secondaries, adjacency, A_bf16)
+        sec_dtype = LV_F16 if secondaries.dtype == torch.float16 else LV_F32
+        self.desc = IndexDesc(N, D, d, bits, records.shape[1], _dev(records, torch.uint8),
+                              _dev(mu, torch.float32), sec_dtype, _dev(secondaries),
+                              adjacency.shape[1], _dev(adjacency, torch.int32), entry,
+                              _dev(A_bf16) if A_bf16 is not None else None)
+        h = _vp()
+        _check(load().lv_index_create(ctypes.byref(self.desc), ctypes.byref(h)))
+        self.handle = h
+        self.N, self.D, self.d = N, D, d
+
+    def close(self):
+        if self.handle:
+            load().lv_index_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _params(hash_slots: int = 0, waves_per_group: int = 0):
+    return ctypes.byref(SearchParams(hash_slots, waves_per_group))
+
+
+def lv_search_workspace_size(index: Index, m: int) -> int:
+    return load().lv_search_workspace_size(index.handle, m)
+
+
+def lv_search(index: Index, Q, k: int, L: int, ids, scores, counters=None, ws=None,
+              hash_slots: int = 0, stream=None) -> None:
+    import torch
+
+    m = Q.shape[0]
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    _check(load().lv_search(index.handle, _dev(Q, torch.float32), m, k, L,
+                            _dev(ids, torch.int32), _dev(scores, torch.float32),
+                            _dev(counters, torch.int32), _dev(ws), ws_bytes,
+                            _params(hash_slots), _stream(stream)))
+
+
+def lv_search_projected(index: Index, Q, Qp, k: int, L: int, ids, scores, counters=None,
+                        hash_slots: int = 0, stream=None) -> None:
+    import torch
+
+    m = Q.shape[0]
+    _check(load().lv_search_projected(index.handle, _dev(Q, torch.float32),
+                                      _dev(Qp, torch.float32), m, k, L, _dev(ids, torch.int32),
+                                      _dev(scores, torch.float32), _dev(counters, torch.int32),
+                                      _params(hash_slots), _stream(stream)))

@@ -1,0 +1,132 @@
+// LVQ encoding of the primary vectors and float16 conversion of the
+// secondary vectors (Section 2: primary vectors quant(Bx), secondary vectors
+// quant(x)).
+//
+// One wavefront encodes one vector: lanes own component pairs (2i, 2i+1),
+// the min / max of r = y - mu are wave reductions in float64, and every
+// code is computed with IEEE float64 division and floor, so the bytes equal
+// a float64 reference exactly.  This file is compiled without floating-point
+// contraction.
+#include "lv_common.h"
+
+namespace lv {
+namespace {
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t lvq_code(double r, double lo, double delta, double levels) {
+  if (delta == 0.0) return 0u;
+  double c = floor((r - lo) / delta + 0.5);
+  c = c < 0.0 ? 0.0 : (c > levels ? levels : c);
+  return (uint32_t)c;
+}
+
+template <int BITS>
+__global__ __launch_bounds__(256) void encode_kernel(const float *__restrict__ Y, int64_t n,
+                                                     int32_t d, const float *__restrict__ mu,
+                                                     unsigned char *__restrict__ rec,
+                                                     int32_t stride) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (v >= n) return;
+  const float *y = Y + v * d;
+  double lmin = INFINITY, lmax = -INFINITY;
+  for (int j = lane; j < d; j += 64) {
+    const double r = (double)y[j] - (double)mu[j];
+    lmin = fmin(lmin, r);
+    lmax = fmax(lmax, r);
+  }
+  const double l = wave_min(lmin);
+  const double u = wave_max(lmax);
+  const double levels = (double)((1 << BITS) - 1);
+  const float delta32 = (float)((u - l) / levels);
+  const float lo32 = (float)l;
+  const double delta = (double)delta32, lo = (double)lo32;
+  unsigned char *out = rec + v * (int64_t)stride;
+  for (int i = lane; 2 * i < d; i += 64) {
+    const double r0 = (double)y[2 * i] - (double)mu[2 * i];
+    const double r1 = (double)y[2 * i + 1] - (double)mu[2 * i + 1];
+    const uint32_t c0 = lvq_code(r0, lo, delta, levels);
+    const uint32_t c1 = lvq_code(r1, lo, delta, levels);
+    if (BITS == 8) {
+      *reinterpret_cast<uint16_t *>(out + 2 * i) = (uint16_t)(c0 | (c1 << 8));
+    } else {
+      out[i] = (unsigned char)(c0 | (c1 << 4));
+    }
+  }
+  const int cb = d * BITS / 8;
+  if (lane == 0) {
+    uint32_t *w = reinterpret_cast<uint32_t *>(out + cb);
+    w[0] = __float_as_uint(delta32);
+    w[1] = __float_as_uint(lo32);
+  }
+  for (int b = cb + 8 + 4 * lane; b < stride; b += 256)
+    *reinterpret_cast<uint32_t *>(out + b) = 0u;
+}
+
+// float32 -> float16 with the hardware conversion (round to nearest even).
+__global__ __launch_bounds__(256) void to_f16_kernel(const float *__restrict__ x, int64_t count,
+                                                     _Float16 *__restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    out[i] = (_Float16)x[i];
+}
+
+}  // namespace
+}  // namespace lv
+
+extern "C" int32_t lv_record_stride(int32_t d, int32_t bits) {
+  if (d < 1 || (bits != 4 && bits != 8) || (d * bits) % 32 != 0) return 0;
+  const int32_t need = d * bits / 8 + 8;
+  static const int32_t strides[] = {64, 128, 192, 256, 512, 768, 1024};
+  for (int32_t s : strides)
+    if (need <= s) return s;
+  return 0;
+}
+
+extern "C" int lv_lvq_encode(const float *Y, int64_t n, int32_t d, const float *mu, int32_t bits,
+                             void *records, int32_t record_stride, void *stream) {
+  lv::clear_error();
+  if (bits != 4 && bits != 8) LV_FAIL(LV_EINVAL, "bits must be 4 or 8 (got %d)", bits);
+  if (d < 8 || d > 2048 || d % 8 != 0) LV_FAIL(LV_EINVAL, "d must be a multiple of 8 in [8, 2048]");
+  if (n < 0) LV_FAIL(LV_EINVAL, "n must be >= 0");
+  if (record_stride < d * bits / 8 + 8 || record_stride % 4 != 0)
+    LV_FAIL(LV_EINVAL, "record_stride %d too small or not a multiple of 4", record_stride);
+  if (n > 0 && (!Y || !mu || !records)) LV_FAIL(LV_EINVAL, "NULL pointer");
+  if (n == 0) return LV_OK;
+  const int per_block = 4;
+  const int64_t blocks = (n + per_block - 1) / per_block;
+  if (blocks > 0x7FFFFFFF) LV_FAIL(LV_EINVAL, "n too large");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (bits == 8)
+    hipLaunchKernelGGL(lv::encode_kernel<8>, dim3((unsigned)blocks), dim3(64 * per_block), 0, s, Y,
+                       n, d, mu, static_cast<unsigned char *>(records), record_stride);
+  else
+    hipLaunchKernelGGL(lv::encode_kernel<4>, dim3((unsigned)blocks), dim3(64 * per_block), 0, s, Y,
+                       n, d, mu, static_cast<unsigned char *>(records), record_stride);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+extern "C" int lv_to_f16(const float *X, int64_t count, uint16_t *out, void *stream) {
+  lv::clear_error();
+  if (count < 0) LV_FAIL(LV_EINVAL, "count must be >= 0");
+  if (count == 0) return LV_OK;
+  if (!X || !out) LV_FAIL(LV_EINVAL, "NULL pointer");
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(lv::to_f16_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), X, count, reinterpret_cast<_Float16 *>(out));
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}

@@ -1,0 +1,152 @@
+// Reduced vectors out = V M^T on the gfx950 matrix cores (Eq. 1: A q and
+// B x).  bfloat16 operands, float32 accumulation.
+//
+// The projection streams V once and is bound by HBM bandwidth (about 2d/4
+// flop per byte for float32 input), so the design goal is one pass over V
+// with full cache lines: each wavefront owns 32 rows and all d output
+// columns (ceil(d/32) 32x32 accumulator tiles), walks D in steps of 32
+// (two 32x32x16 MFMAs per tile per step, so every 128-byte line of a row is
+// consumed by one wavefront in one step), rounds V to bfloat16 in
+// registers, and reads M (d x D bfloat16, a few hundred KB, L2-resident)
+// directly as the B operand.  No LDS is needed.
+#include "lv_common.h"
+
+namespace lv {
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+
+// float32 -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+  return bf16_bits(lo) | (bf16_bits(hi) << 16);
+}
+
+// A operand: 8 consecutive k of one row, as bfloat16.
+__device__ __forceinline__ bf16x8 load_a(const float *p, bool ok) {
+  u32x4 w;
+  if (ok) {
+    const float4 x0 = *reinterpret_cast<const float4 *>(p);
+    const float4 x1 = *reinterpret_cast<const float4 *>(p + 4);
+    w[0] = pack2(x0.x, x0.y);
+    w[1] = pack2(x0.z, x0.w);
+    w[2] = pack2(x1.x, x1.y);
+    w[3] = pack2(x1.z, x1.w);
+  } else {
+    w[0] = w[1] = w[2] = w[3] = 0u;
+  }
+  return __builtin_bit_cast(bf16x8, w);
+}
+
+__device__ __forceinline__ bf16x8 load_b(const uint16_t *p, bool ok) {
+  u32x4 w;
+  if (ok) {
+    const uint4 x = *reinterpret_cast<const uint4 *>(p);
+    w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
+  } else {
+    w[0] = w[1] = w[2] = w[3] = 0u;
+  }
+  return __builtin_bit_cast(bf16x8, w);
+}
+
+// NT = number of 32-column output tiles handled by one wavefront.
+template <int NT>
+__global__ __launch_bounds__(256) void project_kernel(const float *__restrict__ V, int64_t rows,
+                                                      int32_t D, const uint16_t *__restrict__ M,
+                                                      int32_t d, int32_t col0,
+                                                      float *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 32;
+  if (row0 >= rows) return;
+  const int r = lane & 31;      // row of the A operand / column of the B operand
+  const int kh = lane >> 5;     // which 8-wide k half of a 16-wide step
+  const int64_t arow = row0 + r;
+  const bool arow_ok = arow < rows;
+  const float *ap = V + (arow_ok ? arow : 0) * (int64_t)D;
+
+  f32x16 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+
+  for (int k0 = 0; k0 < D; k0 += 32) {
+    const int ka = k0 + 8 * kh;       // first MFMA of the step
+    const int kb = k0 + 16 + 8 * kh;  // second MFMA
+    const bf16x8 a0 = load_a(ap + ka, arow_ok && ka < D);
+    const bf16x8 a1 = load_a(ap + kb, arow_ok && kb < D);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = col0 + t * 32 + r;
+      const bool cok = col < d;
+      const uint16_t *bp = M + (int64_t)(cok ? col : 0) * D;
+      const bf16x8 b0 = load_b(bp + ka, cok && ka < D);
+      const bf16x8 b1 = load_b(bp + kb, cok && kb < D);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[t], 0, 0, 0);
+    }
+  }
+  // accumulator layout: lane holds column (lane % 32); register i holds row
+  // 8 * (i / 4) + 4 * (lane / 32) + (i % 4)
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = col0 + t * 32 + r;
+    if (col >= d) continue;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int64_t row = row0 + 8 * (i >> 2) + 4 * kh + (i & 3);
+      if (row < rows) out[row * d + col] = acc[t][i];
+    }
+  }
+}
+
+template <int NT>
+void launch_nt(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32_t d, int32_t col0,
+               float *out, hipStream_t s) {
+  const int64_t blocks = (rows + 127) / 128;
+  hipLaunchKernelGGL(project_kernel<NT>, dim3((unsigned)blocks), dim3(256), 0, s, V, rows, D, M,
+                     d, col0, out);
+}
+
+}  // namespace
+
+int launch_project(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32_t d,
+                   float *out, hipStream_t stream) {
+  if (rows == 0) return LV_OK;
+  if ((rows + 127) / 128 > 0x7FFFFFFF) LV_FAIL(LV_EINVAL, "too many rows");
+  for (int32_t col0 = 0; col0 < d; col0 += 256) {
+    const int nt = ((d - col0) + 31) / 32;
+    switch (nt > 8 ? 8 : nt) {
+      case 1: launch_nt<1>(V, rows, D, M, d, col0, out, stream); break;
+      case 2: launch_nt<2>(V, rows, D, M, d, col0, out, stream); break;
+      case 3: launch_nt<3>(V, rows, D, M, d, col0, out, stream); break;
+      case 4: launch_nt<4>(V, rows, D, M, d, col0, out, stream); break;
+      case 5: launch_nt<5>(V, rows, D, M, d, col0, out, stream); break;
+      case 6: launch_nt<6>(V, rows, D, M, d, col0, out, stream); break;
+      case 7: launch_nt<7>(V, rows, D, M, d, col0, out, stream); break;
+      default: launch_nt<8>(V, rows, D, M, d, col0, out, stream); break;
+    }
+    LV_CHECK_LAUNCH();
+  }
+  return LV_OK;
+}
+
+}  // namespace lv
+
+extern "C" int lv_project(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32_t d,
+                          float *out, void *stream) {
+  lv::clear_error();
+  if (rows < 0) LV_FAIL(LV_EINVAL, "rows must be >= 0");
+  if (D < 8 || D % 8 != 0) LV_FAIL(LV_EINVAL, "D must be a positive multiple of 8 (got %d)", D);
+  if (d < 1 || d > 1024) LV_FAIL(LV_EINVAL, "d must be in [1, 1024] (got %d)", d);
+  if (rows > 0 && (!V || !M || !out)) LV_FAIL(LV_EINVAL, "NULL pointer");
+  return lv::launch_project(V, rows, D, M, d, out, static_cast<hipStream_t>(stream));
+}

@@ -69,7 +69,7 @@ class Workload:
     seed_rot: int = 0
     seed_shift: int = 0
     shift: float = 0.5
-    notes: str = ""
+    graph_alphas: Tuple[float, ...] = (1.0, 1.2)   # pruning factor per build pass
 
     def scaled(self, N: Optional[int] = None, m_test: Optional[int] = None,
                m_learn: Optional[int] = None) -> "Workload":
@@ -84,7 +84,7 @@ WORKLOADS = {
     "id-small": Workload("id-small", D=128, d=32, N=10_000, K=50, spectrum="iso",
                          sigma=0.3, seed_basis=100, seed_data=101, seed_test=102,
                          seed_learn=103, m_test=100, m_learn=1000, bits=8,
-                         sec_dtype="f32", R=32, L_list=(50,), k=10),
+                         sec_dtype="f32", R=32, L_list=(50,), k=10, graph_alphas=(1.0,)),
     # LeanVec-ID at scale: 1M x 768, 1000 anisotropic clusters, d=160.
     "id-1m-768": Workload("id-1m-768", D=768, d=160, N=1_000_000, K=1000,
                           spectrum="inv", sigma=0.3, seed_basis=200, seed_data=201,

@@ -45,6 +45,10 @@ def _load():
                                       ctypes.c_uint32, ctypes.c_void_p]
         lib.lvg_medoid.restype = ctypes.c_uint32
         lib.lvg_medoid.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32]
+        lib.lvg_repair.restype = ctypes.c_int64
+        lib.lvg_repair.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_uint32, ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -74,6 +78,8 @@ def build_graph(X: np.ndarray, R: int, L: int = 0, metric: int = METRIC_L2,
                               float(batch_frac), seed, threads, adj.ctypes.data)
     if entry < 0:
         raise ValueError("graph build rejected its arguments")
+    # connect anything the entry cannot reach (deterministic, usually a few nodes)
+    _load().lvg_repair(X.ctypes.data, n, dim, metric, R, L, entry, adj.ctypes.data)
     return adj, int(entry)
 
 

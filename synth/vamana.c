@@ -408,6 +408,79 @@ int64_t lvg_build(const float *X, int64_t n, int32_t dim, int32_t metric, int32_
   return (int64_t)entry;
 }
 
+/* mark everything reachable from s that is not marked yet; returns the count */
+static int64_t bfs_mark(const uint32_t *adj, int64_t n, int32_t R, uint32_t s, uint8_t *mark,
+                        uint32_t *q) {
+  int64_t h = 0, t = 0;
+  if (mark[s]) return 0;
+  mark[s] = 1;
+  q[t++] = s;
+  while (h < t) {
+    uint32_t u = q[h++];
+    for (int r = 0; r < R; ++r) {
+      uint32_t v = adj[(size_t)u * R + r];
+      if (v == SENT) break;
+      if (v < (uint64_t)n && !mark[v]) { mark[v] = 1; q[t++] = v; }
+    }
+  }
+  return t;
+}
+
+/*
+ * Make every node reachable from the entry.  Unreachable nodes are visited in
+ * increasing id; for each one still unreachable, a greedy search from the
+ * entry (which only walks reachable nodes) ranks reachable candidates, and
+ * the most similar one with a free slot gets an edge to it (the most similar
+ * one overall has its last edge replaced if none has a free slot).  Repeats
+ * until a full BFS reaches everything (bounded).  Returns the number of
+ * edges added.
+ */
+int64_t lvg_repair(const float *X, int64_t n, int32_t dim, int32_t metric, int32_t R, int32_t L,
+                   uint32_t entry, uint32_t *adj) {
+  uint8_t *mark = (uint8_t *)malloc((size_t)n);
+  uint32_t *q = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  float *nrm = (float *)malloc(sizeof(float) * n);
+  for (int64_t i = 0; i < n; ++i) nrm[i] = dotf(X + (size_t)i * dim, X + (size_t)i * dim, dim);
+  space_t space = {X, nrm, dim, metric};
+  scratch_t w;
+  scratch_init(&w, L, R);
+  int64_t added = 0;
+  for (int round = 0; round < 8; ++round) {
+    memset(mark, 0, (size_t)n);
+    if (bfs_mark(adj, n, R, entry, mark, q) == n) break;
+    for (int64_t u = 0; u < n; ++u) {
+      if (mark[u]) continue;
+      const float *xu = X + (size_t)u * dim;
+      greedy(&w, &space, adj, R, entry, xu, nrm[u], L);
+      pool_reserve(&w, w.nvis);
+      for (size_t v = 0; v < w.nvis; ++v) w.pool[v] = w.vis[v];
+      qsort(w.pool, w.nvis, sizeof(cand_t), cmp_cand);
+      int64_t pick = -1;
+      for (size_t v = 0; v < w.nvis && pick < 0; ++v) {
+        uint32_t c = w.pool[v].id;
+        if (c == (uint32_t)u || !mark[c]) continue;
+        if (adj[(size_t)c * R + R - 1] == SENT) pick = c;
+      }
+      if (pick < 0) {
+        for (size_t v = 0; v < w.nvis && pick < 0; ++v)
+          if (w.pool[v].id != (uint32_t)u && mark[w.pool[v].id]) pick = w.pool[v].id;
+        if (pick < 0) pick = entry;
+        adj[(size_t)pick * R + R - 1] = (uint32_t)u;
+      } else {
+        uint32_t *row = adj + (size_t)pick * R;
+        int deg = 0;
+        while (deg < R && row[deg] != SENT) ++deg;
+        row[deg] = (uint32_t)u;
+      }
+      ++added;
+      bfs_mark(adj, n, R, (uint32_t)u, mark, q);
+    }
+  }
+  scratch_free(&w);
+  free(mark); free(q); free(nrm);
+  return added;
+}
+
 /* number of nodes reachable from entry (BFS); marks reach[i] = 1 */
 int64_t lvg_reachable(const uint32_t *adj, int64_t n, int32_t R, uint32_t entry,
                       uint8_t *reach) {

@@ -1,0 +1,95 @@
+"""GPU parity: LVQ encoding (bit-exact), float16 secondaries (bit-exact), and the
+bfloat16 matrix-core projection (exact on bfloat16-representable inputs,
+stated error bound otherwise)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import fit as ofit
+from oracle import lvq as olvq
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2312_16335_amd as lv
+
+    lv.load()
+    return lv
+
+
+DEV = "cuda:0"
+
+
+@pytest.mark.parametrize("bits,d,n", [(8, 160, 3001), (8, 32, 777), (4, 128, 2049), (4, 8, 65),
+                                      (8, 512, 130), (8, 1024, 33)])
+def test_lvq_encode_bit_exact(lv, bits, d, n):
+    rng = np.random.default_rng(d + bits)
+    Y = (rng.standard_normal((n, d)) * rng.uniform(1e-3, 10, (n, 1))).astype(np.float32)
+    Y[0] = 0.25  # constant row: delta = 0
+    mu = (0.1 * rng.standard_normal(d)).astype(np.float32)
+    stride = lv.lv_record_stride(d, bits)
+    c, delta, lo = olvq.encode(Y, mu, bits)
+    want = olvq.pack_records(c, delta, lo, bits, stride)
+    rec = torch.full((n, stride), 0xAB, dtype=torch.uint8, device=DEV)
+    lv.lv_lvq_encode(torch.from_numpy(Y).to(DEV), torch.from_numpy(mu).to(DEV), bits, rec)
+    got = rec.cpu().numpy()
+    assert np.array_equal(got, want)
+
+
+def test_lvq_encode_empty_and_errors(lv):
+    Y = torch.zeros((0, 16), device=DEV)
+    mu = torch.zeros(16, device=DEV)
+    rec = torch.zeros((0, 64), dtype=torch.uint8, device=DEV)
+    lv.lv_lvq_encode(Y, mu, 8, rec)
+    with pytest.raises(lv.LVError):
+        lv.lv_lvq_encode(torch.zeros((4, 16), device=DEV), mu, 3,
+                         torch.zeros((4, 64), dtype=torch.uint8, device=DEV))
+
+
+def test_f16_secondaries_bit_exact(lv):
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.standard_normal(100_003).astype(np.float32),
+                        np.array([65504, 65520, 1e-8, -6e-8, 3e-5, 0.0, -0.0], np.float32)])
+    out = torch.empty(x.size, dtype=torch.float16, device=DEV)
+    lv.lv_to_f16(torch.from_numpy(x).to(DEV), out)
+    assert np.array_equal(out.cpu().numpy().view(np.uint16), x.astype(np.float16).view(np.uint16))
+
+
+@pytest.mark.parametrize("rows,D,d", [(1000, 768, 160), (77, 128, 32), (300, 512, 128),
+                                      (33, 64, 300), (5, 8, 1)])
+def test_projection_exact_on_bf16_integers(lv, rows, D, d):
+    # small integers are exact in bfloat16 and their products sum exactly in
+    # float32, so any lane-layout or indexing mistake shows up as a mismatch
+    rng = np.random.default_rng(rows + D)
+    V = rng.integers(-8, 9, size=(rows, D)).astype(np.float32)
+    M = rng.integers(-4, 5, size=(d, D)).astype(np.float64)
+    want = V.astype(np.float64) @ M.T
+    assert np.abs(want).max() < 2 ** 24
+    Mb = torch.from_numpy(lv.lv_to_bf16(M).view(np.int16)).to(DEV)
+    out = torch.full((rows, d), np.nan, dtype=torch.float32, device=DEV)
+    lv.lv_project(torch.from_numpy(V).to(DEV), Mb, out)
+    assert np.array_equal(out.cpu().numpy().astype(np.float64), want)
+
+
+def test_projection_error_against_float64(lv):
+    rng = np.random.default_rng(9)
+    V = rng.standard_normal((4096, 768)).astype(np.float32)
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    M, _ = np.linalg.qr(rng.standard_normal((768, 160)))
+    M = M.T
+    Mb = torch.from_numpy(lv.lv_to_bf16(M).view(np.int16)).to(DEV)
+    out = torch.empty((4096, 160), dtype=torch.float32, device=DEV)
+    lv.lv_project(torch.from_numpy(V).to(DEV), Mb, out)
+    got = out.cpu().numpy().astype(np.float64)
+    want = ofit.project(V, M)
+    # each product carries at most two bfloat16 roundings (2 * 2^-9 relative)
+    # plus float32 accumulation: bound by 2^-7 * sum_j |v_j m_j|
+    bound = 2.0 ** -7 * (np.abs(V.astype(np.float64)) @ np.abs(M).T) + 1e-6
+    assert np.all(np.abs(got - want) <= bound)
+    rel_rms = np.sqrt(np.mean((got - want) ** 2) / np.mean(want ** 2))
+    assert rel_rms < 5e-3

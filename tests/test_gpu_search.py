@@ -1,0 +1,173 @@
+"""GPU parity of the graph search against the float64 oracle.
+
+Inputs come from synth (data, graph) and the oracle (projection, LVQ codes);
+both sides walk the same graph with the same reduced vectors.  Bar: ids equal
+the oracle's (ties resolved by the same total order), scores within 1e-4
+relative, expansion counts equal (exact visited set) and primary-scoring
+counts equal with an exact-size visited set, >= with a small one.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_common import Case, make_case, stride_for
+from oracle import exact
+from oracle import lvq as olvq
+from oracle import search as osearch
+from synth import gen, graph
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def lv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2312_16335_amd as lv
+
+    lv.load()
+    return lv
+
+
+def gpu_index(lv, c: Case):
+    Yd = torch.from_numpy(c.Y).to(DEV)
+    mud = torch.from_numpy(c.mu).to(DEV)
+    rec = torch.empty((c.wl.N, c.stride), dtype=torch.uint8, device=DEV)
+    lv.lv_lvq_encode(Yd, mud, c.wl.bits, rec)
+    sec = torch.from_numpy(c.sec).to(DEV)
+    adj = torch.from_numpy(c.adj.view(np.int32)).to(DEV)
+    Pb = torch.from_numpy(lv.lv_to_bf16(c.P).view(np.int16)).to(DEV)
+    return lv.Index(rec, mud, sec, adj, c.entry, c.wl.bits, c.wl.d, A_bf16=Pb), rec
+
+
+def run_projected(lv, index, c: Case, k, L, hash_slots=0, Q=None, Qp=None):
+    Q = c.Q if Q is None else Q
+    Qp = c.Qp if Qp is None else Qp
+    m = len(Q)
+    ids = torch.full((m, k), 7, dtype=torch.int32, device=DEV)
+    sc = torch.full((m, k), 7.0, dtype=torch.float32, device=DEV)
+    cnt = torch.zeros((m, 2), dtype=torch.int32, device=DEV)
+    lv.lv_search_projected(index, torch.from_numpy(Q).to(DEV), torch.from_numpy(Qp).to(DEV), k, L,
+                           ids, sc, cnt, hash_slots=hash_slots)
+    torch.cuda.synchronize()
+    return (ids.cpu().numpy().view(np.uint32).astype(np.int64), sc.cpu().numpy(),
+            cnt.cpu().numpy())
+
+
+def assert_parity(c, oidx, got_ids, got_sc, want_ids, want_sc):
+    sent = osearch.SENTINEL
+    mism = got_ids != want_ids
+    if mism.any():
+        # tolerate only swaps of exactly tied secondary scores
+        for qi in np.unique(np.nonzero(mism)[0]):
+            g = [int(x) for x in got_ids[qi] if x != sent]
+            w = [int(x) for x in want_ids[qi] if x != sent]
+            sg = osearch.secondary_scores(oidx, c.Q[qi].astype(np.float64), g)
+            sw = osearch.secondary_scores(oidx, c.Q[qi].astype(np.float64), w)
+            assert np.allclose(np.sort(sg), np.sort(sw), rtol=0, atol=1e-12), f"query {qi}"
+    finite = np.isfinite(want_sc)
+    assert np.array_equal(np.isfinite(got_sc), finite)
+    scale = np.maximum(np.abs(want_sc[finite]), 1.0)
+    assert np.all(np.abs(got_sc[finite] - want_sc[finite]) <= 1e-4 * scale)
+
+
+@pytest.fixture(scope="module")
+def small():
+    return make_case(gen.WORKLOADS["id-small"])
+
+
+def test_encoded_records_match_oracle(lv, small):
+    index, rec = gpu_index(lv, small)
+    c, dl, lo = olvq.encode(small.Y, small.mu, small.wl.bits)
+    assert np.array_equal(rec.cpu().numpy(), olvq.pack_records(c, dl, lo, small.wl.bits,
+                                                               small.stride))
+
+
+@pytest.mark.parametrize("k,L", [(10, 50), (1, 1), (10, 10), (100, 128), (5, 300)])
+def test_search_parity_small(lv, small, k, L):
+    index, _ = gpu_index(lv, small)
+    oidx = small.oracle_index()
+    want_ids, want_sc, want_cnt = osearch.search_many(oidx, small.Q, small.Qp, k, L)
+    got_ids, got_sc, got_cnt = run_projected(lv, index, small, k, L, hash_slots=16384)
+    assert_parity(small, oidx, got_ids, got_sc, want_ids, want_sc)
+    assert np.array_equal(got_cnt[:, 0], want_cnt[:, 0])
+    assert np.array_equal(got_cnt[:, 1], want_cnt[:, 1])
+
+
+def test_small_visited_hash_changes_nothing(lv, small):
+    index, _ = gpu_index(lv, small)
+    ref = run_projected(lv, index, small, 10, 200, hash_slots=16384)
+    for hs in (256, 1024):
+        got = run_projected(lv, index, small, 10, 200, hash_slots=hs)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+        assert np.array_equal(got[2][:, 0], ref[2][:, 0])
+        assert np.all(got[2][:, 1] >= ref[2][:, 1])
+
+
+def test_full_window_is_exact_knn(lv):
+    wl = gen.WORKLOADS["id-small"].scaled(N=900, m_test=8)
+    c = make_case(wl)
+    assert graph.reachable(c.adj, c.entry).all()
+    index, _ = gpu_index(lv, c)
+    got_ids, got_sc, _ = run_projected(lv, index, c, 10, 1024)
+    truth = exact.ground_truth(c.Q, c.X, 10)
+    assert np.array_equal(got_ids, truth)
+
+
+def test_ragged_and_empty_batches(lv, small):
+    index, _ = gpu_index(lv, small)
+    oidx = small.oracle_index()
+    for m in (1, 3, 65):
+        Q, Qp = small.Q[:m], small.Qp[:m]
+        want = osearch.search_many(oidx, Q, Qp, 10, 50)
+        got = run_projected(lv, index, small, 10, 50, Q=Q, Qp=Qp)
+        assert np.array_equal(got[0], want[0])
+    z = run_projected(lv, index, small, 10, 50, Q=small.Q[:0], Qp=small.Qp[:0])
+    assert z[0].shape == (0, 10)
+
+
+def test_unreachable_tail_is_padded(lv):
+    # a graph where the entry reaches only 3 nodes: results pad with sentinel / -inf
+    wl = gen.WORKLOADS["id-small"].scaled(N=64, m_test=2)
+    c = make_case(wl)
+    adj = np.full_like(c.adj, osearch.SENTINEL)
+    others = [i for i in range(wl.N) if i != c.entry][:2]
+    adj[c.entry, :2] = others
+    c.adj = adj
+    index, _ = gpu_index(lv, c)
+    got_ids, got_sc, _ = run_projected(lv, index, c, 5, 8)
+    want_ids, want_sc, _ = osearch.search_many(c.oracle_index(), c.Q, c.Qp, 5, 8)
+    assert np.array_equal(got_ids, want_ids)
+    assert np.all(got_ids[:, 3:] == osearch.SENTINEL) and np.all(np.isneginf(got_sc[:, 3:]))
+
+
+@pytest.mark.parametrize("name,N", [("ood-1m-512", 6000), ("id-1m-768", 6000)])
+def test_search_parity_lvq4_and_f16(lv, name, N):
+    wl = gen.WORKLOADS[name].scaled(N=N, m_test=40)
+    c = make_case(wl)
+    index, _ = gpu_index(lv, c)
+    oidx = c.oracle_index()
+    for L in (20, 60):
+        want_ids, want_sc, want_cnt = osearch.search_many(oidx, c.Q, c.Qp, wl.k, L)
+        got_ids, got_sc, got_cnt = run_projected(lv, index, c, wl.k, L, hash_slots=16384)
+        assert_parity(c, oidx, got_ids, got_sc, want_ids, want_sc)
+        assert np.array_equal(got_cnt, want_cnt)
+
+
+def test_full_path_recall_matches_oracle(lv, small):
+    # end to end: GPU projection (bfloat16) + search vs oracle float64 projection
+    index, _ = gpu_index(lv, small)
+    m, k, L = len(small.Q), 10, 50
+    ids = torch.empty((m, k), dtype=torch.int32, device=DEV)
+    sc = torch.empty((m, k), dtype=torch.float32, device=DEV)
+    ws = torch.empty(lv.lv_search_workspace_size(index, m), dtype=torch.uint8, device=DEV)
+    lv.lv_search(index, torch.from_numpy(small.Q).to(DEV), k, L, ids, sc, ws=ws)
+    torch.cuda.synchronize()
+    got = ids.cpu().numpy().view(np.uint32).astype(np.int64)
+    want, _, _ = osearch.search_many(small.oracle_index(), small.Q, small.Qp, k, L)
+    truth = exact.ground_truth(small.Q, small.X, k)
+    r_gpu = exact.recall_at_k(got, truth, k)
+    r_orc = exact.recall_at_k(want, truth, k)
+    assert abs(r_gpu - r_orc) <= 0.005 + 1e-12, (r_gpu, r_orc)
