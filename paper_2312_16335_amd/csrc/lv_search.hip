@@ -510,7 +510,12 @@ int launch_beam(const lv_index *ix, const float *Q, const float *Qp, int64_t m, 
   a.hash_log2 = log2h;
   a.max_hops = (uint32_t)dsc.N + 1u;  // every node is expanded at most once
   const size_t lds = beam_lds_bytes(L, log2h);
-  if (lds > 64 * 1024) LV_FAIL(LV_EINVAL, "window %d with %d hash slots exceeds LDS", L, hs);
+  int dev = 0, lds_max = 0;
+  LV_CHECK_HIP(hipGetDevice(&dev));
+  LV_CHECK_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if (lds > (size_t)lds_max)
+    LV_FAIL(LV_EINVAL, "window %d with %d hash slots needs %zu bytes of LDS (limit %d)", L, hs,
+            lds, lds_max);
   const int key = ix->group * 100 + ix->vbytes;
   if (dsc.bits == 8) {
     switch (key) {

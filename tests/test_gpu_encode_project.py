@@ -32,7 +32,8 @@ def test_lvq_encode_bit_exact(lv, bits, d, n):
     Y = (rng.standard_normal((n, d)) * rng.uniform(1e-3, 10, (n, 1))).astype(np.float32)
     Y[0] = 0.25  # constant row: delta = 0
     mu = (0.1 * rng.standard_normal(d)).astype(np.float32)
-    stride = lv.lv_record_stride(d, bits)
+    # the search's stride where one exists, else any multiple of 4 that fits
+    stride = lv.lv_record_stride(d, bits) or (d * bits // 8 + 12)
     c, delta, lo = olvq.encode(Y, mu, bits)
     want = olvq.pack_records(c, delta, lo, bits, stride)
     rec = torch.full((n, stride), 0xAB, dtype=torch.uint8, device=DEV)

@@ -90,7 +90,7 @@ def test_search_parity_small(lv, small, k, L):
     index, _ = gpu_index(lv, small)
     oidx = small.oracle_index()
     want_ids, want_sc, want_cnt = osearch.search_many(oidx, small.Q, small.Qp, k, L)
-    got_ids, got_sc, got_cnt = run_projected(lv, index, small, k, L, hash_slots=16384)
+    got_ids, got_sc, got_cnt = run_projected(lv, index, small, k, L, hash_slots=8192)
     assert_parity(small, oidx, got_ids, got_sc, want_ids, want_sc)
     assert np.array_equal(got_cnt[:, 0], want_cnt[:, 0])
     assert np.array_equal(got_cnt[:, 1], want_cnt[:, 1])
@@ -98,7 +98,7 @@ def test_search_parity_small(lv, small, k, L):
 
 def test_small_visited_hash_changes_nothing(lv, small):
     index, _ = gpu_index(lv, small)
-    ref = run_projected(lv, index, small, 10, 200, hash_slots=16384)
+    ref = run_projected(lv, index, small, 10, 200, hash_slots=8192)
     for hs in (256, 1024):
         got = run_projected(lv, index, small, 10, 200, hash_slots=hs)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
@@ -151,7 +151,7 @@ def test_search_parity_lvq4_and_f16(lv, name, N):
     oidx = c.oracle_index()
     for L in (20, 60):
         want_ids, want_sc, want_cnt = osearch.search_many(oidx, c.Q, c.Qp, wl.k, L)
-        got_ids, got_sc, got_cnt = run_projected(lv, index, c, wl.k, L, hash_slots=16384)
+        got_ids, got_sc, got_cnt = run_projected(lv, index, c, wl.k, L, hash_slots=8192)
         assert_parity(c, oidx, got_ids, got_sc, want_ids, want_sc)
         assert np.array_equal(got_cnt, want_cnt)
 
