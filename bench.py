@@ -1,0 +1,415 @@
+"""Benchmark: LeanVec search QPS at 10-recall@10 = 0.90 on one MI355X.
+
+Workload (synthetic stand-in for the paper's rqa-768-1M, Table 1): 1M
+database vectors of dimension 768 drawn from a 1,000-cluster mixture with a
+1/i spectrum (L2-normalised), 10,000 test queries from the same mixture,
+LeanVec-ID projection to d = 160, LVQ-8 primary records, float16 secondary
+vectors, graph out-degree 64.  Index preparation (data, fit, projection,
+encoding, graph, ground truth) is untimed.
+
+A step is one pass of the hot path over the whole query set: query
+projection on the matrix cores, then the per-query traversal + re-ranking
+kernel, at the smallest window L whose recall reaches 0.90 (found by a sweep
+before the timed region).  The query set arrives as a stream of requests of
+uneven size (uniform in [1, 4096]); "plain" launches one search per request.
+
+Prints one JSON line (rank 0).  Extra fields: the recall/QPS sweep, the
+interpolated QPS at exactly 0.90, the roofline of the traversal kernel, and
+the float64 CPU oracle timed on a bounded sample (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="id-1m-768")
+    ap.add_argument("--n", type=int, default=0, help="override database size (testing)")
+    ap.add_argument("--target", type=float, default=0.90)
+    ap.add_argument("--hash-slots", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1000)
+    ap.add_argument("--only-steps", action="store_true",
+                    help="skip the sweep refinement (profiling runs)")
+    ap.add_argument("--L", type=int, default=0, help="fixed window (skips the sweep)")
+    return ap.parse_args()
+
+
+def cache_dir():
+    d = os.environ.get("LV_CACHE", "/tmp/lv_cache")
+    os.makedirs(d, exist_ok=True)
+    return d
+
+
+def build_graph_cached(wl, X, out):
+    from synth import graph
+
+    key = f"{wl.name}_s{wl.seed_data}_n{wl.N}_R{wl.R}_a{'-'.join(map(str, wl.graph_alphas))}_v3"
+    p = os.path.join(cache_dir(), key + ".npz")
+    if os.path.exists(p):
+        z = np.load(p)
+        out["adj"], out["entry"] = z["adj"], int(z["entry"])
+        out["graph_s"] = 0.0
+        return
+    t = time.time()
+    adj, entry = graph.build_graph(X, wl.R, alphas=wl.graph_alphas)
+    out["graph_s"] = time.time() - t
+    np.savez(p + ".tmp.npz", adj=adj, entry=np.int64(entry))
+    os.replace(p + ".tmp.npz", p)
+    out["adj"], out["entry"] = adj, entry
+
+
+def ground_truth_gpu(torch, Xd, Q, k):
+    """Exact top-k ids by <q, x> (float32 candidates, float64 re-scoring)."""
+    dev = Xd.device
+    m = len(Q)
+    cand_k = 64
+    Qd = torch.from_numpy(Q).to(dev)
+    best_s = torch.full((m, 0), -math.inf, device=dev)
+    best_i = torch.zeros((m, 0), dtype=torch.int64, device=dev)
+    for lo in range(0, Xd.shape[0], 1 << 18):
+        S = Qd @ Xd[lo:lo + (1 << 18)].T
+        s, i = torch.topk(S, min(cand_k, S.shape[1]), dim=1)
+        best_s = torch.cat([best_s, s], 1)
+        best_i = torch.cat([best_i, i + lo], 1)
+        s, j = torch.topk(best_s, min(cand_k, best_s.shape[1]), dim=1)
+        best_s, best_i = s, torch.gather(best_i, 1, j)
+    # float64 re-score of the candidates, ties to the smaller id
+    cand = best_i
+    Xc = Xd[cand.reshape(-1)].reshape(m, cand.shape[1], -1).double()
+    s64 = torch.einsum("mkd,md->mk", Xc, Qd.double())
+    s64 = s64.cpu().numpy()
+    ci = cand.cpu().numpy()
+    out = np.empty((m, k), dtype=np.int64)
+    for r in range(m):
+        order = np.lexsort((ci[r], -s64[r]))[:k]
+        out[r] = ci[r][order]
+    return out
+
+
+def recall(ids, truth, k):
+    hit = 0
+    for a, b in zip(ids[:, :k], truth[:, :k]):
+        hit += len(set(a.tolist()) & set(b.tolist()))
+    return hit / (k * len(truth))
+
+
+def profile_traffic(kernel_src):
+    """HBM bytes per launch from committed counter runs, if the kernel is unchanged."""
+    p = os.path.join(ROOT, "profiles", "beam_id-1m-768_counters.md")
+    if not os.path.exists(p):
+        return None
+    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    vals = {}
+    for line in open(p):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this implementation runs on exactly one GPU; "
+                                   "--gpus %d is not supported (query or database sharding "
+                                   "across GPUs is described in DESIGN.md, not built)" % args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_2312_16335_amd as lv
+    from synth import gen
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    lv.load()
+    dev = torch.device("cuda:0")
+    wl = gen.WORKLOADS[args.workload]
+    if args.n:
+        wl = wl.scaled(N=args.n)
+    k = wl.k
+    t0 = time.time()
+    mix = gen.mixture(wl)
+    X = gen.database(wl, mix)
+    Q = gen.queries(wl, "test", mix=mix)
+    log(f"data {X.shape} queries {Q.shape} in {time.time() - t0:.1f}s")
+
+    g = {}
+    th = threading.Thread(target=build_graph_cached, args=(wl, X, g))
+    th.start()
+
+    # ---- index side: fit (host float64), projection + encoding (GPU)
+    rng = np.random.default_rng(7)
+    ns = min(wl.N, 100_000)  # uniform subsample for the second moment (Section 2.2)
+    sub = np.sort(rng.choice(wl.N, size=ns, replace=False))
+    Xs = np.ascontiguousarray(X[sub])
+    K = np.zeros((wl.D, wl.D))
+    ssum = np.zeros(wl.D)
+    lv.lv_second_moment(Xs, K, ssum)
+    P = lv.lv_fit_id(K, wl.d)
+    mu = lv.lv_mean_reduced(P, ssum, ns)
+    Pb = torch.from_numpy(lv.lv_to_bf16(P).view(np.int16)).to(dev)
+    mud = torch.from_numpy(mu).to(dev)
+    Xd = torch.from_numpy(X).to(dev)
+    stride = lv.lv_record_stride(wl.d, wl.bits)
+    rec = torch.empty((wl.N, stride), dtype=torch.uint8, device=dev)
+    Y = torch.empty((wl.N, wl.d), dtype=torch.float32, device=dev)
+    sec = torch.empty((wl.N, wl.D), dtype=torch.float16, device=dev)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    lv.lv_project(Xd, Pb, Y)
+    ev1.record()
+    lv.lv_lvq_encode(Y, mud, wl.bits, rec)
+    lv.lv_to_f16(Xd, sec)
+    torch.cuda.synchronize()
+    db_proj_ms = ev0.elapsed_time(ev1)
+    truth = ground_truth_gpu(torch, Xd, Q, k)
+    del Y
+    Xd = None
+    torch.cuda.empty_cache()
+    log(f"fit + encode + ground truth done at {time.time() - t0:.1f}s")
+    th.join()
+    adj, entry = g["adj"], g["entry"]
+    log(f"graph ready at {time.time() - t0:.1f}s (build {g['graph_s']:.1f}s)")
+    adjd = torch.from_numpy(adj.view(np.int32)).to(dev)
+    index = lv.Index(rec, mud, sec, adjd, entry, wl.bits, wl.d, A_bf16=Pb)
+
+    # ---- request stream over the test queries (uneven batches)
+    m = len(Q)
+    sizes = []
+    rs = np.random.Generator(np.random.PCG64(401))
+    left = m
+    while left > 0:
+        b = int(min(left, rs.integers(1, 4097)))
+        sizes.append(b)
+        left -= b
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    Qd = torch.from_numpy(Q).to(dev)
+    Qp = torch.empty((m, wl.d), dtype=torch.float32, device=dev)
+    ids = torch.empty((m, k), dtype=torch.int32, device=dev)
+    scores = torch.empty((m, k), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(L, ev=None):
+        """One pass over the request stream; optional per-kernel events."""
+        for i, b in enumerate(sizes):
+            lo, hi = int(offs[i]), int(offs[i + 1])
+            if ev is not None:
+                ev[0][i].record(stream)
+            lv.lv_project(Qd[lo:hi], Pb, Qp[lo:hi])
+            if ev is not None:
+                ev[1][i].record(stream)
+            lv.lv_search_projected(index, Qd[lo:hi], Qp[lo:hi], k, L, ids[lo:hi],
+                                   scores[lo:hi], hash_slots=args.hash_slots)
+            if ev is not None:
+                ev[2][i].record(stream)
+
+    def measure(L, reps=3):
+        step(L)
+        torch.cuda.synchronize()
+        best = math.inf
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            step(L)
+            b.record()
+            torch.cuda.synchronize()
+            best = min(best, a.elapsed_time(b))
+        got = ids.cpu().numpy().view(np.uint32).astype(np.int64)
+        return recall(got, truth, k), m / (best / 1e3)
+
+    sweep = {}
+    if args.L:
+        L_star = args.L
+        sweep[L_star] = measure(L_star)
+    else:
+        for L in sorted(set(list(wl.L_list) + [k])):
+            if L < k:
+                continue
+            sweep[L] = measure(L)
+            log(f"L={L}: recall {sweep[L][0]:.4f}, {sweep[L][1]:.0f} QPS")
+            if sweep[L][0] >= args.target:
+                break
+        reach = [L for L, (r, _) in sweep.items() if r >= args.target]
+        if not reach:
+            L = max(sweep)
+            while L < 1024:
+                L = min(1024, int(L * 1.5))
+                sweep[L] = measure(L)
+                log(f"L={L}: recall {sweep[L][0]:.4f}")
+                if sweep[L][0] >= args.target:
+                    break
+            reach = [L for L, (r, _) in sweep.items() if r >= args.target]
+        L_hi = min(reach) if reach else max(sweep)
+        lower = [L for L in sweep if L < L_hi]
+        L_lo = max(lower) if lower else L_hi
+        if not args.only_steps:
+            # refine: smallest window in (L_lo, L_hi] reaching the target
+            lo_, hi_ = L_lo, L_hi
+            while hi_ - lo_ > max(1, hi_ // 20):
+                mid = (lo_ + hi_) // 2
+                sweep[mid] = measure(mid)
+                if sweep[mid][0] >= args.target:
+                    hi_ = mid
+                else:
+                    lo_ = mid
+            L_hi = hi_
+        L_star = L_hi
+
+    # interpolated QPS at exactly the target recall, in (recall, log QPS)
+    pts = sorted(sweep.items())
+    qps_interp = None
+    for (La, (ra, qa)), (Lb, (rb, qb)) in zip(pts, pts[1:]):
+        if ra < args.target <= rb and rb > ra:
+            w = (args.target - ra) / (rb - ra)
+            qps_interp = math.exp(math.log(qa) + w * (math.log(qb) - math.log(qa)))
+    log(f"operating window L={L_star}")
+
+    # ---- algorithmic bytes per query at L* from the debug counters (exact visited set)
+    cnt = torch.zeros((m, 2), dtype=torch.int32, device=dev)
+    lv.lv_search_projected(index, Qd, Qp, k, L_star, ids, scores, cnt, hash_slots=8192)
+    torch.cuda.synchronize()
+    c = cnt.cpu().numpy().astype(np.float64)
+    n_exp, n_dist = c[:, 0], c[:, 1]
+    n_rr = np.minimum(L_star, n_dist)
+    code_bytes = wl.d * wl.bits // 8
+    esec = 2
+    bytes_q = (4 * wl.D + n_exp * 4 * wl.R + n_dist * (code_bytes + 8) + n_rr * wl.D * esec
+               + 8 * k)
+    alg_bytes_total = float(bytes_q.sum())
+
+    # ---- timed region
+    nreq = len(sizes)
+    for _ in range(args.warmup):
+        step(L_star)
+    torch.cuda.synchronize()
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(nreq)] for _ in range(3)]
+           for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record()
+    for s in range(args.steps):
+        step(L_star, evs[s])
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t_start.elapsed_time(t_end)
+    proj_ms = sum(evs[s][0][i].elapsed_time(evs[s][1][i]) for s in range(args.steps)
+                  for i in range(nreq))
+    beam_ms = sum(evs[s][1][i].elapsed_time(evs[s][2][i]) for s in range(args.steps)
+                  for i in range(nreq))
+    ms_per_step = total_ms / args.steps
+    qps = m * args.steps / (total_ms / 1e3)
+    got = ids.cpu().numpy().view(np.uint32).astype(np.int64)
+    rec_star = recall(got, truth, k)
+    beam_launch_ms = beam_ms / (args.steps * nreq)
+    achieved = (alg_bytes_total / nreq) / (beam_launch_ms / 1e3) / 1e9
+    traffic = profile_traffic(os.path.join(ROOT, "paper_2312_16335_amd", "csrc", "lv_search.hip"))
+
+    # ---- CPU oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, X, Q, adj, entry, K, ssum, ns, L_star, args.cpu_sample)
+
+    out = {
+        "metric": "QPS at 10-recall@10=0.90 (1M x 768, d=160), batched vs plain; HBM GB/s",
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "N": wl.N, "D": wl.D, "d": wl.d, "lvq_bits": wl.bits,
+                   "secondary": wl.sec_dtype, "R": wl.R, "k": k, "queries": m, "L": L_star,
+                   "requests": nreq, "mode": "plain"},
+        "recall_at_L": rec_star,
+        "qps_interp_at_target": qps_interp,
+        "sweep": {str(L): {"recall": r, "qps": q} for L, (r, q) in sorted(sweep.items())},
+        "wall_s_timed": wall,
+        "per_query": {"expansions": float(n_exp.mean()), "primary_scorings": float(n_dist.mean()),
+                      "reranked": float(n_rr.mean()), "alg_bytes": float(bytes_q.mean())},
+        "kernels_ms_per_step": {"query_projection": proj_ms / args.steps,
+                                "traversal": beam_ms / args.steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "beam_kernel (traversal + re-rank)"},
+        "index_build": {"db_projection_ms": db_proj_ms, "graph_build_s": g.get("graph_s")},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(wl, X, Q, adj, entry, K, ssum, ns, L, sample):
+    """The float64 oracle, timed on a bounded query sample over all host cores."""
+    from oracle import fit as ofit
+    from oracle import lvq as olvq
+    from oracle import search as osearch
+
+    t = time.time()
+    P = ofit.fit_id(K, wl.d)
+    mu = (P @ (ssum / ns)).astype(np.float32)
+    Y = np.empty((wl.N, wl.d), dtype=np.float32)
+    for lo in range(0, wl.N, 1 << 17):
+        Y[lo:lo + (1 << 17)] = ofit.project(X[lo:lo + (1 << 17)], P)
+    Qp = ofit.project(Q, P).astype(np.float32)
+    codes, delta, lo_ = olvq.encode(Y, mu, wl.bits)
+    index = osearch.Index(adj, entry, codes, delta, lo_, mu, X.astype(np.float16))
+    log(f"oracle index ready in {time.time() - t:.1f}s")
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    n = min(sample, len(Q))
+    t = time.perf_counter()
+    osearch.search_many(index, Q[:n], Qp[:n], wl.k, L, procs=procs, chunk=16)
+    dt = time.perf_counter() - t
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    log(f"oracle: {n} queries in {dt:.1f}s on {procs} processes")
+    return {"value": n / dt, "unit": "queries/s", "cores": procs, "kind": "oracle",
+            "sample": f"first {n} of {len(Q)} test queries, window L={L}, float64 numpy "
+                      f"oracle, one process per core (includes process start-up)",
+            "cpu_model": model}
+
+
+if __name__ == "__main__":
+    main()

@@ -142,7 +142,17 @@ int lv_fit_es(const double *KQ, int64_t m, const double *KX, int64_t n, int32_t 
 int lv_ood_loss(const double *KQ, int64_t m, const double *KX, int64_t n, int32_t D, int32_t d,
                 const double *A, const double *B, double *f);
 
-/* Host float64 -> bfloat16 (round to nearest even), for the device projections. */
+/*
+ * LVQ centring vector mu = M (sum / n): the projection of the mean of the
+ * vectors whose sum lv_second_moment accumulated, rounded to float32.
+ *   M: host float64 [d][D]; sum: host float64 [D]; mu: host float32 [d] out
+ * Errors: LV_EINVAL for NULL pointers, n < 1 or bad sizes.
+ */
+int lv_mean_reduced(const double *M, int32_t d, int32_t D, const double *sum, int64_t n,
+                    float *mu);
+
+/* Host float64 -> float32 -> bfloat16 (each step round to nearest even),
+ * for the device projections. */
 int lv_to_bf16(const double *src, int64_t count, uint16_t *dst);
 
 /* ------------------------------------------------------------------------

@@ -249,11 +249,15 @@ def search_many(index: Index, Q, Qp, k: int, L: int, procs: int = 1,
         if not os.path.exists(p):
             np.save(p, np.ascontiguousarray(arr))
         paths[name] = p
+    from concurrent.futures import ProcessPoolExecutor
+
     try:
-        ctx = mp.get_context("spawn")
-        with ctx.Pool(procs, initializer=_init_worker, initargs=(paths, int(index.entry))) as pool:
+        # a worker that dies raises BrokenProcessPool here instead of hanging
+        with ProcessPoolExecutor(procs, mp_context=mp.get_context("spawn"),
+                                 initializer=_init_worker,
+                                 initargs=(paths, int(index.entry))) as pool:
             jobs = [(Q[lo:lo + chunk], Qp[lo:lo + chunk], k, L, lo) for lo in range(0, m, chunk)]
-            for lo, a, b, c in pool.imap_unordered(_run_chunk, jobs):
+            for lo, a, b, c in pool.map(_run_chunk, jobs):
                 ids[lo:lo + len(a)], sc[lo:lo + len(a)], cnt[lo:lo + len(a)] = a, b, c
     finally:
         if own:

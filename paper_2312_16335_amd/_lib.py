@@ -61,6 +61,7 @@ _SIGS = {
     "lv_fit_ood": (_c_i32, [_vp, _c_i64, _vp, _c_i64, _c_i32, _c_i32, _vp, _vp, _vp, _vp]),
     "lv_fit_es": (_c_i32, [_vp, _c_i64, _vp, _c_i64, _c_i32, _c_i32, _c_dbl, _vp, _vp]),
     "lv_ood_loss": (_c_i32, [_vp, _c_i64, _vp, _c_i64, _c_i32, _c_i32, _vp, _vp, _vp]),
+    "lv_mean_reduced": (_c_i32, [_vp, _c_i32, _c_i32, _vp, _c_i64, _vp]),
     "lv_to_bf16": (_c_i32, [_vp, _c_i64, _vp]),
     "lv_project": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _vp]),
     "lv_record_stride": (_c_i32, [_c_i32, _c_i32]),
@@ -196,6 +197,14 @@ def lv_ood_loss(KQ, m, KX, n, A, B) -> float:
     _check(load().lv_ood_loss(KQ.ctypes.data, m, KX.ctypes.data, n, KQ.shape[0], A.shape[0],
                               A.ctypes.data, B.ctypes.data, ctypes.byref(f)))
     return f.value
+
+
+def lv_mean_reduced(M: np.ndarray, sum_: np.ndarray, n: int) -> np.ndarray:
+    M = _host(M, np.float64)
+    mu = np.empty(M.shape[0], np.float32)
+    _check(load().lv_mean_reduced(M.ctypes.data, M.shape[0], M.shape[1],
+                                  _host(sum_, np.float64).ctypes.data, n, mu.ctypes.data))
+    return mu
 
 
 def lv_to_bf16(M: np.ndarray) -> np.ndarray:

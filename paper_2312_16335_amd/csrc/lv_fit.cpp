@@ -487,3 +487,16 @@ extern "C" int lv_to_bf16(const double *src, int64_t count, uint16_t *dst) {
   }
   return LV_OK;
 }
+
+extern "C" int lv_mean_reduced(const double *M, int32_t d, int32_t D, const double *sum,
+                               int64_t n, float *mu) {
+  lv::clear_error();
+  if (!M || !sum || !mu) LV_FAIL(LV_EINVAL, "NULL pointer");
+  if (d < 1 || D < 1 || n < 1) LV_FAIL(LV_EINVAL, "bad sizes");
+  for (int i = 0; i < d; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < D; ++j) s += M[(size_t)i * D + j] * (sum[j] / (double)n);
+    mu[i] = (float)s;
+  }
+  return LV_OK;
+}

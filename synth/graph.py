@@ -62,13 +62,14 @@ def build_graph(X: np.ndarray, R: int, L: int = 0, metric: int = METRIC_L2,
                 threads: int = 0) -> Tuple[np.ndarray, int]:
     """Graph over the rows of X.
 
-    The default is the Euclidean rule with alpha 1.0 then 1.2 (the paper's
+    Rows are rounded to float16 (as the secondary vectors are).  The
+    default is the Euclidean rule with alpha 1.0 then 1.2 (the paper's
     Euclidean setting); on unit-norm rows it ranks neighbours exactly as
     inner product does.  L defaults to 2R (search window during
     construction); maxc caps the pruning pool (default 2R).  Deterministic
     for any thread count.
     """
-    X = np.ascontiguousarray(X, dtype=np.float32)
+    X = _as_f16(X)
     n, dim = X.shape
     L = L or 2 * R
     maxc = maxc or 2 * R
@@ -92,5 +93,12 @@ def reachable(adj: np.ndarray, entry: int) -> np.ndarray:
 
 
 def medoid(X: np.ndarray) -> int:
-    X = np.ascontiguousarray(X, dtype=np.float32)
+    X = _as_f16(X)
     return int(_load().lvg_medoid(X.ctypes.data, X.shape[0], X.shape[1]))
+
+
+def _as_f16(X: np.ndarray) -> np.ndarray:
+    """The builder works on float16 copies (round to nearest even)."""
+    if X.dtype == np.float16 and X.flags.c_contiguous:
+        return X
+    return np.ascontiguousarray(X, dtype=np.float16)

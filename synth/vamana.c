@@ -19,28 +19,33 @@
  * node's new edge list is computed independently, and reverse edges are
  * applied per target in sorted source order.
  *
- * Inner products are float32, accumulated in 16 fixed lanes.
+ * Vectors are float16; inner products accumulate in float32 in a fixed order.
  * Rows of the adjacency hold the valid neighbours first, then 0xFFFFFFFF.
  */
+#include <immintrin.h>
 #include <math.h>
 #include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
+#include <stdio.h>
 #include <string.h>
+#include <time.h>
 
 #define SENT 0xFFFFFFFFu
 
-static inline float dotf(const float *a, const float *b, int n) {
-  float acc[16];
-  for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+/* vectors are float16 (IEEE binary16 bits); products accumulate in float32
+ * over 16 fixed lanes, then a fixed reduction */
+static inline float dotf(const uint16_t *a, const uint16_t *b, int n) {
+  __m512 acc = _mm512_setzero_ps();
   int i = 0;
-  for (; i + 16 <= n; i += 16)
-    for (int j = 0; j < 16; ++j) acc[j] += a[i + j] * b[i + j];
-  float t = 0.f;
-  for (; i < n; ++i) t += a[i] * b[i];
-  for (int w = 8; w >= 1; w >>= 1)
-    for (int j = 0; j < w; ++j) acc[j] += acc[j + w];
-  return acc[0] + t;
+  for (; i + 16 <= n; i += 16) {
+    __m512 x = _mm512_cvtph_ps(_mm256_loadu_si256((const __m256i *)(a + i)));
+    __m512 y = _mm512_cvtph_ps(_mm256_loadu_si256((const __m256i *)(b + i)));
+    acc = _mm512_fmadd_ps(x, y, acc);
+  }
+  float t = _mm512_reduce_add_ps(acc);
+  for (; i < n; ++i) t += _cvtsh_ss(a[i]) * _cvtsh_ss(b[i]);
+  return t;
 }
 
 typedef struct {
@@ -51,12 +56,12 @@ typedef struct {
 /* Similarity used by search and pruning.  metric 0 (Euclidean): s(a,b) =
  * -||a-b||^2 computed as 2<a,b> - |a|^2 - |b|^2; metric 1: s(a,b) = <a,b>. */
 typedef struct {
-  const float *X;
+  const uint16_t *X;
   const float *nrm; /* squared norms (metric 0) */
   int dim, metric;
 } space_t;
 
-static inline float sim(const space_t *sp, const float *qa, float qn, uint32_t b) {
+static inline float sim(const space_t *sp, const uint16_t *qa, float qn, uint32_t b) {
   float d = dotf(qa, sp->X + (size_t)b * sp->dim, sp->dim);
   if (sp->metric == 0) return 2.f * d - qn - sp->nrm[b];
   return d;
@@ -149,8 +154,8 @@ static void vis_push(scratch_t *w, float s, uint32_t id) {
 
 /* best-first beam search with window L from the entry; fills w->vis */
 static void greedy(scratch_t *w, const space_t *sp, const uint32_t *adj, int R,
-                   uint32_t entry, const float *q, float qn, int L) {
-  const float *X = sp->X;
+                   uint32_t entry, const uint16_t *q, float qn, int L) {
+  const uint16_t *X = sp->X;
   const int dim = sp->dim;
   w->stamp++;
   if (w->stamp == 0) { /* wrapped: clear stamps */
@@ -202,7 +207,7 @@ static void greedy(scratch_t *w, const space_t *sp, const uint32_t *adj, int R,
  * already filled in) using the diversity rule; writes a padded row. */
 static void prune(scratch_t *w, size_t np, const space_t *sp, uint32_t p,
                   float alpha, int R, int maxc, uint32_t *out) {
-  const float *X = sp->X;
+  const uint16_t *X = sp->X;
   const int dim = sp->dim;
   qsort(w->pool, np, sizeof(cand_t), cmp_cand);
   int nsel = 0;
@@ -214,7 +219,7 @@ static void prune(scratch_t *w, size_t np, const space_t *sp, uint32_t p,
     last = c;
     if ((int)seen >= maxc) break;
     ++seen;
-    const float *xc = X + (size_t)c * dim;
+    const uint16_t *xc = X + (size_t)c * dim;
     const float nc = sp->metric == 0 ? sp->nrm[c] : 0.f;
     int keep = 1;
     for (int j = 0; j < nsel; ++j) {
@@ -254,7 +259,7 @@ static int cmp_edge(const void *a, const void *b) {
 }
 
 /* entry = vector closest (L2) to the mean; ties to the lower id */
-uint32_t lvg_medoid(const float *X, int64_t n, int32_t dim) {
+uint32_t lvg_medoid(const uint16_t *X, int64_t n, int32_t dim) {
   const int64_t CH = 4096;
   int64_t nch = (n + CH - 1) / CH;
   double *part = (double *)calloc((size_t)nch * dim, sizeof(double));
@@ -262,7 +267,7 @@ uint32_t lvg_medoid(const float *X, int64_t n, int32_t dim) {
   for (int64_t c = 0; c < nch; ++c) {
     double *acc = part + (size_t)c * dim;
     for (int64_t i = c * CH; i < n && i < (c + 1) * CH; ++i)
-      for (int j = 0; j < dim; ++j) acc[j] += X[(size_t)i * dim + j];
+      for (int j = 0; j < dim; ++j) acc[j] += _cvtsh_ss(X[(size_t)i * dim + j]);
   }
   double *mean = (double *)calloc(dim, sizeof(double));
   for (int64_t c = 0; c < nch; ++c)
@@ -277,7 +282,7 @@ uint32_t lvg_medoid(const float *X, int64_t n, int32_t dim) {
     for (int64_t i = c * CH; i < n && i < (c + 1) * CH; ++i) {
       double s = 0.0;
       for (int j = 0; j < dim; ++j) {
-        double t = (double)X[(size_t)i * dim + j] - mean[j];
+        double t = (double)_cvtsh_ss(X[(size_t)i * dim + j]) - mean[j];
         s += t * t;
       }
       if (s < bd) { bd = s; bi = i; }
@@ -293,11 +298,11 @@ uint32_t lvg_medoid(const float *X, int64_t n, int32_t dim) {
 }
 
 /*
- * Build the graph.  X: float32 [n][dim] row-major (host).  adj: [n][R] out.
+ * Build the graph.  X: float16 bits [n][dim] row-major (host).  adj: [n][R] out.
  * alphas[npasses]: pruning factor per pass (first pass usually 1.0).
  * Returns the entry id, or -1 on bad arguments.
  */
-int64_t lvg_build(const float *X, int64_t n, int32_t dim, int32_t metric, int32_t R,
+int64_t lvg_build(const uint16_t *X, int64_t n, int32_t dim, int32_t metric, int32_t R,
                   int32_t L, int32_t maxc, const float *alphas, int32_t npasses,
                   double batch_frac, uint64_t seed, int32_t nthreads, uint32_t *adj) {
   if (!X || !adj || n < 1 || n >= (int64_t)SENT || dim < 1 || R < 1 || L < 1 ||
@@ -331,6 +336,12 @@ int64_t lvg_build(const float *X, int64_t n, int32_t dim, int32_t metric, int32_
   scratch_t *ws = (scratch_t *)malloc(sizeof(scratch_t) * nt);
   for (int t = 0; t < nt; ++t) scratch_init(&ws[t], L, R);
 
+  double last_report = 0.0;
+  {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    last_report = ts.tv_sec + 1e-9 * ts.tv_nsec;
+  }
   for (int pass = 0; pass < npasses; ++pass) {
     float alpha = alphas[pass];
     int64_t start = 0, bs = pass == 0 ? 1 : maxb;
@@ -341,7 +352,7 @@ int64_t lvg_build(const float *X, int64_t n, int32_t dim, int32_t metric, int32_
       for (int64_t i = 0; i < B; ++i) {
         scratch_t *w = &ws[omp_get_thread_num()];
         uint32_t p = perm[start + i];
-        const float *xp = X + (size_t)p * dim;
+        const uint16_t *xp = X + (size_t)p * dim;
         greedy(w, sp, adj, R, entry, xp, nrm[p], L);
         pool_reserve(w, w->nvis + R);
         size_t np = 0;
@@ -392,7 +403,7 @@ int64_t lvg_build(const float *X, int64_t n, int32_t dim, int32_t metric, int32_
           for (size_t r = 0; r < np; ++r) row[r] = w->pool[r].id;
           for (int r = (int)np; r < R; ++r) row[r] = SENT;
         } else {
-          const float *xj = X + (size_t)j * dim;
+          const uint16_t *xj = X + (size_t)j * dim;
           for (size_t r = 0; r < np; ++r)
             w->pool[r].s = sim(sp, xj, nrm[j], w->pool[r].id);
           prune(w, np, sp, j, alpha, R, maxc, w->fresh);
@@ -400,6 +411,17 @@ int64_t lvg_build(const float *X, int64_t n, int32_t dim, int32_t metric, int32_
         }
       }
       start = end;
+      if (n >= 200000) { /* progress on long builds, about every 20 s */
+        struct timespec ts;
+        clock_gettime(CLOCK_MONOTONIC, &ts);
+        double now = ts.tv_sec + 1e-9 * ts.tv_nsec;
+        if (now - last_report > 20.0) {
+          fprintf(stderr, "graph build: pass %d/%d, %lld of %lld inserted\n", pass + 1, npasses,
+                  (long long)start, (long long)n);
+          fflush(stderr);
+          last_report = now;
+        }
+      }
       bs = bs * 2 < maxb ? bs * 2 : maxb;
     }
   }
@@ -435,7 +457,7 @@ static int64_t bfs_mark(const uint32_t *adj, int64_t n, int32_t R, uint32_t s, u
  * until a full BFS reaches everything (bounded).  Returns the number of
  * edges added.
  */
-int64_t lvg_repair(const float *X, int64_t n, int32_t dim, int32_t metric, int32_t R, int32_t L,
+int64_t lvg_repair(const uint16_t *X, int64_t n, int32_t dim, int32_t metric, int32_t R, int32_t L,
                    uint32_t entry, uint32_t *adj) {
   uint8_t *mark = (uint8_t *)malloc((size_t)n);
   uint32_t *q = (uint32_t *)malloc(sizeof(uint32_t) * n);
@@ -450,7 +472,7 @@ int64_t lvg_repair(const float *X, int64_t n, int32_t dim, int32_t metric, int32
     if (bfs_mark(adj, n, R, entry, mark, q) == n) break;
     for (int64_t u = 0; u < n; ++u) {
       if (mark[u]) continue;
-      const float *xu = X + (size_t)u * dim;
+      const uint16_t *xu = X + (size_t)u * dim;
       greedy(&w, &space, adj, R, entry, xu, nrm[u], L);
       pool_reserve(&w, w.nvis);
       for (size_t v = 0; v < w.nvis; ++v) w.pool[v] = w.vis[v];

@@ -116,6 +116,16 @@ def _moments(D=24, n=700, m=500, seed=0):
     return X, Q
 
 
+def test_mean_reduced_matches_oracle():
+    X, _ = _moments(D=24, n=500)
+    P = ofit.fit_id(ofit.second_moment(X), 6)
+    s = X.astype(np.float64).sum(0)
+    mu = lv.lv_mean_reduced(np.ascontiguousarray(P), s, len(X))
+    want = ofit.mean_reduced(X, P)
+    assert np.allclose(mu, want, rtol=1e-6, atol=1e-7)
+    assert mu.dtype == np.float32
+
+
 def test_second_moment_matches_oracle():
     X, _ = _moments()
     K = np.zeros((X.shape[1],) * 2)
