@@ -268,6 +268,94 @@ int lv_search_projected(const lv_index *index, const float *Q, const float *Qp, 
                         int32_t k, int32_t L, uint32_t *ids, float *scores, uint32_t *counters,
                         const lv_search_params *params, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched search over several indexes (device, persistent kernel).
+ *
+ * The paper answers one query per thread with no batching (Eq. 1 needs no
+ * batch processing).  A GPU needs many queries in flight, and a serving
+ * stream brings requests of uneven size against different indexes, so a
+ * step packs many requests into one persistent launch: its wavefronts take
+ * queries from a device counter, each query searched exactly as by
+ * lv_search (same results).  Steps are captured as hipGraphs.
+ * ---------------------------------------------------------------------- */
+
+typedef struct lv_multi lv_multi;
+
+/* A set of sub-indexes searched together.  All must share D, d, bits,
+ * record_stride, secondary type and have a query projection A; d <= 256.
+ * The handle copies the index descriptors to the device (it borrows the
+ * indexes' device data, which must outlive it).
+ * Errors: LV_EINVAL for count < 1, NULL entries or mismatched layouts. */
+int lv_multi_create(const lv_index *const *subs, int32_t count, lv_multi **out);
+int lv_multi_destroy(lv_multi *multi);
+
+/* One request of a step: `count` consecutive queries searched in sub-index
+ * `sub` with (k, L).  Queries of request i follow those of request i-1 in
+ * the step's query array; results of request i (count * k ids and scores)
+ * follow those of request i-1 in the output arrays. */
+typedef struct {
+  int32_t sub;
+  int32_t k;
+  int32_t L;
+  int32_t count;
+} lv_request;
+
+typedef struct {
+  int32_t max_requests; /* requests per step */
+  int32_t max_L;        /* largest window of any request */
+  int64_t max_queries;  /* queries per step */
+} lv_batch_caps;
+
+typedef struct lv_batch lv_batch;
+
+/* Allocate a step's device buffers (request table, projected-query
+ * workspace) and pinned request tables, size the persistent grid to the
+ * device's resident wavefronts, and capture the step (request-table copy,
+ * grouped query projection on the matrix cores, persistent search) as two
+ * hipGraphs used alternately.  Knobs in params change no result.
+ * Errors: LV_EINVAL for bad caps, LV_ENOMEM, LV_EDEVICE. */
+int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps, const lv_search_params *params,
+                    lv_batch **out);
+int lv_batch_destroy(lv_batch *batch);
+
+/*
+ * Run one step on `stream`: validate and pack the requests on the host,
+ * then launch the captured graph.  Asynchronous; the pinned table is
+ * reused two steps later, after that step's completion.
+ *   Q:        device float32 [sum count][D]
+ *   ids:      device uint32 [sum count * k] out; scores: device float32, same
+ *   counters: device uint32 [sum count][2] out (expansions, scorings) or NULL
+ * Errors: LV_EINVAL for nreq outside [1, max_requests], a request with a bad
+ *         sub-index, k < 1, L < k, L > max_L, count < 1, or more than
+ *         max_queries queries in total.
+ */
+int lv_batch_step(lv_batch *batch, const lv_request *reqs, int32_t nreq, const float *Q,
+                  uint32_t *ids, float *scores, uint32_t *counters, void *stream);
+
+/*
+ * Autotuner, result-affecting part: the smallest window L in [k, L_max]
+ * whose k-recall@k on learning queries (Q: device float32 [m][D]) against
+ * their true neighbours (truth: host uint32 [m][truth_k], truth_k >= k)
+ * reaches `target` in sub-index `sub` (runtime parameters are calibrated on
+ * a learning query set, Section 3).  Doubling, then bisection; recall is
+ * taken as non-decreasing in L.  Writes L_out (L_max if never reached) and
+ * the recall there.  Synchronises `stream`.
+ */
+int lv_autotune_window(lv_multi *multi, int32_t sub, const float *Q, int64_t m,
+                       const uint32_t *truth, int32_t truth_k, int32_t k, double target,
+                       int32_t L_max, const lv_search_params *params, int32_t *L_out,
+                       double *recall_out, void *stream);
+
+/*
+ * Autotuner, performance part: times `reps` steps of the given requests for
+ * each visited-set size in {1024, 2048, 4096, 8192} that fits, and returns
+ * the fastest in best (these knobs never change results).  best_ms gets the
+ * mean step time.  Synchronises `stream`.
+ */
+int lv_autotune_knobs(lv_multi *multi, const lv_batch_caps *caps, const lv_request *reqs,
+                      int32_t nreq, const float *Q, uint32_t *ids, float *scores, int32_t reps,
+                      lv_search_params *best, double *best_ms, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

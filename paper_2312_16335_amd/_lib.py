@@ -43,6 +43,14 @@ class SearchParams(ctypes.Structure):
     _fields_ = [("hash_slots", _c_i32), ("waves_per_group", _c_i32)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("sub", _c_i32), ("k", _c_i32), ("L", _c_i32), ("count", _c_i32)]
+
+
+class BatchCaps(ctypes.Structure):
+    _fields_ = [("max_requests", _c_i32), ("max_L", _c_i32), ("max_queries", _c_i64)]
+
+
 class FWParams(ctypes.Structure):
     _fields_ = [("alpha", _c_dbl), ("tol", _c_dbl), ("max_iter", _c_i32), ("init", _c_i32)]
 
@@ -74,6 +82,18 @@ _SIGS = {
                            ctypes.POINTER(SearchParams), _vp]),
     "lv_search_projected": (_c_i32, [_vp, _vp, _vp, _c_i64, _c_i32, _c_i32, _vp, _vp, _vp,
                                      ctypes.POINTER(SearchParams), _vp]),
+    "lv_multi_create": (_c_i32, [ctypes.POINTER(_vp), _c_i32, ctypes.POINTER(_vp)]),
+    "lv_multi_destroy": (_c_i32, [_vp]),
+    "lv_batch_create": (_c_i32, [_vp, ctypes.POINTER(BatchCaps), ctypes.POINTER(SearchParams),
+                                 ctypes.POINTER(_vp)]),
+    "lv_batch_destroy": (_c_i32, [_vp]),
+    "lv_batch_step": (_c_i32, [_vp, ctypes.POINTER(Request), _c_i32, _vp, _vp, _vp, _vp, _vp]),
+    "lv_autotune_window": (_c_i32, [_vp, _c_i32, _vp, _c_i64, _vp, _c_i32, _c_i32, _c_dbl,
+                                    _c_i32, ctypes.POINTER(SearchParams),
+                                    ctypes.POINTER(_c_i32), ctypes.POINTER(_c_dbl), _vp]),
+    "lv_autotune_knobs": (_c_i32, [_vp, ctypes.POINTER(BatchCaps), ctypes.POINTER(Request),
+                                   _c_i32, _vp, _vp, _vp, _c_i32, ctypes.POINTER(SearchParams),
+                                   ctypes.POINTER(_c_dbl), _vp]),
 }
 
 _lib = None
@@ -305,3 +325,95 @@ def lv_search_projected(index: Index, Q, Qp, k: int, L: int, ids, scores, counte
                                       _dev(Qp, torch.float32), m, k, L, _dev(ids, torch.int32),
                                       _dev(scores, torch.float32), _dev(counters, torch.int32),
                                       _params(hash_slots), _stream(stream)))
+
+
+# ------------------------------------------------------------ batched search
+
+class Multi:
+    """Several Index handles searched together (keeps them alive)."""
+
+    def __init__(self, indexes):
+        self._subs = list(indexes)
+        arr = (_vp * len(self._subs))(*[ix.handle for ix in self._subs])
+        h = _vp()
+        _check(load().lv_multi_create(arr, len(self._subs), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            load().lv_multi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _requests(reqs):
+    arr = (Request * len(reqs))()
+    for i, (sub, k, L, count) in enumerate(reqs):
+        arr[i] = Request(sub, k, L, count)
+    return arr
+
+
+class Batch:
+    """Captured batched step (lv_batch_create)."""
+
+    def __init__(self, multi: Multi, max_requests: int, max_queries: int, max_L: int,
+                 hash_slots: int = 0):
+        self.multi = multi
+        self.caps = BatchCaps(max_requests, max_L, max_queries)
+        h = _vp()
+        _check(load().lv_batch_create(multi.handle, ctypes.byref(self.caps), _params(hash_slots),
+                                      ctypes.byref(h)))
+        self.handle = h
+
+    def step(self, reqs, Q, ids, scores, counters=None, stream=None):
+        """reqs: list of (sub, k, L, count); Q rows and outputs packed in request order."""
+        import torch
+
+        arr = _requests(reqs)
+        _check(load().lv_batch_step(self.handle, arr, len(reqs), _dev(Q, torch.float32),
+                                    _dev(ids, torch.int32), _dev(scores, torch.float32),
+                                    _dev(counters, torch.int32), _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            load().lv_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lv_autotune_window(multi: Multi, sub: int, Q, truth: np.ndarray, k: int, target: float,
+                       L_max: int, hash_slots: int = 0, stream=None):
+    import torch
+
+    truth = np.ascontiguousarray(truth, dtype=np.uint32)
+    L = ctypes.c_int32(0)
+    rec = ctypes.c_double(0.0)
+    _check(load().lv_autotune_window(multi.handle, sub, _dev(Q, torch.float32), Q.shape[0],
+                                      truth.ctypes.data, truth.shape[1], k, target, L_max,
+                                      _params(hash_slots), ctypes.byref(L), ctypes.byref(rec),
+                                      _stream(stream)))
+    return L.value, rec.value
+
+
+def lv_autotune_knobs(multi: Multi, max_requests, max_queries, max_L, reqs, Q, ids, scores,
+                      reps=3, stream=None):
+    import torch
+
+    caps = BatchCaps(max_requests, max_L, max_queries)
+    best = SearchParams(0, 0)
+    ms = ctypes.c_double(0.0)
+    _check(load().lv_autotune_knobs(multi.handle, ctypes.byref(caps), _requests(reqs), len(reqs),
+                                    _dev(Q, torch.float32), _dev(ids, torch.int32),
+                                    _dev(scores, torch.float32), reps, ctypes.byref(best),
+                                    ctypes.byref(ms), _stream(stream)))
+    return {"hash_slots": best.hash_slots}, ms.value

@@ -10,6 +10,7 @@
 // registers, and reads M (d x D bfloat16, a few hundred KB, L2-resident)
 // directly as the B operand.  No LDS is needed.
 #include "lv_common.h"
+#include "lv_search.h"
 
 namespace lv {
 namespace {
@@ -56,21 +57,19 @@ __device__ __forceinline__ bf16x8 load_b(const uint16_t *p, bool ok) {
   return __builtin_bit_cast(bf16x8, w);
 }
 
-// NT = number of 32-column output tiles handled by one wavefront.
+// One wavefront computes out[row][col0 + c] for rows [row0, row0 + 32) that
+// are < row_end and the NT * 32 columns from col0 (those < d).
 template <int NT>
-__global__ __launch_bounds__(256) void project_kernel(const float *__restrict__ V, int64_t rows,
-                                                      int32_t D, const uint16_t *__restrict__ M,
-                                                      int32_t d, int32_t col0,
-                                                      float *__restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 32;
-  if (row0 >= rows) return;
-  const int r = lane & 31;      // row of the A operand / column of the B operand
-  const int kh = lane >> 5;     // which 8-wide k half of a 16-wide step
+__device__ __forceinline__ void project_rows(const float *__restrict__ V, int64_t row0,
+                                             int64_t row_end, int32_t D,
+                                             const uint16_t *__restrict__ M, int32_t d,
+                                             int32_t col0, float *__restrict__ out,
+                                             int64_t out_stride, int lane) {
+  const int r = lane & 31;   // row of the A operand / column of the B operand
+  const int kh = lane >> 5;  // which 8-wide k half of a 16-wide step
   const int64_t arow = row0 + r;
-  const bool arow_ok = arow < rows;
-  const float *ap = V + (arow_ok ? arow : 0) * (int64_t)D;
+  const bool arow_ok = arow < row_end;
+  const float *ap = V + (arow_ok ? arow : row0) * (int64_t)D;
 
   f32x16 acc[NT];
 #pragma unroll
@@ -103,9 +102,44 @@ __global__ __launch_bounds__(256) void project_kernel(const float *__restrict__ 
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int64_t row = row0 + 8 * (i >> 2) + 4 * kh + (i & 3);
-      if (row < rows) out[row * d + col] = acc[t][i];
+      if (row < row_end) out[row * out_stride + col] = acc[t][i];
     }
   }
+}
+
+// NT = number of 32-column output tiles handled by one wavefront.
+template <int NT>
+__global__ __launch_bounds__(256) void project_kernel(const float *__restrict__ V, int64_t rows,
+                                                      int32_t D, const uint16_t *__restrict__ M,
+                                                      int32_t d, int32_t col0,
+                                                      float *__restrict__ out) {
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+  if (row0 >= rows) return;
+  project_rows<NT>(V, row0, rows, D, M, d, col0, out, d, threadIdx.x & 63);
+}
+
+// Batched form: 32-row tiles over the requests of a step; each tile uses the
+// query projection of its request's sub-index.  Tiles beyond the step's
+// count exit (the grid is sized for the capacity).
+template <int NT>
+__global__ __launch_bounds__(256) void project_grouped_kernel(const StepHeader *__restrict__ hdr,
+                                                              const IndexView *__restrict__ subs,
+                                                              int32_t D, int32_t d) {
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= hdr->ntiles) return;
+  const Request *req = reinterpret_cast<const Request *>(hdr + 1);
+  int lo = 0, hi = hdr->nreq - 1;  // last request with tile0 <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (req[mid].tile0 <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const Request r = req[lo];
+  const int64_t row0 = r.q_begin + (int64_t)(t - r.tile0) * 32;
+  project_rows<NT>(hdr->Q, row0, r.q_end, D, subs[r.sub].A, d, 0, hdr->Qp, hdr->qp_stride,
+                   threadIdx.x & 63);
 }
 
 template <int NT>
@@ -117,6 +151,24 @@ void launch_nt(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32
 }
 
 }  // namespace
+
+int launch_project_grouped(const StepHeader *hdr, const IndexView *subs, int max_tiles, int d,
+                           int D, hipStream_t stream) {
+  if (d < 1 || d > 256) LV_FAIL(LV_EUNSUPPORTED, "batched projection needs d <= 256");
+  const unsigned blocks = (unsigned)((max_tiles + 3) / 4);
+  const int nt = (d + 31) / 32;
+#define LV_GRP(NT)                                                                          \
+  case NT:                                                                                  \
+    hipLaunchKernelGGL(project_grouped_kernel<NT>, dim3(blocks), dim3(256), 0, stream, hdr, \
+                       subs, D, d);                                                         \
+    break;
+  switch (nt) {
+    LV_GRP(1) LV_GRP(2) LV_GRP(3) LV_GRP(4) LV_GRP(5) LV_GRP(6) LV_GRP(7) LV_GRP(8)
+  }
+#undef LV_GRP
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
 
 int launch_project(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32_t d,
                    float *out, hipStream_t stream) {

@@ -1,0 +1,68 @@
+// Device-side views shared by the search kernels and their host launchers.
+#pragma once
+
+#include <cstdint>
+
+#include "lv_common.h"
+
+namespace lv {
+
+constexpr int kDefaultHashSlots = 2048;
+
+// What the traversal reads of one index (device pointers).
+struct IndexView {
+  const unsigned char *records;
+  int64_t stride;
+  int32_t d;
+  int32_t code_bytes;
+  const float *mu;
+  const unsigned char *sec;
+  int32_t D;
+  int32_t sec_row_bytes;
+  int32_t sec_packets;
+  int32_t sec_f16;
+  const uint32_t *adj;
+  int32_t R;
+  uint32_t entry;
+  uint32_t N;
+  const uint16_t *A;  // bfloat16 [d][D] query projection (may be null)
+};
+
+// One request of a batched step: queries [q_begin, q_end) of the step, all
+// searched in sub-index `sub` with (k, L); results at element out_off of
+// the step's ids / scores arrays (count * k of them).
+struct Request {
+  int32_t sub;
+  int32_t k;
+  int32_t L;
+  int32_t tile0;   // first 32-row projection tile of this request
+  int64_t q_begin;
+  int64_t q_end;
+  int64_t out_off;
+};
+
+// Per-step header, followed in memory by nreq Request entries.
+struct StepHeader {
+  const float *Q;        // [nq][D]
+  float *Qp;             // [nq][qp_stride] projected queries (workspace)
+  uint32_t *ids;
+  float *scores;
+  uint32_t *counters;    // [nq][2] or null
+  int64_t nq;
+  int64_t qp_stride;
+  int32_t nreq;
+  int32_t ntiles;        // 32-row projection tiles over all requests
+};
+
+IndexView make_view(const lv_index *ix);
+int hash_log2_for(const lv_search_params *params, int *log2h);
+size_t beam_lds_bytes(int L, int log2h);
+int check_lds(size_t lds, int L, int log2h);
+int launch_persistent(int bits, int group, int vbytes, const StepHeader *hdr,
+                      const IndexView *subs, unsigned int *counter, int Lmax, int log2h, int grid,
+                      hipStream_t stream);
+int persistent_occupancy(int bits, int group, int vbytes, int Lmax, int log2h, int *blocks);
+int launch_project_grouped(const StepHeader *hdr, const IndexView *subs, int max_tiles, int d,
+                           int D, hipStream_t stream);
+
+}  // namespace lv

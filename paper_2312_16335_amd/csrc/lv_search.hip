@@ -18,13 +18,22 @@
 //     equals <q', y^_n> for the LVQ reconstruction y^_n;
 //   * the batch is sorted across lanes (bitonic), merged with the window by
 //     binary search, duplicates dropped, and the window truncated to L;
+//   * while a hop is processed, the adjacency row of the runner-up
+//     unexpanded candidate is already being fetched; when it is still the
+//     best candidate at the next hop (the common case late in a search) that
+//     hop skips one dependent memory round trip.  Results do not change;
 //   * at the end every window entry is re-ranked with <q, secondary> (the
 //     whole wavefront streams one secondary row, several rows in flight)
 //     and the best k are selected.
 // Scores are accumulated in float64: on gfx950 a float64 FMA issues at the
 // same rate as an unpacked float32 FMA, and float64 keeps the traversal
 // order equal to a float64 reference except at exact ties.
+//
+// Two kernels share the per-query body: a plain launch with one workgroup
+// per query, and a persistent launch whose wavefronts pull queries of many
+// requests (each with its own sub-index, k and L) from a device counter.
 #include "lv_common.h"
+#include "lv_search.h"
 
 namespace lv {
 namespace {
@@ -34,37 +43,48 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
 constexpr int kProbes = 16;
 
-struct BeamArgs {
-  const unsigned char *records;
-  int64_t stride;
-  int32_t d;
-  int32_t code_bytes;
-  const float *mu;
-  const unsigned char *sec;
-  int32_t D;
-  int32_t sec_row_bytes;
-  int32_t sec_packets;
-  const uint32_t *adj;
-  int32_t R;
-  uint32_t entry;
-  uint32_t N;
-  const float *Q;
-  const float *Qp;
-  int64_t m;
-  int32_t k;
-  int32_t L;
-  uint32_t *out_ids;
-  float *out_scores;
-  uint32_t *counters;
-  int32_t hash_log2;
-  uint32_t max_hops;
+// Everything one query needs besides the index.
+struct Job {
+  const float *q;    // [D] original query
+  const float *qp;   // [d] projected query
+  int32_t k, L;
+  uint32_t *ids;     // [k]
+  float *scores;     // [k]
+  uint32_t *counters;  // [2] or nullptr
 };
+
+// Window buffers are selected with conditionals, not indexed arrays, so
+// they stay in registers (a dynamically indexed pointer array would go to
+// scratch memory).
+struct Lds {
+  double *ls0, *ls1;
+  uint32_t *lid0, *lid1;
+  __device__ __forceinline__ double *ls(int b) const { return b ? ls1 : ls0; }
+  __device__ __forceinline__ uint32_t *lid(int b) const { return b ? lid1 : lid0; }
+  double *cs;
+  uint32_t *cid;
+  int32_t *lbc;
+  uint32_t *hash;
+};
+
+__device__ __forceinline__ Lds carve(unsigned char *smem, int Lmax) {
+  Lds s;
+  s.ls0 = reinterpret_cast<double *>(smem);
+  s.ls1 = s.ls0 + Lmax;
+  s.cs = s.ls1 + Lmax;
+  s.lid0 = reinterpret_cast<uint32_t *>(s.cs + 64);
+  s.lid1 = s.lid0 + Lmax;
+  s.cid = s.lid1 + Lmax;
+  s.lbc = reinterpret_cast<int32_t *>(s.cid + 64);
+  s.hash = reinterpret_cast<uint32_t *>(s.lbc + 64);
+  return s;
+}
 
 __device__ __forceinline__ bool better(double as, uint32_t aid, double bs, uint32_t bid) {
   return as > bs || (as == bs && aid < bid);
 }
 
-// Order LDS traffic between lanes of one wavefront (the workgroup is one
+// Order LDS traffic between lanes of one wavefront (a workgroup is one
 // wavefront; LDS operations of a wave complete in issue order).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -84,7 +104,6 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-// V-byte chunk of a record: V / 4 dwords.
 template <int V>
 struct Chunk {
   uint32_t w[V / 4];
@@ -96,14 +115,14 @@ __device__ __forceinline__ Chunk<V> load_chunk(const unsigned char *p) {
   if constexpr (V == 4) {
     c.w[0] = *reinterpret_cast<const uint32_t *>(p);
   } else if constexpr (V == 8) {
-    uint2 t = *reinterpret_cast<const uint2 *>(p);
+    const uint2 t = *reinterpret_cast<const uint2 *>(p);
     c.w[0] = t.x; c.w[1] = t.y;
   } else if constexpr (V == 12) {
-    uint3 t = *reinterpret_cast<const uint3 *>(p);
+    const uint3 t = *reinterpret_cast<const uint3 *>(p);
     c.w[0] = t.x; c.w[1] = t.y; c.w[2] = t.z;
   } else {
     static_assert(V == 16, "record chunk of 4, 8, 12 or 16 bytes");
-    uint4 t = *reinterpret_cast<const uint4 *>(p);
+    const uint4 t = *reinterpret_cast<const uint4 *>(p);
     c.w[0] = t.x; c.w[1] = t.y; c.w[2] = t.z; c.w[3] = t.w;
   }
   return c;
@@ -111,41 +130,41 @@ __device__ __forceinline__ Chunk<V> load_chunk(const unsigned char *p) {
 
 template <int BITS, int V>
 __device__ __forceinline__ uint32_t code_at(const Chunk<V> &c, int t) {
-  if constexpr (BITS == 8) {
+  if constexpr (BITS == 8)
     return (c.w[t >> 2] >> (8 * (t & 3))) & 0xFFu;
-  } else {
+  else
     return (c.w[t >> 3] >> (4 * (t & 7))) & 0xFu;
-  }
 }
 
 // Score the nc candidate ids in cid[] into cs[].  Group g of G lanes takes
 // candidates g, g + 64/G, ...; U records per group are in flight at once.
 template <int BITS, int G, int V>
-__device__ __forceinline__ void score_batch(const BeamArgs &a, const double (&qv)[V * 8 / BITS],
+__device__ __forceinline__ void score_batch(const IndexView &ix, const double (&qv)[V * 8 / BITS],
                                             double sq, double cq, const uint32_t *cid, double *cs,
                                             int nc, int lane) {
   constexpr int NQ = V * 8 / BITS;
   constexpr int RPP = 64 / G;
-  constexpr int U = (96 / V) < 2 ? 2 : (96 / V);
+  constexpr int U = (48 / V) < 2 ? 2 : (48 / V);
   const int gl = lane % G;
   const int grp = lane / G;
   for (int base = 0; base < nc; base += RPP * U) {
     Chunk<V> ch[U];
-    uint2 dl[U];
+    uint32_t dlw[U], low[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int c = base + u * RPP + grp;
+      dlw[u] = low[u] = 0u;
       if (c < nc) {
-        const unsigned char *rec = a.records + (size_t)cid[c] * (size_t)a.stride;
+        const unsigned char *rec = ix.records + (size_t)cid[c] * (size_t)ix.stride;
         ch[u] = load_chunk<V>(rec + gl * V);
         if (gl == 0) {
-          const uint32_t *cw = reinterpret_cast<const uint32_t *>(rec + a.code_bytes);
-          dl[u] = make_uint2(cw[0], cw[1]);
+          const uint32_t *cw = reinterpret_cast<const uint32_t *>(rec + ix.code_bytes);
+          dlw[u] = cw[0];
+          low[u] = cw[1];
         }
       } else {
 #pragma unroll
         for (int w = 0; w < V / 4; ++w) ch[u].w[w] = 0u;
-        dl[u] = make_uint2(0u, 0u);
       }
     }
 #pragma unroll
@@ -156,8 +175,8 @@ __device__ __forceinline__ void score_batch(const BeamArgs &a, const double (&qv
       acc = group_sum<G>(acc);
       const int c = base + u * RPP + grp;
       if (gl == 0 && c < nc) {
-        const double delta = (double)__uint_as_float(dl[u].x);
-        const double lo = (double)__uint_as_float(dl[u].y);
+        const double delta = (double)__uint_as_float(dlw[u]);
+        const double lo = (double)__uint_as_float(low[u]);
         cs[c] = delta * acc + lo * sq + cq;
       }
     }
@@ -196,8 +215,8 @@ __device__ __forceinline__ bool hash_visit(uint32_t *hash, int log2h, uint32_t n
 }
 
 template <bool F16>
-__device__ __forceinline__ void rerank_rows(const BeamArgs &a, const float *q, const uint32_t *ids,
-                                            double *out, int nl, int lane) {
+__device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
+                                            const uint32_t *ids, double *out, int nl, int lane) {
   constexpr int E = F16 ? 8 : 4;  // elements per 16-byte packet
   constexpr int PPL = 2;          // packets per lane (rows up to 2 KiB)
   constexpr int UR = 4;           // rows in flight
@@ -208,7 +227,7 @@ __device__ __forceinline__ void rerank_rows(const BeamArgs &a, const float *q, c
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = packet * E + e;
-      qq[pk][e] = (packet < a.sec_packets && j < a.D) ? q[j] : 0.f;
+      qq[pk][e] = (packet < ix.sec_packets && j < ix.D) ? q[j] : 0.f;
     }
   }
   for (int base = 0; base < nl; base += UR) {
@@ -217,11 +236,11 @@ __device__ __forceinline__ void rerank_rows(const BeamArgs &a, const float *q, c
     for (int u = 0; u < UR; ++u) {
       const int idx = base + u;
       const uint32_t id = idx < nl ? (ids[idx] & kIdMask) : 0u;
-      const unsigned char *row = a.sec + (size_t)id * (size_t)a.sec_row_bytes;
+      const unsigned char *row = ix.sec + (size_t)id * (size_t)ix.sec_row_bytes;
 #pragma unroll
       for (int pk = 0; pk < PPL; ++pk) {
         const int packet = lane + 64 * pk;
-        if (idx < nl && packet < a.sec_packets)
+        if (idx < nl && packet < ix.sec_packets)
           v[u][pk] = *reinterpret_cast<const uint4 *>(row + (size_t)packet * 16);
         else
           v[u][pk] = make_uint4(0u, 0u, 0u, 0u);
@@ -236,12 +255,10 @@ __device__ __forceinline__ void rerank_rows(const BeamArgs &a, const float *q, c
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           float x;
-          if constexpr (F16) {
-            const uint16_t hbits = (uint16_t)(w[e >> 1] >> (16 * (e & 1)));
-            x = (float)__builtin_bit_cast(_Float16, hbits);
-          } else {
+          if constexpr (F16)
+            x = (float)__builtin_bit_cast(_Float16, (uint16_t)(w[e >> 1] >> (16 * (e & 1))));
+          else
             x = __uint_as_float(w[e]);
-          }
           acc = fma((double)x, (double)qq[pk][e], acc);
         }
       }
@@ -251,109 +268,113 @@ __device__ __forceinline__ void rerank_rows(const BeamArgs &a, const float *q, c
   }
 }
 
+// The whole search of one query by one wavefront.
 template <int BITS, int G, int V>
-__global__ __launch_bounds__(64) void beam_kernel(BeamArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm, int log2h,
+                             int lane) {
   constexpr int NQ = V * 8 / BITS;
-  const int lane = threadIdx.x;
-  const int64_t qi = blockIdx.x;
-  if (qi >= a.m) return;
-  const int L = a.L;
-  double *ls_buf[2];
-  uint32_t *lid_buf[2];
-  ls_buf[0] = reinterpret_cast<double *>(smem);
-  ls_buf[1] = ls_buf[0] + L;
-  double *cs = ls_buf[1] + L;
-  lid_buf[0] = reinterpret_cast<uint32_t *>(cs + 64);
-  lid_buf[1] = lid_buf[0] + L;
-  uint32_t *cid = lid_buf[1] + L;
-  int32_t *lbc = reinterpret_cast<int32_t *>(cid + 64);
-  uint32_t *hash = reinterpret_cast<uint32_t *>(lbc + 64);
-  const int hslots = 1 << a.hash_log2;
+  const int L = job.L;
+  const int hslots = 1 << log2h;
 
   // projected query slice of this lane, float64
   const int gl = lane % G;
   double qv[NQ];
   double sq = 0.0, cq = 0.0;
-  {
-    const float *qp = a.Qp + qi * a.d;
 #pragma unroll
-    for (int t = 0; t < NQ; ++t) {
-      const int j = gl * NQ + t;
-      const double x = j < a.d ? (double)qp[j] : 0.0;
-      qv[t] = x;
-      sq += x;
-      if (j < a.d) cq = fma(x, (double)a.mu[j], cq);
-    }
-    sq = group_sum<G>(sq);
-    cq = group_sum<G>(cq);
+  for (int t = 0; t < NQ; ++t) {
+    const int j = gl * NQ + t;
+    const double x = j < ix.d ? (double)job.qp[j] : 0.0;
+    qv[t] = x;
+    sq += x;
+    if (j < ix.d) cq = fma(x, (double)ix.mu[j], cq);
   }
-  for (int i = lane; i < hslots; i += 64) hash[i] = kEmpty;
+  sq = group_sum<G>(sq);
+  cq = group_sum<G>(cq);
+  for (int i = lane; i < hslots; i += 64) sm.hash[i] = kEmpty;
   wave_sync();
 
   // seed the window with the entry node
   if (lane == 0) {
-    cid[0] = a.entry;
-    hash_visit(hash, a.hash_log2, a.entry);
+    sm.cid[0] = ix.entry;
+    hash_visit(sm.hash, log2h, ix.entry);
   }
   wave_sync();
-  score_batch<BITS, G, V>(a, qv, sq, cq, cid, cs, 1, lane);
+  score_batch<BITS, G, V>(ix, qv, sq, cq, sm.cid, sm.cs, 1, lane);
   wave_sync();
   if (lane == 0) {
-    ls_buf[0][0] = cs[0];
-    lid_buf[0][0] = a.entry;
+    sm.ls0[0] = sm.cs[0];
+    sm.lid0[0] = ix.entry;
   }
   wave_sync();
   int nl = 1;
   int cur = 0;
   uint32_t n_exp = 0, n_dist = 1;
+  uint32_t pf_id = kSentinel;   // node whose first adjacency chunk is in pf_row
+  uint32_t pf_row = kSentinel;
+  const uint32_t max_hops = ix.N + 1u;  // every node is expanded at most once
 
-  for (uint32_t hop = 0; hop < a.max_hops; ++hop) {
-    double *ls = ls_buf[cur];
-    uint32_t *lid = lid_buf[cur];
-    // best unexpanded entry = first unexpanded position of the sorted window
-    int pos = -1;
+  for (uint32_t hop = 0; hop < max_hops; ++hop) {
+    double *ls = sm.ls(cur);
+    uint32_t *lid = sm.lid(cur);
+    // best unexpanded entry = first unexpanded position of the sorted window;
+    // the next one is the runner-up whose row is prefetched
+    int pos = -1, pos2 = -1;
     for (int base = 0; base < nl; base += 64) {
       const int i = base + lane;
       const bool un = i < nl && !(lid[i] & kExpanded);
-      const uint64_t msk = __ballot(un);
+      uint64_t msk = __ballot(un);
       if (msk) {
-        pos = base + __ffsll((unsigned long long)msk) - 1;
-        break;
+        if (pos < 0) {
+          pos = base + __ffsll((unsigned long long)msk) - 1;
+          msk &= msk - 1;
+        }
+        if (msk) {
+          pos2 = base + __ffsll((unsigned long long)msk) - 1;
+          break;
+        }
       }
     }
     if (pos < 0) break;
     const uint32_t p = lid[pos];
+    const uint32_t p2 = pos2 >= 0 ? lid[pos2] : kSentinel;
     wave_sync();
     if (lane == 0) lid[pos] = p | kExpanded;
     wave_sync();
     ++n_exp;
-    const uint32_t *row = a.adj + (size_t)p * (size_t)a.R;
-    for (int rb = 0; rb < a.R; rb += 64) {
-      uint32_t n = kSentinel;
-      if (rb + lane < a.R) n = row[rb + lane];
+    const uint32_t *row = ix.adj + (size_t)p * (size_t)ix.R;
+    uint32_t first = kSentinel;
+    if (p == pf_id)
+      first = pf_row;
+    else if (lane < ix.R)
+      first = row[lane];
+    // prefetch the runner-up's first chunk; consumed at the next hop if it is
+    // still the best unexpanded candidate then
+    pf_id = p2;
+    pf_row = (p2 != kSentinel && lane < ix.R) ? ix.adj[(size_t)p2 * (size_t)ix.R + lane]
+                                              : kSentinel;
+    for (int rb = 0; rb < ix.R; rb += 64) {
+      uint32_t n = rb == 0 ? first : (rb + lane < ix.R ? row[rb + lane] : kSentinel);
       bool fresh = false;
-      if (n < a.N) fresh = hash_visit(hash, a.hash_log2, n);
+      if (n < ix.N) fresh = hash_visit(sm.hash, log2h, n);
       const uint64_t fm = __ballot(fresh);
       const int nc = __popcll(fm);
       if (nc == 0) continue;
-      if (fresh) cid[lane_rank(fm)] = n;
+      if (fresh) sm.cid[lane_rank(fm)] = n;
       wave_sync();
-      score_batch<BITS, G, V>(a, qv, sq, cq, cid, cs, nc, lane);
+      score_batch<BITS, G, V>(ix, qv, sq, cq, sm.cid, sm.cs, nc, lane);
       wave_sync();
       n_dist += nc;
 
       // merge the scored batch into the window
-      ls = ls_buf[cur];
-      lid = lid_buf[cur];
+      ls = sm.ls(cur);
+      lid = sm.lid(cur);
       double bs = -INFINITY;
       uint32_t bid = kSentinel;
       if (lane < nc) {
-        bs = cs[lane];
-        bid = cid[lane];
+        bs = sm.cs[lane];
+        bid = sm.cid[lane];
       }
-      if (nl == L && bid != kSentinel &&
-          !better(bs, bid, ls[L - 1], lid[L - 1] & kIdMask)) {
+      if (nl == L && bid != kSentinel && !better(bs, bid, ls[L - 1], lid[L - 1] & kIdMask)) {
         bs = -INFINITY;
         bid = kSentinel;
       }
@@ -377,15 +398,15 @@ __global__ __launch_bounds__(64) void beam_kernel(BeamArgs a) {
       const int nv = __popcll(vm);
       if (nv == 0) continue;
       const int r = lane_rank(vm);
-      if (valid) lbc[r] = lb;
+      if (valid) sm.lbc[r] = lb;
       wave_sync();
-      double *ls_n = ls_buf[cur ^ 1];
-      uint32_t *lid_n = lid_buf[cur ^ 1];
+      double *ls_n = sm.ls(cur ^ 1);
+      uint32_t *lid_n = sm.lid(cur ^ 1);
       for (int j = lane; j < nl; j += 64) {
-        int lo = 0, hi = nv;  // count of new entries placed before window entry j
+        int lo = 0, hi = nv;  // new entries placed before window entry j
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if (lbc[mid] <= j)
+          if (sm.lbc[mid] <= j)
             lo = mid + 1;
           else
             hi = mid;
@@ -407,138 +428,286 @@ __global__ __launch_bounds__(64) void beam_kernel(BeamArgs a) {
   }
 
   // re-rank the window with the secondary vectors
-  {
-    const uint32_t *lid = lid_buf[cur];
-    double *s2 = ls_buf[cur ^ 1];
-    uint32_t *id2 = lid_buf[cur ^ 1];
-    const float *q = a.Q + qi * a.D;
-    if (a.sec_row_bytes == a.D * 2)
-      rerank_rows<true>(a, q, lid, s2, nl, lane);
-    else
-      rerank_rows<false>(a, q, lid, s2, nl, lane);
-    for (int j = lane; j < nl; j += 64) id2[j] = lid[j] & kIdMask;
-    wave_sync();
-    // selection of the best k
-    for (int t = 0; t < a.k; ++t) {
-      double bs = -INFINITY;
-      uint32_t bid = kSentinel;
-      for (int j = lane; j < nl; j += 64) {
-        const uint32_t id = id2[j];
-        if (id != kSentinel && better(s2[j], id, bs, bid)) {
-          bs = s2[j];
-          bid = id;
-        }
+  const uint32_t *lid = sm.lid(cur);
+  double *s2 = sm.ls(cur ^ 1);
+  uint32_t *id2 = sm.lid(cur ^ 1);
+  if (ix.sec_f16)
+    rerank_rows<true>(ix, job.q, lid, s2, nl, lane);
+  else
+    rerank_rows<false>(ix, job.q, lid, s2, nl, lane);
+  for (int j = lane; j < nl; j += 64) id2[j] = lid[j] & kIdMask;
+  wave_sync();
+  for (int t = 0; t < job.k; ++t) {
+    double bs = -INFINITY;
+    uint32_t bid = kSentinel;
+    for (int j = lane; j < nl; j += 64) {
+      const uint32_t id = id2[j];
+      if (id != kSentinel && better(s2[j], id, bs, bid)) {
+        bs = s2[j];
+        bid = id;
       }
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const double ps = __shfl_xor(bs, o, 64);
-        const uint32_t pid = (uint32_t)__shfl_xor((int)bid, o, 64);
-        if (better(ps, pid, bs, bid)) {
-          bs = ps;
-          bid = pid;
-        }
-      }
-      if (lane == 0) {
-        a.out_ids[qi * a.k + t] = bid;
-        a.out_scores[qi * a.k + t] = bid == kSentinel ? -INFINITY : (float)bs;
-      }
-      if (bid == kSentinel) {
-        for (int t2 = t + 1 + lane; t2 < a.k; t2 += 64) {
-          a.out_ids[qi * a.k + t2] = kSentinel;
-          a.out_scores[qi * a.k + t2] = -INFINITY;
-        }
-        break;
-      }
-      for (int j = lane; j < nl; j += 64)
-        if (id2[j] == bid) id2[j] = kSentinel;
-      wave_sync();
     }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double ps = __shfl_xor(bs, o, 64);
+      const uint32_t pid = (uint32_t)__shfl_xor((int)bid, o, 64);
+      if (better(ps, pid, bs, bid)) {
+        bs = ps;
+        bid = pid;
+      }
+    }
+    if (lane == 0) {
+      job.ids[t] = bid;
+      job.scores[t] = bid == kSentinel ? -INFINITY : (float)bs;
+    }
+    if (bid == kSentinel) {
+      for (int t2 = t + 1 + lane; t2 < job.k; t2 += 64) {
+        job.ids[t2] = kSentinel;
+        job.scores[t2] = -INFINITY;
+      }
+      break;
+    }
+    for (int j = lane; j < nl; j += 64)
+      if (id2[j] == bid) id2[j] = kSentinel;
+    wave_sync();
   }
-  if (a.counters && lane == 0) {
-    a.counters[2 * qi] = n_exp;
-    a.counters[2 * qi + 1] = n_dist;
+  if (job.counters && lane == 0) {
+    job.counters[0] = n_exp;
+    job.counters[1] = n_dist;
   }
+  wave_sync();
+}
+
+struct PlainArgs {
+  IndexView ix;
+  const float *Q;
+  const float *Qp;
+  int64_t m;
+  int32_t k, L;
+  uint32_t *ids;
+  float *scores;
+  uint32_t *counters;
+  int32_t hash_log2;
+};
+
+template <int BITS, int G, int V>
+__global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t qi = blockIdx.x;
+  if (qi >= a.m) return;
+  const Lds sm = carve(smem, a.L);
+  Job job;
+  job.q = a.Q + qi * a.ix.D;
+  job.qp = a.Qp + qi * a.ix.d;
+  job.k = a.k;
+  job.L = a.L;
+  job.ids = a.ids + qi * a.k;
+  job.scores = a.scores + qi * a.k;
+  job.counters = a.counters ? a.counters + 2 * qi : nullptr;
+  search_query<BITS, G, V>(a.ix, job, sm, a.hash_log2, threadIdx.x);
+}
+
+// Persistent form: wavefronts take queries from a device counter until the
+// step's queries run out.  Requests are sorted by q_begin; a query finds its
+// request by binary search.
+template <int BITS, int G, int V>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void persistent_kernel(
+    const StepHeader *__restrict__ hdr,
+                                                        const IndexView *__restrict__ subs,
+                                                        unsigned int *__restrict__ counter,
+                                                        int32_t Lmax, int32_t hash_log2) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x;
+  const Lds sm = carve(smem, Lmax);
+  const int64_t nq = hdr->nq;
+  const int32_t nreq = hdr->nreq;
+  const Request *req = reinterpret_cast<const Request *>(hdr + 1);
+  for (;;) {
+    unsigned int u = 0;
+    if (lane == 0) u = atomicAdd(counter, 1u);
+    // wave-uniform from here on, so request and index fields live in SGPRs
+    u = __builtin_amdgcn_readfirstlane(__shfl(u, 0, 64));
+    if ((int64_t)u >= nq) break;
+    int lo = 0, hi = nreq - 1;  // last request with q_begin <= u
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (req[mid].q_begin <= (int64_t)u)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const Request r = req[lo];
+    const IndexView ix = subs[r.sub];
+    const int64_t j = (int64_t)u - r.q_begin;
+    Job job;
+    job.q = hdr->Q + (int64_t)u * ix.D;
+    job.qp = hdr->Qp + (int64_t)u * hdr->qp_stride;
+    job.k = r.k;
+    job.L = r.L;
+    job.ids = hdr->ids + r.out_off + j * r.k;
+    job.scores = hdr->scores + r.out_off + j * r.k;
+    job.counters = hdr->counters ? hdr->counters + 2 * (int64_t)u : nullptr;
+    search_query<BITS, G, V>(ix, job, sm, hash_log2, lane);
+  }
+}
+
+__global__ void reset_counter_kernel(unsigned int *counter) { *counter = 0u; }
+
+template <int BITS, int G, int V>
+int launch_plain_t(const PlainArgs &a, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((beam_kernel<BITS, G, V>), dim3((unsigned)a.m), dim3(64), lds, s, a);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+template <int BITS, int G, int V>
+int launch_persistent_t(const StepHeader *hdr, const IndexView *subs, unsigned int *counter,
+                        int Lmax, int log2h, size_t lds, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  hipLaunchKernelGGL((persistent_kernel<BITS, G, V>), dim3(grid), dim3(64), lds, s, hdr, subs,
+                     counter, Lmax, log2h);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+template <int BITS, int G, int V>
+int occupancy_t(size_t lds, int *blocks) {
+  LV_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks, reinterpret_cast<const void *>(persistent_kernel<BITS, G, V>), 64, lds));
+  return LV_OK;
+}
+
+// Dispatch on (bits, group, vbytes) to the matching template instance.
+template <class F>
+int dispatch(int bits, int group, int vbytes, F &&f) {
+  const int key = group * 100 + vbytes;
+#define LV_CASE(B, GG, VV) \
+  if (bits == B && key == GG * 100 + VV) return f.template operator()<B, GG, VV>();
+  LV_CASE(8, 16, 4) LV_CASE(8, 16, 8) LV_CASE(8, 16, 12) LV_CASE(8, 16, 16)
+  LV_CASE(8, 64, 8) LV_CASE(8, 64, 12) LV_CASE(8, 64, 16)
+  LV_CASE(4, 16, 4) LV_CASE(4, 16, 8) LV_CASE(4, 16, 12) LV_CASE(4, 16, 16)
+  LV_CASE(4, 64, 8) LV_CASE(4, 64, 12) LV_CASE(4, 64, 16)
+#undef LV_CASE
+  LV_FAIL(LV_EUNSUPPORTED, "no search kernel for %d-bit records of group %d x %d bytes", bits,
+          group, vbytes);
+}
+
+struct PlainLaunch {
+  const PlainArgs &a;
+  size_t lds;
+  hipStream_t s;
+  template <int B, int GG, int VV>
+  int operator()() { return launch_plain_t<B, GG, VV>(a, lds, s); }
+};
+
+struct PersistentLaunch {
+  const StepHeader *hdr;
+  const IndexView *subs;
+  unsigned int *counter;
+  int Lmax, log2h;
+  size_t lds;
+  int grid;
+  hipStream_t s;
+  template <int B, int GG, int VV>
+  int operator()() {
+    return launch_persistent_t<B, GG, VV>(hdr, subs, counter, Lmax, log2h, lds, grid, s);
+  }
+};
+
+struct Occupancy {
+  size_t lds;
+  int *blocks;
+  template <int B, int GG, int VV>
+  int operator()() { return occupancy_t<B, GG, VV>(lds, blocks); }
+};
+
+}  // namespace
+
+IndexView make_view(const lv_index *ix) {
+  const lv_index_desc &d = ix->desc;
+  IndexView v;
+  v.records = static_cast<const unsigned char *>(d.records);
+  v.stride = d.record_stride;
+  v.d = d.d;
+  v.code_bytes = ix->code_bytes;
+  v.mu = d.mu;
+  v.sec = static_cast<const unsigned char *>(d.secondaries);
+  v.D = d.D;
+  v.sec_row_bytes = d.D * (d.sec_dtype == LV_F16 ? 2 : 4);
+  v.sec_packets = ix->sec_packets;
+  v.sec_f16 = d.sec_dtype == LV_F16 ? 1 : 0;
+  v.adj = d.adjacency;
+  v.R = d.R;
+  v.entry = d.entry;
+  v.N = (uint32_t)d.N;
+  v.A = d.A;
+  return v;
+}
+
+int hash_log2_for(const lv_search_params *params, int *log2h) {
+  const int hs = params && params->hash_slots ? params->hash_slots : kDefaultHashSlots;
+  if (hs < 256 || hs > 65536 || (hs & (hs - 1)))
+    LV_FAIL(LV_EINVAL, "hash_slots must be a power of two in [256, 65536] (got %d)", hs);
+  int l = 0;
+  while ((1 << l) < hs) ++l;
+  *log2h = l;
+  return LV_OK;
 }
 
 size_t beam_lds_bytes(int L, int log2h) {
   return (size_t)L * 24 + 64 * 16 + ((size_t)4 << log2h);
 }
 
-template <int BITS, int G, int V>
-int launch_t(const BeamArgs &args, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL((beam_kernel<BITS, G, V>), dim3((unsigned)args.m), dim3(64), lds, stream,
-                     args);
-  LV_CHECK_LAUNCH();
+int check_lds(size_t lds, int L, int log2h) {
+  int dev = 0, lds_max = 0;
+  LV_CHECK_HIP(hipGetDevice(&dev));
+  LV_CHECK_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if (lds > (size_t)lds_max)
+    LV_FAIL(LV_EINVAL, "window %d with %d hash slots needs %zu bytes of LDS (limit %d)", L,
+            1 << log2h, lds, lds_max);
   return LV_OK;
 }
-
-}  // namespace
 
 int launch_beam(const lv_index *ix, const float *Q, const float *Qp, int64_t m, int32_t k,
                 int32_t L, uint32_t *ids, float *scores, uint32_t *counters,
                 const lv_search_params *params, hipStream_t stream) {
-  const lv_index_desc &dsc = ix->desc;
-  int hs = params && params->hash_slots ? params->hash_slots : 4096;
-  if (hs < 256 || hs > 65536 || (hs & (hs - 1)))
-    LV_FAIL(LV_EINVAL, "hash_slots must be a power of two in [256, 65536] (got %d)", hs);
   int log2h = 0;
-  while ((1 << log2h) < hs) ++log2h;
+  int rc = hash_log2_for(params, &log2h);
+  if (rc != LV_OK) return rc;
   if (m == 0) return LV_OK;
   if (m > 0x7FFFFFFF) LV_FAIL(LV_EINVAL, "at most 2^31-1 queries per call");
-  BeamArgs a;
-  a.records = static_cast<const unsigned char *>(dsc.records);
-  a.stride = dsc.record_stride;
-  a.d = dsc.d;
-  a.code_bytes = ix->code_bytes;
-  a.mu = dsc.mu;
-  a.sec = static_cast<const unsigned char *>(dsc.secondaries);
-  a.D = dsc.D;
-  a.sec_row_bytes = dsc.D * (dsc.sec_dtype == LV_F16 ? 2 : 4);
-  a.sec_packets = ix->sec_packets;
-  a.adj = dsc.adjacency;
-  a.R = dsc.R;
-  a.entry = dsc.entry;
-  a.N = (uint32_t)dsc.N;
+  const size_t lds = beam_lds_bytes(L, log2h);
+  rc = check_lds(lds, L, log2h);
+  if (rc != LV_OK) return rc;
+  PlainArgs a;
+  a.ix = make_view(ix);
   a.Q = Q;
   a.Qp = Qp;
   a.m = m;
   a.k = k;
   a.L = L;
-  a.out_ids = ids;
-  a.out_scores = scores;
+  a.ids = ids;
+  a.scores = scores;
   a.counters = counters;
   a.hash_log2 = log2h;
-  a.max_hops = (uint32_t)dsc.N + 1u;  // every node is expanded at most once
-  const size_t lds = beam_lds_bytes(L, log2h);
-  int dev = 0, lds_max = 0;
-  LV_CHECK_HIP(hipGetDevice(&dev));
-  LV_CHECK_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  if (lds > (size_t)lds_max)
-    LV_FAIL(LV_EINVAL, "window %d with %d hash slots needs %zu bytes of LDS (limit %d)", L, hs,
-            lds, lds_max);
-  const int key = ix->group * 100 + ix->vbytes;
-  if (dsc.bits == 8) {
-    switch (key) {
-      case 1604: return launch_t<8, 16, 4>(a, lds, stream);
-      case 1608: return launch_t<8, 16, 8>(a, lds, stream);
-      case 1612: return launch_t<8, 16, 12>(a, lds, stream);
-      case 1616: return launch_t<8, 16, 16>(a, lds, stream);
-      case 6408: return launch_t<8, 64, 8>(a, lds, stream);
-      case 6412: return launch_t<8, 64, 12>(a, lds, stream);
-      case 6416: return launch_t<8, 64, 16>(a, lds, stream);
-    }
-  } else {
-    switch (key) {
-      case 1604: return launch_t<4, 16, 4>(a, lds, stream);
-      case 1608: return launch_t<4, 16, 8>(a, lds, stream);
-      case 1612: return launch_t<4, 16, 12>(a, lds, stream);
-      case 1616: return launch_t<4, 16, 16>(a, lds, stream);
-      case 6408: return launch_t<4, 64, 8>(a, lds, stream);
-      case 6412: return launch_t<4, 64, 12>(a, lds, stream);
-      case 6416: return launch_t<4, 64, 16>(a, lds, stream);
-    }
-  }
-  LV_FAIL(LV_EUNSUPPORTED, "no search kernel for record stride %d", dsc.record_stride);
+  PlainLaunch f{a, lds, stream};
+  return dispatch(ix->desc.bits, ix->group, ix->vbytes, f);
+}
+
+int launch_persistent(int bits, int group, int vbytes, const StepHeader *hdr,
+                      const IndexView *subs, unsigned int *counter, int Lmax, int log2h, int grid,
+                      hipStream_t stream) {
+  const size_t lds = beam_lds_bytes(Lmax, log2h);
+  PersistentLaunch f{hdr, subs, counter, Lmax, log2h, lds, grid, stream};
+  return dispatch(bits, group, vbytes, f);
+}
+
+int persistent_occupancy(int bits, int group, int vbytes, int Lmax, int log2h, int *blocks) {
+  const size_t lds = beam_lds_bytes(Lmax, log2h);
+  int rc = check_lds(lds, Lmax, log2h);
+  if (rc != LV_OK) return rc;
+  Occupancy f{lds, blocks};
+  return dispatch(bits, group, vbytes, f);
 }
 
 }  // namespace lv

@@ -66,13 +66,13 @@ def build_graph(X: np.ndarray, R: int, L: int = 0, metric: int = METRIC_L2,
     default is the Euclidean rule with alpha 1.0 then 1.2 (the paper's
     Euclidean setting); on unit-norm rows it ranks neighbours exactly as
     inner product does.  L defaults to 2R (search window during
-    construction); maxc caps the pruning pool (default 2R).  Deterministic
+    construction); maxc caps the pruning pool (default 8R).  Deterministic
     for any thread count.
     """
     X = _as_f16(X)
     n, dim = X.shape
     L = L or 2 * R
-    maxc = maxc or 2 * R
+    maxc = maxc or 8 * R
     al = np.ascontiguousarray(alphas, dtype=np.float32)
     adj = np.empty((n, R), dtype=np.uint32)
     entry = _load().lvg_build(X.ctypes.data, n, dim, metric, R, L, maxc, al.ctypes.data, len(al),

@@ -1,0 +1,153 @@
+"""GPU tests of the batched persistent search: identical results to the plain
+search request by request (several sub-indexes, uneven batch sizes, mixed k
+and L), consecutive captured steps, validation, and the autotuner."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_common import make_case
+from oracle import exact
+from synth import gen
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def lv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2312_16335_amd as lv
+
+    lv.load()
+    return lv
+
+
+@pytest.fixture(scope="module")
+def subs(lv):
+    base = gen.WORKLOADS["id-1m-768"]
+    out = []
+    for s, n in enumerate((3000, 5000, 8000)):
+        wl = replace(base, name=f"sub{s}", N=n, m_test=300, m_learn=300, seed_data=4000 + s,
+                     seed_test=4100 + s, seed_learn=4200 + s)
+        c = make_case(wl)
+        Yd = torch.from_numpy(c.Y).to(DEV)
+        mud = torch.from_numpy(c.mu).to(DEV)
+        rec = torch.empty((wl.N, c.stride), dtype=torch.uint8, device=DEV)
+        lv.lv_lvq_encode(Yd, mud, wl.bits, rec)
+        sec = torch.from_numpy(c.sec).to(DEV)
+        adj = torch.from_numpy(c.adj.view(np.int32)).to(DEV)
+        Pb = torch.from_numpy(lv.lv_to_bf16(c.P).view(np.int16)).to(DEV)
+        ix = lv.Index(rec, mud, sec, adj, c.entry, wl.bits, wl.d, A_bf16=Pb)
+        out.append((c, ix))
+    return out
+
+
+def plain(lv, ix, Q, k, L, hash_slots=0):
+    m = len(Q)
+    ids = torch.empty((m, k), dtype=torch.int32, device=DEV)
+    sc = torch.empty((m, k), dtype=torch.float32, device=DEV)
+    cnt = torch.zeros((m, 2), dtype=torch.int32, device=DEV)
+    ws = torch.empty(lv.lv_search_workspace_size(ix, m), dtype=torch.uint8, device=DEV)
+    lv.lv_search(ix, Q, k, L, ids, sc, cnt, ws=ws, hash_slots=hash_slots)
+    return ids, sc, cnt
+
+
+def run_step(lv, batch, subs, reqs, cursor):
+    """Pack queries per request (taken from each sub-index's pool) and run one step."""
+    Qs, spans = [], []
+    for sub, k, L, count in reqs:
+        c = subs[sub][0]
+        lo = cursor[sub]
+        Qs.append(c.Q[lo:lo + count])
+        cursor[sub] += count
+        spans.append((sub, k, L, count))
+    Q = torch.from_numpy(np.concatenate(Qs)).to(DEV)
+    nout = sum(k * count for _, k, _, count in reqs)
+    ids = torch.full((nout,), -7, dtype=torch.int32, device=DEV)
+    sc = torch.zeros((nout,), dtype=torch.float32, device=DEV)
+    cnt = torch.zeros((len(Q), 2), dtype=torch.int32, device=DEV)
+    batch.step(reqs, Q, ids, sc, cnt)
+    return Q, ids, sc, cnt
+
+
+def check_against_plain(lv, subs, reqs, Q, ids, sc, cnt):
+    torch.cuda.synchronize()
+    q0 = o0 = 0
+    for sub, k, L, count in reqs:
+        pi, ps, pc = plain(lv, subs[sub][1], Q[q0:q0 + count], k, L)
+        torch.cuda.synchronize()
+        bi = ids[o0:o0 + count * k].view(count, k)
+        bs = sc[o0:o0 + count * k].view(count, k)
+        assert torch.equal(bi, pi), (sub, k, L, count)
+        assert torch.equal(bs, ps), (sub, k, L, count)
+        assert torch.equal(cnt[q0:q0 + count], pc)
+        q0 += count
+        o0 += count * k
+
+
+def test_batched_equals_plain_over_consecutive_steps(lv, subs):
+    multi = lv.Multi([ix for _, ix in subs])
+    batch = lv.Batch(multi, max_requests=16, max_queries=1024, max_L=200)
+    cursor = [0, 0, 0]
+    steps = [
+        [(0, 10, 40, 1), (1, 1, 20, 33), (2, 100, 128, 70), (0, 10, 60, 5), (1, 10, 40, 64)],
+        [(2, 10, 200, 31), (2, 1, 1, 2)],
+        [(1, 10, 30, 100), (0, 5, 5, 7), (2, 10, 50, 3), (1, 100, 100, 9)],
+    ]
+    for reqs in steps:
+        out = run_step(lv, batch, subs, reqs, cursor)
+        check_against_plain(lv, subs, reqs, *out)
+    batch.close()
+    multi.close()
+
+
+def test_batch_validation(lv, subs):
+    multi = lv.Multi([ix for _, ix in subs])
+    batch = lv.Batch(multi, max_requests=4, max_queries=100, max_L=64)
+    Q = torch.zeros((200, 768), device=DEV)
+    ids = torch.zeros((2000,), dtype=torch.int32, device=DEV)
+    sc = torch.zeros((2000,), dtype=torch.float32, device=DEV)
+    for bad in ([(0, 10, 65, 5)], [(3, 10, 20, 5)], [(0, 10, 5, 5)], [(0, 10, 20, 0)],
+                [(0, 10, 20, 101)], [(0, 10, 20, 1)] * 5, []):
+        with pytest.raises((lv.LVError, ValueError)):
+            batch.step(bad, Q, ids, sc)
+    batch.close()
+    with pytest.raises(lv.LVError):
+        lv.Batch(multi, max_requests=0, max_queries=10, max_L=10)
+    multi.close()
+
+
+def test_autotune_window_is_minimal(lv, subs):
+    c, ix = subs[2]
+    multi = lv.Multi([ix])
+    Ql = c.Q[:200]
+    truth = exact.ground_truth(Ql, c.X, 10).astype(np.uint32)
+    Qd = torch.from_numpy(Ql).to(DEV)
+    L, rec = lv.lv_autotune_window(multi, 0, Qd, truth, 10, 0.9, 512)
+    assert rec >= 0.9 and 10 <= L <= 512
+
+    def recall_at(L):
+        ids, _, _ = plain(lv, ix, Qd, 10, L)
+        torch.cuda.synchronize()
+        return exact.recall_at_k(ids.cpu().numpy().view(np.uint32).astype(np.int64),
+                                 truth.astype(np.int64), 10)
+
+    assert recall_at(L) == pytest.approx(rec)
+    if L > 10:
+        assert recall_at(L - 1) < 0.9
+    multi.close()
+
+
+def test_autotune_knobs_returns_a_valid_choice(lv, subs):
+    multi = lv.Multi([ix for _, ix in subs])
+    reqs = [(0, 10, 40, 50), (1, 10, 40, 50), (2, 10, 40, 50)]
+    Q = torch.from_numpy(np.concatenate([subs[s][0].Q[:50] for s in range(3)])).to(DEV)
+    ids = torch.zeros((1500,), dtype=torch.int32, device=DEV)
+    sc = torch.zeros((1500,), dtype=torch.float32, device=DEV)
+    best, ms = lv.lv_autotune_knobs(multi, 4, 256, 64, reqs, Q, ids, sc, reps=2)
+    assert best["hash_slots"] in (1024, 2048, 4096, 8192) and ms > 0
+    multi.close()
