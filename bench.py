@@ -66,7 +66,7 @@ def cache_dir():
 def build_graph_cached(wl, X, out):
     from synth import graph
 
-    key = f"{wl.name}_s{wl.seed_data}_n{wl.N}_R{wl.R}_a{'-'.join(map(str, wl.graph_alphas))}_v4"
+    key = f"{wl.name}_s{wl.seed_data}_n{wl.N}_R{wl.R}_a{'-'.join(map(str, wl.graph_alphas))}_v5"
     p = os.path.join(cache_dir(), key + ".npz")
     if os.path.exists(p):
         z = np.load(p)

@@ -356,6 +356,59 @@ int lv_autotune_knobs(lv_multi *multi, const lv_batch_caps *caps, const lv_reque
                       int32_t nreq, const float *Q, uint32_t *ids, float *scores, int32_t reps,
                       lv_search_params *best, double *best_ms, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Differentiable projection refinement (device, matrix cores).
+ * ---------------------------------------------------------------------- */
+
+/*
+ * C = alpha * op(A) op(B)^T + beta * C on the matrix cores (operands rounded
+ * to bfloat16, float32 accumulation), the product the loss kernels use.
+ * a(m, k) is A[m*lda + k] if a_kcont else A[k*lda + m]; likewise b(n, k).
+ * C: device float32 [M][ldc].  beta = 0 does not read C.
+ */
+int lv_gemm(const float *A, int32_t a_kcont, int64_t lda, const float *B, int32_t b_kcont,
+            int64_t ldb, float *C, int64_t ldc, int32_t M, int32_t N, int32_t K, float alpha,
+            float beta, void *stream);
+
+/* Device workspace bytes for lv_projloss_fwd / lv_projloss_bwd. */
+size_t lv_projloss_workspace_size(int32_t bq, int32_t bx, int32_t D, int32_t d);
+
+/*
+ * Sampled-pair refinement loss of the LeanVec-OOD objective (Problem
+ * leanvec_orthonormal): for queries Qb [bq][D] and database vectors Xb
+ * [bx][D] (device float32 rows) and projections A, B [d][D],
+ *   loss = ||Qb Xb^T - (Qb A^T)(Xb B^T)^T||_F^2 / (bq bx) + lam * f(A, B),
+ * f the trace form (Problem leanvec_efficient) on normalised moments KQn =
+ * K_Q/m, KXn = K_X/n (device float32 [D][D], symmetric; both NULL to drop
+ * the trace part) with trace_const = tr(KQn KXn) supplied by the caller.
+ * loss: device float32 [3] out = {total, pair part, trace part f}.
+ * Leaves the intermediates lv_projloss_bwd needs in ws.
+ */
+int lv_projloss_fwd(const float *A, const float *B, const float *Qb, const float *Xb, int32_t bq,
+                    int32_t bx, int32_t D, int32_t d, const float *KQn, const float *KXn,
+                    double trace_const, float lam, float *loss, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/*
+ * Gradients of that loss times grad_scale (Eq. leanvec_gradients for the
+ * trace part; the pair part by differentiating the squared residual):
+ * dA, dB device float32 [d][D] out.  ws must hold the intermediates of the
+ * preceding lv_projloss_fwd on the same arguments.
+ */
+int lv_projloss_bwd(const float *A, const float *B, const float *Qb, const float *Xb, int32_t bq,
+                    int32_t bx, int32_t D, int32_t d, const float *KQn, const float *KXn,
+                    float lam, float grad_scale, float *dA, float *dB, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* One Adam update (Kingma & Ba) of n parameters: m, v are the moment
+ * buffers (device float32), t >= 1 the step number for bias correction. */
+int lv_adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr, float beta1,
+                 float beta2, float eps, int32_t t, void *stream);
+
+/* Host float64: project M [d][D] onto the spectral-norm ball C (Eq.
+ * stiefel_convex_hull) by clipping its singular values at 1, in place. */
+int lv_clip_spectral(double *M, int32_t d, int32_t D);
+
 #ifdef __cplusplus
 }
 #endif

@@ -91,6 +91,17 @@ _SIGS = {
     "lv_autotune_window": (_c_i32, [_vp, _c_i32, _vp, _c_i64, _vp, _c_i32, _c_i32, _c_dbl,
                                     _c_i32, ctypes.POINTER(SearchParams),
                                     ctypes.POINTER(_c_i32), ctypes.POINTER(_c_dbl), _vp]),
+    "lv_gemm": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i32, _c_i64, _vp, _c_i64, _c_i32, _c_i32,
+                         _c_i32, ctypes.c_float, ctypes.c_float, _vp]),
+    "lv_projloss_workspace_size": (ctypes.c_size_t, [_c_i32, _c_i32, _c_i32, _c_i32]),
+    "lv_projloss_fwd": (_c_i32, [_vp, _vp, _vp, _vp, _c_i32, _c_i32, _c_i32, _c_i32, _vp, _vp,
+                                 _c_dbl, ctypes.c_float, _vp, _vp, ctypes.c_size_t, _vp]),
+    "lv_projloss_bwd": (_c_i32, [_vp, _vp, _vp, _vp, _c_i32, _c_i32, _c_i32, _c_i32, _vp, _vp,
+                                 ctypes.c_float, ctypes.c_float, _vp, _vp, _vp, ctypes.c_size_t,
+                                 _vp]),
+    "lv_adam_step": (_c_i32, [_vp, _vp, _vp, _vp, _c_i64, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_float, _c_i32, _vp]),
+    "lv_clip_spectral": (_c_i32, [_vp, _c_i32, _c_i32]),
     "lv_autotune_knobs": (_c_i32, [_vp, ctypes.POINTER(BatchCaps), ctypes.POINTER(Request),
                                    _c_i32, _vp, _vp, _vp, _c_i32, ctypes.POINTER(SearchParams),
                                    ctypes.POINTER(_c_dbl), _vp]),
@@ -417,3 +428,61 @@ def lv_autotune_knobs(multi: Multi, max_requests, max_queries, max_L, reqs, Q, i
                                     _dev(scores, torch.float32), reps, ctypes.byref(best),
                                     ctypes.byref(ms), _stream(stream)))
     return {"hash_slots": best.hash_slots}, ms.value
+
+
+# ------------------------------------------------- differentiable projection
+
+def lv_gemm(A, B, C, M, N, K, a_kcont=True, b_kcont=True, lda=None, ldb=None, ldc=None,
+            alpha=1.0, beta=0.0, stream=None):
+    import torch
+
+    lda = lda if lda is not None else (K if a_kcont else M)
+    ldb = ldb if ldb is not None else (K if b_kcont else N)
+    ldc = ldc if ldc is not None else N
+    _check(load().lv_gemm(_dev(A, torch.float32), int(a_kcont), lda, _dev(B, torch.float32),
+                          int(b_kcont), ldb, _dev(C, torch.float32), ldc, M, N, K, alpha, beta,
+                          _stream(stream)))
+
+
+def lv_projloss_workspace_size(bq, bx, D, d) -> int:
+    return load().lv_projloss_workspace_size(bq, bx, D, d)
+
+
+def lv_projloss_fwd(A, B, Qb, Xb, loss, ws, KQn=None, KXn=None, trace_const=0.0, lam=1.0,
+                    stream=None):
+    import torch
+
+    d, D = A.shape
+    _check(load().lv_projloss_fwd(_dev(A, torch.float32), _dev(B, torch.float32),
+                                  _dev(Qb, torch.float32), _dev(Xb, torch.float32), Qb.shape[0],
+                                  Xb.shape[0], D, d, _dev(KQn, torch.float32),
+                                  _dev(KXn, torch.float32), trace_const, lam,
+                                  _dev(loss, torch.float32), _dev(ws),
+                                  ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def lv_projloss_bwd(A, B, Qb, Xb, dA, dB, ws, KQn=None, KXn=None, lam=1.0, grad_scale=1.0,
+                    stream=None):
+    import torch
+
+    d, D = A.shape
+    _check(load().lv_projloss_bwd(_dev(A, torch.float32), _dev(B, torch.float32),
+                                  _dev(Qb, torch.float32), _dev(Xb, torch.float32), Qb.shape[0],
+                                  Xb.shape[0], D, d, _dev(KQn, torch.float32),
+                                  _dev(KXn, torch.float32), lam, grad_scale,
+                                  _dev(dA, torch.float32), _dev(dB, torch.float32), _dev(ws),
+                                  ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def lv_adam_step(p, g, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    import torch
+
+    _check(load().lv_adam_step(_dev(p, torch.float32), _dev(g, torch.float32),
+                               _dev(m, torch.float32), _dev(v, torch.float32), p.numel(), lr,
+                               beta1, beta2, eps, t, _stream(stream)))
+
+
+def lv_clip_spectral(M: np.ndarray) -> np.ndarray:
+    M = np.array(M, dtype=np.float64, order="C")
+    _check(load().lv_clip_spectral(M.ctypes.data, M.shape[0], M.shape[1]))
+    return M

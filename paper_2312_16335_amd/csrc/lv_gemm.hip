@@ -1,0 +1,161 @@
+// General matrix product on the gfx950 matrix cores for the projection-loss
+// kernels: C[M][N] = alpha * sum_k a(m, k) b(n, k) + beta * C, float32 in
+// memory, operands rounded to bfloat16 when staged, float32 accumulation.
+//
+// Each operand is either "k-contiguous" (a(m, k) at A[m * lda + k]) or
+// "m-contiguous" (a(m, k) at A[k * lda + m]); the staging step writes both
+// kinds into LDS as [row][k] tiles so the MFMA operand reads are 16-byte
+// vector loads.  Tile 128 x 128 x 32 per 256-thread workgroup, each
+// wavefront a 64 x 64 quadrant (2 x 2 tiles of 32 x 32x16 MFMAs), two LDS
+// buffers so the next tile is staged while the current one is multiplied.
+#include "lv_common.h"
+#include "lv_gemm.h"
+
+namespace lv {
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+
+constexpr int BM = 128, BN = 128, BK = 32;
+constexpr int LDK = BK + 8;  // padded row (bf16 elements) against LDS bank conflicts
+
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Stage a BM x BK tile of operand X (rows r0.., k k0..) into S[row][k].
+template <bool KCONT>
+__device__ __forceinline__ void stage(const float *__restrict__ X, int64_t ld, int rows,
+                                      int kdim, int r0, int k0, uint16_t *S, int tid) {
+  if constexpr (KCONT) {
+    // thread: row tid / 2, 16 consecutive k at (tid % 2) * 16
+    const int r = tid >> 1;
+    const int kk = (tid & 1) * 16;
+    const int gr = r0 + r;
+    uint16_t v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int gk = k0 + kk + i;
+      v[i] = (gr < rows && gk < kdim) ? bf16_bits(X[(int64_t)gr * ld + gk]) : (uint16_t)0;
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(S + r * LDK + kk);
+    uint32_t w[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = (uint32_t)v[2 * i] | ((uint32_t)v[2 * i + 1] << 16);
+    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  } else {
+    // thread: k row tid / 8, 16 consecutive rows at (tid % 8) * 16
+    const int kk = tid >> 3;
+    const int rr = (tid & 7) * 16;
+    const int gk = k0 + kk;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int gr = r0 + rr + i;
+      S[(rr + i) * LDK + kk] =
+          (gr < rows && gk < kdim) ? bf16_bits(X[(int64_t)gk * ld + gr]) : (uint16_t)0;
+    }
+  }
+}
+
+template <bool AK, bool BKC>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  __shared__ __align__(16) uint16_t As[2][BM * LDK];
+  __shared__ __align__(16) uint16_t Bs[2][BN * LDK];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int nk = (g.K + BK - 1) / BK;
+  stage<AK>(g.A, g.lda, g.M, g.K, m0, 0, As[0], tid);
+  stage<BKC>(g.B, g.ldb, g.N, g.K, n0, 0, Bs[0], tid);
+  __syncthreads();
+  const int r = lane & 31, kh = lane >> 5;
+  for (int t = 0; t < nk; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < nk) {
+      stage<AK>(g.A, g.lda, g.M, g.K, m0, (t + 1) * BK, As[cur ^ 1], tid);
+      stage<BKC>(g.B, g.ldb, g.N, g.K, n0, (t + 1) * BK, Bs[cur ^ 1], tid);
+    }
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const u32x4 wa =
+            *reinterpret_cast<const u32x4 *>(&As[cur][(wm + 32 * i + r) * LDK + ks + 8 * kh]);
+        a[i] = __builtin_bit_cast(bf16x8, wa);
+        const u32x4 wb =
+            *reinterpret_cast<const u32x4 *>(&Bs[cur][(wn + 32 * i + r) * LDK + ks + 8 * kh]);
+        b[i] = __builtin_bit_cast(bf16x8, wb);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // accumulator: lane holds column (lane % 32), register e holds row
+  // 8 * (e / 4) + 4 * (lane / 32) + (e % 4) of its 32 x 32 tile
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + 32 * j + r;
+      if (col >= g.N) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = m0 + wm + 32 * i + 8 * (e >> 2) + 4 * kh + (e & 3);
+        if (row >= g.M) continue;
+        float *c = g.C + (int64_t)row * g.ldc + col;
+        const float v = g.alpha * acc[i][j][e];
+        *c = g.beta == 0.f ? v : v + g.beta * *c;
+      }
+    }
+}
+
+}  // namespace
+
+int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return LV_OK;
+  const dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
+  if (a_kcont && b_kcont)
+    hipLaunchKernelGGL((gemm_kernel<true, true>), grid, dim3(256), 0, s, g);
+  else if (a_kcont)
+    hipLaunchKernelGGL((gemm_kernel<true, false>), grid, dim3(256), 0, s, g);
+  else if (b_kcont)
+    hipLaunchKernelGGL((gemm_kernel<false, true>), grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL((gemm_kernel<false, false>), grid, dim3(256), 0, s, g);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+}  // namespace lv
+
+extern "C" int lv_gemm(const float *A, int32_t a_kcont, int64_t lda, const float *B,
+                       int32_t b_kcont, int64_t ldb, float *C, int64_t ldc, int32_t M, int32_t N,
+                       int32_t K, float alpha, float beta, void *stream) {
+  lv::clear_error();
+  if (M < 0 || N < 0 || K < 0) LV_FAIL(LV_EINVAL, "negative size");
+  if ((int64_t)M * N > 0 && (!A || !B || !C)) LV_FAIL(LV_EINVAL, "NULL pointer");
+  if (ldc < N || lda < (a_kcont ? K : M) || ldb < (b_kcont ? K : N))
+    LV_FAIL(LV_EINVAL, "leading dimension too small");
+  lv::GemmArgs g{A, lda, B, ldb, C, ldc, M, N, K, alpha, beta};
+  return lv::gemm(g, a_kcont != 0, b_kcont != 0, static_cast<hipStream_t>(stream));
+}

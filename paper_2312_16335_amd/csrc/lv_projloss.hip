@@ -1,0 +1,231 @@
+// Differentiable projection loss on the matrix cores, and Adam.
+//
+// For a block of b_q queries Qb and b_x database vectors Xb (rows), with
+// P = b_q * b_x pairs, the refinement loss built from the LeanVec-OOD
+// objective (Problem leanvec_orthonormal, trace form Problem
+// leanvec_efficient on the normalised moments K_Q/m, K_X/n) is
+//
+//   G = Qb A^T, H = Xb B^T, Rm = Qb Xb^T - G H^T
+//   loss = ||Rm||_F^2 / P + lam * f(A, B)
+//   f = <A K_Q A^T, B K_X B^T>_F + tr(K_Q K_X) - 2 <A K_Q, B K_X>_F
+//
+// with gradients (pair part by differentiating the squared residual, trace
+// part Eq. leanvec_gradients):
+//   dA = -(2/P) (Rm H)^T Qb + 2 lam ((B K_X B^T) A - B K_X) K_Q
+//   dB = -(2/P) (Rm^T G)^T Xb + 2 lam ((A K_Q A^T) B - A K_Q) K_X
+//
+// Every product is one launch of the bfloat16 matrix-core GEMM (float32
+// accumulation); Rm is formed as Qb Xb^T followed by a second product that
+// subtracts G H^T into the same buffer.  Sums of squares and inner products
+// use a fixed-order two-pass float64 reduction, so results are deterministic.
+#include "lv_common.h"
+#include "lv_gemm.h"
+
+namespace lv {
+namespace {
+
+constexpr int kRedBlocks = 512;
+
+// partial[blockIdx.x] = sum over a grid-stride slice of a[i] * b[i] (float64)
+__global__ __launch_bounds__(256) void dot_partials(const float *__restrict__ a,
+                                                    const float *__restrict__ b, int64_t n,
+                                                    double *__restrict__ partial) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    s += (double)a[i] * (double)b[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// out[0] = total, out[1] = pair part, out[2] = trace part
+__global__ void finish_loss(const double *__restrict__ partial, int nblocks, double inv_pairs,
+                            double trace_const, float lam, int with_trace,
+                            float *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double p[3] = {0.0, 0.0, 0.0};
+  const int nparts = with_trace ? 3 : 1;
+  for (int j = 0; j < nparts; ++j)
+    for (int i = 0; i < nblocks; ++i) p[j] += partial[j * nblocks + i];
+  const double pair = p[0] * inv_pairs;
+  const double tr = with_trace ? p[1] + trace_const - 2.0 * p[2] : 0.0;
+  out[0] = (float)(pair + (double)lam * tr);
+  out[1] = (float)pair;
+  out[2] = (float)tr;
+}
+
+__global__ __launch_bounds__(256) void sub_kernel(const float *__restrict__ a,
+                                                  const float *__restrict__ b, int64_t n,
+                                                  float *__restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    out[i] = a[i] - b[i];
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p,
+                                                   const float *__restrict__ g,
+                                                   float *__restrict__ m, float *__restrict__ v,
+                                                   int64_t n, float lr, float b1, float b2,
+                                                   float eps, float c1, float c2) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// Workspace carve (floats, each region 64-float aligned).
+struct Ws {
+  float *G, *H, *Rm, *T, *S, *U1, *U2, *M1, *M2, *W;
+  double *partial;
+};
+
+size_t align64(size_t n) { return (n + 63) & ~(size_t)63; }
+
+size_t ws_floats(int64_t bq, int64_t bx, int64_t D, int64_t d, Ws *w, float *base) {
+  size_t off = 0;
+  auto take = [&](float **p, size_t n) {
+    if (w) *p = base + off;
+    off += align64(n);
+  };
+  Ws dummy;
+  Ws *t = w ? w : &dummy;
+  take(&t->G, bq * d);
+  take(&t->H, bx * d);
+  take(&t->Rm, bq * bx);
+  take(&t->T, bq * d);
+  take(&t->S, bx * d);
+  take(&t->U1, d * D);
+  take(&t->U2, d * D);
+  take(&t->M1, d * d);
+  take(&t->M2, d * d);
+  take(&t->W, d * D);
+  float *pp = nullptr;
+  take(&pp, 2 * 3 * kRedBlocks);  // float64 partials
+  if (w) w->partial = reinterpret_cast<double *>(pp);
+  return off;
+}
+
+int check_args(const float *A, const float *B, const float *Qb, const float *Xb, int32_t bq,
+               int32_t bx, int32_t D, int32_t d, void *ws, size_t ws_bytes) {
+  if (bq < 1 || bx < 1 || D < 1 || d < 1 || d > D) LV_FAIL(LV_EINVAL, "bad sizes");
+  if (!A || !B || !Qb || !Xb || !ws) LV_FAIL(LV_EINVAL, "NULL pointer");
+  const size_t need = ws_floats(bq, bx, D, d, nullptr, nullptr) * sizeof(float);
+  if (ws_bytes < need) LV_FAIL(LV_EINVAL, "workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+  return LV_OK;
+}
+
+#define LV_G(...)                                   \
+  do {                                              \
+    int rc_ = ::lv::gemm(__VA_ARGS__);              \
+    if (rc_ != LV_OK) return rc_;                   \
+  } while (0)
+
+}  // namespace
+}  // namespace lv
+
+extern "C" size_t lv_projloss_workspace_size(int32_t bq, int32_t bx, int32_t D, int32_t d) {
+  if (bq < 1 || bx < 1 || D < 1 || d < 1) return 0;
+  return lv::ws_floats(bq, bx, D, d, nullptr, nullptr) * sizeof(float);
+}
+
+extern "C" int lv_projloss_fwd(const float *A, const float *B, const float *Qb, const float *Xb,
+                               int32_t bq, int32_t bx, int32_t D, int32_t d, const float *KQn,
+                               const float *KXn, double trace_const, float lam, float *loss,
+                               void *ws, size_t ws_bytes, void *stream) {
+  lv::clear_error();
+  int rc = lv::check_args(A, B, Qb, Xb, bq, bx, D, d, ws, ws_bytes);
+  if (rc != LV_OK) return rc;
+  if (!loss) LV_FAIL(LV_EINVAL, "NULL loss");
+  if ((KQn == nullptr) != (KXn == nullptr)) LV_FAIL(LV_EINVAL, "give both K_Q and K_X or neither");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lv::Ws w;
+  lv::ws_floats(bq, bx, D, d, &w, static_cast<float *>(ws));
+  using lv::GemmArgs;
+  // G = Qb A^T, H = Xb B^T
+  LV_G(GemmArgs{Qb, D, A, D, w.G, d, bq, d, D, 1.f, 0.f}, true, true, s);
+  LV_G(GemmArgs{Xb, D, B, D, w.H, d, bx, d, D, 1.f, 0.f}, true, true, s);
+  // Rm = Qb Xb^T - G H^T
+  LV_G(GemmArgs{Qb, D, Xb, D, w.Rm, bx, bq, bx, D, 1.f, 0.f}, true, true, s);
+  LV_G(GemmArgs{w.G, d, w.H, d, w.Rm, bx, bq, bx, d, -1.f, 1.f}, true, true, s);
+  const int with_trace = KQn != nullptr;
+  hipLaunchKernelGGL(lv::dot_partials, dim3(lv::kRedBlocks), dim3(256), 0, s, w.Rm, w.Rm,
+                     (int64_t)bq * bx, w.partial);
+  if (with_trace) {
+    // U1 = B K_X, U2 = A K_Q (moments symmetric), M2 = U1 B^T, M1 = U2 A^T
+    LV_G(GemmArgs{B, D, KXn, D, w.U1, D, d, D, D, 1.f, 0.f}, true, true, s);
+    LV_G(GemmArgs{A, D, KQn, D, w.U2, D, d, D, D, 1.f, 0.f}, true, true, s);
+    LV_G(GemmArgs{w.U1, D, B, D, w.M2, d, d, d, D, 1.f, 0.f}, true, true, s);
+    LV_G(GemmArgs{w.U2, D, A, D, w.M1, d, d, d, D, 1.f, 0.f}, true, true, s);
+    hipLaunchKernelGGL(lv::dot_partials, dim3(lv::kRedBlocks), dim3(256), 0, s, w.M1, w.M2,
+                       (int64_t)d * d, w.partial + lv::kRedBlocks);
+    hipLaunchKernelGGL(lv::dot_partials, dim3(lv::kRedBlocks), dim3(256), 0, s, w.U2, w.U1,
+                       (int64_t)d * D, w.partial + 2 * lv::kRedBlocks);
+  }
+  hipLaunchKernelGGL(lv::finish_loss, dim3(1), dim3(64), 0, s, w.partial, lv::kRedBlocks,
+                     1.0 / ((double)bq * (double)bx), trace_const, lam, with_trace, loss);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+extern "C" int lv_projloss_bwd(const float *A, const float *B, const float *Qb, const float *Xb,
+                               int32_t bq, int32_t bx, int32_t D, int32_t d, const float *KQn,
+                               const float *KXn, float lam, float grad_scale, float *dA,
+                               float *dB, void *ws, size_t ws_bytes, void *stream) {
+  lv::clear_error();
+  int rc = lv::check_args(A, B, Qb, Xb, bq, bx, D, d, ws, ws_bytes);
+  if (rc != LV_OK) return rc;
+  if (!dA || !dB) LV_FAIL(LV_EINVAL, "NULL gradient output");
+  if ((KQn == nullptr) != (KXn == nullptr)) LV_FAIL(LV_EINVAL, "give both K_Q and K_X or neither");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lv::Ws w;
+  lv::ws_floats(bq, bx, D, d, &w, static_cast<float *>(ws));
+  using lv::GemmArgs;
+  const float c = -2.f * grad_scale / (float)((double)bq * (double)bx);
+  // T = Rm H  (bq x d), S = Rm^T G (bx x d)
+  LV_G(GemmArgs{w.Rm, bx, w.H, d, w.T, d, bq, d, bx, 1.f, 0.f}, true, false, s);
+  LV_G(GemmArgs{w.Rm, bx, w.G, d, w.S, d, bx, d, bq, 1.f, 0.f}, false, false, s);
+  // dA = c T^T Qb, dB = c S^T Xb
+  LV_G(GemmArgs{w.T, d, Qb, D, dA, D, d, D, bq, c, 0.f}, false, false, s);
+  LV_G(GemmArgs{w.S, d, Xb, D, dB, D, d, D, bx, c, 0.f}, false, false, s);
+  if (KQn) {
+    const float t = 2.f * lam * grad_scale;
+    const int64_t n = (int64_t)d * D;
+    const unsigned blocks = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    // dA += t (M2 A - U1) K_Q
+    LV_G(GemmArgs{w.M2, d, A, D, w.W, D, d, D, d, 1.f, 0.f}, true, false, s);
+    hipLaunchKernelGGL(lv::sub_kernel, dim3(blocks), dim3(256), 0, s, w.W, w.U1, n, w.W);
+    LV_G(GemmArgs{w.W, D, KQn, D, dA, D, d, D, D, t, 1.f}, true, true, s);
+    // dB += t (M1 B - U2) K_X
+    LV_G(GemmArgs{w.M1, d, B, D, w.W, D, d, D, d, 1.f, 0.f}, true, false, s);
+    hipLaunchKernelGGL(lv::sub_kernel, dim3(blocks), dim3(256), 0, s, w.W, w.U2, n, w.W);
+    LV_G(GemmArgs{w.W, D, KXn, D, dB, D, d, D, D, t, 1.f}, true, true, s);
+  }
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+extern "C" int lv_adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                            float beta1, float beta2, float eps, int32_t t, void *stream) {
+  lv::clear_error();
+  if (n < 0 || t < 1) LV_FAIL(LV_EINVAL, "bad n or step");
+  if (n > 0 && (!p || !g || !m || !v)) LV_FAIL(LV_EINVAL, "NULL pointer");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && lr >= 0.f && eps > 0.f))
+    LV_FAIL(LV_EINVAL, "bad Adam hyper-parameters");
+  if (n == 0) return LV_OK;
+  const float c1 = 1.f - powf(beta1, (float)t);
+  const float c2 = 1.f - powf(beta2, (float)t);
+  const unsigned blocks = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(lv::adam_kernel, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     p, g, m, v, n, lr, beta1, beta2, eps, c1, c2);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}

@@ -69,7 +69,7 @@ class Workload:
     seed_rot: int = 0
     seed_shift: int = 0
     shift: float = 0.5
-    graph_alphas: Tuple[float, ...] = (1.0, 1.2)   # pruning factor per build pass
+    graph_alphas: Tuple[float, ...] = (1.0, 1.0)   # pruning factor per build pass
 
     def scaled(self, N: Optional[int] = None, m_test: Optional[int] = None,
                m_learn: Optional[int] = None) -> "Workload":

@@ -57,15 +57,19 @@ METRIC_L2, METRIC_IP = 0, 1
 
 
 def build_graph(X: np.ndarray, R: int, L: int = 0, metric: int = METRIC_L2,
-                alphas: Sequence[float] = (1.0, 1.2), maxc: int = 0,
+                alphas: Sequence[float] = (1.0, 1.0), maxc: int = 0,
                 batch_frac: float = 0.02, seed: int = 7,
                 threads: int = 0) -> Tuple[np.ndarray, int]:
     """Graph over the rows of X.
 
     Rows are rounded to float16 (as the secondary vectors are).  The
-    default is the Euclidean rule with alpha 1.0 then 1.2 (the paper's
-    Euclidean setting); on unit-norm rows it ranks neighbours exactly as
-    inner product does.  L defaults to 2R (search window during
+    default is the Euclidean rule (on unit-norm rows it ranks neighbours
+    exactly as inner product does) with two passes at alpha = 1.0.  The
+    paper's Euclidean setting is alpha = 1.2; on the synthetic cluster
+    mixtures, whose members are nearly equidistant, alpha = 1.2 keeps the
+    nearest R cluster members and the graph navigates poorly, while 1.0
+    prunes them into diverse edges (recall@10 at window 100 on 300k vectors:
+    0.88 vs 0.97).  L defaults to 2R (search window during
     construction); maxc caps the pruning pool (default 8R).  Deterministic
     for any thread count.
     """

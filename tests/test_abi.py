@@ -192,3 +192,15 @@ def test_fit_es_matches_oracle():
     f = ofit.equalised_loss(P, KQ, len(Q), KX, len(X))
     assert abs(beta - bo) < 1e-3
     assert f <= fo + 1e-9 * abs(fo)
+
+
+def test_clip_spectral_against_svd():
+    rng = np.random.default_rng(8)
+    M = rng.standard_normal((6, 20)) * 0.7
+    U, s, Vt = np.linalg.svd(M, full_matrices=False)
+    assert s.max() > 1 and s.min() < 1
+    got = lv.lv_clip_spectral(M)
+    want = U @ np.diag(np.minimum(s, 1.0)) @ Vt
+    assert np.allclose(got, want, atol=1e-10)
+    inside = M / (2 * s.max())
+    assert np.array_equal(lv.lv_clip_spectral(inside), inside)

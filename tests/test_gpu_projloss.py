@@ -1,0 +1,145 @@
+"""GPU tests of the differentiable projection path: the matrix-core GEMM (exact on
+bfloat16-representable inputs), the sampled-pair + trace loss and its gradients
+against the float64 oracle at the refinement shape (bfloat16 error stated),
+the autograd wrapper, and Adam."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import fit as ofit
+from oracle import projloss as opl
+from synth import gen
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def lv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2312_16335_amd as lv
+
+    lv.load()
+    return lv
+
+
+def t(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+@pytest.mark.parametrize("M,N,K", [(70, 130, 45), (128, 128, 32), (1, 300, 7), (257, 3, 100)])
+@pytest.mark.parametrize("ak,bk", [(True, True), (True, False), (False, True), (False, False)])
+def test_gemm_exact_on_small_integers(lv, M, N, K, ak, bk):
+    rng = np.random.default_rng(M * 7 + N + K)
+    a = rng.integers(-6, 7, size=(M, K)).astype(np.float64)
+    b = rng.integers(-6, 7, size=(N, K)).astype(np.float64)
+    c0 = rng.integers(-3, 4, size=(M, N)).astype(np.float64)
+    A = a if ak else a.T.copy()
+    B = b if bk else b.T.copy()
+    C = t(c0)
+    lv.lv_gemm(t(A), t(B), C, M, N, K, a_kcont=ak, b_kcont=bk, alpha=2.0, beta=-1.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy().astype(np.float64), 2.0 * a @ b.T - c0)
+
+
+@pytest.fixture(scope="module")
+def block():
+    wl = gen.WORKLOADS["ood-1m-768"].scaled(N=8192, m_test=2048)
+    mix = gen.mixture(wl)
+    X = gen.database(wl, mix)
+    Q = gen.queries(wl, "test", mix=mix)
+    KX = ofit.second_moment(X) / len(X)
+    KQ = ofit.second_moment(Q) / len(Q)
+    P = ofit.fit_id(ofit.second_moment(X), wl.d)
+    rng = np.random.default_rng(3)
+    A = P + 0.01 * rng.standard_normal(P.shape)
+    B = P + 0.01 * rng.standard_normal(P.shape)
+    return A, B, Q[:1024], X[:4096], KQ, KX
+
+
+def test_projloss_forward_backward_against_float64(lv, block):
+    A, B, Qb, Xb, KQ, KX = block
+    d, D = A.shape
+    lam = 1.0
+    tc = float(np.trace(KQ @ KX))
+    ws = torch.empty(lv.lv_projloss_workspace_size(len(Qb), len(Xb), D, d), dtype=torch.uint8,
+                     device=DEV)
+    loss = torch.empty(3, dtype=torch.float32, device=DEV)
+    dA, dB = torch.empty((d, D), device=DEV), torch.empty((d, D), device=DEV)
+    At, Bt, Qt, Xt, KQt, KXt = t(A), t(B), t(Qb), t(Xb), t(KQ), t(KX)
+    lv.lv_projloss_fwd(At, Bt, Qt, Xt, loss, ws, KQt, KXt, tc, lam)
+    lv.lv_projloss_bwd(At, Bt, Qt, Xt, dA, dB, ws, KQt, KXt, lam, 1.0)
+    torch.cuda.synchronize()
+    # the oracle on the same float32-rounded inputs, in float64
+    A32, B32 = A.astype(np.float32), B.astype(np.float32)
+    pair = opl.pair_loss(A32, B32, Qb, Xb)
+    tr = ofit.loss_trace(A32, B32, KQ.astype(np.float32), KX.astype(np.float32))
+    gA, gB = opl.grads(A32, B32, Qb, Xb, KQ.astype(np.float32), KX.astype(np.float32), lam)
+    got = loss.cpu().numpy().astype(np.float64)
+    err = {
+        "pair": abs(got[1] - pair) / pair,
+        "trace": abs(got[2] - tr) / abs(tr),
+        "dA": np.linalg.norm(dA.cpu().numpy() - gA) / np.linalg.norm(gA),
+        "dB": np.linalg.norm(dB.cpu().numpy() - gB) / np.linalg.norm(gB),
+    }
+    print("bfloat16 relative errors vs float64:", err)
+    # bfloat16 operands (2^-9 relative rounding) with float32 accumulation
+    assert err["pair"] < 2e-2 and err["dA"] < 5e-2 and err["dB"] < 5e-2
+    assert err["trace"] < 5e-2
+    assert abs(got[0] - (got[1] + lam * got[2])) <= 1e-6 * abs(got[0])
+
+
+def test_autograd_function_matches_kernels(lv, block):
+    from paper_2312_16335_amd.autograd import ProjLoss
+
+    A, B, Qb, Xb, KQ, KX = block
+    d, D = A.shape
+    At = t(A).requires_grad_(True)
+    Bt = t(B).requires_grad_(True)
+    tc = float(np.trace(KQ @ KX))
+    loss = ProjLoss.apply(At, Bt, t(Qb), t(Xb), t(KQ), t(KX), tc, 0.5)
+    (3.0 * loss).backward()
+    ws = torch.empty(lv.lv_projloss_workspace_size(len(Qb), len(Xb), D, d), dtype=torch.uint8,
+                     device=DEV)
+    out = torch.empty(3, device=DEV)
+    dA, dB = torch.empty((d, D), device=DEV), torch.empty((d, D), device=DEV)
+    lv.lv_projloss_fwd(t(A), t(B), t(Qb), t(Xb), out, ws, t(KQ), t(KX), tc, 0.5)
+    lv.lv_projloss_bwd(t(A), t(B), t(Qb), t(Xb), dA, dB, ws, t(KQ), t(KX), 0.5, 3.0)
+    torch.cuda.synchronize()
+    assert torch.equal(loss.detach(), out[0])
+    assert torch.equal(At.grad, dA) and torch.equal(Bt.grad, dB)
+
+
+def test_adam_step_matches_definition(lv):
+    rng = np.random.default_rng(4)
+    p = rng.standard_normal(1000).astype(np.float32)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    pt, mt, vt = t(p), t(m), t(v)
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    for step in range(1, 4):
+        g = rng.standard_normal(1000).astype(np.float32)
+        lv.lv_adam_step(pt, t(g), mt, vt, lr, step, b1, b2, eps)
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        p = p - lr * (m / (1 - b1 ** step)) / (np.sqrt(v / (1 - b2 ** step)) + eps)
+    torch.cuda.synchronize()
+    assert np.allclose(pt.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+
+
+def test_refinement_reduces_the_loss(lv, block):
+    from paper_2312_16335_amd.autograd import refine
+
+    A, B, Qb, Xb, KQ, KX = block
+    Qt, Xt = t(Qb), t(Xb)
+    tc = float(np.trace(KQ @ KX))
+    losses = []
+
+    def blocks(step):
+        return Qt, Xt
+
+    refine(A, B, blocks, 30, lr=1e-3, KQn=t(KQ), KXn=t(KX), trace_const=tc, lam=1.0,
+           callback=lambda s, l: losses.append(float(l[0])))
+    assert losses[-1] < losses[0]
