@@ -196,7 +196,7 @@ def test_fit_es_matches_oracle():
 
 def test_clip_spectral_against_svd():
     rng = np.random.default_rng(8)
-    M = rng.standard_normal((6, 20)) * 0.7
+    M = rng.standard_normal((6, 20)) * 0.25
     U, s, Vt = np.linalg.svd(M, full_matrices=False)
     assert s.max() > 1 and s.min() < 1
     got = lv.lv_clip_spectral(M)
