@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--only-steps", action="store_true",
                     help="skip the sweep refinement (profiling runs)")
     ap.add_argument("--L", type=int, default=0, help="fixed window (skips the sweep)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -149,6 +151,16 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.calibrate_copy:
+        # 1 GiB read + 1 GiB written per copy, three copies
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_copy": 1 << 30,
+                          "bytes_written_per_copy": 1 << 30, "copies": 3}))
+        return
     lv.load()
     dev = torch.device("cuda:0")
     wl = gen.WORKLOADS[args.workload]
@@ -314,9 +326,12 @@ def main():
     multi = lv.Multi([index])
     reqs = [(0, k, L_star, b) for b in sizes]
     ids_flat, scores_flat = ids.view(-1), scores.view(-1)
-    knobs, _ = lv.lv_autotune_knobs(multi, nreq, m, L_star, reqs, Qd, ids_flat, scores_flat,
-                                    reps=2)
-    hs = args.hash_slots or knobs["hash_slots"]
+    if args.hash_slots:
+        hs = args.hash_slots
+    else:
+        knobs, _ = lv.lv_autotune_knobs(multi, nreq, m, L_star, reqs, Qd, ids_flat, scores_flat,
+                                        reps=2)
+        hs = knobs["hash_slots"]
     knob_hs[0] = hs
     batch = lv.Batch(multi, max_requests=nreq, max_queries=m, max_L=L_star, hash_slots=hs)
     log(f"batched step captured (visited-set slots {hs} chosen by the autotuner)")

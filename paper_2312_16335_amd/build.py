@@ -36,7 +36,8 @@ def _run(cmd):
     return r.stdout
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, extra_flags=()) -> str:
+    """Compile every source and link ``out`` (the package library by default)."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
@@ -44,23 +45,24 @@ def build(verbose: bool = False) -> str:
     for src in HIP_SOURCES:
         obj = os.path.join(objdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC] + HIP_FLAGS + PER_FILE.get(src, []) + lang + ["-c", os.path.join(CSRC, src),
-                                                                   "-o", obj]
-        out = _run(cmd)
-        if verbose and out.strip():
-            print(out)
+        cmd = ([HIPCC] + HIP_FLAGS + list(extra_flags) + PER_FILE.get(src, []) + lang
+               + ["-c", os.path.join(CSRC, src), "-o", obj])
+        msg = _run(cmd)
+        if verbose and msg.strip():
+            print(msg)
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(objdir, src + ".o")
         _run(["g++", "-O3", "-std=c++17", "-fPIC", "-fopenmp", "-march=x86-64-v3", "-c",
               os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp%d" % os.getpid()
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
          + ["-lgomp", "-Wl,-rpath," + os.path.join(ROCM, "lib")])
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     shutil.rmtree(objdir, ignore_errors=True)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":

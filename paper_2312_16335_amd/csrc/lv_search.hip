@@ -41,7 +41,8 @@ namespace {
 constexpr uint32_t kExpanded = 0x80000000u;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
-constexpr int kProbes = 16;
+constexpr int kProbes = 8;
+constexpr int kFastMerge = 8;  // survivors merged by counting instead of sorting
 
 // Everything one query needs besides the index.
 struct Job {
@@ -53,30 +54,35 @@ struct Job {
   uint32_t *counters;  // [2] or nullptr
 };
 
-// Window buffers are selected with conditionals, not indexed arrays, so
-// they stay in registers (a dynamically indexed pointer array would go to
-// scratch memory).
+// Dynamic LDS of the search kernels.  All per-query LDS state is addressed
+// from this array by offsets, so every access compiles to an LDS
+// instruction (a pointer chosen at run time between two buffers would
+// otherwise fall back to flat addressing).
+extern __shared__ __align__(16) unsigned char lv_smem[];
+
 struct Lds {
-  double *ls0, *ls1;
-  uint32_t *lid0, *lid1;
-  __device__ __forceinline__ double *ls(int b) const { return b ? ls1 : ls0; }
-  __device__ __forceinline__ uint32_t *lid(int b) const { return b ? lid1 : lid0; }
-  double *cs;
-  uint32_t *cid;
-  int32_t *lbc;
-  uint32_t *hash;
+  int Lmax;
+  __device__ __forceinline__ double *ls(int b) const {
+    return reinterpret_cast<double *>(lv_smem) + b * Lmax;
+  }
+  __device__ __forceinline__ double *cs() const {
+    return reinterpret_cast<double *>(lv_smem) + 2 * Lmax;
+  }
+  __device__ __forceinline__ uint32_t *lid(int b) const {
+    return reinterpret_cast<uint32_t *>(cs() + 64) + b * Lmax;
+  }
+  __device__ __forceinline__ uint32_t *cid() const { return lid(0) + 2 * Lmax; }
+  __device__ __forceinline__ int32_t *lbc() const {
+    return reinterpret_cast<int32_t *>(cid() + 64);
+  }
+  __device__ __forceinline__ uint32_t *hash() const {
+    return reinterpret_cast<uint32_t *>(lbc() + 64);
+  }
 };
 
-__device__ __forceinline__ Lds carve(unsigned char *smem, int Lmax) {
+__device__ __forceinline__ Lds carve(int Lmax) {
   Lds s;
-  s.ls0 = reinterpret_cast<double *>(smem);
-  s.ls1 = s.ls0 + Lmax;
-  s.cs = s.ls1 + Lmax;
-  s.lid0 = reinterpret_cast<uint32_t *>(s.cs + 64);
-  s.lid1 = s.lid0 + Lmax;
-  s.cid = s.lid1 + Lmax;
-  s.lbc = reinterpret_cast<int32_t *>(s.cid + 64);
-  s.hash = reinterpret_cast<uint32_t *>(s.lbc + 64);
+  s.Lmax = Lmax;
   return s;
 }
 
@@ -97,6 +103,28 @@ __device__ __forceinline__ int lane_rank(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Index data arrive through memory in the persistent kernel; marking the
+// pointers global keeps the loads global (not flat) instructions.
+#define LV_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const LV_GLOBAL T *gp(const T *p) {
+  return (const LV_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ LV_GLOBAL T *gpw(T *p) {
+  return (LV_GLOBAL T *)p;
+}
+
+__device__ __forceinline__ uint32_t lane_u32(uint32_t v, int j) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, j);
+}
+
+__device__ __forceinline__ double lane_f64(double v, int j) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = lane_u32((uint32_t)b, j), hi = lane_u32((uint32_t)(b >> 32), j);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <int W>
 __device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
@@ -109,21 +137,23 @@ struct Chunk {
   uint32_t w[V / 4];
 };
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 template <int V>
-__device__ __forceinline__ Chunk<V> load_chunk(const unsigned char *p) {
+__device__ __forceinline__ Chunk<V> load_chunk(const LV_GLOBAL unsigned char *p) {
   Chunk<V> c;
-  if constexpr (V == 4) {
-    c.w[0] = *reinterpret_cast<const uint32_t *>(p);
+  if constexpr (V == 16) {
+    const u32x4 t = *reinterpret_cast<const LV_GLOBAL u32x4 *>(p);
+    c.w[0] = t[0]; c.w[1] = t[1]; c.w[2] = t[2]; c.w[3] = t[3];
   } else if constexpr (V == 8) {
-    const uint2 t = *reinterpret_cast<const uint2 *>(p);
-    c.w[0] = t.x; c.w[1] = t.y;
-  } else if constexpr (V == 12) {
-    const uint3 t = *reinterpret_cast<const uint3 *>(p);
-    c.w[0] = t.x; c.w[1] = t.y; c.w[2] = t.z;
+    const u32x2 t = *reinterpret_cast<const LV_GLOBAL u32x2 *>(p);
+    c.w[0] = t[0]; c.w[1] = t[1];
   } else {
-    static_assert(V == 16, "record chunk of 4, 8, 12 or 16 bytes");
-    const uint4 t = *reinterpret_cast<const uint4 *>(p);
-    c.w[0] = t.x; c.w[1] = t.y; c.w[2] = t.z; c.w[3] = t.w;
+    static_assert(V == 4 || V == 12, "record chunk of 4, 8, 12 or 16 bytes");
+    const LV_GLOBAL uint32_t *w = reinterpret_cast<const LV_GLOBAL uint32_t *>(p);
+#pragma unroll
+    for (int i = 0; i < V / 4; ++i) c.w[i] = w[i];
   }
   return c;
 }
@@ -139,7 +169,7 @@ __device__ __forceinline__ uint32_t code_at(const Chunk<V> &c, int t) {
 // Score the nc candidate ids in cid[] into cs[].  Group g of G lanes takes
 // candidates g, g + 64/G, ...; U records per group are in flight at once.
 template <int BITS, int G, int V>
-__device__ __forceinline__ void score_batch(const IndexView &ix, const double (&qv)[V * 8 / BITS],
+__device__ __forceinline__ void score_batch(const IndexView &ix, const float (&qv)[V * 8 / BITS],
                                             double sq, double cq, const uint32_t *cid, double *cs,
                                             int nc, int lane) {
   constexpr int NQ = V * 8 / BITS;
@@ -154,11 +184,12 @@ __device__ __forceinline__ void score_batch(const IndexView &ix, const double (&
     for (int u = 0; u < U; ++u) {
       const int c = base + u * RPP + grp;
       dlw[u] = low[u] = 0u;
-      if (c < nc) {
-        const unsigned char *rec = ix.records + (size_t)cid[c] * (size_t)ix.stride;
+      if (base + u * RPP < nc && c < nc) {
+        const LV_GLOBAL unsigned char *rec = gp(ix.records) + (size_t)cid[c] * (size_t)ix.stride;
         ch[u] = load_chunk<V>(rec + gl * V);
         if (gl == 0) {
-          const uint32_t *cw = reinterpret_cast<const uint32_t *>(rec + ix.code_bytes);
+          const LV_GLOBAL uint32_t *cw =
+              reinterpret_cast<const LV_GLOBAL uint32_t *>(rec + ix.code_bytes);
           dlw[u] = cw[0];
           low[u] = cw[1];
         }
@@ -169,9 +200,11 @@ __device__ __forceinline__ void score_batch(const IndexView &ix, const double (&
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      if (base + u * RPP >= nc) break;  // uniform: no record in this pass
       double acc = 0.0;
 #pragma unroll
-      for (int t = 0; t < NQ; ++t) acc = fma((double)code_at<BITS, V>(ch[u], t), qv[t], acc);
+      for (int t = 0; t < NQ; ++t)
+        acc = fma((double)code_at<BITS, V>(ch[u], t), (double)qv[t], acc);
       acc = group_sum<G>(acc);
       const int c = base + u * RPP + grp;
       if (gl == 0 && c < nc) {
@@ -201,9 +234,13 @@ __device__ __forceinline__ void sort64(double &s, uint32_t &id, int lane) {
   }
 }
 
+// Visited test-and-set.  After kProbes occupied slots the id replaces the
+// one in its home slot (the set forgets an older id) and counts as unknown:
+// it is scored, and the merge drops it if it is in the window.
 __device__ __forceinline__ bool hash_visit(uint32_t *hash, int log2h, uint32_t n) {
   const uint32_t mask = (1u << log2h) - 1u;
-  uint32_t h = (n * 2654435761u) >> (32 - log2h);
+  const uint32_t h0 = (n * 2654435761u) >> (32 - log2h);
+  uint32_t h = h0;
 #pragma unroll 1
   for (int t = 0; t < kProbes; ++t) {
     const uint32_t old = atomicCAS(&hash[h], kEmpty, n);
@@ -211,7 +248,8 @@ __device__ __forceinline__ bool hash_visit(uint32_t *hash, int log2h, uint32_t n
     if (old == n) return false;
     h = (h + 1u) & mask;
   }
-  return true;  // unknown: score it; the merge drops it if it is in the window
+  atomicExch(&hash[h0], n);
+  return true;
 }
 
 template <bool F16>
@@ -227,23 +265,23 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = packet * E + e;
-      qq[pk][e] = (packet < ix.sec_packets && j < ix.D) ? q[j] : 0.f;
+      qq[pk][e] = (packet < ix.sec_packets && j < ix.D) ? gp(q)[j] : 0.f;
     }
   }
   for (int base = 0; base < nl; base += UR) {
-    uint4 v[UR][PPL];
+    u32x4 v[UR][PPL];
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
       const int idx = base + u;
       const uint32_t id = idx < nl ? (ids[idx] & kIdMask) : 0u;
-      const unsigned char *row = ix.sec + (size_t)id * (size_t)ix.sec_row_bytes;
+      const LV_GLOBAL unsigned char *row = gp(ix.sec) + (size_t)id * (size_t)ix.sec_row_bytes;
 #pragma unroll
       for (int pk = 0; pk < PPL; ++pk) {
         const int packet = lane + 64 * pk;
         if (idx < nl && packet < ix.sec_packets)
-          v[u][pk] = *reinterpret_cast<const uint4 *>(row + (size_t)packet * 16);
+          v[u][pk] = *reinterpret_cast<const LV_GLOBAL u32x4 *>(row + (size_t)packet * 16);
         else
-          v[u][pk] = make_uint4(0u, 0u, 0u, 0u);
+          v[u][pk] = u32x4{0u, 0u, 0u, 0u};
       }
     }
 #pragma unroll
@@ -251,7 +289,7 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
       double acc = 0.0;
 #pragma unroll
       for (int pk = 0; pk < PPL; ++pk) {
-        const uint32_t w[4] = {v[u][pk].x, v[u][pk].y, v[u][pk].z, v[u][pk].w};
+        const uint32_t w[4] = {v[u][pk][0], v[u][pk][1], v[u][pk][2], v[u][pk][3]};
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           float x;
@@ -276,34 +314,35 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
   const int L = job.L;
   const int hslots = 1 << log2h;
 
-  // projected query slice of this lane, float64
+  // projected query slice of this lane (float32, exact in float64 products)
   const int gl = lane % G;
-  double qv[NQ];
+  float qv[NQ];
   double sq = 0.0, cq = 0.0;
 #pragma unroll
   for (int t = 0; t < NQ; ++t) {
     const int j = gl * NQ + t;
-    const double x = j < ix.d ? (double)job.qp[j] : 0.0;
+    const float x = j < ix.d ? gp(job.qp)[j] : 0.f;
     qv[t] = x;
-    sq += x;
-    if (j < ix.d) cq = fma(x, (double)ix.mu[j], cq);
+    sq += (double)x;
+    if (j < ix.d) cq = fma((double)x, (double)gp(ix.mu)[j], cq);
   }
-  sq = group_sum<G>(sq);
-  cq = group_sum<G>(cq);
-  for (int i = lane; i < hslots; i += 64) sm.hash[i] = kEmpty;
+  // the same in every lane after the group reduction: keep them scalar
+  sq = lane_f64(group_sum<G>(sq), 0);
+  cq = lane_f64(group_sum<G>(cq), 0);
+  for (int i = lane; i < hslots; i += 64) sm.hash()[i] = kEmpty;
   wave_sync();
 
   // seed the window with the entry node
   if (lane == 0) {
-    sm.cid[0] = ix.entry;
-    hash_visit(sm.hash, log2h, ix.entry);
+    sm.cid()[0] = ix.entry;
+    hash_visit(sm.hash(), log2h, ix.entry);
   }
   wave_sync();
-  score_batch<BITS, G, V>(ix, qv, sq, cq, sm.cid, sm.cs, 1, lane);
+  score_batch<BITS, G, V>(ix, qv, sq, cq, sm.cid(), sm.cs(), 1, lane);
   wave_sync();
   if (lane == 0) {
-    sm.ls0[0] = sm.cs[0];
-    sm.lid0[0] = ix.entry;
+    sm.ls(0)[0] = sm.cs()[0];
+    sm.lid(0)[0] = ix.entry;
   }
   wave_sync();
   int nl = 1;
@@ -341,7 +380,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
     if (lane == 0) lid[pos] = p | kExpanded;
     wave_sync();
     ++n_exp;
-    const uint32_t *row = ix.adj + (size_t)p * (size_t)ix.R;
+    const LV_GLOBAL uint32_t *row = gp(ix.adj) + (size_t)p * (size_t)ix.R;
     uint32_t first = kSentinel;
     if (p == pf_id)
       first = pf_row;
@@ -350,18 +389,18 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
     // prefetch the runner-up's first chunk; consumed at the next hop if it is
     // still the best unexpanded candidate then
     pf_id = p2;
-    pf_row = (p2 != kSentinel && lane < ix.R) ? ix.adj[(size_t)p2 * (size_t)ix.R + lane]
+    pf_row = (p2 != kSentinel && lane < ix.R) ? gp(ix.adj)[(size_t)p2 * (size_t)ix.R + lane]
                                               : kSentinel;
     for (int rb = 0; rb < ix.R; rb += 64) {
       uint32_t n = rb == 0 ? first : (rb + lane < ix.R ? row[rb + lane] : kSentinel);
       bool fresh = false;
-      if (n < ix.N) fresh = hash_visit(sm.hash, log2h, n);
+      if (n < ix.N) fresh = hash_visit(sm.hash(), log2h, n);
       const uint64_t fm = __ballot(fresh);
       const int nc = __popcll(fm);
       if (nc == 0) continue;
-      if (fresh) sm.cid[lane_rank(fm)] = n;
+      if (fresh) sm.cid()[lane_rank(fm)] = n;
       wave_sync();
-      score_batch<BITS, G, V>(ix, qv, sq, cq, sm.cid, sm.cs, nc, lane);
+      score_batch<BITS, G, V>(ix, qv, sq, cq, sm.cid(), sm.cs(), nc, lane);
       wave_sync();
       n_dist += nc;
 
@@ -371,14 +410,81 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
       double bs = -INFINITY;
       uint32_t bid = kSentinel;
       if (lane < nc) {
-        bs = sm.cs[lane];
-        bid = sm.cid[lane];
+        bs = sm.cs()[lane];
+        bid = sm.cid()[lane];
       }
       if (nl == L && bid != kSentinel && !better(bs, bid, ls[L - 1], lid[L - 1] & kIdMask)) {
         bs = -INFINITY;
         bid = kSentinel;
       }
-      if (__ballot(bid != kSentinel) == 0) continue;
+      const uint64_t surv = __ballot(bid != kSentinel);
+      if (surv == 0) continue;
+      const int nsurv = __popcll(surv);
+      if (nsurv <= kFastMerge && nl <= 256) {
+        // Few survivors (the common case once the window is full): a survivor
+        // lands at (#window entries better) + (#kept survivors better), a
+        // window entry moves down by the kept survivors better than it.  The
+        // window is read into registers; survivors are broadcast one by one.
+        double es[4];
+        uint32_t er[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int e = lane + 64 * t;
+          const bool ok = e < nl;
+          es[t] = ok ? ls[e] : -INFINITY;
+          er[t] = ok ? lid[e] : kSentinel;
+        }
+        int sh[4] = {0, 0, 0, 0};  // kept survivors better than window entry t
+        int my_lb = 0, my_rank = 0;
+        bool my_keep = false;
+        int nkeep = 0;
+        uint64_t rem = surv;
+        while (rem) {  // uniform loop over survivors
+          const int j = __ffsll((unsigned long long)rem) - 1;
+          rem &= rem - 1;
+          const double cj = lane_f64(bs, j);
+          const uint32_t ij = lane_u32(bid, j);
+          int cnt = 0;
+          uint64_t dm = 0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const bool ok = er[t] != kSentinel;
+            const uint32_t idt = er[t] & kIdMask;
+            cnt += __popcll(__ballot(ok && better(es[t], idt, cj, ij)));
+            dm |= __ballot(ok && idt == ij);
+          }
+          const bool keep = dm == 0;  // not already in the window
+          if (keep) {
+            ++nkeep;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) sh[t] += (lane + 64 * t >= cnt) ? 1 : 0;
+            my_rank += (bid != kSentinel && better(cj, ij, bs, bid)) ? 1 : 0;
+          }
+          if (lane == j) {
+            my_lb = cnt;
+            my_keep = keep;
+          }
+        }
+        if (nkeep == 0) continue;
+        double *ls_n = sm.ls(cur ^ 1);
+        uint32_t *lid_n = sm.lid(cur ^ 1);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int e = lane + 64 * t;
+          if (e < nl && e + sh[t] < L) {
+            ls_n[e + sh[t]] = es[t];
+            lid_n[e + sh[t]] = er[t];
+          }
+        }
+        if (my_keep && my_lb + my_rank < L) {
+          ls_n[my_lb + my_rank] = bs;
+          lid_n[my_lb + my_rank] = bid;
+        }
+        nl = nl + nkeep < L ? nl + nkeep : L;
+        cur ^= 1;
+        wave_sync();
+        continue;
+      }
       sort64(bs, bid, lane);
       int lb = 0;
       bool valid = bid != kSentinel;
@@ -398,7 +504,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
       const int nv = __popcll(vm);
       if (nv == 0) continue;
       const int r = lane_rank(vm);
-      if (valid) sm.lbc[r] = lb;
+      if (valid) sm.lbc()[r] = lb;
       wave_sync();
       double *ls_n = sm.ls(cur ^ 1);
       uint32_t *lid_n = sm.lid(cur ^ 1);
@@ -406,7 +512,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
         int lo = 0, hi = nv;  // new entries placed before window entry j
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if (sm.lbc[mid] <= j)
+          if (sm.lbc()[mid] <= j)
             lo = mid + 1;
           else
             hi = mid;
@@ -457,13 +563,13 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
       }
     }
     if (lane == 0) {
-      job.ids[t] = bid;
-      job.scores[t] = bid == kSentinel ? -INFINITY : (float)bs;
+      gpw(job.ids)[t] = bid;
+      gpw(job.scores)[t] = bid == kSentinel ? -INFINITY : (float)bs;
     }
     if (bid == kSentinel) {
       for (int t2 = t + 1 + lane; t2 < job.k; t2 += 64) {
-        job.ids[t2] = kSentinel;
-        job.scores[t2] = -INFINITY;
+        gpw(job.ids)[t2] = kSentinel;
+        gpw(job.scores)[t2] = -INFINITY;
       }
       break;
     }
@@ -472,8 +578,8 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
     wave_sync();
   }
   if (job.counters && lane == 0) {
-    job.counters[0] = n_exp;
-    job.counters[1] = n_dist;
+    gpw(job.counters)[0] = n_exp;
+    gpw(job.counters)[1] = n_dist;
   }
   wave_sync();
 }
@@ -492,10 +598,9 @@ struct PlainArgs {
 
 template <int BITS, int G, int V>
 __global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
   const int64_t qi = blockIdx.x;
   if (qi >= a.m) return;
-  const Lds sm = carve(smem, a.L);
+  const Lds sm = carve(a.L);
   Job job;
   job.q = a.Q + qi * a.ix.D;
   job.qp = a.Qp + qi * a.ix.d;
@@ -511,14 +616,16 @@ __global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
 // step's queries run out.  Requests are sorted by q_begin; a query finds its
 // request by binary search.
 template <int BITS, int G, int V>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void persistent_kernel(
+#ifndef LV_PERSISTENT_WAVES_PER_EU
+#define LV_PERSISTENT_WAVES_PER_EU 5
+#endif
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LV_PERSISTENT_WAVES_PER_EU))) void persistent_kernel(
     const StepHeader *__restrict__ hdr,
                                                         const IndexView *__restrict__ subs,
                                                         unsigned int *__restrict__ counter,
                                                         int32_t Lmax, int32_t hash_log2) {
-  extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x;
-  const Lds sm = carve(smem, Lmax);
+  const Lds sm = carve(Lmax);
   const int64_t nq = hdr->nq;
   const int32_t nreq = hdr->nreq;
   const Request *req = reinterpret_cast<const Request *>(hdr + 1);
@@ -547,7 +654,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void pe
     job.ids = hdr->ids + r.out_off + j * r.k;
     job.scores = hdr->scores + r.out_off + j * r.k;
     job.counters = hdr->counters ? hdr->counters + 2 * (int64_t)u : nullptr;
-    search_query<BITS, G, V>(ix, job, sm, hash_log2, lane);
+    // An opaque copy of the lane id: lane-dependent constants of the search
+    // are then recomputed per query instead of being hoisted out of this
+    // loop, where they would stay live (and spill) for the kernel's lifetime.
+    int lane_q = lane;
+    asm volatile("" : "+v"(lane_q));
+    search_query<BITS, G, V>(ix, job, sm, hash_log2, lane_q);
   }
 }
 
