@@ -320,7 +320,8 @@ int lv_batch_destroy(lv_batch *batch);
 
 /*
  * Run one step on `stream`: validate and pack the requests on the host,
- * then launch the captured graph.  Asynchronous; the pinned table is
+ * then launch the two captured graphs (table copy + grouped projection,
+ * then counter reset + persistent traversal).  Asynchronous; the pinned table is
  * reused two steps later, after that step's completion.
  *   Q:        device float32 [sum count][D]
  *   ids:      device uint32 [sum count * k] out; scores: device float32, same
@@ -331,6 +332,17 @@ int lv_batch_destroy(lv_batch *batch);
  */
 int lv_batch_step(lv_batch *batch, const lv_request *reqs, int32_t nreq, const float *Q,
                   uint32_t *ids, float *scores, uint32_t *counters, void *stream);
+
+/*
+ * lv_batch_step, and record two caller-owned hipEvents (created with timing
+ * enabled) on `stream`: ev_begin after the table copy and query projection,
+ * ev_end after the persistent traversal, so that their elapsed time is the
+ * traversal kernel's own duration (counter reset included).
+ * Errors: those of lv_batch_step; LV_EINVAL if an event is NULL.
+ */
+int lv_batch_step_timed(lv_batch *batch, const lv_request *reqs, int32_t nreq, const float *Q,
+                        uint32_t *ids, float *scores, uint32_t *counters, void *ev_begin,
+                        void *ev_end, void *stream);
 
 /*
  * Autotuner, result-affecting part: the smallest window L in [k, L_max]

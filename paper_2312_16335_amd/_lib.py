@@ -88,6 +88,8 @@ _SIGS = {
                                  ctypes.POINTER(_vp)]),
     "lv_batch_destroy": (_c_i32, [_vp]),
     "lv_batch_step": (_c_i32, [_vp, ctypes.POINTER(Request), _c_i32, _vp, _vp, _vp, _vp, _vp]),
+    "lv_batch_step_timed": (_c_i32, [_vp, ctypes.POINTER(Request), _c_i32, _vp, _vp, _vp, _vp,
+                                     _vp, _vp, _vp]),
     "lv_autotune_window": (_c_i32, [_vp, _c_i32, _vp, _c_i64, _vp, _c_i32, _c_i32, _c_dbl,
                                     _c_i32, ctypes.POINTER(SearchParams),
                                     ctypes.POINTER(_c_i32), ctypes.POINTER(_c_dbl), _vp]),
@@ -381,14 +383,24 @@ class Batch:
                                       ctypes.byref(h)))
         self.handle = h
 
-    def step(self, reqs, Q, ids, scores, counters=None, stream=None):
-        """reqs: list of (sub, k, L, count); Q rows and outputs packed in request order."""
+    def step(self, reqs, Q, ids, scores, counters=None, stream=None, events=None):
+        """reqs: list of (sub, k, L, count); Q rows and outputs packed in request order.
+        events: optional pair of timing torch.cuda.Event recorded around the traversal
+        (lv_batch_step_timed)."""
         import torch
 
         arr = _requests(reqs)
-        _check(load().lv_batch_step(self.handle, arr, len(reqs), _dev(Q, torch.float32),
-                                    _dev(ids, torch.int32), _dev(scores, torch.float32),
-                                    _dev(counters, torch.int32), _stream(stream)))
+        args = (self.handle, arr, len(reqs), _dev(Q, torch.float32), _dev(ids, torch.int32),
+                _dev(scores, torch.float32), _dev(counters, torch.int32))
+        if events is None:
+            _check(load().lv_batch_step(*args, _stream(stream)))
+            return
+        raw = []
+        for ev in events:
+            if not ev.cuda_event:  # torch creates the event on its first record
+                ev.record(None if isinstance(stream, int) else stream)
+            raw.append(_vp(ev.cuda_event))
+        _check(load().lv_batch_step_timed(*args, raw[0], raw[1], _stream(stream)))
 
     def close(self):
         if self.handle:

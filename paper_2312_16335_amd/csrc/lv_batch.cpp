@@ -1,5 +1,10 @@
 // Batched search: several sub-indexes, uneven requests, one persistent
 // launch per step, captured as hipGraphs; plus the autotuner.
+//
+// A step is two graph launches on the caller's stream: pre[i] (copy of the
+// pinned request table i, grouped query projection) and trav (counter reset,
+// persistent traversal).  The split lets a caller bracket the traversal alone
+// with its own timing events.
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -25,8 +30,10 @@ struct lv_batch {
   unsigned int *d_counter = nullptr;
   float *d_qp = nullptr;
   hipStream_t capture = nullptr;
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipGraph_t pre_graph[2] = {nullptr, nullptr};
+  hipGraphExec_t pre_exec[2] = {nullptr, nullptr};
+  hipGraph_t trav_graph = nullptr;
+  hipGraphExec_t trav_exec = nullptr;
   hipEvent_t done[2] = {nullptr, nullptr};
   int next = 0;
 };
@@ -40,10 +47,12 @@ void free_batch(lv_batch *b) {
       (void)hipEventSynchronize(b->done[i]);
       (void)hipEventDestroy(b->done[i]);
     }
-    if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
-    if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+    if (b->pre_exec[i]) (void)hipGraphExecDestroy(b->pre_exec[i]);
+    if (b->pre_graph[i]) (void)hipGraphDestroy(b->pre_graph[i]);
     if (b->h_table[i]) (void)hipHostFree(b->h_table[i]);
   }
+  if (b->trav_exec) (void)hipGraphExecDestroy(b->trav_exec);
+  if (b->trav_graph) (void)hipGraphDestroy(b->trav_graph);
   if (b->capture) (void)hipStreamDestroy(b->capture);
   if (b->d_table) (void)hipFree(b->d_table);
   if (b->d_counter) (void)hipFree(b->d_counter);
@@ -152,27 +161,33 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
     LV_BATCH_TRY(hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming));
   }
   LV_BATCH_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+  const lv::StepHeader *hdr = reinterpret_cast<const lv::StepHeader *>(b->d_table);
   for (int i = 0; i < 2; ++i) {
     LV_BATCH_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed));
     hipError_t e1 = hipMemcpyAsync(b->d_table, b->h_table[i], b->table_bytes,
                                    hipMemcpyHostToDevice, b->capture);
-    const lv::StepHeader *hdr = reinterpret_cast<const lv::StepHeader *>(b->d_table);
     int r1 = e1 == hipSuccess
                  ? lv::launch_project_grouped(hdr, multi->d_views, b->max_tiles, multi->d,
                                               multi->D, b->capture)
                  : LV_EDEVICE;
-    int r2 = r1 == LV_OK ? lv::launch_persistent(multi->bits, multi->group, multi->vbytes, hdr,
-                                                 multi->d_views, b->d_counter, caps->max_L,
-                                                 log2h, b->grid, b->capture)
-                         : r1;
-    hipError_t e2 = hipStreamEndCapture(b->capture, &b->graph[i]);
-    if (e1 != hipSuccess || r2 != LV_OK || e2 != hipSuccess) {
-      if (r2 == LV_OK) lv::set_error("graph capture failed");
+    hipError_t e2 = hipStreamEndCapture(b->capture, &b->pre_graph[i]);
+    if (e1 != hipSuccess || r1 != LV_OK || e2 != hipSuccess) {
+      if (r1 == LV_OK) lv::set_error("graph capture failed");
       free_batch(b);
-      return r2 != LV_OK ? r2 : LV_EDEVICE;
+      return r1 != LV_OK ? r1 : LV_EDEVICE;
     }
-    LV_BATCH_TRY(hipGraphInstantiate(&b->exec[i], b->graph[i], nullptr, nullptr, 0));
+    LV_BATCH_TRY(hipGraphInstantiate(&b->pre_exec[i], b->pre_graph[i], nullptr, nullptr, 0));
   }
+  LV_BATCH_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed));
+  int r2 = lv::launch_persistent(multi->bits, multi->group, multi->vbytes, hdr, multi->d_views,
+                                 b->d_counter, caps->max_L, log2h, b->grid, b->capture);
+  hipError_t e3 = hipStreamEndCapture(b->capture, &b->trav_graph);
+  if (r2 != LV_OK || e3 != hipSuccess) {
+    if (r2 == LV_OK) lv::set_error("graph capture failed");
+    free_batch(b);
+    return r2 != LV_OK ? r2 : LV_EDEVICE;
+  }
+  LV_BATCH_TRY(hipGraphInstantiate(&b->trav_exec, b->trav_graph, nullptr, nullptr, 0));
   *out = b;
   return LV_OK;
 }
@@ -183,9 +198,11 @@ extern "C" int lv_batch_destroy(lv_batch *batch) {
   return LV_OK;
 }
 
-extern "C" int lv_batch_step(lv_batch *b, const lv_request *reqs, int32_t nreq, const float *Q,
-                             uint32_t *ids, float *scores, uint32_t *counters, void *stream) {
-  lv::clear_error();
+namespace {
+
+int batch_step(lv_batch *b, const lv_request *reqs, int32_t nreq, const float *Q, uint32_t *ids,
+               float *scores, uint32_t *counters, hipEvent_t ev_begin, hipEvent_t ev_end,
+               hipStream_t s) {
   if (!b) LV_FAIL(LV_EINVAL, "NULL batch");
   if (!reqs || nreq < 1 || nreq > b->caps.max_requests)
     LV_FAIL(LV_EINVAL, "nreq must be in [1, %d]", b->caps.max_requests);
@@ -236,11 +253,32 @@ extern "C" int lv_batch_step(lv_batch *b, const lv_request *reqs, int32_t nreq, 
     t0 += (reqs[r].count + 31) / 32;
   }
   (void)nout;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  LV_CHECK_HIP(hipGraphLaunch(b->exec[i], s));
+  LV_CHECK_HIP(hipGraphLaunch(b->pre_exec[i], s));
   LV_CHECK_HIP(hipEventRecord(b->done[i], s));
   b->next ^= 1;
+  if (ev_begin) LV_CHECK_HIP(hipEventRecord(ev_begin, s));
+  LV_CHECK_HIP(hipGraphLaunch(b->trav_exec, s));
+  if (ev_end) LV_CHECK_HIP(hipEventRecord(ev_end, s));
   return LV_OK;
+}
+
+}  // namespace
+
+extern "C" int lv_batch_step(lv_batch *b, const lv_request *reqs, int32_t nreq, const float *Q,
+                             uint32_t *ids, float *scores, uint32_t *counters, void *stream) {
+  lv::clear_error();
+  return batch_step(b, reqs, nreq, Q, ids, scores, counters, nullptr, nullptr,
+                    static_cast<hipStream_t>(stream));
+}
+
+extern "C" int lv_batch_step_timed(lv_batch *b, const lv_request *reqs, int32_t nreq,
+                                   const float *Q, uint32_t *ids, float *scores,
+                                   uint32_t *counters, void *ev_begin, void *ev_end,
+                                   void *stream) {
+  lv::clear_error();
+  if (!ev_begin || !ev_end) LV_FAIL(LV_EINVAL, "NULL timing event");
+  return batch_step(b, reqs, nreq, Q, ids, scores, counters, static_cast<hipEvent_t>(ev_begin),
+                    static_cast<hipEvent_t>(ev_end), static_cast<hipStream_t>(stream));
 }
 
 namespace {

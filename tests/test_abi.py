@@ -94,6 +94,18 @@ def test_encode_and_project_validation():
     assert lv.lv_record_stride(32, 8) == 64 and lv.lv_record_stride(3000, 8) == 0
 
 
+def test_batch_step_validation_without_a_device():
+    lib = lv.load()
+    one = (lv.Request * 1)(lv.Request(0, 10, 20, 5))
+    assert lib.lv_batch_step(None, one, 1, FAKE, FAKE, FAKE, None, None) == lv.LV_EINVAL
+    assert lib.lv_batch_step_timed(None, one, 1, FAKE, FAKE, FAKE, None, FAKE, FAKE,
+                                   None) == lv.LV_EINVAL
+    # a NULL timing event is refused before the batch is looked at
+    assert lib.lv_batch_step_timed(FAKE, one, 1, FAKE, FAKE, FAKE, None, None, FAKE,
+                                   None) == lv.LV_EINVAL
+    assert "event" in lib.lv_last_error().decode()
+
+
 def test_bf16_conversion_is_round_to_nearest_even():
     rng = np.random.default_rng(0)
     x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-5, 5, 10000),

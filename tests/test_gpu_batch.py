@@ -151,3 +151,30 @@ def test_autotune_knobs_returns_a_valid_choice(lv, subs):
     best, ms = lv.lv_autotune_knobs(multi, 4, 256, 64, reqs, Q, ids, sc, reps=2)
     assert best["hash_slots"] in (1024, 2048, 4096, 8192) and ms > 0
     multi.close()
+
+
+def test_timed_step_equals_untimed_and_brackets_the_traversal(lv, subs):
+    multi = lv.Multi([ix for _, ix in subs])
+    batch = lv.Batch(multi, max_requests=4, max_queries=512, max_L=100)
+    reqs = [(0, 10, 60, 200), (2, 10, 100, 150), (1, 1, 20, 100)]
+    Q = torch.from_numpy(np.concatenate([subs[0][0].Q[:200], subs[2][0].Q[:150],
+                                         subs[1][0].Q[:100]])).to(DEV)
+    nout = 200 * 10 + 150 * 10 + 100
+    outs = []
+    for timed in (False, True, True):
+        ids = torch.full((nout,), -7, dtype=torch.int32, device=DEV)
+        sc = torch.zeros((nout,), dtype=torch.float32, device=DEV)
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        batch.step(reqs, Q, ids, sc, events=ev if timed else None)
+        t1.record()
+        torch.cuda.synchronize()
+        if timed:
+            kernel_ms, step_ms = ev[0].elapsed_time(ev[1]), t0.elapsed_time(t1)
+            assert 0 < kernel_ms <= step_ms
+        outs.append((ids, sc))
+    for ids, sc in outs[1:]:
+        assert torch.equal(ids, outs[0][0]) and torch.equal(sc, outs[0][1])
+    batch.close()
+    multi.close()
