@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--target", type=float, default=0.90)
     ap.add_argument("--hash-slots", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1000)
+    ap.add_argument("--cpu-sample", type=int, default=10000)
     ap.add_argument("--only-steps", action="store_true",
                     help="skip the sweep refinement (profiling runs)")
     ap.add_argument("--L", type=int, default=0, help="fixed window (skips the sweep)")
@@ -350,20 +350,24 @@ def main():
         wall0 = time.perf_counter()
         t_start.record()
         for sidx in range(args.steps):
+            per[sidx][0].record(stream)
             if evs:
                 fn(evs[sidx])
             else:
-                per[sidx][0].record(stream)
                 fn()
-                per[sidx][1].record(stream)
+            per[sidx][1].record(stream)
         t_end.record()
         torch.cuda.synchronize()
         return t_start.elapsed_time(t_end), time.perf_counter() - wall0, per
 
+    def step_stats(per):
+        t = sorted(a_.elapsed_time(b_) for a_, b_ in per)
+        return {"best_ms": t[0], "median_ms": float(np.median(t)), "worst_ms": t[-1]}
+
     # plain: one projection + one traversal launch per request, events per kernel
     evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(nreq)] for _ in range(3)]
            for _ in range(args.steps)]
-    plain_ms, plain_wall, _ = timed(lambda e: step(L_star, e), evs)
+    plain_ms, plain_wall, plain_per = timed(lambda e: step(L_star, e), evs)
     got = ids.cpu().numpy().view(np.uint32).astype(np.int64)
     rec_plain = recall(got, truth, k)
     proj_ms = sum(evs[s_][0][i].elapsed_time(evs[s_][1][i]) for s_ in range(args.steps)
@@ -377,7 +381,7 @@ def main():
     ids.fill_(-1)
     trav = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in range(args.steps)]
-    total_ms, wall, _ = timed(step_batched, trav)
+    total_ms, wall, batched_per = timed(step_batched, trav)
     got = ids.cpu().numpy().view(np.uint32).astype(np.int64)
     rec_star = recall(got, truth, k)
     ms_per_step = total_ms / args.steps
@@ -390,10 +394,27 @@ def main():
     batch.close()
     multi.close()
 
+    # reference: the plain path as one launch pair over all queries
+    def single():
+        lv.lv_project(Qd, Pb, Qp)
+        lv.lv_search_projected(index, Qd, Qp, k, L_star, ids, scores, hash_slots=hs)
+
+    single()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        single()
+    e1.record()
+    torch.cuda.synchronize()
+    single_qps = m * 5 / (e0.elapsed_time(e1) / 1e3)
+
     # ---- CPU oracle on a bounded sample
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, X, Q, adj, entry, K, ssum, ns, L_star, args.cpu_sample)
+        cpu = cpu_baseline(wl, X, Xs, Q, adj, entry, L_star, args.cpu_sample, truth)
+        if cpu["sample"].startswith("all") and abs(cpu["recall"] - rec_star) > 0.005:
+            log(f"WARNING: GPU recall {rec_star:.4f} vs oracle {cpu['recall']:.4f}")
 
     out = {
         "metric": "QPS at 10-recall@10=0.90 (1M x 768, d=160), batched vs plain; HBM GB/s",
@@ -416,6 +437,9 @@ def main():
                   "traversal_kernel_GBs": achieved_plain,
                   "traversal_kernel_frac": achieved_plain / HBM_PEAK_GBS},
         "batched_over_plain": qps / plain_qps,
+        "batched_step_ms": step_stats(batched_per),
+        "plain_step_ms": step_stats(plain_per),
+        "plain_single_launch_qps": single_qps,
         "qps_interp_at_target": qps_interp,
         "sweep": {str(L): {"recall": r, "qps": q} for L, (r, q) in sorted(sweep.items())},
         "wall_s_timed": wall,
@@ -430,21 +454,25 @@ def main():
                      "alg_bytes_per_launch": alg_bytes_total, "launch_ms": kernel_ms,
                      "kernel": "persistent_kernel (traversal + re-rank), one launch per step, "
                                "HIP events around its graph on the launch stream"},
-        "index_build": {"db_projection_ms": db_proj_ms, "graph_build_s": g.get("graph_s")},
+        "index_build": {"db_projection_ms": db_proj_ms, "graph_build_s": g.get("graph_s"),
+                        "graph_build_threads": int(os.environ.get("OMP_NUM_THREADS") or
+                                                   os.cpu_count()),
+                        "graph_cached": g.get("graph_s") == 0.0},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 
 
-def cpu_baseline(wl, X, Q, adj, entry, K, ssum, ns, L, sample):
-    """The float64 oracle, timed on a bounded query sample over all host cores."""
+def cpu_baseline(wl, X, Xs, Q, adj, entry, L, sample, truth):
+    """The float64 oracle (its own projection and encoding), timed on a bounded query
+    sample over all host cores; also its recall on that sample."""
     from oracle import fit as ofit
     from oracle import lvq as olvq
     from oracle import search as osearch
 
     t = time.time()
-    P = ofit.fit_id(K, wl.d)
-    mu = (P @ (ssum / ns)).astype(np.float32)
+    P = ofit.fit_id(ofit.second_moment(Xs), wl.d)
+    mu = ofit.mean_reduced(Xs, P).astype(np.float32)
     Y = np.empty((wl.N, wl.d), dtype=np.float32)
     for lo in range(0, wl.N, 1 << 17):
         Y[lo:lo + (1 << 17)] = ofit.project(X[lo:lo + (1 << 17)], P)
@@ -455,8 +483,9 @@ def cpu_baseline(wl, X, Q, adj, entry, K, ssum, ns, L, sample):
     procs = max(1, min(16, len(os.sched_getaffinity(0))))
     n = min(sample, len(Q))
     t = time.perf_counter()
-    osearch.search_many(index, Q[:n], Qp[:n], wl.k, L, procs=procs, chunk=16)
+    got, _, _ = osearch.search_many(index, Q[:n], Qp[:n], wl.k, L, procs=procs, chunk=16)
     dt = time.perf_counter() - t
+    rec = recall(np.asarray(got).astype(np.int64), truth[:n], wl.k)
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -466,10 +495,12 @@ def cpu_baseline(wl, X, Q, adj, entry, K, ssum, ns, L, sample):
     except OSError:
         pass
     log(f"oracle: {n} queries in {dt:.1f}s on {procs} processes")
+    which = f"all {n}" if n == len(Q) else f"first {n} of {len(Q)}"
     return {"value": n / dt, "unit": "queries/s", "cores": procs, "kind": "oracle",
-            "sample": f"first {n} of {len(Q)} test queries, window L={L}, float64 numpy "
-                      f"oracle, one process per core (includes process start-up)",
-            "cpu_model": model}
+            "sample": f"{which} test queries, window L={L}, float64 numpy oracle with its own "
+                      f"projection and encoding, one process per core (process start-up "
+                      f"included)",
+            "recall": rec, "cpu_model": model}
 
 
 if __name__ == "__main__":

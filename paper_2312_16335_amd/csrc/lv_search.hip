@@ -3,8 +3,11 @@
 // Per query (Section 2 "Search"; traversal of Appendix C read as a
 // best-first beam with window L):
 //   * the candidate window (L entries of float64 score + id, kept sorted by
-//     score descending then id ascending) lives in LDS, double-buffered so a
-//     batch of new candidates merges in one parallel pass;
+//     score descending then id ascending) lives in LDS as one buffer that a
+//     batch of new candidates is merged into in place: an entry only moves
+//     towards the end, by a shift that does not decrease along the window,
+//     so 64-entry chunks taken from the end, each read before it is written,
+//     never overwrite an entry not yet read;
 //   * the visited set is an LDS open-addressed hash of node ids.  It may
 //     forget (bounded probing): a forgotten node is scored again, and the
 //     merge drops it if it is already in the window.  A node that left the
@@ -60,18 +63,16 @@ struct Job {
 // otherwise fall back to flat addressing).
 extern __shared__ __align__(16) unsigned char lv_smem[];
 
+// Layout: window scores [Lmax] f64, batch scores [64] f64, window ids
+// [Lmax] u32, batch ids [64] u32, merge positions [64] i32, visited hash.
 struct Lds {
   int Lmax;
-  __device__ __forceinline__ double *ls(int b) const {
-    return reinterpret_cast<double *>(lv_smem) + b * Lmax;
+  __device__ __forceinline__ double *ls() const { return reinterpret_cast<double *>(lv_smem); }
+  __device__ __forceinline__ double *cs() const { return ls() + Lmax; }
+  __device__ __forceinline__ uint32_t *lid() const {
+    return reinterpret_cast<uint32_t *>(cs() + 64);
   }
-  __device__ __forceinline__ double *cs() const {
-    return reinterpret_cast<double *>(lv_smem) + 2 * Lmax;
-  }
-  __device__ __forceinline__ uint32_t *lid(int b) const {
-    return reinterpret_cast<uint32_t *>(cs() + 64) + b * Lmax;
-  }
-  __device__ __forceinline__ uint32_t *cid() const { return lid(0) + 2 * Lmax; }
+  __device__ __forceinline__ uint32_t *cid() const { return lid() + Lmax; }
   __device__ __forceinline__ int32_t *lbc() const {
     return reinterpret_cast<int32_t *>(cid() + 64);
   }
@@ -320,11 +321,14 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
   double sq = 0.0, cq = 0.0;
 #pragma unroll
   for (int t = 0; t < NQ; ++t) {
+    // unconditional loads (clamped index) so that all of them are in flight
     const int j = gl * NQ + t;
-    const float x = j < ix.d ? gp(job.qp)[j] : 0.f;
-    qv[t] = x;
-    sq += (double)x;
-    if (j < ix.d) cq = fma((double)x, (double)gp(ix.mu)[j], cq);
+    const bool in = j < ix.d;
+    const float x = gp(job.qp)[in ? j : 0];
+    const float mj = gp(ix.mu)[in ? j : 0];
+    qv[t] = in ? x : 0.f;
+    sq += (double)qv[t];
+    cq = fma((double)qv[t], (double)mj, cq);
   }
   // the same in every lane after the group reduction: keep them scalar
   sq = lane_f64(group_sum<G>(sq), 0);
@@ -341,20 +345,19 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
   score_batch<BITS, G, V>(ix, qv, sq, cq, sm.cid(), sm.cs(), 1, lane);
   wave_sync();
   if (lane == 0) {
-    sm.ls(0)[0] = sm.cs()[0];
-    sm.lid(0)[0] = ix.entry;
+    sm.ls()[0] = sm.cs()[0];
+    sm.lid()[0] = ix.entry;
   }
   wave_sync();
   int nl = 1;
-  int cur = 0;
   uint32_t n_exp = 0, n_dist = 1;
   uint32_t pf_id = kSentinel;   // node whose first adjacency chunk is in pf_row
   uint32_t pf_row = kSentinel;
   const uint32_t max_hops = ix.N + 1u;  // every node is expanded at most once
 
   for (uint32_t hop = 0; hop < max_hops; ++hop) {
-    double *ls = sm.ls(cur);
-    uint32_t *lid = sm.lid(cur);
+    const double *ls = sm.ls();
+    uint32_t *lid = sm.lid();
     // best unexpanded entry = first unexpanded position of the sorted window;
     // the next one is the runner-up whose row is prefetched
     int pos = -1, pos2 = -1;
@@ -405,8 +408,6 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
       n_dist += nc;
 
       // merge the scored batch into the window
-      ls = sm.ls(cur);
-      lid = sm.lid(cur);
       double bs = -INFINITY;
       uint32_t bid = kSentinel;
       if (lane < nc) {
@@ -466,22 +467,21 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
           }
         }
         if (nkeep == 0) continue;
-        double *ls_n = sm.ls(cur ^ 1);
-        uint32_t *lid_n = sm.lid(cur ^ 1);
+        // in place: the whole window was read into registers above
+        double *ls_w = sm.ls();
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int e = lane + 64 * t;
           if (e < nl && e + sh[t] < L) {
-            ls_n[e + sh[t]] = es[t];
-            lid_n[e + sh[t]] = er[t];
+            ls_w[e + sh[t]] = es[t];
+            lid[e + sh[t]] = er[t];
           }
         }
         if (my_keep && my_lb + my_rank < L) {
-          ls_n[my_lb + my_rank] = bs;
-          lid_n[my_lb + my_rank] = bid;
+          ls_w[my_lb + my_rank] = bs;
+          lid[my_lb + my_rank] = bid;
         }
         nl = nl + nkeep < L ? nl + nkeep : L;
-        cur ^= 1;
         wave_sync();
         continue;
       }
@@ -506,42 +506,48 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
       const int r = lane_rank(vm);
       if (valid) sm.lbc()[r] = lb;
       wave_sync();
-      double *ls_n = sm.ls(cur ^ 1);
-      uint32_t *lid_n = sm.lid(cur ^ 1);
-      for (int j = lane; j < nl; j += 64) {
-        int lo = 0, hi = nv;  // new entries placed before window entry j
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (sm.lbc()[mid] <= j)
-            lo = mid + 1;
-          else
-            hi = mid;
-        }
-        const int np = j + lo;
-        if (np < L) {
-          ls_n[np] = ls[j];
-          lid_n[np] = lid[j];
+      // in place, 64-entry chunks from the end: entry e moves to e + (number
+      // of new entries placed before it), never onto an entry not yet read
+      double *ls_w = sm.ls();
+      for (int c = (nl - 1) >> 6; c >= 0; --c) {
+        const int e = 64 * c + lane;
+        if (e < nl) {
+          const double se = ls[e];
+          const uint32_t ie = lid[e];
+          int lo = 0, hi = nv;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sm.lbc()[mid] <= e)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          const int np = e + lo;
+          if (np < L) {
+            ls_w[np] = se;
+            lid[np] = ie;
+          }
         }
       }
       if (valid && lb + r < L) {
-        ls_n[lb + r] = bs;
-        lid_n[lb + r] = bid;
+        ls_w[lb + r] = bs;
+        lid[lb + r] = bid;
       }
       nl = nl + nv < L ? nl + nv : L;
-      cur ^= 1;
       wave_sync();
     }
   }
 
-  // re-rank the window with the secondary vectors
-  const uint32_t *lid = sm.lid(cur);
-  double *s2 = sm.ls(cur ^ 1);
-  uint32_t *id2 = sm.lid(cur ^ 1);
+  // re-rank the window with the secondary vectors, in place: the secondary
+  // score of entry j replaces its primary score, its id loses the flag
+  uint32_t *id2 = sm.lid();
+  double *s2 = sm.ls();
   if (ix.sec_f16)
-    rerank_rows<true>(ix, job.q, lid, s2, nl, lane);
+    rerank_rows<true>(ix, job.q, id2, s2, nl, lane);
   else
-    rerank_rows<false>(ix, job.q, lid, s2, nl, lane);
-  for (int j = lane; j < nl; j += 64) id2[j] = lid[j] & kIdMask;
+    rerank_rows<false>(ix, job.q, id2, s2, nl, lane);
+  wave_sync();
+  for (int j = lane; j < nl; j += 64) id2[j] &= kIdMask;
   wave_sync();
   for (int t = 0; t < job.k; ++t) {
     double bs = -INFINITY;
@@ -615,15 +621,17 @@ __global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
 // Persistent form: wavefronts take queries from a device counter until the
 // step's queries run out.  Requests are sorted by q_begin; a query finds its
 // request by binary search.
+// Waves per SIMD the register allocation aims at: 5 (at most 102 VGPRs)
+// for 8-bit records, 4 for 4-bit records, whose lanes hold twice as many
+// projected-query components.
+template <int BITS, int V>
+constexpr int persistent_waves() { return BITS == 8 ? 5 : 4; }
+
 template <int BITS, int G, int V>
-#ifndef LV_PERSISTENT_WAVES_PER_EU
-#define LV_PERSISTENT_WAVES_PER_EU 5
-#endif
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LV_PERSISTENT_WAVES_PER_EU))) void persistent_kernel(
-    const StepHeader *__restrict__ hdr,
-                                                        const IndexView *__restrict__ subs,
-                                                        unsigned int *__restrict__ counter,
-                                                        int32_t Lmax, int32_t hash_log2) {
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(persistent_waves<BITS, V>()))) void persistent_kernel(
+    const StepHeader *__restrict__ hdr, const IndexView *__restrict__ subs,
+    unsigned int *__restrict__ counter, int32_t Lmax, int32_t hash_log2) {
   const int lane = threadIdx.x;
   const Lds sm = carve(Lmax);
   const int64_t nq = hdr->nq;
@@ -767,7 +775,7 @@ int hash_log2_for(const lv_search_params *params, int *log2h) {
 }
 
 size_t beam_lds_bytes(int L, int log2h) {
-  return (size_t)L * 24 + 64 * 16 + ((size_t)4 << log2h);
+  return (size_t)L * 12 + 64 * 16 + ((size_t)4 << log2h);
 }
 
 int check_lds(size_t lds, int L, int log2h) {

@@ -1,0 +1,187 @@
+"""GPU parity at the full benchmark size: 1M x 768 database, d = 160, LVQ-8
+records, float16 secondaries, R = 64, 10,000 queries, window L = 143, in the
+launch configuration the benchmark times (one captured batched step over a
+stream of uneven requests, 1024 visited-set slots).
+
+The oracle fits on a 100k uniform subsample (Section 2.2) and projects in
+float64; the GPU receives the oracle's reduced vectors rounded to float32.
+Checks:
+  * sampled LVQ records and float16 secondaries are bit-exact;
+  * the batched step equals the plain search (GPU projection) query by query;
+  * on sampled queries, the plain search over the oracle's projected queries
+    returns the oracle's ids, scores within float32 rounding, and the oracle's
+    expansion count;
+  * on all 10,000 queries: ids are valid and distinct, each score equals the
+    float64 secondary inner product of its id, and lists are sorted by
+    descending score.
+"""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_common import graph_cached
+from oracle import exact
+from oracle import fit as ofit
+from oracle import lvq as olvq
+from oracle import search as osearch
+from synth import gen
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+L_OP = 143        # window reaching 10-recall@10 = 0.90 on this workload
+HASH_SLOTS = 1024  # visited-set size the benchmark's autotuner picks
+N_SAMPLE = 48
+
+
+def log(msg):
+    print(f"[fullsize {time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def lv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2312_16335_amd as lv
+
+    lv.load()
+    return lv
+
+
+@pytest.fixture(scope="module")
+def full(lv):
+    wl = gen.WORKLOADS["id-1m-768"]
+    mix = gen.mixture(wl)
+    X = gen.database(wl, mix)
+    Q = gen.queries(wl, "test", mix=mix)
+    log(f"data {X.shape}, queries {Q.shape}")
+    rng = np.random.default_rng(7)
+    sub = np.sort(rng.choice(wl.N, size=100_000, replace=False))
+    P = ofit.fit_id(ofit.second_moment(X[sub]), wl.d)
+    mu = ofit.mean_reduced(X[sub], P).astype(np.float32)
+    Y = np.empty((wl.N, wl.d), np.float32)
+    for lo in range(0, wl.N, 1 << 16):
+        Y[lo:lo + (1 << 16)] = ofit.project(X[lo:lo + (1 << 16)], P)
+    Qp = ofit.project(Q, P).astype(np.float32)
+    log("oracle fit and projection done")
+    adj, entry = graph_cached(wl, X)
+    log("graph ready")
+    codes, delta, lo_ = olvq.encode(Y, mu, wl.bits)
+    sec = X.astype(np.float16)
+    oix = osearch.Index(adj, entry, codes, delta, lo_, mu, sec)
+    log("oracle index ready")
+
+    Xd = torch.from_numpy(X).to(DEV)
+    Yd = torch.from_numpy(Y).to(DEV)
+    mud = torch.from_numpy(mu).to(DEV)
+    stride = lv.lv_record_stride(wl.d, wl.bits)
+    rec = torch.empty((wl.N, stride), dtype=torch.uint8, device=DEV)
+    lv.lv_lvq_encode(Yd, mud, wl.bits, rec)
+    secd = torch.empty((wl.N, wl.D), dtype=torch.float16, device=DEV)
+    lv.lv_to_f16(Xd, secd)
+    del Yd, Xd
+    adjd = torch.from_numpy(adj.view(np.int32)).to(DEV)
+    Pb = torch.from_numpy(lv.lv_to_bf16(P).view(np.int16)).to(DEV)
+    index = lv.Index(rec, mud, secd, adjd, entry, wl.bits, wl.d, A_bf16=Pb)
+    torch.cuda.synchronize()
+    log("GPU index ready")
+    yield dict(wl=wl, X=X, Q=Q, Qp=Qp, mu=mu, codes=codes, delta=delta, lo=lo_, sec=sec,
+               oix=oix, rec=rec, secd=secd, index=index, stride=stride)
+    index.close()
+
+
+def request_sizes(m):
+    """The benchmark's stream: batch sizes uniform in [1, 4096] until m queries."""
+    rs = np.random.Generator(np.random.PCG64(401))
+    sizes, left = [], m
+    while left > 0:
+        b = int(min(left, rs.integers(1, 4097)))
+        sizes.append(b)
+        left -= b
+    return sizes
+
+
+def test_sampled_records_and_secondaries_bit_exact(lv, full):
+    wl = full["wl"]
+    rng = np.random.default_rng(21)
+    rows = np.unique(np.concatenate([[0, wl.N - 1], rng.choice(wl.N, 4096, replace=False)]))
+    got = full["rec"][torch.from_numpy(rows).to(DEV)].cpu().numpy()
+    want = olvq.pack_records(full["codes"][rows], full["delta"][rows], full["lo"][rows], wl.bits,
+                             full["stride"])
+    assert np.array_equal(got, want)
+    gs = full["secd"][torch.from_numpy(rows).to(DEV)].cpu().numpy()
+    assert np.array_equal(gs.view(np.uint16), full["sec"][rows].view(np.uint16))
+
+
+def test_batched_step_equals_plain_and_oracle(lv, full):
+    wl, Q, index = full["wl"], full["Q"], full["index"]
+    m, k = len(Q), wl.k
+    Qd = torch.from_numpy(Q).to(DEV)
+    sizes = request_sizes(m)
+    reqs = [(0, k, L_OP, b) for b in sizes]
+
+    # the benchmark's launch: one captured step over the whole stream
+    multi = lv.Multi([index])
+    batch = lv.Batch(multi, max_requests=len(reqs), max_queries=m, max_L=L_OP,
+                     hash_slots=HASH_SLOTS)
+    ids_b = torch.full((m * k,), -7, dtype=torch.int32, device=DEV)
+    sc_b = torch.zeros((m * k,), dtype=torch.float32, device=DEV)
+    for _ in range(2):  # two consecutive steps (alternating request tables)
+        batch.step(reqs, Qd, ids_b, sc_b)
+    torch.cuda.synchronize()
+    log(f"batched step over {len(reqs)} requests done")
+
+    # plain search per request with the same (GPU) query projection
+    ids_p = torch.empty((m, k), dtype=torch.int32, device=DEV)
+    sc_p = torch.empty((m, k), dtype=torch.float32, device=DEV)
+    ws = torch.empty(lv.lv_search_workspace_size(index, max(sizes)), dtype=torch.uint8,
+                     device=DEV)
+    q0 = 0
+    for b in sizes:
+        lv.lv_search(index, Qd[q0:q0 + b], k, L_OP, ids_p[q0:q0 + b], sc_p[q0:q0 + b], None,
+                     ws=ws, hash_slots=HASH_SLOTS)
+        q0 += b
+    torch.cuda.synchronize()
+    assert torch.equal(ids_b.view(m, k), ids_p)
+    assert torch.equal(sc_b.view(m, k), sc_p)
+    batch.close()
+    multi.close()
+
+    # properties on every query
+    ids = ids_b.view(m, k).cpu().numpy().view(np.uint32).astype(np.int64)
+    sc = sc_b.view(m, k).cpu().numpy()
+    assert (ids < wl.N).all()
+    assert all(len(set(r)) == k for r in ids)
+    s64 = np.einsum("mkd,md->mk", full["sec"][ids].astype(np.float64), Q.astype(np.float64))
+    assert np.allclose(sc, s64, rtol=0, atol=2e-7)
+    # the order is taken in float64 (distinct float64 scores may round to one float32)
+    assert (sc[:, :-1] >= sc[:, 1:]).all()
+    assert (s64[:, :-1] >= s64[:, 1:] - 1e-12).all()
+
+    # the plain search over the oracle's projected queries against the oracle
+    Qpd = torch.from_numpy(full["Qp"]).to(DEV)
+    ids_o = torch.empty((m, k), dtype=torch.int32, device=DEV)
+    sc_o = torch.empty((m, k), dtype=torch.float32, device=DEV)
+    cnt = torch.zeros((m, 2), dtype=torch.int32, device=DEV)
+    lv.lv_search_projected(index, Qd, Qpd, k, L_OP, ids_o, sc_o, cnt, hash_slots=HASH_SLOTS)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(22)
+    sample = np.sort(rng.choice(m, N_SAMPLE, replace=False))
+    got_i = ids_o.cpu().numpy().view(np.uint32).astype(np.int64)
+    got_s = sc_o.cpu().numpy()
+    got_c = cnt.cpu().numpy()
+    hits_gpu = hits_orc = 0
+    truth = exact.ground_truth(Q[sample], full["X"], k)
+    for n, qi in enumerate(sample):
+        tr = osearch.Trace()
+        oi, os_ = osearch.search_one(full["oix"], Q[qi], full["Qp"][qi], k, L_OP, trace=tr)
+        assert np.array_equal(got_i[qi], oi), qi
+        assert np.allclose(got_s[qi], os_, rtol=0, atol=2e-7), qi
+        assert got_c[qi, 0] == tr.n_exp, qi
+        assert got_c[qi, 1] >= tr.n_dist, qi  # re-scorings after the set forgot an id
+        hits_gpu += len(set(got_i[qi]) & set(truth[n]))
+        hits_orc += len(set(oi) & set(truth[n]))
+    log(f"sampled recall GPU {hits_gpu / (N_SAMPLE * k):.3f} oracle {hits_orc / (N_SAMPLE * k):.3f}")
+    assert hits_gpu == hits_orc
