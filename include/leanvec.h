@@ -321,8 +321,12 @@ int lv_batch_destroy(lv_batch *batch);
 /*
  * Run one step on `stream`: validate and pack the requests on the host,
  * then launch the two captured graphs (table copy + grouped projection,
- * then counter reset + persistent traversal).  Asynchronous; the pinned table is
- * reused two steps later, after that step's completion.
+ * then counter reset + persistent traversal).  Asynchronous.  Steps use two
+ * alternating sets of pinned table and device state; a set is reused two
+ * steps later, once the step that used it has finished (the host waits for
+ * its table copy, `stream` waits for its traversal).  Two consecutive steps
+ * issued on different streams therefore run concurrently; their output
+ * buffers must then be distinct.
  *   Q:        device float32 [sum count][D]
  *   ids:      device uint32 [sum count * k] out; scores: device float32, same
  *   counters: device uint32 [sum count][2] out (expansions, scorings) or NULL

@@ -2,9 +2,16 @@
 // launch per step, captured as hipGraphs; plus the autotuner.
 //
 // A step is two graph launches on the caller's stream: pre[i] (copy of the
-// pinned request table i, grouped query projection) and trav (counter reset,
-// persistent traversal).  The split lets a caller bracket the traversal alone
-// with its own timing events.
+// pinned request table i, grouped query projection) and trav[i] (counter
+// reset, persistent traversal).  The split lets a caller bracket the
+// traversal alone with its own timing events.
+//
+// Steps alternate between two sets of device state (request table, work
+// counter, projected queries), so two consecutive steps may run at once when
+// the caller issues them on different streams: the next step's wavefronts
+// then fill the compute units that the slowest queries of the previous step
+// leave idle.  A set is reused two steps later, after the step that last used
+// it has finished (its stream is made to wait for that).
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -25,16 +32,19 @@ struct lv_batch {
   int grid = 0;
   int max_tiles = 0;
   size_t table_bytes = 0;
-  unsigned char *d_table = nullptr;  // StepHeader + Request[max_requests]
-  unsigned char *h_table[2] = {nullptr, nullptr};
-  unsigned int *d_counter = nullptr;
-  float *d_qp = nullptr;
-  hipStream_t capture = nullptr;
+  // per step parity
+  unsigned char *d_table[2] = {nullptr, nullptr};  // StepHeader + Request[max_requests]
+  unsigned char *h_table[2] = {nullptr, nullptr};  // pinned
+  unsigned int *d_counter[2] = {nullptr, nullptr};
+  float *d_qp[2] = {nullptr, nullptr};
   hipGraph_t pre_graph[2] = {nullptr, nullptr};
   hipGraphExec_t pre_exec[2] = {nullptr, nullptr};
-  hipGraph_t trav_graph = nullptr;
-  hipGraphExec_t trav_exec = nullptr;
-  hipEvent_t done[2] = {nullptr, nullptr};
+  hipGraph_t trav_graph[2] = {nullptr, nullptr};
+  hipGraphExec_t trav_exec[2] = {nullptr, nullptr};
+  hipEvent_t copied[2] = {nullptr, nullptr};  // pinned table i consumed
+  hipEvent_t done[2] = {nullptr, nullptr};    // step on set i finished
+  bool used[2] = {false, false};
+  hipStream_t capture = nullptr;
   int next = 0;
 };
 
@@ -47,16 +57,20 @@ void free_batch(lv_batch *b) {
       (void)hipEventSynchronize(b->done[i]);
       (void)hipEventDestroy(b->done[i]);
     }
+    if (b->copied[i]) {
+      (void)hipEventSynchronize(b->copied[i]);
+      (void)hipEventDestroy(b->copied[i]);
+    }
     if (b->pre_exec[i]) (void)hipGraphExecDestroy(b->pre_exec[i]);
     if (b->pre_graph[i]) (void)hipGraphDestroy(b->pre_graph[i]);
+    if (b->trav_exec[i]) (void)hipGraphExecDestroy(b->trav_exec[i]);
+    if (b->trav_graph[i]) (void)hipGraphDestroy(b->trav_graph[i]);
     if (b->h_table[i]) (void)hipHostFree(b->h_table[i]);
+    if (b->d_table[i]) (void)hipFree(b->d_table[i]);
+    if (b->d_counter[i]) (void)hipFree(b->d_counter[i]);
+    if (b->d_qp[i]) (void)hipFree(b->d_qp[i]);
   }
-  if (b->trav_exec) (void)hipGraphExecDestroy(b->trav_exec);
-  if (b->trav_graph) (void)hipGraphDestroy(b->trav_graph);
   if (b->capture) (void)hipStreamDestroy(b->capture);
-  if (b->d_table) (void)hipFree(b->d_table);
-  if (b->d_counter) (void)hipFree(b->d_counter);
-  if (b->d_qp) (void)hipFree(b->d_qp);
   delete b;
 }
 
@@ -151,20 +165,21 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
   b->grid = blocks * cus;
   b->max_tiles = (int)((caps->max_queries + 31) / 32) + caps->max_requests;
   b->table_bytes = sizeof(lv::StepHeader) + sizeof(lv::Request) * (size_t)caps->max_requests;
-  LV_BATCH_TRY(hipMalloc(&b->d_table, b->table_bytes));
-  LV_BATCH_TRY(hipMalloc(&b->d_counter, sizeof(unsigned int)));
-  LV_BATCH_TRY(hipMalloc(&b->d_qp, sizeof(float) * (size_t)caps->max_queries * multi->d));
   for (int i = 0; i < 2; ++i) {
+    LV_BATCH_TRY(hipMalloc(&b->d_table[i], b->table_bytes));
+    LV_BATCH_TRY(hipMalloc(&b->d_counter[i], sizeof(unsigned int)));
+    LV_BATCH_TRY(hipMalloc(&b->d_qp[i], sizeof(float) * (size_t)caps->max_queries * multi->d));
     LV_BATCH_TRY(hipHostMalloc(reinterpret_cast<void **>(&b->h_table[i]), b->table_bytes,
                                hipHostMallocDefault));
     std::fill(b->h_table[i], b->h_table[i] + b->table_bytes, (unsigned char)0);
+    LV_BATCH_TRY(hipEventCreateWithFlags(&b->copied[i], hipEventDisableTiming));
     LV_BATCH_TRY(hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming));
   }
   LV_BATCH_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
-  const lv::StepHeader *hdr = reinterpret_cast<const lv::StepHeader *>(b->d_table);
   for (int i = 0; i < 2; ++i) {
+    const lv::StepHeader *hdr = reinterpret_cast<const lv::StepHeader *>(b->d_table[i]);
     LV_BATCH_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed));
-    hipError_t e1 = hipMemcpyAsync(b->d_table, b->h_table[i], b->table_bytes,
+    hipError_t e1 = hipMemcpyAsync(b->d_table[i], b->h_table[i], b->table_bytes,
                                    hipMemcpyHostToDevice, b->capture);
     int r1 = e1 == hipSuccess
                  ? lv::launch_project_grouped(hdr, multi->d_views, b->max_tiles, multi->d,
@@ -177,17 +192,17 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
       return r1 != LV_OK ? r1 : LV_EDEVICE;
     }
     LV_BATCH_TRY(hipGraphInstantiate(&b->pre_exec[i], b->pre_graph[i], nullptr, nullptr, 0));
+    LV_BATCH_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed));
+    int r2 = lv::launch_persistent(multi->bits, multi->group, multi->vbytes, hdr, multi->d_views,
+                                   b->d_counter[i], caps->max_L, log2h, b->grid, b->capture);
+    hipError_t e3 = hipStreamEndCapture(b->capture, &b->trav_graph[i]);
+    if (r2 != LV_OK || e3 != hipSuccess) {
+      if (r2 == LV_OK) lv::set_error("graph capture failed");
+      free_batch(b);
+      return r2 != LV_OK ? r2 : LV_EDEVICE;
+    }
+    LV_BATCH_TRY(hipGraphInstantiate(&b->trav_exec[i], b->trav_graph[i], nullptr, nullptr, 0));
   }
-  LV_BATCH_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed));
-  int r2 = lv::launch_persistent(multi->bits, multi->group, multi->vbytes, hdr, multi->d_views,
-                                 b->d_counter, caps->max_L, log2h, b->grid, b->capture);
-  hipError_t e3 = hipStreamEndCapture(b->capture, &b->trav_graph);
-  if (r2 != LV_OK || e3 != hipSuccess) {
-    if (r2 == LV_OK) lv::set_error("graph capture failed");
-    free_batch(b);
-    return r2 != LV_OK ? r2 : LV_EDEVICE;
-  }
-  LV_BATCH_TRY(hipGraphInstantiate(&b->trav_exec, b->trav_graph, nullptr, nullptr, 0));
   *out = b;
   return LV_OK;
 }
@@ -225,12 +240,13 @@ int batch_step(lv_batch *b, const lv_request *reqs, int32_t nreq, const float *Q
     tiles += (r.count + 31) / 32;
   }
   const int i = b->next;
-  // the table copy of the step that last used this buffer must be done
-  LV_CHECK_HIP(hipEventSynchronize(b->done[i]));
+  // the pinned table is rewritten once the copy of the step that last used
+  // it has been done
+  LV_CHECK_HIP(hipEventSynchronize(b->copied[i]));
   lv::StepHeader *hdr = reinterpret_cast<lv::StepHeader *>(b->h_table[i]);
   lv::Request *rq = reinterpret_cast<lv::Request *>(hdr + 1);
   hdr->Q = Q;
-  hdr->Qp = b->d_qp;
+  hdr->Qp = b->d_qp[i];
   hdr->ids = ids;
   hdr->scores = scores;
   hdr->counters = counters;
@@ -253,12 +269,17 @@ int batch_step(lv_batch *b, const lv_request *reqs, int32_t nreq, const float *Q
     t0 += (reqs[r].count + 31) / 32;
   }
   (void)nout;
+  // device set i is free once the step that last used it has finished, on
+  // whatever stream that step ran
+  if (b->used[i]) LV_CHECK_HIP(hipStreamWaitEvent(s, b->done[i], 0));
   LV_CHECK_HIP(hipGraphLaunch(b->pre_exec[i], s));
-  LV_CHECK_HIP(hipEventRecord(b->done[i], s));
-  b->next ^= 1;
+  LV_CHECK_HIP(hipEventRecord(b->copied[i], s));
   if (ev_begin) LV_CHECK_HIP(hipEventRecord(ev_begin, s));
-  LV_CHECK_HIP(hipGraphLaunch(b->trav_exec, s));
+  LV_CHECK_HIP(hipGraphLaunch(b->trav_exec[i], s));
   if (ev_end) LV_CHECK_HIP(hipEventRecord(ev_end, s));
+  LV_CHECK_HIP(hipEventRecord(b->done[i], s));
+  b->used[i] = true;
+  b->next ^= 1;
   return LV_OK;
 }
 

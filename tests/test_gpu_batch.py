@@ -178,3 +178,43 @@ def test_timed_step_equals_untimed_and_brackets_the_traversal(lv, subs):
         assert torch.equal(ids, outs[0][0]) and torch.equal(sc, outs[0][1])
     batch.close()
     multi.close()
+
+
+def test_consecutive_steps_on_two_streams(lv, subs):
+    """Steps issued alternately on two streams run concurrently on alternating
+    device state; every step still equals the plain search."""
+    multi = lv.Multi([ix for _, ix in subs])
+    batch = lv.Batch(multi, max_requests=4, max_queries=600, max_L=128)
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    cursor = [0, 0, 0]
+    plan = [
+        [(0, 10, 60, 150), (2, 10, 100, 200)],
+        [(1, 10, 40, 250), (0, 1, 10, 40)],
+        [(2, 100, 128, 90), (1, 10, 80, 160)],
+        [(0, 10, 50, 60), (2, 5, 20, 300), (1, 10, 30, 7)],
+        [(1, 10, 64, 120)],
+    ]
+    runs = []
+    streams[1].wait_stream(streams[0])
+    for i, reqs in enumerate(plan):
+        Qs = []
+        for sub, k, L, count in reqs:
+            pool = subs[sub][0].Q
+            Qs.append(pool[(cursor[sub] + np.arange(count)) % len(pool)])
+            cursor[sub] += count
+        Q = torch.from_numpy(np.concatenate(Qs)).to(DEV)
+        nout = sum(k * c for _, k, _, c in reqs)
+        ids = torch.full((nout,), -7, dtype=torch.int32, device=DEV)
+        sc = torch.zeros((nout,), dtype=torch.float32, device=DEV)
+        cnt = torch.zeros((len(Q), 2), dtype=torch.int32, device=DEV)
+        st = streams[i % 2]
+        if i % 2:
+            st.wait_stream(streams[0])  # inputs were made on stream 0
+        batch.step(reqs, Q, ids, sc, cnt, stream=st)
+        runs.append((reqs, Q, ids, sc, cnt))
+    streams[0].wait_stream(streams[1])
+    torch.cuda.synchronize()
+    for reqs, Q, ids, sc, cnt in runs:
+        check_against_plain(lv, subs, reqs, Q, ids, sc, cnt)
+    batch.close()
+    multi.close()
