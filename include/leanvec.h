@@ -231,10 +231,16 @@ typedef struct lv_index lv_index;
 int lv_index_create(const lv_index_desc *desc, lv_index **out);
 int lv_index_destroy(lv_index *index);
 
-/* Performance knobs.  They never change results. */
+/*
+ * Performance knobs.  They never change results.  The per-query visited set
+ * lives in LDS and may forget an id (a forgotten node met again is scored
+ * again and dropped if it is already in the window), so its size trades LDS
+ * (and hence resident wavefronts) against repeated scoring.
+ */
 typedef struct {
-  int32_t hash_slots;      /* visited-set slots per query (power of 2, 256..65536; 0 = 4096) */
-  int32_t waves_per_group; /* queries per workgroup (1..4; 0 = 1) */
+  int32_t hash_slots; /* visited-set slots per query (power of 2, 256..65536; 0 = 1024) */
+  int32_t probes;     /* slots tried before an id replaces the one in its home slot
+                         (1..16; 0 = 2 below 4096 slots, 8 from 4096 slots) */
 } lv_search_params;
 
 /* Bytes of device workspace lv_search needs for m queries. */

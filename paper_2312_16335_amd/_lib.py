@@ -40,7 +40,7 @@ class IndexDesc(ctypes.Structure):
 
 
 class SearchParams(ctypes.Structure):
-    _fields_ = [("hash_slots", _c_i32), ("waves_per_group", _c_i32)]
+    _fields_ = [("hash_slots", _c_i32), ("probes", _c_i32)]
 
 
 class Request(ctypes.Structure):
@@ -309,8 +309,8 @@ class Index:
             pass
 
 
-def _params(hash_slots: int = 0, waves_per_group: int = 0):
-    return ctypes.byref(SearchParams(hash_slots, waves_per_group))
+def _params(hash_slots: int = 0, probes: int = 0):
+    return ctypes.byref(SearchParams(hash_slots, probes))
 
 
 def lv_search_workspace_size(index: Index, m: int) -> int:
@@ -318,7 +318,7 @@ def lv_search_workspace_size(index: Index, m: int) -> int:
 
 
 def lv_search(index: Index, Q, k: int, L: int, ids, scores, counters=None, ws=None,
-              hash_slots: int = 0, stream=None) -> None:
+              hash_slots: int = 0, stream=None, probes: int = 0) -> None:
     import torch
 
     m = Q.shape[0]
@@ -326,18 +326,18 @@ def lv_search(index: Index, Q, k: int, L: int, ids, scores, counters=None, ws=No
     _check(load().lv_search(index.handle, _dev(Q, torch.float32), m, k, L,
                             _dev(ids, torch.int32), _dev(scores, torch.float32),
                             _dev(counters, torch.int32), _dev(ws), ws_bytes,
-                            _params(hash_slots), _stream(stream)))
+                            _params(hash_slots, probes), _stream(stream)))
 
 
 def lv_search_projected(index: Index, Q, Qp, k: int, L: int, ids, scores, counters=None,
-                        hash_slots: int = 0, stream=None) -> None:
+                        hash_slots: int = 0, stream=None, probes: int = 0) -> None:
     import torch
 
     m = Q.shape[0]
     _check(load().lv_search_projected(index.handle, _dev(Q, torch.float32),
                                       _dev(Qp, torch.float32), m, k, L, _dev(ids, torch.int32),
                                       _dev(scores, torch.float32), _dev(counters, torch.int32),
-                                      _params(hash_slots), _stream(stream)))
+                                      _params(hash_slots, probes), _stream(stream)))
 
 
 # ------------------------------------------------------------ batched search
@@ -375,12 +375,12 @@ class Batch:
     """Captured batched step (lv_batch_create)."""
 
     def __init__(self, multi: Multi, max_requests: int, max_queries: int, max_L: int,
-                 hash_slots: int = 0):
+                 hash_slots: int = 0, probes: int = 0):
         self.multi = multi
         self.caps = BatchCaps(max_requests, max_L, max_queries)
         h = _vp()
-        _check(load().lv_batch_create(multi.handle, ctypes.byref(self.caps), _params(hash_slots),
-                                      ctypes.byref(h)))
+        _check(load().lv_batch_create(multi.handle, ctypes.byref(self.caps),
+                                      _params(hash_slots, probes), ctypes.byref(h)))
         self.handle = h
 
     def step(self, reqs, Q, ids, scores, counters=None, stream=None, events=None):
@@ -439,7 +439,7 @@ def lv_autotune_knobs(multi: Multi, max_requests, max_queries, max_L, reqs, Q, i
                                     _dev(Q, torch.float32), _dev(ids, torch.int32),
                                     _dev(scores, torch.float32), reps, ctypes.byref(best),
                                     ctypes.byref(ms), _stream(stream)))
-    return {"hash_slots": best.hash_slots}, ms.value
+    return {"hash_slots": best.hash_slots, "probes": best.probes}, ms.value
 
 
 # ------------------------------------------------- differentiable projection

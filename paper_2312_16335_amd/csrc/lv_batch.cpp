@@ -28,7 +28,7 @@ struct lv_multi {
 struct lv_batch {
   lv_multi *multi = nullptr;
   lv_batch_caps caps{};
-  int log2h = 0;
+  lv::VisitedCfg vc{};
   int grid = 0;
   int max_tiles = 0;
   size_t table_bytes = 0;
@@ -145,11 +145,11 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
   if (caps->max_requests < 1 || caps->max_queries < 1 || caps->max_queries > 0x7FFFFFFF)
     LV_FAIL(LV_EINVAL, "bad capacities");
   if (caps->max_L < 1 || caps->max_L > LV_MAX_L) LV_FAIL(LV_EINVAL, "max_L must be in [1, %d]", LV_MAX_L);
-  int log2h = 0;
-  int rc = lv::hash_log2_for(params, &log2h);
+  lv::VisitedCfg vc{};
+  int rc = lv::visited_config(params, &vc);
   if (rc != LV_OK) return rc;
   int blocks = 0;
-  rc = lv::persistent_occupancy(multi->bits, multi->group, multi->vbytes, caps->max_L, log2h,
+  rc = lv::persistent_occupancy(multi->bits, multi->group, multi->vbytes, caps->max_L, vc.log2h,
                                 &blocks);
   if (rc != LV_OK) return rc;
   if (blocks < 1) LV_FAIL(LV_EUNSUPPORTED, "the persistent kernel does not fit on a compute unit");
@@ -161,7 +161,7 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
   if (!b) LV_FAIL(LV_ENOMEM, "out of host memory");
   b->multi = multi;
   b->caps = *caps;
-  b->log2h = log2h;
+  b->vc = vc;
   b->grid = blocks * cus;
   b->max_tiles = (int)((caps->max_queries + 31) / 32) + caps->max_requests;
   b->table_bytes = sizeof(lv::StepHeader) + sizeof(lv::Request) * (size_t)caps->max_requests;
@@ -194,7 +194,7 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
     LV_BATCH_TRY(hipGraphInstantiate(&b->pre_exec[i], b->pre_graph[i], nullptr, nullptr, 0));
     LV_BATCH_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed));
     int r2 = lv::launch_persistent(multi->bits, multi->group, multi->vbytes, hdr, multi->d_views,
-                                   b->d_counter[i], caps->max_L, log2h, b->grid, b->capture);
+                                   b->d_counter[i], caps->max_L, vc, b->grid, b->capture);
     hipError_t e3 = hipStreamEndCapture(b->capture, &b->trav_graph[i]);
     if (r2 != LV_OK || e3 != hipSuccess) {
       if (r2 == LV_OK) lv::set_error("graph capture failed");
@@ -407,7 +407,7 @@ extern "C" int lv_autotune_knobs(lv_multi *multi, const lv_batch_caps *caps,
   lv_search_params keep{0, 0};
   int last_rc = LV_OK;
   for (int hs : {1024, 2048, 4096, 8192}) {
-    lv_search_params p{hs, 1};
+    lv_search_params p{hs, 0};
     lv_batch *b = nullptr;
     int rc = lv_batch_create(multi, caps, &p, &b);
     if (rc != LV_OK) {

@@ -7,7 +7,7 @@
 
 namespace lv {
 
-constexpr int kDefaultHashSlots = 2048;
+constexpr int kDefaultHashSlots = 1024;
 
 // What the traversal reads of one index (device pointers).
 struct IndexView {
@@ -55,12 +55,18 @@ struct StepHeader {
 };
 
 IndexView make_view(const lv_index *ix);
-int hash_log2_for(const lv_search_params *params, int *log2h);
+// Visited set of one query: 2^log2h slots in LDS, up to `probes` slots tried
+// before an id replaces the one in its home slot.
+struct VisitedCfg {
+  int log2h;
+  int probes;
+};
+int visited_config(const lv_search_params *params, VisitedCfg *cfg);
 size_t beam_lds_bytes(int L, int log2h);
 int check_lds(size_t lds, int L, int log2h);
 int launch_persistent(int bits, int group, int vbytes, const StepHeader *hdr,
-                      const IndexView *subs, unsigned int *counter, int Lmax, int log2h, int grid,
-                      hipStream_t stream);
+                      const IndexView *subs, unsigned int *counter, int Lmax, VisitedCfg vc,
+                      int grid, hipStream_t stream);
 int persistent_occupancy(int bits, int group, int vbytes, int Lmax, int log2h, int *blocks);
 int launch_project_grouped(const StepHeader *hdr, const IndexView *subs, int max_tiles, int d,
                            int D, hipStream_t stream);

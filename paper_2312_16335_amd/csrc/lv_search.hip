@@ -44,7 +44,6 @@ namespace {
 constexpr uint32_t kExpanded = 0x80000000u;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
-constexpr int kProbes = 8;
 constexpr int kFastMerge = 8;  // survivors merged by counting instead of sorting
 
 // Everything one query needs besides the index.
@@ -87,8 +86,10 @@ __device__ __forceinline__ Lds carve(int Lmax) {
   return s;
 }
 
+// Total order of candidates: higher score first, then smaller id.  Bitwise
+// operators keep it branch-free across lanes.
 __device__ __forceinline__ bool better(double as, uint32_t aid, double bs, uint32_t bid) {
-  return as > bs || (as == bs && aid < bid);
+  return (as > bs) | ((as == bs) & (aid < bid));
 }
 
 // Order LDS traffic between lanes of one wavefront (a workgroup is one
@@ -126,10 +127,37 @@ __device__ __forceinline__ double lane_f64(double v, int j) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// DPP lane patterns (a row is 16 lanes): swap neighbours and pairs within
+// each quad, rotate a row right by 4 and by 8 lanes.
+constexpr int kDppQuadXor1 = 0xB1;
+constexpr int kDppQuadXor2 = 0x4E;
+constexpr int kDppRowRor4 = 0x124;
+constexpr int kDppRowRor8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over each aligned group of W lanes (16: one row; 64: the wavefront).
+// Rows reduce with DPP moves (no LDS round trip); the result may differ in
+// the last bit between lanes of a row, so callers read one fixed lane.
 template <int W>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = 1; o < W; o <<= 1) v += __shfl_xor(v, o, 64);
+  static_assert(W == 16 || W == 64, "groups of 16 or 64 lanes");
+  v += dpp_f64<kDppQuadXor1>(v);
+  v += dpp_f64<kDppQuadXor2>(v);
+  v += dpp_f64<kDppRowRor4>(v);
+  v += dpp_f64<kDppRowRor8>(v);
+  if constexpr (W == 64) {
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+  }
   return v;
 }
 
@@ -235,15 +263,15 @@ __device__ __forceinline__ void sort64(double &s, uint32_t &id, int lane) {
   }
 }
 
-// Visited test-and-set.  After kProbes occupied slots the id replaces the
+// Visited test-and-set.  After `probes` occupied slots the id replaces the
 // one in its home slot (the set forgets an older id) and counts as unknown:
 // it is scored, and the merge drops it if it is in the window.
-__device__ __forceinline__ bool hash_visit(uint32_t *hash, int log2h, uint32_t n) {
+__device__ __forceinline__ bool hash_visit(uint32_t *hash, int log2h, int probes, uint32_t n) {
   const uint32_t mask = (1u << log2h) - 1u;
   const uint32_t h0 = (n * 2654435761u) >> (32 - log2h);
   uint32_t h = h0;
 #pragma unroll 1
-  for (int t = 0; t < kProbes; ++t) {
+  for (int t = 0; t < probes; ++t) {
     const uint32_t old = atomicCAS(&hash[h], kEmpty, n);
     if (old == kEmpty) return true;
     if (old == n) return false;
@@ -310,6 +338,7 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
 // The whole search of one query by one wavefront.
 template <int BITS, int G, int V>
 __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm, int log2h,
+                             int probes,
                              int lane) {
   constexpr int NQ = V * 8 / BITS;
   const int L = job.L;
@@ -339,7 +368,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
   // seed the window with the entry node
   if (lane == 0) {
     sm.cid()[0] = ix.entry;
-    hash_visit(sm.hash(), log2h, ix.entry);
+    hash_visit(sm.hash(), log2h, probes, ix.entry);
   }
   wave_sync();
   score_batch<BITS, G, V>(ix, qv, sq, cq, sm.cid(), sm.cs(), 1, lane);
@@ -397,7 +426,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
     for (int rb = 0; rb < ix.R; rb += 64) {
       uint32_t n = rb == 0 ? first : (rb + lane < ix.R ? row[rb + lane] : kSentinel);
       bool fresh = false;
-      if (n < ix.N) fresh = hash_visit(sm.hash(), log2h, n);
+      if (n < ix.N) fresh = hash_visit(sm.hash(), log2h, probes, n);
       const uint64_t fm = __ballot(fresh);
       const int nc = __popcll(fm);
       if (nc == 0) continue;
@@ -445,14 +474,14 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
           rem &= rem - 1;
           const double cj = lane_f64(bs, j);
           const uint32_t ij = lane_u32(bid, j);
+          // empty slots hold (-inf, sentinel): never better, never equal
           int cnt = 0;
           uint64_t dm = 0;
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            const bool ok = er[t] != kSentinel;
             const uint32_t idt = er[t] & kIdMask;
-            cnt += __popcll(__ballot(ok && better(es[t], idt, cj, ij)));
-            dm |= __ballot(ok && idt == ij);
+            cnt += __popcll(__ballot(better(es[t], idt, cj, ij)));
+            dm |= __ballot(idt == ij);
           }
           const bool keep = dm == 0;  // not already in the window
           if (keep) {
@@ -600,6 +629,7 @@ struct PlainArgs {
   float *scores;
   uint32_t *counters;
   int32_t hash_log2;
+  int32_t probes;
 };
 
 template <int BITS, int G, int V>
@@ -615,7 +645,7 @@ __global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
   job.ids = a.ids + qi * a.k;
   job.scores = a.scores + qi * a.k;
   job.counters = a.counters ? a.counters + 2 * qi : nullptr;
-  search_query<BITS, G, V>(a.ix, job, sm, a.hash_log2, threadIdx.x);
+  search_query<BITS, G, V>(a.ix, job, sm, a.hash_log2, a.probes, threadIdx.x);
 }
 
 // Persistent form: wavefronts take queries from a device counter until the
@@ -631,7 +661,7 @@ template <int BITS, int G, int V>
 __global__ __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(persistent_waves<BITS, V>()))) void persistent_kernel(
     const StepHeader *__restrict__ hdr, const IndexView *__restrict__ subs,
-    unsigned int *__restrict__ counter, int32_t Lmax, int32_t hash_log2) {
+    unsigned int *__restrict__ counter, int32_t Lmax, int32_t hash_log2, int32_t probes) {
   const int lane = threadIdx.x;
   const Lds sm = carve(Lmax);
   const int64_t nq = hdr->nq;
@@ -667,7 +697,7 @@ __attribute__((amdgpu_waves_per_eu(persistent_waves<BITS, V>()))) void persisten
     // loop, where they would stay live (and spill) for the kernel's lifetime.
     int lane_q = lane;
     asm volatile("" : "+v"(lane_q));
-    search_query<BITS, G, V>(ix, job, sm, hash_log2, lane_q);
+    search_query<BITS, G, V>(ix, job, sm, hash_log2, probes, lane_q);
   }
 }
 
@@ -682,10 +712,10 @@ int launch_plain_t(const PlainArgs &a, size_t lds, hipStream_t s) {
 
 template <int BITS, int G, int V>
 int launch_persistent_t(const StepHeader *hdr, const IndexView *subs, unsigned int *counter,
-                        int Lmax, int log2h, size_t lds, int grid, hipStream_t s) {
+                        int Lmax, VisitedCfg vc, size_t lds, int grid, hipStream_t s) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
   hipLaunchKernelGGL((persistent_kernel<BITS, G, V>), dim3(grid), dim3(64), lds, s, hdr, subs,
-                     counter, Lmax, log2h);
+                     counter, Lmax, vc.log2h, vc.probes);
   LV_CHECK_LAUNCH();
   return LV_OK;
 }
@@ -724,13 +754,14 @@ struct PersistentLaunch {
   const StepHeader *hdr;
   const IndexView *subs;
   unsigned int *counter;
-  int Lmax, log2h;
+  int Lmax;
+  VisitedCfg vc;
   size_t lds;
   int grid;
   hipStream_t s;
   template <int B, int GG, int VV>
   int operator()() {
-    return launch_persistent_t<B, GG, VV>(hdr, subs, counter, Lmax, log2h, lds, grid, s);
+    return launch_persistent_t<B, GG, VV>(hdr, subs, counter, Lmax, vc, lds, grid, s);
   }
 };
 
@@ -764,13 +795,17 @@ IndexView make_view(const lv_index *ix) {
   return v;
 }
 
-int hash_log2_for(const lv_search_params *params, int *log2h) {
+int visited_config(const lv_search_params *params, VisitedCfg *cfg) {
   const int hs = params && params->hash_slots ? params->hash_slots : kDefaultHashSlots;
   if (hs < 256 || hs > 65536 || (hs & (hs - 1)))
     LV_FAIL(LV_EINVAL, "hash_slots must be a power of two in [256, 65536] (got %d)", hs);
+  const int pr = params ? params->probes : 0;
+  if (pr < 0 || pr > 16) LV_FAIL(LV_EINVAL, "probes must be in [0, 16] (got %d)", pr);
   int l = 0;
   while ((1 << l) < hs) ++l;
-  *log2h = l;
+  cfg->log2h = l;
+  // small sets (occupancy matters): few probes; large sets: nearly exact
+  cfg->probes = pr ? pr : (hs >= 4096 ? 8 : 2);
   return LV_OK;
 }
 
@@ -791,13 +826,13 @@ int check_lds(size_t lds, int L, int log2h) {
 int launch_beam(const lv_index *ix, const float *Q, const float *Qp, int64_t m, int32_t k,
                 int32_t L, uint32_t *ids, float *scores, uint32_t *counters,
                 const lv_search_params *params, hipStream_t stream) {
-  int log2h = 0;
-  int rc = hash_log2_for(params, &log2h);
+  VisitedCfg vc;
+  int rc = visited_config(params, &vc);
   if (rc != LV_OK) return rc;
   if (m == 0) return LV_OK;
   if (m > 0x7FFFFFFF) LV_FAIL(LV_EINVAL, "at most 2^31-1 queries per call");
-  const size_t lds = beam_lds_bytes(L, log2h);
-  rc = check_lds(lds, L, log2h);
+  const size_t lds = beam_lds_bytes(L, vc.log2h);
+  rc = check_lds(lds, L, vc.log2h);
   if (rc != LV_OK) return rc;
   PlainArgs a;
   a.ix = make_view(ix);
@@ -809,16 +844,17 @@ int launch_beam(const lv_index *ix, const float *Q, const float *Qp, int64_t m, 
   a.ids = ids;
   a.scores = scores;
   a.counters = counters;
-  a.hash_log2 = log2h;
+  a.hash_log2 = vc.log2h;
+  a.probes = vc.probes;
   PlainLaunch f{a, lds, stream};
   return dispatch(ix->desc.bits, ix->group, ix->vbytes, f);
 }
 
 int launch_persistent(int bits, int group, int vbytes, const StepHeader *hdr,
-                      const IndexView *subs, unsigned int *counter, int Lmax, int log2h, int grid,
-                      hipStream_t stream) {
-  const size_t lds = beam_lds_bytes(Lmax, log2h);
-  PersistentLaunch f{hdr, subs, counter, Lmax, log2h, lds, grid, stream};
+                      const IndexView *subs, unsigned int *counter, int Lmax, VisitedCfg vc,
+                      int grid, hipStream_t stream) {
+  const size_t lds = beam_lds_bytes(Lmax, vc.log2h);
+  PersistentLaunch f{hdr, subs, counter, Lmax, vc, lds, grid, stream};
   return dispatch(bits, group, vbytes, f);
 }
 

@@ -66,9 +66,11 @@ def test_search_argument_validation_before_launch():
         rc = lib.lv_search_projected(h, FAKE, FAKE, m, k, L, FAKE, FAKE, None,
                                      ctypes.byref(prm), None)
         assert rc == lv.LV_EINVAL, (m, k, L)
-    bad = lv.SearchParams(1000, 0)  # not a power of two
-    assert lib.lv_search_projected(h, FAKE, FAKE, 10, 5, 50, FAKE, FAKE, None,
-                                   ctypes.byref(bad), None) == lv.LV_EINVAL
+    for bad in (lv.SearchParams(1000, 0),   # slots not a power of two
+                lv.SearchParams(1024, 17),  # too many probes
+                lv.SearchParams(1024, -1)):
+        assert lib.lv_search_projected(h, FAKE, FAKE, 10, 5, 50, FAKE, FAKE, None,
+                                       ctypes.byref(bad), None) == lv.LV_EINVAL
     # workspace too small
     assert lib.lv_search(h, FAKE, 10, 5, 50, FAKE, FAKE, None, FAKE, 16,
                          ctypes.byref(prm), None) == lv.LV_EINVAL
