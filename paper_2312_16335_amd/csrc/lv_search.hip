@@ -63,7 +63,8 @@ struct Job {
 extern __shared__ __align__(16) unsigned char lv_smem[];
 
 // Layout: window scores [Lmax] f64, batch scores [64] f64, window ids
-// [Lmax] u32, batch ids [64] u32, merge positions [64] i32, visited hash.
+// [Lmax] u32, batch ids [64] u32, visited hash.  The merge positions of the
+// sorting merge reuse the batch scores' space (read into registers first).
 struct Lds {
   int Lmax;
   __device__ __forceinline__ double *ls() const { return reinterpret_cast<double *>(lv_smem); }
@@ -72,12 +73,8 @@ struct Lds {
     return reinterpret_cast<uint32_t *>(cs() + 64);
   }
   __device__ __forceinline__ uint32_t *cid() const { return lid() + Lmax; }
-  __device__ __forceinline__ int32_t *lbc() const {
-    return reinterpret_cast<int32_t *>(cid() + 64);
-  }
-  __device__ __forceinline__ uint32_t *hash() const {
-    return reinterpret_cast<uint32_t *>(lbc() + 64);
-  }
+  __device__ __forceinline__ int32_t *lbc() const { return reinterpret_cast<int32_t *>(cs()); }
+  __device__ __forceinline__ uint32_t *hash() const { return cid() + 64; }
 };
 
 __device__ __forceinline__ Lds carve(int Lmax) {
@@ -810,7 +807,7 @@ int visited_config(const lv_search_params *params, VisitedCfg *cfg) {
 }
 
 size_t beam_lds_bytes(int L, int log2h) {
-  return (size_t)L * 12 + 64 * 16 + ((size_t)4 << log2h);
+  return (size_t)L * 12 + 64 * 12 + ((size_t)4 << log2h);
 }
 
 int check_lds(size_t lds, int L, int log2h) {
