@@ -68,7 +68,7 @@ def cache_dir():
 def build_graph_cached(wl, X, out):
     from synth import graph
 
-    key = f"{wl.name}_s{wl.seed_data}_n{wl.N}_R{wl.R}_a{'-'.join(map(str, wl.graph_alphas))}_v5"
+    key = f"{wl.name}_s{wl.seed_data}_n{wl.N}_R{wl.R}_a{'-'.join(map(str, wl.graph_alphas))}_v6"
     p = os.path.join(cache_dir(), key + ".npz")
     if os.path.exists(p):
         z = np.load(p)
@@ -118,8 +118,9 @@ def recall(ids, truth, k):
     return hit / (k * len(truth))
 
 
-def profile_traffic(kernel_src):
-    """HBM bytes per launch from committed counter runs, if the kernel is unchanged."""
+def profile_traffic(kernel_src, L, slots):
+    """HBM bytes per launch from committed counter runs, if the kernel is unchanged and
+    the counters were taken at this window and visited-set size."""
     p = os.path.join(ROOT, "profiles", "persistent_kernel_id-1m-768_counters.md")
     if not os.path.exists(p):
         return None
@@ -129,7 +130,8 @@ def profile_traffic(kernel_src):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256") != sha:
+    if (vals.get("kernel_source_sha256") != sha or vals.get("window_L") != str(L)
+            or vals.get("visited_slots") != str(slots)):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -430,7 +432,8 @@ def main():
     achieved_serial = alg_bytes_total / (kernel_ms / 1e3) / 1e9
     beam_launch_ms = beam_ms / (args.steps * nreq)
     achieved_plain = (alg_bytes_total / nreq) / (beam_launch_ms / 1e3) / 1e9
-    traffic = profile_traffic(os.path.join(ROOT, "paper_2312_16335_amd", "csrc", "lv_search.hip"))
+    traffic = profile_traffic(os.path.join(ROOT, "paper_2312_16335_amd", "csrc", "lv_search.hip"),
+                              L_star, hs)
     batch.close()
     multi.close()
 

@@ -69,13 +69,14 @@ def build_graph(X: np.ndarray, R: int, L: int = 0, metric: int = METRIC_L2,
     mixtures, whose members are nearly equidistant, alpha = 1.2 keeps the
     nearest R cluster members and the graph navigates poorly, while 1.0
     prunes them into diverse edges (recall@10 at window 100 on 300k vectors:
-    0.88 vs 0.97).  L defaults to 2R (search window during
-    construction); maxc caps the pruning pool (default 8R).  Deterministic
-    for any thread count.
+    0.88 vs 0.97).  L defaults to R (search window during construction):
+    on the 1M x 768 mixture (R = 64), build windows of 64, 96, 128 and 200
+    need search windows of 96, 112, 143 and 175 for 10-recall@10 = 0.90.  maxc caps the
+    pruning pool (default 8R).  Deterministic for any thread count.
     """
     X = _as_f16(X)
     n, dim = X.shape
-    L = L or 2 * R
+    L = L or R
     maxc = maxc or 8 * R
     al = np.ascontiguousarray(alphas, dtype=np.float32)
     adj = np.empty((n, R), dtype=np.uint32)

@@ -44,7 +44,7 @@ def stride_for(d: int, bits: int) -> int:
 
 def graph_cached(wl: gen.Workload, X: np.ndarray):
     os.makedirs(CACHE, exist_ok=True)
-    key = f"{wl.name}_s{wl.seed_data}_n{wl.N}_R{wl.R}_a{'-'.join(map(str, wl.graph_alphas))}_v5"
+    key = f"{wl.name}_s{wl.seed_data}_n{wl.N}_R{wl.R}_a{'-'.join(map(str, wl.graph_alphas))}_v6"
     p = os.path.join(CACHE, key + ".npz")
     if os.path.exists(p):
         z = np.load(p)
