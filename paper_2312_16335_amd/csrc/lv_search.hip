@@ -130,20 +130,25 @@ constexpr int kDppQuadXor1 = 0xB1;
 constexpr int kDppQuadXor2 = 0x4E;
 constexpr int kDppRowRor4 = 0x124;
 constexpr int kDppRowRor8 = 0x128;
+constexpr int kDppRowBcast15 = 0x142;  // last lane of a row to the next row
+constexpr int kDppRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
 
-template <int CTRL>
+// v moved across lanes by a DPP pattern; rows outside ROWS receive +0.0.
+template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ double dpp_f64(double v) {
   const uint64_t b = __builtin_bit_cast(uint64_t, v);
   const uint32_t lo =
-      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xF, false);
   const uint32_t hi =
-      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xF, false);
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Sum over each aligned group of W lanes (16: one row; 64: the wavefront).
-// Rows reduce with DPP moves (no LDS round trip); the result may differ in
-// the last bit between lanes of a row, so callers read one fixed lane.
+// Sum over each aligned group of W lanes (16: one row; 64: the wavefront),
+// with DPP moves only (no LDS round trip).  W = 16: every lane of a row
+// ends with the row's sum (possibly differing in the last bit between
+// lanes, so callers read one fixed lane).  W = 64: row sums are chained
+// into lane 63 and broadcast, so every lane returns the same value.
 template <int W>
 __device__ __forceinline__ double group_sum(double v) {
   static_assert(W == 16 || W == 64, "groups of 16 or 64 lanes");
@@ -152,8 +157,9 @@ __device__ __forceinline__ double group_sum(double v) {
   v += dpp_f64<kDppRowRor4>(v);
   v += dpp_f64<kDppRowRor8>(v);
   if constexpr (W == 64) {
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
+    v += dpp_f64<kDppRowBcast15, 0xA>(v);  // rows 1, 3: + previous row
+    v += dpp_f64<kDppRowBcast31, 0xC>(v);  // rows 2, 3: + rows 0..1
+    v = lane_f64(v, 63);
   }
   return v;
 }
@@ -386,26 +392,26 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
     uint32_t *lid = sm.lid();
     // best unexpanded entry = first unexpanded position of the sorted window;
     // the next one is the runner-up whose row is prefetched
-    int pos = -1, pos2 = -1;
+    int pos = -1;
+    uint32_t p = kSentinel, p2 = kSentinel;
     for (int base = 0; base < nl; base += 64) {
       const int i = base + lane;
-      const bool un = i < nl && !(lid[i] & kExpanded);
-      uint64_t msk = __ballot(un);
+      const uint32_t v = i < nl ? lid[i] : kExpanded;
+      uint64_t msk = __ballot(!(v & kExpanded));
       if (msk) {
         if (pos < 0) {
-          pos = base + __ffsll((unsigned long long)msk) - 1;
+          const int b = __ffsll((unsigned long long)msk) - 1;
+          pos = base + b;
+          p = lane_u32(v, b);
           msk &= msk - 1;
         }
         if (msk) {
-          pos2 = base + __ffsll((unsigned long long)msk) - 1;
+          p2 = lane_u32(v, __ffsll((unsigned long long)msk) - 1);
           break;
         }
       }
     }
     if (pos < 0) break;
-    const uint32_t p = lid[pos];
-    const uint32_t p2 = pos2 >= 0 ? lid[pos2] : kSentinel;
-    wave_sync();
     if (lane == 0) lid[pos] = p | kExpanded;
     wave_sync();
     ++n_exp;
@@ -452,6 +458,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
         // lands at (#window entries better) + (#kept survivors better), a
         // window entry moves down by the kept survivors better than it.  The
         // window is read into registers; survivors are broadcast one by one.
+        const int nt = (nl + 63) >> 6;  // 64-entry chunks in use (uniform)
         double es[4];
         uint32_t er[4];
 #pragma unroll
@@ -476,15 +483,18 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
           uint64_t dm = 0;
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            const uint32_t idt = er[t] & kIdMask;
-            cnt += __popcll(__ballot(better(es[t], idt, cj, ij)));
-            dm |= __ballot(idt == ij);
+            if (t < nt) {
+              const uint32_t idt = er[t] & kIdMask;
+              cnt += __popcll(__ballot(better(es[t], idt, cj, ij)));
+              dm |= __ballot(idt == ij);
+            }
           }
           const bool keep = dm == 0;  // not already in the window
           if (keep) {
             ++nkeep;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) sh[t] += (lane + 64 * t >= cnt) ? 1 : 0;
+            for (int t = 0; t < 4; ++t)
+              if (t < nt) sh[t] += (lane + 64 * t >= cnt) ? 1 : 0;
             my_rank += (bid != kSentinel && better(cj, ij, bs, bid)) ? 1 : 0;
           }
           if (lane == j) {
