@@ -291,7 +291,7 @@ def main():
         if not args.only_steps:
             # refine: smallest window in (L_lo, L_hi] reaching the target
             lo_, hi_ = L_lo, L_hi
-            while hi_ - lo_ > max(1, hi_ // 20):
+            while hi_ - lo_ > 1:
                 mid = (lo_ + hi_) // 2
                 sweep[mid] = measure(mid)
                 if sweep[mid][0] >= args.target:

@@ -134,13 +134,19 @@ constexpr int kDppRowBcast15 = 0x142;  // last lane of a row to the next row
 constexpr int kDppRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
 
 // v moved across lanes by a DPP pattern; rows outside ROWS receive +0.0.
+// With all rows enabled every lane is written, so no initial value is needed.
 template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ double dpp_f64(double v) {
   const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo =
-      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xF, false);
-  const uint32_t hi =
-      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xF, false);
+  uint32_t lo, hi;
+  if constexpr (ROWS == 0xF) {
+    lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  } else {
+    lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xF, false);
+    hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xF,
+                                               false);
+  }
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
@@ -209,6 +215,13 @@ __device__ __forceinline__ void score_batch(const IndexView &ix, const float (&q
   constexpr int U = (48 / V) < 2 ? 2 : (48 / V);
   const int gl = lane % G;
   const int grp = lane / G;
+  // The record's delta and lo follow its codes.  When both lie in one lane's
+  // chunk, that lane (whose code slots past d meet zero query components)
+  // writes the score; otherwise lane 0 loads them separately.
+  const int cl = ix.code_bytes / V;
+  const int cw0 = (ix.code_bytes % V) / 4;
+  const bool in_chunk = (ix.code_bytes % V) + 8 <= V && cl < G;
+  const int wl = in_chunk ? cl : 0;
   for (int base = 0; base < nc; base += RPP * U) {
     Chunk<V> ch[U];
     uint32_t dlw[U], low[U];
@@ -219,7 +232,7 @@ __device__ __forceinline__ void score_batch(const IndexView &ix, const float (&q
       if (base + u * RPP < nc && c < nc) {
         const LV_GLOBAL unsigned char *rec = gp(ix.records) + (size_t)cid[c] * (size_t)ix.stride;
         ch[u] = load_chunk<V>(rec + gl * V);
-        if (gl == 0) {
+        if (!in_chunk && gl == 0) {
           const LV_GLOBAL uint32_t *cw =
               reinterpret_cast<const LV_GLOBAL uint32_t *>(rec + ix.code_bytes);
           dlw[u] = cw[0];
@@ -239,7 +252,14 @@ __device__ __forceinline__ void score_batch(const IndexView &ix, const float (&q
         acc = fma((double)code_at<BITS, V>(ch[u], t), (double)qv[t], acc);
       acc = group_sum<G>(acc);
       const int c = base + u * RPP + grp;
-      if (gl == 0 && c < nc) {
+      if (in_chunk) {
+#pragma unroll
+        for (int w = 0; w < V / 4; ++w) {
+          if (w == cw0) dlw[u] = ch[u].w[w];
+          if (w == cw0 + 1) low[u] = ch[u].w[w];
+        }
+      }
+      if (gl == wl && c < nc) {
         const double delta = (double)__uint_as_float(dlw[u]);
         const double lo = (double)__uint_as_float(low[u]);
         cs[c] = delta * acc + lo * sq + cq;
