@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--target", type=float, default=0.90)
     ap.add_argument("--hash-slots", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sec", choices=("f16", "lvq8"), default="f16",
+                    help="secondary vectors: float16 (the benchmark configuration) or LVQ-8 "
+                         "(no CPU baseline)")
     ap.add_argument("--cpu-sample", type=int, default=10000)
     ap.add_argument("--only-steps", action="store_true",
                     help="skip the sweep refinement (profiling runs)")
@@ -195,14 +198,24 @@ def main():
     stride = lv.lv_record_stride(wl.d, wl.bits)
     rec = torch.empty((wl.N, stride), dtype=torch.uint8, device=dev)
     Y = torch.empty((wl.N, wl.d), dtype=torch.float32, device=dev)
-    sec = torch.empty((wl.N, wl.D), dtype=torch.float16, device=dev)
+    smud = None
+    if args.sec == "lvq8":
+        # LVQ-8 secondaries centred on the sample mean of the database
+        smud = torch.from_numpy((ssum / ns).astype(np.float32)).to(dev)
+        sec = torch.empty((wl.N, lv.lv_secondary_row_bytes(wl.D, lv.LV_LVQ8)), dtype=torch.uint8,
+                          device=dev)
+    else:
+        sec = torch.empty((wl.N, wl.D), dtype=torch.float16, device=dev)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     lv.lv_project(Xd, Pb, Y)
     ev1.record()
     lv.lv_lvq_encode(Y, mud, wl.bits, rec)
-    lv.lv_to_f16(Xd, sec)
+    if smud is not None:
+        lv.lv_lvq_encode(Xd, smud, 8, sec)
+    else:
+        lv.lv_to_f16(Xd, sec)
     torch.cuda.synchronize()
     db_proj_ms = ev0.elapsed_time(ev1)
     truth = ground_truth_gpu(torch, Xd, Q, k)
@@ -214,7 +227,7 @@ def main():
     adj, entry = g["adj"], g["entry"]
     log(f"graph ready at {time.time() - t0:.1f}s (build {g['graph_s']:.1f}s)")
     adjd = torch.from_numpy(adj.view(np.int32)).to(dev)
-    index = lv.Index(rec, mud, sec, adjd, entry, wl.bits, wl.d, A_bf16=Pb)
+    index = lv.Index(rec, mud, sec, adjd, entry, wl.bits, wl.d, A_bf16=Pb, sec_mu=smud)
 
     # ---- request stream over the test queries (uneven batches)
     m = len(Q)
@@ -318,8 +331,8 @@ def main():
     n_exp, n_dist = c[:, 0], c[:, 1]
     n_rr = np.minimum(L_star, n_dist)
     code_bytes = wl.d * wl.bits // 8
-    esec = 2
-    bytes_q = (4 * wl.D + n_exp * 4 * wl.R + n_dist * (code_bytes + 8) + n_rr * wl.D * esec
+    sec_row = wl.D * 2 if smud is None else wl.D + 8  # bytes of one secondary (codes + 8)
+    bytes_q = (4 * wl.D + n_exp * 4 * wl.R + n_dist * (code_bytes + 8) + n_rr * sec_row
                + 8 * k)
     alg_bytes_total = float(bytes_q.sum())
 
@@ -433,7 +446,7 @@ def main():
     beam_launch_ms = beam_ms / (args.steps * nreq)
     achieved_plain = (alg_bytes_total / nreq) / (beam_launch_ms / 1e3) / 1e9
     traffic = profile_traffic(os.path.join(ROOT, "paper_2312_16335_amd", "csrc", "lv_search.hip"),
-                              L_star, hs)
+                              L_star, hs) if smud is None else None
     batch.close()
     multi.close()
 
@@ -454,7 +467,7 @@ def main():
 
     # ---- CPU oracle on a bounded sample
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and smud is None:
         cpu = cpu_baseline(wl, X, Xs, Q, adj, entry, L_star, args.cpu_sample, truth)
         if cpu["sample"].startswith("all") and abs(cpu["recall"] - rec_star) > 0.005:
             log(f"WARNING: GPU recall {rec_star:.4f} vs oracle {cpu['recall']:.4f}")
@@ -473,7 +486,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "N": wl.N, "D": wl.D, "d": wl.d, "lvq_bits": wl.bits,
-                   "secondary": wl.sec_dtype, "R": wl.R, "k": k, "queries": m, "L": L_star,
+                   "secondary": args.sec, "R": wl.R, "k": k, "queries": m, "L": L_star,
                    "requests": nreq, "mode": "batched, 2 steps in flight",
                    "visited_slots": hs},
         "recall_at_L": rec_star,

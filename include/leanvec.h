@@ -48,6 +48,7 @@ extern "C" {
 /* Secondary-vector element types. */
 #define LV_F32 0
 #define LV_F16 1
+#define LV_LVQ8 2 /* secondary vectors compressed with LVQ-8 */
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int lv_version(void);
@@ -215,13 +216,25 @@ typedef struct {
   int32_t record_stride;   /* bytes per primary record (lv_record_stride) */
   const void *records;     /* [N][record_stride] LVQ records */
   const float *mu;         /* [d] LVQ centring vector */
-  int32_t sec_dtype;       /* LV_F32 or LV_F16 */
-  const void *secondaries; /* [N][D] secondary vectors */
+  int32_t sec_dtype;       /* LV_F32, LV_F16 or LV_LVQ8 */
+  const void *secondaries; /* [N][lv_secondary_row_bytes(D, sec_dtype)] bytes */
   int32_t R;               /* graph out-degree, 1..1024 */
   const uint32_t *adjacency; /* [N][R]; valid ids first, then LV_SENTINEL */
   uint32_t entry;          /* traversal start node */
   const uint16_t *A;       /* [d][D] bfloat16 query projection, or NULL */
+  const float *sec_mu;     /* [D] centring vector of LV_LVQ8 secondaries, else NULL */
 } lv_index_desc;
+
+/*
+ * Bytes per secondary row: 4 D (LV_F32), 2 D (LV_F16), or for LV_LVQ8 (the
+ * secondary vectors compressed with 8-bit LVQ, Section 3 ablation on the
+ * secondary representation) D code bytes, float32 delta, float32 lo and zero
+ * padding to D + 16 bytes, written by lv_lvq_encode(X, N, D, sec_mu, 8, rows,
+ * D + 16) and scored as <q, sec_mu + lo + delta * c>.  Returns 0 when the
+ * search kernels do not support the combination (rows above 2 KiB, or
+ * LV_LVQ8 with D not a multiple of 16 or above 1008).
+ */
+int32_t lv_secondary_row_bytes(int32_t D, int32_t sec_dtype);
 
 typedef struct lv_index lv_index;
 

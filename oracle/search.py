@@ -45,7 +45,10 @@ class Index:
     delta: np.ndarray      # float32 [N]
     lo: np.ndarray         # float32 [N]
     mu: np.ndarray         # float32 [d]
-    sec: np.ndarray        # float16 or float32 [N, D]
+    sec: np.ndarray        # float16 or float32 [N, D]; uint8 LVQ-8 codes when sec_delta is set
+    sec_delta: Optional[np.ndarray] = None   # float32 [N]  LVQ-8 secondaries (Section 3:
+    sec_lo: Optional[np.ndarray] = None      # float32 [N]  secondary vectors compressed
+    sec_mu: Optional[np.ndarray] = None      # float32 [D]  with LVQ-8)
 
     @property
     def N(self) -> int:
@@ -82,9 +85,16 @@ def primary_scores(index: Index, qp64: np.ndarray, ids) -> np.ndarray:
 
 
 def secondary_scores(index: Index, q64: np.ndarray, ids) -> np.ndarray:
-    """<q, secondary(n)> in float64 (Section 2, re-ranking)."""
+    """<q, secondary(n)> in float64 (Section 2, re-ranking); an LVQ-8 secondary
+    is its reconstruction mu + lo + delta * c."""
     ids = np.asarray(ids, dtype=np.int64)
-    return rowdot(index.sec[ids], q64)
+    if index.sec_delta is None:
+        return rowdot(index.sec[ids], q64)
+    xhat = (index.sec_mu.astype(np.float64)[None, :]
+            + index.sec_lo[ids].astype(np.float64)[:, None]
+            + index.sec_delta[ids].astype(np.float64)[:, None]
+            * index.sec[ids].astype(np.float64))
+    return rowdot(xhat, q64)
 
 
 @dataclass
@@ -208,7 +218,8 @@ _G = {}
 def _init_worker(paths, entry):
     arrs = {k: np.load(v, mmap_mode="r") for k, v in paths.items()}
     _G["index"] = Index(arrs["adj"], entry, arrs["codes"], arrs["delta"], arrs["lo"],
-                        arrs["mu"], arrs["sec"])
+                        arrs["mu"], arrs["sec"], arrs.get("sec_delta"), arrs.get("sec_lo"),
+                        arrs.get("sec_mu"))
 
 
 def _run_chunk(args):
@@ -243,7 +254,10 @@ def search_many(index: Index, Q, Qp, k: int, L: int, procs: int = 1,
     own = workdir is None
     wd = workdir or tempfile.mkdtemp(prefix="lv_oracle_")
     paths = {}
-    for name in ("adj", "codes", "delta", "lo", "mu", "sec"):
+    names = ["adj", "codes", "delta", "lo", "mu", "sec"]
+    if index.sec_delta is not None:
+        names += ["sec_delta", "sec_lo", "sec_mu"]
+    for name in names:
         arr = getattr(index, name)
         p = os.path.join(wd, name + ".npy")
         if not os.path.exists(p):

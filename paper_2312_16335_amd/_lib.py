@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "liblv.so")
 
 LV_OK, LV_WNOTCONVERGED = 0, 1
 LV_EINVAL, LV_ENOMEM, LV_EDEVICE, LV_EUNSUPPORTED = -1, -2, -3, -4
-LV_F32, LV_F16 = 0, 1
+LV_F32, LV_F16, LV_LVQ8 = 0, 1, 2
 LV_SENTINEL = 0xFFFFFFFF
 LV_FW_INIT_ES, LV_FW_INIT_ZERO, LV_FW_INIT_GIVEN = 0, 1, 2
 
@@ -36,7 +36,7 @@ class IndexDesc(ctypes.Structure):
     _fields_ = [("N", _c_i64), ("D", _c_i32), ("d", _c_i32), ("bits", _c_i32),
                 ("record_stride", _c_i32), ("records", _vp), ("mu", _vp), ("sec_dtype", _c_i32),
                 ("secondaries", _vp), ("R", _c_i32), ("adjacency", _vp), ("entry", _c_u32),
-                ("A", _vp)]
+                ("A", _vp), ("sec_mu", _vp)]
 
 
 class SearchParams(ctypes.Structure):
@@ -73,6 +73,7 @@ _SIGS = {
     "lv_to_bf16": (_c_i32, [_vp, _c_i64, _vp]),
     "lv_project": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _vp]),
     "lv_record_stride": (_c_i32, [_c_i32, _c_i32]),
+    "lv_secondary_row_bytes": (_c_i32, [_c_i32, _c_i32]),
     "lv_lvq_encode": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _c_i32, _vp]),
     "lv_to_f16": (_c_i32, [_vp, _c_i64, _vp, _vp]),
     "lv_index_create": (_c_i32, [ctypes.POINTER(IndexDesc), ctypes.POINTER(_vp)]),
@@ -263,6 +264,10 @@ def lv_record_stride(d: int, bits: int) -> int:
     return load().lv_record_stride(d, bits)
 
 
+def lv_secondary_row_bytes(D: int, sec_dtype: int) -> int:
+    return load().lv_secondary_row_bytes(D, sec_dtype)
+
+
 def lv_lvq_encode(Y, mu, bits: int, records, stream=None) -> None:
     import torch
 
@@ -282,16 +287,23 @@ class Index:
     """Handle over device arrays (borrowed: keep the tensors alive)."""
 
     def __init__(self, records, mu, secondaries, adjacency, entry: int, bits: int, d: int,
-                 A_bf16=None):
+                 A_bf16=None, sec_mu=None):
+        """secondaries: float16 or float32 [N][D], or (with sec_mu, float32 [D]) uint8
+        LVQ-8 rows [N][D + 16] from lv_lvq_encode."""
         import torch
 
-        N, D = secondaries.shape
-        self._keep = (records, mu, secondaries, adjacency, A_bf16)
-        sec_dtype = LV_F16 if secondaries.dtype == torch.float16 else LV_F32
+        N = secondaries.shape[0]
+        if sec_mu is not None:
+            sec_dtype, D = LV_LVQ8, sec_mu.shape[0]
+        else:
+            sec_dtype = LV_F16 if secondaries.dtype == torch.float16 else LV_F32
+            D = secondaries.shape[1]
+        self._keep = (records, mu, secondaries, adjacency, A_bf16, sec_mu)
         self.desc = IndexDesc(N, D, d, bits, records.shape[1], _dev(records, torch.uint8),
                               _dev(mu, torch.float32), sec_dtype, _dev(secondaries),
                               adjacency.shape[1], _dev(adjacency, torch.int32), entry,
-                              _dev(A_bf16) if A_bf16 is not None else None)
+                              _dev(A_bf16) if A_bf16 is not None else None,
+                              _dev(sec_mu, torch.float32) if sec_mu is not None else None)
         h = _vp()
         _check(load().lv_index_create(ctypes.byref(self.desc), ctypes.byref(h)))
         self.handle = h

@@ -12,7 +12,9 @@ int validate_desc(const lv_index_desc *d, lv_index *ix) {
   if (d->d < 8 || d->d % 8 != 0) LV_FAIL(LV_EINVAL, "d must be a positive multiple of 8");
   if (d->D < d->d) LV_FAIL(LV_EINVAL, "D must be >= d");
   if (d->bits != 4 && d->bits != 8) LV_FAIL(LV_EINVAL, "bits must be 4 or 8");
-  if (d->sec_dtype != LV_F32 && d->sec_dtype != LV_F16) LV_FAIL(LV_EINVAL, "bad sec_dtype");
+  if (d->sec_dtype != LV_F32 && d->sec_dtype != LV_F16 && d->sec_dtype != LV_LVQ8)
+    LV_FAIL(LV_EINVAL, "bad sec_dtype");
+  if (d->sec_dtype == LV_LVQ8 && !d->sec_mu) LV_FAIL(LV_EINVAL, "LV_LVQ8 secondaries need sec_mu");
   if (d->R < 1 || d->R > 1024) LV_FAIL(LV_EINVAL, "R must be in [1, 1024]");
   if ((uint64_t)d->entry >= (uint64_t)d->N) LV_FAIL(LV_EINVAL, "entry out of range");
   if (!d->records || !d->mu || !d->secondaries || !d->adjacency)
@@ -32,10 +34,10 @@ int validate_desc(const lv_index_desc *d, lv_index *ix) {
       LV_FAIL(LV_EUNSUPPORTED, "record_stride %d unsupported (use lv_record_stride)",
               d->record_stride);
   }
-  const int esize = d->sec_dtype == LV_F16 ? 2 : 4;
-  const int64_t row_bytes = (int64_t)d->D * esize;
-  if (row_bytes % 16 != 0) LV_FAIL(LV_EUNSUPPORTED, "secondary rows must be a multiple of 16 bytes");
-  if (row_bytes > 2048) LV_FAIL(LV_EUNSUPPORTED, "secondary rows above 2 KiB are not supported");
+  const int64_t row_bytes = lv_secondary_row_bytes(d->D, d->sec_dtype);
+  if (row_bytes == 0)
+    LV_FAIL(LV_EUNSUPPORTED, "secondary rows of D = %d and type %d are not supported", d->D,
+            d->sec_dtype);
   if (d->A && d->D % 8 != 0) LV_FAIL(LV_EUNSUPPORTED, "query projection needs D % 8 == 0");
   ix->desc = *d;
   ix->code_bytes = cb;
@@ -57,6 +59,16 @@ int validate_query(const lv_index *ix, const float *Q, int64_t m, int32_t k, int
 }
 
 }  // namespace
+
+extern "C" int32_t lv_secondary_row_bytes(int32_t D, int32_t sec_dtype) {
+  int64_t b = 0;
+  if (D < 1) return 0;
+  if (sec_dtype == LV_F32) b = 4 * (int64_t)D;
+  else if (sec_dtype == LV_F16) b = 2 * (int64_t)D;
+  else if (sec_dtype == LV_LVQ8) b = D % 16 == 0 && D <= 1008 ? (int64_t)D + 16 : 0;
+  if (b == 0 || b % 16 != 0 || b > 2048) return 0;
+  return (int32_t)b;
+}
 
 extern "C" int lv_index_create(const lv_index_desc *desc, lv_index **out) {
   lv::clear_error();

@@ -20,7 +20,8 @@ struct IndexView {
   int32_t D;
   int32_t sec_row_bytes;
   int32_t sec_packets;
-  int32_t sec_f16;
+  int32_t sec_kind;  // LV_F32, LV_F16 or LV_LVQ8
+  const float *sec_mu;  // [D] for LV_LVQ8
   const uint32_t *adj;
   int32_t R;
   uint32_t entry;

@@ -304,21 +304,41 @@ __device__ __forceinline__ bool hash_visit(uint32_t *hash, int log2h, int probes
   return true;
 }
 
-template <bool F16>
+// Secondary scores of window entries ids[0..nl) into out[], one row at a
+// time across the wavefront (16-byte packets, UR rows in flight).  KIND is
+// LV_F32, LV_F16 or LV_LVQ8; an LVQ-8 row is scored as
+// delta * <q, c> + lo * sum(q) + <q, sec_mu>, which equals <q, x^> for its
+// reconstruction x^ = sec_mu + lo + delta * c.  The packet after the codes
+// holds delta and lo; its query components are zero.
+template <int KIND>
 __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
                                             const uint32_t *ids, double *out, int nl, int lane) {
-  constexpr int E = F16 ? 8 : 4;  // elements per 16-byte packet
-  constexpr int PPL = 2;          // packets per lane (rows up to 2 KiB)
-  constexpr int UR = 4;           // rows in flight
+  constexpr int E = KIND == LV_F16 ? 8 : (KIND == LV_F32 ? 4 : 16);  // elements per packet
+  // packets per lane: rows up to 2 KiB (LV_LVQ8 rows up to 1 KiB)
+  constexpr int PPL = KIND == LV_LVQ8 ? 1 : 2;
+  constexpr int UR = 4;   // rows in flight
   float qq[PPL][E];
+  double sq = 0.0, cq = 0.0;
 #pragma unroll
   for (int pk = 0; pk < PPL; ++pk) {
     const int packet = lane + 64 * pk;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = packet * E + e;
-      qq[pk][e] = (packet < ix.sec_packets && j < ix.D) ? gp(q)[j] : 0.f;
+      const bool in = packet < ix.sec_packets && j < ix.D;
+      qq[pk][e] = in ? gp(q)[j] : 0.f;
+      if constexpr (KIND == LV_LVQ8) {
+        sq += (double)qq[pk][e];
+        cq = fma((double)qq[pk][e], in ? (double)gp(ix.sec_mu)[j] : 0.0, cq);
+      }
     }
+  }
+  int cl = 0, cpk = 0;  // lane and packet slot holding an LVQ-8 row's delta and lo
+  if constexpr (KIND == LV_LVQ8) {
+    sq = group_sum<64>(sq);
+    cq = group_sum<64>(cq);
+    cl = (ix.D / 16) % 64;
+    cpk = (ix.D / 16) / 64;
   }
   for (int base = 0; base < nl; base += UR) {
     u32x4 v[UR][PPL];
@@ -344,15 +364,22 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
         const uint32_t w[4] = {v[u][pk][0], v[u][pk][1], v[u][pk][2], v[u][pk][3]};
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          float x;
-          if constexpr (F16)
-            x = (float)__builtin_bit_cast(_Float16, (uint16_t)(w[e >> 1] >> (16 * (e & 1))));
+          double x;
+          if constexpr (KIND == LV_F16)
+            x = (double)(float)__builtin_bit_cast(_Float16, (uint16_t)(w[e >> 1] >> (16 * (e & 1))));
+          else if constexpr (KIND == LV_F32)
+            x = (double)__uint_as_float(w[e]);
           else
-            x = __uint_as_float(w[e]);
-          acc = fma((double)x, (double)qq[pk][e], acc);
+            x = (double)((w[e >> 2] >> (8 * (e & 3))) & 0xFFu);
+          acc = fma(x, (double)qq[pk][e], acc);
         }
       }
       acc = group_sum<64>(acc);
+      if constexpr (KIND == LV_LVQ8) {
+        const uint32_t dw = lane_u32(cpk == 0 ? v[u][0][0] : v[u][PPL - 1][0], cl);
+        const uint32_t lw = lane_u32(cpk == 0 ? v[u][0][1] : v[u][PPL - 1][1], cl);
+        acc = (double)__uint_as_float(dw) * acc + (double)__uint_as_float(lw) * sq + cq;
+      }
       if (lane == 0 && base + u < nl) out[base + u] = acc;
     }
   }
@@ -598,10 +625,12 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
   // score of entry j replaces its primary score, its id loses the flag
   uint32_t *id2 = sm.lid();
   double *s2 = sm.ls();
-  if (ix.sec_f16)
-    rerank_rows<true>(ix, job.q, id2, s2, nl, lane);
+  if (ix.sec_kind == LV_F16)
+    rerank_rows<LV_F16>(ix, job.q, id2, s2, nl, lane);
+  else if (ix.sec_kind == LV_LVQ8)
+    rerank_rows<LV_LVQ8>(ix, job.q, id2, s2, nl, lane);
   else
-    rerank_rows<false>(ix, job.q, id2, s2, nl, lane);
+    rerank_rows<LV_F32>(ix, job.q, id2, s2, nl, lane);
   wave_sync();
   for (int j = lane; j < nl; j += 64) id2[j] &= kIdMask;
   wave_sync();
@@ -811,9 +840,10 @@ IndexView make_view(const lv_index *ix) {
   v.mu = d.mu;
   v.sec = static_cast<const unsigned char *>(d.secondaries);
   v.D = d.D;
-  v.sec_row_bytes = d.D * (d.sec_dtype == LV_F16 ? 2 : 4);
+  v.sec_row_bytes = lv_secondary_row_bytes(d.D, d.sec_dtype);
   v.sec_packets = ix->sec_packets;
-  v.sec_f16 = d.sec_dtype == LV_F16 ? 1 : 0;
+  v.sec_kind = d.sec_dtype;
+  v.sec_mu = d.sec_mu;
   v.adj = d.adjacency;
   v.R = d.R;
   v.entry = d.entry;

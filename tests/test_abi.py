@@ -56,6 +56,22 @@ def test_index_descriptor_validation(kw, code):
     assert lv.load().lv_last_error()
 
 
+def test_secondary_row_bytes_and_lvq8_descriptor():
+    rb = lv.lv_secondary_row_bytes
+    assert rb(768, lv.LV_F16) == 1536 and rb(256, lv.LV_F32) == 1024
+    assert rb(768, lv.LV_LVQ8) == 784 and rb(1008, lv.LV_LVQ8) == 1024
+    assert rb(1024, lv.LV_LVQ8) == 0 and rb(100, lv.LV_LVQ8) == 0   # > 1008, D % 16
+    assert rb(1032, lv.LV_F16) == 0 and rb(12, lv.LV_F16) == 0      # > 2 KiB, not 16-B rows
+    assert rb(0, lv.LV_F32) == 0 and rb(64, 7) == 0
+    rc, h = _create(_desc(sec_dtype=lv.LV_LVQ8))                     # no sec_mu
+    assert rc == lv.LV_EINVAL and not h.value
+    rc, h = _create(_desc(sec_dtype=lv.LV_LVQ8, sec_mu=FAKE, D=136))  # D % 16 != 0
+    assert rc == lv.LV_EUNSUPPORTED and not h.value
+    rc, h = _create(_desc(sec_dtype=lv.LV_LVQ8, sec_mu=FAKE))
+    assert rc == lv.LV_OK
+    lv.load().lv_index_destroy(h)
+
+
 def test_search_argument_validation_before_launch():
     rc, h = _create(_desc())
     assert rc == lv.LV_OK

@@ -156,6 +156,39 @@ def test_search_parity_lvq4_and_f16(lv, name, N):
         assert np.array_equal(got_cnt, want_cnt)
 
 
+@pytest.mark.parametrize("name,N", [("ood-1m-512", 6000), ("id-1m-768", 6000)])
+def test_search_parity_lvq8_secondaries(lv, name, N):
+    """Re-ranking with LVQ-8 secondary vectors: encoded rows bit-exact, search
+    ids, scores and counters equal to the oracle's (secondary score of the
+    LVQ-8 reconstruction)."""
+    from dataclasses import replace
+
+    wl = gen.WORKLOADS[name].scaled(N=N, m_test=40)
+    c = make_case(wl)
+    D = wl.D
+    smu = c.X.astype(np.float64).mean(axis=0).astype(np.float32)
+    rb = lv.lv_secondary_row_bytes(D, lv.LV_LVQ8)
+    assert rb == D + 16
+    rows = torch.full((wl.N, rb), 0xAB, dtype=torch.uint8, device=DEV)
+    smud = torch.from_numpy(smu).to(DEV)
+    lv.lv_lvq_encode(torch.from_numpy(c.X).to(DEV), smud, 8, rows)
+    sc_, sd_, sl_ = olvq.encode(c.X, smu, 8)
+    assert np.array_equal(rows.cpu().numpy(), olvq.pack_records(sc_, sd_, sl_, 8, rb))
+    Yd = torch.from_numpy(c.Y).to(DEV)
+    mud = torch.from_numpy(c.mu).to(DEV)
+    rec = torch.empty((wl.N, c.stride), dtype=torch.uint8, device=DEV)
+    lv.lv_lvq_encode(Yd, mud, wl.bits, rec)
+    adj = torch.from_numpy(c.adj.view(np.int32)).to(DEV)
+    index = lv.Index(rec, mud, rows, adj, c.entry, wl.bits, wl.d, sec_mu=smud)
+    oidx = replace(c.oracle_index(), sec=sc_, sec_delta=sd_, sec_lo=sl_, sec_mu=smu)
+    for L in (20, 60):
+        want_ids, want_sc, want_cnt = osearch.search_many(oidx, c.Q, c.Qp, wl.k, L)
+        got_ids, got_sc, got_cnt = run_projected(lv, index, c, wl.k, L, hash_slots=8192)
+        assert_parity(c, oidx, got_ids, got_sc, want_ids, want_sc)
+        assert np.array_equal(got_cnt, want_cnt)
+    index.close()
+
+
 def test_full_path_recall_matches_oracle(lv, small):
     # end to end: GPU projection (bfloat16) + search vs oracle float64 projection
     index, _ = gpu_index(lv, small)

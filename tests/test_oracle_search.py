@@ -123,3 +123,51 @@ def test_recall_reasonable_on_tiny(tiny):
     X64 = idx.sec.astype(np.float32)
     truth = exact.ground_truth(Q, X64, wl.k)
     assert exact.recall_at_k(ids, truth, wl.k) >= 0.8
+
+
+def _lvq8_secondaries(idx, X):
+    """The tiny index with LVQ-8 secondaries (centred on the database mean)."""
+    smu = X.astype(np.float64).mean(axis=0).astype(np.float32)
+    sc, sd, sl = lvq.encode(X, smu, 8)
+    return replace(idx, sec=sc, sec_delta=sd, sec_lo=sl, sec_mu=smu), smu
+
+
+def test_lvq8_secondaries_full_window_equals_brute_force(tiny):
+    """With L >= N, the re-rank over LVQ-8 secondaries returns the exact top-k of
+    <q, x^> over the reconstructed vectors (brute force with a full sort)."""
+    wl, idx, Q, Qp = tiny
+    X = idx.sec.astype(np.float32)
+    idx8, smu = _lvq8_secondaries(idx, X)
+    xhat = lvq.decode(idx8.sec, idx8.sec_delta, idx8.sec_lo, smu)
+    S = xhat.astype(np.float64) @ Q.astype(np.float64).T
+    for i in range(3):
+        ids, sc = search.search_one(idx8, Q[i], Qp[i], wl.k, idx8.N)
+        order = np.argsort(-S[:, i], kind="stable")[:wl.k]
+        assert ids.tolist() == order.tolist()
+        assert np.allclose(sc, S[order, i], rtol=0, atol=1e-12)
+
+
+def test_lvq8_secondary_score_within_half_step_bound(tiny):
+    """|<q, x^> - <q, x>| <= sum_j |q_j| (delta/2 + float32 rounding of lo), the
+    per-component half-step bound of the quantiser."""
+    wl, idx, Q, Qp = tiny
+    X = idx.sec.astype(np.float32)
+    idx8, smu = _lvq8_secondaries(idx, X)
+    ids = np.arange(200)
+    q64 = Q[0].astype(np.float64)
+    got = search.secondary_scores(idx8, q64, ids)
+    exact_s = X[ids].astype(np.float64) @ q64
+    r = X[ids].astype(np.float64) - smu.astype(np.float64)
+    slack = (idx8.sec_delta[ids].astype(np.float64) / 2
+             + np.abs(idx8.sec_lo[ids].astype(np.float64) - r.min(axis=1))
+             + 4 * np.finfo(np.float32).eps * np.abs(r).max(axis=1))
+    assert (np.abs(got - exact_s) <= slack * np.abs(q64).sum() + 1e-12).all()
+
+
+def test_lvq8_secondaries_parallel_matches_serial(tiny):
+    wl, idx, Q, Qp = tiny
+    idx8, _ = _lvq8_secondaries(idx, idx.sec.astype(np.float32))
+    a = search.search_many(idx8, Q, Qp, wl.k, 24, procs=1)
+    b = search.search_many(idx8, Q, Qp, wl.k, 24, procs=2, chunk=3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
