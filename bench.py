@@ -48,7 +48,10 @@ def parse():
     ap.add_argument("--workload", default="id-1m-768")
     ap.add_argument("--n", type=int, default=0, help="override database size (testing)")
     ap.add_argument("--target", type=float, default=0.90)
-    ap.add_argument("--hash-slots", type=int, default=0)
+    ap.add_argument("--hash-slots", type=int, default=0,
+                    help="visited-set slots (with --launch, skips the knob search)")
+    ap.add_argument("--launch", choices=("per_query", "persistent"), default="per_query",
+                    help="batched traversal launch when --hash-slots is given")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sec", choices=("f16", "lvq8"), default="f16",
                     help="secondary vectors: float16 (the benchmark configuration) or LVQ-8 "
@@ -121,10 +124,10 @@ def recall(ids, truth, k):
     return hit / (k * len(truth))
 
 
-def profile_traffic(kernel_src, L, slots):
+def profile_traffic(kernel_src, L, slots, launch):
     """HBM bytes per launch from committed counter runs, if the kernel is unchanged and
     the counters were taken at this window and visited-set size."""
-    p = os.path.join(ROOT, "profiles", "persistent_kernel_id-1m-768_counters.md")
+    p = os.path.join(ROOT, "profiles", "batched_kernel_id-1m-768_counters.md")
     if not os.path.exists(p):
         return None
     sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
@@ -134,7 +137,7 @@ def profile_traffic(kernel_src, L, slots):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip()
     if (vals.get("kernel_source_sha256") != sha or vals.get("window_L") != str(L)
-            or vals.get("visited_slots") != str(slots)):
+            or vals.get("visited_slots") != str(slots) or vals.get("launch") != launch):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -343,13 +346,18 @@ def main():
     ids_flat, scores_flat = ids.view(-1), scores.view(-1)
     if args.hash_slots:
         hs = args.hash_slots
+        launch = lv.LV_LAUNCH_PERSISTENT if args.launch == "persistent" else lv.LV_LAUNCH_PER_QUERY
+        how = "given"
     else:
         knobs, _ = lv.lv_autotune_knobs(multi, nreq, m, L_star, reqs, Qd, ids_flat, scores_flat,
                                         reps=2)
-        hs = knobs["hash_slots"]
+        hs, launch = knobs["hash_slots"], knobs["launch"]
+        how = "chosen by the autotuner"
+    launch_name = "persistent" if launch == lv.LV_LAUNCH_PERSISTENT else "per_query"
     knob_hs[0] = hs
-    batch = lv.Batch(multi, max_requests=nreq, max_queries=m, max_L=L_star, hash_slots=hs)
-    log(f"batched step captured (visited-set slots {hs} chosen by the autotuner)")
+    batch = lv.Batch(multi, max_requests=nreq, max_queries=m, max_L=L_star, hash_slots=hs,
+                     launch=launch)
+    log(f"batched step captured (visited-set slots {hs}, {launch_name} launch, {how})")
 
     def step_batched(ev=None):
         batch.step(reqs, Qd, ids_flat, scores_flat, events=ev)
@@ -402,22 +410,25 @@ def main():
     serial_qps = m * args.steps / (total_ms / 1e3)
     kernel_ms = sum(a_.elapsed_time(b_) for a_, b_ in trav) / args.steps
 
-    # batched, pipelined: consecutive steps alternate between two streams (and two
-    # output buffers), so a step's wavefronts start while the previous step's
-    # slowest queries finish; the timed region still spans exactly K whole steps
-    s_alt = torch.cuda.Stream()
-    outs = [(ids_flat, scores_flat), (torch.empty_like(ids_flat), torch.empty_like(scores_flat))]
-    strs = [stream, s_alt]
+    # batched, pipelined: consecutive steps rotate over three streams (and three
+    # output buffers), so a step's wavefronts start while earlier steps' slowest
+    # queries finish; the timed region still spans exactly K whole steps
+    IN_FLIGHT = 3
+    strs = [stream] + [torch.cuda.Stream() for _ in range(IN_FLIGHT - 1)]
+    outs = [(ids_flat, scores_flat)] + [(torch.empty_like(ids_flat), torch.empty_like(scores_flat))
+                                        for _ in range(IN_FLIGHT - 1)]
 
     def run_pipelined(n, evs=None):
         for i_ in range(n):
-            o_ = outs[i_ % 2]
-            batch.step(reqs, Qd, o_[0], o_[1], stream=strs[i_ % 2],
+            o_ = outs[i_ % IN_FLIGHT]
+            batch.step(reqs, Qd, o_[0], o_[1], stream=strs[i_ % IN_FLIGHT],
                        events=None if evs is None else evs[i_])
 
-    s_alt.wait_stream(stream)
-    run_pipelined(max(2, args.warmup))
-    stream.wait_stream(s_alt)
+    for s_ in strs[1:]:
+        s_.wait_stream(stream)
+    run_pipelined(max(IN_FLIGHT, args.warmup))
+    for s_ in strs[1:]:
+        stream.wait_stream(s_)
     torch.cuda.synchronize()
     for o_ in outs:
         o_[0].fill_(-1)
@@ -426,19 +437,21 @@ def main():
     p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     wall_p0 = time.perf_counter()
     p0.record(stream)
-    s_alt.wait_event(p0)
+    for s_ in strs[1:]:
+        s_.wait_event(p0)
     run_pipelined(args.steps, trav_p)
-    stream.wait_stream(s_alt)
+    for s_ in strs[1:]:
+        stream.wait_stream(s_)
     p1.record(stream)
     torch.cuda.synchronize()
     wall_p = time.perf_counter() - wall_p0
     total_p_ms = p0.elapsed_time(p1)
     qps = m * args.steps / (total_p_ms / 1e3)
     ms_per_step = total_p_ms / args.steps
-    for o_ in outs[: min(2, args.steps)]:
+    for o_ in outs[: min(IN_FLIGHT, args.steps)]:
         got_p = o_[0].view(m, k).cpu().numpy().view(np.uint32).astype(np.int64)
         assert np.array_equal(got_p, got), "pipelined steps differ from serial steps"
-    # effective launch duration with two launches in flight: span of the K traversals / K
+    # effective launch duration with several launches in flight: span of the K traversals / K
     span_ms = trav_p[0][0].elapsed_time(trav_p[-1][1])
     launch_eff_ms = span_ms / args.steps
     achieved = alg_bytes_total / (launch_eff_ms / 1e3) / 1e9
@@ -446,7 +459,7 @@ def main():
     beam_launch_ms = beam_ms / (args.steps * nreq)
     achieved_plain = (alg_bytes_total / nreq) / (beam_launch_ms / 1e3) / 1e9
     traffic = profile_traffic(os.path.join(ROOT, "paper_2312_16335_amd", "csrc", "lv_search.hip"),
-                              L_star, hs) if smud is None else None
+                              L_star, hs, launch_name) if smud is None else None
     batch.close()
     multi.close()
 
@@ -487,8 +500,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "N": wl.N, "D": wl.D, "d": wl.d, "lvq_bits": wl.bits,
                    "secondary": args.sec, "R": wl.R, "k": k, "queries": m, "L": L_star,
-                   "requests": nreq, "mode": "batched, 2 steps in flight",
-                   "visited_slots": hs},
+                   "requests": nreq, "mode": "batched, 3 steps in flight",
+                   "visited_slots": hs, "launch": launch_name},
         "recall_at_L": rec_star,
         "plain": {"qps": plain_qps, "recall": rec_plain, "ms_per_step": plain_ms / args.steps,
                   "traversal_kernel_GBs": achieved_plain,
@@ -514,9 +527,9 @@ def main():
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled)",
                      "alg_bytes_per_launch": alg_bytes_total, "launch_ms": launch_eff_ms,
                      "launch_ms_alone": kernel_ms,
-                     "kernel": "persistent_kernel (traversal + re-rank), one launch per step; "
+                     "kernel": "batched_kernel (traversal + re-rank), one launch per step; "
                                "launch_ms = (last traversal end - first traversal start) / K "
-                               "with two steps in flight, from HIP events around the "
+                               "with three steps in flight, from HIP events around the "
                                "traversal graphs on their launch streams"},
         "index_build": {"db_projection_ms": db_proj_ms, "graph_build_s": g.get("graph_s"),
                         "graph_build_threads": int(os.environ.get("OMP_NUM_THREADS") or

@@ -254,7 +254,12 @@ typedef struct {
   int32_t hash_slots; /* visited-set slots per query (power of 2, 256..65536; 0 = 1024) */
   int32_t probes;     /* slots tried before an id replaces the one in its home slot
                          (1..16; 0 = 2 below 4096 slots, 8 from 4096 slots) */
+  int32_t launch;     /* batched traversal only: LV_LAUNCH_PER_QUERY (0, one workgroup
+                         per query, scheduled by the hardware) or LV_LAUNCH_PERSISTENT
+                         (1, resident wavefronts pull queries from a device counter) */
 } lv_search_params;
+#define LV_LAUNCH_PER_QUERY 0
+#define LV_LAUNCH_PERSISTENT 1
 
 /* Bytes of device workspace lv_search needs for m queries. */
 size_t lv_search_workspace_size(const lv_index *index, int64_t m);
@@ -340,12 +345,12 @@ int lv_batch_destroy(lv_batch *batch);
 /*
  * Run one step on `stream`: validate and pack the requests on the host,
  * then launch the two captured graphs (table copy + grouped projection,
- * then counter reset + persistent traversal).  Asynchronous.  Steps use two
- * alternating sets of pinned table and device state; a set is reused two
+ * then counter reset + persistent traversal).  Asynchronous.  Steps rotate
+ * through three sets of pinned table and device state; a set is reused three
  * steps later, once the step that used it has finished (the host waits for
- * its table copy, `stream` waits for its traversal).  Two consecutive steps
- * issued on different streams therefore run concurrently; their output
- * buffers must then be distinct.
+ * its table copy, `stream` waits for its traversal).  Up to three
+ * consecutive steps issued on different streams therefore run concurrently;
+ * their output buffers must then be distinct.
  *   Q:        device float32 [sum count][D]
  *   ids:      device uint32 [sum count * k] out; scores: device float32, same
  *   counters: device uint32 [sum count][2] out (expansions, scorings) or NULL
@@ -382,10 +387,14 @@ int lv_autotune_window(lv_multi *multi, int32_t sub, const float *Q, int64_t m,
                        double *recall_out, void *stream);
 
 /*
- * Autotuner, performance part: times `reps` steps of the given requests for
- * each visited-set size in {1024, 2048, 4096, 8192} that fits, and returns
- * the fastest in best (these knobs never change results).  best_ms gets the
- * mean step time.  Synchronises `stream`.
+ * Autotuner, performance part: for each visited-set size in {1024, 2048,
+ * 4096, 8192} that fits, times `reps` rounds of three steps of the given
+ * requests in flight at once (on internal streams, the way consecutive steps
+ * overlap in service) with the per-query launch, and returns the fastest in
+ * best (these knobs never change results).  The persistent launch is not
+ * searched: with steps in flight its resident wavefronts hold the compute
+ * units that the next step's query projection needs.  best_ms gets the mean
+ * time per step.  ids/scores receive one step's output.  Synchronises `stream`.
  */
 int lv_autotune_knobs(lv_multi *multi, const lv_batch_caps *caps, const lv_request *reqs,
                       int32_t nreq, const float *Q, uint32_t *ids, float *scores, int32_t reps,

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "liblv.so")
 LV_OK, LV_WNOTCONVERGED = 0, 1
 LV_EINVAL, LV_ENOMEM, LV_EDEVICE, LV_EUNSUPPORTED = -1, -2, -3, -4
 LV_F32, LV_F16, LV_LVQ8 = 0, 1, 2
+LV_LAUNCH_PER_QUERY, LV_LAUNCH_PERSISTENT = 0, 1
 LV_SENTINEL = 0xFFFFFFFF
 LV_FW_INIT_ES, LV_FW_INIT_ZERO, LV_FW_INIT_GIVEN = 0, 1, 2
 
@@ -40,7 +41,7 @@ class IndexDesc(ctypes.Structure):
 
 
 class SearchParams(ctypes.Structure):
-    _fields_ = [("hash_slots", _c_i32), ("probes", _c_i32)]
+    _fields_ = [("hash_slots", _c_i32), ("probes", _c_i32), ("launch", _c_i32)]
 
 
 class Request(ctypes.Structure):
@@ -321,8 +322,8 @@ class Index:
             pass
 
 
-def _params(hash_slots: int = 0, probes: int = 0):
-    return ctypes.byref(SearchParams(hash_slots, probes))
+def _params(hash_slots: int = 0, probes: int = 0, launch: int = 0):
+    return ctypes.byref(SearchParams(hash_slots, probes, launch))
 
 
 def lv_search_workspace_size(index: Index, m: int) -> int:
@@ -387,12 +388,12 @@ class Batch:
     """Captured batched step (lv_batch_create)."""
 
     def __init__(self, multi: Multi, max_requests: int, max_queries: int, max_L: int,
-                 hash_slots: int = 0, probes: int = 0):
+                 hash_slots: int = 0, probes: int = 0, launch: int = LV_LAUNCH_PER_QUERY):
         self.multi = multi
         self.caps = BatchCaps(max_requests, max_L, max_queries)
         h = _vp()
         _check(load().lv_batch_create(multi.handle, ctypes.byref(self.caps),
-                                      _params(hash_slots, probes), ctypes.byref(h)))
+                                      _params(hash_slots, probes, launch), ctypes.byref(h)))
         self.handle = h
 
     def step(self, reqs, Q, ids, scores, counters=None, stream=None, events=None):
@@ -445,13 +446,13 @@ def lv_autotune_knobs(multi: Multi, max_requests, max_queries, max_L, reqs, Q, i
     import torch
 
     caps = BatchCaps(max_requests, max_L, max_queries)
-    best = SearchParams(0, 0)
+    best = SearchParams(0, 0, 0)
     ms = ctypes.c_double(0.0)
     _check(load().lv_autotune_knobs(multi.handle, ctypes.byref(caps), _requests(reqs), len(reqs),
                                     _dev(Q, torch.float32), _dev(ids, torch.int32),
                                     _dev(scores, torch.float32), reps, ctypes.byref(best),
                                     ctypes.byref(ms), _stream(stream)))
-    return {"hash_slots": best.hash_slots, "probes": best.probes}, ms.value
+    return {"hash_slots": best.hash_slots, "probes": best.probes, "launch": best.launch}, ms.value
 
 
 # ------------------------------------------------- differentiable projection

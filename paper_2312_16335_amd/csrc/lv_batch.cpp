@@ -3,15 +3,15 @@
 //
 // A step is two graph launches on the caller's stream: pre[i] (copy of the
 // pinned request table i, grouped query projection) and trav[i] (counter
-// reset, persistent traversal).  The split lets a caller bracket the
-// traversal alone with its own timing events.
+// reset if persistent, then the search kernel).  The split lets a caller
+// bracket the search alone with its own timing events.
 //
-// Steps alternate between two sets of device state (request table, work
-// counter, projected queries), so two consecutive steps may run at once when
-// the caller issues them on different streams: the next step's wavefronts
-// then fill the compute units that the slowest queries of the previous step
-// leave idle.  A set is reused two steps later, after the step that last used
-// it has finished (its stream is made to wait for that).
+// Steps rotate through kSets sets of device state (request table, work
+// counter, projected queries), so up to kSets consecutive steps may run at
+// once when the caller issues them on different streams: later steps'
+// wavefronts then fill the compute units that the slowest queries of earlier
+// steps leave idle.  A set is reused kSets steps later, after the step that
+// last used it has finished (its stream is made to wait for that).
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -25,25 +25,28 @@ struct lv_multi {
   int bits = 0, group = 0, vbytes = 0, D = 0, d = 0;
 };
 
+constexpr int kSets = 3;
+
 struct lv_batch {
   lv_multi *multi = nullptr;
   lv_batch_caps caps{};
   lv::VisitedCfg vc{};
+  int launch = LV_LAUNCH_PER_QUERY;
   int grid = 0;
   int max_tiles = 0;
   size_t table_bytes = 0;
   // per step parity
-  unsigned char *d_table[2] = {nullptr, nullptr};  // StepHeader + Request[max_requests]
-  unsigned char *h_table[2] = {nullptr, nullptr};  // pinned
-  unsigned int *d_counter[2] = {nullptr, nullptr};
-  float *d_qp[2] = {nullptr, nullptr};
-  hipGraph_t pre_graph[2] = {nullptr, nullptr};
-  hipGraphExec_t pre_exec[2] = {nullptr, nullptr};
-  hipGraph_t trav_graph[2] = {nullptr, nullptr};
-  hipGraphExec_t trav_exec[2] = {nullptr, nullptr};
-  hipEvent_t copied[2] = {nullptr, nullptr};  // pinned table i consumed
-  hipEvent_t done[2] = {nullptr, nullptr};    // step on set i finished
-  bool used[2] = {false, false};
+  unsigned char *d_table[kSets] = {};  // StepHeader + Request[max_requests]
+  unsigned char *h_table[kSets] = {};  // pinned
+  unsigned int *d_counter[kSets] = {};
+  float *d_qp[kSets] = {};
+  hipGraph_t pre_graph[kSets] = {};
+  hipGraphExec_t pre_exec[kSets] = {};
+  hipGraph_t trav_graph[kSets] = {};
+  hipGraphExec_t trav_exec[kSets] = {};
+  hipEvent_t copied[kSets] = {};  // pinned table i consumed
+  hipEvent_t done[kSets] = {};    // step on set i finished
+  bool used[kSets] = {};
   hipStream_t capture = nullptr;
   int next = 0;
 };
@@ -52,7 +55,7 @@ namespace {
 
 void free_batch(lv_batch *b) {
   if (!b) return;
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < kSets; ++i) {
     if (b->done[i]) {
       (void)hipEventSynchronize(b->done[i]);
       (void)hipEventDestroy(b->done[i]);
@@ -148,8 +151,11 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
   lv::VisitedCfg vc{};
   int rc = lv::visited_config(params, &vc);
   if (rc != LV_OK) return rc;
+  const int launch = params ? params->launch : LV_LAUNCH_PER_QUERY;
+  if (launch != LV_LAUNCH_PER_QUERY && launch != LV_LAUNCH_PERSISTENT)
+    LV_FAIL(LV_EINVAL, "launch must be LV_LAUNCH_PER_QUERY or LV_LAUNCH_PERSISTENT");
   int blocks = 0;
-  rc = lv::persistent_occupancy(multi->bits, multi->group, multi->vbytes, caps->max_L, vc.log2h,
+  rc = lv::batched_occupancy(multi->bits, multi->group, multi->vbytes, caps->max_L, vc.log2h,
                                 &blocks);
   if (rc != LV_OK) return rc;
   if (blocks < 1) LV_FAIL(LV_EUNSUPPORTED, "the persistent kernel does not fit on a compute unit");
@@ -162,10 +168,11 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
   b->multi = multi;
   b->caps = *caps;
   b->vc = vc;
+  b->launch = launch;
   b->grid = blocks * cus;
   b->max_tiles = (int)((caps->max_queries + 31) / 32) + caps->max_requests;
   b->table_bytes = sizeof(lv::StepHeader) + sizeof(lv::Request) * (size_t)caps->max_requests;
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < kSets; ++i) {
     LV_BATCH_TRY(hipMalloc(&b->d_table[i], b->table_bytes));
     LV_BATCH_TRY(hipMalloc(&b->d_counter[i], sizeof(unsigned int)));
     LV_BATCH_TRY(hipMalloc(&b->d_qp[i], sizeof(float) * (size_t)caps->max_queries * multi->d));
@@ -176,7 +183,7 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
     LV_BATCH_TRY(hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming));
   }
   LV_BATCH_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < kSets; ++i) {
     const lv::StepHeader *hdr = reinterpret_cast<const lv::StepHeader *>(b->d_table[i]);
     LV_BATCH_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed));
     hipError_t e1 = hipMemcpyAsync(b->d_table[i], b->h_table[i], b->table_bytes,
@@ -193,8 +200,12 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
     }
     LV_BATCH_TRY(hipGraphInstantiate(&b->pre_exec[i], b->pre_graph[i], nullptr, nullptr, 0));
     LV_BATCH_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed));
-    int r2 = lv::launch_persistent(multi->bits, multi->group, multi->vbytes, hdr, multi->d_views,
-                                   b->d_counter[i], caps->max_L, vc, b->grid, b->capture);
+    // per query: one workgroup per query slot of the step (slots past the
+    // step's queries exit at once); persistent: resident wavefronts and a counter
+    const bool pq = launch == LV_LAUNCH_PER_QUERY;
+    int r2 = lv::launch_batched(multi->bits, multi->group, multi->vbytes, hdr, multi->d_views,
+                                   pq ? nullptr : b->d_counter[i], caps->max_L, vc,
+                                   pq ? (int)caps->max_queries : b->grid, b->capture);
     hipError_t e3 = hipStreamEndCapture(b->capture, &b->trav_graph[i]);
     if (r2 != LV_OK || e3 != hipSuccess) {
       if (r2 == LV_OK) lv::set_error("graph capture failed");
@@ -279,7 +290,7 @@ int batch_step(lv_batch *b, const lv_request *reqs, int32_t nreq, const float *Q
   if (ev_end) LV_CHECK_HIP(hipEventRecord(ev_end, s));
   LV_CHECK_HIP(hipEventRecord(b->done[i], s));
   b->used[i] = true;
-  b->next ^= 1;
+  b->next = (b->next + 1) % kSets;
   return LV_OK;
 }
 
@@ -399,45 +410,91 @@ extern "C" int lv_autotune_knobs(lv_multi *multi, const lv_batch_caps *caps,
                                  double *best_ms, void *stream) {
   lv::clear_error();
   if (!multi || !caps || !reqs || !best || reps < 1) LV_FAIL(LV_EINVAL, "bad arguments");
+  if (nreq < 1 || nreq > caps->max_requests) LV_FAIL(LV_EINVAL, "bad request count");
+  int64_t nout = 0;
+  for (int i = 0; i < nreq; ++i) nout += (int64_t)reqs[i].count * reqs[i].k;
+  constexpr int kFlight = 3;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipEvent_t e0, e1;
-  LV_CHECK_HIP(hipEventCreate(&e0));
-  LV_CHECK_HIP(hipEventCreate(&e1));
+  hipStream_t st[kFlight] = {s, nullptr, nullptr};
+  uint32_t *xids[kFlight] = {ids, nullptr, nullptr};
+  float *xsc[kFlight] = {scores, nullptr, nullptr};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    for (int f = 1; f < kFlight; ++f) {
+      if (st[f]) (void)hipStreamDestroy(st[f]);
+      if (xids[f]) (void)hipFree(xids[f]);
+      if (xsc[f]) (void)hipFree(xsc[f]);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  for (int f = 1; f < kFlight && ok; ++f)
+    ok = hipStreamCreateWithFlags(&st[f], hipStreamNonBlocking) == hipSuccess &&
+         hipMalloc(&xids[f], sizeof(uint32_t) * (size_t)(nout > 0 ? nout : 1)) == hipSuccess &&
+         hipMalloc(&xsc[f], sizeof(float) * (size_t)(nout > 0 ? nout : 1)) == hipSuccess;
+  if (!ok) {
+    cleanup();
+    LV_FAIL(LV_ENOMEM, "autotune streams or buffers");
+  }
   double best_t = -1.0;
-  lv_search_params keep{0, 0};
+  lv_search_params keep{0, 0, 0};
   int last_rc = LV_OK;
-  for (int hs : {1024, 2048, 4096, 8192}) {
-    lv_search_params p{hs, 0};
-    lv_batch *b = nullptr;
-    int rc = lv_batch_create(multi, caps, &p, &b);
-    if (rc != LV_OK) {
-      last_rc = rc;
-      continue;  // e.g. does not fit in LDS
-    }
-    rc = lv_batch_step(b, reqs, nreq, Q, ids, scores, nullptr, stream);  // warm-up
-    if (rc == LV_OK) (void)hipEventRecord(e0, s);
-    for (int r = 0; r < reps && rc == LV_OK; ++r)
-      rc = lv_batch_step(b, reqs, nreq, Q, ids, scores, nullptr, stream);
-    float ms = 0.f;
-    if (rc == LV_OK) {
-      (void)hipEventRecord(e1, s);
-      (void)hipEventSynchronize(e1);
-      (void)hipEventElapsedTime(&ms, e0, e1);
-    }
-    lv_batch_destroy(b);
-    if (rc != LV_OK) {
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      return rc;
-    }
-    const double t = ms / reps;
-    if (best_t < 0 || t < best_t) {
-      best_t = t;
-      keep = p;
+  // The persistent launch is not searched: with steps in flight its resident
+  // wavefronts keep the next step's query projection waiting for compute
+  // units, which stalls the pipeline (and it is not faster on its own).
+  for (int launch : {LV_LAUNCH_PER_QUERY}) {
+    for (int hs : {1024, 2048, 4096, 8192}) {
+      lv_search_params p{hs, 0, launch};
+      lv_batch *b = nullptr;
+      int rc = lv_batch_create(multi, caps, &p, &b);
+      if (rc != LV_OK) {
+        last_rc = rc;
+        continue;  // e.g. does not fit in LDS
+      }
+      // f-th step of a round on stream f; streams 1.. start after `s` reaches e0
+      auto round = [&]() -> int {
+        for (int f = 0; f < kFlight; ++f) {
+          int r = lv_batch_step(b, reqs, nreq, Q, xids[f], xsc[f], nullptr, st[f]);
+          if (r != LV_OK) return r;
+        }
+        return LV_OK;
+      };
+      auto fork = [&]() {
+        (void)hipEventRecord(e0, s);
+        for (int f = 1; f < kFlight; ++f) (void)hipStreamWaitEvent(st[f], e0, 0);
+      };
+      auto join = [&]() {
+        for (int f = 1; f < kFlight; ++f) {
+          (void)hipEventRecord(e1, st[f]);
+          (void)hipStreamWaitEvent(s, e1, 0);
+        }
+      };
+      fork();
+      rc = round();  // warm-up
+      join();
+      float ms = 0.f;
+      if (rc == LV_OK) {
+        fork();
+        for (int r = 0; r < reps && rc == LV_OK; ++r) rc = round();
+        join();
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+      }
+      lv_batch_destroy(b);
+      if (rc != LV_OK) {
+        cleanup();
+        return rc;
+      }
+      const double t = ms / (reps * kFlight);
+      if (best_t < 0 || t < best_t) {
+        best_t = t;
+        keep = p;
+      }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  cleanup();
   if (best_t < 0) return last_rc != LV_OK ? last_rc : LV_EDEVICE;
   *best = keep;
   if (best_ms) *best_ms = best_t;

@@ -65,10 +65,10 @@ struct VisitedCfg {
 int visited_config(const lv_search_params *params, VisitedCfg *cfg);
 size_t beam_lds_bytes(int L, int log2h);
 int check_lds(size_t lds, int L, int log2h);
-int launch_persistent(int bits, int group, int vbytes, const StepHeader *hdr,
+int launch_batched(int bits, int group, int vbytes, const StepHeader *hdr,
                       const IndexView *subs, unsigned int *counter, int Lmax, VisitedCfg vc,
                       int grid, hipStream_t stream);
-int persistent_occupancy(int bits, int group, int vbytes, int Lmax, int log2h, int *blocks);
+int batched_occupancy(int bits, int group, int vbytes, int Lmax, int log2h, int *blocks);
 int launch_project_grouped(const StepHeader *hdr, const IndexView *subs, int max_tiles, int d,
                            int D, hipStream_t stream);
 

@@ -33,8 +33,9 @@
 // order equal to a float64 reference except at exact ties.
 //
 // Two kernels share the per-query body: a plain launch with one workgroup
-// per query, and a persistent launch whose wavefronts pull queries of many
-// requests (each with its own sub-index, k and L) from a device counter.
+// per query of one request, and a batched launch over the queries of many
+// requests (each with its own sub-index, k and L), either one workgroup per
+// query or resident wavefronts pulling queries from a device counter.
 #include "lv_common.h"
 #include "lv_search.h"
 
@@ -704,18 +705,20 @@ __global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
   search_query<BITS, G, V>(a.ix, job, sm, a.hash_log2, a.probes, threadIdx.x);
 }
 
-// Persistent form: wavefronts take queries from a device counter until the
-// step's queries run out.  Requests are sorted by q_begin; a query finds its
-// request by binary search.
+// Batched form over a step's request table.  With a counter (persistent
+// launch), resident wavefronts take queries from it until the step's queries
+// run out; without one, workgroup b searches query b once (one workgroup per
+// query slot, scheduled by the hardware).  Requests are sorted by q_begin; a
+// query finds its request by binary search.
 // Waves per SIMD the register allocation aims at: 5 (at most 102 VGPRs)
 // for 8-bit records, 4 for 4-bit records, whose lanes hold twice as many
 // projected-query components.
 template <int BITS, int V>
-constexpr int persistent_waves() { return BITS == 8 ? 5 : 4; }
+constexpr int batched_waves() { return BITS == 8 ? 5 : 4; }
 
 template <int BITS, int G, int V>
 __global__ __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu(persistent_waves<BITS, V>()))) void persistent_kernel(
+__attribute__((amdgpu_waves_per_eu(batched_waves<BITS, V>()))) void batched_kernel(
     const StepHeader *__restrict__ hdr, const IndexView *__restrict__ subs,
     unsigned int *__restrict__ counter, int32_t Lmax, int32_t hash_log2, int32_t probes) {
   const int lane = threadIdx.x;
@@ -723,9 +726,15 @@ __attribute__((amdgpu_waves_per_eu(persistent_waves<BITS, V>()))) void persisten
   const int64_t nq = hdr->nq;
   const int32_t nreq = hdr->nreq;
   const Request *req = reinterpret_cast<const Request *>(hdr + 1);
+  unsigned int own = blockIdx.x;  // without a counter: this block's query, once
   for (;;) {
     unsigned int u = 0;
-    if (lane == 0) u = atomicAdd(counter, 1u);
+    if (counter) {
+      if (lane == 0) u = atomicAdd(counter, 1u);
+    } else {
+      u = own;
+      own = 0xFFFFFFFFu;
+    }
     // wave-uniform from here on, so request and index fields live in SGPRs
     u = __builtin_amdgcn_readfirstlane(__shfl(u, 0, 64));
     if ((int64_t)u >= nq) break;
@@ -740,6 +749,11 @@ __attribute__((amdgpu_waves_per_eu(persistent_waves<BITS, V>()))) void persisten
     const Request r = req[lo];
     const IndexView ix = subs[r.sub];
     const int64_t j = (int64_t)u - r.q_begin;
+    // An opaque copy of the lane id: lane-dependent constants of the search
+    // are then recomputed per query instead of being hoisted out of this
+    // loop, where they would stay live (and spill) for the kernel's lifetime.
+    int lane_q = lane;
+    asm volatile("" : "+v"(lane_q));
     Job job;
     job.q = hdr->Q + (int64_t)u * ix.D;
     job.qp = hdr->Qp + (int64_t)u * hdr->qp_stride;
@@ -748,11 +762,6 @@ __attribute__((amdgpu_waves_per_eu(persistent_waves<BITS, V>()))) void persisten
     job.ids = hdr->ids + r.out_off + j * r.k;
     job.scores = hdr->scores + r.out_off + j * r.k;
     job.counters = hdr->counters ? hdr->counters + 2 * (int64_t)u : nullptr;
-    // An opaque copy of the lane id: lane-dependent constants of the search
-    // are then recomputed per query instead of being hoisted out of this
-    // loop, where they would stay live (and spill) for the kernel's lifetime.
-    int lane_q = lane;
-    asm volatile("" : "+v"(lane_q));
     search_query<BITS, G, V>(ix, job, sm, hash_log2, probes, lane_q);
   }
 }
@@ -767,10 +776,10 @@ int launch_plain_t(const PlainArgs &a, size_t lds, hipStream_t s) {
 }
 
 template <int BITS, int G, int V>
-int launch_persistent_t(const StepHeader *hdr, const IndexView *subs, unsigned int *counter,
+int launch_batched_t(const StepHeader *hdr, const IndexView *subs, unsigned int *counter,
                         int Lmax, VisitedCfg vc, size_t lds, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
-  hipLaunchKernelGGL((persistent_kernel<BITS, G, V>), dim3(grid), dim3(64), lds, s, hdr, subs,
+  if (counter) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  hipLaunchKernelGGL((batched_kernel<BITS, G, V>), dim3(grid), dim3(64), lds, s, hdr, subs,
                      counter, Lmax, vc.log2h, vc.probes);
   LV_CHECK_LAUNCH();
   return LV_OK;
@@ -779,7 +788,7 @@ int launch_persistent_t(const StepHeader *hdr, const IndexView *subs, unsigned i
 template <int BITS, int G, int V>
 int occupancy_t(size_t lds, int *blocks) {
   LV_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks, reinterpret_cast<const void *>(persistent_kernel<BITS, G, V>), 64, lds));
+      blocks, reinterpret_cast<const void *>(batched_kernel<BITS, G, V>), 64, lds));
   return LV_OK;
 }
 
@@ -806,7 +815,7 @@ struct PlainLaunch {
   int operator()() { return launch_plain_t<B, GG, VV>(a, lds, s); }
 };
 
-struct PersistentLaunch {
+struct BatchedLaunch {
   const StepHeader *hdr;
   const IndexView *subs;
   unsigned int *counter;
@@ -817,7 +826,7 @@ struct PersistentLaunch {
   hipStream_t s;
   template <int B, int GG, int VV>
   int operator()() {
-    return launch_persistent_t<B, GG, VV>(hdr, subs, counter, Lmax, vc, lds, grid, s);
+    return launch_batched_t<B, GG, VV>(hdr, subs, counter, Lmax, vc, lds, grid, s);
   }
 };
 
@@ -907,15 +916,15 @@ int launch_beam(const lv_index *ix, const float *Q, const float *Qp, int64_t m, 
   return dispatch(ix->desc.bits, ix->group, ix->vbytes, f);
 }
 
-int launch_persistent(int bits, int group, int vbytes, const StepHeader *hdr,
+int launch_batched(int bits, int group, int vbytes, const StepHeader *hdr,
                       const IndexView *subs, unsigned int *counter, int Lmax, VisitedCfg vc,
                       int grid, hipStream_t stream) {
   const size_t lds = beam_lds_bytes(Lmax, vc.log2h);
-  PersistentLaunch f{hdr, subs, counter, Lmax, vc, lds, grid, stream};
+  BatchedLaunch f{hdr, subs, counter, Lmax, vc, lds, grid, stream};
   return dispatch(bits, group, vbytes, f);
 }
 
-int persistent_occupancy(int bits, int group, int vbytes, int Lmax, int log2h, int *blocks) {
+int batched_occupancy(int bits, int group, int vbytes, int Lmax, int log2h, int *blocks) {
   const size_t lds = beam_lds_bytes(Lmax, log2h);
   int rc = check_lds(lds, Lmax, log2h);
   if (rc != LV_OK) return rc;

@@ -76,15 +76,15 @@ def test_search_argument_validation_before_launch():
     rc, h = _create(_desc())
     assert rc == lv.LV_OK
     lib = lv.load()
-    prm = lv.SearchParams(0, 0)
+    prm = lv.SearchParams(0, 0, 0)
     cases = [(10, 0, 50), (10, 5, 3), (10, 5, 2000), (-1, 5, 50), (10, 2000, 3000)]
     for m, k, L in cases:
         rc = lib.lv_search_projected(h, FAKE, FAKE, m, k, L, FAKE, FAKE, None,
                                      ctypes.byref(prm), None)
         assert rc == lv.LV_EINVAL, (m, k, L)
-    for bad in (lv.SearchParams(1000, 0),   # slots not a power of two
-                lv.SearchParams(1024, 17),  # too many probes
-                lv.SearchParams(1024, -1)):
+    for bad in (lv.SearchParams(1000, 0, 0),   # slots not a power of two
+                lv.SearchParams(1024, 17, 0),  # too many probes
+                lv.SearchParams(1024, -1, 0)):
         assert lib.lv_search_projected(h, FAKE, FAKE, 10, 5, 50, FAKE, FAKE, None,
                                        ctypes.byref(bad), None) == lv.LV_EINVAL
     # workspace too small

@@ -89,9 +89,10 @@ def check_against_plain(lv, subs, reqs, Q, ids, sc, cnt):
         o0 += count * k
 
 
-def test_batched_equals_plain_over_consecutive_steps(lv, subs):
+@pytest.mark.parametrize("launch", [0, 1], ids=["per_query", "persistent"])
+def test_batched_equals_plain_over_consecutive_steps(lv, subs, launch):
     multi = lv.Multi([ix for _, ix in subs])
-    batch = lv.Batch(multi, max_requests=16, max_queries=1024, max_L=200)
+    batch = lv.Batch(multi, max_requests=16, max_queries=1024, max_L=200, launch=launch)
     cursor = [0, 0, 0]
     steps = [
         [(0, 10, 40, 1), (1, 1, 20, 33), (2, 100, 128, 70), (0, 10, 60, 5), (1, 10, 40, 64)],
@@ -118,6 +119,8 @@ def test_batch_validation(lv, subs):
     batch.close()
     with pytest.raises(lv.LVError):
         lv.Batch(multi, max_requests=0, max_queries=10, max_L=10)
+    with pytest.raises(lv.LVError):
+        lv.Batch(multi, max_requests=4, max_queries=10, max_L=10, launch=2)
     multi.close()
 
 
@@ -150,6 +153,7 @@ def test_autotune_knobs_returns_a_valid_choice(lv, subs):
     sc = torch.zeros((1500,), dtype=torch.float32, device=DEV)
     best, ms = lv.lv_autotune_knobs(multi, 4, 256, 64, reqs, Q, ids, sc, reps=2)
     assert best["hash_slots"] in (1024, 2048, 4096, 8192) and ms > 0
+    assert best["launch"] in (0, 1)
     multi.close()
 
 
@@ -180,12 +184,13 @@ def test_timed_step_equals_untimed_and_brackets_the_traversal(lv, subs):
     multi.close()
 
 
-def test_consecutive_steps_on_two_streams(lv, subs):
-    """Steps issued alternately on two streams run concurrently on alternating
+@pytest.mark.parametrize("launch", [0, 1], ids=["per_query", "persistent"])
+def test_consecutive_steps_on_several_streams(lv, subs, launch):
+    """Steps issued in turn on three streams run concurrently on rotating
     device state; every step still equals the plain search."""
     multi = lv.Multi([ix for _, ix in subs])
-    batch = lv.Batch(multi, max_requests=4, max_queries=600, max_L=128)
-    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    batch = lv.Batch(multi, max_requests=4, max_queries=600, max_L=128, launch=launch)
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream(), torch.cuda.Stream()]
     cursor = [0, 0, 0]
     plan = [
         [(0, 10, 60, 150), (2, 10, 100, 200)],
@@ -193,9 +198,12 @@ def test_consecutive_steps_on_two_streams(lv, subs):
         [(2, 100, 128, 90), (1, 10, 80, 160)],
         [(0, 10, 50, 60), (2, 5, 20, 300), (1, 10, 30, 7)],
         [(1, 10, 64, 120)],
+        [(2, 10, 90, 64), (0, 10, 30, 33)],
+        [(0, 1, 1, 5), (1, 100, 100, 20)],
     ]
+    # 3 in flight at first; later a device set is reused from another stream
+    order = [0, 1, 2, 1, 2, 0, 1]
     runs = []
-    streams[1].wait_stream(streams[0])
     for i, reqs in enumerate(plan):
         Qs = []
         for sub, k, L, count in reqs:
@@ -207,12 +215,13 @@ def test_consecutive_steps_on_two_streams(lv, subs):
         ids = torch.full((nout,), -7, dtype=torch.int32, device=DEV)
         sc = torch.zeros((nout,), dtype=torch.float32, device=DEV)
         cnt = torch.zeros((len(Q), 2), dtype=torch.int32, device=DEV)
-        st = streams[i % 2]
-        if i % 2:
+        st = streams[order[i]]
+        if st is not streams[0]:
             st.wait_stream(streams[0])  # inputs were made on stream 0
         batch.step(reqs, Q, ids, sc, cnt, stream=st)
         runs.append((reqs, Q, ids, sc, cnt))
-    streams[0].wait_stream(streams[1])
+    for st in streams[1:]:
+        streams[0].wait_stream(st)
     torch.cuda.synchronize()
     for reqs, Q, ids, sc, cnt in runs:
         check_against_plain(lv, subs, reqs, Q, ids, sc, cnt)
