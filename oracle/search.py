@@ -106,20 +106,25 @@ class Trace:
 
 
 def beam(index: Index, qp, L: int, visited_cap: Optional[int] = None,
-         trace: Optional[Trace] = None) -> List[Tuple[float, int]]:
+         trace: Optional[Trace] = None, scorer=None) -> List[Tuple[float, int]]:
     """Best-first traversal; returns the final list as (score, id), best first.
 
     visited_cap bounds the visited set (oldest entries forgotten first).  A
     forgotten node that is met again is scored again and merged only if it
     is not in the list already; the final list is the same as with an exact
     visited set (a node dropped earlier was worse than L others, and the
-    L-th best score never decreases).
+    L-th best score never decreases).  scorer(ids), when given, replaces
+    the primary score (graph construction scores with a distance).
     """
-    qp64 = np.asarray(qp, dtype=np.float32).astype(np.float64)
     tr = trace if trace is not None else Trace()
+    if scorer is None:
+        qp64 = np.asarray(qp, dtype=np.float32).astype(np.float64)
+
+        def scorer(ids):
+            return primary_scores(index, qp64, ids)
     adj = index.adj
     e = int(index.entry)
-    s0 = float(primary_scores(index, qp64, [e])[0])
+    s0 = float(scorer([e])[0])
     keys = [(-s0, e)]          # sorted ascending == score desc, id asc
     in_list = {e}
     expanded = set()
@@ -161,7 +166,7 @@ def beam(index: Index, qp, L: int, visited_cap: Optional[int] = None,
             continue
         tr.n_dist += len(newly)
         tr.n_rescored += len(rescored)
-        sc = primary_scores(index, qp64, newly)
+        sc = scorer(newly)
         for s, n in zip(sc.tolist(), newly):
             if tr.scored is not None:
                 tr.scored[n] = s
