@@ -401,6 +401,58 @@ int lv_autotune_knobs(lv_multi *multi, const lv_batch_caps *caps, const lv_reque
                       lv_search_params *best, double *best_ms, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Graph construction on the primary vectors (device).
+ * ---------------------------------------------------------------------- */
+
+#define LV_MAX_BUILD_PASSES 8
+
+typedef struct {
+  int32_t R;          /* largest out-degree, 1..64 */
+  int32_t L;          /* search window while building, 1..LV_MAX_L (more than R
+                         gives the pruning a choice) */
+  int32_t passes;     /* 1..LV_MAX_BUILD_PASSES */
+  int32_t hash_slots; /* visited-set slots of the construction searches (0: 2048);
+                         the result does not depend on it */
+  double alphas[LV_MAX_BUILD_PASSES]; /* pruning factor of each pass, >= 0 */
+  int64_t max_batch;  /* largest number of nodes inserted together, >= 1 */
+  int64_t stop_after; /* 0: complete build; n > 0: stop after n batches */
+} lv_build_params;
+
+/*
+ * Build a graph of out-degree <= R over the primary vectors (Appendix A:
+ * per node, a search of the current graph with the node as query collects
+ * L candidates, which are pruned to at most R diverse out-neighbours;
+ * Section 2 "Graph construction": only the primary vectors take part;
+ * Appendix C: Vamana's pruning with factor alpha).  Distances are squared
+ * Euclidean distances between LVQ reconstructions, from exact integer code
+ * sums and one fixed sequence of float64 operations.
+ *
+ * Nodes are inserted in `order` (host [N], a permutation of 0..N-1) in
+ * batches: 1, 2, 4, ... up to max_batch nodes in pass 0, max_batch nodes in
+ * later passes.  Inside a batch every search sees the graph as it was when
+ * the batch began; a node's pool is its final window followed by its current
+ * out-neighbours; pruning sorts the pool by (distance, id), skips the node
+ * and repeats, and keeps c unless a kept k has alpha^2 d(k,c) <= d(p,c), up
+ * to R.  Then every target j of a new edge p -> j gets the new sources
+ * (ascending) that are not in its row; a row longer than R is pruned around
+ * j.  The result is fully determined by the inputs (no dependence on
+ * scheduling).
+ *
+ * records: device, [N][record_stride] in the lv_lvq_encode layout (d
+ *   components of `bits` bits, d * bits / 8 <= 256 bytes).  entry: start
+ *   node of every search.  adjacency: device [N][R], written (valid ids
+ *   first, then LV_SENTINEL).  Allocates and frees its own device scratch;
+ *   runs on `stream` and synchronizes it before returning.
+ * Errors: LV_EINVAL for NULL pointers, bad sizes or parameters, an order
+ *   that is not a permutation; LV_EUNSUPPORTED for R > 64, wider records,
+ *   an unsupported stride, or a node receiving more than 256 new edges in
+ *   one batch (lower max_batch); LV_EDEVICE, LV_ENOMEM.
+ */
+int lv_graph_build(const void *records, int32_t record_stride, int64_t N, int32_t d,
+                   int32_t bits, const uint32_t *order, uint32_t entry,
+                   const lv_build_params *params, uint32_t *adjacency, void *stream);
+
+/* ------------------------------------------------------------------------
  * Differentiable projection refinement (device, matrix cores).
  * ---------------------------------------------------------------------- */
 

@@ -52,6 +52,15 @@ class BatchCaps(ctypes.Structure):
     _fields_ = [("max_requests", _c_i32), ("max_L", _c_i32), ("max_queries", _c_i64)]
 
 
+LV_MAX_BUILD_PASSES = 8
+
+
+class BuildParams(ctypes.Structure):
+    _fields_ = [("R", _c_i32), ("L", _c_i32), ("passes", _c_i32), ("hash_slots", _c_i32),
+                ("alphas", _c_dbl * LV_MAX_BUILD_PASSES), ("max_batch", _c_i64),
+                ("stop_after", _c_i64)]
+
+
 class FWParams(ctypes.Structure):
     _fields_ = [("alpha", _c_dbl), ("tol", _c_dbl), ("max_iter", _c_i32), ("init", _c_i32)]
 
@@ -106,6 +115,8 @@ _SIGS = {
     "lv_adam_step": (_c_i32, [_vp, _vp, _vp, _vp, _c_i64, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, ctypes.c_float, _c_i32, _vp]),
     "lv_clip_spectral": (_c_i32, [_vp, _c_i32, _c_i32]),
+    "lv_graph_build": (_c_i32, [_vp, _c_i32, _c_i64, _c_i32, _c_i32, _vp, _c_u32,
+                                ctypes.POINTER(BuildParams), _vp, _vp]),
     "lv_autotune_knobs": (_c_i32, [_vp, ctypes.POINTER(BatchCaps), ctypes.POINTER(Request),
                                    _c_i32, _vp, _vp, _vp, _c_i32, ctypes.POINTER(SearchParams),
                                    ctypes.POINTER(_c_dbl), _vp]),
@@ -282,6 +293,32 @@ def lv_to_f16(X, out, stream=None) -> None:
 
     _check(load().lv_to_f16(_dev(X, torch.float32), X.numel(), _dev(out, torch.float16),
                             _stream(stream)))
+
+
+def build_params(R: int, L: int, alphas=(1.0, 1.0), max_batch: int = 1, stop_after: int = 0,
+                 hash_slots: int = 0) -> BuildParams:
+    if not 1 <= len(alphas) <= LV_MAX_BUILD_PASSES:
+        raise ValueError(f"1..{LV_MAX_BUILD_PASSES} passes")
+    bp = BuildParams()
+    bp.R, bp.L, bp.passes, bp.hash_slots = R, L, len(alphas), hash_slots
+    for i, a in enumerate(alphas):
+        bp.alphas[i] = float(a)
+    bp.max_batch, bp.stop_after = max_batch, stop_after
+    return bp
+
+
+def lv_graph_build(records, N: int, d: int, bits: int, order: np.ndarray, entry: int,
+                   params: BuildParams, adjacency, stream=None) -> None:
+    """records: device uint8 [N][stride]; order: host uint32 [N]; adjacency:
+    device int32 [N][R] (uint32 ids, LV_SENTINEL = -1), written."""
+    import torch
+
+    order = _host(order, np.uint32)
+    if order.shape != (N,) or records.shape[0] < N or tuple(adjacency.shape) != (N, params.R):
+        raise ValueError("order must be [N], records [>= N][stride], adjacency [N][R]")
+    _check(load().lv_graph_build(_dev(records, torch.uint8), records.shape[1], N, d, bits,
+                                 order.ctypes.data, entry, ctypes.byref(params),
+                                 _dev(adjacency, torch.int32), _stream(stream)))
 
 
 class Index:

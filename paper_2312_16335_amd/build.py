@@ -19,8 +19,8 @@ LIB = os.path.join(LIBDIR, "liblv.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HIP_SOURCES = ["lv_api.cpp", "lv_batch.cpp", "lv_search.hip", "lv_lvq.hip", "lv_project.hip",
-               "lv_gemm.hip", "lv_projloss.hip"]
+HIP_SOURCES = ["lv_api.cpp", "lv_batch.cpp", "lv_search.hip", "lv_graph.hip", "lv_lvq.hip",
+               "lv_project.hip", "lv_gemm.hip", "lv_projloss.hip"]
 HOST_SOURCES = ["lv_fit.cpp", "lv_error.cpp"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

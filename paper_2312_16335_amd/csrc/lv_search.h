@@ -55,6 +55,23 @@ struct StepHeader {
   int32_t ntiles;        // 32-row projection tiles over all requests
 };
 
+// One batch of construction searches (graph construction, Appendix A):
+// node order[start + b] for b < B, window L, pool rows of pool_stride
+// (>= L + R) ids at pool + b * pool_stride; optional counters [B][2]
+// (expansions, scorings).  ix.adj is the graph being built.
+struct BuildSearchArgs {
+  IndexView ix;
+  const uint32_t *order;
+  int64_t start;
+  int32_t B;
+  int32_t L;
+  int32_t pool_stride;
+  uint32_t *pool;
+  uint32_t *counters;
+  int32_t hash_log2;
+  int32_t probes;
+};
+
 IndexView make_view(const lv_index *ix);
 // Visited set of one query: 2^log2h slots in LDS, up to `probes` slots tried
 // before an id replaces the one in its home slot.
@@ -69,6 +86,8 @@ int launch_batched(int bits, int group, int vbytes, const StepHeader *hdr,
                       const IndexView *subs, unsigned int *counter, int Lmax, VisitedCfg vc,
                       int grid, hipStream_t stream);
 int batched_occupancy(int bits, int group, int vbytes, int Lmax, int log2h, int *blocks);
+int launch_build_search(int bits, int group, int vbytes, const BuildSearchArgs &a,
+                        hipStream_t stream);
 int launch_project_grouped(const StepHeader *hdr, const IndexView *subs, int max_tiles, int d,
                            int D, hipStream_t stream);
 

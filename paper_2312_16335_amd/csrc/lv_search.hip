@@ -36,7 +36,13 @@
 // per query of one request, and a batched launch over the queries of many
 // requests (each with its own sub-index, k and L), either one workgroup per
 // query or resident wavefronts pulling queries from a device counter.
+//
+// Graph construction (Appendix A) runs the same body with a database node as
+// the query: its own codes take the place of the projected query, a record
+// is scored with minus the squared distance of the two LVQ reconstructions,
+// and the final window is the result (no re-ranking).
 #include "lv_common.h"
+#include "lv_l2.h"
 #include "lv_search.h"
 
 namespace lv {
@@ -55,6 +61,13 @@ struct Job {
   uint32_t *ids;     // [k]
   float *scores;     // [k]
   uint32_t *counters;  // [2] or nullptr
+  uint32_t node;     // construction: the database node searched for
+};
+
+// Query-side constants of a construction search: d, the node's delta and
+// lo, and the integer sums of its codes and of their squares.
+struct BuildQ {
+  double d, da, lo, s, ss;
 };
 
 // Dynamic LDS of the search kernels.  All per-query LDS state is addressed
@@ -207,10 +220,14 @@ __device__ __forceinline__ uint32_t code_at(const Chunk<V> &c, int t) {
 
 // Score the nc candidate ids in cid[] into cs[].  Group g of G lanes takes
 // candidates g, g + 64/G, ...; U records per group are in flight at once.
-template <int BITS, int G, int V>
+// BUILD: qv holds the searched node's codes, so the dot product is the
+// integer sum S_ab; the candidate's S_b and S_bb are summed alongside
+// (packed as S_bb + 2^32 S_b, exact in float64) and the score is minus the
+// squared distance.
+template <int BITS, int G, int V, bool BUILD = false>
 __device__ __forceinline__ void score_batch(const IndexView &ix, const float (&qv)[V * 8 / BITS],
-                                            double sq, double cq, const uint32_t *cid, double *cs,
-                                            int nc, int lane) {
+                                            double sq, double cq, const BuildQ &bq,
+                                            const uint32_t *cid, double *cs, int nc, int lane) {
   constexpr int NQ = V * 8 / BITS;
   constexpr int RPP = 64 / G;
   constexpr int U = (48 / V) < 2 ? 2 : (48 / V);
@@ -252,6 +269,17 @@ __device__ __forceinline__ void score_batch(const IndexView &ix, const float (&q
       for (int t = 0; t < NQ; ++t)
         acc = fma((double)code_at<BITS, V>(ch[u], t), (double)qv[t], acc);
       acc = group_sum<G>(acc);
+      double pk = 0.0;
+      if constexpr (BUILD) {
+        uint32_t s1 = 0u, s2 = 0u;
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+          const uint32_t cv = gl * NQ + t < ix.d ? code_at<BITS, V>(ch[u], t) : 0u;
+          s1 += cv;
+          s2 += cv * cv;
+        }
+        pk = group_sum<G>((double)s2 + 4294967296.0 * (double)s1);
+      }
       const int c = base + u * RPP + grp;
       if (in_chunk) {
 #pragma unroll
@@ -263,7 +291,13 @@ __device__ __forceinline__ void score_batch(const IndexView &ix, const float (&q
       if (gl == wl && c < nc) {
         const double delta = (double)__uint_as_float(dlw[u]);
         const double lo = (double)__uint_as_float(low[u]);
-        cs[c] = delta * acc + lo * sq + cq;
+        if constexpr (BUILD) {
+          const double sb = floor(pk * 0x1p-32);
+          const double sbb = pk - sb * 4294967296.0;
+          cs[c] = -lvq_l2(bq.d, bq.da, bq.lo, bq.s, bq.ss, delta, lo, sb, sbb, acc);
+        } else {
+          cs[c] = delta * acc + lo * sq + cq;
+        }
       }
     }
   }
@@ -386,8 +420,10 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
   }
 }
 
-// The whole search of one query by one wavefront.
-template <int BITS, int G, int V>
+// The whole search of one query by one wavefront.  BUILD: construction
+// search for node job.node; the final window goes to job.ids (L entries,
+// padded with the sentinel).
+template <int BITS, int G, int V, bool BUILD = false>
 __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm, int log2h,
                              int probes,
                              int lane) {
@@ -399,20 +435,41 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
   const int gl = lane % G;
   float qv[NQ];
   double sq = 0.0, cq = 0.0;
+  BuildQ bq{};
+  if constexpr (BUILD) {
+    // the node's own codes (small integers, exact in float32 and float64)
+    const LV_GLOBAL unsigned char *rec = gp(ix.records) + (size_t)job.node * (size_t)ix.stride;
+    const Chunk<V> ch = load_chunk<V>(rec + gl * V);
+    uint32_t s1 = 0u, s2 = 0u;
 #pragma unroll
-  for (int t = 0; t < NQ; ++t) {
-    // unconditional loads (clamped index) so that all of them are in flight
-    const int j = gl * NQ + t;
-    const bool in = j < ix.d;
-    const float x = gp(job.qp)[in ? j : 0];
-    const float mj = gp(ix.mu)[in ? j : 0];
-    qv[t] = in ? x : 0.f;
-    sq += (double)qv[t];
-    cq = fma((double)qv[t], (double)mj, cq);
+    for (int t = 0; t < NQ; ++t) {
+      const uint32_t cv = gl * NQ + t < ix.d ? code_at<BITS, V>(ch, t) : 0u;
+      qv[t] = (float)cv;
+      s1 += cv;
+      s2 += cv * cv;
+    }
+    const LV_GLOBAL float *cw = reinterpret_cast<const LV_GLOBAL float *>(rec + ix.code_bytes);
+    bq.d = (double)ix.d;
+    bq.da = (double)cw[0];
+    bq.lo = (double)cw[1];
+    bq.s = lane_f64(group_sum<G>((double)s1), 0);
+    bq.ss = lane_f64(group_sum<G>((double)s2), 0);
+  } else {
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+      // unconditional loads (clamped index) so that all of them are in flight
+      const int j = gl * NQ + t;
+      const bool in = j < ix.d;
+      const float x = gp(job.qp)[in ? j : 0];
+      const float mj = gp(ix.mu)[in ? j : 0];
+      qv[t] = in ? x : 0.f;
+      sq += (double)qv[t];
+      cq = fma((double)qv[t], (double)mj, cq);
+    }
+    // the same in every lane after the group reduction: keep them scalar
+    sq = lane_f64(group_sum<G>(sq), 0);
+    cq = lane_f64(group_sum<G>(cq), 0);
   }
-  // the same in every lane after the group reduction: keep them scalar
-  sq = lane_f64(group_sum<G>(sq), 0);
-  cq = lane_f64(group_sum<G>(cq), 0);
   for (int i = lane; i < hslots; i += 64) sm.hash()[i] = kEmpty;
   wave_sync();
 
@@ -422,7 +479,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
     hash_visit(sm.hash(), log2h, probes, ix.entry);
   }
   wave_sync();
-  score_batch<BITS, G, V>(ix, qv, sq, cq, sm.cid(), sm.cs(), 1, lane);
+  score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), 1, lane);
   wave_sync();
   if (lane == 0) {
     sm.ls()[0] = sm.cs()[0];
@@ -483,7 +540,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
       if (nc == 0) continue;
       if (fresh) sm.cid()[lane_rank(fm)] = n;
       wave_sync();
-      score_batch<BITS, G, V>(ix, qv, sq, cq, sm.cid(), sm.cs(), nc, lane);
+      score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), nc, lane);
       wave_sync();
       n_dist += nc;
 
@@ -620,6 +677,17 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
       nl = nl + nv < L ? nl + nv : L;
       wave_sync();
     }
+  }
+
+  if constexpr (BUILD) {
+    for (int j = lane; j < L; j += 64)
+      gpw(job.ids)[j] = j < nl ? (sm.lid()[j] & kIdMask) : kSentinel;
+    if (job.counters && lane == 0) {
+      gpw(job.counters)[0] = n_exp;
+      gpw(job.counters)[1] = n_dist;
+    }
+    wave_sync();
+    return;
   }
 
   // re-rank the window with the secondary vectors, in place: the secondary
@@ -766,6 +834,29 @@ __attribute__((amdgpu_waves_per_eu(batched_waves<BITS, V>()))) void batched_kern
   }
 }
 
+// Construction searches of one batch: workgroup b searches node
+// order[start + b] on the graph as it stands (no kernel of the batch writes
+// it meanwhile) and writes its pool row: the final window (L ids), then the
+// node's current out-neighbours (R ids).
+template <int BITS, int G, int V>
+__global__ __launch_bounds__(64) void build_search_kernel(BuildSearchArgs a) {
+  const int b = blockIdx.x;
+  if (b >= a.B) return;
+  const uint32_t p = a.order[a.start + b];
+  Job job;
+  job.q = nullptr;
+  job.qp = nullptr;
+  job.k = 0;
+  job.L = a.L;
+  job.ids = a.pool + (size_t)b * (size_t)a.pool_stride;
+  job.scores = nullptr;
+  job.counters = a.counters ? a.counters + 2 * (size_t)b : nullptr;
+  job.node = p;
+  search_query<BITS, G, V, true>(a.ix, job, carve(a.L), a.hash_log2, a.probes, threadIdx.x);
+  for (int r = threadIdx.x; r < a.ix.R; r += 64)
+    gpw(job.ids)[a.L + r] = gp(a.ix.adj)[(size_t)p * (size_t)a.ix.R + r];
+}
+
 __global__ void reset_counter_kernel(unsigned int *counter) { *counter = 0u; }
 
 template <int BITS, int G, int V>
@@ -827,6 +918,19 @@ struct BatchedLaunch {
   template <int B, int GG, int VV>
   int operator()() {
     return launch_batched_t<B, GG, VV>(hdr, subs, counter, Lmax, vc, lds, grid, s);
+  }
+};
+
+struct BuildLaunch {
+  const BuildSearchArgs &a;
+  size_t lds;
+  hipStream_t s;
+  template <int B, int GG, int VV>
+  int operator()() {
+    hipLaunchKernelGGL((build_search_kernel<B, GG, VV>), dim3((unsigned)a.B), dim3(64), lds, s,
+                       a);
+    LV_CHECK_LAUNCH();
+    return LV_OK;
   }
 };
 
@@ -921,6 +1025,14 @@ int launch_batched(int bits, int group, int vbytes, const StepHeader *hdr,
                       int grid, hipStream_t stream) {
   const size_t lds = beam_lds_bytes(Lmax, vc.log2h);
   BatchedLaunch f{hdr, subs, counter, Lmax, vc, lds, grid, stream};
+  return dispatch(bits, group, vbytes, f);
+}
+
+int launch_build_search(int bits, int group, int vbytes, const BuildSearchArgs &a,
+                        hipStream_t stream) {
+  if (a.B <= 0) return LV_OK;
+  const size_t lds = beam_lds_bytes(a.L, a.hash_log2);
+  BuildLaunch f{a, lds, stream};
   return dispatch(bits, group, vbytes, f);
 }
 

@@ -234,3 +234,45 @@ def test_clip_spectral_against_svd():
     assert np.allclose(got, want, atol=1e-10)
     inside = M / (2 * s.max())
     assert np.array_equal(lv.lv_clip_spectral(inside), inside)
+
+
+def test_graph_build_validation_without_a_device():
+    lib = lv.load()
+    order = np.arange(100, dtype=np.uint32)
+    op = order.ctypes.data
+
+    def call(records=FAKE, stride=64, N=100, d=32, bits=8, order_p=op, entry=0, adj=FAKE,
+             **kw):
+        base = dict(R=16, L=32, alphas=(1.0, 1.0), max_batch=8)
+        base.update(kw)
+        bp = lv.build_params(**base)
+        return lib.lv_graph_build(records, stride, N, d, bits, order_p, entry, ctypes.byref(bp),
+                                  adj, None)
+
+    assert call(records=None) == lv.LV_EINVAL
+    assert call(adj=None) == lv.LV_EINVAL
+    assert call(order_p=None) == lv.LV_EINVAL
+    assert call(N=0) == lv.LV_EINVAL
+    assert call(d=12) == lv.LV_EINVAL
+    assert call(bits=3) == lv.LV_EINVAL
+    assert call(d=512, stride=1024) == lv.LV_EUNSUPPORTED  # 512 code bytes per record
+    assert call(stride=96) == lv.LV_EUNSUPPORTED
+    assert call(d=64, stride=64) == lv.LV_EINVAL  # no room for delta and lo
+    assert call(R=65) == lv.LV_EUNSUPPORTED
+    assert call(R=0) == lv.LV_EUNSUPPORTED
+    assert call(L=0) == lv.LV_EINVAL
+    assert call(alphas=(1.0, -0.5)) == lv.LV_EINVAL
+    assert call(alphas=(float("nan"),)) == lv.LV_EINVAL
+    assert call(max_batch=0) == lv.LV_EINVAL
+    assert call(stop_after=-1) == lv.LV_EINVAL
+    assert call(entry=100) == lv.LV_EINVAL
+    assert call(hash_slots=1000) == lv.LV_EINVAL
+    dup = order.copy()
+    dup[5] = 4
+    assert call(order_p=dup.ctypes.data) == lv.LV_EINVAL
+    assert "permutation" in lib.lv_last_error().decode()
+    big = order.copy()
+    big[7] = 100
+    assert call(order_p=big.ctypes.data) == lv.LV_EINVAL
+    with pytest.raises(ValueError):
+        lv.build_params(16, 32, alphas=(1.0,) * 9)

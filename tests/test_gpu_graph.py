@@ -1,0 +1,100 @@
+"""Graph construction on the GPU against the oracle: the adjacency must be
+identical (integer output), at sizes spanning many batches, for 8- and 4-bit
+records, the record layouts of the 16- and 64-lane groups, alpha != 1, the
+largest R and record width, partial builds, and points on a line (the path
+graph).  Inputs come from the oracle's encoder; nothing the oracle reads
+comes from the device."""
+import numpy as np
+import pytest
+
+import paper_2312_16335_amd as lv
+from oracle import graph as og
+from oracle import lvq
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SENT = og.SENTINEL
+
+
+def _clustered(n, d, bits, seed, clusters=8):
+    rng = np.random.default_rng(seed)
+    C = rng.standard_normal((clusters, d)) * 2
+    Y = (C[rng.integers(0, clusters, n)] + rng.standard_normal((n, d))).astype(np.float32)
+    codes, delta, lo = lvq.encode(Y, Y.mean(axis=0).astype(np.float32), bits)
+    rec = lvq.pack_records(codes, delta, lo, bits, lv.lv_record_stride(d, bits))
+    return og.Primaries(codes, delta, lo), rec, rng.permutation(n).astype(np.uint32)
+
+
+def _gpu_build(rec, n, d, bits, order, entry, R, L, alphas, max_batch, stop_after=0):
+    recs = torch.from_numpy(rec).cuda()
+    adj = torch.empty((n, R), dtype=torch.int32, device="cuda")
+    bp = lv.build_params(R, L, alphas, max_batch, stop_after)
+    lv.lv_graph_build(recs, n, d, bits, order, entry, bp, adj)
+    torch.cuda.synchronize()
+    return adj.cpu().numpy().view(np.uint32)
+
+
+CASES = [
+    # n, d, bits, R, L, max_batch, alphas
+    (1000, 32, 8, 16, 32, 64, (1.0, 1.0)),
+    (600, 160, 8, 24, 40, 32, (1.0, 1.2)),
+    (800, 64, 4, 16, 24, 50, (1.0,)),
+    (500, 256, 8, 64, 80, 40, (1.0, 1.0)),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "n%d-d%d-b%d-R%d-L%d-mb%d" % c[:6])
+def test_build_equals_oracle(case):
+    n, d, bits, R, L, mb, alphas = case
+    prim, rec, order = _clustered(n, d, bits, seed=n + d)
+    entry = int(order[0])
+    want = og.build(prim, order, entry, R, L, alphas, mb)
+    got = _gpu_build(rec, n, d, bits, order, entry, R, L, alphas, mb)
+    og.check_rows(got)
+    bad = np.nonzero((got != want).any(axis=1))[0]
+    assert bad.size == 0, "rows differ: %s (first: gpu %s oracle %s)" % (
+        bad[:10].tolist(), got[bad[0]].tolist(), want[bad[0]].tolist())
+
+
+@pytest.mark.parametrize("stop_after", [1, 2, 5, 9, 12])
+def test_partial_builds_equal_oracle(stop_after):
+    n, d, bits, R, L, mb = 700, 32, 8, 12, 24, 48
+    prim, rec, order = _clustered(n, d, bits, seed=21)
+    entry = int(order[0])
+    want = og.build(prim, order, entry, R, L, (1.0, 1.0), mb, stop_after=stop_after)
+    got = _gpu_build(rec, n, d, bits, order, entry, R, L, (1.0, 1.0), mb, stop_after)
+    assert np.array_equal(got, want)
+
+
+def test_points_on_a_line_give_the_path():
+    rng = np.random.default_rng(5)
+    n, d = 64, 8
+    t = rng.permutation(n).astype(np.float64) * 0.5 + rng.uniform(0, 0.2, n)
+    Y = np.asarray(t, np.float32)[:, None] * np.ones((1, d), np.float32)
+    codes, delta, lo = lvq.encode(Y, np.zeros(d, np.float32), 8)
+    rec = lvq.pack_records(codes, delta, lo, 8, lv.lv_record_stride(d, 8))
+    order = rng.permutation(n).astype(np.uint32)
+    got = _gpu_build(rec, n, d, 8, order, int(order[0]), 2, n, (1.0, 1.0), 4)
+    srt = np.argsort(t)
+    for k, i in enumerate(srt):
+        want = {int(x) for x in (srt[k - 1] if k else None, srt[k + 1] if k + 1 < n else None)
+                if x is not None}
+        assert set(int(x) for x in got[i] if x != SENT) == want, int(i)
+
+
+def test_too_many_new_edges_in_one_batch_is_an_error():
+    # identical points: every node of a batch links to the same node, and a
+    # batch of 512 gives it more new sources than one batch may bring
+    n, d = 1200, 8
+    Y = np.tile(np.arange(d, dtype=np.float32), (n, 1))
+    codes, delta, lo = lvq.encode(Y, np.zeros(d, np.float32), 8)
+    rec = lvq.pack_records(codes, delta, lo, 8, lv.lv_record_stride(d, 8))
+    order = np.arange(n, dtype=np.uint32)
+    with pytest.raises(lv.LVError) as e:
+        _gpu_build(rec, n, d, 8, order, 0, 8, 16, (1.0,), 512)
+    assert e.value.code == lv.LV_EUNSUPPORTED
+    # the library stays usable: a small build still matches the oracle
+    prim, rec2, order2 = _clustered(300, 32, 8, seed=3)
+    want = og.build(prim, order2, 0, 8, 16, (1.0,), 16)
+    assert np.array_equal(_gpu_build(rec2, 300, 32, 8, order2, 0, 8, 16, (1.0,), 16), want)
