@@ -60,6 +60,13 @@ def parse():
     ap.add_argument("--only-steps", action="store_true",
                     help="skip the sweep refinement (profiling runs)")
     ap.add_argument("--L", type=int, default=0, help="fixed window (skips the sweep)")
+    ap.add_argument("--graph", choices=("cpu", "gpu"), default="cpu",
+                    help="index graph: the host builder on float16 vectors (cached), or "
+                         "lv_graph_build on the primary vectors (timed)")
+    ap.add_argument("--build-L", type=int, default=0,
+                    help="search window of the GPU graph build (default 2R)")
+    ap.add_argument("--build-batch", type=int, default=0,
+                    help="largest insertion batch of the GPU graph build (default N/50)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -87,6 +94,34 @@ def build_graph_cached(wl, X, out):
     np.savez(p + ".tmp.npz", adj=adj, entry=np.int64(entry))
     os.replace(p + ".tmp.npz", p)
     out["adj"], out["entry"] = adj, entry
+
+
+def build_graph_gpu(lv, torch, wl, X, rec, args, out):
+    """lv_graph_build over the primary records; entry = medoid of the database
+    (as for the host builder), insertion order = a seeded permutation."""
+    from synth import graph as sgraph
+
+    entry = sgraph.medoid(X)
+    order = np.random.default_rng(wl.seed_data + 17).permutation(wl.N).astype(np.uint32)
+    bL = args.build_L or 2 * wl.R
+    mb = args.build_batch or max(1, wl.N // 50)
+    adjd = torch.empty((wl.N, wl.R), dtype=torch.int32, device=rec.device)
+    bp = lv.build_params(wl.R, bL, wl.graph_alphas, mb)
+    torch.cuda.synchronize()
+    t = time.time()
+    lv.lv_graph_build(rec, wl.N, wl.d, wl.bits, order, entry, bp, adjd)
+    torch.cuda.synchronize()
+    out["graph_s"] = time.time() - t
+    # again with the work counters (a second, untimed build; must be identical)
+    again = torch.empty_like(adjd)
+    out["stats"] = lv.lv_graph_build(rec, wl.N, wl.d, wl.bits, order, entry, bp, again,
+                                     stats=True)
+    torch.cuda.synchronize()
+    out["deterministic"] = bool(torch.equal(adjd, again))
+    del again
+    out["kind"] = (f"lv_graph_build on the primary vectors (window {bL}, batches up to {mb}, "
+                   f"alphas {list(wl.graph_alphas)})")
+    return adjd, entry
 
 
 def ground_truth_gpu(torch, Xd, Q, k):
@@ -182,8 +217,10 @@ def main():
     log(f"data {X.shape} queries {Q.shape} in {time.time() - t0:.1f}s")
 
     g = {}
-    th = threading.Thread(target=build_graph_cached, args=(wl, X, g))
-    th.start()
+    th = None
+    if args.graph == "cpu":
+        th = threading.Thread(target=build_graph_cached, args=(wl, X, g))
+        th.start()
 
     # ---- index side: fit (host float64), projection + encoding (GPU)
     rng = np.random.default_rng(7)
@@ -226,10 +263,17 @@ def main():
     Xd = None
     torch.cuda.empty_cache()
     log(f"fit + encode + ground truth done at {time.time() - t0:.1f}s")
-    th.join()
-    adj, entry = g["adj"], g["entry"]
+    if th is not None:
+        th.join()
+        adj, entry = g["adj"], g["entry"]
+        adjd = torch.from_numpy(adj.view(np.int32)).to(dev)
+    else:
+        adjd, entry = build_graph_gpu(lv, torch, wl, X, rec, args, g)
+        adj = adjd.cpu().numpy().view(np.uint32)
+        from synth import graph as sgraph
+
+        g["reachable"] = float(sgraph.reachable(adj, entry).mean())
     log(f"graph ready at {time.time() - t0:.1f}s (build {g['graph_s']:.1f}s)")
-    adjd = torch.from_numpy(adj.view(np.int32)).to(dev)
     index = lv.Index(rec, mud, sec, adjd, entry, wl.bits, wl.d, A_bf16=Pb, sec_mu=smud)
 
     # ---- request stream over the test queries (uneven batches)
@@ -532,9 +576,14 @@ def main():
                                "with three steps in flight, from HIP events around the "
                                "traversal graphs on their launch streams"},
         "index_build": {"db_projection_ms": db_proj_ms, "graph_build_s": g.get("graph_s"),
-                        "graph_build_threads": int(os.environ.get("OMP_NUM_THREADS") or
-                                                   os.cpu_count()),
-                        "graph_cached": g.get("graph_s") == 0.0},
+                        "graph": g.get("kind", "host builder, float16 vectors"),
+                        "graph_build_threads": (None if args.graph == "gpu" else
+                                                int(os.environ.get("OMP_NUM_THREADS") or
+                                                    os.cpu_count())),
+                        "graph_cached": g.get("graph_s") == 0.0,
+                        "graph_reachable": g.get("reachable"),
+                        "graph_build_work": g.get("stats"),
+                        "graph_build_repeatable": g.get("deterministic")},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

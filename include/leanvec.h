@@ -416,7 +416,18 @@ typedef struct {
   double alphas[LV_MAX_BUILD_PASSES]; /* pruning factor of each pass, >= 0 */
   int64_t max_batch;  /* largest number of nodes inserted together, >= 1 */
   int64_t stop_after; /* 0: complete build; n > 0: stop after n batches */
+  int64_t *stats;     /* optional host [LV_BUILD_STATS]: work done (see below), or NULL */
 } lv_build_params;
+
+/* Work counters of lv_graph_build (indexes into lv_build_params.stats). */
+#define LV_BUILD_STATS 7
+#define LV_BS_SEARCHES 0    /* construction searches */
+#define LV_BS_EXPANSIONS 1  /* adjacency rows read by them */
+#define LV_BS_SCORINGS 2    /* records scored by them */
+#define LV_BS_FWD_CANDS 3   /* candidates scored by forward pruning */
+#define LV_BS_REV_TARGETS 4 /* nodes that received reverse edges */
+#define LV_BS_REV_PRUNES 5  /* of those, rows pruned (union longer than R) */
+#define LV_BS_REV_CANDS 6   /* candidates scored by reverse pruning */
 
 /*
  * Build a graph of out-degree <= R over the primary vectors (Appendix A:

@@ -58,7 +58,12 @@ LV_MAX_BUILD_PASSES = 8
 class BuildParams(ctypes.Structure):
     _fields_ = [("R", _c_i32), ("L", _c_i32), ("passes", _c_i32), ("hash_slots", _c_i32),
                 ("alphas", _c_dbl * LV_MAX_BUILD_PASSES), ("max_batch", _c_i64),
-                ("stop_after", _c_i64)]
+                ("stop_after", _c_i64), ("stats", _vp)]
+
+
+LV_BUILD_STATS = 7
+BUILD_STAT_NAMES = ("searches", "expansions", "scorings", "forward_candidates",
+                    "reverse_targets", "reverse_prunes", "reverse_candidates")
 
 
 class FWParams(ctypes.Structure):
@@ -308,17 +313,24 @@ def build_params(R: int, L: int, alphas=(1.0, 1.0), max_batch: int = 1, stop_aft
 
 
 def lv_graph_build(records, N: int, d: int, bits: int, order: np.ndarray, entry: int,
-                   params: BuildParams, adjacency, stream=None) -> None:
+                   params: BuildParams, adjacency, stream=None, stats: bool = False):
     """records: device uint8 [N][stride]; order: host uint32 [N]; adjacency:
-    device int32 [N][R] (uint32 ids, LV_SENTINEL = -1), written."""
+    device int32 [N][R] (uint32 ids, LV_SENTINEL = -1), written.  With
+    stats=True returns the work counters as a dict."""
     import torch
 
     order = _host(order, np.uint32)
     if order.shape != (N,) or records.shape[0] < N or tuple(adjacency.shape) != (N, params.R):
         raise ValueError("order must be [N], records [>= N][stride], adjacency [N][R]")
-    _check(load().lv_graph_build(_dev(records, torch.uint8), records.shape[1], N, d, bits,
-                                 order.ctypes.data, entry, ctypes.byref(params),
-                                 _dev(adjacency, torch.int32), _stream(stream)))
+    st = np.zeros(LV_BUILD_STATS, dtype=np.int64)
+    params.stats = st.ctypes.data if stats else None
+    try:
+        _check(load().lv_graph_build(_dev(records, torch.uint8), records.shape[1], N, d, bits,
+                                     order.ctypes.data, entry, ctypes.byref(params),
+                                     _dev(adjacency, torch.int32), _stream(stream)))
+    finally:
+        params.stats = None
+    return dict(zip(BUILD_STAT_NAMES, st.tolist())) if stats else None
 
 
 class Index:

@@ -106,6 +106,7 @@ struct BatchState {
   uint32_t *touched;   // [max_batch * R]
   uint32_t *srcs;      // [max_batch * R]
   uint32_t *misc;      // [0] touched count, [1] source cursor, [2] overflow flag
+  unsigned long long *stats;  // optional work totals (LV_BS_* order) or null
 };
 
 extern __shared__ __align__(16) unsigned char lv_gsmem[];
@@ -308,6 +309,7 @@ __global__ __launch_bounds__(64) void prune_forward_kernel(ForwardArgs a) {
   const int nk = prune_core<BITS>(v, p, m, sm, lane);
   uint32_t *out = v.adj + (size_t)p * (size_t)v.R;
   for (int j = lane; j < v.R; j += 64) out[j] = j < nk ? sm.kid[j] : kSentinel;
+  if (a.st.stats && lane == 0) atomicAdd(&a.st.stats[LV_BS_FWD_CANDS], (unsigned long long)m);
   if (lane < nk) {
     const uint32_t j = sm.kid[lane];
     if (atomicAdd(&a.st.cnt[j], 1u) == 0u) a.st.touched[atomicAdd(&a.st.misc[0], 1u)] = j;
@@ -392,7 +394,12 @@ __global__ __launch_bounds__(64) void reverse_kernel(PruneView v, BatchState st)
     } else {
       const int nk = prune_core<BITS>(v, j, u, sm, lane);
       for (int k = lane; k < v.R; k += 64) row[k] = k < nk ? sm.kid[k] : kSentinel;
+      if (st.stats && lane == 0) {
+        atomicAdd(&st.stats[LV_BS_REV_PRUNES], 1ull);
+        atomicAdd(&st.stats[LV_BS_REV_CANDS], (unsigned long long)u);
+      }
     }
+    if (st.stats && lane == 0) atomicAdd(&st.stats[LV_BS_REV_TARGETS], 1ull);
     if (lane == 0) st.cnt[j] = 0u;
   }
 }
@@ -508,6 +515,14 @@ extern "C" int lv_graph_build(const void *records, int32_t record_stride, int64_
   if ((rc = sc.alloc(&st.touched, (size_t)maxb * R)) != LV_OK) return rc;
   if ((rc = sc.alloc(&st.srcs, (size_t)maxb * R)) != LV_OK) return rc;
   if ((rc = sc.alloc(&st.misc, 4)) != LV_OK) return rc;
+  uint32_t *counters = nullptr;
+  if (bp.stats) {
+    if ((rc = sc.alloc(&st.stats, LV_BUILD_STATS)) != LV_OK) return rc;
+    if ((rc = sc.alloc(&counters, (size_t)maxb * 2)) != LV_OK) return rc;
+    if ((rc = fill_u32(reinterpret_cast<uint32_t *>(st.stats), 2 * LV_BUILD_STATS, 0u, s)) !=
+        LV_OK)
+      return rc;
+  }
   LV_CHECK_HIP(hipMemcpyAsync(order_d, order, (size_t)N * sizeof(uint32_t),
                               hipMemcpyHostToDevice, s));
   if ((rc = fill_u32(adjacency, N * (int64_t)R, kSentinel, s)) != LV_OK) return rc;
@@ -527,7 +542,8 @@ extern "C" int lv_graph_build(const void *records, int32_t record_stride, int64_
   sa.L = L;
   sa.pool_stride = pool_stride;
   sa.pool = pool;
-  sa.counters = nullptr;
+  sa.counters = counters;
+  sa.stats = st.stats;
   sa.hash_log2 = vc.log2h;
   sa.probes = vc.probes;
   ForwardArgs fa{};
@@ -580,7 +596,12 @@ extern "C" int lv_graph_build(const void *records, int32_t record_stride, int64_
   }
   uint32_t misc[4] = {0, 0, 0, 0};
   LV_CHECK_HIP(hipMemcpyAsync(misc, st.misc, sizeof(misc), hipMemcpyDeviceToHost, s));
+  unsigned long long tot[LV_BUILD_STATS] = {};
+  if (bp.stats)
+    LV_CHECK_HIP(hipMemcpyAsync(tot, st.stats, sizeof(tot), hipMemcpyDeviceToHost, s));
   LV_CHECK_HIP(hipStreamSynchronize(s));
+  if (bp.stats)
+    for (int i = 0; i < LV_BUILD_STATS; ++i) bp.stats[i] = (int64_t)tot[i];
   if (misc[2])
     LV_FAIL(LV_EUNSUPPORTED,
             "a node received more than %d new edges in one batch; use a smaller max_batch",

@@ -68,6 +68,7 @@ struct BuildSearchArgs {
   int32_t pool_stride;
   uint32_t *pool;
   uint32_t *counters;
+  unsigned long long *stats;  // optional totals: [0] searches, [1] expansions, [2] scorings
   int32_t hash_log2;
   int32_t probes;
 };

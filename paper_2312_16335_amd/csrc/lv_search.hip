@@ -855,6 +855,11 @@ __global__ __launch_bounds__(64) void build_search_kernel(BuildSearchArgs a) {
   search_query<BITS, G, V, true>(a.ix, job, carve(a.L), a.hash_log2, a.probes, threadIdx.x);
   for (int r = threadIdx.x; r < a.ix.R; r += 64)
     gpw(job.ids)[a.L + r] = gp(a.ix.adj)[(size_t)p * (size_t)a.ix.R + r];
+  if (a.stats && job.counters && threadIdx.x == 0) {  // the lane that wrote the counters
+    atomicAdd(&a.stats[0], 1ull);
+    atomicAdd(&a.stats[1], (unsigned long long)job.counters[0]);
+    atomicAdd(&a.stats[2], (unsigned long long)job.counters[1]);
+  }
 }
 
 __global__ void reset_counter_kernel(unsigned int *counter) { *counter = 0u; }

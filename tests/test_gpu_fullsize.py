@@ -13,7 +13,10 @@ Checks:
     expansion count;
   * on all 10,000 queries: ids are valid and distinct, each score equals the
     float64 secondary inner product of its id, and lists are sorted by
-    descending score.
+    descending score;
+  * graph construction over the oracle's records with the benchmark's build
+    settings: valid rows, two builds identical, reachability from the entry,
+    and the search quality of the result.
 """
 import time
 
@@ -88,7 +91,8 @@ def full(lv):
     torch.cuda.synchronize()
     log("GPU index ready")
     yield dict(wl=wl, X=X, Q=Q, Qp=Qp, mu=mu, codes=codes, delta=delta, lo=lo_, sec=sec,
-               oix=oix, rec=rec, secd=secd, index=index, stride=stride)
+               oix=oix, rec=rec, secd=secd, index=index, stride=stride, entry=entry, mud=mud,
+               Pb=Pb)
     index.close()
 
 
@@ -185,3 +189,61 @@ def test_batched_step_equals_plain_and_oracle(lv, full):
         hits_orc += len(set(oi) & set(truth[n]))
     log(f"sampled recall GPU {hits_gpu / (N_SAMPLE * k):.3f} oracle {hits_orc / (N_SAMPLE * k):.3f}")
     assert hits_gpu == hits_orc
+
+
+def test_graph_build_at_full_size(lv, full):
+    """lv_graph_build on the oracle's LVQ records (window 64, batches of N/50,
+    two passes at alpha = 1, as bench.py --graph gpu): every row valid, two
+    builds bit-identical (the result must not depend on scheduling), all but
+    a handful of nodes reachable from the entry, and 10-recall@10 >= 0.90 at
+    window 128 on sampled queries (exact neighbours from the oracle)."""
+    from synth import graph as sgraph
+
+    wl = full["wl"]
+    N, R = wl.N, wl.R
+    recs = torch.from_numpy(olvq.pack_records(full["codes"], full["delta"], full["lo"], wl.bits,
+                                              full["stride"])).to(DEV)
+    order = np.random.default_rng(wl.seed_data + 17).permutation(N).astype(np.uint32)
+    entry = full["entry"]
+    bp = lv.build_params(R, 64, (1.0, 1.0), N // 50)
+    adjs = []
+    for rep in range(2):
+        a = torch.empty((N, R), dtype=torch.int32, device=DEV)
+        t = time.time()
+        lv.lv_graph_build(recs, N, wl.d, wl.bits, order, entry, bp, a)
+        torch.cuda.synchronize()
+        log(f"graph build {rep}: {time.time() - t:.2f}s")
+        adjs.append(a)
+    assert torch.equal(adjs[0], adjs[1])
+    del recs
+    adj = adjs[0].cpu().numpy().view(np.uint32)
+    SENT = 0xFFFFFFFF
+    valid = adj != SENT
+    assert (valid[:, 1:] <= valid[:, :-1]).all()          # valid ids first
+    assert valid[:, 0].all()                               # no empty row
+    assert (adj[valid] < N).all()
+    assert not (adj == np.arange(N, dtype=np.uint32)[:, None]).any()
+    srt = np.sort(adj, axis=1)
+    assert not ((srt[:, 1:] == srt[:, :-1]) & (srt[:, 1:] != SENT)).any()
+    reach = sgraph.reachable(adj, entry)
+    log(f"mean degree {valid.sum(1).mean():.1f}, unreachable {int((~reach).sum())}")
+    assert (~reach).sum() <= 100
+
+    index = lv.Index(full["rec"], full["mud"], full["secd"], adjs[0], entry, wl.bits, wl.d,
+                     A_bf16=full["Pb"])
+    Q = full["Q"]
+    rng = np.random.default_rng(23)
+    sample = np.sort(rng.choice(len(Q), 400, replace=False))
+    Qd = torch.from_numpy(Q[sample]).to(DEV)
+    ids = torch.empty((len(sample), wl.k), dtype=torch.int32, device=DEV)
+    sc = torch.empty((len(sample), wl.k), dtype=torch.float32, device=DEV)
+    ws = torch.empty(lv.lv_search_workspace_size(index, len(sample)), dtype=torch.uint8,
+                     device=DEV)
+    lv.lv_search(index, Qd, wl.k, 128, ids, sc, None, ws=ws, hash_slots=HASH_SLOTS)
+    torch.cuda.synchronize()
+    index.close()
+    got = ids.cpu().numpy().view(np.uint32).astype(np.int64)
+    truth = exact.ground_truth(Q[sample], full["X"], wl.k)
+    rec_at = sum(len(set(g) & set(t)) for g, t in zip(got, truth)) / (len(sample) * wl.k)
+    log(f"10-recall@10 at window 128 on the GPU-built graph: {rec_at:.4f}")
+    assert rec_at >= 0.90

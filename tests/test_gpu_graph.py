@@ -26,13 +26,15 @@ def _clustered(n, d, bits, seed, clusters=8):
     return og.Primaries(codes, delta, lo), rec, rng.permutation(n).astype(np.uint32)
 
 
-def _gpu_build(rec, n, d, bits, order, entry, R, L, alphas, max_batch, stop_after=0):
+def _gpu_build(rec, n, d, bits, order, entry, R, L, alphas, max_batch, stop_after=0,
+               stats=False):
     recs = torch.from_numpy(rec).cuda()
     adj = torch.empty((n, R), dtype=torch.int32, device="cuda")
     bp = lv.build_params(R, L, alphas, max_batch, stop_after)
-    lv.lv_graph_build(recs, n, d, bits, order, entry, bp, adj)
+    st = lv.lv_graph_build(recs, n, d, bits, order, entry, bp, adj, stats=stats)
     torch.cuda.synchronize()
-    return adj.cpu().numpy().view(np.uint32)
+    out = adj.cpu().numpy().view(np.uint32)
+    return (out, st) if stats else out
 
 
 CASES = [
@@ -50,8 +52,14 @@ def test_build_equals_oracle(case):
     prim, rec, order = _clustered(n, d, bits, seed=n + d)
     entry = int(order[0])
     want = og.build(prim, order, entry, R, L, alphas, mb)
-    got = _gpu_build(rec, n, d, bits, order, entry, R, L, alphas, mb)
+    got, st = _gpu_build(rec, n, d, bits, order, entry, R, L, alphas, mb, stats=True)
     og.check_rows(got)
+    # work counters: one search per node and pass, each scoring at least the entry
+    assert st["searches"] == n * len(alphas)
+    assert st["scorings"] >= st["searches"] and st["expansions"] >= st["searches"] - 1
+    assert st["forward_candidates"] <= st["searches"] * (L + R)
+    assert st["reverse_prunes"] <= st["reverse_targets"]
+    assert st["reverse_candidates"] > R * st["reverse_prunes"] or st["reverse_prunes"] == 0
     bad = np.nonzero((got != want).any(axis=1))[0]
     assert bad.size == 0, "rows differ: %s (first: gpu %s oracle %s)" % (
         bad[:10].tolist(), got[bad[0]].tolist(), want[bad[0]].tolist())
