@@ -69,11 +69,29 @@ __device__ __forceinline__ int lane_rank(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
-  return v;
+// v moved across lanes by a DPP pattern (rows outside ROWS receive 0).
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  if constexpr (ROWS == 0xF)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+  else
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
 }
+
+// Sum over the wavefront (all lanes active), returned in every lane: sums
+// within quads (swap neighbours, swap pairs), within rows (rotate by 4 and
+// 8), then rows chained into lane 63 (row broadcasts 15 and 31).
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  v += dpp_u32<0xB1>(v);
+  v += dpp_u32<0x4E>(v);
+  v += dpp_u32<0x124>(v);
+  v += dpp_u32<0x128>(v);
+  v += dpp_u32<0x142, 0xA>(v);
+  v += dpp_u32<0x143, 0xC>(v);
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Sum of code products over one 32-bit word of two records.
 template <int BITS>
@@ -112,8 +130,8 @@ struct BatchState {
 extern __shared__ __align__(16) unsigned char lv_gsmem[];
 
 // Per-wavefront LDS of the pruning kernels for M candidates and rows of kw
-// code words (odd, so that lanes reading different kept rows hit different
-// banks).
+// code words: an odd number of 16-byte chunks (zero padded), so that 16
+// lanes reading 16 bytes each from 16 different kept rows cover all banks.
 struct PruneLds {
   double *cs;       // [M] -f(p, c)
   uint32_t *cid;    // [M]
@@ -128,7 +146,7 @@ struct PruneLds {
   uint32_t *stage;  // [kw] codes of the candidate under test
 };
 
-__host__ __device__ inline int row_words(int cw) { return cw | 1; }
+__host__ __device__ inline int row_words(int cw) { return 4 * (((cw + 3) / 4) | 1); }
 
 __host__ __device__ inline size_t prune_lds_bytes(int M, int R, int cw) {
   const int kw = row_words(cw);
@@ -139,21 +157,21 @@ __device__ __forceinline__ PruneLds carve_prune(int M, int R, int cw) {
   PruneLds s;
   unsigned char *b = lv_gsmem;
   const int kw = row_words(cw);
-  s.cs = reinterpret_cast<double *>(b);
-  b += (size_t)M * 8;
-  s.cid = reinterpret_cast<uint32_t *>(b);
+  // 16-byte aligned rows first: kept codes, then the staged candidate
+  s.krow = reinterpret_cast<uint32_t *>(b);
+  s.stage = s.krow + (size_t)R * kw;
+  s.cs = reinterpret_cast<double *>(s.stage + kw);
+  s.cid = reinterpret_cast<uint32_t *>(s.cs + M);
   s.cdl = reinterpret_cast<float *>(s.cid + M);
   s.clo = s.cdl + M;
   s.csum = reinterpret_cast<uint32_t *>(s.clo + M);
   s.csq = s.csum + M;
   s.ord = s.csq + M;
-  s.krow = s.ord + M;
-  s.kdl = reinterpret_cast<float *>(s.krow + (size_t)R * kw);
+  s.kdl = reinterpret_cast<float *>(s.ord + M);
   s.klo = s.kdl + R;
   s.ks = reinterpret_cast<uint32_t *>(s.klo + R);
   s.kss = s.ks + R;
   s.kid = s.kss + R;
-  s.stage = s.kid + R;
   return s;
 }
 
@@ -226,7 +244,11 @@ __device__ int prune_core(const PruneView &v, uint32_t p, int m, const PruneLds 
     sm.ord[r] = (uint32_t)i;
   }
   wave_sync();
-  // greedy walk
+  // greedy walk.  Row words past the codes stay zero (written once here;
+  // the walk writes code words only).
+  const int pad = kw - cw;
+  for (int t = lane; t < (v.R + 1) * pad; t += 64)
+    sm.krow[(size_t)(t / pad) * kw + cw + t % pad] = 0u;  // row R is the stage
   int nk = 0;
   uint32_t prev = kSentinel;
   int nxt_i = 0;
@@ -254,8 +276,16 @@ __device__ int prune_core(const PruneView &v, uint32_t p, int m, const PruneLds 
     bool dom = false;
     if (lane < nk) {
       uint32_t sab = 0u;
-      const uint32_t *kr = sm.krow + (size_t)lane * kw;
-      for (int w = 0; w < cw; ++w) sab = dot_codes<BITS>(kr[w], sm.stage[w], sab);
+      const u32x4 *kr = reinterpret_cast<const u32x4 *>(sm.krow + (size_t)lane * kw);
+      const u32x4 *sg = reinterpret_cast<const u32x4 *>(sm.stage);
+#pragma unroll 4
+      for (int w = 0; w < kw / 4; ++w) {
+        const u32x4 a = kr[w], b = sg[w];
+        sab = dot_codes<BITS>(a[0], b[0], sab);
+        sab = dot_codes<BITS>(a[1], b[1], sab);
+        sab = dot_codes<BITS>(a[2], b[2], sab);
+        sab = dot_codes<BITS>(a[3], b[3], sab);
+      }
       const double f = lvq_l2(dd, (double)sm.kdl[lane], (double)sm.klo[lane],
                               (double)sm.ks[lane], (double)sm.kss[lane], (double)sm.cdl[i],
                               (double)sm.clo[i], (double)sm.csum[i], (double)sm.csq[i],
@@ -383,7 +413,11 @@ __global__ __launch_bounds__(64) void reverse_kernel(PruneView v, BatchState st)
       const uint32_t i = i0 + lane;
       const uint32_t s = i < cnt ? sm.csum[i] : kSentinel;
       bool add = i < cnt && s != j && s < v.N;
-      for (int k = 0; k < deg; ++k) add &= sm.cid[k] != s;
+      const uint32_t nc = cnt - i0 < 64u ? cnt - i0 : 64u;
+      for (uint32_t t = 0; t < nc; ++t) {  // is source t in the row (lane k holds entry k)?
+        const uint32_t st_ = (uint32_t)__builtin_amdgcn_readlane((int)s, (int)t);
+        if (__ballot(lane < deg && rv == st_) && lane == (int)t) add = false;
+      }
       const uint64_t msk = __ballot(add);
       if (add) sm.cid[u + lane_rank(msk)] = s;
       u += __popcll(msk);
