@@ -106,7 +106,7 @@ class Trace:
 
 
 def beam(index: Index, qp, L: int, visited_cap: Optional[int] = None,
-         trace: Optional[Trace] = None, scorer=None) -> List[Tuple[float, int]]:
+         trace: Optional[Trace] = None, scorer=None, expand: int = 1) -> List[Tuple[float, int]]:
     """Best-first traversal; returns the final list as (score, id), best first.
 
     visited_cap bounds the visited set (oldest entries forgotten first).  A
@@ -115,6 +115,12 @@ def beam(index: Index, qp, L: int, visited_cap: Optional[int] = None,
     visited set (a node dropped earlier was worse than L others, and the
     L-th best score never decreases).  scorer(ids), when given, replaces
     the primary score (graph construction scores with a distance).
+
+    expand > 1 is a throughput variant (not the paper's traversal): each
+    iteration expands the `expand` best unexpanded entries together, scores
+    the unvisited out-neighbours of all of them (row by row, in the order
+    the entries are taken) and inserts them; it stops when every entry of
+    the list is expanded.
     """
     tr = trace if trace is not None else Trace()
     if scorer is None:
@@ -133,32 +139,22 @@ def beam(index: Index, qp, L: int, visited_cap: Optional[int] = None,
     if tr.scored is not None:
         tr.scored[e] = s0
     while True:
-        p = None
-        for _, i in keys:
-            if i not in expanded:
-                p = i
-                break
-        if p is None:
+        ps = [i for _, i in keys if i not in expanded][:max(1, expand)]
+        if not ps:
             break
-        expanded.add(p)
-        tr.n_exp += 1
-        fresh = []
-        rescored = []
-        for n in adj[p]:
-            n = int(n)
-            if n == SENTINEL:
-                continue
-            if n in visited:
-                continue
-            if n in in_list:       # only reachable when the visited set forgot n
-                rescored.append(n)
-            elif visited_cap is not None and n in expanded:
-                rescored.append(n)
-            else:
-                fresh.append(n)
-        newly = fresh + rescored
-        for n in newly:
-            visited[n] = None
+        newly = []
+        for p in ps:
+            expanded.add(p)
+            tr.n_exp += 1
+            for n in adj[p]:
+                n = int(n)
+                if n == SENTINEL or n in visited:
+                    continue
+                # (an id met again after the bounded visited set forgot it is
+                # scored again; the insertion below drops it if listed)
+                visited[n] = None
+                newly.append(n)
+        rescored = [n for n in newly if n in in_list or n in expanded]
         if visited_cap is not None:
             while len(visited) > visited_cap:
                 visited.pop(next(iter(visited)))
@@ -197,11 +193,11 @@ def rerank(index: Index, q, cand_ids, k: int) -> Tuple[np.ndarray, np.ndarray]:
     return out_i, out_s
 
 
-def search_one(index: Index, q, qp, k: int, L: int, visited_cap=None, trace=None):
+def search_one(index: Index, q, qp, k: int, L: int, visited_cap=None, trace=None, expand=1):
     """Full query: traversal with window L, then re-rank to k (requires L >= k)."""
     if L < k:
         raise ValueError("window L must be at least k")
-    lst = beam(index, qp, L, visited_cap=visited_cap, trace=trace)
+    lst = beam(index, qp, L, visited_cap=visited_cap, trace=trace, expand=expand)
     return rerank(index, q, [i for _, i in lst], k)
 
 

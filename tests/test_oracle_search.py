@@ -171,3 +171,42 @@ def test_lvq8_secondaries_parallel_matches_serial(tiny):
     b = search.search_many(idx8, Q, Qp, wl.k, 24, procs=2, chunk=3)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_expand_variant_hand_traced():
+    # several expansions per iteration (throughput variant), traced by hand on
+    # the 6-node example of beam_hand.json (scores v = [10, 20, 5, 30, 25, 1])
+    _, idx = _hand_index()
+    qp = np.array([1, 0, 0, 0], np.float32)
+    cases = [
+        # L = 3, two per iteration: {0}, then {1, 2} (adds 3, 5, 4), then {3, 4}
+        (3, 2, [3, 4, 1], 5, 6),
+        # L = 2: {0} keeps 1 (2 falls off), {1} adds 3, {3} finds nothing new
+        (2, 2, [3, 1], 3, 5),
+        # expand = 1 is the traversal itself
+        (3, 1, [i for _, i in search.beam(idx, qp, 3)], None, None),
+    ]
+    for L, e, want, n_exp, n_dist in cases:
+        tr = search.Trace()
+        got = [i for _, i in search.beam(idx, qp, L, trace=tr, expand=e)]
+        assert got == want, (L, e)
+        if n_exp is not None:
+            assert (tr.n_exp, tr.n_dist) == (n_exp, n_dist), (L, e)
+
+
+@pytest.mark.parametrize("expand", [2, 4])
+def test_expand_variant_invariants(tiny, expand):
+    wl, idx, Q, Qp = tiny
+    k = wl.k
+    S = idx.sec.astype(np.float64) @ Q.astype(np.float64).T
+    for i in range(2):
+        # a window holding every node: brute force whatever the expansion order
+        ids, _ = search.search_one(idx, Q[i], Qp[i], k, idx.N, expand=expand)
+        assert ids.tolist() == sorted(range(idx.N), key=lambda j: (-S[j, i], j))[:k]
+        # the final list is the top L of what was scored, and a bounded visited
+        # set does not change it
+        tr = search.Trace(scored={})
+        lst = search.beam(idx, Qp[i], 24, trace=tr, expand=expand)
+        top = sorted(tr.scored.items(), key=lambda kv: (-kv[1], kv[0]))[:24]
+        assert [j for j, _ in top] == [j for _, j in lst]
+        assert search.beam(idx, Qp[i], 24, visited_cap=40, expand=expand) == lst
