@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--only-steps", action="store_true",
                     help="skip the sweep refinement (profiling runs)")
     ap.add_argument("--L", type=int, default=0, help="fixed window (skips the sweep)")
+    ap.add_argument("--expand", type=int, default=1,
+                    help="entries expanded per traversal iteration: 1 = the paper's traversal; "
+                         "2..8 = the throughput variant (no CPU baseline)")
     ap.add_argument("--graph", choices=("cpu", "gpu"), default="cpu",
                     help="index graph: the host builder on float16 vectors (cached), or "
                          "lv_graph_build on the primary vectors (timed)")
@@ -304,7 +307,7 @@ def main():
             if ev is not None:
                 ev[1][i].record(stream)
             lv.lv_search_projected(index, Qd[lo:hi], Qp[lo:hi], k, L, ids[lo:hi],
-                                   scores[lo:hi], hash_slots=knob_hs[0])
+                                   scores[lo:hi], hash_slots=knob_hs[0], expand=args.expand)
             if ev is not None:
                 ev[2][i].record(stream)
 
@@ -372,7 +375,8 @@ def main():
 
     # ---- algorithmic bytes per query at L* from the debug counters (exact visited set)
     cnt = torch.zeros((m, 2), dtype=torch.int32, device=dev)
-    lv.lv_search_projected(index, Qd, Qp, k, L_star, ids, scores, cnt, hash_slots=8192)
+    lv.lv_search_projected(index, Qd, Qp, k, L_star, ids, scores, cnt, hash_slots=8192,
+                           expand=args.expand)
     torch.cuda.synchronize()
     c = cnt.cpu().numpy().astype(np.float64)
     n_exp, n_dist = c[:, 0], c[:, 1]
@@ -394,13 +398,13 @@ def main():
         how = "given"
     else:
         knobs, _ = lv.lv_autotune_knobs(multi, nreq, m, L_star, reqs, Qd, ids_flat, scores_flat,
-                                        reps=2)
+                                        reps=2, expand=args.expand)
         hs, launch = knobs["hash_slots"], knobs["launch"]
         how = "chosen by the autotuner"
     launch_name = "persistent" if launch == lv.LV_LAUNCH_PERSISTENT else "per_query"
     knob_hs[0] = hs
     batch = lv.Batch(multi, max_requests=nreq, max_queries=m, max_L=L_star, hash_slots=hs,
-                     launch=launch)
+                     launch=launch, expand=args.expand)
     log(f"batched step captured (visited-set slots {hs}, {launch_name} launch, {how})")
 
     def step_batched(ev=None):
@@ -510,7 +514,8 @@ def main():
     # reference: the plain path as one launch pair over all queries
     def single():
         lv.lv_project(Qd, Pb, Qp)
-        lv.lv_search_projected(index, Qd, Qp, k, L_star, ids, scores, hash_slots=hs)
+        lv.lv_search_projected(index, Qd, Qp, k, L_star, ids, scores, hash_slots=hs,
+                               expand=args.expand)
 
     single()
     torch.cuda.synchronize()
@@ -524,7 +529,7 @@ def main():
 
     # ---- CPU oracle on a bounded sample
     cpu = None
-    if not args.no_cpu_baseline and smud is None:
+    if not args.no_cpu_baseline and smud is None and args.expand <= 1:
         cpu = cpu_baseline(wl, X, Xs, Q, adj, entry, L_star, args.cpu_sample, truth)
         if cpu["sample"].startswith("all") and abs(cpu["recall"] - rec_star) > 0.005:
             log(f"WARNING: GPU recall {rec_star:.4f} vs oracle {cpu['recall']:.4f}")
@@ -545,7 +550,8 @@ def main():
         "config": {"workload": wl.name, "N": wl.N, "D": wl.D, "d": wl.d, "lvq_bits": wl.bits,
                    "secondary": args.sec, "R": wl.R, "k": k, "queries": m, "L": L_star,
                    "requests": nreq, "mode": "batched, 3 steps in flight",
-                   "visited_slots": hs, "launch": launch_name},
+                   "visited_slots": hs, "launch": launch_name,
+                   "expand": max(1, args.expand)},
         "recall_at_L": rec_star,
         "plain": {"qps": plain_qps, "recall": rec_plain, "ms_per_step": plain_ms / args.steps,
                   "traversal_kernel_GBs": achieved_plain,

@@ -257,6 +257,10 @@ typedef struct {
   int32_t launch;     /* batched traversal only: LV_LAUNCH_PER_QUERY (0, one workgroup
                          per query, scheduled by the hardware) or LV_LAUNCH_PERSISTENT
                          (1, resident wavefronts pull queries from a device counter) */
+  int32_t expand;     /* entries expanded per iteration: 0 or 1 = the paper's traversal
+                         (one expansion at a time); 2..8 = a throughput variant that
+                         expands the `expand` best unexpanded entries together (its results
+                         differ; they are exact for that variant) */
 } lv_search_params;
 #define LV_LAUNCH_PER_QUERY 0
 #define LV_LAUNCH_PERSISTENT 1
@@ -394,7 +398,9 @@ int lv_autotune_window(lv_multi *multi, int32_t sub, const float *Q, int64_t m,
  * best (these knobs never change results).  The persistent launch is not
  * searched: with steps in flight its resident wavefronts hold the compute
  * units that the next step's query projection needs.  best_ms gets the mean
- * time per step.  ids/scores receive one step's output.  Synchronises `stream`.
+ * time per step.  ids/scores receive one step's output.  best->expand is read
+ * on input and kept (the traversal is the caller's choice, not a knob).
+ * Synchronises `stream`.
  */
 int lv_autotune_knobs(lv_multi *multi, const lv_batch_caps *caps, const lv_request *reqs,
                       int32_t nreq, const float *Q, uint32_t *ids, float *scores, int32_t reps,

@@ -41,7 +41,8 @@ class IndexDesc(ctypes.Structure):
 
 
 class SearchParams(ctypes.Structure):
-    _fields_ = [("hash_slots", _c_i32), ("probes", _c_i32), ("launch", _c_i32)]
+    _fields_ = [("hash_slots", _c_i32), ("probes", _c_i32), ("launch", _c_i32),
+                ("expand", _c_i32)]
 
 
 class Request(ctypes.Structure):
@@ -371,8 +372,8 @@ class Index:
             pass
 
 
-def _params(hash_slots: int = 0, probes: int = 0, launch: int = 0):
-    return ctypes.byref(SearchParams(hash_slots, probes, launch))
+def _params(hash_slots: int = 0, probes: int = 0, launch: int = 0, expand: int = 0):
+    return ctypes.byref(SearchParams(hash_slots, probes, launch, expand))
 
 
 def lv_search_workspace_size(index: Index, m: int) -> int:
@@ -380,7 +381,7 @@ def lv_search_workspace_size(index: Index, m: int) -> int:
 
 
 def lv_search(index: Index, Q, k: int, L: int, ids, scores, counters=None, ws=None,
-              hash_slots: int = 0, stream=None, probes: int = 0) -> None:
+              hash_slots: int = 0, stream=None, probes: int = 0, expand: int = 0) -> None:
     import torch
 
     m = Q.shape[0]
@@ -388,18 +389,19 @@ def lv_search(index: Index, Q, k: int, L: int, ids, scores, counters=None, ws=No
     _check(load().lv_search(index.handle, _dev(Q, torch.float32), m, k, L,
                             _dev(ids, torch.int32), _dev(scores, torch.float32),
                             _dev(counters, torch.int32), _dev(ws), ws_bytes,
-                            _params(hash_slots, probes), _stream(stream)))
+                            _params(hash_slots, probes, 0, expand), _stream(stream)))
 
 
 def lv_search_projected(index: Index, Q, Qp, k: int, L: int, ids, scores, counters=None,
-                        hash_slots: int = 0, stream=None, probes: int = 0) -> None:
+                        hash_slots: int = 0, stream=None, probes: int = 0,
+                        expand: int = 0) -> None:
     import torch
 
     m = Q.shape[0]
     _check(load().lv_search_projected(index.handle, _dev(Q, torch.float32),
                                       _dev(Qp, torch.float32), m, k, L, _dev(ids, torch.int32),
                                       _dev(scores, torch.float32), _dev(counters, torch.int32),
-                                      _params(hash_slots, probes), _stream(stream)))
+                                      _params(hash_slots, probes, 0, expand), _stream(stream)))
 
 
 # ------------------------------------------------------------ batched search
@@ -437,12 +439,14 @@ class Batch:
     """Captured batched step (lv_batch_create)."""
 
     def __init__(self, multi: Multi, max_requests: int, max_queries: int, max_L: int,
-                 hash_slots: int = 0, probes: int = 0, launch: int = LV_LAUNCH_PER_QUERY):
+                 hash_slots: int = 0, probes: int = 0, launch: int = LV_LAUNCH_PER_QUERY,
+                 expand: int = 0):
         self.multi = multi
         self.caps = BatchCaps(max_requests, max_L, max_queries)
         h = _vp()
         _check(load().lv_batch_create(multi.handle, ctypes.byref(self.caps),
-                                      _params(hash_slots, probes, launch), ctypes.byref(h)))
+                                      _params(hash_slots, probes, launch, expand),
+                                      ctypes.byref(h)))
         self.handle = h
 
     def step(self, reqs, Q, ids, scores, counters=None, stream=None, events=None):
@@ -477,7 +481,7 @@ class Batch:
 
 
 def lv_autotune_window(multi: Multi, sub: int, Q, truth: np.ndarray, k: int, target: float,
-                       L_max: int, hash_slots: int = 0, stream=None):
+                       L_max: int, hash_slots: int = 0, stream=None, expand: int = 0):
     import torch
 
     truth = np.ascontiguousarray(truth, dtype=np.uint32)
@@ -485,23 +489,25 @@ def lv_autotune_window(multi: Multi, sub: int, Q, truth: np.ndarray, k: int, tar
     rec = ctypes.c_double(0.0)
     _check(load().lv_autotune_window(multi.handle, sub, _dev(Q, torch.float32), Q.shape[0],
                                       truth.ctypes.data, truth.shape[1], k, target, L_max,
-                                      _params(hash_slots), ctypes.byref(L), ctypes.byref(rec),
+                                      _params(hash_slots, 0, 0, expand), ctypes.byref(L),
+                                      ctypes.byref(rec),
                                       _stream(stream)))
     return L.value, rec.value
 
 
 def lv_autotune_knobs(multi: Multi, max_requests, max_queries, max_L, reqs, Q, ids, scores,
-                      reps=3, stream=None):
+                      reps=3, stream=None, expand: int = 0):
     import torch
 
     caps = BatchCaps(max_requests, max_L, max_queries)
-    best = SearchParams(0, 0, 0)
+    best = SearchParams(0, 0, 0, expand)
     ms = ctypes.c_double(0.0)
     _check(load().lv_autotune_knobs(multi.handle, ctypes.byref(caps), _requests(reqs), len(reqs),
                                     _dev(Q, torch.float32), _dev(ids, torch.int32),
                                     _dev(scores, torch.float32), reps, ctypes.byref(best),
                                     ctypes.byref(ms), _stream(stream)))
-    return {"hash_slots": best.hash_slots, "probes": best.probes, "launch": best.launch}, ms.value
+    return {"hash_slots": best.hash_slots, "probes": best.probes, "launch": best.launch,
+            "expand": best.expand}, ms.value
 
 
 # ------------------------------------------------- differentiable projection

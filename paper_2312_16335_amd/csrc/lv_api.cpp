@@ -3,6 +3,7 @@
 #include <new>
 
 #include "lv_common.h"
+#include "lv_search.h"
 
 namespace {
 
@@ -106,6 +107,9 @@ extern "C" int lv_search(const lv_index *index, const float *Q, int64_t m, int32
   const size_t need = lv_search_workspace_size(index, m);
   if (!ws || ws_bytes < need)
     LV_FAIL(LV_EINVAL, "workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+  lv::VisitedCfg vc;  // search options are checked before anything is launched
+  rc = lv::visited_config(params, &vc);
+  if (rc != LV_OK) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   float *Qp = static_cast<float *>(ws);
   rc = lv::launch_project(Q, m, index->desc.D, index->desc.A, index->desc.d, Qp, s);

@@ -155,7 +155,7 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
   if (launch != LV_LAUNCH_PER_QUERY && launch != LV_LAUNCH_PERSISTENT)
     LV_FAIL(LV_EINVAL, "launch must be LV_LAUNCH_PER_QUERY or LV_LAUNCH_PERSISTENT");
   int blocks = 0;
-  rc = lv::batched_occupancy(multi->bits, multi->group, multi->vbytes, caps->max_L, vc.log2h,
+  rc = lv::batched_occupancy(multi->bits, multi->group, multi->vbytes, caps->max_L, vc,
                                 &blocks);
   if (rc != LV_OK) return rc;
   if (blocks < 1) LV_FAIL(LV_EUNSUPPORTED, "the persistent kernel does not fit on a compute unit");
@@ -438,14 +438,15 @@ extern "C" int lv_autotune_knobs(lv_multi *multi, const lv_batch_caps *caps,
     LV_FAIL(LV_ENOMEM, "autotune streams or buffers");
   }
   double best_t = -1.0;
-  lv_search_params keep{0, 0, 0};
+  const int32_t expand = best->expand;  // the traversal is the caller's choice, not a knob
+  lv_search_params keep{0, 0, 0, expand};
   int last_rc = LV_OK;
   // The persistent launch is not searched: with steps in flight its resident
   // wavefronts keep the next step's query projection waiting for compute
   // units, which stalls the pipeline (and it is not faster on its own).
   for (int launch : {LV_LAUNCH_PER_QUERY}) {
     for (int hs : {1024, 2048, 4096, 8192}) {
-      lv_search_params p{hs, 0, launch};
+      lv_search_params p{hs, 0, launch, expand};
       lv_batch *b = nullptr;
       int rc = lv_batch_create(multi, caps, &p, &b);
       if (rc != LV_OK) {

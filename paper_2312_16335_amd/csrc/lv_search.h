@@ -76,9 +76,12 @@ struct BuildSearchArgs {
 IndexView make_view(const lv_index *ix);
 // Visited set of one query: 2^log2h slots in LDS, up to `probes` slots tried
 // before an id replaces the one in its home slot.
+// expand: entries expanded per iteration (1: the paper's traversal; more:
+// the throughput variant).
 struct VisitedCfg {
   int log2h;
   int probes;
+  int expand;
 };
 int visited_config(const lv_search_params *params, VisitedCfg *cfg);
 size_t beam_lds_bytes(int L, int log2h);
@@ -86,7 +89,7 @@ int check_lds(size_t lds, int L, int log2h);
 int launch_batched(int bits, int group, int vbytes, const StepHeader *hdr,
                       const IndexView *subs, unsigned int *counter, int Lmax, VisitedCfg vc,
                       int grid, hipStream_t stream);
-int batched_occupancy(int bits, int group, int vbytes, int Lmax, int log2h, int *blocks);
+int batched_occupancy(int bits, int group, int vbytes, int Lmax, VisitedCfg vc, int *blocks);
 int launch_build_search(int bits, int group, int vbytes, const BuildSearchArgs &a,
                         hipStream_t stream);
 int launch_project_grouped(const StepHeader *hdr, const IndexView *subs, int max_tiles, int d,

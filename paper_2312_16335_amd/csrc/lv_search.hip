@@ -52,6 +52,7 @@ constexpr uint32_t kExpanded = 0x80000000u;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
 constexpr int kFastMerge = 8;  // survivors merged by counting instead of sorting
+constexpr int kMaxExpand = 8;  // entries expanded per iteration by the throughput variant
 
 // Everything one query needs besides the index.
 struct Job {
@@ -77,7 +78,8 @@ struct BuildQ {
 extern __shared__ __align__(16) unsigned char lv_smem[];
 
 // Layout: window scores [Lmax] f64, batch scores [64] f64, window ids
-// [Lmax] u32, batch ids [64] u32, visited hash.  The merge positions of the
+// [Lmax] u32, batch ids [64] u32, ids being expanded [kMaxExpand] u32,
+// visited hash.  The merge positions of the
 // sorting merge reuse the batch scores' space (read into registers first).
 struct Lds {
   int Lmax;
@@ -88,7 +90,8 @@ struct Lds {
   }
   __device__ __forceinline__ uint32_t *cid() const { return lid() + Lmax; }
   __device__ __forceinline__ int32_t *lbc() const { return reinterpret_cast<int32_t *>(cs()); }
-  __device__ __forceinline__ uint32_t *hash() const { return cid() + 64; }
+  __device__ __forceinline__ uint32_t *xid() const { return cid() + 64; }
+  __device__ __forceinline__ uint32_t *hash() const { return xid() + kMaxExpand; }
 };
 
 __device__ __forceinline__ Lds carve(int Lmax) {
@@ -420,13 +423,160 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
   }
 }
 
+// Merge the scored batch (cid/cs[0..nc)) into the window of nl <= L
+// entries, in place; duplicates of window entries are dropped.  DEDUP also
+// drops repeats inside the batch (a batch gathered from several rows can hold
+// an id twice when the visited set forgot it in between).
+template <bool DEDUP = false>
+__device__ __forceinline__ void merge_batch(const Lds &sm, int nc, int L, int &nl, int lane) {
+  const double *ls = sm.ls();
+  uint32_t *lid = sm.lid();
+  double bs = -INFINITY;
+  uint32_t bid = kSentinel;
+  if (lane < nc) {
+    bs = sm.cs()[lane];
+    bid = sm.cid()[lane];
+  }
+  if (nl == L && bid != kSentinel && !better(bs, bid, ls[L - 1], lid[L - 1] & kIdMask)) {
+    bs = -INFINITY;
+    bid = kSentinel;
+  }
+  const uint64_t surv = __ballot(bid != kSentinel);
+  if (surv == 0) return;
+  const int nsurv = __popcll(surv);
+  if (nsurv <= kFastMerge && nl <= 256) {
+    // Few survivors (the common case once the window is full): a survivor
+    // lands at (#window entries better) + (#kept survivors better), a
+    // window entry moves down by the kept survivors better than it.  The
+    // window is read into registers; survivors are broadcast one by one.
+    const int nt = (nl + 63) >> 6;  // 64-entry chunks in use (uniform)
+    double es[4];
+    uint32_t er[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = lane + 64 * t;
+      const bool ok = e < nl;
+      es[t] = ok ? ls[e] : -INFINITY;
+      er[t] = ok ? lid[e] : kSentinel;
+    }
+    int sh[4] = {0, 0, 0, 0};  // kept survivors better than window entry t
+    int my_lb = 0, my_rank = 0;
+    bool my_keep = false;
+    int nkeep = 0;
+    uint64_t rem = surv;
+    while (rem) {  // uniform loop over survivors
+      const int j = __ffsll((unsigned long long)rem) - 1;
+      rem &= rem - 1;
+      const double cj = lane_f64(bs, j);
+      const uint32_t ij = lane_u32(bid, j);
+      // empty slots hold (-inf, sentinel): never better, never equal
+      int cnt = 0;
+      uint64_t dm = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < nt) {
+          const uint32_t idt = er[t] & kIdMask;
+          cnt += __popcll(__ballot(better(es[t], idt, cj, ij)));
+          dm |= __ballot(idt == ij);
+        }
+      }
+      bool keep = dm == 0;  // not already in the window
+      if constexpr (DEDUP)  // nor kept earlier from this batch
+        keep = keep && __ballot(my_keep && bid == ij) == 0;
+      if (keep) {
+        ++nkeep;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t < nt) sh[t] += (lane + 64 * t >= cnt) ? 1 : 0;
+        my_rank += (bid != kSentinel && better(cj, ij, bs, bid)) ? 1 : 0;
+      }
+      if (lane == j) {
+        my_lb = cnt;
+        my_keep = keep;
+      }
+    }
+    if (nkeep == 0) return;
+    // in place: the whole window was read into registers above
+    double *ls_w = sm.ls();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = lane + 64 * t;
+      if (e < nl && e + sh[t] < L) {
+        ls_w[e + sh[t]] = es[t];
+        lid[e + sh[t]] = er[t];
+      }
+    }
+    if (my_keep && my_lb + my_rank < L) {
+      ls_w[my_lb + my_rank] = bs;
+      lid[my_lb + my_rank] = bid;
+    }
+    nl = nl + nkeep < L ? nl + nkeep : L;
+    wave_sync();
+    return;
+  }
+  sort64(bs, bid, lane);
+  int lb = 0;
+  bool valid = bid != kSentinel;
+  if constexpr (DEDUP) {  // repeats are adjacent after the sort
+    const uint32_t pid = (uint32_t)__shfl_up((int)bid, 1, 64);
+    if (lane > 0 && pid == bid) valid = false;
+  }
+  if (valid) {
+    int lo = 0, hi = nl;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (better(ls[mid], lid[mid] & kIdMask, bs, bid))
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    lb = lo;
+    if (lo < nl && (lid[lo] & kIdMask) == bid) valid = false;  // already in the window
+  }
+  const uint64_t vm = __ballot(valid);
+  const int nv = __popcll(vm);
+  if (nv == 0) return;
+  const int r = lane_rank(vm);
+  if (valid) sm.lbc()[r] = lb;
+  wave_sync();
+  // in place, 64-entry chunks from the end: entry e moves to e + (number
+  // of new entries placed before it), never onto an entry not yet read
+  double *ls_w = sm.ls();
+  for (int c = (nl - 1) >> 6; c >= 0; --c) {
+    const int e = 64 * c + lane;
+    if (e < nl) {
+      const double se = ls[e];
+      const uint32_t ie = lid[e];
+      int lo = 0, hi = nv;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sm.lbc()[mid] <= e)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      const int np = e + lo;
+      if (np < L) {
+        ls_w[np] = se;
+        lid[np] = ie;
+      }
+    }
+  }
+  if (valid && lb + r < L) {
+    ls_w[lb + r] = bs;
+    lid[lb + r] = bid;
+  }
+  nl = nl + nv < L ? nl + nv : L;
+  wave_sync();
+}
+
 // The whole search of one query by one wavefront.  BUILD: construction
 // search for node job.node; the final window goes to job.ids (L entries,
-// padded with the sentinel).
-template <int BITS, int G, int V, bool BUILD = false>
+// padded with the sentinel).  MULTI: the throughput variant that expands up
+// to `expand` entries per iteration (not the paper's traversal).
+template <int BITS, int G, int V, bool BUILD = false, bool MULTI = false>
 __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm, int log2h,
-                             int probes,
-                             int lane) {
+                             int probes, int expand, int lane) {
   constexpr int NQ = V * 8 / BITS;
   const int L = job.L;
   const int hslots = 1 << log2h;
@@ -492,6 +642,77 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
   uint32_t pf_row = kSentinel;
   const uint32_t max_hops = ix.N + 1u;  // every node is expanded at most once
 
+  if constexpr (MULTI) {
+    for (uint32_t hop = 0; hop < max_hops; ++hop) {
+      // the first `expand` unexpanded entries in window order, flagged and
+      // listed in xid[]
+      uint32_t *lid = sm.lid();
+      int ne = 0;
+      for (int base = 0; base < nl && ne < expand; base += 64) {
+        const int i = base + lane;
+        const uint32_t v = i < nl ? lid[i] : kExpanded;
+        const bool un = !(v & kExpanded);
+        const uint64_t msk = __ballot(un);
+        const int r = lane_rank(msk);
+        const int need = expand - ne;
+        if (un && r < need) {
+          lid[i] = v | kExpanded;
+          sm.xid()[ne + r] = v;
+        }
+        const int c = __popcll(msk);
+        ne += c < need ? c : need;
+      }
+      if (ne == 0) break;
+      wave_sync();
+      n_exp += (uint32_t)ne;
+      // the first 64 ids of every row are requested before any is used
+      uint32_t first[kMaxExpand];
+#pragma unroll
+      for (int e = 0; e < kMaxExpand; ++e) {
+        first[e] = kSentinel;
+        if (e < ne && lane < ix.R)
+          first[e] = gp(ix.adj)[(size_t)sm.xid()[e] * (size_t)ix.R + lane];
+      }
+      // fresh ids of the rows, in order, collected into batches of <= 64;
+      // the batch is scored and merged when the next chunk would not fit,
+      // and after the last chunk (one scoring / merge site)
+      int nc = 0, e = 0, rb = 0;
+      for (;;) {
+        const bool more = e < ne;  // uniform
+        uint32_t n = kSentinel;
+        if (more) {
+          if (rb == 0)
+            n = first[0];
+          else if (rb + lane < ix.R)
+            n = gp(ix.adj)[(size_t)sm.xid()[e] * (size_t)ix.R + rb + lane];
+        }
+        bool fresh = false;
+        if (n < ix.N) fresh = hash_visit(sm.hash(), log2h, probes, n);
+        const uint64_t fm = __ballot(fresh);
+        const int cnt = __popcll(fm);
+        if (!more || nc + cnt > 64) {
+          if (nc > 0) {
+            wave_sync();
+            score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), nc, lane);
+            wave_sync();
+            n_dist += nc;
+            merge_batch<true>(sm, nc, L, nl, lane);
+            nc = 0;
+          }
+          if (!more) break;
+        }
+        if (fresh) sm.cid()[nc + lane_rank(fm)] = n;
+        nc += cnt;
+        rb += 64;
+        if (rb >= ix.R) {  // next row: its first chunk moves to first[0]
+          rb = 0;
+          ++e;
+#pragma unroll
+          for (int t = 0; t + 1 < kMaxExpand; ++t) first[t] = first[t + 1];
+        }
+      }
+    }
+  } else {
   for (uint32_t hop = 0; hop < max_hops; ++hop) {
     const double *ls = sm.ls();
     uint32_t *lid = sm.lid();
@@ -544,139 +765,9 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
       wave_sync();
       n_dist += nc;
 
-      // merge the scored batch into the window
-      double bs = -INFINITY;
-      uint32_t bid = kSentinel;
-      if (lane < nc) {
-        bs = sm.cs()[lane];
-        bid = sm.cid()[lane];
-      }
-      if (nl == L && bid != kSentinel && !better(bs, bid, ls[L - 1], lid[L - 1] & kIdMask)) {
-        bs = -INFINITY;
-        bid = kSentinel;
-      }
-      const uint64_t surv = __ballot(bid != kSentinel);
-      if (surv == 0) continue;
-      const int nsurv = __popcll(surv);
-      if (nsurv <= kFastMerge && nl <= 256) {
-        // Few survivors (the common case once the window is full): a survivor
-        // lands at (#window entries better) + (#kept survivors better), a
-        // window entry moves down by the kept survivors better than it.  The
-        // window is read into registers; survivors are broadcast one by one.
-        const int nt = (nl + 63) >> 6;  // 64-entry chunks in use (uniform)
-        double es[4];
-        uint32_t er[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int e = lane + 64 * t;
-          const bool ok = e < nl;
-          es[t] = ok ? ls[e] : -INFINITY;
-          er[t] = ok ? lid[e] : kSentinel;
-        }
-        int sh[4] = {0, 0, 0, 0};  // kept survivors better than window entry t
-        int my_lb = 0, my_rank = 0;
-        bool my_keep = false;
-        int nkeep = 0;
-        uint64_t rem = surv;
-        while (rem) {  // uniform loop over survivors
-          const int j = __ffsll((unsigned long long)rem) - 1;
-          rem &= rem - 1;
-          const double cj = lane_f64(bs, j);
-          const uint32_t ij = lane_u32(bid, j);
-          // empty slots hold (-inf, sentinel): never better, never equal
-          int cnt = 0;
-          uint64_t dm = 0;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            if (t < nt) {
-              const uint32_t idt = er[t] & kIdMask;
-              cnt += __popcll(__ballot(better(es[t], idt, cj, ij)));
-              dm |= __ballot(idt == ij);
-            }
-          }
-          const bool keep = dm == 0;  // not already in the window
-          if (keep) {
-            ++nkeep;
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-              if (t < nt) sh[t] += (lane + 64 * t >= cnt) ? 1 : 0;
-            my_rank += (bid != kSentinel && better(cj, ij, bs, bid)) ? 1 : 0;
-          }
-          if (lane == j) {
-            my_lb = cnt;
-            my_keep = keep;
-          }
-        }
-        if (nkeep == 0) continue;
-        // in place: the whole window was read into registers above
-        double *ls_w = sm.ls();
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int e = lane + 64 * t;
-          if (e < nl && e + sh[t] < L) {
-            ls_w[e + sh[t]] = es[t];
-            lid[e + sh[t]] = er[t];
-          }
-        }
-        if (my_keep && my_lb + my_rank < L) {
-          ls_w[my_lb + my_rank] = bs;
-          lid[my_lb + my_rank] = bid;
-        }
-        nl = nl + nkeep < L ? nl + nkeep : L;
-        wave_sync();
-        continue;
-      }
-      sort64(bs, bid, lane);
-      int lb = 0;
-      bool valid = bid != kSentinel;
-      if (valid) {
-        int lo = 0, hi = nl;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (better(ls[mid], lid[mid] & kIdMask, bs, bid))
-            lo = mid + 1;
-          else
-            hi = mid;
-        }
-        lb = lo;
-        if (lo < nl && (lid[lo] & kIdMask) == bid) valid = false;  // already in the window
-      }
-      const uint64_t vm = __ballot(valid);
-      const int nv = __popcll(vm);
-      if (nv == 0) continue;
-      const int r = lane_rank(vm);
-      if (valid) sm.lbc()[r] = lb;
-      wave_sync();
-      // in place, 64-entry chunks from the end: entry e moves to e + (number
-      // of new entries placed before it), never onto an entry not yet read
-      double *ls_w = sm.ls();
-      for (int c = (nl - 1) >> 6; c >= 0; --c) {
-        const int e = 64 * c + lane;
-        if (e < nl) {
-          const double se = ls[e];
-          const uint32_t ie = lid[e];
-          int lo = 0, hi = nv;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (sm.lbc()[mid] <= e)
-              lo = mid + 1;
-            else
-              hi = mid;
-          }
-          const int np = e + lo;
-          if (np < L) {
-            ls_w[np] = se;
-            lid[np] = ie;
-          }
-        }
-      }
-      if (valid && lb + r < L) {
-        ls_w[lb + r] = bs;
-        lid[lb + r] = bid;
-      }
-      nl = nl + nv < L ? nl + nv : L;
-      wave_sync();
+      merge_batch(sm, nc, L, nl, lane);
     }
+  }
   }
 
   if constexpr (BUILD) {
@@ -755,9 +846,10 @@ struct PlainArgs {
   uint32_t *counters;
   int32_t hash_log2;
   int32_t probes;
+  int32_t expand;
 };
 
-template <int BITS, int G, int V>
+template <int BITS, int G, int V, bool MULTI>
 __global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
   const int64_t qi = blockIdx.x;
   if (qi >= a.m) return;
@@ -770,7 +862,8 @@ __global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
   job.ids = a.ids + qi * a.k;
   job.scores = a.scores + qi * a.k;
   job.counters = a.counters ? a.counters + 2 * qi : nullptr;
-  search_query<BITS, G, V>(a.ix, job, sm, a.hash_log2, a.probes, threadIdx.x);
+  search_query<BITS, G, V, false, MULTI>(a.ix, job, sm, a.hash_log2, a.probes, a.expand,
+                                         threadIdx.x);
 }
 
 // Batched form over a step's request table.  With a counter (persistent
@@ -784,11 +877,12 @@ __global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
 template <int BITS, int V>
 constexpr int batched_waves() { return BITS == 8 ? 5 : 4; }
 
-template <int BITS, int G, int V>
+template <int BITS, int G, int V, bool MULTI>
 __global__ __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(batched_waves<BITS, V>()))) void batched_kernel(
     const StepHeader *__restrict__ hdr, const IndexView *__restrict__ subs,
-    unsigned int *__restrict__ counter, int32_t Lmax, int32_t hash_log2, int32_t probes) {
+    unsigned int *__restrict__ counter, int32_t Lmax, int32_t hash_log2, int32_t probes,
+    int32_t expand) {
   const int lane = threadIdx.x;
   const Lds sm = carve(Lmax);
   const int64_t nq = hdr->nq;
@@ -830,7 +924,7 @@ __attribute__((amdgpu_waves_per_eu(batched_waves<BITS, V>()))) void batched_kern
     job.ids = hdr->ids + r.out_off + j * r.k;
     job.scores = hdr->scores + r.out_off + j * r.k;
     job.counters = hdr->counters ? hdr->counters + 2 * (int64_t)u : nullptr;
-    search_query<BITS, G, V>(ix, job, sm, hash_log2, probes, lane_q);
+    search_query<BITS, G, V, false, MULTI>(ix, job, sm, hash_log2, probes, expand, lane_q);
   }
 }
 
@@ -852,7 +946,7 @@ __global__ __launch_bounds__(64) void build_search_kernel(BuildSearchArgs a) {
   job.scores = nullptr;
   job.counters = a.counters ? a.counters + 2 * (size_t)b : nullptr;
   job.node = p;
-  search_query<BITS, G, V, true>(a.ix, job, carve(a.L), a.hash_log2, a.probes, threadIdx.x);
+  search_query<BITS, G, V, true>(a.ix, job, carve(a.L), a.hash_log2, a.probes, 1, threadIdx.x);
   for (int r = threadIdx.x; r < a.ix.R; r += 64)
     gpw(job.ids)[a.L + r] = gp(a.ix.adj)[(size_t)p * (size_t)a.ix.R + r];
   if (a.stats && job.counters && threadIdx.x == 0) {  // the lane that wrote the counters
@@ -866,7 +960,12 @@ __global__ void reset_counter_kernel(unsigned int *counter) { *counter = 0u; }
 
 template <int BITS, int G, int V>
 int launch_plain_t(const PlainArgs &a, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((beam_kernel<BITS, G, V>), dim3((unsigned)a.m), dim3(64), lds, s, a);
+  if (a.expand > 1)
+    hipLaunchKernelGGL((beam_kernel<BITS, G, V, true>), dim3((unsigned)a.m), dim3(64), lds, s,
+                       a);
+  else
+    hipLaunchKernelGGL((beam_kernel<BITS, G, V, false>), dim3((unsigned)a.m), dim3(64), lds, s,
+                       a);
   LV_CHECK_LAUNCH();
   return LV_OK;
 }
@@ -875,16 +974,21 @@ template <int BITS, int G, int V>
 int launch_batched_t(const StepHeader *hdr, const IndexView *subs, unsigned int *counter,
                         int Lmax, VisitedCfg vc, size_t lds, int grid, hipStream_t s) {
   if (counter) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
-  hipLaunchKernelGGL((batched_kernel<BITS, G, V>), dim3(grid), dim3(64), lds, s, hdr, subs,
-                     counter, Lmax, vc.log2h, vc.probes);
+  if (vc.expand > 1)
+    hipLaunchKernelGGL((batched_kernel<BITS, G, V, true>), dim3(grid), dim3(64), lds, s, hdr,
+                       subs, counter, Lmax, vc.log2h, vc.probes, vc.expand);
+  else
+    hipLaunchKernelGGL((batched_kernel<BITS, G, V, false>), dim3(grid), dim3(64), lds, s, hdr,
+                       subs, counter, Lmax, vc.log2h, vc.probes, vc.expand);
   LV_CHECK_LAUNCH();
   return LV_OK;
 }
 
 template <int BITS, int G, int V>
-int occupancy_t(size_t lds, int *blocks) {
-  LV_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks, reinterpret_cast<const void *>(batched_kernel<BITS, G, V>), 64, lds));
+int occupancy_t(size_t lds, bool multi, int *blocks) {
+  const void *k = multi ? reinterpret_cast<const void *>(batched_kernel<BITS, G, V, true>)
+                        : reinterpret_cast<const void *>(batched_kernel<BITS, G, V, false>);
+  LV_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, 64, lds));
   return LV_OK;
 }
 
@@ -941,9 +1045,10 @@ struct BuildLaunch {
 
 struct Occupancy {
   size_t lds;
+  bool multi;
   int *blocks;
   template <int B, int GG, int VV>
-  int operator()() { return occupancy_t<B, GG, VV>(lds, blocks); }
+  int operator()() { return occupancy_t<B, GG, VV>(lds, multi, blocks); }
 };
 
 }  // namespace
@@ -976,6 +1081,10 @@ int visited_config(const lv_search_params *params, VisitedCfg *cfg) {
     LV_FAIL(LV_EINVAL, "hash_slots must be a power of two in [256, 65536] (got %d)", hs);
   const int pr = params ? params->probes : 0;
   if (pr < 0 || pr > 16) LV_FAIL(LV_EINVAL, "probes must be in [0, 16] (got %d)", pr);
+  const int ex = params ? params->expand : 0;
+  if (ex < 0 || ex > kMaxExpand)
+    LV_FAIL(LV_EINVAL, "expand must be in [0, %d] (got %d)", kMaxExpand, ex);
+  cfg->expand = ex > 1 ? ex : 1;
   int l = 0;
   while ((1 << l) < hs) ++l;
   cfg->log2h = l;
@@ -985,7 +1094,7 @@ int visited_config(const lv_search_params *params, VisitedCfg *cfg) {
 }
 
 size_t beam_lds_bytes(int L, int log2h) {
-  return (size_t)L * 12 + 64 * 12 + ((size_t)4 << log2h);
+  return (size_t)L * 12 + 64 * 12 + 4 * kMaxExpand + ((size_t)4 << log2h);
 }
 
 int check_lds(size_t lds, int L, int log2h) {
@@ -1021,6 +1130,7 @@ int launch_beam(const lv_index *ix, const float *Q, const float *Qp, int64_t m, 
   a.counters = counters;
   a.hash_log2 = vc.log2h;
   a.probes = vc.probes;
+  a.expand = vc.expand;
   PlainLaunch f{a, lds, stream};
   return dispatch(ix->desc.bits, ix->group, ix->vbytes, f);
 }
@@ -1041,11 +1151,11 @@ int launch_build_search(int bits, int group, int vbytes, const BuildSearchArgs &
   return dispatch(bits, group, vbytes, f);
 }
 
-int batched_occupancy(int bits, int group, int vbytes, int Lmax, int log2h, int *blocks) {
-  const size_t lds = beam_lds_bytes(Lmax, log2h);
-  int rc = check_lds(lds, Lmax, log2h);
+int batched_occupancy(int bits, int group, int vbytes, int Lmax, VisitedCfg vc, int *blocks) {
+  const size_t lds = beam_lds_bytes(Lmax, vc.log2h);
+  int rc = check_lds(lds, Lmax, vc.log2h);
   if (rc != LV_OK) return rc;
-  Occupancy f{lds, blocks};
+  Occupancy f{lds, vc.expand > 1, blocks};
   return dispatch(bits, group, vbytes, f);
 }
 

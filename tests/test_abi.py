@@ -84,9 +84,15 @@ def test_search_argument_validation_before_launch():
         assert rc == lv.LV_EINVAL, (m, k, L)
     for bad in (lv.SearchParams(1000, 0, 0),   # slots not a power of two
                 lv.SearchParams(1024, 17, 0),  # too many probes
-                lv.SearchParams(1024, -1, 0)):
+                lv.SearchParams(1024, -1, 0),
+                lv.SearchParams(1024, 0, 0, 9),    # more expansions per step than allowed
+                lv.SearchParams(1024, 0, 0, -1)):
         assert lib.lv_search_projected(h, FAKE, FAKE, 10, 5, 50, FAKE, FAKE, None,
                                        ctypes.byref(bad), None) == lv.LV_EINVAL
+        # refused before the query projection is launched
+        ws = lib.lv_search_workspace_size(h, 10)
+        assert lib.lv_search(h, FAKE, 10, 5, 50, FAKE, FAKE, None, FAKE, ws,
+                             ctypes.byref(bad), None) == lv.LV_EINVAL
     # workspace too small
     assert lib.lv_search(h, FAKE, 10, 5, 50, FAKE, FAKE, None, FAKE, 16,
                          ctypes.byref(prm), None) == lv.LV_EINVAL

@@ -46,13 +46,13 @@ def subs(lv):
     return out
 
 
-def plain(lv, ix, Q, k, L, hash_slots=0):
+def plain(lv, ix, Q, k, L, hash_slots=0, expand=0):
     m = len(Q)
     ids = torch.empty((m, k), dtype=torch.int32, device=DEV)
     sc = torch.empty((m, k), dtype=torch.float32, device=DEV)
     cnt = torch.zeros((m, 2), dtype=torch.int32, device=DEV)
     ws = torch.empty(lv.lv_search_workspace_size(ix, m), dtype=torch.uint8, device=DEV)
-    lv.lv_search(ix, Q, k, L, ids, sc, cnt, ws=ws, hash_slots=hash_slots)
+    lv.lv_search(ix, Q, k, L, ids, sc, cnt, ws=ws, hash_slots=hash_slots, expand=expand)
     return ids, sc, cnt
 
 
@@ -74,11 +74,11 @@ def run_step(lv, batch, subs, reqs, cursor):
     return Q, ids, sc, cnt
 
 
-def check_against_plain(lv, subs, reqs, Q, ids, sc, cnt):
+def check_against_plain(lv, subs, reqs, Q, ids, sc, cnt, expand=0):
     torch.cuda.synchronize()
     q0 = o0 = 0
     for sub, k, L, count in reqs:
-        pi, ps, pc = plain(lv, subs[sub][1], Q[q0:q0 + count], k, L)
+        pi, ps, pc = plain(lv, subs[sub][1], Q[q0:q0 + count], k, L, expand=expand)
         torch.cuda.synchronize()
         bi = ids[o0:o0 + count * k].view(count, k)
         bs = sc[o0:o0 + count * k].view(count, k)
@@ -102,6 +102,19 @@ def test_batched_equals_plain_over_consecutive_steps(lv, subs, launch):
     for reqs in steps:
         out = run_step(lv, batch, subs, reqs, cursor)
         check_against_plain(lv, subs, reqs, *out)
+    batch.close()
+    multi.close()
+
+
+@pytest.mark.parametrize("expand", [2, 4])
+def test_batched_equals_plain_with_several_expansions_per_step(lv, subs, expand):
+    multi = lv.Multi([ix for _, ix in subs])
+    batch = lv.Batch(multi, max_requests=8, max_queries=512, max_L=128, expand=expand)
+    cursor = [0, 0, 0]
+    for reqs in ([(0, 10, 40, 17), (1, 1, 20, 33), (2, 100, 128, 70)],
+                 [(2, 10, 64, 31), (0, 5, 5, 3), (1, 10, 96, 50)]):
+        out = run_step(lv, batch, subs, reqs, cursor)
+        check_against_plain(lv, subs, reqs, *out, expand=expand)
     batch.close()
     multi.close()
 

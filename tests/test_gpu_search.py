@@ -42,7 +42,7 @@ def gpu_index(lv, c: Case):
     return lv.Index(rec, mud, sec, adj, c.entry, c.wl.bits, c.wl.d, A_bf16=Pb), rec
 
 
-def run_projected(lv, index, c: Case, k, L, hash_slots=0, Q=None, Qp=None):
+def run_projected(lv, index, c: Case, k, L, hash_slots=0, Q=None, Qp=None, expand=0):
     Q = c.Q if Q is None else Q
     Qp = c.Qp if Qp is None else Qp
     m = len(Q)
@@ -50,7 +50,7 @@ def run_projected(lv, index, c: Case, k, L, hash_slots=0, Q=None, Qp=None):
     sc = torch.full((m, k), 7.0, dtype=torch.float32, device=DEV)
     cnt = torch.zeros((m, 2), dtype=torch.int32, device=DEV)
     lv.lv_search_projected(index, torch.from_numpy(Q).to(DEV), torch.from_numpy(Qp).to(DEV), k, L,
-                           ids, sc, cnt, hash_slots=hash_slots)
+                           ids, sc, cnt, hash_slots=hash_slots, expand=expand)
     torch.cuda.synchronize()
     return (ids.cpu().numpy().view(np.uint32).astype(np.int64), sc.cpu().numpy(),
             cnt.cpu().numpy())
@@ -204,3 +204,31 @@ def test_full_path_recall_matches_oracle(lv, small):
     r_gpu = exact.recall_at_k(got, truth, k)
     r_orc = exact.recall_at_k(want, truth, k)
     assert abs(r_gpu - r_orc) <= 0.005 + 1e-12, (r_gpu, r_orc)
+
+
+@pytest.mark.parametrize("expand", [2, 4, 8])
+@pytest.mark.parametrize("name,N", [("id-1m-768", 6000), ("ood-1m-512", 6000)])
+def test_expand_variant_parity(lv, name, N, expand):
+    """Several expansions per iteration (throughput variant) against the
+    oracle's same variant: ids, scores and expansion / scoring counts."""
+    wl = gen.WORKLOADS[name].scaled(N=N, m_test=40)
+    c = make_case(wl)
+    index, _ = gpu_index(lv, c)
+    oidx = c.oracle_index()
+    for L in (20, 60):
+        want_ids = np.empty((len(c.Q), wl.k), np.int64)
+        want_sc = np.empty((len(c.Q), wl.k))
+        want_cnt = np.empty((len(c.Q), 2), np.int64)
+        for i in range(len(c.Q)):
+            tr = osearch.Trace()
+            want_ids[i], want_sc[i] = osearch.search_one(oidx, c.Q[i], c.Qp[i], wl.k, L, trace=tr,
+                                                         expand=expand)
+            want_cnt[i] = (tr.n_exp, tr.n_dist)
+        got_ids, got_sc, got_cnt = run_projected(lv, index, c, wl.k, L, hash_slots=8192,
+                                                 expand=expand)
+        assert_parity(c, oidx, got_ids, got_sc, want_ids, want_sc)
+        assert np.array_equal(got_cnt, want_cnt)
+        # a small visited set changes nothing but the number of scorings
+        got2 = run_projected(lv, index, c, wl.k, L, hash_slots=256, expand=expand)
+        assert np.array_equal(got2[0], got_ids) and np.array_equal(got2[1], got_sc)
+        assert np.array_equal(got2[2][:, 0], got_cnt[:, 0])
