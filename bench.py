@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--expand", type=int, default=1,
                     help="entries expanded per traversal iteration: 1 = the paper's traversal; "
                          "2..8 = the throughput variant (no CPU baseline)")
+    ap.add_argument("--no-variant", action="store_true",
+                    help="skip timing the four-expansion traversal variant")
     ap.add_argument("--graph", choices=("cpu", "gpu"), default="cpu",
                     help="index graph: the host builder on float16 vectors (cached), or "
                          "lv_graph_build on the primary vectors (timed)")
@@ -466,11 +468,12 @@ def main():
     outs = [(ids_flat, scores_flat)] + [(torch.empty_like(ids_flat), torch.empty_like(scores_flat))
                                         for _ in range(IN_FLIGHT - 1)]
 
-    def run_pipelined(n, evs=None):
+    def run_pipelined(n, evs=None, b=None):
+        b = batch if b is None else b
         for i_ in range(n):
             o_ = outs[i_ % IN_FLIGHT]
-            batch.step(reqs, Qd, o_[0], o_[1], stream=strs[i_ % IN_FLIGHT],
-                       events=None if evs is None else evs[i_])
+            b.step(reqs, Qd, o_[0], o_[1], stream=strs[i_ % IN_FLIGHT],
+                   events=None if evs is None else evs[i_])
 
     for s_ in strs[1:]:
         s_.wait_stream(stream)
@@ -509,6 +512,38 @@ def main():
     traffic = profile_traffic(os.path.join(ROOT, "paper_2312_16335_amd", "csrc", "lv_search.hip"),
                               L_star, hs, launch_name) if smud is None else None
     batch.close()
+
+    # the throughput variant (four expansions per iteration) at the same window,
+    # timed the same way; reported beside the paper's traversal, not as `value`
+    variant = None
+    if args.expand <= 1 and not args.no_variant:
+        bv = lv.Batch(multi, max_requests=nreq, max_queries=m, max_L=L_star, hash_slots=hs,
+                      launch=launch, expand=4)
+        for s_ in strs[1:]:
+            s_.wait_stream(stream)
+        run_pipelined(max(IN_FLIGHT, args.warmup), b=bv)
+        for s_ in strs[1:]:
+            stream.wait_stream(s_)
+        torch.cuda.synchronize()
+        tv = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        v0, v1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        v0.record(stream)
+        for s_ in strs[1:]:
+            s_.wait_event(v0)
+        run_pipelined(args.steps, tv, b=bv)
+        for s_ in strs[1:]:
+            stream.wait_stream(s_)
+        v1.record(stream)
+        torch.cuda.synchronize()
+        vgot = outs[0][0].view(m, k).cpu().numpy().view(np.uint32).astype(np.int64)
+        vms = v0.elapsed_time(v1)
+        variant = {"expand": 4, "L": L_star, "recall": recall(vgot, truth, k),
+                   "qps": m * args.steps / (vms / 1e3), "ms_per_step": vms / args.steps,
+                   "traversal_launch_ms": tv[0][0].elapsed_time(tv[-1][1]) / args.steps}
+        bv.close()
+        log(f"variant expand=4 at L={L_star}: recall {variant['recall']:.4f}, "
+            f"{variant['qps']:.0f} QPS")
     multi.close()
 
     # reference: the plain path as one launch pair over all queries
@@ -591,6 +626,7 @@ def main():
                         "graph_build_work": g.get("stats"),
                         "graph_build_repeatable": g.get("deterministic")},
         "cpu_baseline": cpu,
+        "traversal_variant": variant,
     }
     print(json.dumps(out))
 
