@@ -49,6 +49,7 @@ class Index:
     sec_delta: Optional[np.ndarray] = None   # float32 [N]  LVQ-8 secondaries (Section 3:
     sec_lo: Optional[np.ndarray] = None      # float32 [N]  secondary vectors compressed
     sec_mu: Optional[np.ndarray] = None      # float32 [D]  with LVQ-8)
+    sec_resid: bool = False  # sec holds only the D - d residual coordinates (see below)
 
     @property
     def N(self) -> int:
@@ -84,10 +85,19 @@ def primary_scores(index: Index, qp64: np.ndarray, ids) -> np.ndarray:
     return rowdot(yhat, qp64)
 
 
-def secondary_scores(index: Index, q64: np.ndarray, ids) -> np.ndarray:
+def secondary_scores(index: Index, q64: np.ndarray, ids, qp64=None) -> np.ndarray:
     """<q, secondary(n)> in float64 (Section 2, re-ranking); an LVQ-8 secondary
-    is its reconstruction mu + lo + delta * c."""
+    is its reconstruction mu + lo + delta * c.
+
+    Residual secondaries (sec_resid; the remark after Eq. pca: with an
+    orthonormal M the error e = (I - M^T M) x needs only D - d coordinates):
+    with R = [P; P_perp] orthonormal, <q, x> = <P q, P x> + <P_perp q, P_perp x>;
+    sec holds P_perp x, q64 is P_perp q, and the first term is taken from the
+    primary vector, so the score is the primary score <qp, y^> (qp64 = P q)
+    plus <q64, sec(n)>."""
     ids = np.asarray(ids, dtype=np.int64)
+    if index.sec_resid:
+        return primary_scores(index, qp64, ids) + rowdot(index.sec[ids], q64)
     if index.sec_delta is None:
         return rowdot(index.sec[ids], q64)
     xhat = (index.sec_mu.astype(np.float64)[None, :]
@@ -179,14 +189,16 @@ def beam(index: Index, qp, L: int, visited_cap: Optional[int] = None,
     return [(-k, i) for k, i in keys]
 
 
-def rerank(index: Index, q, cand_ids, k: int) -> Tuple[np.ndarray, np.ndarray]:
-    """Top-k of the candidates by secondary score (ties: smaller id)."""
+def rerank(index: Index, q, cand_ids, k: int, qp=None) -> Tuple[np.ndarray, np.ndarray]:
+    """Top-k of the candidates by secondary score (ties: smaller id).  With
+    residual secondaries q is the residual query and qp the primary one."""
     q64 = np.asarray(q, dtype=np.float32).astype(np.float64)
+    qp64 = None if qp is None else np.asarray(qp, dtype=np.float32).astype(np.float64)
     ids = np.asarray(cand_ids, dtype=np.int64)
     out_i = np.full(k, SENTINEL, dtype=np.int64)
     out_s = np.full(k, -np.inf)
     if ids.size:
-        s2 = secondary_scores(index, q64, ids)
+        s2 = secondary_scores(index, q64, ids, qp64)
         order = np.lexsort((ids, -s2))[:k]
         out_i[:len(order)] = ids[order]
         out_s[:len(order)] = s2[order]
@@ -198,7 +210,7 @@ def search_one(index: Index, q, qp, k: int, L: int, visited_cap=None, trace=None
     if L < k:
         raise ValueError("window L must be at least k")
     lst = beam(index, qp, L, visited_cap=visited_cap, trace=trace, expand=expand)
-    return rerank(index, q, [i for _, i in lst], k)
+    return rerank(index, q, [i for _, i in lst], k, qp)
 
 
 def flat_search(index: Index, q, qp, k: int, L: int):
@@ -206,7 +218,7 @@ def flat_search(index: Index, q, qp, k: int, L: int):
     qp64 = np.asarray(qp, dtype=np.float32).astype(np.float64)
     s = primary_scores(index, qp64, np.arange(index.N))
     order = np.lexsort((np.arange(index.N), -s))[:L]
-    return rerank(index, q, order, k)
+    return rerank(index, q, order, k, qp)
 
 
 # ---------------------------------------------------------------------------
@@ -216,11 +228,11 @@ def flat_search(index: Index, q, qp, k: int, L: int):
 _G = {}
 
 
-def _init_worker(paths, entry):
+def _init_worker(paths, entry, sec_resid=False):
     arrs = {k: np.load(v, mmap_mode="r") for k, v in paths.items()}
     _G["index"] = Index(arrs["adj"], entry, arrs["codes"], arrs["delta"], arrs["lo"],
                         arrs["mu"], arrs["sec"], arrs.get("sec_delta"), arrs.get("sec_lo"),
-                        arrs.get("sec_mu"))
+                        arrs.get("sec_mu"), sec_resid)
 
 
 def _run_chunk(args):
@@ -270,7 +282,8 @@ def search_many(index: Index, Q, Qp, k: int, L: int, procs: int = 1,
         # a worker that dies raises BrokenProcessPool here instead of hanging
         with ProcessPoolExecutor(procs, mp_context=mp.get_context("spawn"),
                                  initializer=_init_worker,
-                                 initargs=(paths, int(index.entry))) as pool:
+                                 initargs=(paths, int(index.entry),
+                                           bool(index.sec_resid))) as pool:
             jobs = [(Q[lo:lo + chunk], Qp[lo:lo + chunk], k, L, lo) for lo in range(0, m, chunk)]
             for lo, a, b, c in pool.map(_run_chunk, jobs):
                 ids[lo:lo + len(a)], sc[lo:lo + len(a)], cnt[lo:lo + len(a)] = a, b, c

@@ -210,3 +210,50 @@ def test_expand_variant_invariants(tiny, expand):
         top = sorted(tr.scored.items(), key=lambda kv: (-kv[1], kv[0]))[:24]
         assert [j for j, _ in top] == [j for _, j in lst]
         assert search.beam(idx, Qp[i], 24, visited_cap=40, expand=expand) == lst
+
+
+def _resid_index(tiny):
+    """The tiny workload with residual secondaries: P_full = all D eigenvectors,
+    primaries from the first d rows, secondaries = the other D - d coordinates."""
+    wl, idx, Q, Qp = tiny
+    mix = gen.mixture(wl)
+    X = gen.database(wl, mix)
+    Pf = ofit.fit_id(ofit.second_moment(X), wl.D)
+    P, Pp = Pf[:wl.d], Pf[wl.d:]
+    Y = ofit.project(X, P).astype(np.float32)
+    mu = ofit.mean_reduced(X, P).astype(np.float32)
+    codes, delta, lo = lvq.encode(Y, mu, wl.bits)
+    sec = ofit.project(X, Pp)  # float64 residual coordinates
+    ridx = search.Index(idx.adj, idx.entry, codes, delta, lo, mu, sec, sec_resid=True)
+    return ridx, X, P, Pp
+
+
+def test_residual_secondaries_decompose_the_inner_product(tiny):
+    wl, _, Q, _ = tiny
+    ridx, X, P, Pp = _resid_index(tiny)
+    # the basis is orthonormal and complete
+    Pf = np.vstack([P, Pp])
+    assert np.allclose(Pf @ Pf.T, np.eye(wl.D), atol=1e-10)
+    ids = np.arange(0, ridx.N, 7)
+    for q in Q[:3].astype(np.float64):
+        qp, qr = P @ q, Pp @ q
+        got = search.secondary_scores(ridx, qr, ids, qp)
+        # = primary score + <P_perp q, P_perp x>, and the exact inner product
+        # differs from it by the LVQ error of the primary part only
+        prim = search.primary_scores(ridx, qp, ids)
+        exact_ip = X[ids].astype(np.float64) @ q
+        true_prim = (X[ids].astype(np.float64) @ P.T) @ qp
+        assert np.allclose(got - prim, exact_ip - true_prim, rtol=0, atol=1e-9)
+
+
+def test_residual_secondaries_full_window_equals_brute_force(tiny):
+    wl, _, Q, _ = tiny
+    ridx, X, P, Pp = _resid_index(tiny)
+    for q in Q[:3].astype(np.float32):
+        qp = (P @ q.astype(np.float64)).astype(np.float32)
+        qr = (Pp @ q.astype(np.float64)).astype(np.float32)
+        ids, sc = search.search_one(ridx, qr, qp, wl.k, ridx.N)
+        s = search.secondary_scores(ridx, qr.astype(np.float64), np.arange(ridx.N),
+                                    qp.astype(np.float64))
+        want = np.lexsort((np.arange(ridx.N), -s))[:wl.k]
+        assert ids.tolist() == want.tolist()
