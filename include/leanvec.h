@@ -49,6 +49,7 @@ extern "C" {
 #define LV_F32 0
 #define LV_F16 1
 #define LV_LVQ8 2 /* secondary vectors compressed with LVQ-8 */
+#define LV_F16_RESID 3 /* float16 residual coordinates: only D - d per vector (see below) */
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int lv_version(void);
@@ -216,12 +217,15 @@ typedef struct {
   int32_t record_stride;   /* bytes per primary record (lv_record_stride) */
   const void *records;     /* [N][record_stride] LVQ records */
   const float *mu;         /* [d] LVQ centring vector */
-  int32_t sec_dtype;       /* LV_F32, LV_F16 or LV_LVQ8 */
-  const void *secondaries; /* [N][lv_secondary_row_bytes(D, sec_dtype)] bytes */
+  int32_t sec_dtype;       /* LV_F32, LV_F16, LV_LVQ8 or LV_F16_RESID */
+  const void *secondaries; /* [N][lv_secondary_row_bytes(D, sec_dtype)] bytes
+                              (D - d in place of D for LV_F16_RESID) */
   int32_t R;               /* graph out-degree, 1..1024 */
   const uint32_t *adjacency; /* [N][R]; valid ids first, then LV_SENTINEL */
   uint32_t entry;          /* traversal start node */
-  const uint16_t *A;       /* [d][D] bfloat16 query projection, or NULL */
+  const uint16_t *A;       /* [d][D] bfloat16 query projection, or NULL; for
+                              LV_F16_RESID [D][D]: the primary projection's d rows
+                              followed by D - d rows completing an orthonormal basis */
   const float *sec_mu;     /* [D] centring vector of LV_LVQ8 secondaries, else NULL */
 } lv_index_desc;
 
@@ -233,6 +237,13 @@ typedef struct {
  * D + 16) and scored as <q, sec_mu + lo + delta * c>.  Returns 0 when the
  * search kernels do not support the combination (rows above 2 KiB, or
  * LV_LVQ8 with D not a multiple of 16 or above 1008).
+ *
+ * LV_F16_RESID (LeanVec-ID, A = B = P with orthonormal rows; the remark after
+ * Eq. pca that the error (I - P^T P) x needs only D - d coordinates): with
+ * R = [P; P_perp] orthonormal, <q, x> = <P q, P x> + <P_perp q, P_perp x>.
+ * A secondary row holds P_perp x in float16 (2 (D - d) bytes: pass D - d here),
+ * and the re-rank score is the traversal's primary score <P q, y^> plus
+ * <P_perp q, P_perp x>, so the first d coordinates are not stored twice.
  */
 int32_t lv_secondary_row_bytes(int32_t D, int32_t sec_dtype);
 
@@ -290,7 +301,9 @@ int lv_search(const lv_index *index, const float *Q, int64_t m, int32_t k, int32
 
 /*
  * The same search with the projected queries supplied by the caller
- * (Qp: device float32 [m][d]); Q is still needed for the re-ranking.
+ * (Qp: device float32 [m][d]); Q is still needed for the re-ranking.  With
+ * LV_F16_RESID secondaries Qp rows hold D values, P q then P_perp q (what
+ * lv_search computes with the [D][D] matrix A), and Q is not read.
  */
 int lv_search_projected(const lv_index *index, const float *Q, const float *Qp, int64_t m,
                         int32_t k, int32_t L, uint32_t *ids, float *scores, uint32_t *counters,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "liblv.so")
 
 LV_OK, LV_WNOTCONVERGED = 0, 1
 LV_EINVAL, LV_ENOMEM, LV_EDEVICE, LV_EUNSUPPORTED = -1, -2, -3, -4
-LV_F32, LV_F16, LV_LVQ8 = 0, 1, 2
+LV_F32, LV_F16, LV_LVQ8, LV_F16_RESID = 0, 1, 2, 3
 LV_LAUNCH_PER_QUERY, LV_LAUNCH_PERSISTENT = 0, 1
 LV_SENTINEL = 0xFFFFFFFF
 LV_FW_INIT_ES, LV_FW_INIT_ZERO, LV_FW_INIT_GIVEN = 0, 1, 2
@@ -338,13 +338,16 @@ class Index:
     """Handle over device arrays (borrowed: keep the tensors alive)."""
 
     def __init__(self, records, mu, secondaries, adjacency, entry: int, bits: int, d: int,
-                 A_bf16=None, sec_mu=None):
+                 A_bf16=None, sec_mu=None, residual: bool = False):
         """secondaries: float16 or float32 [N][D], or (with sec_mu, float32 [D]) uint8
-        LVQ-8 rows [N][D + 16] from lv_lvq_encode."""
+        LVQ-8 rows [N][D + 16] from lv_lvq_encode, or (residual=True) float16
+        residual coordinates [N][D - d] with A_bf16 the [D][D] basis."""
         import torch
 
         N = secondaries.shape[0]
-        if sec_mu is not None:
+        if residual:
+            sec_dtype, D = LV_F16_RESID, secondaries.shape[1] + d
+        elif sec_mu is not None:
             sec_dtype, D = LV_LVQ8, sec_mu.shape[0]
         else:
             sec_dtype = LV_F16 if secondaries.dtype == torch.float16 else LV_F32

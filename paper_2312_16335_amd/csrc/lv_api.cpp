@@ -13,8 +13,11 @@ int validate_desc(const lv_index_desc *d, lv_index *ix) {
   if (d->d < 8 || d->d % 8 != 0) LV_FAIL(LV_EINVAL, "d must be a positive multiple of 8");
   if (d->D < d->d) LV_FAIL(LV_EINVAL, "D must be >= d");
   if (d->bits != 4 && d->bits != 8) LV_FAIL(LV_EINVAL, "bits must be 4 or 8");
-  if (d->sec_dtype != LV_F32 && d->sec_dtype != LV_F16 && d->sec_dtype != LV_LVQ8)
+  if (d->sec_dtype != LV_F32 && d->sec_dtype != LV_F16 && d->sec_dtype != LV_LVQ8 &&
+      d->sec_dtype != LV_F16_RESID)
     LV_FAIL(LV_EINVAL, "bad sec_dtype");
+  const bool resid = d->sec_dtype == LV_F16_RESID;
+  if (resid && d->D <= d->d) LV_FAIL(LV_EINVAL, "LV_F16_RESID needs D > d");
   if (d->sec_dtype == LV_LVQ8 && !d->sec_mu) LV_FAIL(LV_EINVAL, "LV_LVQ8 secondaries need sec_mu");
   if (d->R < 1 || d->R > 1024) LV_FAIL(LV_EINVAL, "R must be in [1, 1024]");
   if ((uint64_t)d->entry >= (uint64_t)d->N) LV_FAIL(LV_EINVAL, "entry out of range");
@@ -35,7 +38,7 @@ int validate_desc(const lv_index_desc *d, lv_index *ix) {
       LV_FAIL(LV_EUNSUPPORTED, "record_stride %d unsupported (use lv_record_stride)",
               d->record_stride);
   }
-  const int64_t row_bytes = lv_secondary_row_bytes(d->D, d->sec_dtype);
+  const int64_t row_bytes = lv_secondary_row_bytes(resid ? d->D - d->d : d->D, d->sec_dtype);
   if (row_bytes == 0)
     LV_FAIL(LV_EUNSUPPORTED, "secondary rows of D = %d and type %d are not supported", d->D,
             d->sec_dtype);
@@ -45,6 +48,7 @@ int validate_desc(const lv_index_desc *d, lv_index *ix) {
   ix->group = group;
   ix->vbytes = vbytes;
   ix->sec_packets = (int32_t)(row_bytes / 16);
+  ix->qp_width = resid ? d->D : d->d;
   return LV_OK;
 }
 
@@ -65,7 +69,7 @@ extern "C" int32_t lv_secondary_row_bytes(int32_t D, int32_t sec_dtype) {
   int64_t b = 0;
   if (D < 1) return 0;
   if (sec_dtype == LV_F32) b = 4 * (int64_t)D;
-  else if (sec_dtype == LV_F16) b = 2 * (int64_t)D;
+  else if (sec_dtype == LV_F16 || sec_dtype == LV_F16_RESID) b = 2 * (int64_t)D;
   else if (sec_dtype == LV_LVQ8) b = D % 16 == 0 && D <= 1008 ? (int64_t)D + 16 : 0;
   if (b == 0 || b % 16 != 0 || b > 2048) return 0;
   return (int32_t)b;
@@ -92,7 +96,7 @@ extern "C" int lv_index_destroy(lv_index *index) {
 
 extern "C" size_t lv_search_workspace_size(const lv_index *index, int64_t m) {
   if (!index || m < 0) return 0;
-  const size_t b = (size_t)m * (size_t)index->desc.d * sizeof(float);
+  const size_t b = (size_t)m * (size_t)index->qp_width * sizeof(float);
   return (b + 255) & ~(size_t)255;
 }
 
@@ -112,7 +116,7 @@ extern "C" int lv_search(const lv_index *index, const float *Q, int64_t m, int32
   if (rc != LV_OK) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   float *Qp = static_cast<float *>(ws);
-  rc = lv::launch_project(Q, m, index->desc.D, index->desc.A, index->desc.d, Qp, s);
+  rc = lv::launch_project(Q, m, index->desc.D, index->desc.A, index->qp_width, Qp, s);
   if (rc != LV_OK) return rc;
   return lv::launch_beam(index, Q, Qp, m, k, L, ids, scores, counters, params, s);
 }

@@ -23,6 +23,7 @@ struct lv_multi {
   std::vector<const lv_index *> subs;
   lv::IndexView *d_views = nullptr;  // device copy of the views
   int bits = 0, group = 0, vbytes = 0, D = 0, d = 0;
+  int pw = 0;  // projected query width: d, or D with residual secondaries
 };
 
 constexpr int kSets = 3;
@@ -104,6 +105,7 @@ extern "C" int lv_multi_create(const lv_index *const *subs, int32_t count, lv_mu
   m->vbytes = s0->vbytes;
   m->D = s0->desc.D;
   m->d = s0->desc.d;
+  m->pw = s0->qp_width;
   std::vector<lv::IndexView> views(count);
   for (int i = 0; i < count; ++i) views[i] = lv::make_view(subs[i]);
   if (hipMalloc(&m->d_views, sizeof(lv::IndexView) * count) != hipSuccess) {
@@ -175,7 +177,7 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
   for (int i = 0; i < kSets; ++i) {
     LV_BATCH_TRY(hipMalloc(&b->d_table[i], b->table_bytes));
     LV_BATCH_TRY(hipMalloc(&b->d_counter[i], sizeof(unsigned int)));
-    LV_BATCH_TRY(hipMalloc(&b->d_qp[i], sizeof(float) * (size_t)caps->max_queries * multi->d));
+    LV_BATCH_TRY(hipMalloc(&b->d_qp[i], sizeof(float) * (size_t)caps->max_queries * multi->pw));
     LV_BATCH_TRY(hipHostMalloc(reinterpret_cast<void **>(&b->h_table[i]), b->table_bytes,
                                hipHostMallocDefault));
     std::fill(b->h_table[i], b->h_table[i] + b->table_bytes, (unsigned char)0);
@@ -189,7 +191,7 @@ extern "C" int lv_batch_create(lv_multi *multi, const lv_batch_caps *caps,
     hipError_t e1 = hipMemcpyAsync(b->d_table[i], b->h_table[i], b->table_bytes,
                                    hipMemcpyHostToDevice, b->capture);
     int r1 = e1 == hipSuccess
-                 ? lv::launch_project_grouped(hdr, multi->d_views, b->max_tiles, multi->d,
+                 ? lv::launch_project_grouped(hdr, multi->d_views, b->max_tiles, multi->pw,
                                               multi->D, b->capture)
                  : LV_EDEVICE;
     hipError_t e2 = hipStreamEndCapture(b->capture, &b->pre_graph[i]);
@@ -262,7 +264,7 @@ int batch_step(lv_batch *b, const lv_request *reqs, int32_t nreq, const float *Q
   hdr->scores = scores;
   hdr->counters = counters;
   hdr->nq = nq;
-  hdr->qp_stride = b->multi->d;
+  hdr->qp_stride = b->multi->pw;
   hdr->nreq = nreq;
   hdr->ntiles = tiles;
   int64_t qb = 0, ob = 0;
@@ -353,11 +355,11 @@ extern "C" int lv_autotune_window(lv_multi *multi, int32_t sub, const float *Q, 
   };
   if (hipMalloc(&d_ids, sizeof(uint32_t) * m * k) != hipSuccess ||
       hipMalloc(&d_sc, sizeof(float) * m * k) != hipSuccess ||
-      hipMalloc(&d_qp, sizeof(float) * m * ix->desc.d) != hipSuccess) {
+      hipMalloc(&d_qp, sizeof(float) * m * ix->qp_width) != hipSuccess) {
     cleanup();
     LV_FAIL(LV_ENOMEM, "autotune buffers");
   }
-  int rc = lv::launch_project(Q, m, ix->desc.D, ix->desc.A, ix->desc.d, d_qp, s);
+  int rc = lv::launch_project(Q, m, ix->desc.D, ix->desc.A, ix->qp_width, d_qp, s);
   std::vector<uint32_t> got((size_t)m * k);
   auto eval = [&](int L, double *rec) -> int {
     int r = lv::launch_beam(ix, Q, d_qp, m, k, L, d_ids, d_sc, nullptr, params, s);

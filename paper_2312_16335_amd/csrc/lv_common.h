@@ -38,6 +38,7 @@ struct lv_index {
   int32_t group;       // lanes cooperating on one primary record
   int32_t vbytes;      // bytes each of those lanes loads
   int32_t sec_packets; // 16-byte packets per secondary row
+  int32_t qp_width;    // projected query floats: d, or D with LV_F16_RESID (P q, then P_perp q)
 };
 
 namespace lv {

@@ -120,11 +120,13 @@ __global__ __launch_bounds__(256) void project_kernel(const float *__restrict__ 
 
 // Batched form: 32-row tiles over the requests of a step; each tile uses the
 // query projection of its request's sub-index.  Tiles beyond the step's
-// count exit (the grid is sized for the capacity).
+// count exit (the grid is sized for the capacity).  Output columns come in
+// blocks of up to 256 (grid y).
 template <int NT>
 __global__ __launch_bounds__(256) void project_grouped_kernel(const StepHeader *__restrict__ hdr,
                                                               const IndexView *__restrict__ subs,
                                                               int32_t D, int32_t d) {
+  const int32_t col0 = (int32_t)blockIdx.y * 256;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= hdr->ntiles) return;
   const Request *req = reinterpret_cast<const Request *>(hdr + 1);
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void project_grouped_kernel(const StepHeader *
   }
   const Request r = req[lo];
   const int64_t row0 = r.q_begin + (int64_t)(t - r.tile0) * 32;
-  project_rows<NT>(hdr->Q, row0, r.q_end, D, subs[r.sub].A, d, 0, hdr->Qp, hdr->qp_stride,
+  project_rows<NT>(hdr->Q, row0, r.q_end, D, subs[r.sub].A, d, col0, hdr->Qp, hdr->qp_stride,
                    threadIdx.x & 63);
 }
 
@@ -154,13 +156,14 @@ void launch_nt(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32
 
 int launch_project_grouped(const StepHeader *hdr, const IndexView *subs, int max_tiles, int d,
                            int D, hipStream_t stream) {
-  if (d < 1 || d > 256) LV_FAIL(LV_EUNSUPPORTED, "batched projection needs d <= 256");
+  if (d < 1 || d > 1024) LV_FAIL(LV_EUNSUPPORTED, "batched projection needs d <= 1024");
   const unsigned blocks = (unsigned)((max_tiles + 3) / 4);
-  const int nt = (d + 31) / 32;
-#define LV_GRP(NT)                                                                          \
-  case NT:                                                                                  \
-    hipLaunchKernelGGL(project_grouped_kernel<NT>, dim3(blocks), dim3(256), 0, stream, hdr, \
-                       subs, D, d);                                                         \
+  const unsigned cblocks = (unsigned)((d + 255) / 256);
+  const int nt = d > 256 ? 8 : (d + 31) / 32;
+#define LV_GRP(NT)                                                                             \
+  case NT:                                                                                     \
+    hipLaunchKernelGGL(project_grouped_kernel<NT>, dim3(blocks, cblocks), dim3(256), 0, stream, \
+                       hdr, subs, D, d);                                                       \
     break;
   switch (nt) {
     LV_GRP(1) LV_GRP(2) LV_GRP(3) LV_GRP(4) LV_GRP(5) LV_GRP(6) LV_GRP(7) LV_GRP(8)

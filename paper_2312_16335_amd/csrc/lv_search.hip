@@ -344,14 +344,18 @@ __device__ __forceinline__ bool hash_visit(uint32_t *hash, int log2h, int probes
 
 // Secondary scores of window entries ids[0..nl) into out[], one row at a
 // time across the wavefront (16-byte packets, UR rows in flight).  KIND is
-// LV_F32, LV_F16 or LV_LVQ8; an LVQ-8 row is scored as
+// LV_F32, LV_F16, LV_LVQ8 or LV_F16_RESID; an LVQ-8 row is scored as
 // delta * <q, c> + lo * sum(q) + <q, sec_mu>, which equals <q, x^> for its
 // reconstruction x^ = sec_mu + lo + delta * c.  The packet after the codes
-// holds delta and lo; its query components are zero.
+// holds delta and lo; its query components are zero.  A residual row (D - d
+// float16 coordinates, q = P_perp q) adds its inner product to the primary
+// score already in out[].
 template <int KIND>
 __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
                                             const uint32_t *ids, double *out, int nl, int lane) {
-  constexpr int E = KIND == LV_F16 ? 8 : (KIND == LV_F32 ? 4 : 16);  // elements per packet
+  constexpr bool F16 = KIND == LV_F16 || KIND == LV_F16_RESID;
+  constexpr int E = F16 ? 8 : (KIND == LV_F32 ? 4 : 16);  // elements per packet
+  const int dim = KIND == LV_F16_RESID ? ix.D - ix.d : ix.D;  // components per row
   // packets per lane: rows up to 2 KiB (LV_LVQ8 rows up to 1 KiB)
   constexpr int PPL = KIND == LV_LVQ8 ? 1 : 2;
   constexpr int UR = 4;   // rows in flight
@@ -363,7 +367,7 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = packet * E + e;
-      const bool in = packet < ix.sec_packets && j < ix.D;
+      const bool in = packet < ix.sec_packets && j < dim;
       qq[pk][e] = in ? gp(q)[j] : 0.f;
       if constexpr (KIND == LV_LVQ8) {
         sq += (double)qq[pk][e];
@@ -403,7 +407,7 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           double x;
-          if constexpr (KIND == LV_F16)
+          if constexpr (F16)
             x = (double)(float)__builtin_bit_cast(_Float16, (uint16_t)(w[e >> 1] >> (16 * (e & 1))));
           else if constexpr (KIND == LV_F32)
             x = (double)__uint_as_float(w[e]);
@@ -418,7 +422,12 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
         const uint32_t lw = lane_u32(cpk == 0 ? v[u][0][1] : v[u][PPL - 1][1], cl);
         acc = (double)__uint_as_float(dw) * acc + (double)__uint_as_float(lw) * sq + cq;
       }
-      if (lane == 0 && base + u < nl) out[base + u] = acc;
+      if (lane == 0 && base + u < nl) {
+        if constexpr (KIND == LV_F16_RESID)
+          out[base + u] += acc;
+        else
+          out[base + u] = acc;
+      }
     }
   }
 }
@@ -789,6 +798,8 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
     rerank_rows<LV_F16>(ix, job.q, id2, s2, nl, lane);
   else if (ix.sec_kind == LV_LVQ8)
     rerank_rows<LV_LVQ8>(ix, job.q, id2, s2, nl, lane);
+  else if (ix.sec_kind == LV_F16_RESID)
+    rerank_rows<LV_F16_RESID>(ix, job.q, id2, s2, nl, lane);
   else
     rerank_rows<LV_F32>(ix, job.q, id2, s2, nl, lane);
   wave_sync();
@@ -847,6 +858,7 @@ struct PlainArgs {
   int32_t hash_log2;
   int32_t probes;
   int32_t expand;
+  int32_t qp_stride;  // floats per projected query (d, or D with residual secondaries)
 };
 
 template <int BITS, int G, int V, bool MULTI>
@@ -855,8 +867,9 @@ __global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
   if (qi >= a.m) return;
   const Lds sm = carve(a.L);
   Job job;
-  job.q = a.Q + qi * a.ix.D;
-  job.qp = a.Qp + qi * a.ix.d;
+  job.qp = a.Qp + qi * a.qp_stride;
+  // residual secondaries are scored with P_perp q, stored after P q
+  job.q = a.ix.sec_kind == LV_F16_RESID ? job.qp + a.ix.d : a.Q + qi * a.ix.D;
   job.k = a.k;
   job.L = a.L;
   job.ids = a.ids + qi * a.k;
@@ -917,8 +930,8 @@ __attribute__((amdgpu_waves_per_eu(batched_waves<BITS, V>()))) void batched_kern
     int lane_q = lane;
     asm volatile("" : "+v"(lane_q));
     Job job;
-    job.q = hdr->Q + (int64_t)u * ix.D;
     job.qp = hdr->Qp + (int64_t)u * hdr->qp_stride;
+    job.q = ix.sec_kind == LV_F16_RESID ? job.qp + ix.d : hdr->Q + (int64_t)u * ix.D;
     job.k = r.k;
     job.L = r.L;
     job.ids = hdr->ids + r.out_off + j * r.k;
@@ -1063,7 +1076,8 @@ IndexView make_view(const lv_index *ix) {
   v.mu = d.mu;
   v.sec = static_cast<const unsigned char *>(d.secondaries);
   v.D = d.D;
-  v.sec_row_bytes = lv_secondary_row_bytes(d.D, d.sec_dtype);
+  v.sec_row_bytes =
+      lv_secondary_row_bytes(d.sec_dtype == LV_F16_RESID ? d.D - d.d : d.D, d.sec_dtype);
   v.sec_packets = ix->sec_packets;
   v.sec_kind = d.sec_dtype;
   v.sec_mu = d.sec_mu;
@@ -1131,6 +1145,7 @@ int launch_beam(const lv_index *ix, const float *Q, const float *Qp, int64_t m, 
   a.hash_log2 = vc.log2h;
   a.probes = vc.probes;
   a.expand = vc.expand;
+  a.qp_stride = ix->qp_width;
   PlainLaunch f{a, lds, stream};
   return dispatch(ix->desc.bits, ix->group, ix->vbytes, f);
 }

@@ -282,3 +282,15 @@ def test_graph_build_validation_without_a_device():
     assert call(order_p=big.ctypes.data) == lv.LV_EINVAL
     with pytest.raises(ValueError):
         lv.build_params(16, 32, alphas=(1.0,) * 9)
+
+
+def test_residual_secondaries_descriptor():
+    assert lv.lv_secondary_row_bytes(608, lv.LV_F16_RESID) == 1216
+    rc, h = _create(_desc(sec_dtype=lv.LV_F16_RESID, D=32, d=32))   # nothing left over
+    assert rc == lv.LV_EINVAL and not h.value
+    rc, h = _create(_desc(sec_dtype=lv.LV_F16_RESID, D=128, d=32))
+    assert rc == lv.LV_OK
+    lib = lv.load()
+    # the workspace holds P q and P_perp q: D floats per query
+    assert lib.lv_search_workspace_size(h, 10) >= 10 * 128 * 4
+    lib.lv_index_destroy(h)

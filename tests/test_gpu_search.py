@@ -13,6 +13,7 @@ torch = pytest.importorskip("torch")
 
 from gpu_common import Case, make_case, stride_for
 from oracle import exact
+from oracle import fit as ofit
 from oracle import lvq as olvq
 from oracle import search as osearch
 from synth import gen, graph
@@ -232,3 +233,86 @@ def test_expand_variant_parity(lv, name, N, expand):
         got2 = run_projected(lv, index, c, wl.k, L, hash_slots=256, expand=expand)
         assert np.array_equal(got2[0], got_ids) and np.array_equal(got2[1], got_sc)
         assert np.array_equal(got2[2][:, 0], got_cnt[:, 0])
+
+
+def _resid_case(lv, N=6000):
+    """id-1m-768 at N = 6000 with residual secondaries: P_full = all D
+    eigenvectors of the oracle's fit, primaries from its first d rows,
+    secondaries = float16 of the other D - d coordinates."""
+    wl = gen.WORKLOADS["id-1m-768"].scaled(N=N, m_test=40)
+    c = make_case(wl)
+    Pf = ofit.fit_id(ofit.second_moment(c.X), wl.D)
+    P, Pp = Pf[:wl.d], Pf[wl.d:]
+    Y = ofit.project(c.X, P).astype(np.float32)
+    mu = ofit.mean_reduced(c.X, P).astype(np.float32)
+    sec = ofit.project(c.X, Pp).astype(np.float16)
+    Qf = ofit.project(c.Q, Pf).astype(np.float32)  # P q then P_perp q
+    codes, delta, lo = olvq.encode(Y, mu, wl.bits)
+    oidx = osearch.Index(c.adj, c.entry, codes, delta, lo, mu, sec, sec_resid=True)
+    Yd = torch.from_numpy(Y).to(DEV)
+    mud = torch.from_numpy(mu).to(DEV)
+    rec = torch.empty((wl.N, c.stride), dtype=torch.uint8, device=DEV)
+    lv.lv_lvq_encode(Yd, mud, wl.bits, rec)
+    secd = torch.from_numpy(sec).to(DEV)
+    adj = torch.from_numpy(c.adj.view(np.int32)).to(DEV)
+    Pb = torch.from_numpy(lv.lv_to_bf16(Pf).view(np.int16)).to(DEV)
+    index = lv.Index(rec, mud, secd, adj, c.entry, wl.bits, wl.d, A_bf16=Pb, residual=True)
+    return wl, c, oidx, index, Qf, (rec, mud, secd, adj, Pb)
+
+
+def test_search_parity_residual_secondaries(lv):
+    wl, c, oidx, index, Qf, keep = _resid_case(lv)
+    m, k = len(c.Q), wl.k
+    for L in (20, 60):
+        want_ids = np.empty((m, k), np.int64)
+        want_sc = np.empty((m, k))
+        want_cnt = np.empty((m, 2), np.int64)
+        for i in range(m):
+            tr = osearch.Trace()
+            want_ids[i], want_sc[i] = osearch.search_one(oidx, Qf[i, wl.d:], Qf[i, :wl.d], k, L,
+                                                         trace=tr)
+            want_cnt[i] = (tr.n_exp, tr.n_dist)
+        ids = torch.empty((m, k), dtype=torch.int32, device=DEV)
+        sc = torch.empty((m, k), dtype=torch.float32, device=DEV)
+        cnt = torch.zeros((m, 2), dtype=torch.int32, device=DEV)
+        Qfd = torch.from_numpy(Qf).to(DEV)
+        lv.lv_search_projected(index, Qfd, Qfd, k, L, ids, sc, cnt, hash_slots=8192)
+        torch.cuda.synchronize()
+        got_ids = ids.cpu().numpy().view(np.uint32).astype(np.int64)
+        got_sc = sc.cpu().numpy()
+        assert np.array_equal(cnt.cpu().numpy(), want_cnt)
+        mism = np.nonzero((got_ids != want_ids).any(axis=1))[0]
+        for qi in mism:  # only swaps of exactly tied scores
+            g = osearch.secondary_scores(oidx, Qf[qi, wl.d:].astype(np.float64), got_ids[qi],
+                                         Qf[qi, :wl.d].astype(np.float64))
+            w = osearch.secondary_scores(oidx, Qf[qi, wl.d:].astype(np.float64), want_ids[qi],
+                                         Qf[qi, :wl.d].astype(np.float64))
+            assert np.allclose(np.sort(g), np.sort(w), rtol=0, atol=1e-12), qi
+        assert np.all(np.abs(got_sc - want_sc) <= 1e-4 * np.maximum(np.abs(want_sc), 1.0))
+    index.close()
+
+
+def test_residual_secondaries_batched_equals_plain(lv):
+    wl, c, oidx, index, Qf, keep = _resid_case(lv, N=4000)
+    m, k, L = len(c.Q), wl.k, 50
+    Qd = torch.from_numpy(c.Q).to(DEV)
+    ids_p = torch.empty((m, k), dtype=torch.int32, device=DEV)
+    sc_p = torch.empty((m, k), dtype=torch.float32, device=DEV)
+    ws = torch.empty(lv.lv_search_workspace_size(index, m), dtype=torch.uint8, device=DEV)
+    lv.lv_search(index, Qd, k, L, ids_p, sc_p, None, ws=ws)
+    multi = lv.Multi([index])
+    batch = lv.Batch(multi, max_requests=4, max_queries=m, max_L=L)
+    reqs = [(0, k, L, 13), (0, k, L, m - 13)]
+    ids_b = torch.full((m * k,), -7, dtype=torch.int32, device=DEV)
+    sc_b = torch.zeros((m * k,), dtype=torch.float32, device=DEV)
+    batch.step(reqs, Qd, ids_b, sc_b)
+    torch.cuda.synchronize()
+    assert torch.equal(ids_b.view(m, k), ids_p) and torch.equal(sc_b.view(m, k), sc_p)
+    # end to end (GPU projection of the full basis): recall against exact neighbours
+    truth = exact.ground_truth(c.Q, c.X, k)
+    got = ids_p.cpu().numpy().view(np.uint32).astype(np.int64)
+    rec = sum(len(set(g) & set(t)) for g, t in zip(got, truth)) / (m * k)
+    assert rec >= 0.9
+    batch.close()
+    multi.close()
+    index.close()
