@@ -53,9 +53,10 @@ def parse():
     ap.add_argument("--launch", choices=("per_query", "persistent"), default="per_query",
                     help="batched traversal launch when --hash-slots is given")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sec", choices=("f16", "lvq8"), default="f16",
-                    help="secondary vectors: float16 (the benchmark configuration) or LVQ-8 "
-                         "(no CPU baseline)")
+    ap.add_argument("--sec", choices=("f16", "lvq8", "resid"), default="f16",
+                    help="secondary vectors: float16 (the benchmark configuration), LVQ-8, or "
+                         "float16 residual coordinates only (D - d per vector); the last two "
+                         "without CPU baseline")
     ap.add_argument("--cpu-sample", type=int, default=10000)
     ap.add_argument("--only-steps", action="store_true",
                     help="skip the sweep refinement (profiling runs)")
@@ -235,9 +236,13 @@ def main():
     K = np.zeros((wl.D, wl.D))
     ssum = np.zeros(wl.D)
     lv.lv_second_moment(Xs, K, ssum)
-    P = lv.lv_fit_id(K, wl.d)
+    resid = args.sec == "resid"
+    # residual secondaries: all D eigenvectors, the first d are the projection
+    Pf = lv.lv_fit_id(K, wl.D if resid else wl.d)
+    P = np.ascontiguousarray(Pf[:wl.d])
     mu = lv.lv_mean_reduced(P, ssum, ns)
     Pb = torch.from_numpy(lv.lv_to_bf16(P).view(np.int16)).to(dev)
+    Pqb = torch.from_numpy(lv.lv_to_bf16(Pf).view(np.int16)).to(dev) if resid else Pb
     mud = torch.from_numpy(mu).to(dev)
     Xd = torch.from_numpy(X).to(dev)
     stride = lv.lv_record_stride(wl.d, wl.bits)
@@ -249,6 +254,8 @@ def main():
         smud = torch.from_numpy((ssum / ns).astype(np.float32)).to(dev)
         sec = torch.empty((wl.N, lv.lv_secondary_row_bytes(wl.D, lv.LV_LVQ8)), dtype=torch.uint8,
                           device=dev)
+    elif resid:
+        sec = torch.empty((wl.N, wl.D - wl.d), dtype=torch.float16, device=dev)
     else:
         sec = torch.empty((wl.N, wl.D), dtype=torch.float16, device=dev)
     torch.cuda.synchronize()
@@ -259,6 +266,12 @@ def main():
     lv.lv_lvq_encode(Y, mud, wl.bits, rec)
     if smud is not None:
         lv.lv_lvq_encode(Xd, smud, 8, sec)
+    elif resid:
+        Pp = torch.from_numpy(lv.lv_to_bf16(np.ascontiguousarray(Pf[wl.d:])).view(np.int16)).to(dev)
+        Yr = torch.empty((wl.N, wl.D - wl.d), dtype=torch.float32, device=dev)
+        lv.lv_project(Xd, Pp, Yr)
+        lv.lv_to_f16(Yr, sec)
+        del Yr, Pp
     else:
         lv.lv_to_f16(Xd, sec)
     torch.cuda.synchronize()
@@ -279,7 +292,8 @@ def main():
 
         g["reachable"] = float(sgraph.reachable(adj, entry).mean())
     log(f"graph ready at {time.time() - t0:.1f}s (build {g['graph_s']:.1f}s)")
-    index = lv.Index(rec, mud, sec, adjd, entry, wl.bits, wl.d, A_bf16=Pb, sec_mu=smud)
+    index = lv.Index(rec, mud, sec, adjd, entry, wl.bits, wl.d, A_bf16=Pqb, sec_mu=smud,
+                     residual=resid)
 
     # ---- request stream over the test queries (uneven batches)
     m = len(Q)
@@ -292,7 +306,7 @@ def main():
         left -= b
     offs = np.concatenate([[0], np.cumsum(sizes)])
     Qd = torch.from_numpy(Q).to(dev)
-    Qp = torch.empty((m, wl.d), dtype=torch.float32, device=dev)
+    Qp = torch.empty((m, wl.D if resid else wl.d), dtype=torch.float32, device=dev)
     ids = torch.empty((m, k), dtype=torch.int32, device=dev)
     scores = torch.empty((m, k), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
@@ -305,7 +319,7 @@ def main():
             lo, hi = int(offs[i]), int(offs[i + 1])
             if ev is not None:
                 ev[0][i].record(stream)
-            lv.lv_project(Qd[lo:hi], Pb, Qp[lo:hi])
+            lv.lv_project(Qd[lo:hi], Pqb, Qp[lo:hi])
             if ev is not None:
                 ev[1][i].record(stream)
             lv.lv_search_projected(index, Qd[lo:hi], Qp[lo:hi], k, L, ids[lo:hi],
@@ -384,7 +398,8 @@ def main():
     n_exp, n_dist = c[:, 0], c[:, 1]
     n_rr = np.minimum(L_star, n_dist)
     code_bytes = wl.d * wl.bits // 8
-    sec_row = wl.D * 2 if smud is None else wl.D + 8  # bytes of one secondary (codes + 8)
+    # bytes of one secondary row: float16, LVQ-8 codes + delta + lo, or residual float16
+    sec_row = wl.D + 8 if smud is not None else (2 * (wl.D - wl.d) if resid else 2 * wl.D)
     bytes_q = (4 * wl.D + n_exp * 4 * wl.R + n_dist * (code_bytes + 8) + n_rr * sec_row
                + 8 * k)
     alg_bytes_total = float(bytes_q.sum())
@@ -510,7 +525,7 @@ def main():
     beam_launch_ms = beam_ms / (args.steps * nreq)
     achieved_plain = (alg_bytes_total / nreq) / (beam_launch_ms / 1e3) / 1e9
     traffic = profile_traffic(os.path.join(ROOT, "paper_2312_16335_amd", "csrc", "lv_search.hip"),
-                              L_star, hs, launch_name) if smud is None else None
+                              L_star, hs, launch_name) if args.sec == "f16" else None
     batch.close()
 
     # the throughput variant (four expansions per iteration) at the same window,
@@ -548,7 +563,7 @@ def main():
 
     # reference: the plain path as one launch pair over all queries
     def single():
-        lv.lv_project(Qd, Pb, Qp)
+        lv.lv_project(Qd, Pqb, Qp)
         lv.lv_search_projected(index, Qd, Qp, k, L_star, ids, scores, hash_slots=hs,
                                expand=args.expand)
 
@@ -564,7 +579,7 @@ def main():
 
     # ---- CPU oracle on a bounded sample
     cpu = None
-    if not args.no_cpu_baseline and smud is None and args.expand <= 1:
+    if not args.no_cpu_baseline and args.sec == "f16" and args.expand <= 1:
         cpu = cpu_baseline(wl, X, Xs, Q, adj, entry, L_star, args.cpu_sample, truth)
         if cpu["sample"].startswith("all") and abs(cpu["recall"] - rec_star) > 0.005:
             log(f"WARNING: GPU recall {rec_star:.4f} vs oracle {cpu['recall']:.4f}")
