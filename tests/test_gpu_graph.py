@@ -106,3 +106,19 @@ def test_too_many_new_edges_in_one_batch_is_an_error():
     prim, rec2, order2 = _clustered(300, 32, 8, seed=3)
     want = og.build(prim, order2, 0, 8, 16, (1.0,), 16)
     assert np.array_equal(_gpu_build(rec2, 300, 32, 8, order2, 0, 8, 16, (1.0,), 16), want)
+
+
+@pytest.mark.parametrize("n,R,L,mb", [(1, 4, 8, 1), (2, 4, 8, 1), (300, 1, 8, 16),
+                                      (400, 8, 4, 32), (300, 8, 16, 1000)],
+                         ids=["N1", "N2", "R1", "window-below-R", "one-large-batch"])
+def test_degenerate_builds_equal_oracle(n, R, L, mb):
+    prim, rec, order = _clustered(n, 16, 8, seed=100 + n + R)
+    entry = int(order[0])
+    want = og.build(prim, order, entry, R, L, (1.0, 1.0), mb)
+    got = _gpu_build(rec, n, 16, 8, order, entry, R, L, (1.0, 1.0), mb)
+    assert np.array_equal(got, want)
+    og.check_rows(got)
+    if n == 1:
+        assert (got == SENT).all()
+    if n == 2:
+        assert got[0, 0] == 1 and got[1, 0] == 0 and (got[:, 1:] == SENT).all()

@@ -316,3 +316,35 @@ def test_residual_secondaries_batched_equals_plain(lv):
     batch.close()
     multi.close()
     index.close()
+
+
+def test_single_vector_index(lv):
+    """N = 1: the entry is the only result; the rest of every list is padding."""
+    rng = np.random.default_rng(31)
+    D, d, k = 32, 8, 4
+    X = rng.standard_normal((1, D)).astype(np.float32)
+    P = np.linalg.qr(rng.standard_normal((D, d)))[0].T
+    Y = ofit.project(X, P).astype(np.float32)
+    mu = Y.mean(axis=0).astype(np.float32)
+    codes, delta, lo = olvq.encode(Y, mu, 8)
+    stride = stride_for(d, 8)
+    rec = torch.from_numpy(olvq.pack_records(codes, delta, lo, 8, stride)).to(DEV)
+    adj = np.full((1, 4), osearch.SENTINEL, dtype=np.uint32)
+    sec = X.astype(np.float16)
+    index = lv.Index(rec, torch.from_numpy(mu).to(DEV), torch.from_numpy(sec).to(DEV),
+                     torch.from_numpy(adj.view(np.int32)).to(DEV), 0, 8, d)
+    Q = rng.standard_normal((3, D)).astype(np.float32)
+    Qp = ofit.project(Q, P).astype(np.float32)
+    ids = torch.empty((3, k), dtype=torch.int32, device=DEV)
+    sc = torch.empty((3, k), dtype=torch.float32, device=DEV)
+    lv.lv_search_projected(index, torch.from_numpy(Q).to(DEV), torch.from_numpy(Qp).to(DEV), k, 5,
+                           ids, sc)
+    torch.cuda.synchronize()
+    got = ids.cpu().numpy().view(np.uint32)
+    oidx = osearch.Index(adj, 0, codes, delta, lo, mu, sec)
+    for i in range(3):
+        wi, ws = osearch.search_one(oidx, Q[i], Qp[i], k, 5)
+        assert got[i].astype(np.int64).tolist() == wi.tolist()
+        assert np.isneginf(sc[i, 1:].cpu().numpy()).all()
+        assert abs(float(sc[i, 0]) - ws[0]) <= 1e-4 * max(1.0, abs(ws[0]))
+    index.close()
