@@ -61,11 +61,13 @@ def parse():
     ap.add_argument("--only-steps", action="store_true",
                     help="skip the sweep refinement (profiling runs)")
     ap.add_argument("--L", type=int, default=0, help="fixed window (skips the sweep)")
-    ap.add_argument("--expand", type=int, default=1,
-                    help="entries expanded per traversal iteration: 1 = the paper's traversal; "
-                         "2..8 = the throughput variant (no CPU baseline)")
+    ap.add_argument("--expand", type=int, default=3,
+                    help="entries expanded per traversal iteration (beam width of a step): "
+                         "1 = the paper's one-at-a-time traversal; 2..8 = several best "
+                         "unexpanded entries per iteration (3 measured fastest at recall 0.90)")
     ap.add_argument("--no-variant", action="store_true",
-                    help="skip timing the four-expansion traversal variant")
+                    help="skip timing the other traversal (one expansion per iteration when "
+                         "--expand > 1, three otherwise) beside the main value")
     ap.add_argument("--graph", choices=("cpu", "gpu"), default="cpu",
                     help="index graph: the host builder on float16 vectors (cached), or "
                          "lv_graph_build on the primary vectors (timed)")
@@ -165,25 +167,27 @@ def recall(ids, truth, k):
     return hit / (k * len(truth))
 
 
-def profile_traffic(kernel_src, L, slots, launch):
+def profile_traffic(kernel_src, L, slots, launch, expand):
     """HBM bytes per launch from committed counter runs, if the kernel is unchanged and
-    the counters were taken at this window and visited-set size."""
+    counters were taken in this configuration (window, visited-set size, launch, expand)."""
     p = os.path.join(ROOT, "profiles", "batched_kernel_id-1m-768_counters.md")
     if not os.path.exists(p):
         return None
     sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    vals = {}
+    want = {"window_L": str(L), "visited_slots": str(slots), "launch": launch,
+            "expand": str(expand)}
+    src_ok = False
     for line in open(p):
-        if ":" in line and line.startswith("- "):
-            k, v = line[2:].split(":", 1)
-            vals[k.strip()] = v.strip()
-    if (vals.get("kernel_source_sha256") != sha or vals.get("window_L") != str(L)
-            or vals.get("visited_slots") != str(slots) or vals.get("launch") != launch):
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        if line.startswith("- kernel_source_sha256:"):
+            src_ok = line.split(":", 1)[1].strip() == sha
+        elif line.startswith("- traffic:") and src_ok:
+            kv = dict(f.split("=", 1) for f in line.split(":", 1)[1].split())
+            if all(kv.get(k_) == v_ for k_, v_ in want.items()):
+                try:
+                    return float(kv["hbm_bytes_per_launch"])
+                except (KeyError, ValueError):
+                    return None
+    return None
 
 
 def main():
@@ -525,15 +529,18 @@ def main():
     beam_launch_ms = beam_ms / (args.steps * nreq)
     achieved_plain = (alg_bytes_total / nreq) / (beam_launch_ms / 1e3) / 1e9
     traffic = profile_traffic(os.path.join(ROOT, "paper_2312_16335_amd", "csrc", "lv_search.hip"),
-                              L_star, hs, launch_name) if args.sec == "f16" else None
+                              L_star, hs, launch_name, max(1, args.expand)) \
+        if args.sec == "f16" else None
     batch.close()
 
-    # the throughput variant (four expansions per iteration) at the same window,
-    # timed the same way; reported beside the paper's traversal, not as `value`
+    # the other traversal at the same window, timed the same way and reported
+    # beside `value`: one expansion per iteration (the paper's traversal) when
+    # the main run expands several, three otherwise
     variant = None
-    if args.expand <= 1 and not args.no_variant:
+    if not args.no_variant:
+        other = 1 if args.expand > 1 else 3
         bv = lv.Batch(multi, max_requests=nreq, max_queries=m, max_L=L_star, hash_slots=hs,
-                      launch=launch, expand=4)
+                      launch=launch, expand=other)
         for s_ in strs[1:]:
             s_.wait_stream(stream)
         run_pipelined(max(IN_FLIGHT, args.warmup), b=bv)
@@ -553,11 +560,11 @@ def main():
         torch.cuda.synchronize()
         vgot = outs[0][0].view(m, k).cpu().numpy().view(np.uint32).astype(np.int64)
         vms = v0.elapsed_time(v1)
-        variant = {"expand": 4, "L": L_star, "recall": recall(vgot, truth, k),
+        variant = {"expand": other, "L": L_star, "recall": recall(vgot, truth, k),
                    "qps": m * args.steps / (vms / 1e3), "ms_per_step": vms / args.steps,
                    "traversal_launch_ms": tv[0][0].elapsed_time(tv[-1][1]) / args.steps}
         bv.close()
-        log(f"variant expand=4 at L={L_star}: recall {variant['recall']:.4f}, "
+        log(f"other traversal expand={other} at L={L_star}: recall {variant['recall']:.4f}, "
             f"{variant['qps']:.0f} QPS")
     multi.close()
 
@@ -579,8 +586,9 @@ def main():
 
     # ---- CPU oracle on a bounded sample
     cpu = None
-    if not args.no_cpu_baseline and args.sec == "f16" and args.expand <= 1:
-        cpu = cpu_baseline(wl, X, Xs, Q, adj, entry, L_star, args.cpu_sample, truth)
+    if not args.no_cpu_baseline and args.sec == "f16":
+        cpu = cpu_baseline(wl, X, Xs, Q, adj, entry, L_star, args.cpu_sample, truth,
+                           max(1, args.expand))
         if cpu["sample"].startswith("all") and abs(cpu["recall"] - rec_star) > 0.005:
             log(f"WARNING: GPU recall {rec_star:.4f} vs oracle {cpu['recall']:.4f}")
 
@@ -641,12 +649,12 @@ def main():
                         "graph_build_work": g.get("stats"),
                         "graph_build_repeatable": g.get("deterministic")},
         "cpu_baseline": cpu,
-        "traversal_variant": variant,
+        "traversal_compare": variant,
     }
     print(json.dumps(out))
 
 
-def cpu_baseline(wl, X, Xs, Q, adj, entry, L, sample, truth):
+def cpu_baseline(wl, X, Xs, Q, adj, entry, L, sample, truth, expand=1):
     """The float64 oracle (its own projection and encoding), timed on a bounded query
     sample over all host cores; also its recall on that sample."""
     from oracle import fit as ofit
@@ -666,7 +674,8 @@ def cpu_baseline(wl, X, Xs, Q, adj, entry, L, sample, truth):
     procs = max(1, min(16, len(os.sched_getaffinity(0))))
     n = min(sample, len(Q))
     t = time.perf_counter()
-    got, _, _ = osearch.search_many(index, Q[:n], Qp[:n], wl.k, L, procs=procs, chunk=16)
+    got, _, _ = osearch.search_many(index, Q[:n], Qp[:n], wl.k, L, procs=procs, chunk=16,
+                                    expand=expand)
     dt = time.perf_counter() - t
     rec = recall(np.asarray(got).astype(np.int64), truth[:n], wl.k)
     model = ""
@@ -680,7 +689,8 @@ def cpu_baseline(wl, X, Xs, Q, adj, entry, L, sample, truth):
     log(f"oracle: {n} queries in {dt:.1f}s on {procs} processes")
     which = f"all {n}" if n == len(Q) else f"first {n} of {len(Q)}"
     return {"value": n / dt, "unit": "queries/s", "cores": procs, "kind": "oracle",
-            "sample": f"{which} test queries, window L={L}, float64 numpy oracle with its own "
+            "sample": f"{which} test queries, window L={L}, {expand} expansion(s) per iteration, "
+                      f"float64 numpy oracle with its own "
                       f"projection and encoding, one process per core (process start-up "
                       f"included)",
             "recall": rec, "cpu_model": model}

@@ -236,20 +236,20 @@ def _init_worker(paths, entry, sec_resid=False):
 
 
 def _run_chunk(args):
-    Q, Qp, k, L, lo = args
+    Q, Qp, k, L, lo, expand = args
     index = _G["index"]
     ids = np.empty((len(Q), k), dtype=np.int64)
     sc = np.empty((len(Q), k))
     cnt = np.zeros((len(Q), 2), dtype=np.int64)
     for i in range(len(Q)):
         tr = Trace()
-        ids[i], sc[i] = search_one(index, Q[i], Qp[i], k, L, trace=tr)
+        ids[i], sc[i] = search_one(index, Q[i], Qp[i], k, L, trace=tr, expand=expand)
         cnt[i] = (tr.n_exp, tr.n_dist)
     return lo, ids, sc, cnt
 
 
 def search_many(index: Index, Q, Qp, k: int, L: int, procs: int = 1,
-                chunk: int = 64, workdir: Optional[str] = None):
+                chunk: int = 64, workdir: Optional[str] = None, expand: int = 1):
     """Search every query; returns (ids [m,k], scores [m,k], counts [m,2])."""
     Q = np.asarray(Q, dtype=np.float32)
     Qp = np.asarray(Qp, dtype=np.float32)
@@ -260,7 +260,7 @@ def search_many(index: Index, Q, Qp, k: int, L: int, procs: int = 1,
     if procs <= 1:
         _G["index"] = index
         for lo in range(0, m, chunk):
-            _, a, b, c = _run_chunk((Q[lo:lo + chunk], Qp[lo:lo + chunk], k, L, lo))
+            _, a, b, c = _run_chunk((Q[lo:lo + chunk], Qp[lo:lo + chunk], k, L, lo, expand))
             ids[lo:lo + len(a)], sc[lo:lo + len(a)], cnt[lo:lo + len(a)] = a, b, c
         return ids, sc, cnt
     import multiprocessing as mp
@@ -284,7 +284,8 @@ def search_many(index: Index, Q, Qp, k: int, L: int, procs: int = 1,
                                  initializer=_init_worker,
                                  initargs=(paths, int(index.entry),
                                            bool(index.sec_resid))) as pool:
-            jobs = [(Q[lo:lo + chunk], Qp[lo:lo + chunk], k, L, lo) for lo in range(0, m, chunk)]
+            jobs = [(Q[lo:lo + chunk], Qp[lo:lo + chunk], k, L, lo, expand)
+                    for lo in range(0, m, chunk)]
             for lo, a, b, c in pool.map(_run_chunk, jobs):
                 ids[lo:lo + len(a)], sc[lo:lo + len(a)], cnt[lo:lo + len(a)] = a, b, c
     finally:

@@ -1,7 +1,8 @@
 """GPU parity at the full benchmark size: 1M x 768 database, d = 160, LVQ-8
 records, float16 secondaries, R = 64, 10,000 queries, window L = 96, in the
 launch configuration the benchmark times (one captured batched step over a
-stream of uneven requests, 1024 visited-set slots).
+stream of uneven requests, 1024 visited-set slots, three expansions per
+iteration; one expansion per iteration, the paper's traversal, as well).
 
 The oracle fits on a 100k uniform subsample (Section 2.2) and projects in
 float64; the GPU receives the oracle's reduced vectors rounded to float32.
@@ -119,7 +120,8 @@ def test_sampled_records_and_secondaries_bit_exact(lv, full):
     assert np.array_equal(gs.view(np.uint16), full["sec"][rows].view(np.uint16))
 
 
-def test_batched_step_equals_plain_and_oracle(lv, full):
+@pytest.mark.parametrize("expand", [1, 3], ids=["one-expansion", "three-expansions"])
+def test_batched_step_equals_plain_and_oracle(lv, full, expand):
     wl, Q, index = full["wl"], full["Q"], full["index"]
     m, k = len(Q), wl.k
     Qd = torch.from_numpy(Q).to(DEV)
@@ -129,7 +131,7 @@ def test_batched_step_equals_plain_and_oracle(lv, full):
     # the benchmark's launch: one captured step over the whole stream
     multi = lv.Multi([index])
     batch = lv.Batch(multi, max_requests=len(reqs), max_queries=m, max_L=L_OP,
-                     hash_slots=HASH_SLOTS)
+                     hash_slots=HASH_SLOTS, expand=expand)
     ids_b = torch.full((m * k,), -7, dtype=torch.int32, device=DEV)
     sc_b = torch.zeros((m * k,), dtype=torch.float32, device=DEV)
     for _ in range(2):  # two consecutive steps (alternating request tables)
@@ -145,7 +147,7 @@ def test_batched_step_equals_plain_and_oracle(lv, full):
     q0 = 0
     for b in sizes:
         lv.lv_search(index, Qd[q0:q0 + b], k, L_OP, ids_p[q0:q0 + b], sc_p[q0:q0 + b], None,
-                     ws=ws, hash_slots=HASH_SLOTS)
+                     ws=ws, hash_slots=HASH_SLOTS, expand=expand)
         q0 += b
     torch.cuda.synchronize()
     assert torch.equal(ids_b.view(m, k), ids_p)
@@ -169,7 +171,8 @@ def test_batched_step_equals_plain_and_oracle(lv, full):
     ids_o = torch.empty((m, k), dtype=torch.int32, device=DEV)
     sc_o = torch.empty((m, k), dtype=torch.float32, device=DEV)
     cnt = torch.zeros((m, 2), dtype=torch.int32, device=DEV)
-    lv.lv_search_projected(index, Qd, Qpd, k, L_OP, ids_o, sc_o, cnt, hash_slots=HASH_SLOTS)
+    lv.lv_search_projected(index, Qd, Qpd, k, L_OP, ids_o, sc_o, cnt, hash_slots=HASH_SLOTS,
+                           expand=expand)
     torch.cuda.synchronize()
     rng = np.random.default_rng(22)
     sample = np.sort(rng.choice(m, N_SAMPLE, replace=False))
@@ -180,7 +183,8 @@ def test_batched_step_equals_plain_and_oracle(lv, full):
     truth = exact.ground_truth(Q[sample], full["X"], k)
     for n, qi in enumerate(sample):
         tr = osearch.Trace()
-        oi, os_ = osearch.search_one(full["oix"], Q[qi], full["Qp"][qi], k, L_OP, trace=tr)
+        oi, os_ = osearch.search_one(full["oix"], Q[qi], full["Qp"][qi], k, L_OP, trace=tr,
+                                     expand=expand)
         assert np.array_equal(got_i[qi], oi), qi
         assert np.allclose(got_s[qi], os_, rtol=0, atol=2e-7), qi
         assert got_c[qi, 0] == tr.n_exp, qi
