@@ -722,61 +722,60 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
       }
     }
   } else {
-  for (uint32_t hop = 0; hop < max_hops; ++hop) {
-    const double *ls = sm.ls();
-    uint32_t *lid = sm.lid();
-    // best unexpanded entry = first unexpanded position of the sorted window;
-    // the next one is the runner-up whose row is prefetched
-    int pos = -1;
-    uint32_t p = kSentinel, p2 = kSentinel;
-    for (int base = 0; base < nl; base += 64) {
-      const int i = base + lane;
-      const uint32_t v = i < nl ? lid[i] : kExpanded;
-      uint64_t msk = __ballot(!(v & kExpanded));
-      if (msk) {
-        if (pos < 0) {
-          const int b = __ffsll((unsigned long long)msk) - 1;
-          pos = base + b;
-          p = lane_u32(v, b);
-          msk &= msk - 1;
-        }
+    for (uint32_t hop = 0; hop < max_hops; ++hop) {
+      uint32_t *lid = sm.lid();
+      // best unexpanded entry = first unexpanded position of the sorted window;
+      // the next one is the runner-up whose row is prefetched
+      int pos = -1;
+      uint32_t p = kSentinel, p2 = kSentinel;
+      for (int base = 0; base < nl; base += 64) {
+        const int i = base + lane;
+        const uint32_t v = i < nl ? lid[i] : kExpanded;
+        uint64_t msk = __ballot(!(v & kExpanded));
         if (msk) {
-          p2 = lane_u32(v, __ffsll((unsigned long long)msk) - 1);
-          break;
+          if (pos < 0) {
+            const int b = __ffsll((unsigned long long)msk) - 1;
+            pos = base + b;
+            p = lane_u32(v, b);
+            msk &= msk - 1;
+          }
+          if (msk) {
+            p2 = lane_u32(v, __ffsll((unsigned long long)msk) - 1);
+            break;
+          }
         }
       }
-    }
-    if (pos < 0) break;
-    if (lane == 0) lid[pos] = p | kExpanded;
-    wave_sync();
-    ++n_exp;
-    const LV_GLOBAL uint32_t *row = gp(ix.adj) + (size_t)p * (size_t)ix.R;
-    uint32_t first = kSentinel;
-    if (p == pf_id)
-      first = pf_row;
-    else if (lane < ix.R)
-      first = row[lane];
-    // prefetch the runner-up's first chunk; consumed at the next hop if it is
-    // still the best unexpanded candidate then
-    pf_id = p2;
-    pf_row = (p2 != kSentinel && lane < ix.R) ? gp(ix.adj)[(size_t)p2 * (size_t)ix.R + lane]
-                                              : kSentinel;
-    for (int rb = 0; rb < ix.R; rb += 64) {
-      uint32_t n = rb == 0 ? first : (rb + lane < ix.R ? row[rb + lane] : kSentinel);
-      bool fresh = false;
-      if (n < ix.N) fresh = hash_visit(sm.hash(), log2h, probes, n);
-      const uint64_t fm = __ballot(fresh);
-      const int nc = __popcll(fm);
-      if (nc == 0) continue;
-      if (fresh) sm.cid()[lane_rank(fm)] = n;
+      if (pos < 0) break;
+      if (lane == 0) lid[pos] = p | kExpanded;
       wave_sync();
-      score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), nc, lane);
-      wave_sync();
-      n_dist += nc;
+      ++n_exp;
+      const LV_GLOBAL uint32_t *row = gp(ix.adj) + (size_t)p * (size_t)ix.R;
+      uint32_t first = kSentinel;
+      if (p == pf_id)
+        first = pf_row;
+      else if (lane < ix.R)
+        first = row[lane];
+      // prefetch the runner-up's first chunk; consumed at the next hop if it is
+      // still the best unexpanded candidate then
+      pf_id = p2;
+      pf_row = (p2 != kSentinel && lane < ix.R) ? gp(ix.adj)[(size_t)p2 * (size_t)ix.R + lane]
+                                                : kSentinel;
+      for (int rb = 0; rb < ix.R; rb += 64) {
+        uint32_t n = rb == 0 ? first : (rb + lane < ix.R ? row[rb + lane] : kSentinel);
+        bool fresh = false;
+        if (n < ix.N) fresh = hash_visit(sm.hash(), log2h, probes, n);
+        const uint64_t fm = __ballot(fresh);
+        const int nc = __popcll(fm);
+        if (nc == 0) continue;
+        if (fresh) sm.cid()[lane_rank(fm)] = n;
+        wave_sync();
+        score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), nc, lane);
+        wave_sync();
+        n_dist += nc;
 
-      merge_batch(sm, nc, L, nl, lane);
+        merge_batch(sm, nc, L, nl, lane);
+      }
     }
-  }
   }
 
   if constexpr (BUILD) {
