@@ -19,8 +19,10 @@
 //   3. every touched target reserves a slice of the source list;
 //   4. every new edge writes its source into its target's slice;
 //   5. reverse edges (one wavefront per touched target): the new sources in
-//      ascending order that are not in the target's row are appended; a
-//      union longer than R is pruned around the target.
+//      ascending order that are not in the target's row are appended, in
+//      registers only (reverse_append_kernel, the common case); a target
+//      whose union is longer than R (or that has more than 64 new sources)
+//      is listed for reverse_kernel, which prunes the union around it.
 // Every row is written by one wavefront, and no row depends on the order in
 // which targets were listed, so the graph does not depend on scheduling.
 //
@@ -123,7 +125,9 @@ struct BatchState {
   uint32_t *base;      // [N]
   uint32_t *touched;   // [max_batch * R]
   uint32_t *srcs;      // [max_batch * R]
-  uint32_t *misc;      // [0] touched count, [1] source cursor, [2] overflow flag
+  uint32_t *deferred;  // [max_batch * R] targets left to reverse_kernel
+  uint32_t *misc;      // [0] touched count, [1] source cursor, [2] overflow flag,
+                       // [3] deferred count
   unsigned long long *stats;  // optional work totals (LV_BS_* order) or null
 };
 
@@ -349,6 +353,7 @@ __global__ __launch_bounds__(64) void prune_forward_kernel(ForwardArgs a) {
 __global__ void batch_reset_kernel(uint32_t *misc) {
   misc[0] = 0u;
   misc[1] = 0u;
+  misc[3] = 0u;
 }
 
 __global__ void alloc_kernel(BatchState st) {
@@ -371,14 +376,56 @@ __global__ void scatter_kernel(const uint32_t *order, int64_t start, int32_t B, 
   st.srcs[st.base[j] + s] = p;
 }
 
+// Reverse edges of one batch, common case (one wavefront per target, no
+// LDS): lane i holds new source i (at most 64) and lane k row entry k; the
+// sources not in the row (and not j) are appended in ascending order when
+// the row has room.  Other targets go to the deferred list.
+__global__ __launch_bounds__(64) void reverse_append_kernel(PruneView v, BatchState st) {
+  const int lane = threadIdx.x;
+  const uint32_t nt = st.misc[0];
+  for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const uint32_t j = st.touched[t];
+    const uint32_t cnt = st.cnt[j];
+    if (st.stats && lane == 0) atomicAdd(&st.stats[LV_BS_REV_TARGETS], 1ull);
+    if (cnt > 64u) {
+      if (lane == 0) st.deferred[atomicAdd(&st.misc[3], 1u)] = j;
+      continue;
+    }
+    uint32_t *row = v.adj + (size_t)j * (size_t)v.R;
+    const uint32_t rv = lane < v.R ? row[lane] : kSentinel;
+    const int deg = __popcll(__ballot(rv != kSentinel));
+    const uint32_t s = lane < (int)cnt ? st.srcs[st.base[j] + lane] : kSentinel;
+    bool add = lane < (int)cnt && s != j && s < v.N;
+    for (uint32_t t2 = 0; t2 < cnt; ++t2) {  // is source t2 in the row?
+      const uint32_t st_ = (uint32_t)__builtin_amdgcn_readlane((int)s, (int)t2);
+      if (__ballot(lane < deg && rv == st_) && lane == (int)t2) add = false;
+    }
+    const uint64_t am = __ballot(add);
+    const int u = deg + __popcll(am);
+    if (u > v.R) {
+      if (lane == 0) st.deferred[atomicAdd(&st.misc[3], 1u)] = j;
+      continue;
+    }
+    int pos = 0;  // rank among the appended sources (ids are distinct)
+    for (uint32_t t2 = 0; t2 < cnt; ++t2) {
+      const uint32_t st_ = (uint32_t)__builtin_amdgcn_readlane((int)s, (int)t2);
+      pos += (int)(((am >> t2) & 1u) && st_ < s);
+    }
+    if (add) row[deg + pos] = s;
+    if (lane == 0) st.cnt[j] = 0u;
+  }
+}
+
+// Reverse edges of the deferred targets: the union of the row and the new
+// sources, pruned around the target when longer than R.
 template <int BITS>
 __global__ __launch_bounds__(64) void reverse_kernel(PruneView v, BatchState st) {
   const int lane = threadIdx.x;
   const int M = v.R + kMaxNewSources;
   const PruneLds sm = carve_prune(M, v.R, v.cw);
-  const uint32_t nt = st.misc[0];
+  const uint32_t nt = st.misc[3];
   for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
-    const uint32_t j = st.touched[t];
+    const uint32_t j = st.deferred[t];
     const uint32_t cnt = st.cnt[j];
     const uint32_t b0 = st.base[j];
     uint32_t *row = v.adj + (size_t)j * (size_t)v.R;
@@ -433,7 +480,6 @@ __global__ __launch_bounds__(64) void reverse_kernel(PruneView v, BatchState st)
         atomicAdd(&st.stats[LV_BS_REV_CANDS], (unsigned long long)u);
       }
     }
-    if (st.stats && lane == 0) atomicAdd(&st.stats[LV_BS_REV_TARGETS], 1ull);
     if (lane == 0) st.cnt[j] = 0u;
   }
 }
@@ -548,6 +594,7 @@ extern "C" int lv_graph_build(const void *records, int32_t record_stride, int64_
   if ((rc = sc.alloc(&st.base, (size_t)N)) != LV_OK) return rc;
   if ((rc = sc.alloc(&st.touched, (size_t)maxb * R)) != LV_OK) return rc;
   if ((rc = sc.alloc(&st.srcs, (size_t)maxb * R)) != LV_OK) return rc;
+  if ((rc = sc.alloc(&st.deferred, (size_t)maxb * R)) != LV_OK) return rc;
   if ((rc = sc.alloc(&st.misc, 4)) != LV_OK) return rc;
   uint32_t *counters = nullptr;
   if (bp.stats) {
@@ -592,7 +639,8 @@ extern "C" int lv_graph_build(const void *records, int32_t record_stride, int64_
   fa.pool = pool;
   fa.pool_stride = pool_stride;
   fa.st = st;
-  const int rev_grid = (int)(maxb * R < 8192 ? maxb * R : 8192);
+  const int app_grid = (int)(maxb * R < 16384 ? maxb * R : 16384);
+  const int rev_grid = (int)(maxb * R < 2048 ? maxb * R : 2048);
   const int alloc_grid = (int)((maxb * R + 255) / 256 < 1024 ? (maxb * R + 255) / 256 : 1024);
 
   int64_t batches = 0;
@@ -618,6 +666,7 @@ extern "C" int lv_graph_build(const void *records, int32_t record_stride, int64_
       hipLaunchKernelGGL(alloc_kernel, dim3(alloc_grid), dim3(256), 0, s, st);
       hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((B * R + 255) / 256)), dim3(256), 0, s,
                          order_d, start, (int32_t)B, adjacency, R, st);
+      hipLaunchKernelGGL(reverse_append_kernel, dim3(app_grid), dim3(64), 0, s, fa.v, st);
       if (bits == 8)
         hipLaunchKernelGGL(reverse_kernel<8>, dim3(rev_grid), dim3(64), lds_rev, s, fa.v, st);
       else
