@@ -75,6 +75,9 @@ def parse():
                     help="search window of the GPU graph build (default 2R)")
     ap.add_argument("--build-batch", type=int, default=0,
                     help="largest insertion batch of the GPU graph build (default N/50)")
+    ap.add_argument("--mfma", action="store_true",
+                    help="only time the matrix-core kernels (projections, refinement step, a "
+                         "large GEMM) against the bf16 peak and HBM, print one JSON line, exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -130,6 +133,78 @@ def build_graph_gpu(lv, torch, wl, X, rec, args, out):
     out["kind"] = (f"lv_graph_build on the primary vectors (window {bL}, batches up to {mb}, "
                    f"alphas {list(wl.graph_alphas)})")
     return adjd, entry
+
+
+MFMA_PEAK_TFLOPS = 2500.0  # dense bf16 on MI355X
+
+
+def mfma_report(lv, torch, reps=10):
+    """Matrix-core kernels on synthetic operands of the workloads' shapes: the
+    database projection (1M x 768 -> 160) and the query projection (10,000
+    queries), one refinement step (forward + backward, b_q = 1024, b_x = 4096,
+    D = 768, d = 128, with the trace term) and one 8192^3 GEMM.  Flops are the
+    products' own (2 M N K each); bytes are the projections' operands and outputs."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def entry(ms, flops, nbytes=None):
+        e = {"ms": ms, "tflops": flops / (ms / 1e3) / 1e12}
+        e["frac_bf16_peak"] = e["tflops"] / MFMA_PEAK_TFLOPS
+        if nbytes is not None:
+            e["GBs"] = nbytes / (ms / 1e3) / 1e9
+            e["frac_hbm_peak"] = e["GBs"] / HBM_PEAK_GBS
+        return e
+
+    out = {"peaks": {"bf16_tflops": MFMA_PEAK_TFLOPS, "hbm_GBs": HBM_PEAK_GBS}}
+    D, d = 768, 160
+    M = torch.randn((d, D), device=dev, generator=g).to(torch.bfloat16).view(torch.int16)
+    for name, rows in (("database_projection", 1_000_000), ("query_projection", 10_000)):
+        V = torch.randn((rows, D), device=dev, generator=g)
+        Y = torch.empty((rows, d), device=dev)
+        ms = timed(lambda: lv.lv_project(V, M, Y))
+        out[name] = dict(rows=rows, D=D, d=d, **entry(ms, 2.0 * rows * D * d,
+                                                         4.0 * rows * (D + d) + 2.0 * d * D))
+        del V, Y
+    bq, bx, D2, d2 = 1024, 4096, 768, 128
+    A = torch.randn((d2, D2), device=dev, generator=g) * 0.03
+    B = torch.randn((d2, D2), device=dev, generator=g) * 0.03
+    Qb = torch.randn((bq, D2), device=dev, generator=g)
+    Xb = torch.randn((bx, D2), device=dev, generator=g)
+    KQ = torch.eye(D2, device=dev)
+    KX = torch.eye(D2, device=dev)
+    loss = torch.zeros(3, device=dev)
+    dA, dB = torch.empty_like(A), torch.empty_like(B)
+    ws = torch.empty(lv.lv_projloss_workspace_size(bq, bx, D2, d2), dtype=torch.uint8,
+                     device=dev)
+
+    def step():
+        lv.lv_projloss_fwd(A, B, Qb, Xb, loss, ws, KQ, KX)
+        lv.lv_projloss_bwd(A, B, Qb, Xb, dA, dB, ws, KQ, KX)
+
+    pair_f = 2.0 * (bq * d2 * D2 + bx * d2 * D2 + bq * bx * D2 + bq * bx * d2)
+    pair_b = 2.0 * (2 * bq * bx * d2 + d2 * D2 * bq + d2 * D2 * bx)
+    trace = 2.0 * (2 * d2 * D2 * D2 + 2 * d2 * d2 * D2) * 2
+    out["refinement_step"] = dict(b_q=bq, b_x=bx, D=D2, d=d2,
+                                  **entry(timed(step), pair_f + pair_b + trace))
+    n = 8192
+    Ga = torch.randn((n, n), device=dev, generator=g)
+    Gb = torch.randn((n, n), device=dev, generator=g)
+    Gc = torch.empty((n, n), device=dev)
+    ms = timed(lambda: lv.lv_gemm(Ga, Gb, Gc, n, n, n))
+    out["gemm_8192"] = entry(ms, 2.0 * n ** 3)
+    return out
 
 
 def ground_truth_gpu(torch, Xd, Q, k):
@@ -215,6 +290,9 @@ def main():
                           "bytes_written_per_copy": 1 << 30, "copies": 3}))
         return
     lv.load()
+    if args.mfma:
+        print(json.dumps(mfma_report(lv, torch)))
+        return
     dev = torch.device("cuda:0")
     wl = gen.WORKLOADS[args.workload]
     if args.n:

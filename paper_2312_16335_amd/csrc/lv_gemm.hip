@@ -5,9 +5,15 @@
 // Each operand is either "k-contiguous" (a(m, k) at A[m * lda + k]) or
 // "m-contiguous" (a(m, k) at A[k * lda + m]); the staging step writes both
 // kinds into LDS as [row][k] tiles so the MFMA operand reads are 16-byte
-// vector loads.  Tile 128 x 128 x 32 per 256-thread workgroup, each
-// wavefront a 64 x 64 quadrant (2 x 2 tiles of 32 x 32x16 MFMAs), two LDS
-// buffers so the next tile is staged while the current one is multiplied.
+// vector loads.  Tile 128 x 128 per 256-thread workgroup, each wavefront a
+// 64 x 64 quadrant (2 x 2 tiles of 32 x 32x16 MFMAs), two LDS buffers.
+//
+// Two kernels: when both operands allow 16-byte loads (aligned pointers,
+// leading dimensions multiples of 4 floats), gemm_vec_kernel walks K in
+// steps of 64 and keeps the next tile's float32 operands in registers while
+// the current tile is multiplied (one barrier per step), with float4 loads
+// for both operand layouts; otherwise gemm_kernel stages element by element
+// in steps of 32.
 #include "lv_common.h"
 #include "lv_gemm.h"
 
@@ -129,11 +135,183 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
 }
 
+// ---- vector-load kernel
+
+constexpr int VK = 64;       // K per step
+constexpr int VLD = VK + 8;  // LDS row (bf16 elements): 144 bytes, 16-byte aligned rows
+
+// The float32 values one thread stages for one operand in one step.
+struct Frag {
+  float4 v[8];
+};
+
+__device__ __forceinline__ float4 load4(const float *p, bool all, bool e0, bool e1, bool e2,
+                                        bool e3) {
+  if (all) return *reinterpret_cast<const float4 *>(p);
+  return make_float4(e0 ? p[0] : 0.f, e1 ? p[1] : 0.f, e2 ? p[2] : 0.f, e3 ? p[3] : 0.f);
+}
+
+// Global -> registers.  k-contiguous: thread row tid / 2, 32 consecutive k at
+// (tid % 2) * 32.  m-contiguous (memory rows are k): thread k rows 2 (tid / 8)
+// and 2 (tid / 8) + 1, 16 consecutive m at (tid % 8) * 16.
+template <bool KCONT>
+__device__ __forceinline__ void vload(const float *__restrict__ X, int64_t ld, int rows, int kdim,
+                                      int r0, int k0, Frag &f, int tid) {
+  if constexpr (KCONT) {
+    const int r = tid >> 1, kk = (tid & 1) * 32;
+    const int gr = r0 + r;
+    const bool rok = gr < rows;
+    const float *p = X + (int64_t)(rok ? gr : 0) * ld + k0 + kk;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int gk = k0 + kk + 4 * i;
+      f.v[i] = load4(p + 4 * i, rok && gk + 3 < kdim, rok && gk < kdim, rok && gk + 1 < kdim,
+                     rok && gk + 2 < kdim, false);
+    }
+  } else {
+    const int k = 2 * (tid >> 3), mm = (tid & 7) * 16;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int gk = k0 + k + h;
+      const bool kok = gk < kdim;
+      const float *p = X + (int64_t)(kok ? gk : 0) * ld + r0 + mm;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gm = r0 + mm + 4 * i;
+        f.v[4 * h + i] = load4(p + 4 * i, kok && gm + 3 < rows, kok && gm < rows,
+                               kok && gm + 1 < rows, kok && gm + 2 < rows, false);
+      }
+    }
+  }
+}
+
+// Two floats to bfloat16 (round to nearest even) in one conversion instruction.
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+  const bf16x2 h = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, h);
+}
+
+// Registers -> LDS tile S[row][k] (bfloat16).
+template <bool KCONT>
+__device__ __forceinline__ void vstore(const Frag &f, uint16_t *S, int tid) {
+  if constexpr (KCONT) {
+    const int r = tid >> 1, kk = (tid & 1) * 32;
+    uint4 *dst = reinterpret_cast<uint4 *>(S + r * VLD + kk);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float4 a = f.v[2 * i], b = f.v[2 * i + 1];
+      dst[i] = make_uint4(pack_bf16(a.x, a.y), pack_bf16(a.z, a.w), pack_bf16(b.x, b.y),
+                          pack_bf16(b.z, b.w));
+    }
+  } else {
+    const int k = 2 * (tid >> 3), mm = (tid & 7) * 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float4 a = f.v[i], b = f.v[4 + i];  // rows k and k + 1, m = mm + 4i ..
+      uint32_t *d = reinterpret_cast<uint32_t *>(S + (mm + 4 * i) * VLD + k);
+      d[0] = pack_bf16(a.x, b.x);
+      d[VLD / 2] = pack_bf16(a.y, b.y);
+      d[VLD] = pack_bf16(a.z, b.z);
+      d[3 * VLD / 2] = pack_bf16(a.w, b.w);
+    }
+  }
+}
+
+template <bool AK, bool BKC>
+__global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g) {
+  __shared__ __align__(16) uint16_t As[2][BM * VLD];
+  __shared__ __align__(16) uint16_t Bs[2][BN * VLD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int nk = (g.K + VK - 1) / VK;
+  Frag fa, fb;
+  vload<AK>(g.A, g.lda, g.M, g.K, m0, 0, fa, tid);
+  vload<BKC>(g.B, g.ldb, g.N, g.K, n0, 0, fb, tid);
+  vstore<AK>(fa, As[0], tid);
+  vstore<BKC>(fb, Bs[0], tid);
+  __syncthreads();
+  const int r = lane & 31, kh = lane >> 5;
+  for (int t = 0; t < nk; ++t) {
+    const int cur = t & 1;
+    const bool more = t + 1 < nk;
+    if (more) {  // next step's operands in flight during this step's products
+      vload<AK>(g.A, g.lda, g.M, g.K, m0, (t + 1) * VK, fa, tid);
+      vload<BKC>(g.B, g.ldb, g.N, g.K, n0, (t + 1) * VK, fb, tid);
+    }
+#pragma unroll
+    for (int ks = 0; ks < VK; ks += 16) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = __builtin_bit_cast(
+            bf16x8,
+            *reinterpret_cast<const u32x4 *>(&As[cur][(wm + 32 * i + r) * VLD + ks + 8 * kh]));
+        b[i] = __builtin_bit_cast(
+            bf16x8,
+            *reinterpret_cast<const u32x4 *>(&Bs[cur][(wn + 32 * i + r) * VLD + ks + 8 * kh]));
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {  // the other buffer was last read before the previous barrier
+      vstore<AK>(fa, As[cur ^ 1], tid);
+      vstore<BKC>(fb, Bs[cur ^ 1], tid);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + 32 * j + r;
+      if (col >= g.N) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = m0 + wm + 32 * i + 8 * (e >> 2) + 4 * kh + (e & 3);
+        if (row >= g.M) continue;
+        float *c = g.C + (int64_t)row * g.ldc + col;
+        const float v = g.alpha * acc[i][j][e];
+        *c = g.beta == 0.f ? v : v + g.beta * *c;
+      }
+    }
+}
+
+bool vec_ok(const float *p, int64_t ld) {
+  return (reinterpret_cast<uintptr_t>(p) & 15u) == 0 && ld % 4 == 0;
+}
+
 }  // namespace
 
 int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return LV_OK;
   const dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
+  if (vec_ok(g.A, g.lda) && vec_ok(g.B, g.ldb)) {
+    if (a_kcont && b_kcont)
+      hipLaunchKernelGGL((gemm_vec_kernel<true, true>), grid, dim3(256), 0, s, g);
+    else if (a_kcont)
+      hipLaunchKernelGGL((gemm_vec_kernel<true, false>), grid, dim3(256), 0, s, g);
+    else if (b_kcont)
+      hipLaunchKernelGGL((gemm_vec_kernel<false, true>), grid, dim3(256), 0, s, g);
+    else
+      hipLaunchKernelGGL((gemm_vec_kernel<false, false>), grid, dim3(256), 0, s, g);
+    LV_CHECK_LAUNCH();
+    return LV_OK;
+  }
   if (a_kcont && b_kcont)
     hipLaunchKernelGGL((gemm_kernel<true, true>), grid, dim3(256), 0, s, g);
   else if (a_kcont)

@@ -19,15 +19,11 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 
-// float32 -> bfloat16 bits, round to nearest even (finite inputs).
-__device__ __forceinline__ uint32_t bf16_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return u >> 16;
-}
-
+// Two floats to bfloat16 (round to nearest even) in one conversion instruction.
 __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
-  return bf16_bits(lo) | (bf16_bits(hi) << 16);
+  typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+  const bf16x2 h = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, h);
 }
 
 // A operand: 8 consecutive k of one row, as bfloat16.

@@ -43,17 +43,26 @@ __global__ __launch_bounds__(256) void dot_partials(const float *__restrict__ a,
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// out[0] = total, out[1] = pair part, out[2] = trace part
-__global__ void finish_loss(const double *__restrict__ partial, int nblocks, double inv_pairs,
-                            double trace_const, float lam, int with_trace,
-                            float *__restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double p[3] = {0.0, 0.0, 0.0};
+// out[0] = total, out[1] = pair part, out[2] = trace part.  One workgroup of
+// kRedBlocks threads adds the partial sums in a fixed tree order.
+__global__ __launch_bounds__(kRedBlocks) void finish_loss(const double *__restrict__ partial,
+                                                          int nblocks, double inv_pairs,
+                                                          double trace_const, float lam,
+                                                          int with_trace, float *__restrict__ out) {
+  __shared__ double red[3][kRedBlocks];
+  const int t = threadIdx.x;
   const int nparts = with_trace ? 3 : 1;
-  for (int j = 0; j < nparts; ++j)
-    for (int i = 0; i < nblocks; ++i) p[j] += partial[j * nblocks + i];
-  const double pair = p[0] * inv_pairs;
-  const double tr = with_trace ? p[1] + trace_const - 2.0 * p[2] : 0.0;
+  for (int j = 0; j < 3; ++j)
+    red[j][t] = (j < nparts && t < nblocks) ? partial[j * nblocks + t] : 0.0;
+  __syncthreads();
+  for (int w = kRedBlocks / 2; w > 0; w >>= 1) {
+    if (t < w)
+      for (int j = 0; j < 3; ++j) red[j][t] += red[j][t + w];
+    __syncthreads();
+  }
+  if (t != 0) return;
+  const double pair = red[0][0] * inv_pairs;
+  const double tr = with_trace ? red[1][0] + trace_const - 2.0 * red[2][0] : 0.0;
   out[0] = (float)(pair + (double)lam * tr);
   out[1] = (float)pair;
   out[2] = (float)tr;
@@ -170,7 +179,8 @@ extern "C" int lv_projloss_fwd(const float *A, const float *B, const float *Qb, 
     hipLaunchKernelGGL(lv::dot_partials, dim3(lv::kRedBlocks), dim3(256), 0, s, w.U2, w.U1,
                        (int64_t)d * D, w.partial + 2 * lv::kRedBlocks);
   }
-  hipLaunchKernelGGL(lv::finish_loss, dim3(1), dim3(64), 0, s, w.partial, lv::kRedBlocks,
+  hipLaunchKernelGGL(lv::finish_loss, dim3(1), dim3(lv::kRedBlocks), 0, s, w.partial,
+                     lv::kRedBlocks,
                      1.0 / ((double)bq * (double)bx), trace_const, lam, with_trace, loss);
   LV_CHECK_LAUNCH();
   return LV_OK;

@@ -29,7 +29,10 @@ def t(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
 
 
-@pytest.mark.parametrize("M,N,K", [(70, 130, 45), (128, 128, 32), (1, 300, 7), (257, 3, 100)])
+# shapes whose leading dimensions are multiples of 4 take the vector-load kernel
+# (full and partial tiles in M, N and K); the others the element-wise one
+@pytest.mark.parametrize("M,N,K", [(70, 130, 45), (128, 128, 32), (1, 300, 7), (257, 3, 100),
+                                   (200, 136, 100), (256, 256, 128), (132, 260, 196)])
 @pytest.mark.parametrize("ak,bk", [(True, True), (True, False), (False, True), (False, False)])
 def test_gemm_exact_on_small_integers(lv, M, N, K, ak, bk):
     rng = np.random.default_rng(M * 7 + N + K)
@@ -143,3 +146,20 @@ def test_refinement_reduces_the_loss(lv, block):
     refine(A, B, blocks, 30, lr=1e-3, KQn=t(KQ), KXn=t(KX), trace_const=tc, lam=1.0,
            callback=lambda s, l: losses.append(float(l[0])))
     assert losses[-1] < losses[0]
+
+
+def test_gemm_unaligned_operands_take_the_elementwise_kernel(lv):
+    # operands starting one float past a 16-byte boundary: same exact result
+    rng = np.random.default_rng(17)
+    M, N, K = 96, 80, 64
+    a = rng.integers(-6, 7, size=(M, K)).astype(np.float64)
+    b = rng.integers(-6, 7, size=(N, K)).astype(np.float64)
+    Ab = torch.zeros(M * K + 1, dtype=torch.float32, device=DEV)
+    Bb = torch.zeros(N * K + 1, dtype=torch.float32, device=DEV)
+    Ab[1:] = t(a).view(-1)
+    Bb[1:] = t(b).view(-1)
+    C = torch.zeros((M, N), dtype=torch.float32, device=DEV)
+    lv.load().lv_gemm(Ab[1:].data_ptr(), 1, K, Bb[1:].data_ptr(), 1, K, C.data_ptr(), N, M, N, K,
+                      1.0, 0.0, None)
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy().astype(np.float64), a @ b.T)
