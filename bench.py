@@ -661,6 +661,8 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     single_qps = m * 5 / (e0.elapsed_time(e1) / 1e3)
+    small_batches = small_batch_report(lv, torch, index, Qd, Qp, k, L_star, hs,
+                                       sorted({1, max(1, args.expand)}))
 
     # ---- CPU oracle on a bounded sample
     cpu = None
@@ -728,8 +730,49 @@ def main():
                         "graph_build_repeatable": g.get("deterministic")},
         "cpu_baseline": cpu,
         "traversal_compare": variant,
+        "small_batches": small_batches,
     }
     print(json.dumps(out))
+
+
+def small_batch_report(lv, torch, index, Qd, Qp, k, L, hs, expands, reps=20):
+    """Latency of one plain search call over b queries (projection excluded,
+    projected queries resident), one wavefront per query against the team
+    launch (four wavefronts per query), at the benchmark's window.  The two
+    launches must return identical ids."""
+    rows = []
+    for b in (1, 16, 64, 256, 1024):
+        for e in expands:
+            res = {}
+            for name, launch in (("one_wave", lv.LV_LAUNCH_PER_QUERY),
+                                 ("team", lv.LV_LAUNCH_TEAM)):
+                ids = torch.empty((b, k), dtype=torch.int32, device=Qd.device)
+                sc = torch.empty((b, k), dtype=torch.float32, device=Qd.device)
+
+                def call():
+                    lv.lv_search_projected(index, Qd[:b], Qp[:b], k, L, ids, sc, hash_slots=hs,
+                                           expand=e, launch=launch)
+
+                call()
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    call()
+                e1.record()
+                torch.cuda.synchronize()
+                us = e0.elapsed_time(e1) * 1e3 / reps
+                res[name] = (us, ids.cpu().numpy().copy())
+            rows.append({"queries": b, "expand": e, "one_wave_us": res["one_wave"][0],
+                         "team_us": res["team"][0],
+                         "team_speedup": res["one_wave"][0] / res["team"][0],
+                         "identical": bool(np.array_equal(res["one_wave"][1], res["team"][1]))})
+            log(f"small batch b={b} E={e}: one wave {res['one_wave'][0]:.1f} us, "
+                f"team {res['team'][0]:.1f} us")
+    return {"L": L, "k": k, "visited_slots": hs, "reps": reps,
+            "timing": "HIP events around reps calls of lv_search_projected (traversal + "
+                      "re-rank), current stream", "rows": rows}
 
 
 def cpu_baseline(wl, X, Xs, Q, adj, entry, L, sample, truth, expand=1):

@@ -265,9 +265,15 @@ typedef struct {
   int32_t hash_slots; /* visited-set slots per query (power of 2, 256..65536; 0 = 1024) */
   int32_t probes;     /* slots tried before an id replaces the one in its home slot
                          (1..16; 0 = 2 below 4096 slots, 8 from 4096 slots) */
-  int32_t launch;     /* batched traversal only: LV_LAUNCH_PER_QUERY (0, one workgroup
+  int32_t launch;     /* batched traversal: LV_LAUNCH_PER_QUERY (0, one workgroup
                          per query, scheduled by the hardware) or LV_LAUNCH_PERSISTENT
-                         (1, resident wavefronts pull queries from a device counter) */
+                         (1, resident wavefronts pull queries from a device counter).
+                         lv_search / lv_search_projected: 0 and 1 give one wavefront
+                         per query; LV_LAUNCH_TEAM (2) gives each query a workgroup of
+                         4 wavefronts that score every batch of candidates together
+                         (lower latency for batches too small to fill the GPU; same
+                         results as one wavefront with the same `expand`).  The batched
+                         traversal refuses LV_LAUNCH_TEAM (LV_EINVAL). */
   int32_t expand;     /* entries expanded per iteration: 0 or 1 = the paper's traversal
                          (one expansion at a time); 2..8 = a throughput variant that
                          expands the `expand` best unexpanded entries together (its results
@@ -275,6 +281,7 @@ typedef struct {
 } lv_search_params;
 #define LV_LAUNCH_PER_QUERY 0
 #define LV_LAUNCH_PERSISTENT 1
+#define LV_LAUNCH_TEAM 2
 
 /* Bytes of device workspace lv_search needs for m queries. */
 size_t lv_search_workspace_size(const lv_index *index, int64_t m);
@@ -491,10 +498,19 @@ int lv_graph_build(const void *records, int32_t record_stride, int64_t N, int32_
  * to bfloat16, float32 accumulation), the product the loss kernels use.
  * a(m, k) is A[m*lda + k] if a_kcont else A[k*lda + m]; likewise b(n, k).
  * C: device float32 [M][ldc].  beta = 0 does not read C.
+ * workspace: optional device buffer of workspace_bytes (caller-owned; NULL
+ * or 0 for none).  With one, a product with few output tiles and a long K
+ * is split over K into partial products there, which a second kernel adds
+ * in a fixed order (the result does not depend on scheduling); a smaller
+ * workspace than lv_gemm_workspace_size gives fewer parts.  Calls that
+ * share a workspace must not overlap.
  */
 int lv_gemm(const float *A, int32_t a_kcont, int64_t lda, const float *B, int32_t b_kcont,
             int64_t ldb, float *C, int64_t ldc, int32_t M, int32_t N, int32_t K, float alpha,
-            float beta, void *stream);
+            float beta, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes with which lv_gemm may split an M x N product the most. */
+size_t lv_gemm_workspace_size(int32_t M, int32_t N);
 
 /* Device workspace bytes for lv_projloss_fwd / lv_projloss_bwd. */
 size_t lv_projloss_workspace_size(int32_t bq, int32_t bx, int32_t D, int32_t d);

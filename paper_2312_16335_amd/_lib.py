@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "liblv.so")
 LV_OK, LV_WNOTCONVERGED = 0, 1
 LV_EINVAL, LV_ENOMEM, LV_EDEVICE, LV_EUNSUPPORTED = -1, -2, -3, -4
 LV_F32, LV_F16, LV_LVQ8, LV_F16_RESID = 0, 1, 2, 3
-LV_LAUNCH_PER_QUERY, LV_LAUNCH_PERSISTENT = 0, 1
+LV_LAUNCH_PER_QUERY, LV_LAUNCH_PERSISTENT, LV_LAUNCH_TEAM = 0, 1, 2
 LV_SENTINEL = 0xFFFFFFFF
 LV_FW_INIT_ES, LV_FW_INIT_ZERO, LV_FW_INIT_GIVEN = 0, 1, 2
 
@@ -111,7 +111,8 @@ _SIGS = {
                                     _c_i32, ctypes.POINTER(SearchParams),
                                     ctypes.POINTER(_c_i32), ctypes.POINTER(_c_dbl), _vp]),
     "lv_gemm": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i32, _c_i64, _vp, _c_i64, _c_i32, _c_i32,
-                         _c_i32, ctypes.c_float, ctypes.c_float, _vp]),
+                         _c_i32, ctypes.c_float, ctypes.c_float, _vp, ctypes.c_size_t, _vp]),
+    "lv_gemm_workspace_size": (ctypes.c_size_t, [_c_i32, _c_i32]),
     "lv_projloss_workspace_size": (ctypes.c_size_t, [_c_i32, _c_i32, _c_i32, _c_i32]),
     "lv_projloss_fwd": (_c_i32, [_vp, _vp, _vp, _vp, _c_i32, _c_i32, _c_i32, _c_i32, _vp, _vp,
                                  _c_dbl, ctypes.c_float, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -384,7 +385,8 @@ def lv_search_workspace_size(index: Index, m: int) -> int:
 
 
 def lv_search(index: Index, Q, k: int, L: int, ids, scores, counters=None, ws=None,
-              hash_slots: int = 0, stream=None, probes: int = 0, expand: int = 0) -> None:
+              hash_slots: int = 0, stream=None, probes: int = 0, expand: int = 0,
+              launch: int = LV_LAUNCH_PER_QUERY) -> None:
     import torch
 
     m = Q.shape[0]
@@ -392,19 +394,20 @@ def lv_search(index: Index, Q, k: int, L: int, ids, scores, counters=None, ws=No
     _check(load().lv_search(index.handle, _dev(Q, torch.float32), m, k, L,
                             _dev(ids, torch.int32), _dev(scores, torch.float32),
                             _dev(counters, torch.int32), _dev(ws), ws_bytes,
-                            _params(hash_slots, probes, 0, expand), _stream(stream)))
+                            _params(hash_slots, probes, launch, expand), _stream(stream)))
 
 
 def lv_search_projected(index: Index, Q, Qp, k: int, L: int, ids, scores, counters=None,
                         hash_slots: int = 0, stream=None, probes: int = 0,
-                        expand: int = 0) -> None:
+                        expand: int = 0, launch: int = LV_LAUNCH_PER_QUERY) -> None:
     import torch
 
     m = Q.shape[0]
     _check(load().lv_search_projected(index.handle, _dev(Q, torch.float32),
                                       _dev(Qp, torch.float32), m, k, L, _dev(ids, torch.int32),
                                       _dev(scores, torch.float32), _dev(counters, torch.int32),
-                                      _params(hash_slots, probes, 0, expand), _stream(stream)))
+                                      _params(hash_slots, probes, launch, expand),
+                                      _stream(stream)))
 
 
 # ------------------------------------------------------------ batched search
@@ -516,15 +519,22 @@ def lv_autotune_knobs(multi: Multi, max_requests, max_queries, max_L, reqs, Q, i
 # ------------------------------------------------- differentiable projection
 
 def lv_gemm(A, B, C, M, N, K, a_kcont=True, b_kcont=True, lda=None, ldb=None, ldc=None,
-            alpha=1.0, beta=0.0, stream=None):
+            alpha=1.0, beta=0.0, workspace=None, stream=None):
     import torch
 
     lda = lda if lda is not None else (K if a_kcont else M)
     ldb = ldb if ldb is not None else (K if b_kcont else N)
     ldc = ldc if ldc is not None else N
+    ws, ws_bytes = None, 0
+    if workspace is not None:
+        ws, ws_bytes = _dev(workspace, workspace.dtype), workspace.numel() * workspace.element_size()
     _check(load().lv_gemm(_dev(A, torch.float32), int(a_kcont), lda, _dev(B, torch.float32),
                           int(b_kcont), ldb, _dev(C, torch.float32), ldc, M, N, K, alpha, beta,
-                          _stream(stream)))
+                          ws, ws_bytes, _stream(stream)))
+
+
+def lv_gemm_workspace_size(M, N) -> int:
+    return load().lv_gemm_workspace_size(M, N)
 
 
 def lv_projloss_workspace_size(bq, bx, D, d) -> int:

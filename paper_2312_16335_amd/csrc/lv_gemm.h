@@ -20,6 +20,13 @@ struct GemmArgs {
 
 // C = alpha * op(A) op(B)^T + beta * C; a_kcont / b_kcont select whether
 // a(m, k) is A[m * lda + k] (true) or A[k * lda + m] (false), same for b(n, k).
-int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s);
+// With a workspace (split_ws, split_floats floats), a product with few output
+// tiles and a long K is split over K: each part writes alpha times its
+// partial product to the workspace, and a second kernel adds the parts in a
+// fixed order (deterministic) before beta * C.
+int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *split_ws = nullptr,
+         size_t split_floats = 0);
+// Workspace floats gemm may use for an M x N product split over K.
+size_t gemm_split_floats(int64_t M, int64_t N);
 
 }  // namespace lv

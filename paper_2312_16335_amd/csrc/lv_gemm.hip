@@ -218,8 +218,11 @@ __device__ __forceinline__ void vstore(const Frag &f, uint16_t *S, int tid) {
   }
 }
 
+// Split over K (grid z): part z covers steps [z * sps, (z + 1) * sps) and,
+// when `part` is set, writes alpha times its partial product to
+// part[z][M][N]; otherwise the whole K range goes to C.
 template <bool AK, bool BKC>
-__global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g, int sps, float *part) {
   __shared__ __align__(16) uint16_t As[2][BM * VLD];
   __shared__ __align__(16) uint16_t Bs[2][BN * VLD];
   const int tid = threadIdx.x;
@@ -235,10 +238,12 @@ __global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
-  const int nk = (g.K + VK - 1) / VK;
+  const int nk_all = (g.K + VK - 1) / VK;
+  const int t0 = (int)blockIdx.z * sps;
+  const int nk = (t0 + sps < nk_all ? t0 + sps : nk_all) - t0;  // steps of this part
   Frag fa, fb;
-  vload<AK>(g.A, g.lda, g.M, g.K, m0, 0, fa, tid);
-  vload<BKC>(g.B, g.ldb, g.N, g.K, n0, 0, fb, tid);
+  vload<AK>(g.A, g.lda, g.M, g.K, m0, t0 * VK, fa, tid);
+  vload<BKC>(g.B, g.ldb, g.N, g.K, n0, t0 * VK, fb, tid);
   vstore<AK>(fa, As[0], tid);
   vstore<BKC>(fb, Bs[0], tid);
   __syncthreads();
@@ -247,8 +252,8 @@ __global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g) {
     const int cur = t & 1;
     const bool more = t + 1 < nk;
     if (more) {  // next step's operands in flight during this step's products
-      vload<AK>(g.A, g.lda, g.M, g.K, m0, (t + 1) * VK, fa, tid);
-      vload<BKC>(g.B, g.ldb, g.N, g.K, n0, (t + 1) * VK, fb, tid);
+      vload<AK>(g.A, g.lda, g.M, g.K, m0, (t0 + t + 1) * VK, fa, tid);
+      vload<BKC>(g.B, g.ldb, g.N, g.K, n0, (t0 + t + 1) * VK, fb, tid);
     }
 #pragma unroll
     for (int ks = 0; ks < VK; ks += 16) {
@@ -274,6 +279,7 @@ __global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g) {
     }
     __syncthreads();
   }
+  float *pz = part ? part + (int64_t)blockIdx.z * g.M * g.N : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -284,12 +290,31 @@ __global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g) {
       for (int e = 0; e < 16; ++e) {
         const int row = m0 + wm + 32 * i + 8 * (e >> 2) + 4 * kh + (e & 3);
         if (row >= g.M) continue;
-        float *c = g.C + (int64_t)row * g.ldc + col;
         const float v = g.alpha * acc[i][j][e];
-        *c = g.beta == 0.f ? v : v + g.beta * *c;
+        if (pz) {
+          pz[(int64_t)row * g.N + col] = v;
+        } else {
+          float *c = g.C + (int64_t)row * g.ldc + col;
+          *c = g.beta == 0.f ? v : v + g.beta * *c;
+        }
       }
     }
 }
+
+// C = sum over z of part[z] (in order z = 0, 1, ...) + beta * C.
+__global__ __launch_bounds__(256) void split_sum_kernel(const float *__restrict__ part, int nz,
+                                                        GemmArgs g) {
+  const int64_t mn = (int64_t)g.M * g.N;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < mn;
+       i += (int64_t)gridDim.x * 256) {
+    float v = part[i];
+    for (int z = 1; z < nz; ++z) v += part[z * mn + i];
+    float *c = g.C + (i / g.N) * g.ldc + i % g.N;
+    *c = g.beta == 0.f ? v : v + g.beta * *c;
+  }
+}
+
+constexpr int kMaxSplit = 16;
 
 bool vec_ok(const float *p, int64_t ld) {
   return (reinterpret_cast<uintptr_t>(p) & 15u) == 0 && ld % 4 == 0;
@@ -297,18 +322,40 @@ bool vec_ok(const float *p, int64_t ld) {
 
 }  // namespace
 
-int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s) {
+size_t gemm_split_floats(int64_t M, int64_t N) { return (size_t)kMaxSplit * M * N; }
+
+int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *split_ws,
+         size_t split_floats) {
   if (g.M <= 0 || g.N <= 0) return LV_OK;
   const dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
   if (vec_ok(g.A, g.lda) && vec_ok(g.B, g.ldb)) {
+    // few output tiles and a long K: split K so that about 128 workgroups run
+    const int tiles = (int)(grid.x * grid.y);
+    const int nk = (g.K + VK - 1) / VK;
+    int parts = 1;
+    if (split_ws && tiles < 64 && g.K >= 512) {
+      parts = 128 / tiles;
+      if (parts > (g.K + 255) / 256) parts = (g.K + 255) / 256;
+      if (parts > kMaxSplit) parts = kMaxSplit;
+      while (parts > 1 && (size_t)parts * g.M * g.N > split_floats) --parts;
+    }
+    const int sps = nk > 0 ? (nk + parts - 1) / parts : 1;  // steps per part
+    parts = nk > 0 ? (nk + sps - 1) / sps : 1;
+    float *part = parts > 1 ? split_ws : nullptr;
+    const dim3 gz(grid.x, grid.y, (unsigned)parts);
     if (a_kcont && b_kcont)
-      hipLaunchKernelGGL((gemm_vec_kernel<true, true>), grid, dim3(256), 0, s, g);
+      hipLaunchKernelGGL((gemm_vec_kernel<true, true>), gz, dim3(256), 0, s, g, sps, part);
     else if (a_kcont)
-      hipLaunchKernelGGL((gemm_vec_kernel<true, false>), grid, dim3(256), 0, s, g);
+      hipLaunchKernelGGL((gemm_vec_kernel<true, false>), gz, dim3(256), 0, s, g, sps, part);
     else if (b_kcont)
-      hipLaunchKernelGGL((gemm_vec_kernel<false, true>), grid, dim3(256), 0, s, g);
+      hipLaunchKernelGGL((gemm_vec_kernel<false, true>), gz, dim3(256), 0, s, g, sps, part);
     else
-      hipLaunchKernelGGL((gemm_vec_kernel<false, false>), grid, dim3(256), 0, s, g);
+      hipLaunchKernelGGL((gemm_vec_kernel<false, false>), gz, dim3(256), 0, s, g, sps, part);
+    if (part) {
+      const int64_t mn = (int64_t)g.M * g.N;
+      const unsigned blocks = (unsigned)((mn + 255) / 256 < 2048 ? (mn + 255) / 256 : 2048);
+      hipLaunchKernelGGL(split_sum_kernel, dim3(blocks), dim3(256), 0, s, part, parts, g);
+    }
     LV_CHECK_LAUNCH();
     return LV_OK;
   }
@@ -328,12 +375,22 @@ int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s) {
 
 extern "C" int lv_gemm(const float *A, int32_t a_kcont, int64_t lda, const float *B,
                        int32_t b_kcont, int64_t ldb, float *C, int64_t ldc, int32_t M, int32_t N,
-                       int32_t K, float alpha, float beta, void *stream) {
+                       int32_t K, float alpha, float beta, void *workspace,
+                       size_t workspace_bytes, void *stream) {
   lv::clear_error();
   if (M < 0 || N < 0 || K < 0) LV_FAIL(LV_EINVAL, "negative size");
   if ((int64_t)M * N > 0 && (!A || !B || !C)) LV_FAIL(LV_EINVAL, "NULL pointer");
   if (ldc < N || lda < (a_kcont ? K : M) || ldb < (b_kcont ? K : N))
     LV_FAIL(LV_EINVAL, "leading dimension too small");
   lv::GemmArgs g{A, lda, B, ldb, C, ldc, M, N, K, alpha, beta};
-  return lv::gemm(g, a_kcont != 0, b_kcont != 0, static_cast<hipStream_t>(stream));
+  if (workspace_bytes > 0 && !workspace) LV_FAIL(LV_EINVAL, "NULL workspace");
+  if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 3u))
+    LV_FAIL(LV_EINVAL, "workspace not 4-byte aligned");
+  return lv::gemm(g, a_kcont != 0, b_kcont != 0, static_cast<hipStream_t>(stream),
+                  static_cast<float *>(workspace), workspace ? workspace_bytes / sizeof(float) : 0);
+}
+
+extern "C" size_t lv_gemm_workspace_size(int32_t M, int32_t N) {
+  if (M <= 0 || N <= 0) return 0;
+  return lv::gemm_split_floats(M, N) * sizeof(float);
 }

@@ -19,6 +19,8 @@
 // subtracts G H^T into the same buffer.  Sums of squares and inner products
 // use a fixed-order two-pass float64 reduction, so results are deterministic.
 #include "lv_common.h"
+#include <algorithm>
+
 #include "lv_gemm.h"
 
 namespace lv {
@@ -94,6 +96,8 @@ __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p,
 // Workspace carve (floats, each region 64-float aligned).
 struct Ws {
   float *G, *H, *Rm, *T, *S, *U1, *U2, *M1, *M2, *W;
+  float *SP;          // partial products of GEMMs split over K
+  size_t sp_floats;
   double *partial;
 };
 
@@ -117,6 +121,10 @@ size_t ws_floats(int64_t bq, int64_t bx, int64_t D, int64_t d, Ws *w, float *bas
   take(&t->M1, d * d);
   take(&t->M2, d * d);
   take(&t->W, d * D);
+  // the split products have at most max(b_q, b_x) x d or d x D outputs
+  const int64_t mn = std::max(std::max(bq, bx) * d, d * D);
+  t->sp_floats = gemm_split_floats(mn, 1);
+  take(&t->SP, t->sp_floats);
   float *pp = nullptr;
   take(&pp, 2 * 3 * kRedBlocks);  // float64 partials
   if (w) w->partial = reinterpret_cast<double *>(pp);
@@ -132,10 +140,12 @@ int check_args(const float *A, const float *B, const float *Qb, const float *Xb,
   return LV_OK;
 }
 
-#define LV_G(...)                                   \
-  do {                                              \
-    int rc_ = ::lv::gemm(__VA_ARGS__);              \
-    if (rc_ != LV_OK) return rc_;                   \
+// One product (arguments of lv::gemm), split over K in the workspace when
+// that gives more workgroups.
+#define LV_G(...)                                         \
+  do {                                                    \
+    int rc_ = ::lv::gemm(__VA_ARGS__, w.SP, w.sp_floats); \
+    if (rc_ != LV_OK) return rc_;                         \
   } while (0)
 
 }  // namespace

@@ -82,6 +82,7 @@ struct VisitedCfg {
   int log2h;
   int probes;
   int expand;
+  bool team = false;  // plain search: kTeamWaves wavefronts per query
 };
 int visited_config(const lv_search_params *params, VisitedCfg *cfg);
 size_t beam_lds_bytes(int L, int log2h);

@@ -37,6 +37,14 @@
 // requests (each with its own sub-index, k and L), either one workgroup per
 // query or resident wavefronts pulling queries from a device counter.
 //
+// For batches too small to fill the GPU a third, team launch gives each
+// query a workgroup of kTeamWaves wavefronts: the first runs the traversal
+// of the multi-expansion body (with one expansion per iteration it is the
+// paper's traversal), and every batch of candidates is scored by all of
+// them, each wavefront a slice, as is the final re-ranking of the window;
+// the others wait at workgroup barriers between batches.  Scores, order and
+// results are those of the one-wavefront body.
+//
 // Graph construction (Appendix A) runs the same body with a database node as
 // the query: its own codes take the place of the projected query, a record
 // is scored with minus the squared distance of the two LVQ reconstructions,
@@ -53,6 +61,8 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
 constexpr int kFastMerge = 8;  // survivors merged by counting instead of sorting
 constexpr int kMaxExpand = 8;  // entries expanded per iteration by the throughput variant
+constexpr int kTeamWaves = 4;  // wavefronts per query of the team launch
+constexpr size_t kTeamLdsBytes = 16;  // the team's command word, after the visited set
 
 // Everything one query needs besides the index.
 struct Job {
@@ -432,6 +442,19 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
   }
 }
 
+// Re-rank entries [0, n) of ids/out with the index's kind of secondaries.
+__device__ __forceinline__ void rerank_any(const IndexView &ix, const float *q,
+                                           const uint32_t *ids, double *out, int n, int lane) {
+  if (ix.sec_kind == LV_F16)
+    rerank_rows<LV_F16>(ix, q, ids, out, n, lane);
+  else if (ix.sec_kind == LV_LVQ8)
+    rerank_rows<LV_LVQ8>(ix, q, ids, out, n, lane);
+  else if (ix.sec_kind == LV_F16_RESID)
+    rerank_rows<LV_F16_RESID>(ix, q, ids, out, n, lane);
+  else
+    rerank_rows<LV_F32>(ix, q, ids, out, n, lane);
+}
+
 // Merge the scored batch (cid/cs[0..nc)) into the window of nl <= L
 // entries, in place; duplicates of window entries are dropped.  DEDUP also
 // drops repeats inside the batch (a batch gathered from several rows can hold
@@ -579,13 +602,40 @@ __device__ __forceinline__ void merge_batch(const Lds &sm, int nc, int L, int &n
   wave_sync();
 }
 
+// Start of wavefront w's slice of a batch of nc candidates in the team
+// launch: slices are whole passes of 64 / G records, as even as possible,
+// in wavefront order (w = WQ gives nc).
+template <int G, int WQ>
+__device__ __forceinline__ int team_slice(int nc, int w) {
+  constexpr int RPP = 64 / G;
+  const int passes = (nc + RPP - 1) / RPP;
+  const int per = (passes + WQ - 1) / WQ;
+  const int o = w * per * RPP;
+  return o < nc ? o : nc;
+}
+
+// The team's command word: the LDS word after the visited set.
+__device__ __forceinline__ int *team_cmd(const Lds &sm, int hslots) {
+  return reinterpret_cast<int *>(sm.hash() + hslots);
+}
+
 // The whole search of one query by one wavefront.  BUILD: construction
 // search for node job.node; the final window goes to job.ids (L entries,
 // padded with the sentinel).  MULTI: the throughput variant that expands up
 // to `expand` entries per iteration (not the paper's traversal).
-template <int BITS, int G, int V, bool BUILD = false, bool MULTI = false>
+//
+// WQ > 1 (team launch, MULTI only): the workgroup has WQ wavefronts and
+// the LDS word after the visited set is the team's command word
+// (kTeamLdsBytes more per workgroup).  Wavefront 0 (the leader) runs the search; at
+// every batch it publishes the candidate count in *cmd and the whole
+// workgroup scores the batch between two barriers; after the traversal it
+// publishes -2 - (window size), the workgroup re-ranks the window between
+// two barriers, and the other wavefronts return.  Every wavefront therefore
+// passes the same sequence of barriers.
+template <int BITS, int G, int V, bool BUILD = false, bool MULTI = false, int WQ = 1>
 __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm, int log2h,
                              int probes, int expand, int lane) {
+  static_assert(WQ == 1 || (MULTI && !BUILD), "team search is the multi-expansion body");
   constexpr int NQ = V * 8 / BITS;
   const int L = job.L;
   const int hslots = 1 << log2h;
@@ -628,6 +678,29 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
     // the same in every lane after the group reduction: keep them scalar
     sq = lane_f64(group_sum<G>(sq), 0);
     cq = lane_f64(group_sum<G>(cq), 0);
+  }
+  if constexpr (WQ > 1) {
+    // slice of each batch: whole passes of 64 / G records per wavefront
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (wave != 0) {
+      for (;;) {
+        __syncthreads();  // the leader has published a batch (or the end)
+        const int nc = __builtin_amdgcn_readfirstlane(*team_cmd(sm, hslots));
+        if (nc < 0) {  // -2 - nl: re-rank this wavefront's slice of the window, end
+          const int nl = -2 - nc;
+          const int r0 = team_slice<16, WQ>(nl, wave);
+          rerank_any(ix, job.q, sm.lid() + r0, sm.ls() + r0,
+                     team_slice<16, WQ>(nl, wave + 1) - r0, lane);
+          __syncthreads();  // slices re-ranked
+          return;
+        }
+        const int off = team_slice<G, WQ>(nc, wave);
+        const int cnt = team_slice<G, WQ>(nc, wave + 1) - off;
+        score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid() + off, sm.cs() + off, cnt,
+                                       lane);
+        __syncthreads();  // scores written
+      }
+    }
   }
   for (int i = lane; i < hslots; i += 64) sm.hash()[i] = kEmpty;
   wave_sync();
@@ -702,7 +775,15 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
         if (!more || nc + cnt > 64) {
           if (nc > 0) {
             wave_sync();
-            score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), nc, lane);
+            if constexpr (WQ > 1) {
+              if (lane == 0) *team_cmd(sm, hslots) = nc;
+              __syncthreads();  // batch and count visible to the workgroup
+              score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(),
+                                             team_slice<G, WQ>(nc, 1), lane);
+              __syncthreads();  // every slice scored
+            } else {
+              score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), nc, lane);
+            }
             wave_sync();
             n_dist += nc;
             merge_batch<true>(sm, nc, L, nl, lane);
@@ -720,6 +801,10 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
           for (int t = 0; t + 1 < kMaxExpand; ++t) first[t] = first[t + 1];
         }
       }
+    }
+    if constexpr (WQ > 1) {  // the window's size: the team's re-ranking order
+      if (lane == 0) *team_cmd(sm, hslots) = -2 - nl;
+      __syncthreads();
     }
   } else {
     for (uint32_t hop = 0; hop < max_hops; ++hop) {
@@ -793,14 +878,20 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
   // score of entry j replaces its primary score, its id loses the flag
   uint32_t *id2 = sm.lid();
   double *s2 = sm.ls();
-  if (ix.sec_kind == LV_F16)
-    rerank_rows<LV_F16>(ix, job.q, id2, s2, nl, lane);
-  else if (ix.sec_kind == LV_LVQ8)
-    rerank_rows<LV_LVQ8>(ix, job.q, id2, s2, nl, lane);
-  else if (ix.sec_kind == LV_F16_RESID)
-    rerank_rows<LV_F16_RESID>(ix, job.q, id2, s2, nl, lane);
-  else
-    rerank_rows<LV_F32>(ix, job.q, id2, s2, nl, lane);
+  if constexpr (WQ > 1) {
+    // the team re-ranks too, a slice of whole 4-row passes each
+    rerank_any(ix, job.q, id2, s2, team_slice<16, WQ>(nl, 1), lane);
+    __syncthreads();  // every slice re-ranked
+  } else {
+    if (ix.sec_kind == LV_F16)
+      rerank_rows<LV_F16>(ix, job.q, id2, s2, nl, lane);
+    else if (ix.sec_kind == LV_LVQ8)
+      rerank_rows<LV_LVQ8>(ix, job.q, id2, s2, nl, lane);
+    else if (ix.sec_kind == LV_F16_RESID)
+      rerank_rows<LV_F16_RESID>(ix, job.q, id2, s2, nl, lane);
+    else
+      rerank_rows<LV_F32>(ix, job.q, id2, s2, nl, lane);
+  }
   wave_sync();
   for (int j = lane; j < nl; j += 64) id2[j] &= kIdMask;
   wave_sync();
@@ -876,6 +967,25 @@ __global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
   job.counters = a.counters ? a.counters + 2 * qi : nullptr;
   search_query<BITS, G, V, false, MULTI>(a.ix, job, sm, a.hash_log2, a.probes, a.expand,
                                          threadIdx.x);
+}
+
+// Team launch: one workgroup of kTeamWaves wavefronts per query (the
+// multi-expansion body; expand = 1 is the paper's traversal).
+template <int BITS, int G, int V>
+__global__ __launch_bounds__(64 * kTeamWaves) void team_kernel(PlainArgs a) {
+  const int64_t qi = blockIdx.x;
+  if (qi >= a.m) return;  // the same for the whole workgroup
+  const Lds sm = carve(a.L);
+  Job job;
+  job.qp = a.Qp + qi * a.qp_stride;
+  job.q = a.ix.sec_kind == LV_F16_RESID ? job.qp + a.ix.d : a.Q + qi * a.ix.D;
+  job.k = a.k;
+  job.L = a.L;
+  job.ids = a.ids + qi * a.k;
+  job.scores = a.scores + qi * a.k;
+  job.counters = a.counters ? a.counters + 2 * qi : nullptr;
+  search_query<BITS, G, V, false, true, kTeamWaves>(a.ix, job, sm, a.hash_log2, a.probes,
+                                                    a.expand, (int)(threadIdx.x & 63u));
 }
 
 // Batched form over a step's request table.  With a counter (persistent
@@ -971,8 +1081,11 @@ __global__ __launch_bounds__(64) void build_search_kernel(BuildSearchArgs a) {
 __global__ void reset_counter_kernel(unsigned int *counter) { *counter = 0u; }
 
 template <int BITS, int G, int V>
-int launch_plain_t(const PlainArgs &a, size_t lds, hipStream_t s) {
-  if (a.expand > 1)
+int launch_plain_t(const PlainArgs &a, bool team, size_t lds, hipStream_t s) {
+  if (team)
+    hipLaunchKernelGGL((team_kernel<BITS, G, V>), dim3((unsigned)a.m), dim3(64 * kTeamWaves),
+                       lds + kTeamLdsBytes, s, a);
+  else if (a.expand > 1)
     hipLaunchKernelGGL((beam_kernel<BITS, G, V, true>), dim3((unsigned)a.m), dim3(64), lds, s,
                        a);
   else
@@ -1021,10 +1134,11 @@ int dispatch(int bits, int group, int vbytes, F &&f) {
 
 struct PlainLaunch {
   const PlainArgs &a;
+  bool team;
   size_t lds;
   hipStream_t s;
   template <int B, int GG, int VV>
-  int operator()() { return launch_plain_t<B, GG, VV>(a, lds, s); }
+  int operator()() { return launch_plain_t<B, GG, VV>(a, team, lds, s); }
 };
 
 struct BatchedLaunch {
@@ -1098,6 +1212,11 @@ int visited_config(const lv_search_params *params, VisitedCfg *cfg) {
   if (ex < 0 || ex > kMaxExpand)
     LV_FAIL(LV_EINVAL, "expand must be in [0, %d] (got %d)", kMaxExpand, ex);
   cfg->expand = ex > 1 ? ex : 1;
+  const int la = params ? params->launch : LV_LAUNCH_PER_QUERY;
+  if (la != LV_LAUNCH_PER_QUERY && la != LV_LAUNCH_PERSISTENT && la != LV_LAUNCH_TEAM)
+    LV_FAIL(LV_EINVAL, "launch must be LV_LAUNCH_PER_QUERY, LV_LAUNCH_PERSISTENT or "
+                       "LV_LAUNCH_TEAM (got %d)", la);
+  cfg->team = la == LV_LAUNCH_TEAM;
   int l = 0;
   while ((1 << l) < hs) ++l;
   cfg->log2h = l;
@@ -1129,7 +1248,7 @@ int launch_beam(const lv_index *ix, const float *Q, const float *Qp, int64_t m, 
   if (m == 0) return LV_OK;
   if (m > 0x7FFFFFFF) LV_FAIL(LV_EINVAL, "at most 2^31-1 queries per call");
   const size_t lds = beam_lds_bytes(L, vc.log2h);
-  rc = check_lds(lds, L, vc.log2h);
+  rc = check_lds(lds + (vc.team ? kTeamLdsBytes : 0), L, vc.log2h);
   if (rc != LV_OK) return rc;
   PlainArgs a;
   a.ix = make_view(ix);
@@ -1145,7 +1264,7 @@ int launch_beam(const lv_index *ix, const float *Q, const float *Qp, int64_t m, 
   a.probes = vc.probes;
   a.expand = vc.expand;
   a.qp_stride = ix->qp_width;
-  PlainLaunch f{a, lds, stream};
+  PlainLaunch f{a, vc.team, lds, stream};
   return dispatch(ix->desc.bits, ix->group, ix->vbytes, f);
 }
 

@@ -86,7 +86,9 @@ def test_search_argument_validation_before_launch():
                 lv.SearchParams(1024, 17, 0),  # too many probes
                 lv.SearchParams(1024, -1, 0),
                 lv.SearchParams(1024, 0, 0, 9),    # more expansions per step than allowed
-                lv.SearchParams(1024, 0, 0, -1)):
+                lv.SearchParams(1024, 0, 0, -1),
+                lv.SearchParams(1024, 0, 3),       # no such launch
+                lv.SearchParams(1024, 0, -1)):
         assert lib.lv_search_projected(h, FAKE, FAKE, 10, 5, 50, FAKE, FAKE, None,
                                        ctypes.byref(bad), None) == lv.LV_EINVAL
         # refused before the query projection is launched
@@ -97,9 +99,12 @@ def test_search_argument_validation_before_launch():
     assert lib.lv_search(h, FAKE, 10, 5, 50, FAKE, FAKE, None, FAKE, 16,
                          ctypes.byref(prm), None) == lv.LV_EINVAL
     assert lib.lv_search_workspace_size(h, 10) >= 10 * 32 * 4
-    # zero queries: valid, nothing to do
+    # zero queries: valid, nothing to do (also with the team launch)
     assert lib.lv_search_projected(h, FAKE, FAKE, 0, 5, 50, FAKE, FAKE, None,
                                    ctypes.byref(prm), None) == lv.LV_OK
+    team = lv.SearchParams(0, 0, lv.LV_LAUNCH_TEAM, 3)
+    assert lib.lv_search_projected(h, FAKE, FAKE, 0, 5, 50, FAKE, FAKE, None,
+                                   ctypes.byref(team), None) == lv.LV_OK
     lib.lv_index_destroy(h)
 
 
@@ -116,6 +121,22 @@ def test_encode_and_project_validation():
     assert lib.lv_to_f16(FAKE, -5, FAKE, None) == lv.LV_EINVAL
     assert lv.lv_record_stride(160, 8) == 192 and lv.lv_record_stride(128, 4) == 128
     assert lv.lv_record_stride(32, 8) == 64 and lv.lv_record_stride(3000, 8) == 0
+
+
+def test_gemm_validation_and_workspace_size():
+    lib = lv.load()
+    assert lib.lv_gemm(FAKE, 1, 8, FAKE, 1, 8, FAKE, 4, 4, 4, 8, 1.0, 0.0, None, 64,
+                       None) == lv.LV_EINVAL
+    assert "workspace" in lib.lv_last_error().decode()
+    assert lib.lv_gemm(FAKE, 1, 8, FAKE, 1, 8, FAKE, 4, 4, 4, 8, 1.0, 0.0, FAKE + 2, 64,
+                       None) == lv.LV_EINVAL
+    assert lib.lv_gemm(FAKE, 1, 7, FAKE, 1, 8, FAKE, 4, 4, 4, 8, 1.0, 0.0, None, 0,
+                       None) == lv.LV_EINVAL
+    assert lib.lv_gemm(FAKE, 1, 8, FAKE, 1, 8, FAKE, 4, -1, 4, 8, 1.0, 0.0, None, 0,
+                       None) == lv.LV_EINVAL
+    # at most 16 parts of M x N floats; nothing for an empty product
+    assert lv.lv_gemm_workspace_size(128, 768) == 16 * 128 * 768 * 4
+    assert lv.lv_gemm_workspace_size(0, 768) == 0
 
 
 def test_batch_step_validation_without_a_device():

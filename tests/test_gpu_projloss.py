@@ -47,6 +47,35 @@ def test_gemm_exact_on_small_integers(lv, M, N, K, ak, bk):
     assert np.array_equal(C.cpu().numpy().astype(np.float64), 2.0 * a @ b.T - c0)
 
 
+# few output tiles and K >= 512 with a workspace: the product is split over K
+# (ragged last part included) and the parts added in order; integer operands
+# keep every partial sum exact, so the result must equal a @ b^T exactly.
+# A workspace too small for any split gives the unsplit kernel, same result.
+@pytest.mark.parametrize("M,N,K", [(128, 768, 4096), (100, 200, 1000), (64, 64, 513),
+                                   (8, 12, 2048), (256, 512, 700)])
+@pytest.mark.parametrize("ak,bk", [(True, True), (True, False), (False, False)])
+@pytest.mark.parametrize("ws", ["full", "tiny"])
+def test_gemm_split_over_k_is_exact(lv, M, N, K, ak, bk, ws):
+    rng = np.random.default_rng(M + 3 * N + 5 * K)
+    a = rng.integers(-6, 7, size=(M, K)).astype(np.float64)
+    b = rng.integers(-6, 7, size=(N, K)).astype(np.float64)
+    c0 = rng.integers(-3, 4, size=(M, N)).astype(np.float64)
+    A = a if ak else a.T.copy()
+    B = b if bk else b.T.copy()
+    nbytes = lv.lv_gemm_workspace_size(M, N) if ws == "full" else 4 * M * N
+    W = torch.full((nbytes // 4,), float("nan"), dtype=torch.float32, device=DEV)
+    C = t(c0)
+    lv.lv_gemm(t(A), t(B), C, M, N, K, a_kcont=ak, b_kcont=bk, alpha=2.0, beta=-1.0,
+               workspace=W)
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy().astype(np.float64), 2.0 * a @ b.T - c0)
+    # a second call with beta = 0 reuses the workspace's stale parts
+    C2 = torch.full((M, N), float("nan"), dtype=torch.float32, device=DEV)
+    lv.lv_gemm(t(A), t(B), C2, M, N, K, a_kcont=ak, b_kcont=bk, workspace=W)
+    torch.cuda.synchronize()
+    assert np.array_equal(C2.cpu().numpy().astype(np.float64), a @ b.T)
+
+
 @pytest.fixture(scope="module")
 def block():
     wl = gen.WORKLOADS["ood-1m-768"].scaled(N=8192, m_test=2048)
@@ -160,6 +189,6 @@ def test_gemm_unaligned_operands_take_the_elementwise_kernel(lv):
     Bb[1:] = t(b).view(-1)
     C = torch.zeros((M, N), dtype=torch.float32, device=DEV)
     lv.load().lv_gemm(Ab[1:].data_ptr(), 1, K, Bb[1:].data_ptr(), 1, K, C.data_ptr(), N, M, N, K,
-                      1.0, 0.0, None)
+                      1.0, 0.0, None, 0, None)
     torch.cuda.synchronize()
     assert np.array_equal(C.cpu().numpy().astype(np.float64), a @ b.T)

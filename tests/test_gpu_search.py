@@ -43,7 +43,8 @@ def gpu_index(lv, c: Case):
     return lv.Index(rec, mud, sec, adj, c.entry, c.wl.bits, c.wl.d, A_bf16=Pb), rec
 
 
-def run_projected(lv, index, c: Case, k, L, hash_slots=0, Q=None, Qp=None, expand=0):
+def run_projected(lv, index, c: Case, k, L, hash_slots=0, Q=None, Qp=None, expand=0,
+                  launch=0):
     Q = c.Q if Q is None else Q
     Qp = c.Qp if Qp is None else Qp
     m = len(Q)
@@ -51,7 +52,7 @@ def run_projected(lv, index, c: Case, k, L, hash_slots=0, Q=None, Qp=None, expan
     sc = torch.full((m, k), 7.0, dtype=torch.float32, device=DEV)
     cnt = torch.zeros((m, 2), dtype=torch.int32, device=DEV)
     lv.lv_search_projected(index, torch.from_numpy(Q).to(DEV), torch.from_numpy(Qp).to(DEV), k, L,
-                           ids, sc, cnt, hash_slots=hash_slots, expand=expand)
+                           ids, sc, cnt, hash_slots=hash_slots, expand=expand, launch=launch)
     torch.cuda.synchronize()
     return (ids.cpu().numpy().view(np.uint32).astype(np.int64), sc.cpu().numpy(),
             cnt.cpu().numpy())
@@ -233,6 +234,67 @@ def test_expand_variant_parity(lv, name, N, expand):
         got2 = run_projected(lv, index, c, wl.k, L, hash_slots=256, expand=expand)
         assert np.array_equal(got2[0], got_ids) and np.array_equal(got2[1], got_sc)
         assert np.array_equal(got2[2][:, 0], got_cnt[:, 0])
+
+
+def _oracle_expand(oidx, c, k, L, expand):
+    ids = np.empty((len(c.Q), k), np.int64)
+    sc = np.empty((len(c.Q), k))
+    cnt = np.empty((len(c.Q), 2), np.int64)
+    for i in range(len(c.Q)):
+        tr = osearch.Trace()
+        ids[i], sc[i] = osearch.search_one(oidx, c.Q[i], c.Qp[i], k, L, trace=tr, expand=expand)
+        cnt[i] = (tr.n_exp, tr.n_dist)
+    return ids, sc, cnt
+
+
+@pytest.mark.parametrize("expand", [1, 3, 8])
+@pytest.mark.parametrize("name,N,d", [("id-1m-768", 6000, 0), ("ood-1m-512", 6000, 0),
+                                      ("id-1m-768", 3000, 256)],
+                         ids=["lvq8-g16", "lvq4-g16", "lvq8-g64"])
+def test_team_launch_parity(lv, name, N, d, expand):
+    """Four wavefronts per query (team launch): the oracle's traversal with the
+    same number of expansions per iteration (one: the paper's), and
+    bit-for-bit the one-wavefront kernel's ids, scores and counters."""
+    from dataclasses import replace
+
+    wl = gen.WORKLOADS[name].scaled(N=N, m_test=40)
+    if d:
+        wl = replace(wl, d=d)
+    c = make_case(wl)
+    index, _ = gpu_index(lv, c)
+    oidx = c.oracle_index()
+    for L in (20, 60):
+        want_ids, want_sc, want_cnt = _oracle_expand(oidx, c, wl.k, L, expand)
+        got = run_projected(lv, index, c, wl.k, L, hash_slots=8192, expand=expand,
+                            launch=lv.LV_LAUNCH_TEAM)
+        assert_parity(c, oidx, got[0], got[1], want_ids, want_sc)
+        assert np.array_equal(got[2], want_cnt)
+        one = run_projected(lv, index, c, wl.k, L, hash_slots=8192, expand=expand)
+        for g, o in zip(got, one):
+            assert np.array_equal(g, o)
+        # small visited set: same results, scorings may repeat
+        got2 = run_projected(lv, index, c, wl.k, L, hash_slots=256, expand=expand,
+                             launch=lv.LV_LAUNCH_TEAM)
+        assert np.array_equal(got2[0], got[0]) and np.array_equal(got2[1], got[1])
+        assert np.array_equal(got2[2][:, 0], got[2][:, 0])
+
+
+@pytest.mark.parametrize("k,L", [(1, 1), (100, 128), (5, 300)])
+def test_team_launch_edges(lv, small, k, L):
+    """Team launch at the window extremes, one query, and no query."""
+    index, _ = gpu_index(lv, small)
+    oidx = small.oracle_index()
+    want_ids, want_sc, want_cnt = osearch.search_many(oidx, small.Q, small.Qp, k, L)
+    got_ids, got_sc, got_cnt = run_projected(lv, index, small, k, L, hash_slots=8192,
+                                             launch=lv.LV_LAUNCH_TEAM)
+    assert_parity(small, oidx, got_ids, got_sc, want_ids, want_sc)
+    assert np.array_equal(got_cnt, want_cnt)
+    one = run_projected(lv, index, small, k, L, hash_slots=8192, Q=small.Q[7:8],
+                        Qp=small.Qp[7:8], launch=lv.LV_LAUNCH_TEAM)
+    assert np.array_equal(one[0], got_ids[7:8]) and np.array_equal(one[1], got_sc[7:8])
+    none = run_projected(lv, index, small, k, L, Q=small.Q[:0], Qp=small.Qp[:0],
+                         launch=lv.LV_LAUNCH_TEAM)
+    assert none[0].shape == (0, k)
 
 
 def _resid_case(lv, N=6000):
