@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="id-1m-768")
+    ap.add_argument("--workload", default=None,
+                    help="id-1m-768 (default); with --fit: ood-1m-512 (default)")
     ap.add_argument("--n", type=int, default=0, help="override database size (testing)")
     ap.add_argument("--target", type=float, default=0.90)
     ap.add_argument("--hash-slots", type=int, default=0,
@@ -72,12 +73,16 @@ def parse():
                     help="index graph: the host builder on float16 vectors (cached), or "
                          "lv_graph_build on the primary vectors (timed)")
     ap.add_argument("--build-L", type=int, default=0,
-                    help="search window of the GPU graph build (default 2R)")
+                    help="search window of the GPU graph build (default R, as the host builder)")
     ap.add_argument("--build-batch", type=int, default=0,
                     help="largest insertion batch of the GPU graph build (default N/50)")
     ap.add_argument("--mfma", action="store_true",
                     help="only time the matrix-core kernels (projections, refinement step, a "
                          "large GEMM) against the bf16 peak and HBM, print one JSON line, exit")
+    ap.add_argument("--fit", action="store_true",
+                    help="only time and compare the projection fits (host float64: ID, "
+                         "eigenvector search, Frank-Wolfe; library and oracle) and their "
+                         "brute-force recall in the reduced space, print one JSON line, exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -114,7 +119,7 @@ def build_graph_gpu(lv, torch, wl, X, rec, args, out):
 
     entry = sgraph.medoid(X)
     order = np.random.default_rng(wl.seed_data + 17).permutation(wl.N).astype(np.uint32)
-    bL = args.build_L or 2 * wl.R
+    bL = args.build_L or wl.R
     mb = args.build_batch or max(1, wl.N // 50)
     adjd = torch.empty((wl.N, wl.R), dtype=torch.int32, device=rec.device)
     bp = lv.build_params(wl.R, bL, wl.graph_alphas, mb)
@@ -133,6 +138,121 @@ def build_graph_gpu(lv, torch, wl, X, rec, args, out):
     out["kind"] = (f"lv_graph_build on the primary vectors (window {bL}, batches up to {mb}, "
                    f"alphas {list(wl.graph_alphas)})")
     return adjd, entry
+
+
+def oracle_build_sample(wl, X, bL, n=1000):
+    """The oracle's construction (same R, window and alphas; batches up to
+    n / 50) on the first n database vectors, with the oracle's own fit,
+    projection and encoding: host nodes per second, one thread, for scale
+    beside the GPU build (the work per node grows slowly with N)."""
+    from oracle import fit as ofit
+    from oracle import graph as og
+    from oracle import lvq as olvq
+
+    Xs = X[:n]
+    P = ofit.fit_id(ofit.second_moment(Xs), wl.d)
+    Y = ofit.project(Xs, P).astype(np.float32)
+    mu = Y.astype(np.float64).mean(axis=0).astype(np.float32)
+    codes, delta, lo = olvq.encode(Y, mu, wl.bits)
+    prim = og.Primaries(codes, delta, lo)
+    order = np.random.default_rng(wl.seed_data + 17).permutation(n).astype(np.uint32)
+    t = time.time()
+    og.build(prim, order, int(order[0]), wl.R, bL, wl.graph_alphas, max(1, n // 50))
+    sec = time.time() - t
+    return {"kind": "oracle", "nodes": n, "s": sec, "nodes_per_s": n / sec, "cores": 1,
+            "sample": f"first {n} database vectors, oracle fit / projection / LVQ encoding"}
+
+
+def fit_report(lv, wl, n_s=100_000, m_test=1000, k=10):
+    """Projection fits of Section 2 on one workload, host float64: second
+    moments of n_s database vectors (the first n_s rows of the seeded
+    generator, a uniform sample) and of the learning queries, then LeanVec-ID
+    (top-d eigenvectors of K_X), eigenvector search (Algorithm 2), Frank-Wolfe
+    (Algorithm 1) from its default start (the eigenvectors of K_Q/m + K_X/n),
+    from zero, and from the eigenvector search's result.  Each is timed
+    in the library and in the oracle on the same moments; reported with its
+    loss (Problem leanvec_efficient, normalised moments) and the 10-recall@10
+    of exact search with <A q, B x> over the n_s vectors for m_test test
+    queries (the paper compares the fits by loss and brute-force accuracy)."""
+    from oracle import fit as ofit
+    from synth import gen
+
+    t0 = time.time()
+    mix = gen.mixture(wl)
+    X = gen.database(wl.scaled(N=n_s), mix)
+    Ql = gen.queries(wl, "learn", mix=mix)
+    Qt = gen.queries(wl, "test", m=m_test, mix=mix)
+    log(f"fit data: {X.shape} database sample, {Ql.shape} learning queries "
+        f"in {time.time() - t0:.1f}s")
+    D, d, m = wl.D, wl.d, len(Ql)
+
+    def timed(fn):
+        t = time.time()
+        r = fn()
+        return r, time.time() - t
+
+    KX = np.zeros((D, D))
+    KQ = np.zeros((D, D))
+    _, t_kx = timed(lambda: lv.lv_second_moment(X, KX))
+    _, t_kq = timed(lambda: lv.lv_second_moment(Ql, KQ))
+    KXo, t_kxo = timed(lambda: ofit.second_moment(X))
+    KQo, t_kqo = timed(lambda: ofit.second_moment(Ql))
+    moments = {"lib_s": t_kx + t_kq, "oracle_s": t_kxo + t_kqo,
+               "max_rel_diff": float(max(np.abs(KX - KXo).max() / np.abs(KXo).max(),
+                                         np.abs(KQ - KQo).max() / np.abs(KQo).max()))}
+
+    # exact top-k sets of <q, x> over the sample, and of <A q, B x> per fit
+    # (host float64; torch's top-k only for speed)
+    import torch
+
+    def top_k(Qm, Xm):
+        Xt = torch.from_numpy(np.ascontiguousarray(Xm, np.float64))
+        out = []
+        for i in range(0, len(Qm), 100):
+            S = torch.from_numpy(np.ascontiguousarray(Qm[i:i + 100], np.float64)) @ Xt.T
+            out.append(torch.topk(S, k, dim=1).indices.numpy())
+        return np.concatenate(out)
+
+    truth = top_k(Qt, X)
+
+    def recall(A, B):
+        got = top_k(Qt.astype(np.float64) @ A.T, X.astype(np.float64) @ B.T)
+        return float(np.mean([len(set(g) & set(t)) / k for g, t in zip(got, truth)]))
+
+    def loss(A, B):
+        return lv.lv_ood_loss(KQ, m, KX, n_s, A, B)
+
+    rows = {}
+    P, t = timed(lambda: lv.lv_fit_id(KX, d))
+    Po, to = timed(lambda: ofit.fit_id(KXo, d))
+    rows["id"] = {"lib_s": t, "oracle_s": to, "loss": loss(P, P), "recall": recall(P, P),
+                  "max_abs_diff_vs_oracle": float(np.abs(P - Po).max())}
+    (P, beta), t = timed(lambda: lv.lv_fit_es(KQ, m, KX, n_s, d))
+    (Po, beta_o), to = timed(lambda: ofit.eigsearch(KQo, m, KXo, n_s, d))
+    rows["es"] = {"lib_s": t, "oracle_s": to, "beta": beta, "beta_oracle": beta_o,
+                  "loss": loss(P, P), "loss_oracle": loss(Po, Po), "recall": recall(P, P)}
+    P_es, Po_es = P, Po
+    for name, init in (("fw", lv.LV_FW_INIT_ES), ("fw_from_zero", lv.LV_FW_INIT_ZERO),
+                       ("es_then_fw", lv.LV_FW_INIT_GIVEN)):
+        given = init == lv.LV_FW_INIT_GIVEN
+        (A, B, info), t = timed(lambda: lv.lv_fit_ood(
+            KQ, m, KX, n_s, d, init=init, A0=P_es if given else None,
+            B0=P_es if given else None))
+        (Ao, Bo, rep), to = timed(lambda: ofit.frank_wolfe(
+            KQo, m, KXo, n_s, d, init="zero" if init == lv.LV_FW_INIT_ZERO else "es",
+            A0=Po_es if given else None, B0=Po_es if given else None))
+        rows[name] = {"lib_s": t, "oracle_s": to, "iters": info["iters"],
+                      "iters_oracle": rep.iters, "converged": info["converged"],
+                      "loss": loss(A, B), "loss_oracle": loss(Ao, Bo), "recall": recall(A, B)}
+    for r in rows.values():
+        log("fit " + ", ".join(f"{k_}={v:.4g}" if isinstance(v, float) else f"{k_}={v}"
+                               for k_, v in r.items()))
+    return {"fit": wl.name, "D": D, "d": d, "database_sample": n_s, "learning_queries": m,
+            "test_queries": m_test, "k": k, "threads": int(os.environ.get("OMP_NUM_THREADS")
+                                                          or os.cpu_count()),
+            "timing": "host wall seconds (library: C++ float64, OpenMP; oracle: numpy/scipy)",
+            "second_moments": moments, "fits": rows,
+            "recall_full_dimension": 1.0}
 
 
 MFMA_PEAK_TFLOPS = 2500.0  # dense bf16 on MI355X
@@ -293,8 +413,11 @@ def main():
     if args.mfma:
         print(json.dumps(mfma_report(lv, torch)))
         return
+    if args.fit:
+        print(json.dumps(fit_report(lv, gen.WORKLOADS[args.workload or "ood-1m-512"])))
+        return
     dev = torch.device("cuda:0")
-    wl = gen.WORKLOADS[args.workload]
+    wl = gen.WORKLOADS[args.workload or "id-1m-768"]
     if args.n:
         wl = wl.scaled(N=args.n)
     k = wl.k
@@ -373,6 +496,21 @@ def main():
         from synth import graph as sgraph
 
         g["reachable"] = float(sgraph.reachable(adj, entry).mean())
+        st = g.get("stats") or {}
+        if st:
+            # construction-search bytes (per search: the node's record, its row,
+            # the pool row written; per expansion a row; per scoring a record)
+            cb = wl.d * wl.bits // 8 + 8
+            bL = args.build_L or wl.R
+            nb = (4 * wl.R * st["expansions"] + cb * st["scorings"]
+                  + st["searches"] * (cb + 4 * wl.R + 4 * (bL + wl.R)))
+            g["rates"] = {"nodes_per_s": wl.N / g["graph_s"],
+                          "search_alg_bytes": nb,
+                          "search_alg_GBs_over_whole_build": nb / g["graph_s"] / 1e9}
+        if not args.no_cpu_baseline:
+            g["oracle_sample"] = oracle_build_sample(wl, X, args.build_L or wl.R)
+            log(f"oracle construction: {g['oracle_sample']['nodes']} nodes in "
+                f"{g['oracle_sample']['s']:.1f}s")
     log(f"graph ready at {time.time() - t0:.1f}s (build {g['graph_s']:.1f}s)")
     index = lv.Index(rec, mud, sec, adjd, entry, wl.bits, wl.d, A_bf16=Pqb, sec_mu=smud,
                      residual=resid)
@@ -727,7 +865,9 @@ def main():
                         "graph_cached": g.get("graph_s") == 0.0,
                         "graph_reachable": g.get("reachable"),
                         "graph_build_work": g.get("stats"),
-                        "graph_build_repeatable": g.get("deterministic")},
+                        "graph_build_repeatable": g.get("deterministic"),
+                        "graph_build_rates": g.get("rates"),
+                        "graph_build_oracle_sample": g.get("oracle_sample")},
         "cpu_baseline": cpu,
         "traversal_compare": variant,
         "small_batches": small_batches,
