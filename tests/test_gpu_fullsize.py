@@ -173,7 +173,16 @@ def test_batched_step_equals_plain_and_oracle(lv, full, expand):
     cnt = torch.zeros((m, 2), dtype=torch.int32, device=DEV)
     lv.lv_search_projected(index, Qd, Qpd, k, L_OP, ids_o, sc_o, cnt, hash_slots=HASH_SLOTS,
                            expand=expand)
+    # the team launch (four wavefronts per query) on a small batch: identical
+    nt = 1024
+    ids_t = torch.empty((nt, k), dtype=torch.int32, device=DEV)
+    sc_t = torch.empty((nt, k), dtype=torch.float32, device=DEV)
+    cnt_t = torch.zeros((nt, 2), dtype=torch.int32, device=DEV)
+    lv.lv_search_projected(index, Qd[:nt], Qpd[:nt], k, L_OP, ids_t, sc_t, cnt_t,
+                           hash_slots=HASH_SLOTS, expand=expand, launch=lv.LV_LAUNCH_TEAM)
     torch.cuda.synchronize()
+    assert torch.equal(ids_t, ids_o[:nt]) and torch.equal(sc_t, sc_o[:nt])
+    assert torch.equal(cnt_t, cnt[:nt])
     rng = np.random.default_rng(22)
     sample = np.sort(rng.choice(m, N_SAMPLE, replace=False))
     got_i = ids_o.cpu().numpy().view(np.uint32).astype(np.int64)

@@ -188,6 +188,10 @@ def test_search_parity_lvq8_secondaries(lv, name, N):
         got_ids, got_sc, got_cnt = run_projected(lv, index, c, wl.k, L, hash_slots=8192)
         assert_parity(c, oidx, got_ids, got_sc, want_ids, want_sc)
         assert np.array_equal(got_cnt, want_cnt)
+        # team launch (LVQ-8 re-ranking in slices): identical
+        team = run_projected(lv, index, c, wl.k, L, hash_slots=8192, launch=lv.LV_LAUNCH_TEAM)
+        for g, o in zip(team, (got_ids, got_sc, got_cnt)):
+            assert np.array_equal(g, o)
     index.close()
 
 
@@ -351,6 +355,14 @@ def test_search_parity_residual_secondaries(lv):
                                          Qf[qi, :wl.d].astype(np.float64))
             assert np.allclose(np.sort(g), np.sort(w), rtol=0, atol=1e-12), qi
         assert np.all(np.abs(got_sc - want_sc) <= 1e-4 * np.maximum(np.abs(want_sc), 1.0))
+        # the team launch re-ranks the residual part in slices: same results
+        ids_t = torch.empty_like(ids)
+        sc_t = torch.empty_like(sc)
+        cnt_t = torch.zeros_like(cnt)
+        lv.lv_search_projected(index, Qfd, Qfd, k, L, ids_t, sc_t, cnt_t, hash_slots=8192,
+                               launch=lv.LV_LAUNCH_TEAM)
+        torch.cuda.synchronize()
+        assert torch.equal(ids_t, ids) and torch.equal(sc_t, sc) and torch.equal(cnt_t, cnt)
     index.close()
 
 
