@@ -83,6 +83,10 @@ def parse():
                     help="only time and compare the projection fits (host float64: ID, "
                          "eigenvector search, Frank-Wolfe; library and oracle) and their "
                          "brute-force recall in the reduced space, print one JSON line, exit")
+    ap.add_argument("--refine", type=int, default=0, metavar="STEPS",
+                    help="only run the differentiable refinement (Adam, STEPS steps from the "
+                         "LeanVec-ID fit) on the OOD refinement workload, compare it with the "
+                         "OOD fits on loss and reduced-space recall, print one JSON line, exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -201,23 +205,10 @@ def fit_report(lv, wl, n_s=100_000, m_test=1000, k=10):
                "max_rel_diff": float(max(np.abs(KX - KXo).max() / np.abs(KXo).max(),
                                          np.abs(KQ - KQo).max() / np.abs(KQo).max()))}
 
-    # exact top-k sets of <q, x> over the sample, and of <A q, B x> per fit
-    # (host float64; torch's top-k only for speed)
     import torch
 
-    def top_k(Qm, Xm):
-        Xt = torch.from_numpy(np.ascontiguousarray(Xm, np.float64))
-        out = []
-        for i in range(0, len(Qm), 100):
-            S = torch.from_numpy(np.ascontiguousarray(Qm[i:i + 100], np.float64)) @ Xt.T
-            out.append(torch.topk(S, k, dim=1).indices.numpy())
-        return np.concatenate(out)
-
-    truth = top_k(Qt, X)
-
     def recall(A, B):
-        got = top_k(Qt.astype(np.float64) @ A.T, X.astype(np.float64) @ B.T)
-        return float(np.mean([len(set(g) & set(t)) / k for g, t in zip(got, truth)]))
+        return reduced_recall(torch, Qt, X, {"f": (A, B)}, k)["f"]
 
     def loss(A, B):
         return lv.lv_ood_loss(KQ, m, KX, n_s, A, B)
@@ -253,6 +244,102 @@ def fit_report(lv, wl, n_s=100_000, m_test=1000, k=10):
             "timing": "host wall seconds (library: C++ float64, OpenMP; oracle: numpy/scipy)",
             "second_moments": moments, "fits": rows,
             "recall_full_dimension": 1.0}
+
+
+def reduced_recall(torch, Qt, X, fits, k=10):
+    """10-recall@10 of exact search with <A q, B x> over the rows of X, for
+    each (A, B) of fits, against the exact top k of <q, x> (host float64;
+    torch's top-k only for speed)."""
+    def top_k(Qm, Xm):
+        Xt = torch.from_numpy(np.ascontiguousarray(Xm, np.float64))
+        out = []
+        for i in range(0, len(Qm), 100):
+            S = torch.from_numpy(np.ascontiguousarray(Qm[i:i + 100], np.float64)) @ Xt.T
+            out.append(torch.topk(S, k, dim=1).indices.numpy())
+        return np.concatenate(out)
+
+    truth = top_k(Qt, X)
+    res = {}
+    for name, (A, B) in fits.items():
+        got = top_k(Qt.astype(np.float64) @ A.T, X.astype(np.float64) @ B.T)
+        res[name] = float(np.mean([len(set(g) & set(t)) / k for g, t in zip(got, truth)]))
+    return res
+
+
+def refine_report(lv, torch, wl, steps, n_s=100_000, m_test=1000, bq=1024, bx=4096):
+    """Differentiable refinement (the sampled-pair + trace loss, Adam with the
+    projection onto the spectral-norm ball after each step) from the
+    LeanVec-ID fit, against the OOD fits (Frank-Wolfe, eigenvector search) on
+    the loss of Problem leanvec_efficient and on reduced-space recall.
+    Database: the first n_s vectors of the workload's generator (a uniform
+    sample); learning queries: the workload's; blocks of bq learning queries
+    and bx database vectors drawn per step (seed 506)."""
+    from paper_2312_16335_amd.autograd import refine
+    from synth import gen
+
+    t0 = time.time()
+    mix = gen.mixture(wl)
+    X = gen.database(wl.scaled(N=n_s), mix)
+    Ql = gen.queries(wl, "learn", mix=mix)
+    Qt = gen.queries(wl, "test", m=m_test, mix=mix)
+    D, d, m = wl.D, wl.d, len(Ql)
+    log(f"refine data: {X.shape} database sample, {Ql.shape} learning queries "
+        f"in {time.time() - t0:.1f}s")
+    KX = np.zeros((D, D))
+    KQ = np.zeros((D, D))
+    lv.lv_second_moment(X, KX)
+    lv.lv_second_moment(Ql, KQ)
+    KQn, KXn = KQ / m, KX / n_s
+    fits = {}
+    P = lv.lv_fit_id(KX, d)
+    fits["id"] = (P, P)
+    t = time.time()
+    A, B, info = lv.lv_fit_ood(KQ, m, KX, n_s, d)
+    t_fw = time.time() - t
+    fits["fw"] = (A, B)
+    Pe, beta = lv.lv_fit_es(KQ, m, KX, n_s, d)
+    fits["es"] = (Pe, Pe)
+
+    dev = torch.device("cuda:0")
+    Qd = torch.from_numpy(Ql).to(dev)
+    Xd = torch.from_numpy(X).to(dev)
+    KQd = torch.from_numpy(KQn.astype(np.float32)).to(dev)
+    KXd = torch.from_numpy(KXn.astype(np.float32)).to(dev)
+    tc = float(np.trace(KQn @ KXn))
+    rng = np.random.default_rng(506)
+
+    def sample_block(step):
+        qi = torch.from_numpy(np.sort(rng.choice(m, bq, replace=False))).to(dev)
+        xi = torch.from_numpy(np.sort(rng.choice(n_s, bx, replace=False))).to(dev)
+        return Qd.index_select(0, qi).contiguous(), Xd.index_select(0, xi).contiguous()
+
+    trace = []
+
+    def cb(step, loss):
+        if step == 1 or step % 100 == 0:
+            trace.append((step, [float(v) for v in loss.cpu()]))
+
+    torch.cuda.synchronize()
+    t = time.time()
+    Ar, Br = refine(P, P, sample_block, steps, lr=1e-3, KQn=KQd, KXn=KXd, trace_const=tc,
+                    lam=1.0, callback=cb)
+    torch.cuda.synchronize()
+    t_ref = time.time() - t
+    fits["refined_from_id"] = (Ar, Br)
+    rec = reduced_recall(torch, Qt, X, fits)
+    rows = {name: {"loss": lv.lv_ood_loss(KQ, m, KX, n_s, A_, B_), "recall": rec[name]}
+            for name, (A_, B_) in fits.items()}
+    for name, r in rows.items():
+        log(f"refine {name}: loss {r['loss']:.4e}, recall {r['recall']:.4f}")
+    return {"refine": wl.name, "D": D, "d": d, "database_sample": n_s, "learning_queries": m,
+            "test_queries": m_test, "b_q": bq, "b_x": bx, "steps": steps, "lr": 1e-3,
+            "lam": 1.0, "refine_wall_s": t_ref, "refine_ms_per_step": 1e3 * t_ref / steps,
+            "per_step": "block gather, forward + backward kernels, two Adam kernels, host "
+                        "float64 spectral clip of A and B (device-host copies included)",
+            "fw_s": t_fw, "fw_iters": info["iters"], "es_beta": beta,
+            "loss_trace": [{"step": s_, "total": v[0], "pairs": v[1], "trace": v[2]}
+                           for s_, v in trace],
+            "fits": rows}
 
 
 MFMA_PEAK_TFLOPS = 2500.0  # dense bf16 on MI355X
@@ -415,6 +502,10 @@ def main():
         return
     if args.fit:
         print(json.dumps(fit_report(lv, gen.WORKLOADS[args.workload or "ood-1m-512"])))
+        return
+    if args.refine:
+        print(json.dumps(refine_report(lv, torch, gen.WORKLOADS[args.workload or "ood-1m-768"],
+                                       args.refine)))
         return
     dev = torch.device("cuda:0")
     wl = gen.WORKLOADS[args.workload or "id-1m-768"]
