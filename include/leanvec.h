@@ -176,8 +176,10 @@ int lv_project(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32
 
 /*
  * Record stride the search kernels support for d components at 4 or 8
- * bits: code bytes + 8, rounded up to 64, 128, 192, 256, 512, 768 or 1024
- * (0 if none fits).
+ * bits: code bytes + 8, rounded up to 64, 96, 128, 192, 256, 512, 768 or
+ * 1024 (0 if none fits).  A record is read by a group of lanes, one chunk
+ * each: 16 x 4, 8 x 12, 16 x 8, 16 x 12, 16 x 16, 64 x 8, 64 x 12 or 64 x 16
+ * bytes.
  */
 int32_t lv_record_stride(int32_t d, int32_t bits);
 

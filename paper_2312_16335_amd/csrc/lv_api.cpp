@@ -28,6 +28,7 @@ int validate_desc(const lv_index_desc *d, lv_index *ix) {
   int group = 0, vbytes = 0;
   switch (d->record_stride) {
     case 64: group = 16; vbytes = 4; break;
+    case 96: group = 8; vbytes = 12; break;
     case 128: group = 16; vbytes = 8; break;
     case 192: group = 16; vbytes = 12; break;
     case 256: group = 16; vbytes = 16; break;

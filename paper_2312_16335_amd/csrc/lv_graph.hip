@@ -517,6 +517,7 @@ struct Scratch {
 int stride_layout(int32_t stride, int *group, int *vbytes) {
   switch (stride) {
     case 64: *group = 16; *vbytes = 4; return 1;
+    case 96: *group = 8; *vbytes = 12; return 1;
     case 128: *group = 16; *vbytes = 8; return 1;
     case 192: *group = 16; *vbytes = 12; return 1;
     case 256: *group = 16; *vbytes = 16; return 1;

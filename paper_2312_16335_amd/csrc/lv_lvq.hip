@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void to_f16_kernel(const float *__restrict__ x
 extern "C" int32_t lv_record_stride(int32_t d, int32_t bits) {
   if (d < 1 || (bits != 4 && bits != 8) || (d * bits) % 32 != 0) return 0;
   const int32_t need = d * bits / 8 + 8;
-  static const int32_t strides[] = {64, 128, 192, 256, 512, 768, 1024};
+  static const int32_t strides[] = {64, 96, 128, 192, 256, 512, 768, 1024};
   for (int32_t s : strides)
     if (need <= s) return s;
   return 0;

@@ -155,6 +155,7 @@ __device__ __forceinline__ double lane_f64(double v, int j) {
 // each quad, rotate a row right by 4 and by 8 lanes.
 constexpr int kDppQuadXor1 = 0xB1;
 constexpr int kDppQuadXor2 = 0x4E;
+constexpr int kDppRowHalfMirror = 0x141;  // lane i of a half row from lane 7 - i
 constexpr int kDppRowRor4 = 0x124;
 constexpr int kDppRowRor8 = 0x128;
 constexpr int kDppRowBcast15 = 0x142;  // last lane of a row to the next row
@@ -177,16 +178,20 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Sum over each aligned group of W lanes (16: one row; 64: the wavefront),
-// with DPP moves only (no LDS round trip).  W = 16: every lane of a row
-// ends with the row's sum (possibly differing in the last bit between
-// lanes, so callers read one fixed lane).  W = 64: row sums are chained
+// Sum over each aligned group of W lanes (8: half a row; 16: one row; 64:
+// the wavefront), with DPP moves only (no LDS round trip).  W = 8, 16: every
+// lane of a group ends with the group's sum (possibly differing in the last
+// bit between lanes, so callers read one fixed lane).  W = 64: row sums are chained
 // into lane 63 and broadcast, so every lane returns the same value.
 template <int W>
 __device__ __forceinline__ double group_sum(double v) {
-  static_assert(W == 16 || W == 64, "groups of 16 or 64 lanes");
+  static_assert(W == 8 || W == 16 || W == 64, "groups of 8, 16 or 64 lanes");
   v += dpp_f64<kDppQuadXor1>(v);
   v += dpp_f64<kDppQuadXor2>(v);
+  if constexpr (W == 8) {
+    v += dpp_f64<kDppRowHalfMirror>(v);  // the other quad of the half row
+    return v;
+  }
   v += dpp_f64<kDppRowRor4>(v);
   v += dpp_f64<kDppRowRor8>(v);
   if constexpr (W == 64) {
@@ -1123,9 +1128,9 @@ int dispatch(int bits, int group, int vbytes, F &&f) {
   const int key = group * 100 + vbytes;
 #define LV_CASE(B, GG, VV) \
   if (bits == B && key == GG * 100 + VV) return f.template operator()<B, GG, VV>();
-  LV_CASE(8, 16, 4) LV_CASE(8, 16, 8) LV_CASE(8, 16, 12) LV_CASE(8, 16, 16)
+  LV_CASE(8, 16, 4) LV_CASE(8, 8, 12) LV_CASE(8, 16, 8) LV_CASE(8, 16, 12) LV_CASE(8, 16, 16)
   LV_CASE(8, 64, 8) LV_CASE(8, 64, 12) LV_CASE(8, 64, 16)
-  LV_CASE(4, 16, 4) LV_CASE(4, 16, 8) LV_CASE(4, 16, 12) LV_CASE(4, 16, 16)
+  LV_CASE(4, 16, 4) LV_CASE(4, 8, 12) LV_CASE(4, 16, 8) LV_CASE(4, 16, 12) LV_CASE(4, 16, 16)
   LV_CASE(4, 64, 8) LV_CASE(4, 64, 12) LV_CASE(4, 64, 16)
 #undef LV_CASE
   LV_FAIL(LV_EUNSUPPORTED, "no search kernel for %d-bit records of group %d x %d bytes", bits,

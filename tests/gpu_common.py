@@ -36,7 +36,7 @@ class Case:
 
 def stride_for(d: int, bits: int) -> int:
     need = d * bits // 8 + 8
-    for s in (64, 128, 192, 256, 512, 768, 1024):
+    for s in (64, 96, 128, 192, 256, 512, 768, 1024):
         if need <= s:
             return s
     raise ValueError("no stride")

@@ -47,7 +47,7 @@ def _create(desc):
 @pytest.mark.parametrize("kw,code", [
     (dict(N=0), lv.LV_EINVAL), (dict(d=12), lv.LV_EINVAL), (dict(bits=3), lv.LV_EINVAL),
     (dict(entry=100), lv.LV_EINVAL), (dict(record_stride=32), lv.LV_EINVAL),
-    (dict(record_stride=96), lv.LV_EUNSUPPORTED), (dict(records=None), lv.LV_EINVAL),
+    (dict(record_stride=160), lv.LV_EUNSUPPORTED), (dict(records=None), lv.LV_EINVAL),
     (dict(R=0), lv.LV_EINVAL), (dict(R=2000), lv.LV_EINVAL), (dict(sec_dtype=7), lv.LV_EINVAL),
     (dict(D=2000), lv.LV_EUNSUPPORTED), (dict(D=20), lv.LV_EINVAL)])
 def test_index_descriptor_validation(kw, code):
@@ -119,7 +119,8 @@ def test_encode_and_project_validation():
     assert lib.lv_project(FAKE, 10, 16, FAKE, 0, FAKE, None) == lv.LV_EINVAL
     assert lib.lv_project(FAKE, -1, 16, FAKE, 4, FAKE, None) == lv.LV_EINVAL
     assert lib.lv_to_f16(FAKE, -5, FAKE, None) == lv.LV_EINVAL
-    assert lv.lv_record_stride(160, 8) == 192 and lv.lv_record_stride(128, 4) == 128
+    assert lv.lv_record_stride(160, 8) == 192 and lv.lv_record_stride(128, 4) == 96
+    assert lv.lv_record_stride(112, 8) == 128 and lv.lv_record_stride(64, 8) == 96
     assert lv.lv_record_stride(32, 8) == 64 and lv.lv_record_stride(3000, 8) == 0
 
 
@@ -283,7 +284,7 @@ def test_graph_build_validation_without_a_device():
     assert call(d=12) == lv.LV_EINVAL
     assert call(bits=3) == lv.LV_EINVAL
     assert call(d=512, stride=1024) == lv.LV_EUNSUPPORTED  # 512 code bytes per record
-    assert call(stride=96) == lv.LV_EUNSUPPORTED
+    assert call(stride=160) == lv.LV_EUNSUPPORTED
     assert call(d=64, stride=64) == lv.LV_EINVAL  # no room for delta and lo
     assert call(R=65) == lv.LV_EUNSUPPORTED
     assert call(R=0) == lv.LV_EUNSUPPORTED

@@ -1,6 +1,6 @@
 """Graph construction on the GPU against the oracle: the adjacency must be
 identical (integer output), at sizes spanning many batches, for 8- and 4-bit
-records, the record layouts of the 16- and 64-lane groups, alpha != 1, the
+records, the record layouts of the 8-, 16- and 64-lane groups, alpha != 1, the
 largest R and record width, partial builds, and points on a line (the path
 graph).  Inputs come from the oracle's encoder; nothing the oracle reads
 comes from the device."""
@@ -43,6 +43,7 @@ CASES = [
     (600, 160, 8, 24, 40, 32, (1.0, 1.2)),
     (800, 64, 4, 16, 24, 50, (1.0,)),
     (500, 256, 8, 64, 80, 40, (1.0, 1.0)),
+    (700, 128, 4, 32, 48, 40, (1.0, 1.1)),   # 72-byte records: the 8-lane x 12-byte layout
 ]
 
 

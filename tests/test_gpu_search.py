@@ -292,8 +292,10 @@ def _oracle_expand(oidx, c, k, L, expand):
 
 @pytest.mark.parametrize("expand", [1, 3, 8])
 @pytest.mark.parametrize("name,N,d", [("id-1m-768", 6000, 0), ("ood-1m-512", 6000, 0),
-                                      ("id-1m-768", 3000, 256)],
-                         ids=["lvq8-g16", "lvq4-g16", "lvq8-g64"])
+                                      ("id-1m-768", 3000, 256), ("id-1m-768", 3000, 112),
+                                      ("id-1m-768", 3000, 64)],
+                         ids=["lvq8-g16x12", "lvq4-g8x12", "lvq8-g64x8", "lvq8-g16x8",
+                              "lvq8-g8x12"])
 def test_team_launch_parity(lv, name, N, d, expand):
     """Four wavefronts per query (team launch): the oracle's traversal with the
     same number of expansions per iteration (one: the paper's), and
