@@ -87,6 +87,11 @@ def parse():
                     help="only run the differentiable refinement (Adam, STEPS steps from the "
                          "LeanVec-ID fit) on the OOD refinement workload, compare it with the "
                          "OOD fits on loss and reduced-space recall, print one JSON line, exit")
+    ap.add_argument("--multi", action="store_true",
+                    help="only run the multi-index workload at full size (64 sub-indexes of "
+                         "log-uniform sizes in [1e4, 5e5], 1,024 requests with batch sizes "
+                         "in [1, 4096] and k in {1, 10, 100}, autotuned windows), print one "
+                         "JSON line, exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -244,6 +249,195 @@ def fit_report(lv, wl, n_s=100_000, m_test=1000, k=10):
             "timing": "host wall seconds (library: C++ float64, OpenMP; oracle: numpy/scipy)",
             "second_moments": moments, "fits": rows,
             "recall_full_dimension": 1.0}
+
+
+def multi_report(lv, torch, args, n_sub=64, pool=4096, learn=4096, n_req=1024,
+                 capacity=65536, target=0.90, L_max=512, in_flight=3):
+    """The multi-index workload at full size.  Per sub-index s (sizes
+    log-uniform in [1e4, 5e5], the id-1m-768 distribution with data seed
+    4000 + s): LeanVec-ID fit on up to 100,000 vectors (host float64),
+    projection and LVQ-8 encoding on the GPU, float16 secondaries, graph by
+    lv_graph_build (R = 64, window R, two passes at alpha = 1), a pool of
+    4,096 test and 4,096 learning queries with exact top-100 ids.  Windows L
+    per (sub-index, k) from lv_autotune_window on the learning queries; the
+    request stream (seed 401) is packed greedily into steps of at most
+    65,536 queries; the steps run back to back, three in flight, queries
+    resident.  Reported: whole-stream QPS (batched), the same requests as
+    one plain search per request, and k-recall@k against the exact ids."""
+    from dataclasses import replace
+
+    from synth import gen
+    from synth import graph as sgraph
+
+    dev = torch.device("cuda:0")
+    base = gen.WORKLOADS["id-1m-768"]
+    sizes = gen.subindex_sizes(n_sub)
+    subs, keep = [], []
+    t0 = time.time()
+    build_s = 0.0
+    for s_ in range(n_sub):
+        wl = replace(base, name=f"multi{s_}", N=int(sizes[s_]), m_test=pool, m_learn=learn,
+                     seed_data=4000 + s_, seed_test=4100 + s_, seed_learn=4200 + s_)
+        mix = gen.mixture(wl)
+        X = gen.database(wl, mix)
+        Q = gen.queries(wl, "test", mix=mix)
+        Ql = gen.queries(wl, "learn", mix=mix)
+        ns = min(wl.N, 100_000)
+        K = np.zeros((wl.D, wl.D))
+        ssum = np.zeros(wl.D)
+        lv.lv_second_moment(X[:ns], K, ssum)
+        P = lv.lv_fit_id(K, wl.d)
+        mu = lv.lv_mean_reduced(P, ssum, ns)
+        Xd = torch.from_numpy(X).to(dev)
+        Pb = torch.from_numpy(lv.lv_to_bf16(P).view(np.int16)).to(dev)
+        mud = torch.from_numpy(mu).to(dev)
+        Y = torch.empty((wl.N, wl.d), dtype=torch.float32, device=dev)
+        lv.lv_project(Xd, Pb, Y)
+        rec = torch.empty((wl.N, lv.lv_record_stride(wl.d, wl.bits)), dtype=torch.uint8,
+                          device=dev)
+        lv.lv_lvq_encode(Y, mud, wl.bits, rec)
+        sec = torch.empty((wl.N, wl.D), dtype=torch.float16, device=dev)
+        lv.lv_to_f16(Xd, sec)
+        del Y
+        entry = sgraph.medoid(X)
+        order = np.random.default_rng(wl.seed_data + 17).permutation(wl.N).astype(np.uint32)
+        adjd = torch.empty((wl.N, wl.R), dtype=torch.int32, device=dev)
+        bp = lv.build_params(wl.R, wl.R, wl.graph_alphas, max(1, wl.N // 50))
+        torch.cuda.synchronize()
+        tb = time.time()
+        lv.lv_graph_build(rec, wl.N, wl.d, wl.bits, order, entry, bp, adjd)
+        torch.cuda.synchronize()
+        build_s += time.time() - tb
+        truth = ground_truth_gpu(torch, Xd, Q, 100)
+        truth_l = ground_truth_gpu(torch, Xd, Ql, 100).astype(np.uint32)
+        del Xd
+        ix = lv.Index(rec, mud, sec, adjd, entry, wl.bits, wl.d, A_bf16=Pb)
+        keep.append((rec, mud, sec, adjd, Pb))
+        subs.append(dict(N=wl.N, Q=Q, Ql=Ql, truth=truth, truth_l=truth_l, ix=ix))
+    n_total = int(sum(d_["N"] for d_ in subs))
+    log(f"multi: {n_sub} sub-indexes, {n_total} vectors ready in {time.time() - t0:.1f}s "
+        f"(graph builds {build_s:.1f}s)")
+
+    multi = lv.Multi([d_["ix"] for d_ in subs])
+    sub, cnt, kk, off = gen.request_stream(n_req, n_sub, pool)
+    t1 = time.time()
+    Lsk = {}
+    for s_, k_ in sorted(set(zip(sub.tolist(), kk.tolist()))):
+        Qld = torch.from_numpy(subs[s_]["Ql"]).to(dev)
+        Lsk[(s_, k_)], _ = lv.lv_autotune_window(multi, s_, Qld, subs[s_]["truth_l"], k_,
+                                                 target, L_max)
+    tune_s = time.time() - t1
+    log(f"multi: {len(Lsk)} windows autotuned in {tune_s:.1f}s "
+        f"(L from {min(Lsk.values())} to {max(Lsk.values())})")
+
+    steps, curr, nq = [], [], 0
+    for i in range(n_req):
+        if curr and nq + cnt[i] > capacity:
+            steps.append(curr)
+            curr, nq = [], 0
+        curr.append(i)
+        nq += int(cnt[i])
+    steps.append(curr)
+    staged = []
+    for st in steps:
+        reqs, Qs = [], []
+        for i in st:
+            s_, k_ = int(sub[i]), int(kk[i])
+            rows = (int(off[i]) + np.arange(int(cnt[i]))) % pool
+            Qs.append(subs[s_]["Q"][rows])
+            reqs.append((s_, k_, Lsk[(s_, k_)], int(cnt[i])))
+        nout = sum(k_ * c_ for _, k_, _, c_ in reqs)
+        staged.append(dict(reqs=reqs, rows=[(int(off[i]) + np.arange(int(cnt[i]))) % pool
+                                            for i in st],
+                           Q=torch.from_numpy(np.concatenate(Qs)).to(dev),
+                           ids=torch.empty((nout,), dtype=torch.int32, device=dev),
+                           sc=torch.empty((nout,), dtype=torch.float32, device=dev)))
+    m_total = int(cnt.sum())
+    max_req = max(len(st) for st in steps)
+    batch = lv.Batch(multi, max_requests=max_req, max_queries=capacity,
+                     max_L=max(Lsk.values()), expand=args.expand)
+    stream = torch.cuda.current_stream()
+    strs = [stream] + [torch.cuda.Stream() for _ in range(in_flight - 1)]
+
+    def run_stream():
+        for s_ in strs[1:]:
+            s_.wait_stream(stream)
+        for j, stg in enumerate(staged):
+            batch.step(stg["reqs"], stg["Q"], stg["ids"], stg["sc"], stream=strs[j % in_flight])
+        for s_ in strs[1:]:
+            stream.wait_stream(s_)
+
+    run_stream()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record(stream)
+    for _ in range(reps):
+        run_stream()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batched_ms = e0.elapsed_time(e1) / reps
+
+    # recall (k-recall@k per request, pooled) and the plain search of the same requests
+    hits = total = 0
+    plain_ids = []
+    for stg in staged:
+        o0 = 0
+        for (s_, k_, L_, c_), rows in zip(stg["reqs"], stg["rows"]):
+            got = stg["ids"][o0:o0 + c_ * k_].view(c_, k_).cpu().numpy().view(np.uint32)
+            tr = subs[s_]["truth"][rows, :k_]
+            hits += sum(len(set(a) & set(b)) for a, b in zip(got.tolist(), tr.tolist()))
+            total += c_ * k_
+            o0 += c_ * k_
+    ws = torch.empty(lv.lv_search_workspace_size(subs[0]["ix"], capacity), dtype=torch.uint8,
+                     device=dev)
+    pouts = [(torch.empty((c_, k_), dtype=torch.int32, device=dev),
+              torch.empty((c_, k_), dtype=torch.float32, device=dev))
+             for stg in staged for (_, k_, _, c_) in stg["reqs"]]
+
+    def run_plain():
+        j = 0
+        for stg in staged:
+            q0 = 0
+            for (s_, k_, L_, c_) in stg["reqs"]:
+                lv.lv_search(subs[s_]["ix"], stg["Q"][q0:q0 + c_], k_, L_, pouts[j][0],
+                             pouts[j][1], None, ws=ws, expand=args.expand)
+                q0 += c_
+                j += 1
+
+    run_plain()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    run_plain()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    j = 0
+    same = True
+    for stg in staged:
+        o0 = 0
+        for (_, k_, _, c_) in stg["reqs"]:
+            same &= bool(torch.equal(stg["ids"][o0:o0 + c_ * k_].view(c_, k_), pouts[j][0]))
+            o0 += c_ * k_
+            j += 1
+    batch.close()
+    multi.close()
+    for d_ in subs:
+        d_["ix"].close()
+    qps = m_total / (batched_ms / 1e3)
+    log(f"multi: {len(steps)} steps, {m_total} queries: batched {qps:.0f} QPS, plain "
+        f"{m_total / (plain_ms / 1e3):.0f} QPS, recall {hits / total:.4f}")
+    return {"multi": "id-1m-768 distribution, 64 sub-indexes", "sub_indexes": n_sub,
+            "vectors": n_total, "D": base.D, "d": base.d, "requests": n_req,
+            "steps": len(steps), "queries": m_total, "capacity": capacity,
+            "expand": max(1, args.expand), "in_flight": in_flight,
+            "windows": {"min": min(Lsk.values()), "max": max(Lsk.values()),
+                        "median": float(np.median(list(Lsk.values()))), "count": len(Lsk)},
+            "batched": {"qps": qps, "ms_per_stream": batched_ms, "reps": reps},
+            "plain": {"qps": m_total / (plain_ms / 1e3), "ms_per_stream": plain_ms},
+            "batched_over_plain": plain_ms / batched_ms,
+            "batched_equals_plain": same, "recall": hits / total, "target": target,
+            "prepare_s": time.time() - t0, "graph_build_s": build_s, "autotune_s": tune_s}
 
 
 def reduced_recall(torch, Qt, X, fits, k=10):
@@ -418,7 +612,7 @@ def ground_truth_gpu(torch, Xd, Q, k):
     """Exact top-k ids by <q, x> (float32 candidates, float64 re-scoring)."""
     dev = Xd.device
     m = len(Q)
-    cand_k = 64
+    cand_k = max(64, k + 28)
     Qd = torch.from_numpy(Q).to(dev)
     best_s = torch.full((m, 0), -math.inf, device=dev)
     best_i = torch.zeros((m, 0), dtype=torch.int64, device=dev)
@@ -502,6 +696,9 @@ def main():
         return
     if args.fit:
         print(json.dumps(fit_report(lv, gen.WORKLOADS[args.workload or "ood-1m-512"])))
+        return
+    if args.multi:
+        print(json.dumps(multi_report(lv, torch, args)))
         return
     if args.refine:
         print(json.dumps(refine_report(lv, torch, gen.WORKLOADS[args.workload or "ood-1m-768"],
