@@ -114,17 +114,36 @@ __global__ __launch_bounds__(256) void project_kernel(const float *__restrict__ 
   project_rows<NT>(V, row0, rows, D, M, d, col0, out, d, threadIdx.x & 63);
 }
 
-// Batched form: 32-row tiles over the requests of a step; each tile uses the
-// query projection of its request's sub-index.  Tiles beyond the step's
-// count exit (the grid is sized for the capacity).  Output columns come in
-// blocks of up to 256 (grid y).
-template <int NT>
-__global__ __launch_bounds__(256) void project_grouped_kernel(const StepHeader *__restrict__ hdr,
-                                                              const IndexView *__restrict__ subs,
-                                                              int32_t D, int32_t d) {
-  const int32_t col0 = (int32_t)blockIdx.y * 256;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= hdr->ntiles) return;
+// Few rows (query batches): one workgroup per 32-row tile and one wavefront
+// per 32-column tile (kColWaves per workgroup, grid y for more), so that a
+// batch of a few thousand rows still reaches every CU; the wavefronts of a
+// workgroup share the tile's rows through the caches.  Every output column
+// gets the same sequence of MFMAs as in project_kernel, so the two kernels
+// give bit-identical results.
+constexpr int kColWaves = 8;
+// Up to this many rows the column-tiled kernel is used (the row-tiled one
+// streams a large matrix once; both give the same bits).
+constexpr int64_t kFewRows = 65536;
+
+__global__ __launch_bounds__(64 * kColWaves) void project_cols_kernel(
+    const float *__restrict__ V, int64_t rows, int32_t D, const uint16_t *__restrict__ M,
+    int32_t d, float *__restrict__ out) {
+  const int64_t row0 = (int64_t)blockIdx.x * 32;
+  const int32_t col0 = ((int32_t)blockIdx.y * kColWaves + (int32_t)(threadIdx.x >> 6)) * 32;
+  if (row0 >= rows || col0 >= d) return;
+  project_rows<1>(V, row0, rows, D, M, d, col0, out, d, threadIdx.x & 63);
+}
+
+// Batched form, laid out as project_cols_kernel: one workgroup per 32-row
+// tile of the step's requests (each tile uses the query projection of its
+// request's sub-index), one wavefront per 32-column tile.  Tiles beyond the
+// step's count exit (the grid is sized for the capacity).
+__global__ __launch_bounds__(64 * kColWaves) void project_grouped_kernel(
+    const StepHeader *__restrict__ hdr, const IndexView *__restrict__ subs, int32_t D,
+    int32_t d) {
+  const int32_t col0 = ((int32_t)blockIdx.y * kColWaves + (int32_t)(threadIdx.x >> 6)) * 32;
+  const int t = blockIdx.x;
+  if (t >= hdr->ntiles || col0 >= d) return;
   const Request *req = reinterpret_cast<const Request *>(hdr + 1);
   int lo = 0, hi = hdr->nreq - 1;  // last request with tile0 <= t
   while (lo < hi) {
@@ -136,8 +155,15 @@ __global__ __launch_bounds__(256) void project_grouped_kernel(const StepHeader *
   }
   const Request r = req[lo];
   const int64_t row0 = r.q_begin + (int64_t)(t - r.tile0) * 32;
-  project_rows<NT>(hdr->Q, row0, r.q_end, D, subs[r.sub].A, d, col0, hdr->Qp, hdr->qp_stride,
-                   threadIdx.x & 63);
+  project_rows<1>(hdr->Q, row0, r.q_end, D, subs[r.sub].A, d, col0, hdr->Qp, hdr->qp_stride,
+                  threadIdx.x & 63);
+}
+
+// Wavefronts per workgroup and workgroups along y for d output columns.
+void col_layout(int32_t d, unsigned *waves, unsigned *yblocks) {
+  const unsigned tiles = (unsigned)((d + 31) / 32);
+  *waves = tiles < (unsigned)kColWaves ? tiles : (unsigned)kColWaves;
+  *yblocks = (tiles + *waves - 1) / *waves;
 }
 
 template <int NT>
@@ -153,18 +179,10 @@ void launch_nt(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32
 int launch_project_grouped(const StepHeader *hdr, const IndexView *subs, int max_tiles, int d,
                            int D, hipStream_t stream) {
   if (d < 1 || d > 1024) LV_FAIL(LV_EUNSUPPORTED, "batched projection needs d <= 1024");
-  const unsigned blocks = (unsigned)((max_tiles + 3) / 4);
-  const unsigned cblocks = (unsigned)((d + 255) / 256);
-  const int nt = d > 256 ? 8 : (d + 31) / 32;
-#define LV_GRP(NT)                                                                             \
-  case NT:                                                                                     \
-    hipLaunchKernelGGL(project_grouped_kernel<NT>, dim3(blocks, cblocks), dim3(256), 0, stream, \
-                       hdr, subs, D, d);                                                       \
-    break;
-  switch (nt) {
-    LV_GRP(1) LV_GRP(2) LV_GRP(3) LV_GRP(4) LV_GRP(5) LV_GRP(6) LV_GRP(7) LV_GRP(8)
-  }
-#undef LV_GRP
+  unsigned waves = 0, yblocks = 0;
+  col_layout(d, &waves, &yblocks);
+  hipLaunchKernelGGL(project_grouped_kernel, dim3((unsigned)max_tiles, yblocks), dim3(64 * waves),
+                     0, stream, hdr, subs, D, d);
   LV_CHECK_LAUNCH();
   return LV_OK;
 }
@@ -173,6 +191,14 @@ int launch_project(const float *V, int64_t rows, int32_t D, const uint16_t *M, i
                    float *out, hipStream_t stream) {
   if (rows == 0) return LV_OK;
   if ((rows + 127) / 128 > 0x7FFFFFFF) LV_FAIL(LV_EINVAL, "too many rows");
+  if (rows <= kFewRows) {  // query batches: a wavefront per 32 x 32 output tile
+    unsigned waves = 0, yblocks = 0;
+    col_layout(d, &waves, &yblocks);
+    hipLaunchKernelGGL(project_cols_kernel, dim3((unsigned)((rows + 31) / 32), yblocks),
+                       dim3(64 * waves), 0, stream, V, rows, D, M, d, out);
+    LV_CHECK_LAUNCH();
+    return LV_OK;
+  }
   for (int32_t col0 = 0; col0 < d; col0 += 256) {
     const int nt = ((d - col0) + 31) / 32;
     switch (nt > 8 ? 8 : nt) {

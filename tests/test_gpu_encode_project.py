@@ -77,6 +77,32 @@ def test_projection_exact_on_bf16_integers(lv, rows, D, d):
     assert np.array_equal(out.cpu().numpy().astype(np.float64), want)
 
 
+@pytest.mark.parametrize("D,d", [(256, 160), (128, 520), (64, 1)])
+def test_projection_row_and_column_kernels_agree(lv, D, d):
+    """More than 65,536 rows take the row-tiled kernel, fewer the
+    column-tiled one: the same MFMA sequence per output, so the same bits;
+    integer inputs on the large side check it exactly."""
+    rng = np.random.default_rng(D + d)
+    rows = 70_001
+    V = rng.standard_normal((rows, D)).astype(np.float32)
+    M = rng.standard_normal((d, D))
+    Mb = torch.from_numpy(lv.lv_to_bf16(M).view(np.int16)).to(DEV)
+    Vd = torch.from_numpy(V).to(DEV)
+    big = torch.full((rows, d), np.nan, dtype=torch.float32, device=DEV)
+    lv.lv_project(Vd, Mb, big)
+    for lo, n in ((0, 4099), (65_000, 5_001)):
+        part = torch.full((n, d), np.nan, dtype=torch.float32, device=DEV)
+        lv.lv_project(Vd[lo:lo + n], Mb, part)
+        torch.cuda.synchronize()
+        assert torch.equal(part, big[lo:lo + n])
+    Vi = rng.integers(-8, 9, size=(rows, D)).astype(np.float32)
+    Mi = rng.integers(-4, 5, size=(d, D)).astype(np.float64)
+    Mib = torch.from_numpy(lv.lv_to_bf16(Mi).view(np.int16)).to(DEV)
+    lv.lv_project(torch.from_numpy(Vi).to(DEV), Mib, big)
+    torch.cuda.synchronize()
+    assert np.array_equal(big.cpu().numpy().astype(np.float64), Vi.astype(np.float64) @ Mi.T)
+
+
 def test_projection_error_against_float64(lv):
     rng = np.random.default_rng(9)
     V = rng.standard_normal((4096, 768)).astype(np.float32)
