@@ -553,6 +553,20 @@ int lv_adam_step(float *p, const float *g, float *m, float *v, int64_t n, float 
  * stiefel_convex_hull) by clipping its singular values at 1, in place. */
 int lv_clip_spectral(double *M, int32_t d, int32_t D);
 
+/*
+ * The same projection for a device float32 M [d][D] (1 <= d <= 1024), in
+ * place on `stream`: the Gram matrix M M^T is formed on the device in
+ * float64, its eigendecomposition and the d x d factor are computed on the
+ * host in float64 (as lv_clip_spectral does), and the factor is applied on
+ * the device in float64 with the result rounded to float32.  ws: device
+ * buffer of lv_clip_spectral_device_workspace_size bytes, 8-byte aligned,
+ * caller-owned.  Synchronises with `stream` (the Gram matrix is read back).
+ * Errors: LV_EINVAL for NULL pointers, bad sizes or a small workspace.
+ */
+int lv_clip_spectral_device(float *M, int32_t d, int32_t D, void *ws, size_t ws_bytes,
+                            void *stream);
+size_t lv_clip_spectral_device_workspace_size(int32_t d, int32_t D);
+
 #ifdef __cplusplus
 }
 #endif

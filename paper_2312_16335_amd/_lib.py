@@ -122,6 +122,8 @@ _SIGS = {
     "lv_adam_step": (_c_i32, [_vp, _vp, _vp, _vp, _c_i64, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, ctypes.c_float, _c_i32, _vp]),
     "lv_clip_spectral": (_c_i32, [_vp, _c_i32, _c_i32]),
+    "lv_clip_spectral_device": (_c_i32, [_vp, _c_i32, _c_i32, _vp, ctypes.c_size_t, _vp]),
+    "lv_clip_spectral_device_workspace_size": (ctypes.c_size_t, [_c_i32, _c_i32]),
     "lv_graph_build": (_c_i32, [_vp, _c_i32, _c_i64, _c_i32, _c_i32, _vp, _c_u32,
                                 ctypes.POINTER(BuildParams), _vp, _vp]),
     "lv_autotune_knobs": (_c_i32, [_vp, ctypes.POINTER(BatchCaps), ctypes.POINTER(Request),
@@ -579,3 +581,16 @@ def lv_clip_spectral(M: np.ndarray) -> np.ndarray:
     M = np.array(M, dtype=np.float64, order="C")
     _check(load().lv_clip_spectral(M.ctypes.data, M.shape[0], M.shape[1]))
     return M
+
+
+def lv_clip_spectral_device_workspace_size(d: int, D: int) -> int:
+    return load().lv_clip_spectral_device_workspace_size(d, D)
+
+
+def lv_clip_spectral_device(M, ws, stream=None) -> None:
+    """In place on a device float32 [d][D] tensor; ws: device workspace tensor."""
+    import torch
+
+    d, D = M.shape
+    _check(load().lv_clip_spectral_device(_dev(M, torch.float32), d, D, _dev(ws),
+                                          ws.numel() * ws.element_size(), _stream(stream)))

@@ -41,7 +41,8 @@ class ProjLoss(torch.autograd.Function):
 def refine(A0: np.ndarray, B0: np.ndarray, sample_block, steps: int, lr: float = 1e-3,
            KQn=None, KXn=None, trace_const: float = 0.0, lam: float = 1.0, device="cuda",
            callback=None):
-    """Adam on (A, B) with the projection onto C after each step (host float64)."""
+    """Adam on (A, B) with the projection onto C after each step (device Gram matrix and
+    factor application, host float64 eigendecomposition)."""
     A = torch.tensor(A0, dtype=torch.float32, device=device)
     B = torch.tensor(B0, dtype=torch.float32, device=device)
     mA, vA = torch.zeros_like(A), torch.zeros_like(A)
@@ -50,6 +51,8 @@ def refine(A0: np.ndarray, B0: np.ndarray, sample_block, steps: int, lr: float =
     ws = None
     loss = torch.empty(3, dtype=torch.float32, device=device)
     dA, dB = torch.empty_like(A), torch.empty_like(B)
+    cws = torch.empty(lv.lv_clip_spectral_device_workspace_size(d, D), dtype=torch.uint8,
+                      device=device)
     for t in range(1, steps + 1):
         Qb, Xb = sample_block(t)
         if ws is None:
@@ -59,10 +62,8 @@ def refine(A0: np.ndarray, B0: np.ndarray, sample_block, steps: int, lr: float =
         lv.lv_projloss_bwd(A, B, Qb, Xb, dA, dB, ws, KQn, KXn, lam, 1.0)
         lv.lv_adam_step(A, dA, mA, vA, lr, t)
         lv.lv_adam_step(B, dB, mB, vB, lr, t)
-        An = lv.lv_clip_spectral(A.double().cpu().numpy())
-        Bn = lv.lv_clip_spectral(B.double().cpu().numpy())
-        A.copy_(torch.from_numpy(An).float())
-        B.copy_(torch.from_numpy(Bn).float())
+        lv.lv_clip_spectral_device(A, cws)
+        lv.lv_clip_spectral_device(B, cws)
         if callback is not None:
             callback(t, loss)
     return A.double().cpu().numpy(), B.double().cpu().numpy()

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "lv_error.h"
+#include "lv_fit.h"
 
 namespace lv {
 namespace {
@@ -503,14 +504,16 @@ extern "C" int lv_mean_reduced(const double *M, int32_t d, int32_t D, const doub
 
 // Clip singular values at 1: M <- W diag(min(1, 1/sigma)) W^T M with
 // M M^T = W diag(sigma^2) W^T (rows of W from the symmetric eigensolver).
-extern "C" int lv_clip_spectral(double *M, int32_t d, int32_t D) {
-  lv::clear_error();
-  if (!M) LV_FAIL(LV_EINVAL, "NULL matrix");
-  if (d < 1 || D < 1) LV_FAIL(LV_EINVAL, "bad sizes");
-  Mat MM((size_t)d * d), W((size_t)d * d), T((size_t)d * d), out((size_t)d * D);
+namespace lv {
+
+// With M M^T = W^T diag(lam) W (rows of W the eigenvectors), the projection
+// of M onto the spectral-norm ball is T M, T = W^T diag(min(1, lam^-1/2)) W:
+// singular values above 1 become 1, the singular vectors stay.  Returns
+// false (T untouched) when no singular value exceeds 1.
+bool clip_factor(int32_t d, const double *MMt, double *T) {
+  Mat W((size_t)d * d);
   std::vector<double> lam(d);
-  lv::gemm(d, d, D, M, false, M, true, MM.data());
-  lv::sym_eig(d, MM.data(), lam.data(), W.data());
+  sym_eig(d, MMt, lam.data(), W.data());
   std::vector<double> f(d);
   bool any = false;
   for (int i = 0; i < d; ++i) {
@@ -518,13 +521,25 @@ extern "C" int lv_clip_spectral(double *M, int32_t d, int32_t D) {
     f[i] = s > 1.0 ? 1.0 / s : 1.0;
     any = any || s > 1.0;
   }
-  if (!any) return LV_OK;
+  if (!any) return false;
   for (int a = 0; a < d; ++a)
     for (int b = 0; b < d; ++b) {
       double s = 0.0;
       for (int i = 0; i < d; ++i) s += W[(size_t)i * d + a] * f[i] * W[(size_t)i * d + b];
       T[(size_t)a * d + b] = s;
     }
+  return true;
+}
+
+}  // namespace lv
+
+extern "C" int lv_clip_spectral(double *M, int32_t d, int32_t D) {
+  lv::clear_error();
+  if (!M) LV_FAIL(LV_EINVAL, "NULL matrix");
+  if (d < 1 || D < 1) LV_FAIL(LV_EINVAL, "bad sizes");
+  Mat MM((size_t)d * d), T((size_t)d * d), out((size_t)d * D);
+  lv::gemm(d, d, D, M, false, M, true, MM.data());
+  if (!lv::clip_factor(d, MM.data(), T.data())) return LV_OK;
   lv::gemm(d, D, d, T.data(), false, M, false, out.data());
   std::memcpy(M, out.data(), sizeof(double) * out.size());
   return LV_OK;

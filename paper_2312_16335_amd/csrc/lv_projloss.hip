@@ -1,4 +1,5 @@
-// Differentiable projection loss on the matrix cores, and Adam.
+// Differentiable projection loss on the matrix cores, Adam, and the
+// projection of A and B onto the spectral-norm ball after a step.
 //
 // For a block of b_q queries Qb and b_x database vectors Xb (rows), with
 // P = b_q * b_x pairs, the refinement loss built from the LeanVec-OOD
@@ -18,9 +19,11 @@
 // accumulation); Rm is formed as Qb Xb^T followed by a second product that
 // subtracts G H^T into the same buffer.  Sums of squares and inner products
 // use a fixed-order two-pass float64 reduction, so results are deterministic.
-#include "lv_common.h"
 #include <algorithm>
+#include <vector>
 
+#include "lv_common.h"
+#include "lv_fit.h"
 #include "lv_gemm.h"
 
 namespace lv {
@@ -247,5 +250,75 @@ extern "C" int lv_adam_step(float *p, const float *g, float *m, float *v, int64_
   hipLaunchKernelGGL(lv::adam_kernel, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream),
                      p, g, m, v, n, lr, beta1, beta2, eps, c1, c2);
   LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+namespace lv {
+namespace {
+
+// G = M M^T for M [d][D] float32: one thread per entry, float64 sums in
+// order of k (the products of float32 values are exact in float64).
+__global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ M, int32_t d,
+                                                   int32_t D, double *__restrict__ G) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)d * d) return;
+  const int i = (int)(e / d), j = (int)(e % d);
+  const float *a = M + (int64_t)i * D;
+  const float *b = M + (int64_t)j * D;
+  double s = 0.0;
+  for (int k = 0; k < D; ++k) s = fma((double)a[k], (double)b[k], s);
+  G[e] = s;
+}
+
+// out = T M (T [d][d] float64, M [d][D] float32), float64 sums, rounded to
+// float32.
+__global__ __launch_bounds__(256) void apply_clip_kernel(const double *__restrict__ T,
+                                                         const float *__restrict__ M, int32_t d,
+                                                         int32_t D, float *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)d * D) return;
+  const int i = (int)(e / D), c = (int)(e % D);
+  double s = 0.0;
+  for (int j = 0; j < d; ++j) s = fma(T[(int64_t)i * d + j], (double)M[(int64_t)j * D + c], s);
+  out[e] = (float)s;
+}
+
+}  // namespace
+}  // namespace lv
+
+extern "C" size_t lv_clip_spectral_device_workspace_size(int32_t d, int32_t D) {
+  if (d < 1 || D < 1) return 0;
+  return (size_t)2 * d * d * sizeof(double) + (size_t)d * D * sizeof(float);
+}
+
+extern "C" int lv_clip_spectral_device(float *M, int32_t d, int32_t D, void *ws, size_t ws_bytes,
+                                       void *stream) {
+  lv::clear_error();
+  if (!M) LV_FAIL(LV_EINVAL, "NULL matrix");
+  if (d < 1 || D < 1 || d > 1024) LV_FAIL(LV_EINVAL, "bad sizes (1 <= d <= 1024, D >= 1)");
+  if (!ws || ws_bytes < lv_clip_spectral_device_workspace_size(d, D))
+    LV_FAIL(LV_EINVAL, "workspace too small (need %zu bytes)",
+            lv_clip_spectral_device_workspace_size(d, D));
+  if (reinterpret_cast<uintptr_t>(ws) & 7u) LV_FAIL(LV_EINVAL, "workspace not 8-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *G = static_cast<double *>(ws);
+  double *T = G + (size_t)d * d;
+  float *out = reinterpret_cast<float *>(T + (size_t)d * d);
+  const size_t dd = (size_t)d * d;
+  hipLaunchKernelGGL(lv::gram_kernel, dim3((unsigned)((dd + 255) / 256)), dim3(256), 0, s, M, d,
+                     D, G);
+  LV_CHECK_LAUNCH();
+  std::vector<double> g(dd), t(dd);
+  LV_CHECK_HIP(hipMemcpyAsync(g.data(), G, dd * sizeof(double), hipMemcpyDeviceToHost, s));
+  LV_CHECK_HIP(hipStreamSynchronize(s));
+  if (!lv::clip_factor(d, g.data(), t.data())) return LV_OK;
+  LV_CHECK_HIP(hipMemcpyAsync(T, t.data(), dd * sizeof(double), hipMemcpyHostToDevice, s));
+  const size_t n = (size_t)d * D;
+  hipLaunchKernelGGL(lv::apply_clip_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     T, M, d, D, out);
+  LV_CHECK_LAUNCH();
+  LV_CHECK_HIP(hipMemcpyAsync(M, out, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  // the host copy of T must outlive the transfer
+  LV_CHECK_HIP(hipStreamSynchronize(s));
   return LV_OK;
 }

@@ -140,6 +140,17 @@ def test_gemm_validation_and_workspace_size():
     assert lv.lv_gemm_workspace_size(0, 768) == 0
 
 
+def test_device_clip_validation_and_workspace_size():
+    lib = lv.load()
+    ws = lv.lv_clip_spectral_device_workspace_size(128, 768)
+    assert ws == 2 * 128 * 128 * 8 + 128 * 768 * 4
+    assert lv.lv_clip_spectral_device_workspace_size(0, 768) == 0
+    assert lib.lv_clip_spectral_device(None, 128, 768, FAKE, ws, None) == lv.LV_EINVAL
+    assert lib.lv_clip_spectral_device(FAKE, 128, 768, FAKE, ws - 1, None) == lv.LV_EINVAL
+    assert lib.lv_clip_spectral_device(FAKE, 2000, 768, FAKE, 1 << 30, None) == lv.LV_EINVAL
+    assert lib.lv_clip_spectral_device(FAKE, 128, 768, FAKE + 4, ws, None) == lv.LV_EINVAL
+
+
 def test_batch_step_validation_without_a_device():
     lib = lv.load()
     one = (lv.Request * 1)(lv.Request(0, 10, 20, 5))

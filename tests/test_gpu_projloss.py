@@ -177,6 +177,29 @@ def test_refinement_reduces_the_loss(lv, block):
     assert losses[-1] < losses[0]
 
 
+@pytest.mark.parametrize("d,D,scale", [(128, 768, 3.0), (160, 768, 0.5), (7, 33, 2.0)])
+def test_device_clip_matches_host(lv, d, D, scale):
+    """Projection onto the spectral-norm ball on the device against the host
+    float64 routine (itself pinned against an SVD): equal to float32
+    rounding; a matrix already inside the ball is left bit for bit."""
+    rng = np.random.default_rng(d + D)
+    U, _ = np.linalg.qr(rng.standard_normal((D, d)))
+    sv = scale * np.linspace(0.2, 1.8, d)  # singular values on both sides of 1 (scale 1)
+    Vt, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    M = ((Vt * sv) @ U.T).astype(np.float32)
+    Md = t(M)
+    ws = torch.empty(lv.lv_clip_spectral_device_workspace_size(d, D), dtype=torch.uint8,
+                     device=DEV)
+    lv.lv_clip_spectral_device(Md, ws)
+    torch.cuda.synchronize()
+    want = lv.lv_clip_spectral(M.astype(np.float64))
+    got = Md.cpu().numpy().astype(np.float64)
+    assert np.abs(got - want).max() <= 4e-6 * max(1.0, np.abs(want).max())
+    assert np.linalg.svd(got, compute_uv=False).max() <= 1.0 + 1e-5
+    if sv.max() <= 1.0:
+        assert np.array_equal(got, M.astype(np.float64))
+
+
 def test_gemm_unaligned_operands_take_the_elementwise_kernel(lv):
     # operands starting one float past a 16-byte boundary: same exact result
     rng = np.random.default_rng(17)
