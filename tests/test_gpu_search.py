@@ -342,6 +342,19 @@ def test_team_launch_edges(lv, small, k, L):
     assert none[0].shape == (0, k)
 
 
+@pytest.mark.parametrize("expand", [1, 3])
+def test_team_launch_at_the_largest_window(lv, small, expand):
+    """L = 1024 (the largest window) and k = 100: the team launch equals the
+    one-wavefront kernel bit for bit (ids, scores, counters)."""
+    index, _ = gpu_index(lv, small)
+    team = run_projected(lv, index, small, 100, 1024, hash_slots=8192, expand=expand,
+                         launch=lv.LV_LAUNCH_TEAM)
+    one = run_projected(lv, index, small, 100, 1024, hash_slots=8192, expand=expand)
+    for g, o in zip(team, one):
+        assert np.array_equal(g, o)
+    assert (team[0] != osearch.SENTINEL).all()  # 10,000 nodes: every query finds 100
+
+
 def _resid_case(lv, N=6000):
     """id-1m-768 at N = 6000 with residual secondaries: P_full = all D
     eigenvectors of the oracle's fit, primaries from its first d rows,
