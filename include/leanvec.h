@@ -505,7 +505,8 @@ int lv_graph_build(const void *records, int32_t record_stride, int64_t N, int32_
  * is split over K into partial products there, which a second kernel adds
  * in a fixed order (the result does not depend on scheduling); a smaller
  * workspace than lv_gemm_workspace_size gives fewer parts.  Calls that
- * share a workspace must not overlap.
+ * share a workspace must not overlap, nor may the workspace overlap A, B or
+ * C.
  */
 int lv_gemm(const float *A, int32_t a_kcont, int64_t lda, const float *B, int32_t b_kcont,
             int64_t ldb, float *C, int64_t ldc, int32_t M, int32_t N, int32_t K, float alpha,
