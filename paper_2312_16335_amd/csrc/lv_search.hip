@@ -321,10 +321,16 @@ __device__ __forceinline__ void score_batch(const IndexView &ix, const float (&q
   }
 }
 
-// Bitonic sort of one (score, id) pair per lane, best first.
-__device__ __forceinline__ void sort64(double &s, uint32_t &id, int lane) {
+// Bitonic sort of one (score, id) pair per lane, best first.  Entries sit
+// in lanes [0, n) and the other lanes hold padding (-inf, sentinel), so the
+// phases that merge blocks larger than the smallest power of two >= n only
+// move padding and are skipped.
+__device__ __forceinline__ void sort64(double &s, uint32_t &id, int lane, int n) {
 #pragma unroll
   for (int k = 2; k <= 64; k <<= 1) {
+    // lanes from n on hold only padding: once a block of k/2 lanes holds
+    // every entry, block 0 is already sorted best first and stays so
+    if ((k >> 1) >= n) break;  // uniform
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
       const double ps = __shfl_xor(s, j, 64);
@@ -551,7 +557,7 @@ __device__ __forceinline__ void merge_batch(const Lds &sm, int nc, int L, int &n
     wave_sync();
     return;
   }
-  sort64(bs, bid, lane);
+  sort64(bs, bid, lane, nc);
   int lb = 0;
   bool valid = bid != kSentinel;
   if constexpr (DEDUP) {  // repeats are adjacent after the sort
