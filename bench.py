@@ -1252,10 +1252,12 @@ def cpu_baseline(wl, X, Xs, Q, adj, entry, L, sample, truth, expand=1, mix=None)
     log(f"oracle index ready in {time.time() - t:.1f}s")
     procs = max(1, min(16, len(os.sched_getaffinity(0))))
     n = min(sample, len(Q))
-    t = time.perf_counter()
-    got, _, _ = osearch.search_many(index, Q[:n], Qp[:n], wl.k, L, procs=procs, chunk=16,
-                                    expand=expand)
-    dt = time.perf_counter() - t
+    dt = math.inf
+    for _ in range(3):  # best of three (the runs are short)
+        t = time.perf_counter()
+        got, _, _ = osearch.search_many(index, Q[:n], Qp[:n], wl.k, L, procs=procs, chunk=16,
+                                        expand=expand)
+        dt = min(dt, time.perf_counter() - t)
     rec = recall(np.asarray(got).astype(np.int64), truth[:n], wl.k)
     model = ""
     try:
@@ -1271,7 +1273,7 @@ def cpu_baseline(wl, X, Xs, Q, adj, entry, L, sample, truth, expand=1, mix=None)
             "sample": f"{which} test queries, window L={L}, {expand} expansion(s) per iteration, "
                       f"float64 numpy oracle with its own "
                       f"projection and encoding, one process per core (process start-up "
-                      f"included)",
+                      f"included), best of 3 runs",
             "recall": rec, "cpu_model": model}
 
 
