@@ -181,6 +181,25 @@ def _dev(t, dtype=None):
     return t.data_ptr()
 
 
+def _need(t, n: int, what: str) -> None:
+    """Raise ValueError unless tensor t holds at least n elements."""
+    if t is not None and t.numel() < n:
+        raise ValueError(f"{what} holds {t.numel()} elements, needs at least {n}")
+
+
+def _rows_cols(t, what: str, cols: Optional[int] = None, min_rows: int = 0):
+    """(rows, cols) of a 2-D tensor, checked against the expected columns and
+    a minimum row count; raises ValueError otherwise."""
+    if t.dim() != 2:
+        raise ValueError(f"{what} must be 2-D, got shape {tuple(t.shape)}")
+    r, c = int(t.shape[0]), int(t.shape[1])
+    if cols is not None and c != cols:
+        raise ValueError(f"{what} must have {cols} columns, got shape {tuple(t.shape)}")
+    if r < min_rows:
+        raise ValueError(f"{what} must have at least {min_rows} rows, got {r}")
+    return r, c
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -275,8 +294,11 @@ def lv_project(V, M_bf16, out, stream=None) -> None:
     """out[rows, d] = V[rows, D] @ M^T with M given as bfloat16 bits (int16 tensor)."""
     import torch
 
-    rows, D = V.shape
-    d = M_bf16.shape[0]
+    rows, D = _rows_cols(V, "V")
+    d, _ = _rows_cols(M_bf16, "M_bf16", cols=D)
+    if M_bf16.element_size() != 2:
+        raise ValueError("M_bf16 must hold 2-byte bfloat16 bits")
+    _need(out, rows * d, "out")
     _check(load().lv_project(_dev(V, torch.float32), rows, D, _dev(M_bf16), d,
                              _dev(out, torch.float32), _stream(stream)))
 
@@ -292,7 +314,9 @@ def lv_secondary_row_bytes(D: int, sec_dtype: int) -> int:
 def lv_lvq_encode(Y, mu, bits: int, records, stream=None) -> None:
     import torch
 
-    n, d = Y.shape
+    n, d = _rows_cols(Y, "Y")
+    _need(mu, d, "mu")
+    _rows_cols(records, "records", min_rows=n)
     _check(load().lv_lvq_encode(_dev(Y, torch.float32), n, d, _dev(mu, torch.float32), bits,
                                 _dev(records, torch.uint8), records.shape[1], _stream(stream)))
 
@@ -300,6 +324,7 @@ def lv_lvq_encode(Y, mu, bits: int, records, stream=None) -> None:
 def lv_to_f16(X, out, stream=None) -> None:
     import torch
 
+    _need(out, X.numel(), "out")
     _check(load().lv_to_f16(_dev(X, torch.float32), X.numel(), _dev(out, torch.float16),
                             _stream(stream)))
 
@@ -347,14 +372,25 @@ class Index:
         residual coordinates [N][D - d] with A_bf16 the [D][D] basis."""
         import torch
 
-        N = secondaries.shape[0]
+        N, sec_cols = _rows_cols(secondaries, "secondaries")
         if residual:
-            sec_dtype, D = LV_F16_RESID, secondaries.shape[1] + d
+            sec_dtype, D = LV_F16_RESID, sec_cols + d
         elif sec_mu is not None:
-            sec_dtype, D = LV_LVQ8, sec_mu.shape[0]
+            sec_dtype, D = LV_LVQ8, int(sec_mu.numel())
+            if sec_cols != lv_secondary_row_bytes(D, LV_LVQ8):
+                raise ValueError(f"LVQ-8 secondaries need rows of "
+                                 f"{lv_secondary_row_bytes(D, LV_LVQ8)} bytes for D = {D}")
         else:
             sec_dtype = LV_F16 if secondaries.dtype == torch.float16 else LV_F32
-            D = secondaries.shape[1]
+            D = sec_cols
+        # the library cannot see buffer sizes: check them here, before any launch
+        _rows_cols(records, "records", min_rows=N)
+        _need(mu, d, "mu")
+        R = _rows_cols(adjacency, "adjacency", min_rows=N)[1]
+        if not 0 <= entry < N:
+            raise ValueError(f"entry {entry} outside [0, {N})")
+        if A_bf16 is not None:
+            _rows_cols(A_bf16, "A_bf16", cols=D, min_rows=D if residual else d)
         self._keep = (records, mu, secondaries, adjacency, A_bf16, sec_mu)
         self.desc = IndexDesc(N, D, d, bits, records.shape[1], _dev(records, torch.uint8),
                               _dev(mu, torch.float32), sec_dtype, _dev(secondaries),
@@ -364,7 +400,9 @@ class Index:
         h = _vp()
         _check(load().lv_index_create(ctypes.byref(self.desc), ctypes.byref(h)))
         self.handle = h
-        self.N, self.D, self.d = N, D, d
+        self.N, self.D, self.d, self.R = N, D, d, R
+        # floats per projected query: P q, plus P_perp q with residual secondaries
+        self.qp_width = D if residual else d
 
     def close(self):
         if self.handle:
@@ -382,6 +420,14 @@ def _params(hash_slots: int = 0, probes: int = 0, launch: int = 0, expand: int =
     return ctypes.byref(SearchParams(hash_slots, probes, launch, expand))
 
 
+def _search_outputs(m: int, k: int, ids, scores, counters) -> None:
+    """ids and scores hold m * k results, counters two per query."""
+    if k >= 1:
+        _need(ids, m * k, "ids")
+        _need(scores, m * k, "scores")
+    _need(counters, 2 * m, "counters")
+
+
 def lv_search_workspace_size(index: Index, m: int) -> int:
     return load().lv_search_workspace_size(index.handle, m)
 
@@ -391,8 +437,12 @@ def lv_search(index: Index, Q, k: int, L: int, ids, scores, counters=None, ws=No
               launch: int = LV_LAUNCH_PER_QUERY) -> None:
     import torch
 
-    m = Q.shape[0]
+    m = _rows_cols(Q, "Q", cols=index.D)[0]
+    _search_outputs(m, k, ids, scores, counters)
     ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    if ws_bytes < lv_search_workspace_size(index, m):
+        raise ValueError(f"workspace of {ws_bytes} bytes, needs "
+                         f"{lv_search_workspace_size(index, m)}")
     _check(load().lv_search(index.handle, _dev(Q, torch.float32), m, k, L,
                             _dev(ids, torch.int32), _dev(scores, torch.float32),
                             _dev(counters, torch.int32), _dev(ws), ws_bytes,
@@ -404,7 +454,9 @@ def lv_search_projected(index: Index, Q, Qp, k: int, L: int, ids, scores, counte
                         expand: int = 0, launch: int = LV_LAUNCH_PER_QUERY) -> None:
     import torch
 
-    m = Q.shape[0]
+    m = _rows_cols(Q, "Q", cols=index.D)[0]
+    _rows_cols(Qp, "Qp", cols=index.qp_width, min_rows=m)
+    _search_outputs(m, k, ids, scores, counters)
     _check(load().lv_search_projected(index.handle, _dev(Q, torch.float32),
                                       _dev(Qp, torch.float32), m, k, L, _dev(ids, torch.int32),
                                       _dev(scores, torch.float32), _dev(counters, torch.int32),
@@ -419,6 +471,7 @@ class Multi:
 
     def __init__(self, indexes):
         self._subs = list(indexes)
+        self.D = self._subs[0].D if self._subs else 0
         arr = (_vp * len(self._subs))(*[ix.handle for ix in self._subs])
         h = _vp()
         _check(load().lv_multi_create(arr, len(self._subs), ctypes.byref(h)))
@@ -434,6 +487,17 @@ class Multi:
             self.close()
         except Exception:
             pass
+
+
+def _step_buffers(multi: "Multi", reqs, Q, ids, scores, counters=None) -> None:
+    """Q holds the requests' queries (rows packed in request order), ids and
+    scores count * k results per request, counters two per query."""
+    nq = sum(max(int(c), 0) for (_, _, _, c) in reqs)
+    nres = sum(max(int(c), 0) * max(int(k), 0) for (_, k, _, c) in reqs)
+    _rows_cols(Q, "Q", cols=multi.D, min_rows=nq)
+    _need(ids, nres, "ids")
+    _need(scores, nres, "scores")
+    _need(counters, 2 * nq, "counters")
 
 
 def _requests(reqs):
@@ -463,6 +527,7 @@ class Batch:
         (lv_batch_step_timed)."""
         import torch
 
+        _step_buffers(self.multi, reqs, Q, ids, scores, counters)
         arr = _requests(reqs)
         args = (self.handle, arr, len(reqs), _dev(Q, torch.float32), _dev(ids, torch.int32),
                 _dev(scores, torch.float32), _dev(counters, torch.int32))
@@ -493,6 +558,9 @@ def lv_autotune_window(multi: Multi, sub: int, Q, truth: np.ndarray, k: int, tar
     import torch
 
     truth = np.ascontiguousarray(truth, dtype=np.uint32)
+    m = _rows_cols(Q, "Q", cols=multi.D)[0]
+    if truth.ndim != 2 or truth.shape[0] < m or truth.shape[1] < k:
+        raise ValueError(f"truth must be [{m}][>= {k}], got {truth.shape}")
     L = ctypes.c_int32(0)
     rec = ctypes.c_double(0.0)
     _check(load().lv_autotune_window(multi.handle, sub, _dev(Q, torch.float32), Q.shape[0],
@@ -507,6 +575,7 @@ def lv_autotune_knobs(multi: Multi, max_requests, max_queries, max_L, reqs, Q, i
                       reps=3, stream=None, expand: int = 0):
     import torch
 
+    _step_buffers(multi, reqs, Q, ids, scores)
     caps = BatchCaps(max_requests, max_L, max_queries)
     best = SearchParams(0, 0, 0, expand)
     ms = ctypes.c_double(0.0)
@@ -527,6 +596,10 @@ def lv_gemm(A, B, C, M, N, K, a_kcont=True, b_kcont=True, lda=None, ldb=None, ld
     lda = lda if lda is not None else (K if a_kcont else M)
     ldb = ldb if ldb is not None else (K if b_kcont else N)
     ldc = ldc if ldc is not None else N
+    # element extents of the strided operands (rows of ld elements)
+    _need(A, (M - 1) * lda + K if a_kcont else (K - 1) * lda + M, "A")
+    _need(B, (N - 1) * ldb + K if b_kcont else (K - 1) * ldb + N, "B")
+    _need(C, (M - 1) * ldc + N, "C")
     ws, ws_bytes = None, 0
     if workspace is not None:
         ws, ws_bytes = _dev(workspace, workspace.dtype), workspace.numel() * workspace.element_size()
@@ -543,11 +616,30 @@ def lv_projloss_workspace_size(bq, bx, D, d) -> int:
     return load().lv_projloss_workspace_size(bq, bx, D, d)
 
 
+def _projloss_operands(A, B, Qb, Xb, ws, KQn, KXn):
+    """Shapes of the refinement operands: A, B [d][D], Qb [bq][D], Xb [bx][D],
+    KQn, KXn [D][D] (both or neither), workspace large enough."""
+    d, D = _rows_cols(A, "A")
+    _rows_cols(B, "B", cols=D, min_rows=d)
+    bq = _rows_cols(Qb, "Qb", cols=D)[0]
+    bx = _rows_cols(Xb, "Xb", cols=D)[0]
+    if (KQn is None) != (KXn is None):
+        raise ValueError("KQn and KXn are given together or not at all")
+    if KQn is not None:
+        _rows_cols(KQn, "KQn", cols=D, min_rows=D)
+        _rows_cols(KXn, "KXn", cols=D, min_rows=D)
+    need = lv_projloss_workspace_size(bq, bx, D, d)
+    if ws.numel() * ws.element_size() < need:
+        raise ValueError(f"workspace of {ws.numel() * ws.element_size()} bytes, needs {need}")
+    return d, D
+
+
 def lv_projloss_fwd(A, B, Qb, Xb, loss, ws, KQn=None, KXn=None, trace_const=0.0, lam=1.0,
                     stream=None):
     import torch
 
-    d, D = A.shape
+    d, D = _projloss_operands(A, B, Qb, Xb, ws, KQn, KXn)
+    _need(loss, 3, "loss")
     _check(load().lv_projloss_fwd(_dev(A, torch.float32), _dev(B, torch.float32),
                                   _dev(Qb, torch.float32), _dev(Xb, torch.float32), Qb.shape[0],
                                   Xb.shape[0], D, d, _dev(KQn, torch.float32),
@@ -560,7 +652,9 @@ def lv_projloss_bwd(A, B, Qb, Xb, dA, dB, ws, KQn=None, KXn=None, lam=1.0, grad_
                     stream=None):
     import torch
 
-    d, D = A.shape
+    d, D = _projloss_operands(A, B, Qb, Xb, ws, KQn, KXn)
+    _rows_cols(dA, "dA", cols=D, min_rows=d)
+    _rows_cols(dB, "dB", cols=D, min_rows=d)
     _check(load().lv_projloss_bwd(_dev(A, torch.float32), _dev(B, torch.float32),
                                   _dev(Qb, torch.float32), _dev(Xb, torch.float32), Qb.shape[0],
                                   Xb.shape[0], D, d, _dev(KQn, torch.float32),
@@ -572,6 +666,8 @@ def lv_projloss_bwd(A, B, Qb, Xb, dA, dB, ws, KQn=None, KXn=None, lam=1.0, grad_
 def lv_adam_step(p, g, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     import torch
 
+    for t, what in ((g, "g"), (m, "m"), (v, "v")):
+        _need(t, p.numel(), what)
     _check(load().lv_adam_step(_dev(p, torch.float32), _dev(g, torch.float32),
                                _dev(m, torch.float32), _dev(v, torch.float32), p.numel(), lr,
                                beta1, beta2, eps, t, _stream(stream)))
@@ -591,6 +687,9 @@ def lv_clip_spectral_device(M, ws, stream=None) -> None:
     """In place on a device float32 [d][D] tensor; ws: device workspace tensor."""
     import torch
 
-    d, D = M.shape
+    d, D = _rows_cols(M, "M")
+    need = lv_clip_spectral_device_workspace_size(d, D)
+    if ws.numel() * ws.element_size() < need:
+        raise ValueError(f"workspace of {ws.numel() * ws.element_size()} bytes, needs {need}")
     _check(load().lv_clip_spectral_device(_dev(M, torch.float32), d, D, _dev(ws),
                                           ws.numel() * ws.element_size(), _stream(stream)))

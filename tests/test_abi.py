@@ -327,3 +327,97 @@ def test_residual_secondaries_descriptor():
     # the workspace holds P q and P_perp q: D floats per query
     assert lib.lv_search_workspace_size(h, 10) >= 10 * 128 * 4
     lib.lv_index_destroy(h)
+
+
+def test_binding_checks_buffer_sizes_before_any_call():
+    """The C ABI cannot see buffer sizes, so the binding checks shapes and
+    element counts first: an undersized output raises ValueError before a
+    pointer is taken (host tensors stand in for device ones; with the right
+    shapes the same calls stop at the device-tensor check instead)."""
+    import types
+
+    torch = pytest.importorskip("torch")
+    f32, i32, u8 = torch.float32, torch.int32, torch.uint8
+    z = lambda *s, dt=f32: torch.zeros(s, dtype=dt)  # noqa: E731
+
+    with pytest.raises(ValueError):   # out holds 10 x 3 < 10 x 4
+        lv.lv_project(z(10, 16), z(4, 16, dt=torch.int16), z(10, 3))
+    with pytest.raises(ValueError):   # M has 12 columns, V has 16
+        lv.lv_project(z(10, 16), z(4, 12, dt=torch.int16), z(10, 4))
+    with pytest.raises(TypeError):    # shapes fine: refused as host tensors
+        lv.lv_project(z(10, 16), z(4, 16, dt=torch.int16), z(10, 4))
+    with pytest.raises(ValueError):   # 9 record rows for 10 vectors
+        lv.lv_lvq_encode(z(10, 32), z(32), 8, z(9, 64, dt=u8))
+    with pytest.raises(ValueError):
+        lv.lv_lvq_encode(z(10, 32), z(16), 8, z(10, 64, dt=u8))
+    with pytest.raises(ValueError):
+        lv.lv_to_f16(z(10, 8), z(79, dt=torch.float16))
+
+    N, D, d, R = 100, 128, 32, 32
+    good = dict(records=z(N, 64, dt=u8), mu=z(d), secondaries=z(N, D), adjacency=z(N, R, dt=i32),
+                entry=0, bits=8, d=d)
+    for bad in (dict(records=z(N - 1, 64, dt=u8)), dict(mu=z(d - 1)),
+                dict(adjacency=z(N - 1, R, dt=i32)), dict(entry=N),
+                dict(A_bf16=z(d, D - 1, dt=torch.int16)),
+                dict(secondaries=z(N, D + 8, dt=u8), sec_mu=z(D))):  # LVQ-8 rows are D + 16 B
+        with pytest.raises(ValueError):
+            lv.Index(**{**good, **bad})
+    with pytest.raises(TypeError):
+        lv.Index(**good)
+
+    rc, h = _create(_desc(N=N, D=D, d=d, R=R))
+    assert rc == lv.LV_OK
+    ix = types.SimpleNamespace(handle=h, D=D, d=d, qp_width=d)
+    m, k, L = 10, 5, 50
+    ws = z(lv.lv_search_workspace_size(ix, m), dt=u8)
+    ok = dict(ids=z(m, k, dt=i32), scores=z(m, k), counters=z(m, 2, dt=i32))
+    for bad in (dict(ids=z(m * k - 1, dt=i32)), dict(scores=z(m, k - 1)),
+                dict(counters=z(2 * m - 1, dt=i32))):
+        args = {**ok, **bad}
+        with pytest.raises(ValueError):
+            lv.lv_search(ix, z(m, D), k, L, args["ids"], args["scores"], args["counters"], ws=ws)
+        with pytest.raises(ValueError):
+            lv.lv_search_projected(ix, z(m, D), z(m, d), k, L, args["ids"], args["scores"],
+                                   args["counters"])
+    with pytest.raises(ValueError):   # queries of the wrong dimension
+        lv.lv_search(ix, z(m, D - 1), k, L, ok["ids"], ok["scores"], ws=ws)
+    with pytest.raises(ValueError):   # workspace one byte short
+        lv.lv_search(ix, z(m, D), k, L, ok["ids"], ok["scores"], ws=z(ws.numel() - 1, dt=u8))
+    with pytest.raises(ValueError):   # projected queries of the wrong width
+        lv.lv_search_projected(ix, z(m, D), z(m, d + 1), k, L, ok["ids"], ok["scores"])
+    with pytest.raises(TypeError):
+        lv.lv_search(ix, z(m, D), k, L, ok["ids"], ok["scores"], ws=ws)
+    lv.load().lv_index_destroy(h)
+
+    multi = types.SimpleNamespace(D=D)
+    reqs = [(0, 10, 50, 7), (0, 100, 120, 3)]      # 10 queries, 370 results
+    from paper_2312_16335_amd._lib import _step_buffers
+    _step_buffers(multi, reqs, z(10, D), z(370, dt=i32), z(370), z(20, dt=i32))
+    for args in ((z(9, D), z(370, dt=i32), z(370)), (z(10, D), z(369, dt=i32), z(370)),
+                 (z(10, D), z(370, dt=i32), z(369)), (z(10, D + 1), z(370, dt=i32), z(370))):
+        with pytest.raises(ValueError):
+            _step_buffers(multi, reqs, *args)
+    with pytest.raises(ValueError):
+        _step_buffers(multi, reqs, z(10, D), z(370, dt=i32), z(370), z(19, dt=i32))
+
+    with pytest.raises(ValueError):   # C [M][N] with M = N = K = 8 needs 64 elements
+        lv.lv_gemm(z(64), z(64), z(63), 8, 8, 8)
+    with pytest.raises(ValueError):   # B read with ldb = 16: (8 - 1) * 16 + 8 elements
+        lv.lv_gemm(z(64), z(64), z(64), 8, 8, 8, ldb=16)
+    Dr, dr, bq, bx = 16, 4, 5, 7
+    pws = z(lv.lv_projloss_workspace_size(bq, bx, Dr, dr), dt=u8)
+    A, B, Qb, Xb = z(dr, Dr), z(dr, Dr), z(bq, Dr), z(bx, Dr)
+    with pytest.raises(ValueError):
+        lv.lv_projloss_fwd(A, B, Qb, Xb, z(2), pws)
+    with pytest.raises(ValueError):
+        lv.lv_projloss_fwd(A, B, Qb, Xb, z(3), pws, KQn=z(Dr, Dr))
+    with pytest.raises(ValueError):
+        lv.lv_projloss_fwd(A, B, Qb, Xb, z(3), z(pws.numel() - 1, dt=u8))
+    with pytest.raises(ValueError):
+        lv.lv_projloss_bwd(A, B, Qb, Xb, z(dr, Dr), z(dr, Dr - 1), pws)
+    with pytest.raises(TypeError):
+        lv.lv_projloss_bwd(A, B, Qb, Xb, z(dr, Dr), z(dr, Dr), pws)
+    with pytest.raises(ValueError):
+        lv.lv_adam_step(z(10), z(10), z(9), z(10), 1e-3, 1)
+    with pytest.raises(ValueError):
+        lv.lv_clip_spectral_device(z(dr, Dr), z(1, dt=u8))
