@@ -32,8 +32,13 @@ so that the largest-magnitude entry is positive.
 
 Pinned by: Eckart-Young and an independent SVD of the data, trace form vs
 the direct Frobenius form, central finite differences of the gradients, the
-LMO optimality, the FW gap sign, Proposition 1's first inequality, and the
-eigenvector-search endpoints (tests/test_oracle_fit.py).
+LMO optimality, the FW gap sign, Proposition 1's first inequality, the
+eigenvector-search endpoints, a trace of Algorithm 1 worked by hand on
+D = 2, d = 1 (iterates, losses, gaps, B-step at the new A, the step
+schedule and the stop rule's denominator; tests/golden/fw_hand.json), and
+a hand example of the centring vector (tests/test_oracle_fit.py).
+
+Test infrastructure only: the search library never imports this module.
 """
 from __future__ import annotations
 

@@ -421,3 +421,36 @@ def test_binding_checks_buffer_sizes_before_any_call():
         lv.lv_adam_step(z(10), z(10), z(9), z(10), 1e-3, 1)
     with pytest.raises(ValueError):
         lv.lv_clip_spectral_device(z(dr, Dr), z(1, dt=u8))
+
+
+def test_fit_ood_hand_worked_trace():
+    """lv_fit_ood from a given start against Algorithm 1 worked by hand on
+    D = 2, d = 1 (tests/golden/fw_hand.json): iterates, losses and the sum of
+    the two linear steps' gaps per iteration; the early stop's denominator is
+    the loss before the iteration."""
+    import json
+
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "fw_hand.json")))
+    KQ, KX = np.array(g["KQ"]), np.array(g["KX"])
+    its = g["iterations"]
+    for n_it in range(1, len(its)):
+        A, B, info = lv.lv_fit_ood(KQ, 1, KX, 1, 1, alpha=g["alpha"], tol=0.0, max_iter=n_it,
+                                   init=lv.LV_FW_INIT_GIVEN, A0=[g["A0"]], B0=[g["B0"]])
+        want = its[n_it]
+        assert info["iters"] == n_it and not info["converged"]
+        np.testing.assert_allclose(A[0], want["A"], rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(B[0], want["B"], rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(info["f"], g["f"][:n_it + 1], rtol=1e-12)
+        np.testing.assert_allclose(info["gap"][-1], want["gap_A"] + want["gap_B"], rtol=1e-11)
+    for s in g["stops"]:
+        _, _, info = lv.lv_fit_ood(KQ, 1, KX, 1, 1, alpha=g["alpha"], tol=s["tol"], max_iter=50,
+                                   init=lv.LV_FW_INIT_GIVEN, A0=[g["A0"]], B0=[g["B0"]])
+        assert info["converged"] and info["iters"] == s["iters"]
+
+
+def test_mean_reduced_hand_example():
+    """mu = B * (sum of rows / n): rows (1, 2), (3, 4), (5, 9) sum to (9, 15);
+    B = [[1, 0], [1, 1], [2, -1]] maps their mean (3, 5) to (3, 8, 1)."""
+    B = np.array([[1.0, 0.0], [1.0, 1.0], [2.0, -1.0]])
+    mu = lv.lv_mean_reduced(B, np.array([9.0, 15.0]), 3)
+    np.testing.assert_array_equal(mu, np.array([3.0, 8.0, 1.0], np.float32))

@@ -151,3 +151,68 @@ def test_eigsearch_endpoints_and_id_fallback():
     for b in np.linspace(0, 1, 11):
         assert f_best <= fit.equalised_loss(fit.eigsearch_projection(KQ, m, KX, n, d, b),
                                             KQ, m, KX, n) + 1e-9 * abs(f_best)
+
+
+def _fw_hand():
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fw_hand.json")
+    return json.load(open(path))
+
+
+def test_frank_wolfe_hand_worked_trace():
+    """Algorithm 1 on D = 2, d = 1 against the trace worked by hand
+    (tests/golden/fw_hand.json): the iterates A^(t), B^(t), the losses, the
+    linear steps' gaps after each of the first six iterations, and the early
+    stop with the loss at (A^(t), B^(t)) as denominator.  A B-step taken from
+    the gradient at A^(t) instead of A^(t+1), or a step that ignores alpha,
+    misses the second iterate by far more than the tolerance."""
+    g = _fw_hand()
+    KQ, KX = np.array(g["KQ"]), np.array(g["KX"])
+    A0, B0 = np.array([g["A0"]]), np.array([g["B0"]])
+    its = g["iterations"]
+    for T in range(len(its) - 1):   # the loop runs t = 0, ..., T
+        A, B, rep = fit.frank_wolfe(KQ, g["m"], KX, g["n"], g["d"], alpha=g["alpha"], tol=0.0,
+                                    T=T, A0=A0, B0=B0)
+        want = its[T + 1]
+        assert rep.iters == T + 1
+        np.testing.assert_allclose(A[0], want["A"], rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(B[0], want["B"], rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(rep.f, g["f"][:T + 2], rtol=1e-12)
+        np.testing.assert_allclose(rep.gap_A[T], want["gap_A"], rtol=1e-11)
+        np.testing.assert_allclose(rep.gap_B[T], want["gap_B"], rtol=1e-11)
+    for s in g["stops"]:
+        _, _, rep = fit.frank_wolfe(KQ, 1, KX, 1, 1, alpha=g["alpha"], tol=s["tol"], T=50,
+                                    A0=A0, B0=B0)
+        assert rep.converged and rep.iters == s["iters"], (s, rep.iters)
+
+
+def test_hand_trace_separates_plausible_mistakes():
+    """The golden second iterate is far (>> the tolerance above) from what a
+    B-step at A^(t) or a step 1/(t+1) would give, so the trace test above
+    catches both (evaluated here with the oracle's own gradient and linear
+    step, reordered)."""
+    g = _fw_hand()
+    KQ, KX = np.array(g["KQ"]), np.array(g["KX"])
+    A, B = np.array([g["A0"]]), np.array([g["B0"]])
+    for t in range(2):  # B-step at the old A
+        gam = 1.0 / (t + 1) ** g["alpha"]
+        SA = fit.lmo(-fit.grad_A(A, B, KQ, KX))
+        SB = fit.lmo(-fit.grad_B(A, B, KQ, KX))
+        A, B = (1 - gam) * A + gam * SA, (1 - gam) * B + gam * SB
+    assert np.abs(B[0] - g["iterations"][2]["B"]).max() > 1e-2
+    A, B = np.array([g["A0"]]), np.array([g["B0"]])
+    for t in range(2):  # step ignoring alpha
+        gam = 1.0 / (t + 1)
+        A = (1 - gam) * A + gam * fit.lmo(-fit.grad_A(A, B, KQ, KX))
+        B = (1 - gam) * B + gam * fit.lmo(-fit.grad_B(A, B, KQ, KX))
+    assert np.abs(A[0] - g["iterations"][2]["A"]).max() > 1e-2
+
+
+def test_mean_reduced_hand_example():
+    """mu = B mean(x) (the LVQ centring vector): rows (1, 2), (3, 4), (5, 9)
+    have mean (3, 5); B = [[1, 0], [1, 1], [2, -1]] maps it to (3, 8, 1)."""
+    X = np.array([[1.0, 2.0], [3.0, 4.0], [5.0, 9.0]], np.float32)
+    B = np.array([[1.0, 0.0], [1.0, 1.0], [2.0, -1.0]])
+    np.testing.assert_array_equal(fit.mean_reduced(X, B), [3.0, 8.0, 1.0])
