@@ -10,9 +10,9 @@ pruning factor alpha.  Reading used here (Vamana with batch-synchronous
 insertion, so that a parallel build has one defined result):
 
   distance  f(a, b) = ||y^_a - y^_b||^2 of the LVQ reconstructions
-            y^ = mu + lo + delta * c (mu cancels), evaluated from exact
-            integer code sums and then one fixed sequence of float64
-            operations (see `l2`);
+            y^ = mu + lo + delta * c, by its definition: both vectors
+            decoded in float64 (mu cancels in the difference and is left
+            out), subtracted, squared and summed (see `l2`);
   order     a permutation of the nodes (an input); pass 0 inserts batches
             of 1, 2, 4, ... nodes up to max_batch, later passes use
             max_batch throughout; pass t prunes with alphas[t];
@@ -32,10 +32,17 @@ insertion, so that a parallel build has one defined result):
             order.
 Rows hold their valid ids first, then 0xFFFFFFFF.
 
-Pinned by: the distance against the directly decoded vectors, a hand-worked
-pruning example (tests/golden/prune_hand.json), the path graph that points
-on a line must produce, brute force for the search when L >= N, and the
-row invariants (tests/test_oracle_graph.py).
+Every decision of the build compares two distances (the search's order of
+its scored candidates, the pruning order, the pruning test).  `build`
+reports each of them to an optional monitor (`Monitor`), so that a caller
+can tell which decisions are too close to call for an implementation whose
+distance carries a different rounding error.
+
+Pinned by: the distance against exact rational arithmetic on the decoded
+vectors, a hand-worked pruning example (tests/golden/prune_hand.json), the
+path graph that points on a line must produce, brute force for the search
+when L >= N, hand-traced states after the first batches, and the row
+invariants (tests/test_oracle_graph.py).
 """
 from __future__ import annotations
 
@@ -56,34 +63,48 @@ class Primaries:
         self.delta = np.asarray(delta, dtype=np.float32).astype(np.float64)
         self.lo = np.asarray(lo, dtype=np.float32).astype(np.float64)
         self.n, self.d = self.codes.shape
-        self.s = self.codes.sum(axis=1).astype(np.float64)                 # sum of codes
-        self.ss = (self.codes * self.codes).sum(axis=1).astype(np.float64)  # sum of squares
+
+    def decode(self, ids) -> np.ndarray:
+        """y^ - mu = lo + delta * c for each id, float64 (delta * c is exact)."""
+        ids = np.asarray(ids, dtype=np.int64)
+        return self.lo[ids][..., None] + self.delta[ids][..., None] * self.codes[ids]
 
     def l2(self, a, b) -> np.ndarray:
-        """f(a, b) elementwise over broadcast id arrays a, b.
-
-        With e = lo_a - lo_b, the squared distance expands to
-        d e^2 + delta_a^2 S_aa + delta_b^2 S_bb - 2 delta_a delta_b S_ab
-        + 2 e (delta_a S_a - delta_b S_b), where S are integer code sums
-        (exact in float64).  The operations run in exactly this order and
-        grouping, each rounded once (no fused multiply-add).
-        """
+        """f(a, b) = sum_j (y^_a,j - y^_b,j)^2 elementwise over broadcast id
+        arrays a, b, in float64."""
         a = np.asarray(a, dtype=np.int64)
         b = np.asarray(b, dtype=np.int64)
         a, b = np.broadcast_arrays(a, b)
-        sab = np.einsum("ij,ij->i", self.codes[a.ravel()], self.codes[b.ravel()]).astype(
-            np.float64).reshape(a.shape)
-        da, db = self.delta[a], self.delta[b]
-        e = self.lo[a] - self.lo[b]
-        t = float(self.d) * (e * e)
-        t = t + (da * da) * self.ss[a]
-        t = t + (db * db) * self.ss[b]
-        t = t - 2.0 * ((da * db) * sab)
-        t = t + 2.0 * (e * (da * self.s[a] - db * self.s[b]))
-        return t
+        diff = self.decode(a) - self.decode(b)
+        return np.sum(diff * diff, axis=-1)
 
 
-def prune(p: int, pool: Sequence[int], dist: Callable, alpha: float, R: int) -> List[int]:
+class Monitor:
+    """Receives every comparison of distances the build decides on.
+
+    scored(p, ids, f): the distances from node p of every candidate its
+        construction search scored (the search orders them, keeps the best
+        L and expands them in that order);
+    ordered(p, ids, f): the pruning pool of p, ranked by (f, id);
+    tested(p, c, kept, f_kc, f_pc, alpha2): the pruning test of candidate c
+        against the kept nodes (c goes when alpha2 * f(k, c) <= f(p, c)).
+    `batch` holds the index of the batch being built (over all passes).
+    """
+
+    batch = 0
+
+    def scored(self, p, ids, f):
+        pass
+
+    def ordered(self, p, ids, f):
+        pass
+
+    def tested(self, p, c, kept, f_kc, f_pc, alpha2):
+        pass
+
+
+def prune(p: int, pool: Sequence[int], dist: Callable, alpha: float, R: int,
+          monitor: Optional[Monitor] = None) -> List[int]:
     """Diverse subset of the pool (Appendix A "Pruning"; Vamana's rule).
 
     dist(a, b) returns the distances of id array b to id(s) a.
@@ -93,6 +114,8 @@ def prune(p: int, pool: Sequence[int], dist: Callable, alpha: float, R: int) -> 
         return []
     fp = np.asarray(dist(np.full(ids.shape, p), ids), dtype=np.float64)
     order = np.lexsort((ids, fp))
+    if monitor is not None:
+        monitor.ordered(p, ids[order], fp[order])
     alpha2 = float(alpha) * float(alpha)
     kept: List[int] = []
     last = None
@@ -106,6 +129,8 @@ def prune(p: int, pool: Sequence[int], dist: Callable, alpha: float, R: int) -> 
         if kept:
             fk = np.asarray(dist(np.array(kept, dtype=np.int64), np.full(len(kept), c)),
                             dtype=np.float64)
+            if monitor is not None:
+                monitor.tested(p, c, list(kept), fk, float(fp[o]), alpha2)
             if np.any(alpha2 * fk <= fp[o]):
                 continue
         kept.append(c)
@@ -113,7 +138,7 @@ def prune(p: int, pool: Sequence[int], dist: Callable, alpha: float, R: int) -> 
 
 
 def reverse_row(j: int, cur: Sequence[int], sources: Sequence[int], dist: Callable,
-                alpha: float, R: int) -> List[int]:
+                alpha: float, R: int, monitor: Optional[Monitor] = None) -> List[int]:
     """Row of j after the reverse edges of one batch: the current row, then
     the new sources not in it (ascending); pruned when longer than R."""
     have = set(int(x) for x in cur)
@@ -121,7 +146,7 @@ def reverse_row(j: int, cur: Sequence[int], sources: Sequence[int], dist: Callab
                                      if int(p) not in have and int(p) != j]
     if len(union) <= R:
         return union
-    return prune(j, union, dist, alpha, R)
+    return prune(j, union, dist, alpha, R, monitor)
 
 
 def _pad(row: Sequence[int], R: int) -> np.ndarray:
@@ -130,19 +155,28 @@ def _pad(row: Sequence[int], R: int) -> np.ndarray:
     return out
 
 
-def window(prim: Primaries, adj: np.ndarray, entry: int, p: int, L: int) -> List[int]:
+def window(prim: Primaries, adj: np.ndarray, entry: int, p: int, L: int,
+           monitor: Optional[Monitor] = None) -> List[int]:
     """Ids of the final search window for node p (best first)."""
     ix = _search.Index(adj=adj, entry=int(entry), codes=prim.codes, delta=prim.delta,
                        lo=prim.lo, mu=np.zeros(prim.d), sec=None)
-    lst = _search.beam(ix, None, L, scorer=lambda ids: -prim.l2(np.full(len(ids), p), ids))
+    tr = _search.Trace(scored={} if monitor is not None else None)
+    lst = _search.beam(ix, None, L, trace=tr,
+                       scorer=lambda ids: -prim.l2(np.full(len(ids), p), ids))
+    if monitor is not None:
+        ids = np.fromiter(tr.scored.keys(), dtype=np.int64, count=len(tr.scored))
+        monitor.scored(p, ids, -np.fromiter(tr.scored.values(), dtype=np.float64,
+                                            count=len(ids)))
     return [i for _, i in lst]
 
 
 def build(prim: Primaries, order: Sequence[int], entry: int, R: int, L: int,
-          alphas: Sequence[float], max_batch: int, stop_after: int = 0) -> np.ndarray:
+          alphas: Sequence[float], max_batch: int, stop_after: int = 0,
+          monitor: Optional[Monitor] = None) -> np.ndarray:
     """Adjacency uint32 [N, R] built as described in the module text.
 
     stop_after > 0 stops after that many batches (counted over all passes).
+    monitor, when given, receives every comparison of distances (`Monitor`).
     """
     n = prim.n
     order = np.asarray(order, dtype=np.int64)
@@ -157,12 +191,14 @@ def build(prim: Primaries, order: Sequence[int], entry: int, R: int, L: int,
             if stop_after and batches == stop_after:
                 return adj
             batch = order[start:start + bs]
+            if monitor is not None:
+                monitor.batch = batches
             frozen = adj.copy()
             rows = []
             for p in batch.tolist():
-                pool = window(prim, frozen, entry, p, L)
+                pool = window(prim, frozen, entry, p, L, monitor)
                 pool += [int(x) for x in frozen[p] if x != SENTINEL]
-                rows.append(prune(p, pool, prim.l2, alpha, R))
+                rows.append(prune(p, pool, prim.l2, alpha, R, monitor))
             sources = {}
             for p, row in zip(batch.tolist(), rows):
                 adj[p] = _pad(row, R)
@@ -170,7 +206,7 @@ def build(prim: Primaries, order: Sequence[int], entry: int, R: int, L: int,
                     sources.setdefault(j, []).append(p)
             for j in sorted(sources):
                 cur = [int(x) for x in adj[j] if x != SENTINEL]
-                adj[j] = _pad(reverse_row(j, cur, sources[j], prim.l2, alpha, R), R)
+                adj[j] = _pad(reverse_row(j, cur, sources[j], prim.l2, alpha, R, monitor), R)
             batches += 1
             start += len(batch)
             bs = min(2 * bs, max_batch)

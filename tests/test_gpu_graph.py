@@ -3,11 +3,20 @@ identical (integer output), at sizes spanning many batches, for 8- and 4-bit
 records, the record layouts of the 8-, 16- and 64-lane groups, alpha != 1, the
 largest R and record width, partial builds, and points on a line (the path
 graph).  Inputs come from the oracle's encoder; nothing the oracle reads
-comes from the device."""
+comes from the device.
+
+The oracle evaluates each distance by its definition and the GPU from integer
+code sums, so the two round differently; the comparison is tie-aware
+(tests/graph_ties.py): every decision of the oracle's build is checked
+against both error bounds, the adjacency must be identical when no decision
+is too close to call, and otherwise identical up to the batch before the
+first such decision.  On these inputs no decision is (the count is asserted
+and printed), so the full adjacency is compared bit for bit."""
 import numpy as np
 import pytest
 
 import paper_2312_16335_amd as lv
+from graph_ties import TieMonitor
 from oracle import graph as og
 from oracle import lvq
 
@@ -37,6 +46,27 @@ def _gpu_build(rec, n, d, bits, order, entry, R, L, alphas, max_batch, stop_afte
     return (out, st) if stats else out
 
 
+def _oracle_build(prim, order, entry, R, L, alphas, mb, stop_after=0):
+    mon = TieMonitor(prim)
+    want = og.build(prim, order, entry, R, L, alphas, mb, stop_after=stop_after, monitor=mon)
+    print("oracle build: %d decisions, %d too close to call" % (mon.decisions, mon.fragile))
+    return want, mon
+
+
+def _assert_same(got, want, mon, rebuild):
+    """Bit-exact when no decision was fragile; otherwise the partial builds
+    before the first fragile batch must agree (rebuild(k) -> (gpu, oracle))."""
+    if mon.fragile == 0:
+        bad = np.nonzero((got != want).any(axis=1))[0]
+        assert bad.size == 0, "rows differ: %s (first: gpu %s oracle %s)" % (
+            bad[:10].tolist(), got[bad[0]].tolist(), want[bad[0]].tolist())
+        return
+    og.check_rows(got)
+    if mon.first_batch:
+        g, w = rebuild(mon.first_batch)
+        assert np.array_equal(g, w)
+
+
 CASES = [
     # n, d, bits, R, L, max_batch, alphas
     (1000, 32, 8, 16, 32, 64, (1.0, 1.0)),
@@ -52,7 +82,8 @@ def test_build_equals_oracle(case):
     n, d, bits, R, L, mb, alphas = case
     prim, rec, order = _clustered(n, d, bits, seed=n + d)
     entry = int(order[0])
-    want = og.build(prim, order, entry, R, L, alphas, mb)
+    want, mon = _oracle_build(prim, order, entry, R, L, alphas, mb)
+    assert mon.fragile == 0
     got, st = _gpu_build(rec, n, d, bits, order, entry, R, L, alphas, mb, stats=True)
     og.check_rows(got)
     # work counters: one search per node and pass, each scoring at least the entry
@@ -61,9 +92,9 @@ def test_build_equals_oracle(case):
     assert st["forward_candidates"] <= st["searches"] * (L + R)
     assert st["reverse_prunes"] <= st["reverse_targets"]
     assert st["reverse_candidates"] > R * st["reverse_prunes"] or st["reverse_prunes"] == 0
-    bad = np.nonzero((got != want).any(axis=1))[0]
-    assert bad.size == 0, "rows differ: %s (first: gpu %s oracle %s)" % (
-        bad[:10].tolist(), got[bad[0]].tolist(), want[bad[0]].tolist())
+    _assert_same(got, want, mon, lambda k: (
+        _gpu_build(rec, n, d, bits, order, entry, R, L, alphas, mb, k),
+        og.build(prim, order, entry, R, L, alphas, mb, stop_after=k)))
 
 
 @pytest.mark.parametrize("stop_after", [1, 2, 5, 9, 12])
@@ -71,7 +102,8 @@ def test_partial_builds_equal_oracle(stop_after):
     n, d, bits, R, L, mb = 700, 32, 8, 12, 24, 48
     prim, rec, order = _clustered(n, d, bits, seed=21)
     entry = int(order[0])
-    want = og.build(prim, order, entry, R, L, (1.0, 1.0), mb, stop_after=stop_after)
+    want, mon = _oracle_build(prim, order, entry, R, L, (1.0, 1.0), mb, stop_after)
+    assert mon.fragile == 0
     got = _gpu_build(rec, n, d, bits, order, entry, R, L, (1.0, 1.0), mb, stop_after)
     assert np.array_equal(got, want)
 
@@ -105,7 +137,8 @@ def test_too_many_new_edges_in_one_batch_is_an_error():
     assert e.value.code == lv.LV_EUNSUPPORTED
     # the library stays usable: a small build still matches the oracle
     prim, rec2, order2 = _clustered(300, 32, 8, seed=3)
-    want = og.build(prim, order2, 0, 8, 16, (1.0,), 16)
+    want, mon = _oracle_build(prim, order2, 0, 8, 16, (1.0,), 16)
+    assert mon.fragile == 0
     assert np.array_equal(_gpu_build(rec2, 300, 32, 8, order2, 0, 8, 16, (1.0,), 16), want)
 
 
@@ -115,7 +148,8 @@ def test_too_many_new_edges_in_one_batch_is_an_error():
 def test_degenerate_builds_equal_oracle(n, R, L, mb):
     prim, rec, order = _clustered(n, 16, 8, seed=100 + n + R)
     entry = int(order[0])
-    want = og.build(prim, order, entry, R, L, (1.0, 1.0), mb)
+    want, mon = _oracle_build(prim, order, entry, R, L, (1.0, 1.0), mb)
+    assert mon.fragile == 0
     got = _gpu_build(rec, n, 16, 8, order, entry, R, L, (1.0, 1.0), mb)
     assert np.array_equal(got, want)
     og.check_rows(got)

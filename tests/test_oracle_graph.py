@@ -23,15 +23,35 @@ def _random_primaries(n, d, bits, seed):
 
 
 @pytest.mark.parametrize("bits", [8, 4])
-def test_l2_equals_decoded_distance(bits):
+def test_l2_equals_exact_distance_of_reconstructions(bits):
+    """f(a, b) against ||y^_a - y^_b||^2 in exact rational arithmetic (the
+    float32 constants and integer codes are exact rationals; mu cancels), to
+    within the rounding of the float64 evaluation: decoding, subtracting and
+    squaring cost at most 3u sum_j |y^_a - y^_b|_j (|y^_a|_j + |y^_b|_j +
+    |y^_a - y^_b|_j), summing d u f (u = 2^-53); nearest pairs included."""
+    from fractions import Fraction as Fr
+
     prim, Yh = _random_primaries(200, 24, bits, 3)
     rng = np.random.default_rng(4)
-    a = rng.integers(0, 200, 500)
-    b = rng.integers(0, 200, 500)
-    direct = ((Yh[a] - Yh[b]) ** 2).sum(axis=1)
+    a = rng.integers(0, 200, 300)
+    b = rng.integers(0, 200, 300)
+    # and each node with its nearest other node (the pairs pruning decides on)
+    full = ((Yh[:, None, :].astype(np.float64) - Yh[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(full, np.inf)
+    a = np.concatenate([a, np.arange(200)])
+    b = np.concatenate([b, full.argmin(axis=1)])
     got = prim.l2(a, b)
-    assert np.allclose(got, direct, rtol=1e-12, atol=1e-12 * direct.max())
-    # a node's distance to itself cancels exactly: x + x - 2 x with one rounding each
+    u = 2.0 ** -53
+    for i in range(len(a)):
+        ya = [Fr(float(prim.lo[a[i]])) + Fr(float(prim.delta[a[i]])) * int(c)
+              for c in prim.codes[a[i]]]
+        yb = [Fr(float(prim.lo[b[i]])) + Fr(float(prim.delta[b[i]])) * int(c)
+              for c in prim.codes[b[i]]]
+        exact = sum((x - y) ** 2 for x, y in zip(ya, yb))
+        bound = sum(3 * u * abs(float(x - y)) * (abs(float(x)) + abs(float(y)) + abs(float(x - y)))
+                    for x, y in zip(ya, yb)) + prim.d * u * float(exact)
+        assert abs(Fr(float(got[i])) - exact) <= Fr(2 * bound), (a[i], b[i])
+    # a node's distance to itself is exactly zero
     assert np.all(prim.l2(a, a) == 0.0)
 
 
@@ -150,3 +170,35 @@ def test_stop_after_and_bad_order():
     assert (a2[3:] == SENT).all()
     with pytest.raises(ValueError):
         og.build(prim, np.r_[order[:-1], 0], 0, 4, 8, [1.0], 4)
+
+
+def test_build_monitor_sees_every_decision_and_flags_ties():
+    """The decision hooks leave the build unchanged; on clustered random data
+    no decision is within the rounding bounds of tests/graph_ties.py, while
+    equally spaced points on a line (distinct records at exactly equal
+    distances, ties broken by id) are reported as too close to call."""
+    import sys
+
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from graph_ties import TieMonitor
+
+    rng = np.random.default_rng(11)
+    n, d = 300, 16
+    C = rng.standard_normal((6, d)) * 2
+    Y = (C[rng.integers(0, 6, n)] + rng.standard_normal((n, d))).astype(np.float32)
+    codes, delta, lo = lvq.encode(Y, Y.mean(axis=0).astype(np.float32), 8)
+    prim = og.Primaries(codes, delta, lo)
+    order = rng.permutation(n)
+    mon = TieMonitor(prim)
+    a = og.build(prim, order, int(order[0]), 8, 16, (1.0, 1.2), 16, monitor=mon)
+    assert np.array_equal(a, og.build(prim, order, int(order[0]), 8, 16, (1.0, 1.2), 16))
+    assert mon.decisions > 10000 and mon.fragile == 0 and mon.first_batch is None
+    # points 0, 0.5, 1, ... on the diagonal: each interior point is equally far
+    # from both neighbours
+    t = np.arange(40) * 0.5
+    Yl = (t[:, None] * np.ones((1, 4))).astype(np.float32)
+    cl, dl, ll = lvq.encode(Yl, np.zeros(4, np.float32), 8)
+    pl = og.Primaries(cl, dl, ll)
+    mon = TieMonitor(pl)
+    og.build(pl, np.arange(40)[::-1].copy(), 39, 2, 8, (1.0,), 4, monitor=mon)
+    assert mon.fragile > 0 and mon.first_batch is not None
