@@ -11,6 +11,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -36,26 +37,30 @@ def _run(cmd):
     return r.stdout
 
 
-def build(verbose: bool = False, out: str = LIB, extra_flags=()) -> str:
-    """Compile every source and link ``out`` (the package library by default)."""
+def build(verbose: bool = False, out: str = LIB, extra_flags=(), host_flags=()) -> str:
+    """Compile every source and link ``out`` (the package library by default).
+
+    extra_flags go to every hipcc compile, host_flags to the g++ compiles of
+    the host-only sources."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
-    objs = []
+    cmds = []
     for src in HIP_SOURCES:
         obj = os.path.join(objdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = ([HIPCC] + HIP_FLAGS + list(extra_flags) + PER_FILE.get(src, []) + lang
-               + ["-c", os.path.join(CSRC, src), "-o", obj])
-        msg = _run(cmd)
-        if verbose and msg.strip():
-            print(msg)
-        objs.append(obj)
+        cmds.append(([HIPCC] + HIP_FLAGS + list(extra_flags) + PER_FILE.get(src, []) + lang
+                     + ["-c", os.path.join(CSRC, src), "-o", obj], obj))
     for src in HOST_SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        _run(["g++", "-O3", "-std=c++17", "-fPIC", "-fopenmp", "-march=x86-64-v3", "-c",
-              os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        cmds.append((["g++", "-O3", "-std=c++17", "-fPIC", "-fopenmp", "-march=x86-64-v3"]
+                     + list(host_flags) + ["-c", os.path.join(CSRC, src), "-o", obj], obj))
+    # independent translation units: compiled side by side
+    with ThreadPoolExecutor(max(1, min(len(cmds), os.cpu_count() or 1, 8))) as pool:
+        for msg in pool.map(lambda c: _run(c[0]), cmds):
+            if verbose and msg.strip():
+                print(msg)
+    objs = [o for _, o in cmds]
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp%d" % os.getpid()
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
