@@ -512,6 +512,20 @@ int lv_gemm(const float *A, int32_t a_kcont, int64_t lda, const float *B, int32_
             int64_t ldb, float *C, int64_t ldc, int32_t M, int32_t N, int32_t K, float alpha,
             float beta, void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * The same product with split-precision operands: every float32 operand x
+ * is taken as hi + lo, hi = bf16(x), lo = bf16(x - hi), and the product is
+ * accumulated as hi*hi + hi*lo + lo*hi (three matrix-core passes), for a
+ * relative error per operand of about 2^-17 instead of 2^-9.  The loss
+ * kernels use it for the products whose results cancel (the residual of
+ * Problem leanvec_orthonormal and the trace gradients of Eq.
+ * leanvec_gradients).  Arguments, workspace and errors as for lv_gemm.
+ */
+int lv_gemm_split(const float *A, int32_t a_kcont, int64_t lda, const float *B,
+                  int32_t b_kcont, int64_t ldb, float *C, int64_t ldc, int32_t M, int32_t N,
+                  int32_t K, float alpha, float beta, void *workspace, size_t workspace_bytes,
+                  void *stream);
+
 /* Workspace bytes with which lv_gemm may split an M x N product the most. */
 size_t lv_gemm_workspace_size(int32_t M, int32_t N);
 

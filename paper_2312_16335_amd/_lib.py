@@ -112,6 +112,9 @@ _SIGS = {
                                     ctypes.POINTER(_c_i32), ctypes.POINTER(_c_dbl), _vp]),
     "lv_gemm": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i32, _c_i64, _vp, _c_i64, _c_i32, _c_i32,
                          _c_i32, ctypes.c_float, ctypes.c_float, _vp, ctypes.c_size_t, _vp]),
+    "lv_gemm_split": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i32, _c_i64, _vp, _c_i64, _c_i32,
+                               _c_i32, _c_i32, ctypes.c_float, ctypes.c_float, _vp,
+                               ctypes.c_size_t, _vp]),
     "lv_gemm_workspace_size": (ctypes.c_size_t, [_c_i32, _c_i32]),
     "lv_projloss_workspace_size": (ctypes.c_size_t, [_c_i32, _c_i32, _c_i32, _c_i32]),
     "lv_projloss_fwd": (_c_i32, [_vp, _vp, _vp, _vp, _c_i32, _c_i32, _c_i32, _c_i32, _vp, _vp,
@@ -590,7 +593,8 @@ def lv_autotune_knobs(multi: Multi, max_requests, max_queries, max_L, reqs, Q, i
 # ------------------------------------------------- differentiable projection
 
 def lv_gemm(A, B, C, M, N, K, a_kcont=True, b_kcont=True, lda=None, ldb=None, ldc=None,
-            alpha=1.0, beta=0.0, workspace=None, stream=None):
+            alpha=1.0, beta=0.0, workspace=None, stream=None, split=False):
+    """C = alpha op(A) op(B)^T + beta C (lv_gemm; lv_gemm_split with split=True)."""
     import torch
 
     lda = lda if lda is not None else (K if a_kcont else M)
@@ -603,9 +607,10 @@ def lv_gemm(A, B, C, M, N, K, a_kcont=True, b_kcont=True, lda=None, ldb=None, ld
     ws, ws_bytes = None, 0
     if workspace is not None:
         ws, ws_bytes = _dev(workspace, workspace.dtype), workspace.numel() * workspace.element_size()
-    _check(load().lv_gemm(_dev(A, torch.float32), int(a_kcont), lda, _dev(B, torch.float32),
-                          int(b_kcont), ldb, _dev(C, torch.float32), ldc, M, N, K, alpha, beta,
-                          ws, ws_bytes, _stream(stream)))
+    fn = load().lv_gemm_split if split else load().lv_gemm
+    _check(fn(_dev(A, torch.float32), int(a_kcont), lda, _dev(B, torch.float32), int(b_kcont),
+              ldb, _dev(C, torch.float32), ldc, M, N, K, alpha, beta, ws, ws_bytes,
+              _stream(stream)))
 
 
 def lv_gemm_workspace_size(M, N) -> int:
@@ -666,8 +671,8 @@ def lv_projloss_bwd(A, B, Qb, Xb, dA, dB, ws, KQn=None, KXn=None, lam=1.0, grad_
 def lv_adam_step(p, g, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     import torch
 
-    for t, what in ((g, "g"), (m, "m"), (v, "v")):
-        _need(t, p.numel(), what)
+    for buf, what in ((g, "g"), (m, "m"), (v, "v")):
+        _need(buf, p.numel(), what)
     _check(load().lv_adam_step(_dev(p, torch.float32), _dev(g, torch.float32),
                                _dev(m, torch.float32), _dev(v, torch.float32), p.numel(), lr,
                                beta1, beta2, eps, t, _stream(stream)))

@@ -16,6 +16,7 @@ struct GemmArgs {
   int64_t ldc;
   int32_t M, N, K;
   float alpha, beta;
+  int32_t split = 0;  // 1: split-precision operands (hi + lo bfloat16), three passes
 };
 
 // C = alpha * op(A) op(B)^T + beta * C; a_kcont / b_kcont select whether

@@ -14,6 +14,14 @@
 // the current tile is multiplied (one barrier per step), with float4 loads
 // for both operand layouts; otherwise gemm_kernel stages element by element
 // in steps of 32.
+//
+// Split precision (GemmArgs::split): each float32 operand x is written as
+// hi + lo with hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in
+// float32), and the product is accumulated as hi*hi + hi*lo + lo*hi in three
+// passes over K through the same LDS tiles (the lo*lo term is below 2^-16 of
+// the product).  The relative error per operand falls from about 2^-9 to
+// about 2^-17, at three times the matrix-core work; products whose result
+// cancels (a difference of nearly equal products) need it.
 #include "lv_common.h"
 #include "lv_gemm.h"
 
@@ -33,8 +41,19 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
   return (uint16_t)(u >> 16);
 }
 
+// bfloat16 bits of x (LO = false) or of the remainder x - bf16(x) (LO = true).
+template <bool LO>
+__device__ __forceinline__ uint16_t bf16_part(float x) {
+  if constexpr (LO) {
+    const float hi = __uint_as_float((uint32_t)bf16_bits(x) << 16);
+    return bf16_bits(x - hi);
+  } else {
+    return bf16_bits(x);
+  }
+}
+
 // Stage a BM x BK tile of operand X (rows r0.., k k0..) into S[row][k].
-template <bool KCONT>
+template <bool KCONT, bool LO = false>
 __device__ __forceinline__ void stage(const float *__restrict__ X, int64_t ld, int rows,
                                       int kdim, int r0, int k0, uint16_t *S, int tid) {
   if constexpr (KCONT) {
@@ -46,7 +65,7 @@ __device__ __forceinline__ void stage(const float *__restrict__ X, int64_t ld, i
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int gk = k0 + kk + i;
-      v[i] = (gr < rows && gk < kdim) ? bf16_bits(X[(int64_t)gr * ld + gk]) : (uint16_t)0;
+      v[i] = (gr < rows && gk < kdim) ? bf16_part<LO>(X[(int64_t)gr * ld + gk]) : (uint16_t)0;
     }
     uint4 *dst = reinterpret_cast<uint4 *>(S + r * LDK + kk);
     uint32_t w[8];
@@ -63,38 +82,28 @@ __device__ __forceinline__ void stage(const float *__restrict__ X, int64_t ld, i
     for (int i = 0; i < 16; ++i) {
       const int gr = r0 + rr + i;
       S[(rr + i) * LDK + kk] =
-          (gr < rows && gk < kdim) ? bf16_bits(X[(int64_t)gk * ld + gr]) : (uint16_t)0;
+          (gr < rows && gk < kdim) ? bf16_part<LO>(X[(int64_t)gk * ld + gr]) : (uint16_t)0;
     }
   }
 }
 
-template <bool AK, bool BKC>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
-  __shared__ __align__(16) uint16_t As[2][BM * LDK];
-  __shared__ __align__(16) uint16_t Bs[2][BN * LDK];
-  const int tid = threadIdx.x;
+// One pass over K of the product of the (LA, LB) parts of the operands,
+// accumulated into acc.
+template <bool AK, bool BKC, bool LA, bool LB>
+__device__ __forceinline__ void gemm_pass(const GemmArgs &g, uint16_t (*As)[BM * LDK],
+                                          uint16_t (*Bs)[BN * LDK], int m0, int n0, int wm,
+                                          int wn, int tid, f32x16 (&acc)[2][2]) {
   const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
-
   const int nk = (g.K + BK - 1) / BK;
-  stage<AK>(g.A, g.lda, g.M, g.K, m0, 0, As[0], tid);
-  stage<BKC>(g.B, g.ldb, g.N, g.K, n0, 0, Bs[0], tid);
+  stage<AK, LA>(g.A, g.lda, g.M, g.K, m0, 0, As[0], tid);
+  stage<BKC, LB>(g.B, g.ldb, g.N, g.K, n0, 0, Bs[0], tid);
   __syncthreads();
   const int r = lane & 31, kh = lane >> 5;
   for (int t = 0; t < nk; ++t) {
     const int cur = t & 1;
     if (t + 1 < nk) {
-      stage<AK>(g.A, g.lda, g.M, g.K, m0, (t + 1) * BK, As[cur ^ 1], tid);
-      stage<BKC>(g.B, g.ldb, g.N, g.K, n0, (t + 1) * BK, Bs[cur ^ 1], tid);
+      stage<AK, LA>(g.A, g.lda, g.M, g.K, m0, (t + 1) * BK, As[cur ^ 1], tid);
+      stage<BKC, LB>(g.B, g.ldb, g.N, g.K, n0, (t + 1) * BK, Bs[cur ^ 1], tid);
     }
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
@@ -116,6 +125,30 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
     __syncthreads();
   }
+}
+
+template <bool AK, bool BKC, bool SPLIT>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  __shared__ __align__(16) uint16_t As[2][BM * LDK];
+  __shared__ __align__(16) uint16_t Bs[2][BN * LDK];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  gemm_pass<AK, BKC, false, false>(g, As, Bs, m0, n0, wm, wn, tid, acc);
+  if constexpr (SPLIT) {
+    gemm_pass<AK, BKC, false, true>(g, As, Bs, m0, n0, wm, wn, tid, acc);
+    gemm_pass<AK, BKC, true, false>(g, As, Bs, m0, n0, wm, wn, tid, acc);
+  }
+  const int r = lane & 31, kh = lane >> 5;
   // accumulator: lane holds column (lane % 32), register e holds row
   // 8 * (e / 4) + 4 * (lane / 32) + (e % 4) of its 32 x 32 tile
 #pragma unroll
@@ -185,15 +218,20 @@ __device__ __forceinline__ void vload(const float *__restrict__ X, int64_t ld, i
   }
 }
 
-// Two floats to bfloat16 (round to nearest even) in one conversion instruction.
+// Two floats to bfloat16 (round to nearest even) in one conversion
+// instruction; LO: the remainders x - bf16(x) instead (exact in float32).
+template <bool LO = false>
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
   typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
-  const bf16x2 h = {(__bf16)lo, (__bf16)hi};
+  bf16x2 h = {(__bf16)lo, (__bf16)hi};
+  if constexpr (LO) {
+    h = bf16x2{(__bf16)(lo - (float)h[0]), (__bf16)(hi - (float)h[1])};
+  }
   return __builtin_bit_cast(uint32_t, h);
 }
 
-// Registers -> LDS tile S[row][k] (bfloat16).
-template <bool KCONT>
+// Registers -> LDS tile S[row][k] (bfloat16; LO: the remainders' bfloat16).
+template <bool KCONT, bool LO = false>
 __device__ __forceinline__ void vstore(const Frag &f, uint16_t *S, int tid) {
   if constexpr (KCONT) {
     const int r = tid >> 1, kk = (tid & 1) * 32;
@@ -201,8 +239,8 @@ __device__ __forceinline__ void vstore(const Frag &f, uint16_t *S, int tid) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const float4 a = f.v[2 * i], b = f.v[2 * i + 1];
-      dst[i] = make_uint4(pack_bf16(a.x, a.y), pack_bf16(a.z, a.w), pack_bf16(b.x, b.y),
-                          pack_bf16(b.z, b.w));
+      dst[i] = make_uint4(pack_bf16<LO>(a.x, a.y), pack_bf16<LO>(a.z, a.w),
+                          pack_bf16<LO>(b.x, b.y), pack_bf16<LO>(b.z, b.w));
     }
   } else {
     const int k = 2 * (tid >> 3), mm = (tid & 7) * 16;
@@ -210,42 +248,26 @@ __device__ __forceinline__ void vstore(const Frag &f, uint16_t *S, int tid) {
     for (int i = 0; i < 4; ++i) {
       const float4 a = f.v[i], b = f.v[4 + i];  // rows k and k + 1, m = mm + 4i ..
       uint32_t *d = reinterpret_cast<uint32_t *>(S + (mm + 4 * i) * VLD + k);
-      d[0] = pack_bf16(a.x, b.x);
-      d[VLD / 2] = pack_bf16(a.y, b.y);
-      d[VLD] = pack_bf16(a.z, b.z);
-      d[3 * VLD / 2] = pack_bf16(a.w, b.w);
+      d[0] = pack_bf16<LO>(a.x, b.x);
+      d[VLD / 2] = pack_bf16<LO>(a.y, b.y);
+      d[VLD] = pack_bf16<LO>(a.z, b.z);
+      d[3 * VLD / 2] = pack_bf16<LO>(a.w, b.w);
     }
   }
 }
 
-// Split over K (grid z): part z covers steps [z * sps, (z + 1) * sps) and,
-// when `part` is set, writes alpha times its partial product to
-// part[z][M][N]; otherwise the whole K range goes to C.
-template <bool AK, bool BKC>
-__global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g, int sps, float *part) {
-  __shared__ __align__(16) uint16_t As[2][BM * VLD];
-  __shared__ __align__(16) uint16_t Bs[2][BN * VLD];
-  const int tid = threadIdx.x;
+// One pass over steps [t0, t0 + nk) of K of the product of the (LA, LB)
+// parts of the operands, accumulated into acc.
+template <bool AK, bool BKC, bool LA, bool LB>
+__device__ __forceinline__ void vec_pass(const GemmArgs &g, uint16_t (*As)[BM * VLD],
+                                         uint16_t (*Bs)[BN * VLD], int m0, int n0, int wm,
+                                         int wn, int t0, int nk, int tid, f32x16 (&acc)[2][2]) {
   const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
-
-  const int nk_all = (g.K + VK - 1) / VK;
-  const int t0 = (int)blockIdx.z * sps;
-  const int nk = (t0 + sps < nk_all ? t0 + sps : nk_all) - t0;  // steps of this part
   Frag fa, fb;
   vload<AK>(g.A, g.lda, g.M, g.K, m0, t0 * VK, fa, tid);
   vload<BKC>(g.B, g.ldb, g.N, g.K, n0, t0 * VK, fb, tid);
-  vstore<AK>(fa, As[0], tid);
-  vstore<BKC>(fb, Bs[0], tid);
+  vstore<AK, LA>(fa, As[0], tid);
+  vstore<BKC, LB>(fb, Bs[0], tid);
   __syncthreads();
   const int r = lane & 31, kh = lane >> 5;
   for (int t = 0; t < nk; ++t) {
@@ -274,11 +296,42 @@ __global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g, int sps, floa
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) {  // the other buffer was last read before the previous barrier
-      vstore<AK>(fa, As[cur ^ 1], tid);
-      vstore<BKC>(fb, Bs[cur ^ 1], tid);
+      vstore<AK, LA>(fa, As[cur ^ 1], tid);
+      vstore<BKC, LB>(fb, Bs[cur ^ 1], tid);
     }
     __syncthreads();
   }
+}
+
+// Split over K (grid z): part z covers steps [z * sps, (z + 1) * sps) and,
+// when `part` is set, writes alpha times its partial product to
+// part[z][M][N]; otherwise the whole K range goes to C.
+template <bool AK, bool BKC, bool SPLIT>
+__global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g, int sps, float *part) {
+  __shared__ __align__(16) uint16_t As[2][BM * VLD];
+  __shared__ __align__(16) uint16_t Bs[2][BN * VLD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int nk_all = (g.K + VK - 1) / VK;
+  const int t0 = (int)blockIdx.z * sps;
+  const int nk = (t0 + sps < nk_all ? t0 + sps : nk_all) - t0;  // steps of this part
+  vec_pass<AK, BKC, false, false>(g, As, Bs, m0, n0, wm, wn, t0, nk, tid, acc);
+  if constexpr (SPLIT) {
+    vec_pass<AK, BKC, false, true>(g, As, Bs, m0, n0, wm, wn, t0, nk, tid, acc);
+    vec_pass<AK, BKC, true, false>(g, As, Bs, m0, n0, wm, wn, t0, nk, tid, acc);
+  }
+  const int r = lane & 31, kh = lane >> 5;
   float *pz = part ? part + (int64_t)blockIdx.z * g.M * g.N : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -316,6 +369,44 @@ __global__ __launch_bounds__(256) void split_sum_kernel(const float *__restrict_
 
 constexpr int kMaxSplit = 16;
 
+struct VecLaunch {
+  const GemmArgs &g;
+  dim3 grid;
+  int sps;
+  float *part;
+  hipStream_t s;
+  template <bool AK, bool BKC, bool SPLIT>
+  void go() {
+    hipLaunchKernelGGL((gemm_vec_kernel<AK, BKC, SPLIT>), grid, dim3(256), 0, s, g, sps, part);
+  }
+};
+
+struct ElemLaunch {
+  const GemmArgs &g;
+  dim3 grid;
+  hipStream_t s;
+  template <bool AK, bool BKC, bool SPLIT>
+  void go() {
+    hipLaunchKernelGGL((gemm_kernel<AK, BKC, SPLIT>), grid, dim3(256), 0, s, g);
+  }
+};
+
+// The kernel instance for the operand layouts and precision.
+template <class F>
+void dispatch_layout(bool ak, bool bk, bool split, F &f) {
+  if (split) {
+    if (ak && bk) f.template go<true, true, true>();
+    else if (ak) f.template go<true, false, true>();
+    else if (bk) f.template go<false, true, true>();
+    else f.template go<false, false, true>();
+  } else {
+    if (ak && bk) f.template go<true, true, false>();
+    else if (ak) f.template go<true, false, false>();
+    else if (bk) f.template go<false, true, false>();
+    else f.template go<false, false, false>();
+  }
+}
+
 bool vec_ok(const float *p, int64_t ld) {
   return (reinterpret_cast<uintptr_t>(p) & 15u) == 0 && ld % 4 == 0;
 }
@@ -343,14 +434,8 @@ int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *sp
     parts = nk > 0 ? (nk + sps - 1) / sps : 1;
     float *part = parts > 1 ? split_ws : nullptr;
     const dim3 gz(grid.x, grid.y, (unsigned)parts);
-    if (a_kcont && b_kcont)
-      hipLaunchKernelGGL((gemm_vec_kernel<true, true>), gz, dim3(256), 0, s, g, sps, part);
-    else if (a_kcont)
-      hipLaunchKernelGGL((gemm_vec_kernel<true, false>), gz, dim3(256), 0, s, g, sps, part);
-    else if (b_kcont)
-      hipLaunchKernelGGL((gemm_vec_kernel<false, true>), gz, dim3(256), 0, s, g, sps, part);
-    else
-      hipLaunchKernelGGL((gemm_vec_kernel<false, false>), gz, dim3(256), 0, s, g, sps, part);
+    VecLaunch f{g, gz, sps, part, s};
+    dispatch_layout(a_kcont, b_kcont, g.split != 0, f);
     if (part) {
       const int64_t mn = (int64_t)g.M * g.N;
       const unsigned blocks = (unsigned)((mn + 255) / 256 < 2048 ? (mn + 255) / 256 : 2048);
@@ -359,35 +444,48 @@ int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *sp
     LV_CHECK_LAUNCH();
     return LV_OK;
   }
-  if (a_kcont && b_kcont)
-    hipLaunchKernelGGL((gemm_kernel<true, true>), grid, dim3(256), 0, s, g);
-  else if (a_kcont)
-    hipLaunchKernelGGL((gemm_kernel<true, false>), grid, dim3(256), 0, s, g);
-  else if (b_kcont)
-    hipLaunchKernelGGL((gemm_kernel<false, true>), grid, dim3(256), 0, s, g);
-  else
-    hipLaunchKernelGGL((gemm_kernel<false, false>), grid, dim3(256), 0, s, g);
+  ElemLaunch f{g, grid, s};
+  dispatch_layout(a_kcont, b_kcont, g.split != 0, f);
   LV_CHECK_LAUNCH();
   return LV_OK;
 }
 
 }  // namespace lv
 
-extern "C" int lv_gemm(const float *A, int32_t a_kcont, int64_t lda, const float *B,
-                       int32_t b_kcont, int64_t ldb, float *C, int64_t ldc, int32_t M, int32_t N,
-                       int32_t K, float alpha, float beta, void *workspace,
-                       size_t workspace_bytes, void *stream) {
+namespace {
+
+int gemm_entry(const float *A, int32_t a_kcont, int64_t lda, const float *B, int32_t b_kcont,
+               int64_t ldb, float *C, int64_t ldc, int32_t M, int32_t N, int32_t K, float alpha,
+               float beta, void *workspace, size_t workspace_bytes, void *stream, int split) {
   lv::clear_error();
   if (M < 0 || N < 0 || K < 0) LV_FAIL(LV_EINVAL, "negative size");
   if ((int64_t)M * N > 0 && (!A || !B || !C)) LV_FAIL(LV_EINVAL, "NULL pointer");
   if (ldc < N || lda < (a_kcont ? K : M) || ldb < (b_kcont ? K : N))
     LV_FAIL(LV_EINVAL, "leading dimension too small");
-  lv::GemmArgs g{A, lda, B, ldb, C, ldc, M, N, K, alpha, beta};
+  lv::GemmArgs g{A, lda, B, ldb, C, ldc, M, N, K, alpha, beta, split};
   if (workspace_bytes > 0 && !workspace) LV_FAIL(LV_EINVAL, "NULL workspace");
   if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 3u))
     LV_FAIL(LV_EINVAL, "workspace not 4-byte aligned");
   return lv::gemm(g, a_kcont != 0, b_kcont != 0, static_cast<hipStream_t>(stream),
                   static_cast<float *>(workspace), workspace ? workspace_bytes / sizeof(float) : 0);
+}
+
+}  // namespace
+
+extern "C" int lv_gemm(const float *A, int32_t a_kcont, int64_t lda, const float *B,
+                       int32_t b_kcont, int64_t ldb, float *C, int64_t ldc, int32_t M, int32_t N,
+                       int32_t K, float alpha, float beta, void *workspace,
+                       size_t workspace_bytes, void *stream) {
+  return gemm_entry(A, a_kcont, lda, B, b_kcont, ldb, C, ldc, M, N, K, alpha, beta, workspace,
+                    workspace_bytes, stream, 0);
+}
+
+extern "C" int lv_gemm_split(const float *A, int32_t a_kcont, int64_t lda, const float *B,
+                             int32_t b_kcont, int64_t ldb, float *C, int64_t ldc, int32_t M,
+                             int32_t N, int32_t K, float alpha, float beta, void *workspace,
+                             size_t workspace_bytes, void *stream) {
+  return gemm_entry(A, a_kcont, lda, B, b_kcont, ldb, C, ldc, M, N, K, alpha, beta, workspace,
+                    workspace_bytes, stream, 1);
 }
 
 extern "C" size_t lv_gemm_workspace_size(int32_t M, int32_t N) {

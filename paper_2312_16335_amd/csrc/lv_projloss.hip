@@ -17,7 +17,15 @@
 //
 // Every product is one launch of the bfloat16 matrix-core GEMM (float32
 // accumulation); Rm is formed as Qb Xb^T followed by a second product that
-// subtracts G H^T into the same buffer.  Sums of squares and inner products
+// subtracts G H^T into the same buffer.  Rm is a small difference of two
+// large products, and so are the trace part's M2 A - B K_X and
+// M1 B - A K_Q: the products that feed those differences (G, H, Qb Xb^T,
+// G H^T, B K_X, A K_Q, M1, M2, M2 A, M1 B) and the trace gradients' final
+// products take split-precision operands (hi + lo bfloat16, three matrix-core
+// passes), which brings the relative error of the gradients from about 1e-2
+// (plain bfloat16) to about 2e-4 at the refinement shape.  The pair-part
+// products of the backward (Rm H, Rm^T G, and their products with Qb, Xb)
+// involve no cancellation and stay in plain bfloat16.  Sums of squares and inner products
 // use a fixed-order two-pass float64 reduction, so results are deterministic.
 #include <algorithm>
 #include <vector>
@@ -173,20 +181,20 @@ extern "C" int lv_projloss_fwd(const float *A, const float *B, const float *Qb, 
   lv::ws_floats(bq, bx, D, d, &w, static_cast<float *>(ws));
   using lv::GemmArgs;
   // G = Qb A^T, H = Xb B^T
-  LV_G(GemmArgs{Qb, D, A, D, w.G, d, bq, d, D, 1.f, 0.f}, true, true, s);
-  LV_G(GemmArgs{Xb, D, B, D, w.H, d, bx, d, D, 1.f, 0.f}, true, true, s);
+  LV_G(GemmArgs{Qb, D, A, D, w.G, d, bq, d, D, 1.f, 0.f, 1}, true, true, s);
+  LV_G(GemmArgs{Xb, D, B, D, w.H, d, bx, d, D, 1.f, 0.f, 1}, true, true, s);
   // Rm = Qb Xb^T - G H^T
-  LV_G(GemmArgs{Qb, D, Xb, D, w.Rm, bx, bq, bx, D, 1.f, 0.f}, true, true, s);
-  LV_G(GemmArgs{w.G, d, w.H, d, w.Rm, bx, bq, bx, d, -1.f, 1.f}, true, true, s);
+  LV_G(GemmArgs{Qb, D, Xb, D, w.Rm, bx, bq, bx, D, 1.f, 0.f, 1}, true, true, s);
+  LV_G(GemmArgs{w.G, d, w.H, d, w.Rm, bx, bq, bx, d, -1.f, 1.f, 1}, true, true, s);
   const int with_trace = KQn != nullptr;
   hipLaunchKernelGGL(lv::dot_partials, dim3(lv::kRedBlocks), dim3(256), 0, s, w.Rm, w.Rm,
                      (int64_t)bq * bx, w.partial);
   if (with_trace) {
     // U1 = B K_X, U2 = A K_Q (moments symmetric), M2 = U1 B^T, M1 = U2 A^T
-    LV_G(GemmArgs{B, D, KXn, D, w.U1, D, d, D, D, 1.f, 0.f}, true, true, s);
-    LV_G(GemmArgs{A, D, KQn, D, w.U2, D, d, D, D, 1.f, 0.f}, true, true, s);
-    LV_G(GemmArgs{w.U1, D, B, D, w.M2, d, d, d, D, 1.f, 0.f}, true, true, s);
-    LV_G(GemmArgs{w.U2, D, A, D, w.M1, d, d, d, D, 1.f, 0.f}, true, true, s);
+    LV_G(GemmArgs{B, D, KXn, D, w.U1, D, d, D, D, 1.f, 0.f, 1}, true, true, s);
+    LV_G(GemmArgs{A, D, KQn, D, w.U2, D, d, D, D, 1.f, 0.f, 1}, true, true, s);
+    LV_G(GemmArgs{w.U1, D, B, D, w.M2, d, d, d, D, 1.f, 0.f, 1}, true, true, s);
+    LV_G(GemmArgs{w.U2, D, A, D, w.M1, d, d, d, D, 1.f, 0.f, 1}, true, true, s);
     hipLaunchKernelGGL(lv::dot_partials, dim3(lv::kRedBlocks), dim3(256), 0, s, w.M1, w.M2,
                        (int64_t)d * d, w.partial + lv::kRedBlocks);
     hipLaunchKernelGGL(lv::dot_partials, dim3(lv::kRedBlocks), dim3(256), 0, s, w.U2, w.U1,
@@ -224,13 +232,13 @@ extern "C" int lv_projloss_bwd(const float *A, const float *B, const float *Qb, 
     const int64_t n = (int64_t)d * D;
     const unsigned blocks = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
     // dA += t (M2 A - U1) K_Q
-    LV_G(GemmArgs{w.M2, d, A, D, w.W, D, d, D, d, 1.f, 0.f}, true, false, s);
+    LV_G(GemmArgs{w.M2, d, A, D, w.W, D, d, D, d, 1.f, 0.f, 1}, true, false, s);
     hipLaunchKernelGGL(lv::sub_kernel, dim3(blocks), dim3(256), 0, s, w.W, w.U1, n, w.W);
-    LV_G(GemmArgs{w.W, D, KQn, D, dA, D, d, D, D, t, 1.f}, true, true, s);
+    LV_G(GemmArgs{w.W, D, KQn, D, dA, D, d, D, D, t, 1.f, 1}, true, true, s);
     // dB += t (M1 B - U2) K_X
-    LV_G(GemmArgs{w.M1, d, B, D, w.W, D, d, D, d, 1.f, 0.f}, true, false, s);
+    LV_G(GemmArgs{w.M1, d, B, D, w.W, D, d, D, d, 1.f, 0.f, 1}, true, false, s);
     hipLaunchKernelGGL(lv::sub_kernel, dim3(blocks), dim3(256), 0, s, w.W, w.U2, n, w.W);
-    LV_G(GemmArgs{w.W, D, KXn, D, dB, D, d, D, D, t, 1.f}, true, true, s);
+    LV_G(GemmArgs{w.W, D, KXn, D, dB, D, d, D, D, t, 1.f, 1}, true, true, s);
   }
   LV_CHECK_LAUNCH();
   return LV_OK;

@@ -1,7 +1,8 @@
 """GPU tests of the differentiable projection path: the matrix-core GEMM (exact on
-bfloat16-representable inputs), the sampled-pair + trace loss and its gradients
-against the float64 oracle at the refinement shape (bfloat16 error stated),
-the autograd wrapper, and Adam."""
+bfloat16-representable inputs, plain and split precision), the sampled-pair +
+trace loss and its gradients against the float64 oracle at the refinement
+shape, element by element within derived bounds, the autograd wrapper, and
+Adam."""
 import numpy as np
 import pytest
 
@@ -76,6 +77,35 @@ def test_gemm_split_over_k_is_exact(lv, M, N, K, ak, bk, ws):
     assert np.array_equal(C2.cpu().numpy().astype(np.float64), a @ b.T)
 
 
+# Split precision: one operand of 12-bit integers (not representable in
+# bfloat16, but exactly hi + lo), the other of small integers (exact in
+# bfloat16, lo = 0), so hi*hi + hi*lo + lo*hi is the exact product and every
+# float32 partial sum is an exact integer; plain bfloat16 rounds the wide
+# operand and misses.  Both orders (the hi*lo and the lo*hi pass), both
+# kernels (aligned and element-wise shapes) and the split over K.
+@pytest.mark.parametrize("M,N,K", [(70, 130, 45), (256, 256, 128), (128, 768, 1100)])
+@pytest.mark.parametrize("wide", ["A", "B"])
+@pytest.mark.parametrize("ak,bk", [(True, True), (False, True), (True, False)])
+def test_gemm_split_precision_is_exact_on_wide_integers(lv, M, N, K, wide, ak, bk):
+    rng = np.random.default_rng(M + N + K + (wide == "A"))
+    big = lambda r, c: rng.integers(-2048, 2049, size=(r, c)).astype(np.float64)  # noqa: E731
+    small = lambda r, c: rng.integers(-6, 7, size=(r, c)).astype(np.float64)  # noqa: E731
+    a = big(M, K) if wide == "A" else small(M, K)
+    b = small(N, K) if wide == "A" else big(N, K)
+    c0 = rng.integers(-3, 4, size=(M, N)).astype(np.float64)
+    A = a if ak else a.T.copy()
+    B = b if bk else b.T.copy()
+    W = torch.empty(lv.lv_gemm_workspace_size(M, N) // 4, dtype=torch.float32, device=DEV)
+    C = t(c0)
+    lv.lv_gemm(t(A), t(B), C, M, N, K, a_kcont=ak, b_kcont=bk, alpha=2.0, beta=-1.0,
+               workspace=W, split=True)
+    P = torch.zeros((M, N), dtype=torch.float32, device=DEV)
+    lv.lv_gemm(t(A), t(B), P, M, N, K, a_kcont=ak, b_kcont=bk, workspace=W)
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy().astype(np.float64), 2.0 * a @ b.T - c0)
+    assert not np.array_equal(P.cpu().numpy().astype(np.float64), a @ b.T)
+
+
 @pytest.fixture(scope="module")
 def block():
     wl = gen.WORKLOADS["ood-1m-768"].scaled(N=8192, m_test=2048)
@@ -91,35 +121,94 @@ def block():
     return A, B, Q[:1024], X[:4096], KQ, KX
 
 
-def test_projloss_forward_backward_against_float64(lv, block):
-    A, B, Qb, Xb, KQ, KX = block
+def _gpu_projloss(lv, A, B, Qb, Xb, KQ, KX, lam):
     d, D = A.shape
-    lam = 1.0
-    tc = float(np.trace(KQ @ KX))
+    tc = float(np.trace(KQ.astype(np.float64) @ KX.astype(np.float64))) if KQ is not None else 0.0
     ws = torch.empty(lv.lv_projloss_workspace_size(len(Qb), len(Xb), D, d), dtype=torch.uint8,
                      device=DEV)
     loss = torch.empty(3, dtype=torch.float32, device=DEV)
     dA, dB = torch.empty((d, D), device=DEV), torch.empty((d, D), device=DEV)
-    At, Bt, Qt, Xt, KQt, KXt = t(A), t(B), t(Qb), t(Xb), t(KQ), t(KX)
+    KQt = t(KQ) if KQ is not None else None
+    KXt = t(KX) if KX is not None else None
+    At, Bt, Qt, Xt = t(A), t(B), t(Qb), t(Xb)
     lv.lv_projloss_fwd(At, Bt, Qt, Xt, loss, ws, KQt, KXt, tc, lam)
     lv.lv_projloss_bwd(At, Bt, Qt, Xt, dA, dB, ws, KQt, KXt, lam, 1.0)
     torch.cuda.synchronize()
-    # the oracle on the same float32-rounded inputs, in float64
+    return (loss.cpu().numpy().astype(np.float64), dA.cpu().numpy().astype(np.float64),
+            dB.cpu().numpy().astype(np.float64))
+
+
+def _bounds(A, B, Qb, Xb, KQ, KX, lam):
+    """Element-wise error bounds of the GPU gradients, from float64 magnitudes.
+
+    Pair part, -(2/P) (Rm H)^T Qb (and the same for B with G, Xb): the two
+    backward products round their operands to bfloat16 (2^-9 each), so the
+    error is at most about 2 * 2^-8 (2/P) (|H| |Rm|^T |Qb|)_ij; Rm itself is
+    formed with split precision (relative 2^-16 of |Qb Xb^T| + |G H^T|, far
+    below).  Trace part, 2 lam (M2 A - B K_X) K_Q with M2 = B K_X B^T: every
+    product has split operands, so the error is about 2^-15 of the chain of
+    magnitudes (|B| |K_X| |B|^T |A| + |B| |K_X|) |K_Q|.  Both are widened by
+    4 (pair) and 8 (trace)."""
+    A, B, Qb, Xb = (np.asarray(v, np.float64) for v in (A, B, Qb, Xb))
+    P = len(Qb) * len(Xb)
+    G, H = A @ Qb.T, B @ Xb.T
+    Rm = Qb @ Xb.T - G.T @ H
+    bA = 4 * 2 * 2.0 ** -8 * (2.0 / P) * (np.abs(H) @ np.abs(Rm).T) @ np.abs(Qb)
+    bB = 4 * 2 * 2.0 ** -8 * (2.0 / P) * (np.abs(G) @ np.abs(Rm)) @ np.abs(Xb)
+    if KQ is not None:
+        aA, aB = np.abs(A), np.abs(B)
+        aQ, aX = np.abs(np.asarray(KQ, np.float64)), np.abs(np.asarray(KX, np.float64))
+        UB, UA = aB @ aX, aA @ aQ  # |B| |K_X|, |A| |K_Q|: the magnitudes along each chain
+        bA = bA + 8 * 2.0 ** -15 * 2 * lam * ((UB @ aB.T) @ aA + UB) @ aQ
+        bB = bB + 8 * 2.0 ** -15 * 2 * lam * ((UA @ aA.T) @ aB + UA) @ aX
+    return bA, bB
+
+
+@pytest.mark.parametrize("case", ["pair-only", "full", "trace-dominated"])
+def test_projloss_elementwise_against_float64(lv, block, case):
+    """Loss and gradients against the float64 oracle on the same
+    float32-rounded inputs, element by element within the bounds of
+    `_bounds`: the pair part alone (no moments), pair and trace part with
+    lam = 1, and a trace-dominated case (lam = 100) in which a sign or scale
+    error of the trace gradient would exceed the bound by orders of
+    magnitude.  Relative Frobenius errors are printed and bounded too."""
+    A, B, Qb, Xb, KQ, KX = block
+    lam = {"pair-only": 1.0, "full": 1.0, "trace-dominated": 100.0}[case]
+    if case == "pair-only":
+        KQ = KX = None
     A32, B32 = A.astype(np.float32), B.astype(np.float32)
+    K32 = (None, None) if KQ is None else (KQ.astype(np.float32), KX.astype(np.float32))
+    got, dA, dB = _gpu_projloss(lv, A32, B32, Qb, Xb, K32[0], K32[1], lam)
+    pA, pB = opl.pair_grads(A32, B32, Qb, Xb)
+    gA, gB = pA, pB
     pair = opl.pair_loss(A32, B32, Qb, Xb)
-    tr = ofit.loss_trace(A32, B32, KQ.astype(np.float32), KX.astype(np.float32))
-    gA, gB = opl.grads(A32, B32, Qb, Xb, KQ.astype(np.float32), KX.astype(np.float32), lam)
-    got = loss.cpu().numpy().astype(np.float64)
-    err = {
-        "pair": abs(got[1] - pair) / pair,
-        "trace": abs(got[2] - tr) / abs(tr),
-        "dA": np.linalg.norm(dA.cpu().numpy() - gA) / np.linalg.norm(gA),
-        "dB": np.linalg.norm(dB.cpu().numpy() - gB) / np.linalg.norm(gB),
-    }
-    print("bfloat16 relative errors vs float64:", err)
-    # bfloat16 operands (2^-9 relative rounding) with float32 accumulation
-    assert err["pair"] < 2e-2 and err["dA"] < 5e-2 and err["dB"] < 5e-2
-    assert err["trace"] < 5e-2
+    if KQ is not None:
+        KQ64, KX64 = K32[0].astype(np.float64), K32[1].astype(np.float64)
+        tA = lam * ofit.grad_A(A32, B32, KQ64, KX64)
+        tB = lam * ofit.grad_B(A32, B32, KQ64, KX64)
+        gA, gB = pA + tA, pB + tB
+        tr = ofit.loss_trace(A32, B32, KQ64, KX64)
+    bA, bB = _bounds(A32, B32, Qb, Xb, K32[0], K32[1], lam)
+    err = {"pair": abs(got[1] - pair) / pair,
+           "dA": np.linalg.norm(dA - gA) / np.linalg.norm(gA),
+           "dB": np.linalg.norm(dB - gB) / np.linalg.norm(gB),
+           "dA/bound": float(np.max(np.abs(dA - gA) / bA)),
+           "dB/bound": float(np.max(np.abs(dB - gB) / bB))}
+    if KQ is not None:
+        err["trace"] = abs(got[2] - tr) / abs(tr)
+        err["trace part of dA"] = np.linalg.norm(tA) / np.linalg.norm(gA)
+    print(case, "errors vs float64:", err)
+    assert np.all(np.abs(dA - gA) <= bA), err
+    assert np.all(np.abs(dB - gB) <= bB), err
+    # split-precision residuals: the pair loss to about 2^-15 relative
+    assert err["pair"] < 1e-4
+    assert err["dA"] < 2e-3 and err["dB"] < 2e-3
+    if KQ is not None:
+        # f = <M1, M2> + tr(K_Q K_X) - 2 <A K_Q, B K_X>: error relative to the terms
+        Av, Bv = A32.astype(np.float64), B32.astype(np.float64)
+        terms = (abs(np.trace(Av @ KQ64 @ Av.T @ Bv @ KX64 @ Bv.T)) + abs(np.trace(KQ64 @ KX64))
+                 + 2 * abs(np.trace(KQ64 @ Av.T @ Bv @ KX64)))
+        assert abs(got[2] - tr) <= 2.0 ** -12 * terms
     assert abs(got[0] - (got[1] + lam * got[2])) <= 1e-6 * abs(got[0])
 
 
