@@ -476,3 +476,42 @@ def test_single_vector_index(lv):
         assert np.isneginf(sc[i, 1:].cpu().numpy()).all()
         assert abs(float(sc[i, 0]) - ws[0]) <= 1e-4 * max(1.0, abs(ws[0]))
     index.close()
+
+
+# Record layouts and graph degrees beyond the benchmark's: every record
+# stride the library accepts with 8- and 4-bit codes (8-bit records of up to
+# four 64-byte chunks take the matrix-core scoring, including the 96-byte
+# stride whose last chunk is partial; wider ones and all 4-bit ones the lane
+# groups), and out-degrees above 64 (R = 128, the paper's construction
+# setting, and R = 100, not a multiple of 64), with one and three expansions
+# per iteration.  Ids, scores and both counters against the oracle.
+LAYOUTS = [
+    # bits, d, D, R
+    (8, 160, 256, 128), (8, 160, 256, 100), (8, 32, 128, 64), (8, 88, 128, 64),
+    (8, 120, 128, 64), (8, 240, 256, 64), (8, 384, 512, 64), (8, 752, 768, 64),
+    (8, 1016, 1024, 64), (4, 32, 128, 64), (4, 160, 256, 128), (4, 240, 256, 64),
+    (4, 368, 512, 64), (4, 480, 512, 64), (4, 1000, 1024, 64),
+]
+
+
+@pytest.mark.parametrize("bits,d,D,R", LAYOUTS,
+                         ids=lambda v: str(v))
+def test_search_parity_record_layouts_and_degrees(lv, bits, d, D, R):
+    from dataclasses import replace
+
+    base = gen.WORKLOADS["id-small"]
+    wl = replace(base, name=f"layout-b{bits}-d{d}-D{D}", D=D, d=d, N=1500, m_test=24,
+                 bits=bits, sec_dtype="f16", R=R)
+    c = make_case(wl)
+    assert c.stride == stride_for(d, bits) and c.adj.shape[1] == R
+    index, _ = gpu_index(lv, c)
+    oidx = c.oracle_index()
+    for L, E in ((32, 1), (100, 1), (100, 3)):
+        want_ids, want_sc, want_cnt = osearch.search_many(oidx, c.Q, c.Qp, 10, L, expand=E)
+        got_ids, got_sc, got_cnt = run_projected(lv, index, c, 10, L, hash_slots=8192,
+                                                 expand=E)
+        assert_parity(c, oidx, got_ids, got_sc, want_ids, want_sc)
+        assert np.array_equal(got_cnt, want_cnt), (L, E)
+    # the team launch (four wavefronts per query) takes the same decisions
+    team = run_projected(lv, index, c, 10, 100, hash_slots=8192, expand=3, launch=2)
+    assert np.array_equal(team[0], got_ids) and np.array_equal(team[1], got_sc)
