@@ -260,3 +260,20 @@ def test_graph_build_at_full_size(lv, full):
     rec_at = sum(len(set(g) & set(t)) for g, t in zip(got, truth)) / (len(sample) * wl.k)
     log(f"10-recall@10 at window 128 on the GPU-built graph: {rec_at:.4f}")
     assert rec_at >= 0.90
+
+
+def test_benchmark_ground_truth_equals_oracle(lv, full):
+    """The benchmark's ground truth (float32 candidates on the device, float64
+    re-scoring) equals the oracle's exact float64 top-100 on a 300-query
+    sample of the 1M x 768 workload, so its recall operating point rests on
+    the oracle's definition."""
+    import bench
+
+    X, Q = full["X"], full["Q"][:300]
+    Xd = torch.from_numpy(X).to(DEV)
+    got = bench.ground_truth_gpu(torch, Xd, Q, 100)
+    del Xd
+    torch.cuda.empty_cache()
+    want = exact.ground_truth(Q, X, 100)
+    log("ground truth compared on 300 queries")
+    assert np.array_equal(got, want)

@@ -20,6 +20,8 @@ torch = pytest.importorskip("torch")
 from gpu_common import graph_cached
 from oracle import exact
 from oracle import fit as ofit
+from oracle import lvq as olvq
+from oracle import search as osearch
 from synth import gen
 
 pytestmark = pytest.mark.gpu
@@ -69,6 +71,7 @@ def subs(lv):
         Pb = torch.from_numpy(lv.lv_to_bf16(P).view(np.int16)).to(DEV)
         ix = lv.Index(rec, mud, sec, adjd, entry, wl.bits, wl.d, A_bf16=Pb)
         out.append(dict(wl=wl, X=X, Q=Q, Ql=Ql, ix=ix, keep=(rec, mud, sec, adjd, Pb),
+                        P=P, Y=Y, mu=mu, adj=adj, entry=entry, Pb=Pb,
                         truth=exact.ground_truth(Q, X, 100),
                         truth_l=exact.ground_truth(Ql, X, 100).astype(np.uint32)))
     yield out
@@ -136,5 +139,71 @@ def test_multi_index_stream(lv, subs):
     rec = hits / total
     print(f"{len(steps)} steps, {N_REQ} requests, test recall {rec:.4f}")
     assert rec >= TARGET - 0.03
+    batch.close()
+    multi.close()
+
+
+def test_batched_step_against_oracle(lv, subs):
+    """One captured step of eight requests on eight sub-indexes of uneven
+    sizes, k in {1, 10, 100}, against the float64 oracle directly:
+
+    * given the same projected queries (the device projection, whose bits the
+      step's grouped projection reproduces; lv_project computes them here),
+      the oracle's ids, scores and expansion and scoring counts, request by
+      request (exact visited set);
+    * each side with its own projection (the oracle's in float64), recall@k
+      of the step within 0.5 points of the oracle's, over all requests."""
+    chosen = [3, 11, 17, 25, 34, 42, 50, 61]
+    ks = [1, 10, 100, 10, 1, 100, 10, 10]
+    counts = [37, 128, 64, 1, 90, 50, 128, 7]
+    Ls = {1: 24, 10: 48, 100: 128}
+    multi = lv.Multi([d["ix"] for d in subs])
+    batch = lv.Batch(multi, max_requests=len(chosen), max_queries=sum(counts), max_L=128,
+                     hash_slots=8192)
+    reqs, Qs = [], []
+    for s, k, c in zip(chosen, ks, counts):
+        reqs.append((s, k, Ls[k], c))
+        Qs.append(subs[s]["Q"][:c])
+    Q = np.concatenate(Qs)
+    Qd = torch.from_numpy(Q).to(DEV)
+    nout = sum(k * c for _, k, _, c in reqs)
+    ids = torch.full((nout,), -7, dtype=torch.int32, device=DEV)
+    sc = torch.zeros((nout,), dtype=torch.float32, device=DEV)
+    cnt = torch.zeros((len(Q), 2), dtype=torch.int32, device=DEV)
+    batch.step(reqs, Qd, ids, sc, cnt)
+    torch.cuda.synchronize()
+    ids = ids.cpu().numpy().view(np.uint32).astype(np.int64)
+    sc = sc.cpu().numpy()
+    cnt = cnt.cpu().numpy()
+    hits_gpu = hits_orc = total = 0
+    q0 = o0 = 0
+    for (s, k, L, c) in reqs:
+        d = subs[s]
+        codes, delta, lo = olvq.encode(d["Y"], d["mu"], d["wl"].bits)
+        oidx = osearch.Index(d["adj"], d["entry"], codes, delta, lo, d["mu"],
+                             d["X"].astype(np.float16))
+        Qp = torch.empty((c, d["wl"].d), dtype=torch.float32, device=DEV)
+        lv.lv_project(Qd[q0:q0 + c], d["Pb"], Qp)
+        torch.cuda.synchronize()
+        Qp = Qp.cpu().numpy()
+        w_ids, w_sc, w_cnt = osearch.search_many(oidx, Q[q0:q0 + c], Qp, k, L)
+        g_ids = ids[o0:o0 + c * k].reshape(c, k)
+        g_sc = sc[o0:o0 + c * k].reshape(c, k)
+        assert np.array_equal(g_ids, w_ids), (s, k, L, c)
+        assert np.all(np.abs(g_sc - w_sc) <= 1e-4 * np.maximum(np.abs(w_sc), 1.0)), (s, k)
+        assert np.array_equal(cnt[q0:q0 + c], w_cnt), (s, k)
+        # recall: the oracle with its own float64 projection
+        o_ids, _, _ = osearch.search_many(oidx, Q[q0:q0 + c],
+                                          ofit.project(Q[q0:q0 + c], d["P"]).astype(np.float32),
+                                          k, L)
+        tr = d["truth"][:c, :k]
+        hits_gpu += sum(len(set(a) & set(b)) for a, b in zip(g_ids.tolist(), tr.tolist()))
+        hits_orc += sum(len(set(a) & set(b)) for a, b in zip(o_ids.tolist(), tr.tolist()))
+        total += c * k
+        q0 += c
+        o0 += c * k
+    r_gpu, r_orc = hits_gpu / total, hits_orc / total
+    print(f"batched step recall {r_gpu:.4f}, oracle {r_orc:.4f} over {len(reqs)} requests")
+    assert abs(r_gpu - r_orc) <= 0.005
     batch.close()
     multi.close()
