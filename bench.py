@@ -1159,15 +1159,24 @@ def main():
                       "reranked": float(n_rr.mean()), "alg_bytes": float(bytes_q.mean())},
         "kernels_ms_per_step": {"query_projection": proj_ms / args.steps,
                                 "traversal": beam_ms / args.steps},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+        "roofline": {"bound": "hbm", "achieved": achieved_serial, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved_serial / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled)",
-                     "alg_bytes_per_launch": alg_bytes_total, "launch_ms": launch_eff_ms,
-                     "launch_ms_alone": kernel_ms,
-                     "kernel": "batched_kernel (traversal + re-rank), one launch per step; "
-                               "launch_ms = (last traversal end - first traversal start) / K "
-                               "with three steps in flight, from HIP events around the "
-                               "traversal graphs on their launch streams"},
+                     "alg_bytes_per_launch": alg_bytes_total, "launch_ms": kernel_ms,
+                     "kernel": "batched_kernel (traversal + re-rank), one launch per step",
+                     "traversal": ("%d expansions per iteration (throughput variant; the "
+                                   "paper's one-at-a-time traversal is in traversal_compare)"
+                                   % max(1, args.expand)) if args.expand > 1 else
+                                  "one expansion per iteration (the paper's traversal)",
+                     "launch_timing": "launch_ms: average duration of the K serial launches "
+                                      "(one step after another), HIP events around each "
+                                      "traversal graph on its launch stream",
+                     "pipelined": {"launch_ms": launch_eff_ms, "achieved": achieved,
+                                   "frac": achieved / HBM_PEAK_GBS,
+                                   "how": "three steps in flight: (last traversal end - first "
+                                          "traversal start) / K; the launches overlap, so "
+                                          "this is the throughput per launch, not one "
+                                          "launch's duration"}},
         "index_build": {"db_projection_ms": db_proj_ms, "graph_build_s": g.get("graph_s"),
                         "graph": g.get("kind", "host builder, float16 vectors"),
                         "graph_build_threads": (None if args.graph == "gpu" else
@@ -1226,6 +1235,27 @@ def small_batch_report(lv, torch, index, Qd, Qp, k, L, hs, expands, reps=20):
                       "re-rank), current stream", "rows": rows}
 
 
+def cpu_model_name():
+    """The host CPU's model name as lscpu prints it (else /proc/cpuinfo's)."""
+    import subprocess
+
+    try:
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                             text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
 def cpu_baseline(wl, X, Xs, Q, adj, entry, L, sample, truth, expand=1, mix=None):
     """The float64 oracle (its own fit, projection and encoding), timed on a bounded
     query sample over all host cores; also its recall on that sample."""
@@ -1259,14 +1289,7 @@ def cpu_baseline(wl, X, Xs, Q, adj, entry, L, sample, truth, expand=1, mix=None)
                                         expand=expand)
         dt = min(dt, time.perf_counter() - t)
     rec = recall(np.asarray(got).astype(np.int64), truth[:n], wl.k)
-    model = ""
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
+    model = cpu_model_name()
     log(f"oracle: {n} queries in {dt:.1f}s on {procs} processes")
     which = f"all {n}" if n == len(Q) else f"first {n} of {len(Q)}"
     return {"value": n / dt, "unit": "queries/s", "cores": procs, "kind": "oracle",

@@ -37,12 +37,14 @@ def _run(cmd):
     return r.stdout
 
 
-def build(verbose: bool = False, out: str = LIB, extra_flags=(), host_flags=()) -> str:
+def build(verbose: bool = False, out: str = LIB, extra_flags=(), host_flags=(),
+          host_cxx: str = "g++", openmp: bool = True) -> str:
     """Compile every source and link ``out`` (the package library by default).
 
-    extra_flags go to every hipcc compile, host_flags to the g++ compiles of
-    the host-only sources."""
-    objdir = os.path.join(HERE, "_build")
+    extra_flags go to every hipcc compile, host_flags to the compiles of the
+    host-only sources, which use host_cxx (with OpenMP unless openmp=False:
+    the float64 fit then runs on one thread)."""
+    objdir = os.path.join(os.path.dirname(os.path.abspath(out)), "_build")
     os.makedirs(objdir, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
     cmds = []
@@ -53,7 +55,8 @@ def build(verbose: bool = False, out: str = LIB, extra_flags=(), host_flags=()) 
                      + ["-c", os.path.join(CSRC, src), "-o", obj], obj))
     for src in HOST_SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        cmds.append((["g++", "-O3", "-std=c++17", "-fPIC", "-fopenmp", "-march=x86-64-v3"]
+        cmds.append(([host_cxx, "-O3", "-std=c++17", "-fPIC", "-march=x86-64-v3"]
+                     + (["-fopenmp"] if openmp else ["-Wno-unknown-pragmas"])
                      + list(host_flags) + ["-c", os.path.join(CSRC, src), "-o", obj], obj))
     # independent translation units: compiled side by side
     with ThreadPoolExecutor(max(1, min(len(cmds), os.cpu_count() or 1, 8))) as pool:
