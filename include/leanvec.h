@@ -318,6 +318,24 @@ int lv_search_projected(const lv_index *index, const float *Q, const float *Qp, 
                         int32_t k, int32_t L, uint32_t *ids, float *scores, uint32_t *counters,
                         const lv_search_params *params, void *stream);
 
+/*
+ * lv_search without a workspace, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that
+ * forbid allocation).  It allocates nothing: the projected queries, which
+ * lv_search keeps in the caller's workspace, go to a fixed array of
+ * LV_NOALLOC_SCRATCH_BYTES (16 MiB) that the library holds on each device it
+ * runs on until the process ends, so m * (d, or D with LV_F16_RESID) * 4
+ * bytes must fit in it (about 26,000 queries at d = 160); larger m is
+ * refused with LV_EINVAL before anything is launched.  All calls on one
+ * device share its array: calls that overlap on a device race (serialise
+ * them, e.g. on one stream).  Arguments, results and other errors as for
+ * lv_search; the results are identical to lv_search's.
+ */
+#define LV_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+int lv_search_noalloc(const lv_index *index, const float *Q, int64_t m, int32_t k, int32_t L,
+                      uint32_t *ids, float *scores, uint32_t *counters,
+                      const lv_search_params *params, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched search over several indexes (device, persistent kernel).
  *

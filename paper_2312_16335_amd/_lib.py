@@ -99,6 +99,8 @@ _SIGS = {
                            ctypes.POINTER(SearchParams), _vp]),
     "lv_search_projected": (_c_i32, [_vp, _vp, _vp, _c_i64, _c_i32, _c_i32, _vp, _vp, _vp,
                                      ctypes.POINTER(SearchParams), _vp]),
+    "lv_search_noalloc": (_c_i32, [_vp, _vp, _c_i64, _c_i32, _c_i32, _vp, _vp, _vp,
+                                   ctypes.POINTER(SearchParams), _vp]),
     "lv_multi_create": (_c_i32, [ctypes.POINTER(_vp), _c_i32, ctypes.POINTER(_vp)]),
     "lv_multi_destroy": (_c_i32, [_vp]),
     "lv_batch_create": (_c_i32, [_vp, ctypes.POINTER(BatchCaps), ctypes.POINTER(SearchParams),
@@ -450,6 +452,25 @@ def lv_search(index: Index, Q, k: int, L: int, ids, scores, counters=None, ws=No
                             _dev(ids, torch.int32), _dev(scores, torch.float32),
                             _dev(counters, torch.int32), _dev(ws), ws_bytes,
                             _params(hash_slots, probes, launch, expand), _stream(stream)))
+
+
+LV_NOALLOC_SCRATCH_BYTES = 16 << 20
+
+
+def lv_search_noalloc(index: Index, Q, k: int, L: int, ids, scores, counters=None,
+                      hash_slots: int = 0, stream=None, probes: int = 0, expand: int = 0,
+                      launch: int = LV_LAUNCH_PER_QUERY) -> None:
+    """lv_search with the library's fixed scratch array instead of a workspace
+    (allocates nothing; at most LV_NOALLOC_SCRATCH_BYTES of projected queries)."""
+    import torch
+
+    m = _rows_cols(Q, "Q", cols=index.D)[0]
+    _search_outputs(m, k, ids, scores, counters)
+    _check(load().lv_search_noalloc(index.handle, _dev(Q, torch.float32), m, k, L,
+                                    _dev(ids, torch.int32), _dev(scores, torch.float32),
+                                    _dev(counters, torch.int32),
+                                    _params(hash_slots, probes, launch, expand),
+                                    _stream(stream)))
 
 
 def lv_search_projected(index: Index, Q, Qp, k: int, L: int, ids, scores, counters=None,

@@ -21,7 +21,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HIP_SOURCES = ["lv_api.cpp", "lv_batch.cpp", "lv_search.hip", "lv_graph.hip", "lv_lvq.hip",
-               "lv_project.hip", "lv_gemm.hip", "lv_projloss.hip"]
+               "lv_project.hip", "lv_gemm.hip", "lv_projloss.hip", "lv_noalloc.hip"]
 HOST_SOURCES = ["lv_fit.cpp", "lv_error.cpp"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
