@@ -39,12 +39,6 @@ int validate_desc(const lv_index_desc *d, lv_index *ix) {
       LV_FAIL(LV_EUNSUPPORTED, "record_stride %d unsupported (use lv_record_stride)",
               d->record_stride);
   }
-  // 8-bit records of up to four 64-byte chunks of codes are scored on the
-  // matrix cores (group 0; vbytes = chunks)
-  if (d->bits == 8 && d->d <= 256) {
-    group = 0;
-    vbytes = (d->d + 63) / 64;
-  }
   const int64_t row_bytes = lv_secondary_row_bytes(resid ? d->D - d->d : d->D, d->sec_dtype);
   if (row_bytes == 0)
     LV_FAIL(LV_EUNSUPPORTED, "secondary rows of D = %d and type %d are not supported", d->D,

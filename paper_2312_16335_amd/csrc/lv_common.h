@@ -35,8 +35,8 @@ constexpr uint32_t kSentinel = LV_SENTINEL;
 struct lv_index {
   lv_index_desc desc;
   int32_t code_bytes;  // d * bits / 8
-  int32_t group;       // lanes cooperating on one primary record (0: matrix-core scoring)
-  int32_t vbytes;      // bytes each of those lanes loads (matrix cores: 64-byte chunks)
+  int32_t group;       // lanes cooperating on one primary record
+  int32_t vbytes;      // bytes each of those lanes loads
   int32_t sec_packets; // 16-byte packets per secondary row
   int32_t qp_width;    // projected query floats: d, or D with LV_F16_RESID (P q, then P_perp q)
 };

@@ -14,16 +14,11 @@
 //     window earlier was worse than L others and the L-th score never
 //     decreases, so the final window is the same as with an exact set;
 //   * per expansion the adjacency row is read with one 4-byte id per lane,
-//     unvisited ids are compacted with a ballot, and the fresh records are
-//     scored as s(n) = delta_n * sum_j q'_j c_nj + lo_n * sum_j q'_j + <q', mu>,
-//     which equals <q', y^_n> for the LVQ reconstruction y^_n.  With 8-bit
-//     codes and d <= 256 the inner products sum_j q'_j c_nj of 16 records at
-//     a time are one exact integer product on the matrix cores (see
-//     score_batch_mf): the query is written in fixed point as eight 7-bit
-//     limbs, the codes are the other operand, and the eight integer limb
-//     sums are combined in float64.  Otherwise groups of G lanes each gather
-//     one record (G lanes x V bytes) and dequantise-and-dot it in float64
-//     against the projected query held in registers;
+//     unvisited ids are compacted with a ballot, and groups of G lanes each
+//     gather one primary record (G lanes x V bytes, one load per lane) and
+//     dequantise-and-dot it against the projected query held in registers:
+//     s(n) = delta_n * sum_j q'_j c_nj + lo_n * sum_j q'_j + <q', mu>, which
+//     equals <q', y^_n> for the LVQ reconstruction y^_n;
 //   * the batch is sorted across lanes (bitonic), merged with the window by
 //     binary search, duplicates dropped, and the window truncated to L;
 //   * while a hop is processed, the adjacency row of the runner-up
@@ -321,137 +316,6 @@ __device__ __forceinline__ void score_batch(const IndexView &ix, const float (&q
         } else {
           cs[c] = delta * acc + lo * sq + cq;
         }
-      }
-    }
-  }
-}
-
-typedef int v4i __attribute__((ext_vector_type(4)));
-
-// Query operand of the matrix-core scoring for records of NCH 64-byte chunks
-// of 8-bit codes.  The projected query is written in fixed point,
-// x_j = q'_j 2^F, F chosen so that |x_j| < 2^55 (components down to 2^-32 of
-// the largest magnitude are exact, smaller ones lose bits below 2^-F), as
-// eight 7-bit limbs
-//   x_j = t_0j 2^49 + t_1j 2^42 + ... + t_7j,  t_0 in [-64, 63], t_k in [0, 127].
-// Lane (i = lane % 16, g = lane / 16) holds, for chunk c, the bytes t_ij of
-// the 16 components 64 c + 16 g + [0, 16) (rows i >= 8 are zero): the A
-// operand of V_MFMA_I32_16X16X64_I8 whose rows are limbs.
-template <int NCH>
-struct MfQuery {
-  v4i a[NCH];
-  double unscale;  // 2^-F
-};
-
-// Limb t_i (i < 8) of the fixed-point value x (an integer below 2^55 in
-// magnitude): every step is exact in float64.
-__device__ __forceinline__ int limb7(double x, int i) {
-  const int k = 7 - i;                            // digit position from the bottom
-  const double t = floor(x * exp2((double)(-7 * k)));
-  return k == 7 ? (int)t : (int)fma(-128.0, floor(t * 0x1p-7), t);
-}
-
-// Limbs of the projected query (plus sum_j q'_j and <q', mu> in float64).
-template <int NCH>
-__device__ __forceinline__ void mf_query(const IndexView &ix, const float *qp, int lane,
-                                         MfQuery<NCH> &mq, double &sq, double &cq) {
-  const int i = lane & 15, g = lane >> 4;
-  float amax = 0.f;
-  double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-  for (int c = 0; c < NCH; ++c)
-#pragma unroll
-    for (int p = 0; p < 16; ++p) {
-      const int j = 64 * c + 16 * g + p;
-      const float q = j < ix.d ? gp(qp)[j] : 0.f;
-      amax = fmaxf(amax, fabsf(q));
-      if (j < ix.d && i == 0) {  // one lane per component
-        s1 += (double)q;
-        s2 = fma((double)q, (double)gp(ix.mu)[j], s2);
-      }
-    }
-  // the four lanes with i == 0 hold the partial sums; every lane the maximum
-  sq = (lane_f64(s1, 0) + lane_f64(s1, 16)) + (lane_f64(s1, 32) + lane_f64(s1, 48));
-  cq = (lane_f64(s2, 0) + lane_f64(s2, 16)) + (lane_f64(s2, 32) + lane_f64(s2, 48));
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
-  int e = 0;
-  frexpf(amax, &e);                               // amax < 2^e
-  const int F = amax > 0.f ? 55 - e : 0;
-  const double scale = ldexp(1.0, F);
-  mq.unscale = ldexp(1.0, -F);
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) {
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int p = 0; p < 16; ++p) {
-      const int j = 64 * c + 16 * g + p;
-      const float q = j < ix.d ? gp(qp)[j] : 0.f;
-      const int t = i < 8 ? limb7((double)q * scale, i) : 0;
-      w[p >> 2] |= ((uint32_t)t & 0xFFu) << (8 * (p & 3));
-    }
-    mq.a[c] = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
-  }
-}
-
-// Score the nc candidate ids in cid[] into cs[] on the matrix cores
-// (8-bit codes, d <= 64 NCH).  Sixteen records per product: lane
-// (j = lane % 16, g = lane / 16) loads bytes 64 c + 16 g + [0, 16) of record
-// j for every chunk c (the B operand: columns are records), codes are moved
-// to [-128, 127] by flipping their top bit (c - 128), and one
-// V_MFMA_I32_16X16X64_I8 per chunk accumulates S_ij = sum_k t_ik (c_jk - 128),
-// exact in int32 (|S| < 2^22).  Lane (g, j) then holds S_4g..4g+3 of record
-// j; with P_g = S_4g 2^21 + S_4g+1 2^14 + S_4g+2 2^7 + S_4g+3 (exact in
-// float64) the inner product is
-//   sum_k q'_k c_jk = 2^-F (P_0 2^28 + P_1) + 128 sum_k q'_k,
-// rounded twice in float64.  UG groups of 16 records are in flight.
-template <int NCH>
-__device__ __forceinline__ void score_batch_mf(const IndexView &ix, const MfQuery<NCH> &mq,
-                                               double sq, double cq, const uint32_t *cid,
-                                               double *cs, int nc, int lane) {
-  constexpr int UG = 2;
-  const int j = lane & 15, g = lane >> 4;
-  for (int base = 0; base < nc; base += 16 * UG) {
-    v4i rec[UG][NCH];
-    uint32_t dlw[UG], low[UG];
-#pragma unroll
-    for (int u = 0; u < UG; ++u) {
-      const int r = base + 16 * u + j;
-      const bool ok = r < nc;
-      const LV_GLOBAL unsigned char *p =
-          gp(ix.records) + (size_t)(ok ? cid[r] : 0u) * (size_t)ix.stride;
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const int off = 64 * c + 16 * g;  // below d: inside the record (stride >= 16 ceil(d/16))
-        rec[u][c] = v4i{0, 0, 0, 0};
-        if (ok && off < ix.d) rec[u][c] = *reinterpret_cast<const LV_GLOBAL v4i *>(p + off);
-      }
-      dlw[u] = low[u] = 0u;
-      if (ok && g == 0) {
-        const LV_GLOBAL uint32_t *cw =
-            reinterpret_cast<const LV_GLOBAL uint32_t *>(p + ix.code_bytes);
-        dlw[u] = cw[0];
-        low[u] = cw[1];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < UG; ++u) {
-      if (base + 16 * u >= nc) break;  // uniform: no record in this group
-      v4i acc = {0, 0, 0, 0};
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const v4i b = rec[u][c] ^ (int)0x80808080;
-        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(mq.a[c], b, acc, 0, 0, 0);
-      }
-      double P = (double)acc[0];
-      P = fma(P, 128.0, (double)acc[1]);
-      P = fma(P, 128.0, (double)acc[2]);
-      P = fma(P, 128.0, (double)acc[3]);
-      const double P1 = __shfl_down(P, 16, 64);  // limbs 4..7 of record j, from lane 16 + j
-      const int r = base + 16 * u + j;
-      if (g == 0 && r < nc) {
-        const double a = fma(fma(P, 0x1p28, P1), mq.unscale, 128.0 * sq);
-        cs[r] = (double)__uint_as_float(dlw[u]) * a + (double)__uint_as_float(low[u]) * sq + cq;
       }
     }
   }
@@ -779,31 +643,20 @@ __device__ __forceinline__ int *team_cmd(const Lds &sm, int hslots) {
 // publishes -2 - (window size), the workgroup re-ranks the window between
 // two barriers, and the other wavefronts return.  Every wavefront therefore
 // passes the same sequence of barriers.
-//
-// G == 0 selects the matrix-core scoring of 8-bit records with V 64-byte
-// chunks (score_batch_mf); team slices are then whole groups of 16 records.
 template <int BITS, int G, int V, bool BUILD = false, bool MULTI = false, int WQ = 1>
 __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm, int log2h,
                              int probes, int expand, int lane) {
   static_assert(WQ == 1 || (MULTI && !BUILD), "team search is the multi-expansion body");
-  constexpr bool MF = G == 0;
-  static_assert(!MF || (BITS == 8 && !BUILD && V >= 1 && V <= 4),
-                "matrix-core scoring: 8-bit records of at most 4 chunks, not construction");
-  constexpr int NQ = MF ? 1 : V * 8 / BITS;
-  constexpr int SG = MF ? 4 : G;  // lanes per record of a team slice (16 records per pass)
+  constexpr int NQ = V * 8 / BITS;
   const int L = job.L;
   const int hslots = 1 << log2h;
 
-  // projected query slice of this lane (float32, exact in float64 products);
-  // G == 0: the query's fixed-point limbs for the matrix-core scoring
-  const int gl = G ? lane % G : 0;
+  // projected query slice of this lane (float32, exact in float64 products)
+  const int gl = lane % G;
   float qv[NQ];
-  MfQuery<MF ? V : 1> mq;
   double sq = 0.0, cq = 0.0;
   BuildQ bq{};
-  if constexpr (MF) {
-    mf_query<V>(ix, job.qp, lane, mq, sq, cq);
-  } else if constexpr (BUILD) {
+  if constexpr (BUILD) {
     // the node's own codes (small integers, exact in float32 and float64)
     const LV_GLOBAL unsigned char *rec = gp(ix.records) + (size_t)job.node * (size_t)ix.stride;
     const Chunk<V> ch = load_chunk<V>(rec + gl * V);
@@ -837,15 +690,8 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
     sq = lane_f64(group_sum<G>(sq), 0);
     cq = lane_f64(group_sum<G>(cq), 0);
   }
-  // score candidates cid[0..n) into cs[0..n)
-  auto score = [&](const uint32_t *cid, double *cs, int n) {
-    if constexpr (MF)
-      score_batch_mf<V>(ix, mq, sq, cq, cid, cs, n, lane);
-    else
-      score_batch<BITS, G ? G : 16, V, BUILD>(ix, qv, sq, cq, bq, cid, cs, n, lane);
-  };
   if constexpr (WQ > 1) {
-    // slice of each batch: whole passes of 64 / SG records per wavefront
+    // slice of each batch: whole passes of 64 / G records per wavefront
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (wave != 0) {
       for (;;) {
@@ -859,9 +705,10 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
           __syncthreads();  // slices re-ranked
           return;
         }
-        const int off = team_slice<SG, WQ>(nc, wave);
-        const int cnt = team_slice<SG, WQ>(nc, wave + 1) - off;
-        score(sm.cid() + off, sm.cs() + off, cnt);
+        const int off = team_slice<G, WQ>(nc, wave);
+        const int cnt = team_slice<G, WQ>(nc, wave + 1) - off;
+        score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid() + off, sm.cs() + off, cnt,
+                                       lane);
         __syncthreads();  // scores written
       }
     }
@@ -875,7 +722,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
     hash_visit(sm.hash(), log2h, probes, ix.entry);
   }
   wave_sync();
-  score(sm.cid(), sm.cs(), 1);
+  score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), 1, lane);
   wave_sync();
   if (lane == 0) {
     sm.ls()[0] = sm.cs()[0];
@@ -942,10 +789,11 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
             if constexpr (WQ > 1) {
               if (lane == 0) *team_cmd(sm, hslots) = nc;
               __syncthreads();  // batch and count visible to the workgroup
-              score(sm.cid(), sm.cs(), team_slice<SG, WQ>(nc, 1));
+              score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(),
+                                             team_slice<G, WQ>(nc, 1), lane);
               __syncthreads();  // every slice scored
             } else {
-              score(sm.cid(), sm.cs(), nc);
+              score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), nc, lane);
             }
             wave_sync();
             n_dist += nc;
@@ -1017,7 +865,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
         if (nc == 0) continue;
         if (fresh) sm.cid()[lane_rank(fm)] = n;
         wave_sync();
-        score(sm.cid(), sm.cs(), nc);
+        score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), nc, lane);
         wave_sync();
         n_dist += nc;
 
@@ -1280,34 +1128,20 @@ int occupancy_t(size_t lds, bool multi, int *blocks) {
   return LV_OK;
 }
 
-// Dispatch on (bits, group, vbytes) to the matching template instance:
-// searches use the matrix-core scoring for 8-bit records of up to four
-// 64-byte chunks (group 0, vbytes = chunks) and lane groups otherwise;
-// construction searches use lane groups for every record layout.
-#define LV_CASE(B, GG, VV) \
-  if (bits == B && key == GG * 100 + VV) return f.template operator()<B, GG, VV>();
+// Dispatch on (bits, group, vbytes) to the matching template instance.
 template <class F>
 int dispatch(int bits, int group, int vbytes, F &&f) {
   const int key = group * 100 + vbytes;
-  LV_CASE(8, 0, 1) LV_CASE(8, 0, 2) LV_CASE(8, 0, 3) LV_CASE(8, 0, 4)
-  LV_CASE(8, 64, 8) LV_CASE(8, 64, 12) LV_CASE(8, 64, 16)
-  LV_CASE(4, 16, 4) LV_CASE(4, 8, 12) LV_CASE(4, 16, 8) LV_CASE(4, 16, 12) LV_CASE(4, 16, 16)
-  LV_CASE(4, 64, 8) LV_CASE(4, 64, 12) LV_CASE(4, 64, 16)
-  LV_FAIL(LV_EUNSUPPORTED, "no search kernel for %d-bit records of group %d x %d bytes", bits,
-          group, vbytes);
-}
-
-template <class F>
-int dispatch_build(int bits, int group, int vbytes, F &&f) {
-  const int key = group * 100 + vbytes;
+#define LV_CASE(B, GG, VV) \
+  if (bits == B && key == GG * 100 + VV) return f.template operator()<B, GG, VV>();
   LV_CASE(8, 16, 4) LV_CASE(8, 8, 12) LV_CASE(8, 16, 8) LV_CASE(8, 16, 12) LV_CASE(8, 16, 16)
   LV_CASE(8, 64, 8) LV_CASE(8, 64, 12) LV_CASE(8, 64, 16)
   LV_CASE(4, 16, 4) LV_CASE(4, 8, 12) LV_CASE(4, 16, 8) LV_CASE(4, 16, 12) LV_CASE(4, 16, 16)
   LV_CASE(4, 64, 8) LV_CASE(4, 64, 12) LV_CASE(4, 64, 16)
-  LV_FAIL(LV_EUNSUPPORTED, "no construction kernel for %d-bit records of group %d x %d bytes",
-          bits, group, vbytes);
-}
 #undef LV_CASE
+  LV_FAIL(LV_EUNSUPPORTED, "no search kernel for %d-bit records of group %d x %d bytes", bits,
+          group, vbytes);
+}
 
 struct PlainLaunch {
   const PlainArgs &a;
@@ -1458,7 +1292,7 @@ int launch_build_search(int bits, int group, int vbytes, const BuildSearchArgs &
   if (a.B <= 0) return LV_OK;
   const size_t lds = beam_lds_bytes(a.L, a.hash_log2);
   BuildLaunch f{a, lds, stream};
-  return dispatch_build(bits, group, vbytes, f);
+  return dispatch(bits, group, vbytes, f);
 }
 
 int batched_occupancy(int bits, int group, int vbytes, int Lmax, VisitedCfg vc, int *blocks) {
