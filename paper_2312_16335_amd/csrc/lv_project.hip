@@ -103,15 +103,101 @@ __device__ __forceinline__ void project_rows(const float *__restrict__ V, int64_
   }
 }
 
-// NT = number of 32-column output tiles handled by one wavefront.
+// Large row counts (the database projection): a workgroup of kRowWaves
+// wavefronts owns kRowWaves x 32 rows and NT x 32 columns from col0.  Per
+// K step of 32 the slab of M it needs (NT x 32 columns x 32 k, bfloat16) is
+// staged once in LDS for all its wavefronts (double-buffered, one barrier
+// per step) instead of every wavefront reading it from L2, and each
+// wavefront's next step of V is in flight while the current step's
+// products run.  Every output gets the same MFMA sequence as project_rows
+// (same operand slices, same order), so the result is bit-identical to the
+// query kernels'.
+constexpr int kRowWaves = 8;
+constexpr int kSlabPitch = 40;  // bfloat16 per LDS slab row: 32 k + 8 (bank spread)
+
 template <int NT>
-__global__ __launch_bounds__(256) void project_kernel(const float *__restrict__ V, int64_t rows,
-                                                      int32_t D, const uint16_t *__restrict__ M,
-                                                      int32_t d, int32_t col0,
-                                                      float *__restrict__ out) {
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+__global__ __launch_bounds__(64 * kRowWaves) void project_kernel(
+    const float *__restrict__ V, int64_t rows, int32_t D, const uint16_t *__restrict__ M,
+    int32_t d, int32_t col0, float *__restrict__ out) {
+  __shared__ __align__(16) uint16_t slab[2][NT * 32 * kSlabPitch];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int64_t row0 = ((int64_t)blockIdx.x * kRowWaves + (tid >> 6)) * 32;
+  const int r = lane & 31, kh = lane >> 5;
+  const int64_t arow = row0 + r;
+  const bool arow_ok = arow < rows;
+  const float *ap = V + (arow_ok ? arow : 0) * (int64_t)D;
+  constexpr int kPieces = NT * 32 * 4;  // 16-byte pieces of one slab (4 per column)
+  constexpr int kPer = (kPieces + 64 * kRowWaves - 1) / (64 * kRowWaves);  // per thread
+  // the slab of step k0 (columns past d and k past D are zero): global -> registers,
+  // then registers -> LDS buffer b
+  uint4 mreg[kPer];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int pc = tid + i * 64 * kRowWaves;
+      const int c = pc >> 2, part = pc & 3;
+      const int col = col0 + c, k = k0 + 8 * part;
+      mreg[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (pc < kPieces && col < d && k < D)
+        mreg[i] = *reinterpret_cast<const uint4 *>(M + (int64_t)col * D + k);
+    }
+  };
+  auto put = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int pc = tid + i * 64 * kRowWaves;
+      if (pc < kPieces)
+        *reinterpret_cast<uint4 *>(&slab[b][(pc >> 2) * kSlabPitch + 8 * (pc & 3)]) = mreg[i];
+    }
+  };
+  f32x16 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+  const int nsteps = (D + 31) / 32;
+  fetch(0);
+  put(0);
+  bf16x8 a0 = load_a(ap + 8 * kh, arow_ok && 8 * kh < D);
+  bf16x8 a1 = load_a(ap + 16 + 8 * kh, arow_ok && 16 + 8 * kh < D);
+  __syncthreads();
+  for (int s = 0; s < nsteps; ++s) {
+    const int k0 = 32 * s;
+    const bool more = s + 1 < nsteps;
+    bf16x8 n0 = a0, n1 = a1;
+    if (more) {  // next step's rows of V and slab of M in flight during this step's products
+      const int ka = k0 + 32 + 8 * kh, kb = k0 + 48 + 8 * kh;
+      n0 = load_a(ap + ka, arow_ok && ka < D);
+      n1 = load_a(ap + kb, arow_ok && kb < D);
+      fetch(k0 + 32);
+    }
+    const uint16_t *sb = slab[s & 1];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const uint16_t *bp = sb + (t * 32 + r) * kSlabPitch;
+      const bf16x8 b0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(bp + 8 * kh));
+      const bf16x8 b1 =
+          __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(bp + 16 + 8 * kh));
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[t], 0, 0, 0);
+    }
+    if (more) put((s + 1) & 1);  // that buffer was last read two steps ago
+    __syncthreads();
+    a0 = n0;
+    a1 = n1;
+  }
   if (row0 >= rows) return;
-  project_rows<NT>(V, row0, rows, D, M, d, col0, out, d, threadIdx.x & 63);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = col0 + t * 32 + r;
+    if (col >= d) continue;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int64_t row = row0 + 8 * (i >> 2) + 4 * kh + (i & 3);
+      if (row < rows) out[row * d + col] = acc[t][i];
+    }
+  }
 }
 
 // Few rows (query batches): one workgroup per 32-row tile and one wavefront
@@ -169,9 +255,9 @@ void col_layout(int32_t d, unsigned *waves, unsigned *yblocks) {
 template <int NT>
 void launch_nt(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32_t d, int32_t col0,
                float *out, hipStream_t s) {
-  const int64_t blocks = (rows + 127) / 128;
-  hipLaunchKernelGGL(project_kernel<NT>, dim3((unsigned)blocks), dim3(256), 0, s, V, rows, D, M,
-                     d, col0, out);
+  const int64_t blocks = (rows + 32 * kRowWaves - 1) / (32 * kRowWaves);
+  hipLaunchKernelGGL(project_kernel<NT>, dim3((unsigned)blocks), dim3(64 * kRowWaves), 0, s, V,
+                     rows, D, M, d, col0, out);
 }
 
 }  // namespace
@@ -190,7 +276,7 @@ int launch_project_grouped(const StepHeader *hdr, const IndexView *subs, int max
 int launch_project(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32_t d,
                    float *out, hipStream_t stream) {
   if (rows == 0) return LV_OK;
-  if ((rows + 127) / 128 > 0x7FFFFFFF) LV_FAIL(LV_EINVAL, "too many rows");
+  if ((rows + 255) / 256 > 0x7FFFFFFF) LV_FAIL(LV_EINVAL, "too many rows");
   if (rows <= kFewRows) {  // query batches: a wavefront per 32 x 32 output tile
     unsigned waves = 0, yblocks = 0;
     col_layout(d, &waves, &yblocks);
