@@ -453,17 +453,102 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
   }
 }
 
+// Secondary scores of float16 / float32 rows (KIND LV_F16, LV_F16_RESID or
+// LV_F32, as rerank_rows) two rows at a time: half wavefront h scores row
+// 2 i + h, lane l of the half holding 16-byte packets l, l + 32, ... (PPH
+// of them: rows of at most 32 PPH packets).  Every lane does useful work
+// for rows whose packet count is not a multiple of 64, a row in flight
+// costs 2 PPH registers instead of 8, so UP pairs (2 UP rows) are gathered
+// at once, and the two half sums share one reduction.
+template <int KIND, int PPH>
+__device__ __forceinline__ void rerank_pairs(const IndexView &ix, const float *q,
+                                             const uint32_t *ids, double *out, int nl,
+                                             int lane) {
+  constexpr bool F16 = KIND == LV_F16 || KIND == LV_F16_RESID;
+  constexpr int E = F16 ? 8 : 4;                          // elements per packet
+  constexpr int UP = PPH <= 2 ? 4 : 2;  // pairs in flight
+  const int dim = KIND == LV_F16_RESID ? ix.D - ix.d : ix.D;
+  const int h = lane >> 5, hl = lane & 31;
+  float qq[PPH][E];
+#pragma unroll
+  for (int pk = 0; pk < PPH; ++pk) {
+    const int packet = hl + 32 * pk;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = packet * E + e;
+      qq[pk][e] = packet < ix.sec_packets && j < dim ? gp(q)[j] : 0.f;
+    }
+  }
+  for (int base = 0; base < nl; base += 2 * UP) {
+    u32x4 v[UP][PPH];
+#pragma unroll
+    for (int u = 0; u < UP; ++u) {
+      const int idx = base + 2 * u + h;
+      const uint32_t id = idx < nl ? (ids[idx] & kIdMask) : 0u;
+      const LV_GLOBAL unsigned char *row = gp(ix.sec) + (size_t)id * (size_t)ix.sec_row_bytes;
+#pragma unroll
+      for (int pk = 0; pk < PPH; ++pk) {
+        const int packet = hl + 32 * pk;
+        if (idx < nl && packet < ix.sec_packets)
+          v[u][pk] = *reinterpret_cast<const LV_GLOBAL u32x4 *>(row + (size_t)packet * 16);
+        else
+          v[u][pk] = u32x4{0u, 0u, 0u, 0u};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UP; ++u) {
+      if (base + 2 * u >= nl) break;  // uniform: no row left
+      double acc = 0.0;
+#pragma unroll
+      for (int pk = 0; pk < PPH; ++pk) {
+        const uint32_t w[4] = {v[u][pk][0], v[u][pk][1], v[u][pk][2], v[u][pk][3]};
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          double x;
+          if constexpr (F16)
+            x = (double)(float)__builtin_bit_cast(_Float16, (uint16_t)(w[e >> 1] >> (16 * (e & 1))));
+          else
+            x = (double)__uint_as_float(w[e]);
+          acc = fma(x, (double)qq[pk][e], acc);
+        }
+      }
+      // row sums, then rows 0 + 1 and 2 + 3: the half sums land in lanes 31, 63
+      acc = group_sum<16>(acc);
+      acc += dpp_f64<kDppRowBcast15, 0xA>(acc);
+      const int idx = base + 2 * u + h;
+      if (hl == 31 && idx < nl) {
+        if constexpr (KIND == LV_F16_RESID)
+          out[idx] += acc;
+        else
+          out[idx] = acc;
+      }
+    }
+  }
+}
+
+// Rows of 65..96 packets (float16 rows of 513..768 components, float32 rows
+// of 257..384) are scored in pairs; other rows one at a time.
+template <int KIND>
+__device__ __forceinline__ void rerank_pairs_any(const IndexView &ix, const float *q,
+                                                 const uint32_t *ids, double *out, int n,
+                                                 int lane) {
+  if (ix.sec_packets > 64 && ix.sec_packets <= 96)  // uniform
+    rerank_pairs<KIND, 3>(ix, q, ids, out, n, lane);
+  else
+    rerank_rows<KIND>(ix, q, ids, out, n, lane);
+}
+
 // Re-rank entries [0, n) of ids/out with the index's kind of secondaries.
 __device__ __forceinline__ void rerank_any(const IndexView &ix, const float *q,
                                            const uint32_t *ids, double *out, int n, int lane) {
   if (ix.sec_kind == LV_F16)
-    rerank_rows<LV_F16>(ix, q, ids, out, n, lane);
+    rerank_pairs_any<LV_F16>(ix, q, ids, out, n, lane);
   else if (ix.sec_kind == LV_LVQ8)
     rerank_rows<LV_LVQ8>(ix, q, ids, out, n, lane);
   else if (ix.sec_kind == LV_F16_RESID)
-    rerank_rows<LV_F16_RESID>(ix, q, ids, out, n, lane);
+    rerank_pairs_any<LV_F16_RESID>(ix, q, ids, out, n, lane);
   else
-    rerank_rows<LV_F32>(ix, q, ids, out, n, lane);
+    rerank_pairs_any<LV_F32>(ix, q, ids, out, n, lane);
 }
 
 // Merge the scored batch (cid/cs[0..nc)) into the window of nl <= L
@@ -894,14 +979,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
     rerank_any(ix, job.q, id2, s2, team_slice<16, WQ>(nl, 1), lane);
     __syncthreads();  // every slice re-ranked
   } else {
-    if (ix.sec_kind == LV_F16)
-      rerank_rows<LV_F16>(ix, job.q, id2, s2, nl, lane);
-    else if (ix.sec_kind == LV_LVQ8)
-      rerank_rows<LV_LVQ8>(ix, job.q, id2, s2, nl, lane);
-    else if (ix.sec_kind == LV_F16_RESID)
-      rerank_rows<LV_F16_RESID>(ix, job.q, id2, s2, nl, lane);
-    else
-      rerank_rows<LV_F32>(ix, job.q, id2, s2, nl, lane);
+    rerank_any(ix, job.q, id2, s2, nl, lane);
   }
   wave_sync();
   for (int j = lane; j < nl; j += 64) id2[j] &= kIdMask;
