@@ -3,7 +3,7 @@
 Follows Section 2 ("Search"): primary vectors quant(Bx) drive the graph
 traversal with the approximation <q, x> ~ <Aq, quant(Bx)> (Eq. 1); more than
 k candidates are kept and their inner products are recomputed with the
-secondary vectors, whose top-k is returned.  Appendix C names the traversal
+secondary vectors, whose top-k is returned.  Appendix D names the traversal
 "greedy traversal with backtracking"; the reading used here is the
 best-first beam with window L:
 
@@ -50,6 +50,8 @@ class Index:
     sec_lo: Optional[np.ndarray] = None      # float32 [N]  secondary vectors compressed
     sec_mu: Optional[np.ndarray] = None      # float32 [D]  with LVQ-8)
     sec_resid: bool = False  # sec holds only the D - d residual coordinates (see below)
+    sec_two_level: bool = False  # sec holds the 8-bit second level of the primaries
+                                 # (uint8 [N, d] codes, sec_delta / sec_lo; see below)
 
     @property
     def N(self) -> int:
@@ -98,6 +100,8 @@ def secondary_scores(index: Index, q64: np.ndarray, ids, qp64=None) -> np.ndarra
     ids = np.asarray(ids, dtype=np.int64)
     if index.sec_resid:
         return primary_scores(index, qp64, ids) + rowdot(index.sec[ids], q64)
+    if index.sec_two_level:
+        return two_level_scores(index, qp64, ids)
     if index.sec_delta is None:
         return rowdot(index.sec[ids], q64)
     xhat = (index.sec_mu.astype(np.float64)[None, :]
@@ -105,6 +109,20 @@ def secondary_scores(index: Index, q64: np.ndarray, ids, qp64=None) -> np.ndarra
             + index.sec_delta[ids].astype(np.float64)[:, None]
             * index.sec[ids].astype(np.float64))
     return rowdot(xhat, q64)
+
+
+def two_level_scores(index: Index, qp64: np.ndarray, ids) -> np.ndarray:
+    """Re-ranking with a two-level LVQ of the primaries (LVQ4x8 of the
+    baseline setup, Appendix D and Fig. 1: the first level drives the search,
+    the 8-bit second level refines the same reduced vector for the
+    re-ranking): <q', y^_n + r^_n> with r^_n = lo2 + delta2 * c2 the second
+    level's reconstruction, taken as the primary score plus <q', r^_n>.  The
+    query is the projected one; no full-dimension vector is read."""
+    ids = np.asarray(ids, dtype=np.int64)
+    r = (index.sec_lo[ids].astype(np.float64)[:, None]
+         + index.sec_delta[ids].astype(np.float64)[:, None]
+         * index.sec[ids].astype(np.float64))
+    return primary_scores(index, qp64, ids) + rowdot(r, qp64)
 
 
 @dataclass
@@ -191,7 +209,8 @@ def beam(index: Index, qp, L: int, visited_cap: Optional[int] = None,
 
 def rerank(index: Index, q, cand_ids, k: int, qp=None) -> Tuple[np.ndarray, np.ndarray]:
     """Top-k of the candidates by secondary score (ties: smaller id).  With
-    residual secondaries q is the residual query and qp the primary one."""
+    residual secondaries q is the residual query and qp the primary one; with
+    two-level secondaries only qp is read."""
     q64 = np.asarray(q, dtype=np.float32).astype(np.float64)
     qp64 = None if qp is None else np.asarray(qp, dtype=np.float32).astype(np.float64)
     ids = np.asarray(cand_ids, dtype=np.int64)
@@ -228,11 +247,11 @@ def flat_search(index: Index, q, qp, k: int, L: int):
 _G = {}
 
 
-def _init_worker(paths, entry, sec_resid=False):
+def _init_worker(paths, entry, sec_resid=False, sec_two_level=False):
     arrs = {k: np.load(v, mmap_mode="r") for k, v in paths.items()}
     _G["index"] = Index(arrs["adj"], entry, arrs["codes"], arrs["delta"], arrs["lo"],
                         arrs["mu"], arrs["sec"], arrs.get("sec_delta"), arrs.get("sec_lo"),
-                        arrs.get("sec_mu"), sec_resid)
+                        arrs.get("sec_mu"), sec_resid, sec_two_level)
 
 
 def _run_chunk(args):
@@ -268,8 +287,7 @@ def search_many(index: Index, Q, Qp, k: int, L: int, procs: int = 1,
     wd = workdir or tempfile.mkdtemp(prefix="lv_oracle_")
     paths = {}
     names = ["adj", "codes", "delta", "lo", "mu", "sec"]
-    if index.sec_delta is not None:
-        names += ["sec_delta", "sec_lo", "sec_mu"]
+    names += [n for n in ("sec_delta", "sec_lo", "sec_mu") if getattr(index, n) is not None]
     for name in names:
         arr = getattr(index, name)
         p = os.path.join(wd, name + ".npy")
@@ -282,8 +300,8 @@ def search_many(index: Index, Q, Qp, k: int, L: int, procs: int = 1,
         # a worker that dies raises BrokenProcessPool here instead of hanging
         with ProcessPoolExecutor(procs, mp_context=mp.get_context("spawn"),
                                  initializer=_init_worker,
-                                 initargs=(paths, int(index.entry),
-                                           bool(index.sec_resid))) as pool:
+                                 initargs=(paths, int(index.entry), bool(index.sec_resid),
+                                           bool(index.sec_two_level))) as pool:
             jobs = [(Q[lo:lo + chunk], Qp[lo:lo + chunk], k, L, lo, expand)
                     for lo in range(0, m, chunk)]
             for lo, a, b, c in pool.map(_run_chunk, jobs):

@@ -257,3 +257,61 @@ def test_residual_secondaries_full_window_equals_brute_force(tiny):
                                     qp.astype(np.float64))
         want = np.lexsort((np.arange(ridx.N), -s))[:wl.k]
         assert ids.tolist() == want.tolist()
+
+
+def _two_level_index(tiny, bits):
+    """The tiny workload with primaries of `bits` bits and their 8-bit second
+    level as the re-ranking representation."""
+    wl, idx, Q, Qp = tiny
+    mix = gen.mixture(wl)
+    X = gen.database(wl, mix)
+    P = ofit.fit_id(ofit.second_moment(X), wl.d)
+    Y = ofit.project(X, P).astype(np.float32)
+    mu = idx.mu
+    codes, delta, lo = lvq.encode(Y, mu, bits)
+    c2, d2, l2 = lvq.encode_residual(Y, mu, codes, delta, lo)
+    tidx = search.Index(idx.adj, idx.entry, codes, delta, lo, mu, c2, d2, l2,
+                        sec_two_level=True)
+    return tidx, Y, mu
+
+
+@pytest.mark.parametrize("bits", [4, 8])
+def test_two_level_full_window_equals_brute_force(tiny, bits):
+    """With L >= N the re-rank returns the exact top-k of <q', y^> over the
+    two-level reconstructions (brute force with a full sort), and its scores
+    are those inner products."""
+    wl, _, Q, Qp = tiny
+    tidx, Y, mu = _two_level_index(tiny, bits)
+    yhat = lvq.decode_two_level(tidx.codes, tidx.delta, tidx.lo, tidx.sec, tidx.sec_delta,
+                                tidx.sec_lo, mu)
+    for i in range(3):
+        S = yhat @ Qp[i].astype(np.float64)
+        ids, sc = search.search_one(tidx, None, Qp[i], wl.k, tidx.N)
+        order = np.lexsort((np.arange(tidx.N), -S))[:wl.k]
+        assert ids.tolist() == order.tolist()
+        assert np.allclose(sc, S[order], rtol=0, atol=1e-9)
+
+
+def test_two_level_scores_closer_to_the_reduced_inner_product(tiny):
+    """The second level shrinks the score error against <q', y> to at most
+    sum |q'_j| * delta2 / 2 (plus rounding), far below the first level's."""
+    wl, _, Q, Qp = tiny
+    tidx, Y, mu = _two_level_index(tiny, 4)
+    ids = np.arange(300)
+    qp = Qp[0].astype(np.float64)
+    want = Y[ids].astype(np.float64) @ qp
+    two = search.two_level_scores(tidx, qp, ids)
+    one = search.primary_scores(tidx, qp, ids)
+    bound = (tidx.sec_delta[ids].astype(np.float64) / 2 + 1e-6 * tidx.delta[ids]) \
+        * np.abs(qp).sum()
+    assert np.all(np.abs(two - want) <= bound + 1e-9)
+    assert np.abs(two - want).max() < np.abs(one - want).max() / 20
+
+
+def test_two_level_parallel_matches_serial(tiny):
+    wl, _, Q, Qp = tiny
+    tidx, _, _ = _two_level_index(tiny, 4)
+    a = search.search_many(tidx, Q, Qp, wl.k, 24, procs=1)
+    b = search.search_many(tidx, Q, Qp, wl.k, 24, procs=2, chunk=3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
