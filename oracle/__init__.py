@@ -15,7 +15,7 @@ Modules (each function cites the passage of the paper it follows):
                   the Frank-Wolfe block coordinate descent (Algorithm 1) and
                   the eigenvector search (Section 2.4, Algorithm 2).
 * ``search``   -- greedy graph traversal on primary vectors and re-ranking
-                  with secondary vectors (Section 2 "Search", Appendix C).
+                  with secondary vectors (Section 2 "Search", Appendix D).
 * ``projloss`` -- sampled-pair refinement loss and its gradients, built from
                   the LeanVec-OOD objective (Problem leanvec_orthonormal).
 

@@ -5,7 +5,7 @@ Appendix A describes graph construction as an update run for every node x:
 search the current graph with x as the query for a candidate set larger
 than R, prune that set to at most R diverse out-neighbours, and make them
 x's out-edges.  Section 2 ("Graph construction") fixes the data: only the
-primary vectors quant(Bx) take part.  Appendix C names Vamana with its
+primary vectors quant(Bx) take part.  Appendix D names Vamana with its
 pruning factor alpha.  Reading used here (Vamana with batch-synchronous
 insertion, so that a parallel build has one defined result):
 

@@ -3,7 +3,7 @@
 // Appendix A: per node, search the current graph with the node as the query
 // for more than R candidates, prune them to at most R diverse out-neighbours
 // and make those the node's out-edges.  Section 2 ("Graph construction"):
-// only the primary vectors take part.  Appendix C: Vamana, pruning factor
+// only the primary vectors take part.  Appendix D: Vamana, pruning factor
 // alpha.  Distances are the squared Euclidean distances of the LVQ
 // reconstructions (lv_l2.h).
 //
