@@ -50,6 +50,7 @@ extern "C" {
 #define LV_F16 1
 #define LV_LVQ8 2 /* secondary vectors compressed with LVQ-8 */
 #define LV_F16_RESID 3 /* float16 residual coordinates: only D - d per vector (see below) */
+#define LV_LVQ8_LEVEL2 4 /* 8-bit second level of the primaries' LVQ: d per vector (see below) */
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int lv_version(void);
@@ -201,6 +202,26 @@ int32_t lv_record_stride(int32_t d, int32_t bits);
 int lv_lvq_encode(const float *Y, int64_t n, int32_t d, const float *mu, int32_t bits,
                   void *records, int32_t record_stride, void *stream);
 
+/*
+ * Second level of a two-level LVQ (LV_LVQ8_LEVEL2 rows; the scheme LVQ4x8
+ * of the LVQ baseline in Appendix D and Fig. 1, which the paper names
+ * without restating): for every vector, the residual of its primary record
+ * r2_j = (y_j - mu_j) - (lo + delta c_j) in float64 (in this order; delta c_j
+ * is exact), then l2 = min r2, u2 = max r2, delta2 = float32((u2 - l2) / 255),
+ * lo2 = float32(l2), c2_j = clamp(floor((r2_j - lo2) / delta2 + 0.5), 0, 255)
+ * (all zero when delta2 = 0).  Row layout: see lv_secondary_row_bytes.
+ * Results are bit-exact (IEEE float64 division and floor, no contraction).
+ *   Y, mu, bits: as given to lv_lvq_encode for the records
+ *   records: device [n][record_stride] bytes, the vectors' primary records
+ *   rows:    device [n][row_bytes] bytes out; row_bytes must equal
+ *            lv_secondary_row_bytes(d, LV_LVQ8_LEVEL2)
+ * Errors: LV_EINVAL as for lv_lvq_encode, for d > 1008, a row_bytes other
+ *         than that, or NULL pointers with n > 0.
+ */
+int lv_lvq_encode_level2(const float *Y, int64_t n, int32_t d, const float *mu, int32_t bits,
+                         const void *records, int32_t record_stride, void *rows,
+                         int32_t row_bytes, void *stream);
+
 /* Secondary vectors (Section 2: quant(x), here float16): float32 -> float16,
  * round to nearest even.  X: device float32 [count]; out: device [count]. */
 int lv_to_f16(const float *X, int64_t count, uint16_t *out, void *stream);
@@ -219,9 +240,10 @@ typedef struct {
   int32_t record_stride;   /* bytes per primary record (lv_record_stride) */
   const void *records;     /* [N][record_stride] LVQ records */
   const float *mu;         /* [d] LVQ centring vector */
-  int32_t sec_dtype;       /* LV_F32, LV_F16, LV_LVQ8 or LV_F16_RESID */
+  int32_t sec_dtype;       /* LV_F32, LV_F16, LV_LVQ8, LV_F16_RESID or LV_LVQ8_LEVEL2 */
   const void *secondaries; /* [N][lv_secondary_row_bytes(D, sec_dtype)] bytes
-                              (D - d in place of D for LV_F16_RESID) */
+                              (D - d in place of D for LV_F16_RESID, d for
+                              LV_LVQ8_LEVEL2) */
   int32_t R;               /* graph out-degree, 1..1024 */
   const uint32_t *adjacency; /* [N][R]; valid ids first, then LV_SENTINEL */
   uint32_t entry;          /* traversal start node */
@@ -246,6 +268,18 @@ typedef struct {
  * A secondary row holds P_perp x in float16 (2 (D - d) bytes: pass D - d here),
  * and the re-rank score is the traversal's primary score <P q, y^> plus
  * <P_perp q, P_perp x>, so the first d coordinates are not stored twice.
+ *
+ * LV_LVQ8_LEVEL2 (two-level LVQ of the primaries; LVQ4x8 when the records
+ * have 4 bits, the scheme of the LVQ baseline in Appendix D and Fig. 1): a
+ * row refines the primary record of the same vector with an 8-bit LVQ of its
+ * quantisation residual r2 = (y - mu) - (lo + delta c), per-vector min / max
+ * and no centring: 16 ceil(d / 16) code bytes (one per reduced component,
+ * zero padded), float32 delta2, float32 lo2, 8 zero bytes (pass d here; d <=
+ * 1008), written by lv_lvq_encode_level2.  The re-rank score is the
+ * traversal's primary score plus <A q, lo2 + delta2 c2>, which is <A q, y^>
+ * for the two-level reconstruction y^ = mu + lo + delta c + lo2 + delta2 c2:
+ * re-ranking reads d more bytes per candidate and no full-dimension vector
+ * (Q is not read).
  */
 int32_t lv_secondary_row_bytes(int32_t D, int32_t sec_dtype);
 
@@ -480,7 +514,7 @@ typedef struct {
  * per node, a search of the current graph with the node as query collects
  * L candidates, which are pruned to at most R diverse out-neighbours;
  * Section 2 "Graph construction": only the primary vectors take part;
- * Appendix C: Vamana's pruning with factor alpha).  Distances are squared
+ * Appendix D: Vamana's pruning with factor alpha).  Distances are squared
  * Euclidean distances between LVQ reconstructions, from exact integer code
  * sums and one fixed sequence of float64 operations.
  *

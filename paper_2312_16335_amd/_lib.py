@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "liblv.so")
 
 LV_OK, LV_WNOTCONVERGED = 0, 1
 LV_EINVAL, LV_ENOMEM, LV_EDEVICE, LV_EUNSUPPORTED = -1, -2, -3, -4
-LV_F32, LV_F16, LV_LVQ8, LV_F16_RESID = 0, 1, 2, 3
+LV_F32, LV_F16, LV_LVQ8, LV_F16_RESID, LV_LVQ8_LEVEL2 = 0, 1, 2, 3, 4
 LV_LAUNCH_PER_QUERY, LV_LAUNCH_PERSISTENT, LV_LAUNCH_TEAM = 0, 1, 2
 LV_SENTINEL = 0xFFFFFFFF
 LV_FW_INIT_ES, LV_FW_INIT_ZERO, LV_FW_INIT_GIVEN = 0, 1, 2
@@ -91,6 +91,8 @@ _SIGS = {
     "lv_record_stride": (_c_i32, [_c_i32, _c_i32]),
     "lv_secondary_row_bytes": (_c_i32, [_c_i32, _c_i32]),
     "lv_lvq_encode": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _c_i32, _vp]),
+    "lv_lvq_encode_level2": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _c_i32, _vp,
+                                      _c_i32, _vp]),
     "lv_to_f16": (_c_i32, [_vp, _c_i64, _vp, _vp]),
     "lv_index_create": (_c_i32, [ctypes.POINTER(IndexDesc), ctypes.POINTER(_vp)]),
     "lv_index_destroy": (_c_i32, [_vp]),
@@ -326,6 +328,20 @@ def lv_lvq_encode(Y, mu, bits: int, records, stream=None) -> None:
                                 _dev(records, torch.uint8), records.shape[1], _stream(stream)))
 
 
+def lv_lvq_encode_level2(Y, mu, bits: int, records, rows, stream=None) -> None:
+    """Second level of a two-level LVQ: rows (device uint8 [n][row bytes]) from
+    Y, mu and the primary records written by lv_lvq_encode with the same bits."""
+    import torch
+
+    n, d = _rows_cols(Y, "Y")
+    _need(mu, d, "mu")
+    _rows_cols(records, "records", min_rows=n)
+    _rows_cols(rows, "rows", min_rows=n)
+    _check(load().lv_lvq_encode_level2(_dev(Y, torch.float32), n, d, _dev(mu, torch.float32),
+                                       bits, _dev(records, torch.uint8), records.shape[1],
+                                       _dev(rows, torch.uint8), rows.shape[1], _stream(stream)))
+
+
 def lv_to_f16(X, out, stream=None) -> None:
     import torch
 
@@ -371,14 +387,26 @@ class Index:
     """Handle over device arrays (borrowed: keep the tensors alive)."""
 
     def __init__(self, records, mu, secondaries, adjacency, entry: int, bits: int, d: int,
-                 A_bf16=None, sec_mu=None, residual: bool = False):
+                 A_bf16=None, sec_mu=None, residual: bool = False, level2: bool = False,
+                 D: int = 0):
         """secondaries: float16 or float32 [N][D], or (with sec_mu, float32 [D]) uint8
         LVQ-8 rows [N][D + 16] from lv_lvq_encode, or (residual=True) float16
-        residual coordinates [N][D - d] with A_bf16 the [D][D] basis."""
+        residual coordinates [N][D - d] with A_bf16 the [D][D] basis, or
+        (level2=True) the primaries' second level, uint8 rows from
+        lv_lvq_encode_level2; then D is the argument, else A_bf16's columns."""
         import torch
 
         N, sec_cols = _rows_cols(secondaries, "secondaries")
-        if residual:
+        if level2:
+            if not D:
+                if A_bf16 is None:
+                    raise ValueError("level2 needs D or A_bf16")
+                D = _rows_cols(A_bf16, "A_bf16")[1]
+            sec_dtype = LV_LVQ8_LEVEL2
+            if sec_cols != lv_secondary_row_bytes(d, LV_LVQ8_LEVEL2):
+                raise ValueError(f"second-level rows need "
+                                 f"{lv_secondary_row_bytes(d, LV_LVQ8_LEVEL2)} bytes for d = {d}")
+        elif residual:
             sec_dtype, D = LV_F16_RESID, sec_cols + d
         elif sec_mu is not None:
             sec_dtype, D = LV_LVQ8, int(sec_mu.numel())

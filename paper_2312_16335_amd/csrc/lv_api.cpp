@@ -14,7 +14,7 @@ int validate_desc(const lv_index_desc *d, lv_index *ix) {
   if (d->D < d->d) LV_FAIL(LV_EINVAL, "D must be >= d");
   if (d->bits != 4 && d->bits != 8) LV_FAIL(LV_EINVAL, "bits must be 4 or 8");
   if (d->sec_dtype != LV_F32 && d->sec_dtype != LV_F16 && d->sec_dtype != LV_LVQ8 &&
-      d->sec_dtype != LV_F16_RESID)
+      d->sec_dtype != LV_F16_RESID && d->sec_dtype != LV_LVQ8_LEVEL2)
     LV_FAIL(LV_EINVAL, "bad sec_dtype");
   const bool resid = d->sec_dtype == LV_F16_RESID;
   if (resid && d->D <= d->d) LV_FAIL(LV_EINVAL, "LV_F16_RESID needs D > d");
@@ -39,7 +39,7 @@ int validate_desc(const lv_index_desc *d, lv_index *ix) {
       LV_FAIL(LV_EUNSUPPORTED, "record_stride %d unsupported (use lv_record_stride)",
               d->record_stride);
   }
-  const int64_t row_bytes = lv_secondary_row_bytes(resid ? d->D - d->d : d->D, d->sec_dtype);
+  const int64_t row_bytes = lv_secondary_row_bytes(lv::secondary_dims(*d), d->sec_dtype);
   if (row_bytes == 0)
     LV_FAIL(LV_EUNSUPPORTED, "secondary rows of D = %d and type %d are not supported", d->D,
             d->sec_dtype);
@@ -72,6 +72,7 @@ extern "C" int32_t lv_secondary_row_bytes(int32_t D, int32_t sec_dtype) {
   if (sec_dtype == LV_F32) b = 4 * (int64_t)D;
   else if (sec_dtype == LV_F16 || sec_dtype == LV_F16_RESID) b = 2 * (int64_t)D;
   else if (sec_dtype == LV_LVQ8) b = D % 16 == 0 && D <= 1008 ? (int64_t)D + 16 : 0;
+  else if (sec_dtype == LV_LVQ8_LEVEL2) b = D <= 1008 ? ((int64_t)D + 15) / 16 * 16 + 16 : 0;
   if (b == 0 || b % 16 != 0 || b > 2048) return 0;
   return (int32_t)b;
 }

@@ -28,6 +28,12 @@ namespace lv {
 
 constexpr uint32_t kSentinel = LV_SENTINEL;
 
+// Components per secondary row: D, or D - d for residual coordinates, or d
+// for the second level of the primaries.
+inline int32_t secondary_dims(const lv_index_desc &d) {
+  return d.sec_dtype == LV_F16_RESID ? d.D - d.d : (d.sec_dtype == LV_LVQ8_LEVEL2 ? d.d : d.D);
+}
+
 }  // namespace lv
 
 // The index handle: a validated copy of the descriptor plus derived launch

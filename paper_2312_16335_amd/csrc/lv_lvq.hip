@@ -1,4 +1,5 @@
-// LVQ encoding of the primary vectors and float16 conversion of the
+// LVQ encoding of the primary vectors, the second level of a two-level LVQ
+// (LVQ4x8 of the baseline setup, Appendix D), and float16 conversion of the
 // secondary vectors (Section 2: primary vectors quant(Bx), secondary vectors
 // quant(x)).
 //
@@ -74,6 +75,49 @@ __global__ __launch_bounds__(256) void encode_kernel(const float *__restrict__ Y
     *reinterpret_cast<uint32_t *>(out + b) = 0u;
 }
 
+// Second level of a two-level LVQ: one wavefront per vector re-reads the
+// vector's primary record, forms the residual r2 = (y - mu) - (lo + delta c)
+// in float64 and quantises it to 8 bits (per-vector min / max, no centring).
+// Row: 16 ceil(d / 16) code bytes, float32 delta2, float32 lo2, 8 zero bytes.
+template <int BITS>
+__global__ __launch_bounds__(256) void encode_level2_kernel(
+    const float *__restrict__ Y, int64_t n, int32_t d, const float *__restrict__ mu,
+    const unsigned char *__restrict__ rec, int32_t stride, unsigned char *__restrict__ rows,
+    int32_t row_bytes) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (v >= n) return;
+  const float *y = Y + v * d;
+  const unsigned char *r1 = rec + v * (int64_t)stride;
+  const int cb = d * BITS / 8;
+  const double delta = (double)__uint_as_float(*reinterpret_cast<const uint32_t *>(r1 + cb));
+  const double lo = (double)__uint_as_float(*reinterpret_cast<const uint32_t *>(r1 + cb + 4));
+  auto resid = [&](int j) {
+    const uint32_t c = BITS == 8 ? r1[j] : (r1[j >> 1] >> (4 * (j & 1))) & 0xFu;
+    const double r = (double)y[j] - (double)mu[j];
+    return r - (lo + delta * (double)c);
+  };
+  double lmin = INFINITY, lmax = -INFINITY;
+  for (int j = lane; j < d; j += 64) {
+    const double r2 = resid(j);
+    lmin = fmin(lmin, r2);
+    lmax = fmax(lmax, r2);
+  }
+  const double l = wave_min(lmin);
+  const double u = wave_max(lmax);
+  const float delta32 = (float)((u - l) / 255.0);
+  const float lo32 = (float)l;
+  const double delta2 = (double)delta32, lo2 = (double)lo32;
+  unsigned char *out = rows + v * (int64_t)row_bytes;
+  const int padded = (d + 15) / 16 * 16;
+  for (int j = lane; j < padded; j += 64)
+    out[j] = j < d ? (unsigned char)lvq_code(resid(j), lo2, delta2, 255.0) : (unsigned char)0;
+  if (lane < 4) {
+    const uint32_t w = lane == 0 ? __float_as_uint(delta32) : (lane == 1 ? __float_as_uint(lo32) : 0u);
+    *reinterpret_cast<uint32_t *>(out + padded + 4 * lane) = w;
+  }
+}
+
 // float32 -> float16 with the hardware conversion (round to nearest even).
 __global__ __launch_bounds__(256) void to_f16_kernel(const float *__restrict__ x, int64_t count,
                                                      _Float16 *__restrict__ out) {
@@ -114,6 +158,36 @@ extern "C" int lv_lvq_encode(const float *Y, int64_t n, int32_t d, const float *
   else
     hipLaunchKernelGGL(lv::encode_kernel<4>, dim3((unsigned)blocks), dim3(64 * per_block), 0, s, Y,
                        n, d, mu, static_cast<unsigned char *>(records), record_stride);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+extern "C" int lv_lvq_encode_level2(const float *Y, int64_t n, int32_t d, const float *mu,
+                                    int32_t bits, const void *records, int32_t record_stride,
+                                    void *rows, int32_t row_bytes, void *stream) {
+  lv::clear_error();
+  if (bits != 4 && bits != 8) LV_FAIL(LV_EINVAL, "bits must be 4 or 8 (got %d)", bits);
+  if (d < 8 || d > 1008 || d % 8 != 0) LV_FAIL(LV_EINVAL, "d must be a multiple of 8 in [8, 1008]");
+  if (n < 0) LV_FAIL(LV_EINVAL, "n must be >= 0");
+  if (record_stride < d * bits / 8 + 8 || record_stride % 4 != 0)
+    LV_FAIL(LV_EINVAL, "record_stride %d too small or not a multiple of 4", record_stride);
+  const int32_t want = lv_secondary_row_bytes(d, LV_LVQ8_LEVEL2);
+  if (row_bytes != want)
+    LV_FAIL(LV_EINVAL, "row_bytes %d must be %d for d = %d", row_bytes, want, d);
+  if (n > 0 && (!Y || !mu || !records || !rows)) LV_FAIL(LV_EINVAL, "NULL pointer");
+  if (n == 0) return LV_OK;
+  const int per_block = 4;
+  const int64_t blocks = (n + per_block - 1) / per_block;
+  if (blocks > 0x7FFFFFFF) LV_FAIL(LV_EINVAL, "n too large");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const unsigned char *rec = static_cast<const unsigned char *>(records);
+  unsigned char *out = static_cast<unsigned char *>(rows);
+  if (bits == 8)
+    hipLaunchKernelGGL(lv::encode_level2_kernel<8>, dim3((unsigned)blocks), dim3(64 * per_block), 0,
+                       s, Y, n, d, mu, rec, record_stride, out, row_bytes);
+  else
+    hipLaunchKernelGGL(lv::encode_level2_kernel<4>, dim3((unsigned)blocks), dim3(64 * per_block), 0,
+                       s, Y, n, d, mu, rec, record_stride, out, row_bytes);
   LV_CHECK_LAUNCH();
   return LV_OK;
 }

@@ -20,7 +20,7 @@ struct IndexView {
   int32_t D;
   int32_t sec_row_bytes;
   int32_t sec_packets;
-  int32_t sec_kind;  // LV_F32, LV_F16 or LV_LVQ8
+  int32_t sec_kind;  // LV_F32, LV_F16, LV_LVQ8, LV_F16_RESID or LV_LVQ8_LEVEL2
   const float *sec_mu;  // [D] for LV_LVQ8
   const uint32_t *adj;
   int32_t R;

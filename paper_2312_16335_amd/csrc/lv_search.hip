@@ -1,6 +1,6 @@
 // Graph search on gfx950: one wavefront per query.
 //
-// Per query (Section 2 "Search"; traversal of Appendix C read as a
+// Per query (Section 2 "Search"; traversal of Appendix D read as a
 // best-first beam with window L):
 //   * the candidate window (L entries of float64 score + id, kept sorted by
 //     score descending then id ascending) lives in LDS as one buffer that a
@@ -365,20 +365,24 @@ __device__ __forceinline__ bool hash_visit(uint32_t *hash, int log2h, int probes
 
 // Secondary scores of window entries ids[0..nl) into out[], one row at a
 // time across the wavefront (16-byte packets, UR rows in flight).  KIND is
-// LV_F32, LV_F16, LV_LVQ8 or LV_F16_RESID; an LVQ-8 row is scored as
-// delta * <q, c> + lo * sum(q) + <q, sec_mu>, which equals <q, x^> for its
-// reconstruction x^ = sec_mu + lo + delta * c.  The packet after the codes
-// holds delta and lo; its query components are zero.  A residual row (D - d
-// float16 coordinates, q = P_perp q) adds its inner product to the primary
-// score already in out[].
+// LV_F32, LV_F16, LV_LVQ8, LV_F16_RESID or LV_LVQ8_LEVEL2; an LVQ-8 row is
+// scored as delta * <q, c> + lo * sum(q) + <q, sec_mu>, which equals <q, x^>
+// for its reconstruction x^ = sec_mu + lo + delta * c.  The packet after the
+// codes holds delta and lo; its query components are zero.  A residual row
+// (D - d float16 coordinates, q = P_perp q) and a second-level row (d codes,
+// q = A q, no centring) add their inner product to the primary score
+// already in out[].
 template <int KIND>
 __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
                                             const uint32_t *ids, double *out, int nl, int lane) {
   constexpr bool F16 = KIND == LV_F16 || KIND == LV_F16_RESID;
+  constexpr bool LVQ = KIND == LV_LVQ8 || KIND == LV_LVQ8_LEVEL2;
+  constexpr bool ADD = KIND == LV_F16_RESID || KIND == LV_LVQ8_LEVEL2;
   constexpr int E = F16 ? 8 : (KIND == LV_F32 ? 4 : 16);  // elements per packet
-  const int dim = KIND == LV_F16_RESID ? ix.D - ix.d : ix.D;  // components per row
-  // packets per lane: rows up to 2 KiB (LV_LVQ8 rows up to 1 KiB)
-  constexpr int PPL = KIND == LV_LVQ8 ? 1 : 2;
+  // components per row
+  const int dim = KIND == LV_F16_RESID ? ix.D - ix.d : (KIND == LV_LVQ8_LEVEL2 ? ix.d : ix.D);
+  // packets per lane: rows up to 2 KiB (LVQ rows up to 1 KiB)
+  constexpr int PPL = LVQ ? 1 : 2;
   constexpr int UR = 4;   // rows in flight
   float qq[PPL][E];
   double sq = 0.0, cq = 0.0;
@@ -390,18 +394,17 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
       const int j = packet * E + e;
       const bool in = packet < ix.sec_packets && j < dim;
       qq[pk][e] = in ? gp(q)[j] : 0.f;
-      if constexpr (KIND == LV_LVQ8) {
-        sq += (double)qq[pk][e];
+      if constexpr (LVQ) sq += (double)qq[pk][e];
+      if constexpr (KIND == LV_LVQ8)
         cq = fma((double)qq[pk][e], in ? (double)gp(ix.sec_mu)[j] : 0.0, cq);
-      }
     }
   }
-  int cl = 0, cpk = 0;  // lane and packet slot holding an LVQ-8 row's delta and lo
-  if constexpr (KIND == LV_LVQ8) {
+  int cl = 0, cpk = 0;  // lane and packet slot holding an LVQ row's delta and lo
+  if constexpr (LVQ) {
     sq = group_sum<64>(sq);
-    cq = group_sum<64>(cq);
-    cl = (ix.D / 16) % 64;
-    cpk = (ix.D / 16) / 64;
+    if constexpr (KIND == LV_LVQ8) cq = group_sum<64>(cq);
+    cl = ((dim + 15) / 16) % 64;
+    cpk = ((dim + 15) / 16) / 64;
   }
   for (int base = 0; base < nl; base += UR) {
     u32x4 v[UR][PPL];
@@ -438,13 +441,13 @@ __device__ __forceinline__ void rerank_rows(const IndexView &ix, const float *q,
         }
       }
       acc = group_sum<64>(acc);
-      if constexpr (KIND == LV_LVQ8) {
+      if constexpr (LVQ) {
         const uint32_t dw = lane_u32(cpk == 0 ? v[u][0][0] : v[u][PPL - 1][0], cl);
         const uint32_t lw = lane_u32(cpk == 0 ? v[u][0][1] : v[u][PPL - 1][1], cl);
         acc = (double)__uint_as_float(dw) * acc + (double)__uint_as_float(lw) * sq + cq;
       }
       if (lane == 0 && base + u < nl) {
-        if constexpr (KIND == LV_F16_RESID)
+        if constexpr (ADD)
           out[base + u] += acc;
         else
           out[base + u] = acc;
@@ -538,6 +541,15 @@ __device__ __forceinline__ void rerank_pairs_any(const IndexView &ix, const floa
     rerank_rows<KIND>(ix, q, ids, out, n, lane);
 }
 
+// The query the re-ranking reads: the full query, or the residual part of
+// the projected one (P_perp q), or the projected one itself (second level).
+__device__ __forceinline__ const float *rerank_query(const IndexView &ix, const float *qp,
+                                                     const float *q) {
+  if (ix.sec_kind == LV_F16_RESID) return qp + ix.d;
+  if (ix.sec_kind == LV_LVQ8_LEVEL2) return qp;
+  return q;
+}
+
 // Re-rank entries [0, n) of ids/out with the index's kind of secondaries.
 __device__ __forceinline__ void rerank_any(const IndexView &ix, const float *q,
                                            const uint32_t *ids, double *out, int n, int lane) {
@@ -547,6 +559,8 @@ __device__ __forceinline__ void rerank_any(const IndexView &ix, const float *q,
     rerank_rows<LV_LVQ8>(ix, q, ids, out, n, lane);
   else if (ix.sec_kind == LV_F16_RESID)
     rerank_pairs_any<LV_F16_RESID>(ix, q, ids, out, n, lane);
+  else if (ix.sec_kind == LV_LVQ8_LEVEL2)
+    rerank_rows<LV_LVQ8_LEVEL2>(ix, q, ids, out, n, lane);
   else
     rerank_pairs_any<LV_F32>(ix, q, ids, out, n, lane);
 }
@@ -1048,7 +1062,7 @@ __global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
   Job job;
   job.qp = a.Qp + qi * a.qp_stride;
   // residual secondaries are scored with P_perp q, stored after P q
-  job.q = a.ix.sec_kind == LV_F16_RESID ? job.qp + a.ix.d : a.Q + qi * a.ix.D;
+  job.q = rerank_query(a.ix, job.qp, a.Q + qi * a.ix.D);
   job.k = a.k;
   job.L = a.L;
   job.ids = a.ids + qi * a.k;
@@ -1067,7 +1081,7 @@ __global__ __launch_bounds__(64 * kTeamWaves) void team_kernel(PlainArgs a) {
   const Lds sm = carve(a.L);
   Job job;
   job.qp = a.Qp + qi * a.qp_stride;
-  job.q = a.ix.sec_kind == LV_F16_RESID ? job.qp + a.ix.d : a.Q + qi * a.ix.D;
+  job.q = rerank_query(a.ix, job.qp, a.Q + qi * a.ix.D);
   job.k = a.k;
   job.L = a.L;
   job.ids = a.ids + qi * a.k;
@@ -1129,7 +1143,7 @@ __attribute__((amdgpu_waves_per_eu(batched_waves<BITS, V>()))) void batched_kern
     asm volatile("" : "+v"(lane_q));
     Job job;
     job.qp = hdr->Qp + (int64_t)u * hdr->qp_stride;
-    job.q = ix.sec_kind == LV_F16_RESID ? job.qp + ix.d : hdr->Q + (int64_t)u * ix.D;
+    job.q = rerank_query(ix, job.qp, hdr->Q + (int64_t)u * ix.D);
     job.k = r.k;
     job.L = r.L;
     job.ids = hdr->ids + r.out_off + j * r.k;
@@ -1278,8 +1292,7 @@ IndexView make_view(const lv_index *ix) {
   v.mu = d.mu;
   v.sec = static_cast<const unsigned char *>(d.secondaries);
   v.D = d.D;
-  v.sec_row_bytes =
-      lv_secondary_row_bytes(d.sec_dtype == LV_F16_RESID ? d.D - d.d : d.D, d.sec_dtype);
+  v.sec_row_bytes = lv_secondary_row_bytes(secondary_dims(d), d.sec_dtype);
   v.sec_packets = ix->sec_packets;
   v.sec_kind = d.sec_dtype;
   v.sec_mu = d.sec_mu;

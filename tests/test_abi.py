@@ -115,6 +115,19 @@ def test_encode_and_project_validation():
     assert lib.lv_lvq_encode(FAKE, 10, 160, FAKE, 8, FAKE, 160, None) == lv.LV_EINVAL
     assert lib.lv_lvq_encode(None, 10, 32, FAKE, 8, FAKE, 64, None) == lv.LV_EINVAL
     assert lib.lv_lvq_encode(FAKE, 0, 32, FAKE, 8, FAKE, 64, None) == lv.LV_OK
+    # second level: same checks, d <= 1008 and rows of exactly the level-2 width
+    rb = lib.lv_secondary_row_bytes(32, lv.LV_LVQ8_LEVEL2)
+    assert lib.lv_lvq_encode_level2(FAKE, 10, 32, FAKE, 3, FAKE, 64, FAKE, rb, None) == lv.LV_EINVAL
+    assert lib.lv_lvq_encode_level2(FAKE, 10, 36, FAKE, 8, FAKE, 64, FAKE, rb, None) == lv.LV_EINVAL
+    assert lib.lv_lvq_encode_level2(FAKE, 10, 1016, FAKE, 4, FAKE, 1024, FAKE,
+                                    1040, None) == lv.LV_EINVAL
+    assert lib.lv_lvq_encode_level2(FAKE, 10, 32, FAKE, 8, FAKE, 32, FAKE, rb, None) == lv.LV_EINVAL
+    assert lib.lv_lvq_encode_level2(FAKE, 10, 32, FAKE, 8, FAKE, 64, FAKE, rb + 16,
+                                    None) == lv.LV_EINVAL
+    assert lib.lv_lvq_encode_level2(FAKE, 10, 32, FAKE, 8, None, 64, FAKE, rb, None) == lv.LV_EINVAL
+    assert lib.lv_lvq_encode_level2(FAKE, 10, 32, FAKE, 8, FAKE, 64, None, rb, None) == lv.LV_EINVAL
+    assert lib.lv_lvq_encode_level2(FAKE, -1, 32, FAKE, 8, FAKE, 64, FAKE, rb, None) == lv.LV_EINVAL
+    assert lib.lv_lvq_encode_level2(FAKE, 0, 32, FAKE, 8, FAKE, 64, FAKE, rb, None) == lv.LV_OK
     assert lib.lv_project(FAKE, 10, 12, FAKE, 4, FAKE, None) == lv.LV_EINVAL
     assert lib.lv_project(FAKE, 10, 16, FAKE, 0, FAKE, None) == lv.LV_EINVAL
     assert lib.lv_project(FAKE, -1, 16, FAKE, 4, FAKE, None) == lv.LV_EINVAL
@@ -327,6 +340,19 @@ def test_residual_secondaries_descriptor():
     # the workspace holds P q and P_perp q: D floats per query
     assert lib.lv_search_workspace_size(h, 10) >= 10 * 128 * 4
     lib.lv_index_destroy(h)
+
+
+def test_level2_secondaries_descriptor():
+    # d code bytes padded to 16, then delta2, lo2 and 8 zero bytes
+    for d, want in ((8, 32), (88, 112), (160, 176), (1008, 1024), (1016, 0)):
+        assert lv.lv_secondary_row_bytes(d, lv.LV_LVQ8_LEVEL2) == want, d
+    rc, h = _create(_desc(sec_dtype=lv.LV_LVQ8_LEVEL2, D=128, d=32))
+    assert rc == lv.LV_OK
+    lib = lv.load()
+    assert lib.lv_search_workspace_size(h, 10) == (10 * 32 * 4 + 255) // 256 * 256
+    lib.lv_index_destroy(h)
+    rc, h = _create(_desc(sec_dtype=5, D=128, d=32))
+    assert rc == lv.LV_EINVAL and not h.value
 
 
 def test_binding_checks_buffer_sizes_before_any_call():

@@ -446,6 +446,97 @@ def test_residual_secondaries_batched_equals_plain(lv):
     index.close()
 
 
+def _level2_case(lv, name, bits, N=6000):
+    """A workload with `bits`-bit primaries and their 8-bit second level as
+    the re-ranking rows (LVQ4x8 at bits = 4)."""
+    from dataclasses import replace
+
+    wl = replace(gen.WORKLOADS[name].scaled(N=N, m_test=40), bits=bits)
+    c = make_case(wl)
+    codes, delta, lo = olvq.encode(c.Y, c.mu, bits)
+    c2, d2, l2 = olvq.encode_residual(c.Y, c.mu, codes, delta, lo)
+    oidx = osearch.Index(c.adj, c.entry, codes, delta, lo, c.mu, c2, d2, l2,
+                         sec_two_level=True)
+    Yd = torch.from_numpy(c.Y).to(DEV)
+    mud = torch.from_numpy(c.mu).to(DEV)
+    rec = torch.empty((wl.N, c.stride), dtype=torch.uint8, device=DEV)
+    lv.lv_lvq_encode(Yd, mud, bits, rec)
+    rb = lv.lv_secondary_row_bytes(wl.d, lv.LV_LVQ8_LEVEL2)
+    assert rb == (wl.d + 15) // 16 * 16 + 16
+    rows = torch.full((wl.N, rb), 0xAB, dtype=torch.uint8, device=DEV)
+    lv.lv_lvq_encode_level2(Yd, mud, bits, rec, rows)
+    torch.cuda.synchronize()
+    want = olvq.pack_level2_rows(c2, d2, l2)
+    adj = torch.from_numpy(c.adj.view(np.int32)).to(DEV)
+    Pb = torch.from_numpy(lv.lv_to_bf16(c.P).view(np.int16)).to(DEV)
+    index = lv.Index(rec, mud, rows, adj, c.entry, bits, wl.d, A_bf16=Pb, level2=True)
+    return wl, c, oidx, index, rows, want, (rec, mud, rows, adj, Pb)
+
+
+@pytest.mark.parametrize("name,bits", [("id-1m-768", 4), ("ood-1m-512", 4), ("id-1m-768", 8)])
+def test_search_parity_level2_secondaries(lv, name, bits):
+    """Two-level LVQ (the second level re-ranks): rows bit-exact against the
+    oracle's encoding; ids, scores and counters equal to the oracle's
+    (primary score plus the second level's inner product with A q); the
+    team launch identical; the batched step identical to the plain search."""
+    wl, c, oidx, index, rows, want, keep = _level2_case(lv, name, bits)
+    assert np.array_equal(rows.cpu().numpy(), want)
+    m, k = len(c.Q), wl.k
+    for L in (20, 60):
+        want_ids, want_sc, want_cnt = osearch.search_many(oidx, c.Q, c.Qp, k, L)
+        got_ids, got_sc, got_cnt = run_projected(lv, index, c, k, L, hash_slots=8192)
+        mism = np.nonzero((got_ids != want_ids).any(axis=1))[0]
+        for qi in mism:  # only swaps of exactly tied scores
+            qp = c.Qp[qi].astype(np.float64)
+            g = osearch.two_level_scores(oidx, qp, got_ids[qi])
+            w = osearch.two_level_scores(oidx, qp, want_ids[qi])
+            assert np.allclose(np.sort(g), np.sort(w), rtol=0, atol=1e-12), qi
+        assert np.all(np.abs(got_sc - want_sc) <= 1e-4 * np.maximum(np.abs(want_sc), 1.0))
+        assert np.array_equal(got_cnt, want_cnt)
+        team = run_projected(lv, index, c, k, L, hash_slots=8192, launch=lv.LV_LAUNCH_TEAM)
+        for g, o in zip(team, (got_ids, got_sc, got_cnt)):
+            assert np.array_equal(g, o)
+    # batched step (device projection) equals the plain search with the same projection
+    L = 50
+    Qd = torch.from_numpy(c.Q).to(DEV)
+    ids_p = torch.empty((m, k), dtype=torch.int32, device=DEV)
+    sc_p = torch.empty((m, k), dtype=torch.float32, device=DEV)
+    ws = torch.empty(lv.lv_search_workspace_size(index, m), dtype=torch.uint8, device=DEV)
+    lv.lv_search(index, Qd, k, L, ids_p, sc_p, None, ws=ws)
+    multi = lv.Multi([index])
+    batch = lv.Batch(multi, max_requests=2, max_queries=m, max_L=L)
+    ids_b = torch.full((m * k,), -7, dtype=torch.int32, device=DEV)
+    sc_b = torch.zeros((m * k,), dtype=torch.float32, device=DEV)
+    batch.step([(0, k, L, 11), (0, k, L, m - 11)], Qd, ids_b, sc_b)
+    torch.cuda.synchronize()
+    assert torch.equal(ids_b.view(m, k), ids_p) and torch.equal(sc_b.view(m, k), sc_p)
+    batch.close()
+    multi.close()
+    index.close()
+
+
+def test_level2_rows_edges(lv):
+    """Second-level rows for a ragged count of vectors with d not a multiple
+    of 16 (zero padding), a vector equal to mu (delta2 = 0: all codes zero) and
+    the 4-bit nibble order; bit-exact against the oracle."""
+    rng = np.random.default_rng(77)
+    for bits, d, n in ((4, 88, 37), (8, 8, 5), (4, 1008, 3), (8, 120, 130)):
+        Y = (rng.standard_normal((n, d)) * rng.uniform(0.01, 5, (n, 1))).astype(np.float32)
+        mu = rng.standard_normal(d).astype(np.float32)
+        Y[0] = mu  # exact at the first level: residual 0, delta2 = 0
+        Yd, mud = torch.from_numpy(Y).to(DEV), torch.from_numpy(mu).to(DEV)
+        stride = lv.lv_record_stride(d, bits)
+        rec = torch.empty((n, stride), dtype=torch.uint8, device=DEV)
+        lv.lv_lvq_encode(Yd, mud, bits, rec)
+        rb = lv.lv_secondary_row_bytes(d, lv.LV_LVQ8_LEVEL2)
+        rows = torch.full((n, rb), 0x5A, dtype=torch.uint8, device=DEV)
+        lv.lv_lvq_encode_level2(Yd, mud, bits, rec, rows)
+        torch.cuda.synchronize()
+        codes, delta, lo = olvq.encode(Y, mu, bits)
+        c2, d2, l2 = olvq.encode_residual(Y, mu, codes, delta, lo)
+        assert np.array_equal(rows.cpu().numpy(), olvq.pack_level2_rows(c2, d2, l2)), (bits, d)
+
+
 def test_single_vector_index(lv):
     """N = 1: the entry is the only result; the rest of every list is padding."""
     rng = np.random.default_rng(31)
