@@ -203,6 +203,22 @@ int lv_lvq_encode(const float *Y, int64_t n, int32_t d, const float *mu, int32_t
                   void *records, int32_t record_stride, void *stream);
 
 /*
+ * Database projection and LVQ encoding in one pass (Eq. 1: quant(B x) for
+ * every database vector): the records lv_project(V, rows, D, M, d) followed
+ * by lv_lvq_encode(out, rows, d, mu, bits) would write, bit for bit, without
+ * the float32 reduced vectors going through memory (each workgroup holds
+ * whole rows of B x and encodes them from the accumulators).
+ *   V: device float32 [rows][D];  M: device bfloat16 bits [d][D] (B)
+ *   mu: device float32 [d];  records: device [rows][record_stride] bytes out
+ * Errors: LV_EINVAL for rows < 0, D < 8 or D % 8 != 0, d outside [8, 256] or
+ *         d % 8 != 0, bits not 4 or 8, record_stride < d*bits/8 + 8 or not a
+ *         multiple of 4, NULL pointers with rows > 0.
+ */
+int lv_project_encode(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32_t d,
+                      const float *mu, int32_t bits, void *records, int32_t record_stride,
+                      void *stream);
+
+/*
  * Second level of a two-level LVQ (LV_LVQ8_LEVEL2 rows; the scheme LVQ4x8
  * of the LVQ baseline in Appendix D and Fig. 1, which the paper names
  * without restating): for every vector, the residual of its primary record

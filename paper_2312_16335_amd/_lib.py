@@ -91,6 +91,8 @@ _SIGS = {
     "lv_record_stride": (_c_i32, [_c_i32, _c_i32]),
     "lv_secondary_row_bytes": (_c_i32, [_c_i32, _c_i32]),
     "lv_lvq_encode": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _c_i32, _vp]),
+    "lv_project_encode": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _c_i32, _vp, _c_i32,
+                                   _vp]),
     "lv_lvq_encode_level2": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _c_i32, _vp,
                                       _c_i32, _vp]),
     "lv_to_f16": (_c_i32, [_vp, _c_i64, _vp, _vp]),
@@ -326,6 +328,22 @@ def lv_lvq_encode(Y, mu, bits: int, records, stream=None) -> None:
     _rows_cols(records, "records", min_rows=n)
     _check(load().lv_lvq_encode(_dev(Y, torch.float32), n, d, _dev(mu, torch.float32), bits,
                                 _dev(records, torch.uint8), records.shape[1], _stream(stream)))
+
+
+def lv_project_encode(V, M_bf16, mu, bits: int, records, stream=None) -> None:
+    """LVQ records of V M^T (device uint8 [rows][stride], written) in one pass;
+    the bytes lv_project followed by lv_lvq_encode would give."""
+    import torch
+
+    rows, D = _rows_cols(V, "V")
+    d = _rows_cols(M_bf16, "M_bf16", cols=D)[0]
+    if M_bf16.element_size() != 2:
+        raise ValueError("M_bf16 must hold 2-byte bfloat16 bits")
+    _need(mu, d, "mu")
+    _rows_cols(records, "records", min_rows=rows)
+    _check(load().lv_project_encode(_dev(V, torch.float32), rows, D, _dev(M_bf16), d,
+                                    _dev(mu, torch.float32), bits, _dev(records, torch.uint8),
+                                    records.shape[1], _stream(stream)))
 
 
 def lv_lvq_encode_level2(Y, mu, bits: int, records, rows, stream=None) -> None:

@@ -1,8 +1,8 @@
 """Build the gfx950 library ``liblv.so`` in-tree.
 
 HIP sources are compiled with hipcc for gfx950 (packed float32 instructions
-disabled; the LVQ encoder without floating-point contraction so its bytes
-are exact); the host float64 fitting code is compiled with g++ and OpenMP
+disabled; the LVQ encoders without floating-point contraction so their
+bytes are exact); the host float64 fitting code is compiled with g++ and OpenMP
 (the same libgomp PyTorch uses).  Always rebuilds when called.
 """
 from __future__ import annotations
@@ -26,7 +26,7 @@ HOST_SOURCES = ["lv_fit.cpp", "lv_error.cpp"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
-PER_FILE = {"lv_lvq.hip": ["-ffp-contract=off"]}
+PER_FILE = {"lv_lvq.hip": ["-ffp-contract=off"], "lv_project.hip": ["-ffp-contract=off"]}
 
 
 def _run(cmd):

@@ -9,6 +9,7 @@
 // a float64 reference exactly.  This file is compiled without floating-point
 // contraction.
 #include "lv_common.h"
+#include "lv_lvq.h"
 
 namespace lv {
 namespace {
@@ -23,13 +24,6 @@ __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
-}
-
-__device__ __forceinline__ uint32_t lvq_code(double r, double lo, double delta, double levels) {
-  if (delta == 0.0) return 0u;
-  double c = floor((r - lo) / delta + 0.5);
-  c = c < 0.0 ? 0.0 : (c > levels ? levels : c);
-  return (uint32_t)c;
 }
 
 template <int BITS>

@@ -10,6 +10,7 @@
 // registers, and reads M (d x D bfloat16, a few hundred KB, L2-resident)
 // directly as the B operand.  No LDS is needed.
 #include "lv_common.h"
+#include "lv_lvq.h"
 #include "lv_search.h"
 
 namespace lv {
@@ -115,10 +116,109 @@ __device__ __forceinline__ void project_rows(const float *__restrict__ V, int64_
 constexpr int kRowWaves = 8;
 constexpr int kSlabPitch = 40;  // bfloat16 per LDS slab row: 32 k + 8 (bank spread)
 
-template <int NT>
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double xor16_64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)b, 16, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(b >> 32), 16, 64);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Minimum and maximum over each half wavefront (32 lanes): quad swaps, row
+// rotations by 4 and 8, then the other row of the half.
+__device__ __forceinline__ void half_minmax(double &mn, double &mx) {
+  mn = fmin(mn, dpp64<0xB1>(mn));  // quad_perm [1, 0, 3, 2]
+  mx = fmax(mx, dpp64<0xB1>(mx));
+  mn = fmin(mn, dpp64<0x4E>(mn));  // quad_perm [2, 3, 0, 1]
+  mx = fmax(mx, dpp64<0x4E>(mx));
+  mn = fmin(mn, dpp64<0x124>(mn));  // row_ror 4
+  mx = fmax(mx, dpp64<0x124>(mx));
+  mn = fmin(mn, dpp64<0x128>(mn));  // row_ror 8
+  mx = fmax(mx, dpp64<0x128>(mx));
+  mn = fmin(mn, xor16_64(mn));
+  mx = fmax(mx, xor16_64(mx));
+}
+
+// LVQ records (Eq. 1 quant(Bx); the layout and arithmetic of lv_lvq_encode)
+// of the wavefront's 32 projected rows, straight from the accumulators: per
+// row the float64 min / max of y - mu over the d columns (a reduction across
+// the 32 lanes holding the row), then each lane's codes, stored as bytes
+// (32 consecutive bytes of a row per half wavefront), the row's delta and lo,
+// and the zero padding up to the stride.
+template <int NT, int BITS>
+__device__ __forceinline__ void encode_rows(const f32x16 (&acc)[NT], int64_t row0, int64_t rows,
+                                            int32_t d, const float *__restrict__ mu,
+                                            unsigned char *__restrict__ rec, int32_t stride,
+                                            int lane) {
+  const int r = lane & 31, kh = lane >> 5;
+  constexpr double levels = (double)((1 << BITS) - 1);
+  const int cb = d * BITS / 8;
+  const int npad = (stride - cb - 8) / 4;  // zero words after delta and lo
+  double muv[NT];
+  bool cok[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = t * 32 + r;
+    cok[t] = col < d;
+    muv[t] = cok[t] ? (double)mu[col] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    // one row at a time: keeps the float64 temporaries of one row live, not of all 16
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t grow = row0 + 8 * (i >> 2) + 4 * kh + (i & 3);
+    const bool live = grow < rows;
+    double mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (cok[t]) {
+        const double v = (double)acc[t][i] - muv[t];
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+      }
+    }
+    half_minmax(mn, mx);
+    const float delta32 = (float)((mx - mn) / levels);
+    const float lo32 = (float)mn;
+    const double delta = (double)delta32, lo = (double)lo32;
+    unsigned char *row = rec + (live ? grow : 0) * (int64_t)stride;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = t * 32 + r;
+      const uint32_t c = cok[t] ? lvq_code((double)acc[t][i] - muv[t], lo, delta, levels) : 0u;
+      if constexpr (BITS == 8) {
+        if (live && cok[t]) row[col] = (unsigned char)c;
+      } else {  // component 2j in the low nibble of byte j, 2j + 1 in the high nibble
+        const uint32_t odd = (uint32_t)__builtin_amdgcn_mov_dpp((int)c, 0xB1, 0xF, 0xF, false);
+        if (live && cok[t] && (r & 1) == 0) row[col >> 1] = (unsigned char)(c | (odd << 4));
+      }
+    }
+    if (live) {
+      uint32_t *w = reinterpret_cast<uint32_t *>(row + cb);
+      if (r == 0) w[0] = __float_as_uint(delta32);
+      if (r == 1) w[1] = __float_as_uint(lo32);
+      for (int j = r; j < npad; j += 32) w[2 + j] = 0u;
+    }
+  }
+}
+
+//
+// ENC = 4 or 8: the workgroup holds all d <= 256 columns (col0 = 0) and
+// writes LVQ records of ENC bits (encode_rows) instead of the float32 rows,
+// so the reduced vectors never go through memory.
+template <int NT, int ENC = 0>
 __global__ __launch_bounds__(64 * kRowWaves) void project_kernel(
     const float *__restrict__ V, int64_t rows, int32_t D, const uint16_t *__restrict__ M,
-    int32_t d, int32_t col0, float *__restrict__ out) {
+    int32_t d, int32_t col0, float *__restrict__ out, const float *__restrict__ mu = nullptr,
+    unsigned char *__restrict__ rec = nullptr, int32_t stride = 0) {
   __shared__ __align__(16) uint16_t slab[2][NT * 32 * kSlabPitch];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -188,14 +288,18 @@ __global__ __launch_bounds__(64 * kRowWaves) void project_kernel(
     a1 = n1;
   }
   if (row0 >= rows) return;
+  if constexpr (ENC != 0) {
+    encode_rows<NT, ENC>(acc, row0, rows, d, mu, rec, stride, lane);
+  } else {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int col = col0 + t * 32 + r;
-    if (col >= d) continue;
+    for (int t = 0; t < NT; ++t) {
+      const int col = col0 + t * 32 + r;
+      if (col >= d) continue;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int64_t row = row0 + 8 * (i >> 2) + 4 * kh + (i & 3);
-      if (row < rows) out[row * d + col] = acc[t][i];
+      for (int i = 0; i < 16; ++i) {
+        const int64_t row = row0 + 8 * (i >> 2) + 4 * kh + (i & 3);
+        if (row < rows) out[row * d + col] = acc[t][i];
+      }
     }
   }
 }
@@ -260,6 +364,29 @@ void launch_nt(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32
                      rows, D, M, d, col0, out);
 }
 
+template <int NT, int ENC>
+void launch_enc(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32_t d,
+                const float *mu, unsigned char *rec, int32_t stride, hipStream_t s) {
+  const int64_t blocks = (rows + 32 * kRowWaves - 1) / (32 * kRowWaves);
+  hipLaunchKernelGGL((project_kernel<NT, ENC>), dim3((unsigned)blocks), dim3(64 * kRowWaves), 0, s,
+                     V, rows, D, M, d, 0, nullptr, mu, rec, stride);
+}
+
+template <int ENC>
+void launch_enc_bits(const float *V, int64_t rows, int32_t D, const uint16_t *M, int32_t d,
+                     const float *mu, unsigned char *rec, int32_t stride, hipStream_t s) {
+  switch ((d + 31) / 32) {
+    case 1: launch_enc<1, ENC>(V, rows, D, M, d, mu, rec, stride, s); break;
+    case 2: launch_enc<2, ENC>(V, rows, D, M, d, mu, rec, stride, s); break;
+    case 3: launch_enc<3, ENC>(V, rows, D, M, d, mu, rec, stride, s); break;
+    case 4: launch_enc<4, ENC>(V, rows, D, M, d, mu, rec, stride, s); break;
+    case 5: launch_enc<5, ENC>(V, rows, D, M, d, mu, rec, stride, s); break;
+    case 6: launch_enc<6, ENC>(V, rows, D, M, d, mu, rec, stride, s); break;
+    case 7: launch_enc<7, ENC>(V, rows, D, M, d, mu, rec, stride, s); break;
+    default: launch_enc<8, ENC>(V, rows, D, M, d, mu, rec, stride, s); break;
+  }
+}
+
 }  // namespace
 
 int launch_project_grouped(const StepHeader *hdr, const IndexView *subs, int max_tiles, int d,
@@ -312,4 +439,28 @@ extern "C" int lv_project(const float *V, int64_t rows, int32_t D, const uint16_
   if (d < 1 || d > 1024) LV_FAIL(LV_EINVAL, "d must be in [1, 1024] (got %d)", d);
   if (rows > 0 && (!V || !M || !out)) LV_FAIL(LV_EINVAL, "NULL pointer");
   return lv::launch_project(V, rows, D, M, d, out, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int lv_project_encode(const float *V, int64_t rows, int32_t D, const uint16_t *M,
+                                 int32_t d, const float *mu, int32_t bits, void *records,
+                                 int32_t record_stride, void *stream) {
+  lv::clear_error();
+  if (rows < 0) LV_FAIL(LV_EINVAL, "rows must be >= 0");
+  if (D < 8 || D % 8 != 0) LV_FAIL(LV_EINVAL, "D must be a positive multiple of 8 (got %d)", D);
+  if (d < 8 || d > 256 || d % 8 != 0)
+    LV_FAIL(LV_EINVAL, "d must be a multiple of 8 in [8, 256] (got %d)", d);
+  if (bits != 4 && bits != 8) LV_FAIL(LV_EINVAL, "bits must be 4 or 8 (got %d)", bits);
+  if (record_stride < d * bits / 8 + 8 || record_stride % 4 != 0)
+    LV_FAIL(LV_EINVAL, "record_stride %d too small or not a multiple of 4", record_stride);
+  if (rows > 0 && (!V || !M || !mu || !records)) LV_FAIL(LV_EINVAL, "NULL pointer");
+  if (rows == 0) return LV_OK;
+  if ((rows + 255) / 256 > 0x7FFFFFFF) LV_FAIL(LV_EINVAL, "too many rows");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char *rec = static_cast<unsigned char *>(records);
+  if (bits == 8)
+    lv::launch_enc_bits<8>(V, rows, D, M, d, mu, rec, record_stride, s);
+  else
+    lv::launch_enc_bits<4>(V, rows, D, M, d, mu, rec, record_stride, s);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
 }

@@ -115,6 +115,18 @@ def test_encode_and_project_validation():
     assert lib.lv_lvq_encode(FAKE, 10, 160, FAKE, 8, FAKE, 160, None) == lv.LV_EINVAL
     assert lib.lv_lvq_encode(None, 10, 32, FAKE, 8, FAKE, 64, None) == lv.LV_EINVAL
     assert lib.lv_lvq_encode(FAKE, 0, 32, FAKE, 8, FAKE, 64, None) == lv.LV_OK
+    # one-pass projection and encoding: d in [8, 256], stride checks, NULLs
+    pe = lib.lv_project_encode
+    assert pe(FAKE, 10, 768, FAKE, 264, FAKE, 8, FAKE, 512, None) == lv.LV_EINVAL
+    assert pe(FAKE, 10, 768, FAKE, 12, FAKE, 8, FAKE, 64, None) == lv.LV_EINVAL
+    assert pe(FAKE, 10, 768, FAKE, 160, FAKE, 3, FAKE, 192, None) == lv.LV_EINVAL
+    assert pe(FAKE, 10, 768, FAKE, 160, FAKE, 8, FAKE, 164, None) == lv.LV_EINVAL
+    assert pe(FAKE, 10, 768, FAKE, 160, FAKE, 8, FAKE, 170, None) == lv.LV_EINVAL
+    assert pe(FAKE, 10, 12, FAKE, 160, FAKE, 8, FAKE, 192, None) == lv.LV_EINVAL
+    assert pe(FAKE, -1, 768, FAKE, 160, FAKE, 8, FAKE, 192, None) == lv.LV_EINVAL
+    assert pe(FAKE, 10, 768, FAKE, 160, None, 8, FAKE, 192, None) == lv.LV_EINVAL
+    assert pe(FAKE, 10, 768, FAKE, 160, FAKE, 8, None, 192, None) == lv.LV_EINVAL
+    assert pe(FAKE, 0, 768, FAKE, 160, FAKE, 8, FAKE, 192, None) == lv.LV_OK
     # second level: same checks, d <= 1008 and rows of exactly the level-2 width
     rb = lib.lv_secondary_row_bytes(32, lv.LV_LVQ8_LEVEL2)
     assert lib.lv_lvq_encode_level2(FAKE, 10, 32, FAKE, 3, FAKE, 64, FAKE, rb, None) == lv.LV_EINVAL

@@ -42,6 +42,45 @@ def test_lvq_encode_bit_exact(lv, bits, d, n):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("D,d,bits,rows,stride", [
+    (768, 160, 8, 3001, 192), (512, 128, 4, 2049, 96), (64, 8, 4, 65, 64),
+    (128, 256, 8, 300, 512), (96, 40, 8, 17, 52), (1024, 256, 4, 1000, 136), (64, 32, 8, 1, 64)])
+def test_project_encode_equals_project_then_encode(lv, D, d, bits, rows, stride):
+    """The one-pass database encoding writes exactly the records of the
+    projection followed by the LVQ encoder, and the oracle's encoding of the
+    device projection (ragged row tails, d short of a whole 32-column tile,
+    strides with padding, a zero row with mu = 0 giving delta = 0)."""
+    rng = np.random.default_rng(D + d + bits)
+    V = (rng.standard_normal((rows, D)) * rng.uniform(0.1, 4, (rows, 1))).astype(np.float32)
+    mu = (0.2 * rng.standard_normal(d)).astype(np.float32)
+    if rows > 5:
+        V[5] = 0.0
+        mu[:] = 0.0
+    M = torch.from_numpy(lv.lv_to_bf16(rng.standard_normal((d, D)) / np.sqrt(D)).view(np.int16))
+    Vd, Md, mud = torch.from_numpy(V).to(DEV), M.to(DEV), torch.from_numpy(mu).to(DEV)
+    Y = torch.empty((rows, d), dtype=torch.float32, device=DEV)
+    lv.lv_project(Vd, Md, Y)
+    two = torch.full((rows, stride), 0xAB, dtype=torch.uint8, device=DEV)
+    lv.lv_lvq_encode(Y, mud, bits, two)
+    one = torch.full((rows, stride), 0xCD, dtype=torch.uint8, device=DEV)
+    lv.lv_project_encode(Vd, Md, mud, bits, one)
+    torch.cuda.synchronize()
+    got = one.cpu().numpy()
+    assert np.array_equal(got, two.cpu().numpy())
+    c, delta, lo = olvq.encode(Y.cpu().numpy(), mu, bits)
+    assert np.array_equal(got, olvq.pack_records(c, delta, lo, bits, stride))
+    if rows > 5:
+        assert delta[5] == 0.0 and not got[5, :d * bits // 8].any()
+
+
+def test_project_encode_empty(lv):
+    V = torch.zeros((0, 64), device=DEV)
+    M = torch.zeros((32, 64), dtype=torch.int16, device=DEV)
+    mu = torch.zeros(32, device=DEV)
+    lv.lv_project_encode(V, M, mu, 8, torch.zeros((0, 64), dtype=torch.uint8, device=DEV))
+    torch.cuda.synchronize()
+
+
 def test_lvq_encode_empty_and_errors(lv):
     Y = torch.zeros((0, 16), device=DEV)
     mu = torch.zeros(16, device=DEV)
