@@ -354,6 +354,198 @@ __global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g, int sps, floa
     }
 }
 
+// ---- tiled kernel: TBM x TBN output tile per workgroup of WM x WN
+// wavefronts (each a (TBM / WM) x (TBN / WN) block of 32 x 32 MFMA tiles),
+// K steps of TK with the next step's float32 operands in registers during
+// the current step's products, two LDS buffers, one barrier per step.
+// SPLIT: both parts of every operand (hi, lo) are staged in the same step
+// and each fragment pair takes the three products hi*hi, hi*lo, lo*hi, so
+// the operands are read and converted once (not once per part).
+constexpr int TK = 32;
+constexpr int TLD = TK + 8;  // LDS row (bf16 elements): 80 bytes
+
+template <int ROWS, int THREADS, bool KCONT>
+struct TileFrag {
+  // float4 pieces of a ROWS x TK tile per thread
+  static constexpr int kPer = ROWS * TK / 4 / THREADS;
+  float4 v[kPer];
+};
+
+// Global -> registers.  k-contiguous: piece f (row f / 8, k 4 (f % 8)), so
+// eight consecutive threads read one row's 128 bytes.  m-contiguous: unit u
+// (k rows 2 kp and 2 kp + 1, m 4 mq ..), two pieces per unit.
+template <int ROWS, int THREADS, bool KCONT>
+__device__ __forceinline__ void tload(const float *__restrict__ X, int64_t ld, int rows,
+                                      int kdim, int r0, int k0,
+                                      TileFrag<ROWS, THREADS, KCONT> &f, int tid) {
+  constexpr int P = TileFrag<ROWS, THREADS, KCONT>::kPer;
+  if constexpr (KCONT) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int pc = tid + THREADS * j;
+      const int r = pc >> 3, gk = k0 + 4 * (pc & 7);
+      const int gr = r0 + r;
+      const bool rok = gr < rows;
+      const float *p = X + (int64_t)(rok ? gr : 0) * ld + (gk < kdim ? gk : 0);
+      f.v[j] = load4(p, rok && gk + 3 < kdim, rok && gk < kdim, rok && gk + 1 < kdim,
+                     rok && gk + 2 < kdim, false);
+    }
+  } else {
+    constexpr int MQ = ROWS / 4;  // float4 pieces along m
+#pragma unroll
+    for (int j = 0; j < P / 2; ++j) {
+      const int u = tid + THREADS * j;
+      const int kp = u / MQ, mq = u % MQ;
+      const int gm = r0 + 4 * mq;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int gk = k0 + 2 * kp + h;
+        const bool kok = gk < kdim;
+        const float *p = X + (int64_t)(kok ? gk : 0) * ld + (gm < rows ? gm : 0);
+        f.v[2 * j + h] = load4(p, kok && gm + 3 < rows, kok && gm < rows, kok && gm + 1 < rows,
+                               kok && gm + 2 < rows, false);
+      }
+    }
+  }
+}
+
+// Registers -> LDS tile S[row][k] (bfloat16 hi part, or the remainders' bf16).
+template <int ROWS, int THREADS, bool KCONT, bool LO>
+__device__ __forceinline__ void tstore(const TileFrag<ROWS, THREADS, KCONT> &f, uint16_t *S,
+                                       int tid) {
+  constexpr int P = TileFrag<ROWS, THREADS, KCONT>::kPer;
+  if constexpr (KCONT) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int pc = tid + THREADS * j;
+      const int r = pc >> 3, kq = pc & 7;
+      const float4 a = f.v[j];
+      *reinterpret_cast<uint2 *>(S + r * TLD + 4 * kq) =
+          make_uint2(pack_bf16<LO>(a.x, a.y), pack_bf16<LO>(a.z, a.w));
+    }
+  } else {
+    constexpr int MQ = ROWS / 4;
+#pragma unroll
+    for (int j = 0; j < P / 2; ++j) {
+      const int u = tid + THREADS * j;
+      const int kp = u / MQ, mq = u % MQ;
+      const float4 a = f.v[2 * j], b = f.v[2 * j + 1];  // k rows 2 kp and 2 kp + 1
+      uint32_t *d = reinterpret_cast<uint32_t *>(S + (4 * mq) * TLD + 2 * kp);
+      d[0] = pack_bf16<LO>(a.x, b.x);
+      d[TLD / 2] = pack_bf16<LO>(a.y, b.y);
+      d[TLD] = pack_bf16<LO>(a.z, b.z);
+      d[3 * TLD / 2] = pack_bf16<LO>(a.w, b.w);
+    }
+  }
+}
+
+template <int TBM, int TBN, int WM, int WN, bool AK, bool BKC, bool SPLIT>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int sps,
+                                                                  float *part) {
+  constexpr int THREADS = 64 * WM * WN;
+  constexpr int NP = SPLIT ? 2 : 1;   // operand parts staged per step
+  constexpr int IM = TBM / WM / 32;   // MFMA tiles per wavefront along m
+  constexpr int JN = TBN / WN / 32;   // and along n
+  constexpr int SA = TBM * TLD, SB = TBN * TLD;
+  __shared__ __align__(16) uint16_t tsm[2 * NP * (SA + SB)];
+  uint16_t *As = tsm;                       // [2][NP][SA]
+  uint16_t *Bs = tsm + 2 * NP * SA;         // [2][NP][SB]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
+  const int wm = (wave / WN) * (TBM / WM), wn = (wave % WN) * (TBN / WN);
+  const int r = lane & 31, kh = lane >> 5;
+  f32x16 acc[IM][JN];
+#pragma unroll
+  for (int i = 0; i < IM; ++i)
+#pragma unroll
+    for (int j = 0; j < JN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int nk_all = (g.K + TK - 1) / TK;
+  const int t0 = (int)blockIdx.z * sps;
+  const int nk = (t0 + sps < nk_all ? t0 + sps : nk_all) - t0;
+  TileFrag<TBM, THREADS, AK> fa;
+  TileFrag<TBN, THREADS, BKC> fb;
+  auto put = [&](int b) {
+    tstore<TBM, THREADS, AK, false>(fa, As + (b * NP) * SA, tid);
+    tstore<TBN, THREADS, BKC, false>(fb, Bs + (b * NP) * SB, tid);
+    if constexpr (SPLIT) {
+      tstore<TBM, THREADS, AK, true>(fa, As + (b * NP + 1) * SA, tid);
+      tstore<TBN, THREADS, BKC, true>(fb, Bs + (b * NP + 1) * SB, tid);
+    }
+  };
+  if (nk > 0) {
+    tload<TBM, THREADS, AK>(g.A, g.lda, g.M, g.K, m0, t0 * TK, fa, tid);
+    tload<TBN, THREADS, BKC>(g.B, g.ldb, g.N, g.K, n0, t0 * TK, fb, tid);
+    put(0);
+  }
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) {
+    const int cur = t & 1;
+    const bool more = t + 1 < nk;
+    if (more) {
+      tload<TBM, THREADS, AK>(g.A, g.lda, g.M, g.K, m0, (t0 + t + 1) * TK, fa, tid);
+      tload<TBN, THREADS, BKC>(g.B, g.ldb, g.N, g.K, n0, (t0 + t + 1) * TK, fb, tid);
+    }
+    const uint16_t *ac = As + (cur * NP) * SA;
+    const uint16_t *bc = Bs + (cur * NP) * SB;
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 16) {
+      bf16x8 a[NP][IM], b[NP][JN];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+#pragma unroll
+        for (int i = 0; i < IM; ++i)
+          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(
+                                                   ac + q * SA + (wm + 32 * i + r) * TLD + ks +
+                                                   8 * kh));
+#pragma unroll
+        for (int j = 0; j < JN; ++j)
+          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(
+                                                   bc + q * SB + (wn + 32 * j + r) * TLD + ks +
+                                                   8 * kh));
+      }
+#pragma unroll
+      for (int i = 0; i < IM; ++i)
+#pragma unroll
+        for (int j = 0; j < JN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+          if constexpr (SPLIT) {
+            acc[i][j] =
+                __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+            acc[i][j] =
+                __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+          }
+        }
+    }
+    if (more) put(cur ^ 1);  // that buffer was last read before the previous barrier
+    __syncthreads();
+  }
+  float *pz = part ? part + (int64_t)blockIdx.z * g.M * g.N : nullptr;
+#pragma unroll
+  for (int i = 0; i < IM; ++i)
+#pragma unroll
+    for (int j = 0; j < JN; ++j) {
+      const int col = n0 + wn + 32 * j + r;
+      if (col >= g.N) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = m0 + wm + 32 * i + 8 * (e >> 2) + 4 * kh + (e & 3);
+        if (row >= g.M) continue;
+        const float v = g.alpha * acc[i][j][e];
+        if (pz) {
+          pz[(int64_t)row * g.N + col] = v;
+        } else {
+          float *c = g.C + (int64_t)row * g.ldc + col;
+          *c = g.beta == 0.f ? v : v + g.beta * *c;
+        }
+      }
+    }
+}
+
 // C = sum over z of part[z] (in order z = 0, 1, ...) + beta * C.
 __global__ __launch_bounds__(256) void split_sum_kernel(const float *__restrict__ part, int nz,
                                                         GemmArgs g) {
@@ -378,6 +570,20 @@ struct VecLaunch {
   template <bool AK, bool BKC, bool SPLIT>
   void go() {
     hipLaunchKernelGGL((gemm_vec_kernel<AK, BKC, SPLIT>), grid, dim3(256), 0, s, g, sps, part);
+  }
+};
+
+template <int TBM, int TBN, int WM, int WN>
+struct TileLaunch {
+  const GemmArgs &g;
+  dim3 grid;
+  int sps;
+  float *part;
+  hipStream_t s;
+  template <bool AK, bool BKC, bool SPLIT>
+  void go() {
+    hipLaunchKernelGGL((gemm_tile_kernel<TBM, TBN, WM, WN, AK, BKC, SPLIT>), grid,
+                       dim3(64 * WM * WN), 0, s, g, sps, part);
   }
 };
 
@@ -415,14 +621,32 @@ bool vec_ok(const float *p, int64_t ld) {
 
 size_t gemm_split_floats(int64_t M, int64_t N) { return (size_t)kMaxSplit * M * N; }
 
+// Tile of the large-product kernel (no split precision): 256 x 256 per
+// workgroup of 8 wavefronts, each 128 x 64; used when it still gives at
+// least this many workgroups.
+constexpr int kBigTile = 256;
+constexpr int kBigTileMinTiles = 128;
+
 int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *split_ws,
          size_t split_floats) {
   if (g.M <= 0 || g.N <= 0) return LV_OK;
   const dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
   if (vec_ok(g.A, g.lda) && vec_ok(g.B, g.ldb)) {
+    const bool split = g.split != 0;
+    const int big_tiles = ((g.M + kBigTile - 1) / kBigTile) * ((g.N + kBigTile - 1) / kBigTile);
+    if (!split && big_tiles >= kBigTileMinTiles) {
+      const dim3 gb((unsigned)((g.N + kBigTile - 1) / kBigTile),
+                    (unsigned)((g.M + kBigTile - 1) / kBigTile), 1u);
+      TileLaunch<kBigTile, kBigTile, 2, 4> f{g, gb, (g.K + TK - 1) / TK > 0 ? (g.K + TK - 1) / TK : 1,
+                                          nullptr, s};
+      dispatch_layout(a_kcont, b_kcont, false, f);
+      LV_CHECK_LAUNCH();
+      return LV_OK;
+    }
     // few output tiles and a long K: split K so that about 128 workgroups run
     const int tiles = (int)(grid.x * grid.y);
-    const int nk = (g.K + VK - 1) / VK;
+    const int step = split ? TK : VK;  // K per step of the kernel used
+    const int nk = (g.K + step - 1) / step;
     int parts = 1;
     if (split_ws && tiles < 64 && g.K >= 512) {
       parts = 128 / tiles;
@@ -434,8 +658,13 @@ int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *sp
     parts = nk > 0 ? (nk + sps - 1) / sps : 1;
     float *part = parts > 1 ? split_ws : nullptr;
     const dim3 gz(grid.x, grid.y, (unsigned)parts);
-    VecLaunch f{g, gz, sps, part, s};
-    dispatch_layout(a_kcont, b_kcont, g.split != 0, f);
+    if (split) {  // both parts staged once per step
+      TileLaunch<BM, BN, 2, 2> f{g, gz, sps, part, s};
+      dispatch_layout(a_kcont, b_kcont, true, f);
+    } else {
+      VecLaunch f{g, gz, sps, part, s};
+      dispatch_layout(a_kcont, b_kcont, false, f);
+    }
     if (part) {
       const int64_t mn = (int64_t)g.M * g.N;
       const unsigned blocks = (unsigned)((mn + 255) / 256 < 2048 ? (mn + 255) / 256 : 2048);

@@ -48,6 +48,25 @@ def test_gemm_exact_on_small_integers(lv, M, N, K, ak, bk):
     assert np.array_equal(C.cpu().numpy().astype(np.float64), 2.0 * a @ b.T - c0)
 
 
+# products with at least 128 tiles of 256 x 256 take the large-tile kernel:
+# ragged m, n and k edges, every operand layout, exact on small integers
+@pytest.mark.parametrize("M,N,K", [(3000, 2900, 70), (4096, 2048, 256)])
+@pytest.mark.parametrize("ak,bk", [(True, True), (True, False), (False, True), (False, False)])
+def test_gemm_large_tile_exact_on_small_integers(lv, M, N, K, ak, bk):
+    rng = np.random.default_rng(M + N + K + 2 * ak + bk)
+    a = rng.integers(-6, 7, size=(M, K)).astype(np.float32)
+    b = rng.integers(-6, 7, size=(N, K)).astype(np.float32)
+    c0 = rng.integers(-3, 4, size=(M, N)).astype(np.float32)
+    A = a if ak else np.ascontiguousarray(a.T)
+    B = b if bk else np.ascontiguousarray(b.T)
+    C = torch.from_numpy(c0).to(DEV)
+    lv.lv_gemm(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV), C, M, N, K, a_kcont=ak,
+               b_kcont=bk, alpha=2.0, beta=-1.0)
+    torch.cuda.synchronize()
+    want = 2.0 * (a.astype(np.float64) @ b.astype(np.float64).T) - c0
+    assert np.array_equal(C.cpu().numpy().astype(np.float64), want)
+
+
 # few output tiles and K >= 512 with a workspace: the product is split over K
 # (ragged last part included) and the parts added in order; integer operands
 # keep every partial sum exact, so the result must equal a @ b^T exactly.
