@@ -27,6 +27,7 @@ import os
 import sys
 import threading
 import time
+from dataclasses import replace
 
 import numpy as np
 
@@ -54,10 +55,15 @@ def parse():
     ap.add_argument("--launch", choices=("per_query", "persistent"), default="per_query",
                     help="batched traversal launch when --hash-slots is given")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sec", choices=("f16", "lvq8", "resid"), default="f16",
-                    help="secondary vectors: float16 (the benchmark configuration), LVQ-8, or "
-                         "float16 residual coordinates only (D - d per vector); the last two "
-                         "without CPU baseline")
+    ap.add_argument("--no-ood", action="store_true",
+                    help="skip the cross-modal workload's sub-record (ood-1m-512)")
+    ap.add_argument("--sec", choices=("f16", "lvq8", "resid", "level2"), default="f16",
+                    help="secondary vectors: float16 (the benchmark configuration), LVQ-8, "
+                         "float16 residual coordinates only (D - d per vector), or the 8-bit "
+                         "second level of the primaries' LVQ (two-level LVQ; LVQ4x8 with "
+                         "--bits 4); all but the first without CPU baseline")
+    ap.add_argument("--bits", type=int, choices=(0, 4, 8), default=0,
+                    help="LVQ bits of the primaries (0: the workload's)")
     ap.add_argument("--cpu-sample", type=int, default=10000)
     ap.add_argument("--only-steps", action="store_true",
                     help="skip the sweep refinement (profiling runs)")
@@ -577,6 +583,18 @@ def mfma_report(lv, torch, reps=10):
         ms = timed(lambda: lv.lv_project(V, M, Y))
         out[name] = dict(rows=rows, D=D, d=d, **entry(ms, 2.0 * rows * D * d,
                                                          4.0 * rows * (D + d) + 2.0 * d * D))
+        if rows == 1_000_000:
+            # one pass: LVQ-8 records (192-byte stride) straight from the products,
+            # against the projection followed by the encoder
+            mu = torch.randn(d, device=dev, generator=g) * 0.1
+            rec = torch.empty((rows, 192), dtype=torch.uint8, device=dev)
+            ms1 = timed(lambda: lv.lv_project_encode(V, M, mu, 8, rec))
+            ms_enc = timed(lambda: lv.lv_lvq_encode(Y, mu, 8, rec))
+            out["database_projection_encode"] = dict(
+                rows=rows, D=D, d=d, bits=8, record_stride=192,
+                two_kernels_ms=ms + ms_enc, encode_kernel_ms=ms_enc,
+                **entry(ms1, 2.0 * rows * D * d, 4.0 * rows * D + 2.0 * d * D + 168.0 * rows))
+            del mu, rec
         del V, Y
     bq, bx, D2, d2 = 1024, 4096, 768, 128
     A = torch.randn((d2, D2), device=dev, generator=g) * 0.03
@@ -708,6 +726,8 @@ def main():
     wl = gen.WORKLOADS[args.workload or "id-1m-768"]
     if args.n:
         wl = wl.scaled(N=args.n)
+    if args.bits:
+        wl = replace(wl, bits=args.bits)
     k = wl.k
     t0 = time.time()
     mix = gen.mixture(wl)
@@ -766,14 +786,21 @@ def main():
                           device=dev)
     elif resid:
         sec = torch.empty((wl.N, wl.D - wl.d), dtype=torch.float16, device=dev)
+    elif args.sec == "level2":
+        sec = torch.empty((wl.N, lv.lv_secondary_row_bytes(wl.d, lv.LV_LVQ8_LEVEL2)),
+                          dtype=torch.uint8, device=dev)
     else:
         sec = torch.empty((wl.N, wl.D), dtype=torch.float16, device=dev)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
-    lv.lv_project(Xd, Pb, Y)
-    ev1.record()
-    lv.lv_lvq_encode(Y, mud, wl.bits, rec)
+    if args.sec == "level2":  # the second level needs the reduced vectors themselves
+        lv.lv_project(Xd, Pb, Y)
+        lv.lv_lvq_encode(Y, mud, wl.bits, rec)
+        ev1.record()
+    else:  # records in one pass (the reduced vectors never go through memory)
+        lv.lv_project_encode(Xd, Pb, mud, wl.bits, rec)
+        ev1.record()
     if smud is not None:
         lv.lv_lvq_encode(Xd, smud, 8, sec)
     elif resid:
@@ -782,6 +809,8 @@ def main():
         lv.lv_project(Xd, Pp, Yr)
         lv.lv_to_f16(Yr, sec)
         del Yr, Pp
+    elif args.sec == "level2":
+        lv.lv_lvq_encode_level2(Y, mud, wl.bits, rec, sec)
     else:
         lv.lv_to_f16(Xd, sec)
     torch.cuda.synchronize()
@@ -818,7 +847,7 @@ def main():
                 f"{g['oracle_sample']['s']:.1f}s")
     log(f"graph ready at {time.time() - t0:.1f}s (build {g['graph_s']:.1f}s)")
     index = lv.Index(rec, mud, sec, adjd, entry, wl.bits, wl.d, A_bf16=Pqb, sec_mu=smud,
-                     residual=resid)
+                     residual=resid, level2=args.sec == "level2")
 
     # ---- request stream over the test queries (uneven batches)
     m = len(Q)
@@ -923,8 +952,10 @@ def main():
     n_exp, n_dist = c[:, 0], c[:, 1]
     n_rr = np.minimum(L_star, n_dist)
     code_bytes = wl.d * wl.bits // 8
-    # bytes of one secondary row: float16, LVQ-8 codes + delta + lo, or residual float16
-    sec_row = wl.D + 8 if smud is not None else (2 * (wl.D - wl.d) if resid else 2 * wl.D)
+    # bytes of one secondary row: float16, LVQ-8 codes + delta + lo, residual float16, or
+    # second-level codes + delta2 + lo2
+    sec_row = (wl.D + 8 if smud is not None else 2 * (wl.D - wl.d) if resid else
+               wl.d + 8 if args.sec == "level2" else 2 * wl.D)
     bytes_q = (4 * wl.D + n_exp * 4 * wl.R + n_dist * (code_bytes + 8) + n_rr * sec_row
                + 8 * k)
     alg_bytes_total = float(bytes_q.sum())
@@ -1118,6 +1149,14 @@ def main():
         if cpu["sample"].startswith("all") and abs(cpu["recall"] - rec_star) > 0.005:
             log(f"WARNING: GPU recall {rec_star:.4f} vs oracle {cpu['recall']:.4f}")
 
+    ood = None
+    if (not args.no_ood and wl.name == "id-1m-768" and not args.n and args.sec == "f16"
+            and not args.bits):
+        # the cross-modal workload as a compact sub-record (its own index)
+        index.close()
+        torch.cuda.empty_cache()
+        ood = ood_report(lv, torch, args)
+
     out = {
         "metric": ("QPS at 10-recall@10=0.90 (1M x 768, d=160), batched vs plain; HBM GB/s"
                    if wl.name == "id-1m-768" and not args.n else
@@ -1177,7 +1216,7 @@ def main():
                                           "traversal start) / K; the launches overlap, so "
                                           "this is the throughput per launch, not one "
                                           "launch's duration"}},
-        "index_build": {"db_projection_ms": db_proj_ms, "graph_build_s": g.get("graph_s"),
+        "index_build": {"db_projection_encode_ms": db_proj_ms, "graph_build_s": g.get("graph_s"),
                         "graph": g.get("kind", "host builder, float16 vectors"),
                         "graph_build_threads": (None if args.graph == "gpu" else
                                                 int(os.environ.get("OMP_NUM_THREADS") or
@@ -1191,8 +1230,199 @@ def main():
         "cpu_baseline": cpu,
         "traversal_compare": variant,
         "small_batches": small_batches,
+        "ood": ood,
     }
     print(json.dumps(out))
+
+
+def ood_report(lv, torch, args, steps=10, in_flight=3, target=0.90, expand=3,
+               hash_slots=2048, cpu_sample=1000):
+    """Compact run of the cross-modal workload (ood-1m-512: 1M x 512 database,
+    10,000 out-of-distribution test queries): LeanVec-OOD fit (Algorithm 1, host
+    float64, on 10,000 learning queries and a 100,000-vector sample), A q for the
+    queries and B x for the database on the GPU, LVQ-4 primaries (d = 128),
+    float16 secondaries, the host-built graph (R = 64).  The smallest window
+    reaching 10-recall@10 = 0.90 is found with the plain search, then batched
+    steps over the uneven request stream run one after another (each launch's
+    own duration, for the roofline) and three in flight (the throughput).  The
+    float64 oracle, with its own Frank-Wolfe fit and encoding, searches a sample
+    of the queries at the same window for its recall."""
+    from synth import gen
+
+    dev = torch.device("cuda:0")
+    wl = gen.WORKLOADS["ood-1m-512"]
+    k = wl.k
+    t0 = time.time()
+    mix = gen.mixture(wl)
+    X = gen.database(wl, mix)
+    Q = gen.queries(wl, "test", mix=mix)
+    Ql = gen.queries(wl, "learn", mix=mix)
+    g = {}
+    th = threading.Thread(target=build_graph_cached, args=(wl, X, g))
+    th.start()
+    rng = np.random.default_rng(7)
+    ns = min(wl.N, 100_000)
+    sub = np.sort(rng.choice(wl.N, size=ns, replace=False))
+    Xs = np.ascontiguousarray(X[sub])
+    KX = np.zeros((wl.D, wl.D))
+    ssum = np.zeros(wl.D)
+    lv.lv_second_moment(Xs, KX, ssum)
+    KQ = np.zeros((wl.D, wl.D))
+    lv.lv_second_moment(Ql, KQ)
+    tf = time.time()
+    A, B, info = lv.lv_fit_ood(KQ, len(Ql), KX, ns, wl.d)
+    fit = {"iters": info["iters"], "seconds": time.time() - tf}
+    mu = lv.lv_mean_reduced(B, ssum, ns)
+    Ab = torch.from_numpy(lv.lv_to_bf16(A).view(np.int16)).to(dev)
+    Bb = torch.from_numpy(lv.lv_to_bf16(B).view(np.int16)).to(dev)
+    mud = torch.from_numpy(mu).to(dev)
+    Xd = torch.from_numpy(X).to(dev)
+    Y = torch.empty((wl.N, wl.d), dtype=torch.float32, device=dev)
+    lv.lv_project(Xd, Bb, Y)
+    rec = torch.empty((wl.N, lv.lv_record_stride(wl.d, wl.bits)), dtype=torch.uint8, device=dev)
+    lv.lv_lvq_encode(Y, mud, wl.bits, rec)
+    sec = torch.empty((wl.N, wl.D), dtype=torch.float16, device=dev)
+    lv.lv_to_f16(Xd, sec)
+    torch.cuda.synchronize()
+    truth = ground_truth_gpu(torch, Xd, Q, k)
+    del Y, Xd
+    torch.cuda.empty_cache()
+    th.join()
+    adj, entry = g["adj"], g["entry"]
+    adjd = torch.from_numpy(adj.view(np.int32)).to(dev)
+    index = lv.Index(rec, mud, sec, adjd, entry, wl.bits, wl.d, A_bf16=Ab)
+    log(f"ood index ready at {time.time() - t0:.1f}s (graph {g['graph_s']:.1f}s)")
+    m = len(Q)
+    Qd = torch.from_numpy(Q).to(dev)
+    Qp = torch.empty((m, wl.d), dtype=torch.float32, device=dev)
+    lv.lv_project(Qd, Ab, Qp)
+    ids = torch.empty((m, k), dtype=torch.int32, device=dev)
+    sc = torch.empty((m, k), dtype=torch.float32, device=dev)
+
+    def rec_at(L):
+        lv.lv_search_projected(index, Qd, Qp, k, L, ids, sc, hash_slots=hash_slots,
+                               expand=expand)
+        torch.cuda.synchronize()
+        return recall(ids.cpu().numpy().view(np.uint32).astype(np.int64), truth, k)
+
+    sweep = {}
+    lo_, hi_ = 10, 256
+    sweep[hi_] = rec_at(hi_)
+    while sweep[hi_] < target and hi_ < 1024:
+        lo_, hi_ = hi_, min(1024, 2 * hi_)
+        sweep[hi_] = rec_at(hi_)
+    while hi_ - lo_ > 1:  # smallest window reaching the target
+        mid = (lo_ + hi_) // 2
+        sweep[mid] = rec_at(mid)
+        if sweep[mid] >= target:
+            hi_ = mid
+        else:
+            lo_ = mid
+    L = hi_
+    cnt = torch.zeros((m, 2), dtype=torch.int32, device=dev)
+    lv.lv_search_projected(index, Qd, Qp, k, L, ids, sc, cnt, hash_slots=8192, expand=expand)
+    torch.cuda.synchronize()
+    c = cnt.cpu().numpy().astype(np.float64)
+    n_rr = np.minimum(L, c[:, 1])
+    bytes_q = (4 * wl.D + c[:, 0] * 4 * wl.R + c[:, 1] * (wl.d * wl.bits // 8 + 8)
+               + n_rr * 2 * wl.D + 8 * k)
+    alg = float(bytes_q.sum())
+    rs = np.random.Generator(np.random.PCG64(401))
+    sizes, left = [], m
+    while left > 0:
+        b = int(min(left, rs.integers(1, 4097)))
+        sizes.append(b)
+        left -= b
+    reqs = [(0, k, L, b) for b in sizes]
+    multi = lv.Multi([index])
+    batch = lv.Batch(multi, max_requests=len(reqs), max_queries=m, max_L=L,
+                     hash_slots=hash_slots, expand=expand)
+    stream = torch.cuda.current_stream()
+    strs = [stream] + [torch.cuda.Stream() for _ in range(in_flight - 1)]
+    outs = [(torch.empty(m * k, dtype=torch.int32, device=dev),
+             torch.empty(m * k, dtype=torch.float32, device=dev)) for _ in range(in_flight)]
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    for _ in range(2):
+        batch.step(reqs, Qd, *outs[0])
+    torch.cuda.synchronize()
+    ser = [(ev(), ev()) for _ in range(steps)]
+    for i in range(steps):  # serial: each launch's own duration
+        batch.step(reqs, Qd, *outs[0], events=ser[i])
+    torch.cuda.synchronize()
+    launch_ms = sum(a.elapsed_time(b) for a, b in ser) / steps
+    got = outs[0][0].view(m, k).cpu().numpy().view(np.uint32).astype(np.int64)
+    rec_b = recall(got, truth, k)
+    for s_ in strs[1:]:
+        s_.wait_stream(stream)
+    pip = [(ev(), ev()) for _ in range(steps)]
+    p0, p1 = ev(), ev()
+    p0.record(stream)
+    for s_ in strs[1:]:
+        s_.wait_event(p0)
+    for i in range(steps):
+        batch.step(reqs, Qd, *outs[i % in_flight], stream=strs[i % in_flight], events=pip[i])
+    for s_ in strs[1:]:
+        stream.wait_stream(s_)
+    p1.record(stream)
+    torch.cuda.synchronize()
+    ms = p0.elapsed_time(p1) / steps
+    span = pip[0][0].elapsed_time(pip[-1][1]) / steps
+    batch.close()
+    multi.close()
+    # the oracle at the same window on a sample, with its own fit and encoding
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import fit as ofit
+        from oracle import lvq as olvq
+        from oracle import search as osearch
+
+        t = time.perf_counter()
+        Ao, Bo, _ = ofit.frank_wolfe(ofit.second_moment(Ql), len(Ql), ofit.second_moment(Xs),
+                                     len(Xs), wl.d)
+        muo = ofit.mean_reduced(Xs, Bo).astype(np.float32)
+        Yo = np.empty((wl.N, wl.d), dtype=np.float32)
+        for lo in range(0, wl.N, 1 << 17):
+            Yo[lo:lo + (1 << 17)] = ofit.project(X[lo:lo + (1 << 17)], Bo)
+        codes, delta, lo4 = olvq.encode(Yo, muo, wl.bits)
+        oidx = osearch.Index(adj, entry, codes, delta, lo4, muo, X.astype(np.float16))
+        n = min(cpu_sample, m)
+        Qpo = ofit.project(Q[:n], Ao).astype(np.float32)
+        procs = max(1, min(16, len(os.sched_getaffinity(0))))
+        t1 = time.perf_counter()
+        o_ids, _, _ = osearch.search_many(oidx, Q[:n], Qpo, k, L, procs=procs, chunk=16,
+                                          expand=expand)
+        dt = time.perf_counter() - t1
+        cpu = {"value": n / dt, "unit": "queries/s", "cores": procs, "kind": "oracle",
+               "sample": f"first {n} of {m} test queries at window L={L}, {expand} expansions "
+                         "per iteration, float64 oracle with its own Frank-Wolfe fit and "
+                         "encoding, one process per core",
+               "recall": recall(np.asarray(o_ids).astype(np.int64), truth[:n], k),
+               "gpu_recall_same_sample": recall(got[:n], truth[:n], k),
+               "setup_s": t1 - t}
+        log(f"ood oracle: recall {cpu['recall']:.4f} on {n} queries")
+    index.close()
+    frac = alg / (launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS
+    out = {"workload": wl.name, "N": wl.N, "D": wl.D, "d": wl.d, "lvq_bits": wl.bits,
+           "secondary": "f16", "R": wl.R, "k": k, "queries": m, "L": L, "recall_at_L": rec_b,
+           "fit": dict(kind="ood (Frank-Wolfe, Algorithm 1)", **fit), "expand": expand,
+           "visited_slots": hash_slots, "qps": m / (ms / 1e3), "ms_per_step": ms,
+           "window_sweep": {str(x): r for x, r in sorted(sweep.items())},
+           "per_query": {"expansions": float(c[:, 0].mean()),
+                         "primary_scorings": float(c[:, 1].mean()),
+                         "alg_bytes": float(bytes_q.mean())},
+           "roofline": {"bound": "hbm", "achieved": frac * HBM_PEAK_GBS, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": frac, "alg_bytes_per_launch": alg,
+                        "launch_ms": launch_ms,
+                        "kernel": "batched_kernel (LVQ-4 records in 96-byte slots)",
+                        "launch_timing": "average of the serial launches' own durations",
+                        "pipelined": {"launch_ms": span,
+                                      "frac": alg / (span / 1e3) / 1e9 / HBM_PEAK_GBS}},
+           "cpu_baseline": cpu, "prep_s": time.time() - t0}
+    log(f"ood: L={L} recall {rec_b:.4f}, {out['qps']:.0f} QPS, frac {frac:.3f}")
+    return out
 
 
 def small_batch_report(lv, torch, index, Qd, Qp, k, L, hs, expands, reps=20):

@@ -582,8 +582,11 @@ struct TileLaunch {
   hipStream_t s;
   template <bool AK, bool BKC, bool SPLIT>
   void go() {
-    hipLaunchKernelGGL((gemm_tile_kernel<TBM, TBN, WM, WN, AK, BKC, SPLIT>), grid,
-                       dim3(64 * WM * WN), 0, s, g, sps, part);
+    // split precision runs on 128 x 128 tiles only (the large tile has no
+    // registers left for the second parts)
+    if constexpr (!SPLIT || TBM * TBN <= 128 * 128)
+      hipLaunchKernelGGL((gemm_tile_kernel<TBM, TBN, WM, WN, AK, BKC, SPLIT>), grid,
+                         dim3(64 * WM * WN), 0, s, g, sps, part);
   }
 };
 
