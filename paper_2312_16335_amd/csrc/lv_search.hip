@@ -551,18 +551,32 @@ __device__ __forceinline__ const float *rerank_query(const IndexView &ix, const 
 }
 
 // Re-rank entries [0, n) of ids/out with the index's kind of secondaries.
+// PAIRS = false keeps every row kind on the one-row path (the team launch,
+// whose wavefronts re-rank short slices and whose registers the paired path
+// would overflow).
+template <bool PAIRS = true>
 __device__ __forceinline__ void rerank_any(const IndexView &ix, const float *q,
                                            const uint32_t *ids, double *out, int n, int lane) {
-  if (ix.sec_kind == LV_F16)
-    rerank_pairs_any<LV_F16>(ix, q, ids, out, n, lane);
-  else if (ix.sec_kind == LV_LVQ8)
+  if (ix.sec_kind == LV_F16) {
+    if constexpr (PAIRS)
+      rerank_pairs_any<LV_F16>(ix, q, ids, out, n, lane);
+    else
+      rerank_rows<LV_F16>(ix, q, ids, out, n, lane);
+  } else if (ix.sec_kind == LV_LVQ8) {
     rerank_rows<LV_LVQ8>(ix, q, ids, out, n, lane);
-  else if (ix.sec_kind == LV_F16_RESID)
-    rerank_pairs_any<LV_F16_RESID>(ix, q, ids, out, n, lane);
-  else if (ix.sec_kind == LV_LVQ8_LEVEL2)
+  } else if (ix.sec_kind == LV_F16_RESID) {
+    if constexpr (PAIRS)
+      rerank_pairs_any<LV_F16_RESID>(ix, q, ids, out, n, lane);
+    else
+      rerank_rows<LV_F16_RESID>(ix, q, ids, out, n, lane);
+  } else if (ix.sec_kind == LV_LVQ8_LEVEL2) {
     rerank_rows<LV_LVQ8_LEVEL2>(ix, q, ids, out, n, lane);
-  else
-    rerank_pairs_any<LV_F32>(ix, q, ids, out, n, lane);
+  } else {
+    if constexpr (PAIRS)
+      rerank_pairs_any<LV_F32>(ix, q, ids, out, n, lane);
+    else
+      rerank_rows<LV_F32>(ix, q, ids, out, n, lane);
+  }
 }
 
 // Merge the scored batch (cid/cs[0..nc)) into the window of nl <= L
@@ -799,7 +813,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
         if (nc < 0) {  // -2 - nl: re-rank this wavefront's slice of the window, end
           const int nl = -2 - nc;
           const int r0 = team_slice<16, WQ>(nl, wave);
-          rerank_any(ix, job.q, sm.lid() + r0, sm.ls() + r0,
+          rerank_any<false>(ix, job.q, sm.lid() + r0, sm.ls() + r0,
                      team_slice<16, WQ>(nl, wave + 1) - r0, lane);
           __syncthreads();  // slices re-ranked
           return;
@@ -990,7 +1004,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
   double *s2 = sm.ls();
   if constexpr (WQ > 1) {
     // the team re-ranks too, a slice of whole 4-row passes each
-    rerank_any(ix, job.q, id2, s2, team_slice<16, WQ>(nl, 1), lane);
+    rerank_any<false>(ix, job.q, id2, s2, team_slice<16, WQ>(nl, 1), lane);
     __syncthreads();  // every slice re-ranked
   } else {
     rerank_any(ix, job.q, id2, s2, nl, lane);
