@@ -650,10 +650,13 @@ int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *sp
     const int tiles = (int)(grid.x * grid.y);
     const int step = split ? TK : VK;  // K per step of the kernel used
     const int nk = (g.K + step - 1) / step;
+    // (split precision: three products per step, so parts of at least 64 of K,
+    // about 256 workgroups in all, and from K = 256 on)
+    const int min_k = split ? 256 : 512, part_k = split ? 64 : 256, target = split ? 256 : 128;
     int parts = 1;
-    if (split_ws && tiles < 64 && g.K >= 512) {
-      parts = 128 / tiles;
-      if (parts > (g.K + 255) / 256) parts = (g.K + 255) / 256;
+    if (split_ws && tiles < 64 && g.K >= min_k) {
+      parts = target / tiles;
+      if (parts > (g.K + part_k - 1) / part_k) parts = (g.K + part_k - 1) / part_k;
       if (parts > kMaxSplit) parts = kMaxSplit;
       while (parts > 1 && (size_t)parts * g.M * g.N > split_floats) --parts;
     }
