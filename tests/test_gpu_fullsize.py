@@ -120,6 +120,31 @@ def test_sampled_records_and_secondaries_bit_exact(lv, full):
     assert np.array_equal(gs.view(np.uint16), full["sec"][rows].view(np.uint16))
 
 
+def test_one_pass_encoding_at_full_size(lv, full):
+    """The benchmark's index records (projection and LVQ encoding in one pass,
+    bfloat16 projection on the device) equal, bit for bit over all 1M rows,
+    the projection followed by the encoder, and on sampled rows the oracle's
+    encoding of the device projection."""
+    wl = full["wl"]
+    Xd = torch.from_numpy(full["X"]).to(DEV)
+    Y = torch.empty((wl.N, wl.d), dtype=torch.float32, device=DEV)
+    lv.lv_project(Xd, full["Pb"], Y)
+    two = torch.empty((wl.N, full["stride"]), dtype=torch.uint8, device=DEV)
+    lv.lv_lvq_encode(Y, full["mud"], wl.bits, two)
+    one = torch.full((wl.N, full["stride"]), 0xCD, dtype=torch.uint8, device=DEV)
+    lv.lv_project_encode(Xd, full["Pb"], full["mud"], wl.bits, one)
+    torch.cuda.synchronize()
+    assert torch.equal(one, two)
+    rng = np.random.default_rng(23)
+    rows = np.unique(np.concatenate([[0, wl.N - 1], rng.choice(wl.N, 2048, replace=False)]))
+    rd = torch.from_numpy(rows).to(DEV)
+    c, delta, lo = olvq.encode(Y[rd].cpu().numpy(), full["mu"], wl.bits)
+    want = olvq.pack_records(c, delta, lo, wl.bits, full["stride"])
+    assert np.array_equal(one[rd].cpu().numpy(), want)
+    del Xd, Y, one, two
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("expand", [1, 3], ids=["one-expansion", "three-expansions"])
 def test_batched_step_equals_plain_and_oracle(lv, full, expand):
     wl, Q, index = full["wl"], full["Q"], full["index"]
