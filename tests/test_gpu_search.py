@@ -446,15 +446,16 @@ def test_residual_secondaries_batched_equals_plain(lv):
     index.close()
 
 
-def _level2_case(lv, name, bits, N=6000, full_d=False):
+def _level2_case(lv, name, bits, N=6000, d=0):
     """A workload with `bits`-bit primaries and their 8-bit second level as
-    the re-ranking rows (LVQ4x8 at bits = 4; full_d: d = D, the baseline's own
-    setting, with the full eigenbasis as the projection)."""
+    the re-ranking rows (LVQ4x8 at bits = 4).  d: the workload's if 0, D if -1
+    (the baseline's own setting, the full eigenbasis as the projection), else
+    that value."""
     from dataclasses import replace
 
     wl = replace(gen.WORKLOADS[name].scaled(N=N, m_test=40), bits=bits)
-    if full_d:
-        wl = replace(wl, d=wl.D)
+    if d:
+        wl = replace(wl, d=wl.D if d < 0 else d)
     c = make_case(wl)
     codes, delta, lo = olvq.encode(c.Y, c.mu, bits)
     c2, d2, l2 = olvq.encode_residual(c.Y, c.mu, codes, delta, lo)
@@ -476,14 +477,15 @@ def _level2_case(lv, name, bits, N=6000, full_d=False):
     return wl, c, oidx, index, rows, want, (rec, mud, rows, adj, Pb)
 
 
-@pytest.mark.parametrize("name,bits,full_d", [("id-1m-768", 4, False), ("ood-1m-512", 4, False),
-                                              ("id-1m-768", 8, False), ("id-small", 4, True)])
-def test_search_parity_level2_secondaries(lv, name, bits, full_d):
+@pytest.mark.parametrize("name,bits,d", [("id-1m-768", 4, 0), ("ood-1m-512", 4, 0),
+                                         ("id-1m-768", 8, 0), ("id-small", 4, -1),
+                                         ("id-small", 8, 88)])
+def test_search_parity_level2_secondaries(lv, name, bits, d):
     """Two-level LVQ (the second level re-ranks): rows bit-exact against the
     oracle's encoding; ids, scores and counters equal to the oracle's
     (primary score plus the second level's inner product with A q); the
     team launch identical; the batched step identical to the plain search."""
-    wl, c, oidx, index, rows, want, keep = _level2_case(lv, name, bits, full_d=full_d)
+    wl, c, oidx, index, rows, want, keep = _level2_case(lv, name, bits, d=d)
     assert np.array_equal(rows.cpu().numpy(), want)
     m, k = len(c.Q), wl.k
     for L in (20, 60):
