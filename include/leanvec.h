@@ -203,6 +203,19 @@ int lv_lvq_encode(const float *Y, int64_t n, int32_t d, const float *mu, int32_t
                   void *records, int32_t record_stride, void *stream);
 
 /*
+ * Reconstruction of LVQ records (the decode of the quantiser of Eq. 1; for
+ * checks and tests, not on the search path):
+ * out[v][j] = float32((mu_j + lo_v) + delta_v c_vj), evaluated in float64 in
+ * that order (delta c is exact), i.e. the float64 reconstruction rounded to
+ * float32.
+ *   records: device [n][record_stride] bytes (lv_lvq_encode's layout)
+ *   mu: device float32 [d];  out: device float32 [n][d]
+ * Errors: LV_EINVAL as for lv_lvq_encode, or NULL pointers with n > 0.
+ */
+int lv_lvq_decode(const void *records, int64_t n, int32_t d, int32_t bits, int32_t record_stride,
+                  const float *mu, float *out, void *stream);
+
+/*
  * Database projection and LVQ encoding in one pass (Eq. 1: quant(B x) for
  * every database vector): the records lv_project(V, rows, D, M, d) followed
  * by lv_lvq_encode(out, rows, d, mu, bits) would write, bit for bit, without

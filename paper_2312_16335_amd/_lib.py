@@ -91,6 +91,7 @@ _SIGS = {
     "lv_record_stride": (_c_i32, [_c_i32, _c_i32]),
     "lv_secondary_row_bytes": (_c_i32, [_c_i32, _c_i32]),
     "lv_lvq_encode": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _c_i32, _vp]),
+    "lv_lvq_decode": (_c_i32, [_vp, _c_i64, _c_i32, _c_i32, _c_i32, _vp, _vp, _vp]),
     "lv_project_encode": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _c_i32, _vp, _c_i32,
                                    _vp]),
     "lv_lvq_encode_level2": (_c_i32, [_vp, _c_i64, _c_i32, _vp, _c_i32, _vp, _c_i32, _vp,
@@ -328,6 +329,19 @@ def lv_lvq_encode(Y, mu, bits: int, records, stream=None) -> None:
     _rows_cols(records, "records", min_rows=n)
     _check(load().lv_lvq_encode(_dev(Y, torch.float32), n, d, _dev(mu, torch.float32), bits,
                                 _dev(records, torch.uint8), records.shape[1], _stream(stream)))
+
+
+def lv_lvq_decode(records, d: int, bits: int, mu, out, stream=None) -> None:
+    """out (device float32 [n][d], written) = the float32-rounded reconstruction
+    of the LVQ records (device uint8 [n][stride])."""
+    import torch
+
+    n, stride = _rows_cols(records, "records")
+    _need(mu, d, "mu")
+    _rows_cols(out, "out", cols=d, min_rows=n)
+    _check(load().lv_lvq_decode(_dev(records, torch.uint8), n, d, bits, stride,
+                                _dev(mu, torch.float32), _dev(out, torch.float32),
+                                _stream(stream)))
 
 
 def lv_project_encode(V, M_bf16, mu, bits: int, records, stream=None) -> None:

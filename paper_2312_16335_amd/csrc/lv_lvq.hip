@@ -112,6 +112,27 @@ __global__ __launch_bounds__(256) void encode_level2_kernel(
   }
 }
 
+// Reconstruction of LVQ records: out[v][j] = float32((mu_j + lo) + delta c_j),
+// evaluated in float64 in that order (delta c_j is exact), one wavefront per
+// vector.
+template <int BITS>
+__global__ __launch_bounds__(256) void decode_kernel(const unsigned char *__restrict__ rec,
+                                                     int64_t n, int32_t d, int32_t stride,
+                                                     const float *__restrict__ mu,
+                                                     float *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (v >= n) return;
+  const unsigned char *r = rec + v * (int64_t)stride;
+  const int cb = d * BITS / 8;
+  const double delta = (double)__uint_as_float(*reinterpret_cast<const uint32_t *>(r + cb));
+  const double lo = (double)__uint_as_float(*reinterpret_cast<const uint32_t *>(r + cb + 4));
+  for (int j = lane; j < d; j += 64) {
+    const uint32_t c = BITS == 8 ? r[j] : (r[j >> 1] >> (4 * (j & 1))) & 0xFu;
+    out[v * d + j] = (float)(((double)mu[j] + lo) + delta * (double)c);
+  }
+}
+
 // float32 -> float16 with the hardware conversion (round to nearest even).
 __global__ __launch_bounds__(256) void to_f16_kernel(const float *__restrict__ x, int64_t count,
                                                      _Float16 *__restrict__ out) {
@@ -182,6 +203,31 @@ extern "C" int lv_lvq_encode_level2(const float *Y, int64_t n, int32_t d, const 
   else
     hipLaunchKernelGGL(lv::encode_level2_kernel<4>, dim3((unsigned)blocks), dim3(64 * per_block), 0,
                        s, Y, n, d, mu, rec, record_stride, out, row_bytes);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+extern "C" int lv_lvq_decode(const void *records, int64_t n, int32_t d, int32_t bits,
+                             int32_t record_stride, const float *mu, float *out, void *stream) {
+  lv::clear_error();
+  if (bits != 4 && bits != 8) LV_FAIL(LV_EINVAL, "bits must be 4 or 8 (got %d)", bits);
+  if (d < 8 || d > 2048 || d % 8 != 0) LV_FAIL(LV_EINVAL, "d must be a multiple of 8 in [8, 2048]");
+  if (n < 0) LV_FAIL(LV_EINVAL, "n must be >= 0");
+  if (record_stride < d * bits / 8 + 8 || record_stride % 4 != 0)
+    LV_FAIL(LV_EINVAL, "record_stride %d too small or not a multiple of 4", record_stride);
+  if (n > 0 && (!records || !mu || !out)) LV_FAIL(LV_EINVAL, "NULL pointer");
+  if (n == 0) return LV_OK;
+  const int per_block = 4;
+  const int64_t blocks = (n + per_block - 1) / per_block;
+  if (blocks > 0x7FFFFFFF) LV_FAIL(LV_EINVAL, "n too large");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const unsigned char *rec = static_cast<const unsigned char *>(records);
+  if (bits == 8)
+    hipLaunchKernelGGL(lv::decode_kernel<8>, dim3((unsigned)blocks), dim3(64 * per_block), 0, s,
+                       rec, n, d, record_stride, mu, out);
+  else
+    hipLaunchKernelGGL(lv::decode_kernel<4>, dim3((unsigned)blocks), dim3(64 * per_block), 0, s,
+                       rec, n, d, record_stride, mu, out);
   LV_CHECK_LAUNCH();
   return LV_OK;
 }

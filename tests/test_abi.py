@@ -115,6 +115,15 @@ def test_encode_and_project_validation():
     assert lib.lv_lvq_encode(FAKE, 10, 160, FAKE, 8, FAKE, 160, None) == lv.LV_EINVAL
     assert lib.lv_lvq_encode(None, 10, 32, FAKE, 8, FAKE, 64, None) == lv.LV_EINVAL
     assert lib.lv_lvq_encode(FAKE, 0, 32, FAKE, 8, FAKE, 64, None) == lv.LV_OK
+    # decode: the encoder's checks
+    dec = lib.lv_lvq_decode
+    assert dec(FAKE, 10, 32, 3, 64, FAKE, FAKE, None) == lv.LV_EINVAL
+    assert dec(FAKE, 10, 36, 8, 64, FAKE, FAKE, None) == lv.LV_EINVAL
+    assert dec(FAKE, 10, 160, 8, 160, FAKE, FAKE, None) == lv.LV_EINVAL
+    assert dec(None, 10, 32, 8, 64, FAKE, FAKE, None) == lv.LV_EINVAL
+    assert dec(FAKE, 10, 32, 8, 64, FAKE, None, None) == lv.LV_EINVAL
+    assert dec(FAKE, -1, 32, 8, 64, FAKE, FAKE, None) == lv.LV_EINVAL
+    assert dec(FAKE, 0, 32, 8, 64, FAKE, FAKE, None) == lv.LV_OK
     # one-pass projection and encoding: d in [8, 256], stride checks, NULLs
     pe = lib.lv_project_encode
     assert pe(FAKE, 10, 768, FAKE, 264, FAKE, 8, FAKE, 512, None) == lv.LV_EINVAL

@@ -81,6 +81,28 @@ def test_project_encode_empty(lv):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("bits,d,n", [(8, 160, 3001), (4, 128, 2049), (4, 8, 65), (8, 1024, 33)])
+def test_lvq_decode_bit_exact(lv, bits, d, n):
+    """Device reconstruction equals the oracle's float64 decode rounded to
+    float32, and lies within half a step (plus rounding) of the encoded rows."""
+    rng = np.random.default_rng(3 * d + bits)
+    Y = (rng.standard_normal((n, d)) * rng.uniform(1e-3, 10, (n, 1))).astype(np.float32)
+    Y[0] = 0.25
+    mu = (0.1 * rng.standard_normal(d)).astype(np.float32)
+    stride = lv.lv_record_stride(d, bits) or (d * bits // 8 + 12)
+    c, delta, lo = olvq.encode(Y, mu, bits)
+    rec = torch.from_numpy(olvq.pack_records(c, delta, lo, bits, stride)).to(DEV)
+    out = torch.full((n, d), float("nan"), dtype=torch.float32, device=DEV)
+    lv.lv_lvq_decode(rec, d, bits, torch.from_numpy(mu).to(DEV), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want = olvq.decode(c, delta, lo, mu).astype(np.float32)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    err = np.abs(got.astype(np.float64) - Y)
+    bound = delta.astype(np.float64)[:, None] / 2 + 4 * np.spacing(np.abs(Y).max(axis=1))[:, None]
+    assert np.all(err <= bound + 1e-12)
+
+
 def test_lvq_encode_empty_and_errors(lv):
     Y = torch.zeros((0, 16), device=DEV)
     mu = torch.zeros(16, device=DEV)
