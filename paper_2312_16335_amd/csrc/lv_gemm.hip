@@ -356,13 +356,21 @@ __global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g, int sps, floa
 
 // ---- tiled kernel: TBM x TBN output tile per workgroup of WM x WN
 // wavefronts (each a (TBM / WM) x (TBN / WN) block of 32 x 32 MFMA tiles),
-// K steps of TK with the next step's float32 operands in registers during
-// the current step's products, two LDS buffers, one barrier per step.
+// K steps of TK, two LDS buffers and one barrier per step, and the float32
+// operands of the next two steps in flight in registers while the current
+// step's products run.  Whole tiles (FULL: M, N multiples of the tile and K
+// of TK) load with plain 16-byte loads and no edge tests.
 // SPLIT: both parts of every operand (hi, lo) are staged in the same step
 // and each fragment pair takes the three products hi*hi, hi*lo, lo*hi, so
 // the operands are read and converted once (not once per part).
 constexpr int TK = 32;
-constexpr int TLD = TK + 8;  // LDS row (bf16 elements): 80 bytes
+// LDS tiles: rows of TK bfloat16 (64 bytes, four 16-byte chunks), chunk c of
+// row r stored at chunk c ^ ((r / 4) % 4): the 16-byte reads of a fragment
+// (sixteen rows, one chunk) and the row writes (four rows, four chunks each)
+// then touch distinct banks of a 256-byte bank line.
+constexpr int TLD = TK;
+
+__device__ __forceinline__ int tswz(int r, int c) { return r * TLD + 8 * (c ^ ((r >> 2) & 3)); }
 
 template <int ROWS, int THREADS, bool KCONT>
 struct TileFrag {
@@ -371,24 +379,49 @@ struct TileFrag {
   float4 v[kPer];
 };
 
-// Global -> registers.  k-contiguous: piece f (row f / 8, k 4 (f % 8)), so
-// eight consecutive threads read one row's 128 bytes.  m-contiguous: unit u
-// (k rows 2 kp and 2 kp + 1, m 4 mq ..), two pieces per unit.
-template <int ROWS, int THREADS, bool KCONT>
+// Global -> registers.  k-contiguous: unit u (row u / 4, k 8 (u % 4) ..), two
+// pieces per unit, so four consecutive threads read one row's 128 bytes.
+// m-contiguous: unit u (k rows 2 kp and 2 kp + 1, m 4 mq ..), two pieces.
+template <int ROWS, int THREADS, bool KCONT, bool FULL>
 __device__ __forceinline__ void tload(const float *__restrict__ X, int64_t ld, int rows,
                                       int kdim, int r0, int k0,
                                       TileFrag<ROWS, THREADS, KCONT> &f, int tid) {
   constexpr int P = TileFrag<ROWS, THREADS, KCONT>::kPer;
+  if constexpr (FULL) {  // whole tiles: plain 16-byte loads, no edge tests
+    if constexpr (KCONT) {
+#pragma unroll
+      for (int j = 0; j < P / 2; ++j) {
+        const int u = tid + THREADS * j;
+        const float *p = X + (int64_t)(r0 + (u >> 2)) * ld + k0 + 8 * (u & 3);
+        f.v[2 * j] = *reinterpret_cast<const float4 *>(p);
+        f.v[2 * j + 1] = *reinterpret_cast<const float4 *>(p + 4);
+      }
+    } else {
+      constexpr int MQ = ROWS / 4;
+#pragma unroll
+      for (int j = 0; j < P / 2; ++j) {
+        const int u = tid + THREADS * j;
+        const int kp = u / MQ, mq = u % MQ;
+        const float *p = X + (int64_t)(k0 + 2 * kp) * ld + r0 + 4 * mq;
+        f.v[2 * j] = *reinterpret_cast<const float4 *>(p);
+        f.v[2 * j + 1] = *reinterpret_cast<const float4 *>(p + ld);
+      }
+    }
+    return;
+  }
   if constexpr (KCONT) {
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int pc = tid + THREADS * j;
-      const int r = pc >> 3, gk = k0 + 4 * (pc & 7);
-      const int gr = r0 + r;
+    for (int j = 0; j < P / 2; ++j) {
+      const int u = tid + THREADS * j;
+      const int gr = r0 + (u >> 2);
       const bool rok = gr < rows;
-      const float *p = X + (int64_t)(rok ? gr : 0) * ld + (gk < kdim ? gk : 0);
-      f.v[j] = load4(p, rok && gk + 3 < kdim, rok && gk < kdim, rok && gk + 1 < kdim,
-                     rok && gk + 2 < kdim, false);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int gk = k0 + 8 * (u & 3) + 4 * h;
+        const float *p = X + (int64_t)(rok ? gr : 0) * ld + (gk < kdim ? gk : 0);
+        f.v[2 * j + h] = load4(p, rok && gk + 3 < kdim, rok && gk < kdim, rok && gk + 1 < kdim,
+                               rok && gk + 2 < kdim, false);
+      }
     }
   } else {
     constexpr int MQ = ROWS / 4;  // float4 pieces along m
@@ -416,12 +449,12 @@ __device__ __forceinline__ void tstore(const TileFrag<ROWS, THREADS, KCONT> &f, 
   constexpr int P = TileFrag<ROWS, THREADS, KCONT>::kPer;
   if constexpr (KCONT) {
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int pc = tid + THREADS * j;
-      const int r = pc >> 3, kq = pc & 7;
-      const float4 a = f.v[j];
-      *reinterpret_cast<uint2 *>(S + r * TLD + 4 * kq) =
-          make_uint2(pack_bf16<LO>(a.x, a.y), pack_bf16<LO>(a.z, a.w));
+    for (int j = 0; j < P / 2; ++j) {
+      const int u = tid + THREADS * j;
+      const float4 a = f.v[2 * j], b = f.v[2 * j + 1];
+      *reinterpret_cast<uint4 *>(S + tswz(u >> 2, u & 3)) =
+          make_uint4(pack_bf16<LO>(a.x, a.y), pack_bf16<LO>(a.z, a.w), pack_bf16<LO>(b.x, b.y),
+                     pack_bf16<LO>(b.z, b.w));
     }
   } else {
     constexpr int MQ = ROWS / 4;
@@ -430,16 +463,17 @@ __device__ __forceinline__ void tstore(const TileFrag<ROWS, THREADS, KCONT> &f, 
       const int u = tid + THREADS * j;
       const int kp = u / MQ, mq = u % MQ;
       const float4 a = f.v[2 * j], b = f.v[2 * j + 1];  // k rows 2 kp and 2 kp + 1
-      uint32_t *d = reinterpret_cast<uint32_t *>(S + (4 * mq) * TLD + 2 * kp);
-      d[0] = pack_bf16<LO>(a.x, b.x);
-      d[TLD / 2] = pack_bf16<LO>(a.y, b.y);
-      d[TLD] = pack_bf16<LO>(a.z, b.z);
-      d[3 * TLD / 2] = pack_bf16<LO>(a.w, b.w);
+      const int c = (2 * kp) >> 3, w = (2 * kp) & 7;   // chunk and place of the pair
+      const int m = 4 * mq;
+      *reinterpret_cast<uint32_t *>(S + tswz(m, c) + w) = pack_bf16<LO>(a.x, b.x);
+      *reinterpret_cast<uint32_t *>(S + tswz(m + 1, c) + w) = pack_bf16<LO>(a.y, b.y);
+      *reinterpret_cast<uint32_t *>(S + tswz(m + 2, c) + w) = pack_bf16<LO>(a.z, b.z);
+      *reinterpret_cast<uint32_t *>(S + tswz(m + 3, c) + w) = pack_bf16<LO>(a.w, b.w);
     }
   }
 }
 
-template <int TBM, int TBN, int WM, int WN, bool AK, bool BKC, bool SPLIT>
+template <int TBM, int TBN, int WM, int WN, bool AK, bool BKC, bool SPLIT, bool FULL>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int sps,
                                                                   float *part) {
   constexpr int THREADS = 64 * WM * WN;
@@ -467,29 +501,23 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int
   const int nk_all = (g.K + TK - 1) / TK;
   const int t0 = (int)blockIdx.z * sps;
   const int nk = (t0 + sps < nk_all ? t0 + sps : nk_all) - t0;
-  TileFrag<TBM, THREADS, AK> fa;
-  TileFrag<TBN, THREADS, BKC> fb;
-  auto put = [&](int b) {
-    tstore<TBM, THREADS, AK, false>(fa, As + (b * NP) * SA, tid);
-    tstore<TBN, THREADS, BKC, false>(fb, Bs + (b * NP) * SB, tid);
+  // two register sets: at step t the operands of step t + 1 (loaded during
+  // step t - 1) go to LDS while those of step t + 2 are in flight
+  TileFrag<TBM, THREADS, AK> fa[2];
+  TileFrag<TBN, THREADS, BKC> fb[2];
+  auto load = [&](int t, int q) {
+    tload<TBM, THREADS, AK, FULL>(g.A, g.lda, g.M, g.K, m0, (t0 + t) * TK, fa[q], tid);
+    tload<TBN, THREADS, BKC, FULL>(g.B, g.ldb, g.N, g.K, n0, (t0 + t) * TK, fb[q], tid);
+  };
+  auto put = [&](int b, int q) {
+    tstore<TBM, THREADS, AK, false>(fa[q], As + (b * NP) * SA, tid);
+    tstore<TBN, THREADS, BKC, false>(fb[q], Bs + (b * NP) * SB, tid);
     if constexpr (SPLIT) {
-      tstore<TBM, THREADS, AK, true>(fa, As + (b * NP + 1) * SA, tid);
-      tstore<TBN, THREADS, BKC, true>(fb, Bs + (b * NP + 1) * SB, tid);
+      tstore<TBM, THREADS, AK, true>(fa[q], As + (b * NP + 1) * SA, tid);
+      tstore<TBN, THREADS, BKC, true>(fb[q], Bs + (b * NP + 1) * SB, tid);
     }
   };
-  if (nk > 0) {
-    tload<TBM, THREADS, AK>(g.A, g.lda, g.M, g.K, m0, t0 * TK, fa, tid);
-    tload<TBN, THREADS, BKC>(g.B, g.ldb, g.N, g.K, n0, t0 * TK, fb, tid);
-    put(0);
-  }
-  __syncthreads();
-  for (int t = 0; t < nk; ++t) {
-    const int cur = t & 1;
-    const bool more = t + 1 < nk;
-    if (more) {
-      tload<TBM, THREADS, AK>(g.A, g.lda, g.M, g.K, m0, (t0 + t + 1) * TK, fa, tid);
-      tload<TBN, THREADS, BKC>(g.B, g.ldb, g.N, g.K, n0, (t0 + t + 1) * TK, fb, tid);
-    }
+  auto compute = [&](int cur) {
     const uint16_t *ac = As + (cur * NP) * SA;
     const uint16_t *bc = Bs + (cur * NP) * SB;
 #pragma unroll
@@ -500,13 +528,13 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int
 #pragma unroll
         for (int i = 0; i < IM; ++i)
           a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(
-                                                   ac + q * SA + (wm + 32 * i + r) * TLD + ks +
-                                                   8 * kh));
+                                                   ac + q * SA + tswz(wm + 32 * i + r,
+                                                                      (ks >> 3) + kh)));
 #pragma unroll
         for (int j = 0; j < JN; ++j)
           b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(
-                                                   bc + q * SB + (wn + 32 * j + r) * TLD + ks +
-                                                   8 * kh));
+                                                   bc + q * SB + tswz(wn + 32 * j + r,
+                                                                      (ks >> 3) + kh)));
       }
 #pragma unroll
       for (int i = 0; i < IM; ++i)
@@ -521,9 +549,36 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int
           }
         }
     }
-    if (more) put(cur ^ 1);  // that buffer was last read before the previous barrier
+  };
+  // step t: compute from LDS buffer t % 2, operands of step t + 1 from
+  // register set (t + 1) % 2 into the other buffer, step t + 2 into set t % 2
+  // (scheduling barriers keep the loads in program order, so that the wait
+  // before storing a set covers only that set's loads, not the newer set's)
+  // The loads are unconditional (past the last step they fetch the last step
+  // again, unused) so that every path has the same loads in flight and the
+  // wait before a store counts only the older set.
+  auto step = [&](int t, int q) {  // q = t % 2 (a constant at each call)
+    load(t + 2 < nk ? t + 2 : nk - 1, q);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(q);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + 1 < nk) put(q ^ 1, q ^ 1);  // that buffer was last read before the previous barrier
     __syncthreads();
+  };
+  if (nk > 0) {
+    load(0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(nk > 1 ? 1 : 0, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    put(0, 0);
   }
+  __syncthreads();
+  int t = 0;
+  for (; t + 1 < nk; t += 2) {
+    step(t, 0);
+    step(t + 1, 1);
+  }
+  if (t < nk) step(t, 0);
   float *pz = part ? part + (int64_t)blockIdx.z * g.M * g.N : nullptr;
 #pragma unroll
   for (int i = 0; i < IM; ++i)
@@ -580,13 +635,19 @@ struct TileLaunch {
   int sps;
   float *part;
   hipStream_t s;
+  bool full;
   template <bool AK, bool BKC, bool SPLIT>
   void go() {
     // split precision runs on 128 x 128 tiles only (the large tile has no
     // registers left for the second parts)
-    if constexpr (!SPLIT || TBM * TBN <= 128 * 128)
-      hipLaunchKernelGGL((gemm_tile_kernel<TBM, TBN, WM, WN, AK, BKC, SPLIT>), grid,
-                         dim3(64 * WM * WN), 0, s, g, sps, part);
+    if constexpr (!SPLIT || TBM * TBN <= 128 * 128) {
+      if (full)
+        hipLaunchKernelGGL((gemm_tile_kernel<TBM, TBN, WM, WN, AK, BKC, SPLIT, true>), grid,
+                           dim3(64 * WM * WN), 0, s, g, sps, part);
+      else
+        hipLaunchKernelGGL((gemm_tile_kernel<TBM, TBN, WM, WN, AK, BKC, SPLIT, false>), grid,
+                           dim3(64 * WM * WN), 0, s, g, sps, part);
+    }
   }
 };
 
@@ -640,8 +701,9 @@ int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *sp
     if (!split && big_tiles >= kBigTileMinTiles) {
       const dim3 gb((unsigned)((g.N + kBigTile - 1) / kBigTile),
                     (unsigned)((g.M + kBigTile - 1) / kBigTile), 1u);
+      const bool full = g.M % kBigTile == 0 && g.N % kBigTile == 0 && g.K % TK == 0;
       TileLaunch<kBigTile, kBigTile, 2, 4> f{g, gb, (g.K + TK - 1) / TK > 0 ? (g.K + TK - 1) / TK : 1,
-                                          nullptr, s};
+                                          nullptr, s, full};
       dispatch_layout(a_kcont, b_kcont, false, f);
       LV_CHECK_LAUNCH();
       return LV_OK;
@@ -665,7 +727,8 @@ int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *sp
     float *part = parts > 1 ? split_ws : nullptr;
     const dim3 gz(grid.x, grid.y, (unsigned)parts);
     if (split) {  // both parts staged once per step
-      TileLaunch<BM, BN, 2, 2> f{g, gz, sps, part, s};
+      const bool full = g.M % BM == 0 && g.N % BN == 0 && g.K % TK == 0;
+      TileLaunch<BM, BN, 2, 2> f{g, gz, sps, part, s, full};
       dispatch_layout(a_kcont, b_kcont, true, f);
     } else {
       VecLaunch f{g, gz, sps, part, s};
