@@ -617,6 +617,31 @@ def mfma_report(lv, torch, reps=10):
     trace = 2.0 * (2 * d2 * D2 * D2 + 2 * d2 * d2 * D2) * 2
     out["refinement_step"] = dict(b_q=bq, b_x=bx, D=D2, d=d2,
                                   **entry(timed(step), pair_f + pair_b + trace))
+    # the float64 oracle beside them (host cores): projection + LVQ-8 encoding of
+    # a 20,000-row sample, and one refinement step (loss and gradients)
+    from oracle import fit as ofit
+    from oracle import lvq as olvq
+    from oracle import projloss as oproj
+
+    rows_o = 20_000
+    Vo = torch.randn((rows_o, D), generator=torch.Generator().manual_seed(5)).numpy()
+    Mo = np.asarray(M.view(torch.bfloat16).float().cpu().numpy(), np.float64)
+    muo = np.zeros(d, np.float32)
+    t = time.perf_counter()
+    Yo = ofit.project(Vo, Mo).astype(np.float32)
+    olvq.encode(Yo, muo, 8)
+    dt = time.perf_counter() - t
+    out["database_projection_encode"]["oracle"] = {
+        "rows_per_s": rows_o / dt, "sample": f"{rows_o} rows, float64 numpy on the host",
+        "gpu_rows_per_s": 1_000_000 / (out["database_projection_encode"]["ms"] / 1e3)}
+    Ah, Bh, Qh, Xh = (x.double().cpu().numpy() for x in (A, B, Qb, Xb))
+    KQh, KXh = KQ.double().cpu().numpy(), KX.double().cpu().numpy()
+    t = time.perf_counter()
+    oproj.loss(Ah, Bh, Qh, Xh, KQh, KXh)
+    oproj.grads(Ah, Bh, Qh, Xh, KQh, KXh)
+    out["refinement_step"]["oracle"] = {"ms": (time.perf_counter() - t) * 1e3,
+                                        "sample": "one step at the same block sizes, float64 "
+                                                  "numpy on the host (its BLAS threads)"}
     n = 8192
     Ga = torch.randn((n, n), device=dev, generator=g)
     Gb = torch.randn((n, n), device=dev, generator=g)
