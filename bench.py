@@ -1261,7 +1261,7 @@ def main():
 
 
 def ood_report(lv, torch, args, steps=10, in_flight=3, target=0.90, expand=3,
-               hash_slots=2048, cpu_sample=1000):
+               hash_slots=0, cpu_sample=1000):
     """Compact run of the cross-modal workload (ood-1m-512: 1M x 512 database,
     10,000 out-of-distribution test queries): LeanVec-OOD fit (Algorithm 1, host
     float64, on 10,000 learning queries and a 100,000-vector sample), A q for the
@@ -1360,12 +1360,16 @@ def ood_report(lv, torch, args, steps=10, in_flight=3, target=0.90, expand=3,
         left -= b
     reqs = [(0, k, L, b) for b in sizes]
     multi = lv.Multi([index])
-    batch = lv.Batch(multi, max_requests=len(reqs), max_queries=m, max_L=L,
-                     hash_slots=hash_slots, expand=expand)
     stream = torch.cuda.current_stream()
     strs = [stream] + [torch.cuda.Stream() for _ in range(in_flight - 1)]
     outs = [(torch.empty(m * k, dtype=torch.int32, device=dev),
              torch.empty(m * k, dtype=torch.float32, device=dev)) for _ in range(in_flight)]
+    if not hash_slots:  # visited-set size: the autotuner's choice, as for the main record
+        knobs, _ = lv.lv_autotune_knobs(multi, len(reqs), m, L, reqs, Qd, outs[0][0], outs[0][1],
+                                        reps=2, expand=expand)
+        hash_slots = knobs["hash_slots"]
+    batch = lv.Batch(multi, max_requests=len(reqs), max_queries=m, max_L=L,
+                     hash_slots=hash_slots, expand=expand)
 
     def ev():
         return torch.cuda.Event(enable_timing=True)

@@ -327,7 +327,8 @@ int lv_index_destroy(lv_index *index);
  * (and hence resident wavefronts) against repeated scoring.
  */
 typedef struct {
-  int32_t hash_slots; /* visited-set slots per query (power of 2, 256..65536; 0 = 1024) */
+  int32_t hash_slots; /* visited-set slots per query (a multiple of 256 in 256..65536;
+                         0 = 1024) */
   int32_t probes;     /* slots tried before an id replaces the one in its home slot
                          (1..16; 0 = 2 below 4096 slots, 8 from 4096 slots) */
   int32_t launch;     /* batched traversal: LV_LAUNCH_PER_QUERY (0, one workgroup
@@ -358,7 +359,11 @@ size_t lv_search_workspace_size(const lv_index *index, int64_t m);
  * order (score descending, id ascending), score its unvisited
  * out-neighbours, keep the best L), then re-ranks every candidate left in
  * the window with <q, secondary> and returns the best k (ties: smaller id).
- * Primary and secondary scores are accumulated in float64.
+ * Scores are float64.  Primary scores use the projected query on a grid of
+ * its own, q~_j = rint(q_j 2^s) 2^-s with s = 22 - e for the largest |q_j| =
+ * f 2^e, f in [0.5, 1) (within 2^-22 of the largest component), on which the
+ * inner product with the codes is an exact integer sum; re-ranking reads the
+ * query as given.  Projected queries must be finite.
  *   Q:        device float32 [m][D]
  *   ids:      device uint32 [m][k] out;  scores: device float32 [m][k] out
  *   counters: device uint32 [m][2] out (expansions, primary scorings) or NULL
@@ -494,8 +499,8 @@ int lv_autotune_window(lv_multi *multi, int32_t sub, const float *Q, int64_t m,
                        double *recall_out, void *stream);
 
 /*
- * Autotuner, performance part: for each visited-set size in {1024, 2048,
- * 4096, 8192} that fits, times `reps` rounds of three steps of the given
+ * Autotuner, performance part: for each visited-set size in {1024, 1280,
+ * 1536, 2048, 4096, 8192} that fits, times `reps` rounds of three steps of the given
  * requests in flight at once (on internal streams, the way consecutive steps
  * overlap in service) with the per-query launch, and returns the fastest in
  * best (these knobs never change results).  The persistent launch is not

@@ -17,7 +17,14 @@ best-first beam with window L:
            return the best k under (s2 descending, id ascending).
 
 Scores are float64.  The primary score is the plain definition
-<q', y^_n> with y^_n the LVQ reconstruction (mu + lo + delta * c).
+<q~, y^_n> with y^_n the LVQ reconstruction (mu + lo + delta * c) and q~
+the projected query on its grid (grid_query): every component rounded to
+the nearest multiple of 2^-s, with s fixed by the largest component m so
+that a step is at most 2^-22 m (a shared-exponent fixed point of 23 bits,
+far finer than the bfloat16 products that compute the projection).  The
+paper does not fix the arithmetic of the traversal's inner products; on
+this grid <q~, c> is a sum of integers, exact in any order.  Re-ranking
+reads the query as given.
 
 Pinned by: brute force when L >= N on a connected graph, the exhaustive
 "flat" variant, and the top-L-of-visited invariant (tests/test_oracle_search.py).
@@ -77,9 +84,24 @@ def rowdot(M: np.ndarray, v: np.ndarray) -> np.ndarray:
     return P[:, 0]
 
 
+def grid_query(qp) -> np.ndarray:
+    """The projected query on its grid, float64: with m the largest |q_j| and
+    m = f 2^e, f in [0.5, 1) (e = 0 for m = 0), s = 22 - e and
+    q~_j = rint(q_j 2^s) 2^-s (nearest, ties to even).  Every |rint(q_j 2^s)|
+    is at most 2^22 and |q~_j - q_j| is at most half a step, 2^(e - 23) <=
+    2^-22 m."""
+    q = np.asarray(qp, dtype=np.float64)
+    m = float(np.max(np.abs(q))) if q.size else 0.0
+    e = int(np.frexp(m)[1])
+    s = 22 - e
+    return np.ldexp(np.rint(np.ldexp(q, s)), -s)
+
+
 def primary_scores(index: Index, qp64: np.ndarray, ids) -> np.ndarray:
-    """<q', y^_n> in float64 for the given ids (Eq. 1 with LVQ reconstruction)."""
+    """<q~, y^_n> in float64 for the given ids (Eq. 1 with LVQ reconstruction;
+    q~ = grid_query(qp64))."""
     ids = np.asarray(ids, dtype=np.int64)
+    qp64 = grid_query(qp64)
     yhat = (index.mu.astype(np.float64)[None, :]
             + index.lo[ids].astype(np.float64)[:, None]
             + index.delta[ids].astype(np.float64)[:, None]
@@ -116,7 +138,8 @@ def two_level_scores(index: Index, qp64: np.ndarray, ids) -> np.ndarray:
     baseline setup, Appendix D and Fig. 1: the first level drives the search,
     the 8-bit second level refines the same reduced vector for the
     re-ranking): <q', y^_n + r^_n> with r^_n = lo2 + delta2 * c2 the second
-    level's reconstruction, taken as the primary score plus <q', r^_n>.  The
+    level's reconstruction, taken as the primary score (on the query's grid)
+    plus <q', r^_n> (the query as given).  The
     query is the projected one; no full-dimension vector is read."""
     ids = np.asarray(ids, dtype=np.int64)
     r = (index.sec_lo[ids].astype(np.float64)[:, None]

@@ -447,7 +447,9 @@ extern "C" int lv_autotune_knobs(lv_multi *multi, const lv_batch_caps *caps,
   // wavefronts keep the next step's query projection waiting for compute
   // units, which stalls the pipeline (and it is not faster on its own).
   for (int launch : {LV_LAUNCH_PER_QUERY}) {
-    for (int hs : {1024, 2048, 4096, 8192}) {
+    // Sizes between 1024 and 2048 matter: a smaller set forgets more ids
+    // (more re-scoring), a larger one leaves room in LDS for fewer wavefronts.
+    for (int hs : {1024, 1280, 1536, 2048, 4096, 8192}) {
       lv_search_params p{hs, 0, launch, expand};
       lv_batch *b = nullptr;
       int rc = lv_batch_create(multi, caps, &p, &b);

@@ -574,14 +574,14 @@ extern "C" int lv_graph_build(const void *records, int32_t record_stride, int64_
       seen[order[i]] = 1;
     }
   }
-  rc = check_lds(beam_lds_bytes(bp.L, vc.log2h), bp.L, vc.log2h);
+  rc = check_lds(beam_lds_bytes(bp.L, vc.slots), bp.L, vc.slots);
   if (rc != LV_OK) return rc;
   const int R = bp.R, L = bp.L, cw = cb / 4;
   const int pool_stride = L + R;
   const int64_t maxb = bp.max_batch < N ? bp.max_batch : N;
   const size_t lds_fwd = prune_lds_bytes(pool_stride, R, cw);
   const size_t lds_rev = prune_lds_bytes(R + kMaxNewSources, R, cw);
-  rc = check_lds(lds_fwd > lds_rev ? lds_fwd : lds_rev, L, vc.log2h);
+  rc = check_lds(lds_fwd > lds_rev ? lds_fwd : lds_rev, L, vc.slots);
   if (rc != LV_OK) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
 
@@ -626,7 +626,7 @@ extern "C" int lv_graph_build(const void *records, int32_t record_stride, int64_
   sa.pool = pool;
   sa.counters = counters;
   sa.stats = st.stats;
-  sa.hash_log2 = vc.log2h;
+  sa.hash_slots = vc.slots;
   sa.probes = vc.probes;
   ForwardArgs fa{};
   fa.v.records = sa.ix.records;

@@ -69,24 +69,24 @@ struct BuildSearchArgs {
   uint32_t *pool;
   uint32_t *counters;
   unsigned long long *stats;  // optional totals: [0] searches, [1] expansions, [2] scorings
-  int32_t hash_log2;
+  int32_t hash_slots;
   int32_t probes;
 };
 
 IndexView make_view(const lv_index *ix);
-// Visited set of one query: 2^log2h slots in LDS, up to `probes` slots tried
+// Visited set of one query: `slots` slots in LDS (a multiple of 256), up to `probes` slots tried
 // before an id replaces the one in its home slot.
 // expand: entries expanded per iteration (1: the paper's traversal; more:
 // the throughput variant).
 struct VisitedCfg {
-  int log2h;
+  int slots;
   int probes;
   int expand;
   bool team = false;  // plain search: kTeamWaves wavefronts per query
 };
 int visited_config(const lv_search_params *params, VisitedCfg *cfg);
-size_t beam_lds_bytes(int L, int log2h);
-int check_lds(size_t lds, int L, int log2h);
+size_t beam_lds_bytes(int L, int slots);
+int check_lds(size_t lds, int L, int slots);
 int launch_batched(int bits, int group, int vbytes, const StepHeader *hdr,
                       const IndexView *subs, unsigned int *counter, int Lmax, VisitedCfg vc,
                       int grid, hipStream_t stream);

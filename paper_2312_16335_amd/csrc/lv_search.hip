@@ -202,9 +202,85 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// Sum over each aligned group of W lanes (8, 16 or 64) of 32-bit integers
+// (modulo 2^32), with DPP adds; every lane of a group ends with its sum.
+template <int W>
+__device__ __forceinline__ uint32_t group_sum_u32(uint32_t v) {
+  static_assert(W == 8 || W == 16 || W == 64, "groups of 8, 16 or 64 lanes");
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppQuadXor1, 0xF, 0xF, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppQuadXor2, 0xF, 0xF, true);
+  if constexpr (W == 8) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowHalfMirror, 0xF, 0xF, true);
+    return v;
+  }
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowRor4, 0xF, 0xF, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowRor8, 0xF, 0xF, true);
+  if constexpr (W == 64) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast15, 0xA, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast31, 0xC, 0xF, false);
+    v = lane_u32(v, 63);
+  }
+  return v;
+}
+
+// Largest value over each aligned group of W lanes, for v >= 0.
+template <int W>
+__device__ __forceinline__ float group_max_nonneg(float v) {
+  static_assert(W == 8 || W == 16 || W == 64, "groups of 8, 16 or 64 lanes");
+  auto mx = [](float a, int b) { return fmaxf(a, __int_as_float(b)); };
+  v = mx(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), kDppQuadXor1, 0xF, 0xF, true));
+  v = mx(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), kDppQuadXor2, 0xF, 0xF, true));
+  if constexpr (W == 8) {
+    return mx(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), kDppRowHalfMirror, 0xF, 0xF,
+                                             true));
+  }
+  v = mx(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), kDppRowRor4, 0xF, 0xF, true));
+  v = mx(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), kDppRowRor8, 0xF, 0xF, true));
+  if constexpr (W == 64) {  // rows that receive nothing take max(v, +0.0) = v
+    v = mx(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), kDppRowBcast15, 0xA, 0xF,
+                                          false));
+    v = mx(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), kDppRowBcast31, 0xC, 0xF,
+                                          false));
+    v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+  }
+  return v;
+}
+
 template <int V>
 struct Chunk {
   uint32_t w[V / 4];
+};
+
+constexpr uint32_t kOnes = 0x01010101u;  // one per byte: udot4 with it sums the bytes
+constexpr uint32_t kNib = 0x0F0F0F0Fu;   // the low nibble of every byte
+
+__device__ __forceinline__ uint32_t udot4(uint32_t a, uint32_t b, uint32_t acc) {
+  return __builtin_amdgcn_udot4(a, b, acc, false);
+}
+
+// Query side of the primary scoring in one lane: its code slots t = 0..NQ-1
+// are components gl NQ + t.
+//
+// Search: the projected query on its grid, q~_t = Q_t 2^-s with integers
+// |Q_t| <= 2^22 (s from the largest |q_j|: the largest is below 2^(22 - s)),
+// held as the three bytes of Q_t + 2^23 (at most 3 * 2^22 < 2^24).  For
+// 8-bit codes l[k][w] packs byte k of the offset values of slots 4w..4w+3,
+// so that udot4(code dword w, l[k][w]) sums code * byte k over four slots;
+// for 4-bit codes l[k][w] (k < 3) covers the low nibbles of dword w (slots
+// 8w, 8w+2, 8w+4, 8w+6) and l[3 + k][w] the high nibbles.  Then
+// sum_t c_t Q_t = A0 + 2^8 A1 + 2^16 A2 - 2^23 sum_t c_t with Ak the sums of
+// code * byte k: integers, exact.  Slots past d have Q_t = 0 (offset bytes
+// only), whatever their record bytes hold.
+//
+// Construction: the searched node's own codes (zero past d) in l[0] (8-bit)
+// or its low / high nibbles in l[0] / l[1] (4-bit), and in m the mask of the
+// code bits below d, applied to a candidate's bytes for its code sums.
+template <int BITS, int V, bool BUILD>
+struct QCode {
+  static constexpr int NW = V / 4;
+  static constexpr int NL = BUILD ? (BITS == 8 ? 1 : 2) : (BITS == 8 ? 3 : 6);
+  uint32_t l[NL][NW];
+  uint32_t m[BUILD ? NW : 1];
 };
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -228,25 +304,23 @@ __device__ __forceinline__ Chunk<V> load_chunk(const LV_GLOBAL unsigned char *p)
   return c;
 }
 
-template <int BITS, int V>
-__device__ __forceinline__ uint32_t code_at(const Chunk<V> &c, int t) {
-  if constexpr (BITS == 8)
-    return (c.w[t >> 2] >> (8 * (t & 3))) & 0xFFu;
-  else
-    return (c.w[t >> 3] >> (4 * (t & 7))) & 0xFu;
-}
-
 // Score the nc candidate ids in cid[] into cs[].  Group g of G lanes takes
 // candidates g, g + 64/G, ...; U records per group are in flight at once.
-// BUILD: qv holds the searched node's codes, so the dot product is the
-// integer sum S_ab; the candidate's S_b and S_bb are summed alongside
-// (packed as S_bb + 2^32 S_b, exact in float64) and the score is minus the
-// squared distance.
+// Search: score = delta <c, q~> + lo sum(q~) + <q~, mu> with <c, q~> =
+// 2^-s sum_t c_t Q_t (scale = 2^-s; sq, cq the other two terms): the
+// integer sum is exact (see QCode), so <c, q~> is exact in float64.
+// Groups of 8 or 16 lanes add its parts as 32-bit integers (with 8-bit
+// codes a record of at most 256 bytes keeps the low part below 2^32);
+// 64-lane groups (records up to 1 KiB) join the parts in float64 per lane
+// first, exactly (integers below 2^53).
+// BUILD: the query is the searched node's codes, so the sum is the integer
+// S_ab; the candidate's S_b and S_bb are summed alongside and the score is
+// minus the squared distance.
 template <int BITS, int G, int V, bool BUILD = false>
-__device__ __forceinline__ void score_batch(const IndexView &ix, const float (&qv)[V * 8 / BITS],
-                                            double sq, double cq, const BuildQ &bq,
+__device__ __forceinline__ void score_batch(const IndexView &ix, const QCode<BITS, V, BUILD> &qc,
+                                            double scale, double sq, double cq, const BuildQ &bq,
                                             const uint32_t *cid, double *cs, int nc, int lane) {
-  constexpr int NQ = V * 8 / BITS;
+  constexpr int NW = V / 4;
   constexpr int RPP = 64 / G;
   constexpr int U = (48 / V) < 2 ? 2 : (48 / V);
   const int gl = lane % G;
@@ -276,32 +350,68 @@ __device__ __forceinline__ void score_batch(const IndexView &ix, const float (&q
         }
       } else {
 #pragma unroll
-        for (int w = 0; w < V / 4; ++w) ch[u].w[w] = 0u;
+        for (int w = 0; w < NW; ++w) ch[u].w[w] = 0u;
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (base + u * RPP >= nc) break;  // uniform: no record in this pass
-      double acc = 0.0;
-#pragma unroll
-      for (int t = 0; t < NQ; ++t)
-        acc = fma((double)code_at<BITS, V>(ch[u], t), (double)qv[t], acc);
-      acc = group_sum<G>(acc);
-      double pk = 0.0;
+      double acc;
+      double sb = 0.0, sbb = 0.0;
       if constexpr (BUILD) {
-        uint32_t s1 = 0u, s2 = 0u;
+        uint32_t ab = 0u, s1 = 0u, s2 = 0u;
 #pragma unroll
-        for (int t = 0; t < NQ; ++t) {
-          const uint32_t cv = gl * NQ + t < ix.d ? code_at<BITS, V>(ch[u], t) : 0u;
-          s1 += cv;
-          s2 += cv * cv;
+        for (int w = 0; w < NW; ++w) {
+          const uint32_t c = ch[u].w[w], cm = c & qc.m[w];
+          if constexpr (BITS == 8) {
+            ab = udot4(c, qc.l[0][w], ab);
+            s1 = udot4(cm, kOnes, s1);
+            s2 = udot4(cm, cm, s2);
+          } else {
+            ab = udot4(c & kNib, qc.l[0][w], ab);
+            ab = udot4((c >> 4) & kNib, qc.l[1][w], ab);
+            const uint32_t e = cm & kNib, o = (cm >> 4) & kNib;
+            s1 = udot4(e + o, kOnes, s1);
+            s2 = udot4(e, e, s2);
+            s2 = udot4(o, o, s2);
+          }
         }
-        pk = group_sum<G>((double)s2 + 4294967296.0 * (double)s1);
+        acc = (double)group_sum_u32<G>(ab);
+        sb = (double)group_sum_u32<G>(s1);
+        sbb = (double)group_sum_u32<G>(s2);
+      } else {
+        uint32_t a0 = 0u, a1 = 0u, a2 = 0u, as = 0u;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const uint32_t c = ch[u].w[w];
+          if constexpr (BITS == 8) {
+            a0 = udot4(c, qc.l[0][w], a0);
+            a1 = udot4(c, qc.l[1][w], a1);
+            a2 = udot4(c, qc.l[2][w], a2);
+            as = udot4(c, kOnes, as);
+          } else {
+            const uint32_t e = c & kNib, o = (c >> 4) & kNib;
+            a0 = udot4(o, qc.l[3][w], udot4(e, qc.l[0][w], a0));
+            a1 = udot4(o, qc.l[4][w], udot4(e, qc.l[1][w], a1));
+            a2 = udot4(o, qc.l[5][w], udot4(e, qc.l[2][w], a2));
+            as = udot4(e + o, kOnes, as);
+          }
+        }
+        const uint32_t lo32 = a0 + (a1 << 8);   // < 2^32 over the group (G <= 16)
+        const uint32_t hi32 = a2 - (as << 7);   // A2 - 2^7 sum(c): a signed 32-bit value
+        double S;
+        if constexpr (G == 64) {
+          S = group_sum<64>(fma((double)(int32_t)hi32, 65536.0, (double)lo32));
+        } else {
+          S = fma((double)(int32_t)group_sum_u32<G>(hi32), 65536.0,
+                  (double)group_sum_u32<G>(lo32));
+        }
+        acc = S * scale;
       }
       const int c = base + u * RPP + grp;
       if (in_chunk) {
 #pragma unroll
-        for (int w = 0; w < V / 4; ++w) {
+        for (int w = 0; w < NW; ++w) {
           if (w == cw0) dlw[u] = ch[u].w[w];
           if (w == cw0 + 1) low[u] = ch[u].w[w];
         }
@@ -310,8 +420,6 @@ __device__ __forceinline__ void score_batch(const IndexView &ix, const float (&q
         const double delta = (double)__uint_as_float(dlw[u]);
         const double lo = (double)__uint_as_float(low[u]);
         if constexpr (BUILD) {
-          const double sb = floor(pk * 0x1p-32);
-          const double sbb = pk - sb * 4294967296.0;
           cs[c] = -lvq_l2(bq.d, bq.da, bq.lo, bq.s, bq.ss, delta, lo, sb, sbb, acc);
         } else {
           cs[c] = delta * acc + lo * sq + cq;
@@ -348,16 +456,18 @@ __device__ __forceinline__ void sort64(double &s, uint32_t &id, int lane, int n)
 // Visited test-and-set.  After `probes` occupied slots the id replaces the
 // one in its home slot (the set forgets an older id) and counts as unknown:
 // it is scored, and the merge drops it if it is in the window.
-__device__ __forceinline__ bool hash_visit(uint32_t *hash, int log2h, int probes, uint32_t n) {
-  const uint32_t mask = (1u << log2h) - 1u;
-  const uint32_t h0 = (n * 2654435761u) >> (32 - log2h);
+// The home slot is the high half of (Knuth's multiplicative hash of n) x
+// slots, which for 2^k slots is the hash's top k bits.
+__device__ __forceinline__ bool hash_visit(uint32_t *hash, uint32_t slots, int probes,
+                                           uint32_t n) {
+  const uint32_t h0 = __umulhi(n * 2654435761u, slots);
   uint32_t h = h0;
 #pragma unroll 1
   for (int t = 0; t < probes; ++t) {
     const uint32_t old = atomicCAS(&hash[h], kEmpty, n);
     if (old == kEmpty) return true;
     if (old == n) return false;
-    h = (h + 1u) & mask;
+    h = h + 1u == slots ? 0u : h + 1u;
   }
   atomicExch(&hash[h0], n);
   return true;
@@ -757,50 +867,88 @@ __device__ __forceinline__ int *team_cmd(const Lds &sm, int hslots) {
 // two barriers, and the other wavefronts return.  Every wavefront therefore
 // passes the same sequence of barriers.
 template <int BITS, int G, int V, bool BUILD = false, bool MULTI = false, int WQ = 1>
-__device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm, int log2h,
+__device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm, int hslots,
                              int probes, int expand, int lane) {
   static_assert(WQ == 1 || (MULTI && !BUILD), "team search is the multi-expansion body");
   constexpr int NQ = V * 8 / BITS;
   const int L = job.L;
-  const int hslots = 1 << log2h;
 
-  // projected query slice of this lane (float32, exact in float64 products)
+  // this lane's part of the query side of the scoring (see QCode)
   const int gl = lane % G;
-  float qv[NQ];
-  double sq = 0.0, cq = 0.0;
+  QCode<BITS, V, BUILD> qc;
+  double scale = 1.0, sq = 0.0, cq = 0.0;
   BuildQ bq{};
   if constexpr (BUILD) {
-    // the node's own codes (small integers, exact in float32 and float64)
+    // the node's own codes (small integers), masked past d
     const LV_GLOBAL unsigned char *rec = gp(ix.records) + (size_t)job.node * (size_t)ix.stride;
     const Chunk<V> ch = load_chunk<V>(rec + gl * V);
+    constexpr int CPW = 32 / BITS;  // codes per dword
     uint32_t s1 = 0u, s2 = 0u;
 #pragma unroll
-    for (int t = 0; t < NQ; ++t) {
-      const uint32_t cv = gl * NQ + t < ix.d ? code_at<BITS, V>(ch, t) : 0u;
-      qv[t] = (float)cv;
-      s1 += cv;
-      s2 += cv * cv;
+    for (int w = 0; w < qc.NW; ++w) {
+      uint32_t m = 0u;
+#pragma unroll
+      for (int i = 0; i < CPW; ++i)
+        if (gl * NQ + w * CPW + i < ix.d) m |= ((1u << BITS) - 1u) << (BITS * i);
+      qc.m[w] = m;
+      const uint32_t c = ch.w[w] & m;
+      if constexpr (BITS == 8) {
+        qc.l[0][w] = c;
+        s1 = udot4(c, kOnes, s1);
+        s2 = udot4(c, c, s2);
+      } else {
+        const uint32_t e = c & kNib, o = (c >> 4) & kNib;
+        qc.l[0][w] = e;
+        qc.l[1][w] = o;
+        s1 = udot4(e + o, kOnes, s1);
+        s2 = udot4(o, o, udot4(e, e, s2));
+      }
     }
     const LV_GLOBAL float *cw = reinterpret_cast<const LV_GLOBAL float *>(rec + ix.code_bytes);
     bq.d = (double)ix.d;
     bq.da = (double)cw[0];
     bq.lo = (double)cw[1];
-    bq.s = lane_f64(group_sum<G>((double)s1), 0);
-    bq.ss = lane_f64(group_sum<G>((double)s2), 0);
+    bq.s = (double)lane_u32(group_sum_u32<G>(s1), 0);
+    bq.ss = (double)lane_u32(group_sum_u32<G>(s2), 0);
   } else {
+    float qv[NQ];
+    float am = 0.f;
 #pragma unroll
     for (int t = 0; t < NQ; ++t) {
       // unconditional loads (clamped index) so that all of them are in flight
       const int j = gl * NQ + t;
-      const bool in = j < ix.d;
-      const float x = gp(job.qp)[in ? j : 0];
-      const float mj = gp(ix.mu)[in ? j : 0];
-      qv[t] = in ? x : 0.f;
-      sq += (double)qv[t];
-      cq = fma((double)qv[t], (double)mj, cq);
+      const float x = gp(job.qp)[j < ix.d ? j : 0];
+      qv[t] = j < ix.d ? x : 0.f;
+      am = fmaxf(am, fabsf(qv[t]));
+    }
+    // the grid: s = 22 - e with max |q_j| = f 2^e, f in [0.5, 1) (e = 0 for 0)
+    am = group_max_nonneg<G>(am);
+    int e = 0;
+    (void)frexpf(am, &e);
+    const int sh = 22 - __builtin_amdgcn_readfirstlane(e);
+    scale = ldexp(1.0, -sh);
+    double sumq = 0.0;
+#pragma unroll
+    for (int w = 0; w < qc.NW; ++w)
+#pragma unroll
+      for (int k = 0; k < qc.NL; ++k) qc.l[k][w] = 0u;
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+      const int j = gl * NQ + t;
+      const double Qt = rint(ldexp((double)qv[t], sh));  // |Qt| <= 2^22, exact
+      sumq += Qt;
+      const float mj = gp(ix.mu)[j < ix.d ? j : 0];
+      cq = fma(Qt * scale, j < ix.d ? (double)mj : 0.0, cq);
+      const uint32_t off = (uint32_t)((int32_t)Qt + (1 << 23));
+      constexpr int CPW = 32 / BITS;
+      const int w = t / CPW, i = t % CPW;
+      const int set = BITS == 8 ? 0 : 3 * (i & 1);  // 4-bit: low / high nibbles
+      const int b = BITS == 8 ? i : i >> 1;          // byte of the code dword
+#pragma unroll
+      for (int k = 0; k < 3; ++k) qc.l[set + k][w] |= ((off >> (8 * k)) & 0xFFu) << (8 * b);
     }
     // the same in every lane after the group reduction: keep them scalar
-    sq = lane_f64(group_sum<G>(sq), 0);
+    sq = lane_f64(group_sum<G>(sumq), 0) * scale;  // exact: |sum| < 2^53
     cq = lane_f64(group_sum<G>(cq), 0);
   }
   if constexpr (WQ > 1) {
@@ -820,7 +968,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
         }
         const int off = team_slice<G, WQ>(nc, wave);
         const int cnt = team_slice<G, WQ>(nc, wave + 1) - off;
-        score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid() + off, sm.cs() + off, cnt,
+        score_batch<BITS, G, V, BUILD>(ix, qc, scale, sq, cq, bq, sm.cid() + off, sm.cs() + off, cnt,
                                        lane);
         __syncthreads();  // scores written
       }
@@ -832,10 +980,10 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
   // seed the window with the entry node
   if (lane == 0) {
     sm.cid()[0] = ix.entry;
-    hash_visit(sm.hash(), log2h, probes, ix.entry);
+    hash_visit(sm.hash(), (uint32_t)hslots, probes, ix.entry);
   }
   wave_sync();
-  score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), 1, lane);
+  score_batch<BITS, G, V, BUILD>(ix, qc, scale, sq, cq, bq, sm.cid(), sm.cs(), 1, lane);
   wave_sync();
   if (lane == 0) {
     sm.ls()[0] = sm.cs()[0];
@@ -893,7 +1041,7 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
             n = gp(ix.adj)[(size_t)sm.xid()[e] * (size_t)ix.R + rb + lane];
         }
         bool fresh = false;
-        if (n < ix.N) fresh = hash_visit(sm.hash(), log2h, probes, n);
+        if (n < ix.N) fresh = hash_visit(sm.hash(), (uint32_t)hslots, probes, n);
         const uint64_t fm = __ballot(fresh);
         const int cnt = __popcll(fm);
         if (!more || nc + cnt > 64) {
@@ -902,11 +1050,11 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
             if constexpr (WQ > 1) {
               if (lane == 0) *team_cmd(sm, hslots) = nc;
               __syncthreads();  // batch and count visible to the workgroup
-              score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(),
+              score_batch<BITS, G, V, BUILD>(ix, qc, scale, sq, cq, bq, sm.cid(), sm.cs(),
                                              team_slice<G, WQ>(nc, 1), lane);
               __syncthreads();  // every slice scored
             } else {
-              score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), nc, lane);
+              score_batch<BITS, G, V, BUILD>(ix, qc, scale, sq, cq, bq, sm.cid(), sm.cs(), nc, lane);
             }
             wave_sync();
             n_dist += nc;
@@ -972,13 +1120,13 @@ __device__ void search_query(const IndexView &ix, const Job &job, const Lds &sm,
       for (int rb = 0; rb < ix.R; rb += 64) {
         uint32_t n = rb == 0 ? first : (rb + lane < ix.R ? row[rb + lane] : kSentinel);
         bool fresh = false;
-        if (n < ix.N) fresh = hash_visit(sm.hash(), log2h, probes, n);
+        if (n < ix.N) fresh = hash_visit(sm.hash(), (uint32_t)hslots, probes, n);
         const uint64_t fm = __ballot(fresh);
         const int nc = __popcll(fm);
         if (nc == 0) continue;
         if (fresh) sm.cid()[lane_rank(fm)] = n;
         wave_sync();
-        score_batch<BITS, G, V, BUILD>(ix, qv, sq, cq, bq, sm.cid(), sm.cs(), nc, lane);
+        score_batch<BITS, G, V, BUILD>(ix, qc, scale, sq, cq, bq, sm.cid(), sm.cs(), nc, lane);
         wave_sync();
         n_dist += nc;
 
@@ -1062,7 +1210,7 @@ struct PlainArgs {
   uint32_t *ids;
   float *scores;
   uint32_t *counters;
-  int32_t hash_log2;
+  int32_t hash_slots;
   int32_t probes;
   int32_t expand;
   int32_t qp_stride;  // floats per projected query (d, or D with residual secondaries)
@@ -1082,7 +1230,7 @@ __global__ __launch_bounds__(64) void beam_kernel(PlainArgs a) {
   job.ids = a.ids + qi * a.k;
   job.scores = a.scores + qi * a.k;
   job.counters = a.counters ? a.counters + 2 * qi : nullptr;
-  search_query<BITS, G, V, false, MULTI>(a.ix, job, sm, a.hash_log2, a.probes, a.expand,
+  search_query<BITS, G, V, false, MULTI>(a.ix, job, sm, a.hash_slots, a.probes, a.expand,
                                          threadIdx.x);
 }
 
@@ -1101,7 +1249,7 @@ __global__ __launch_bounds__(64 * kTeamWaves) void team_kernel(PlainArgs a) {
   job.ids = a.ids + qi * a.k;
   job.scores = a.scores + qi * a.k;
   job.counters = a.counters ? a.counters + 2 * qi : nullptr;
-  search_query<BITS, G, V, false, true, kTeamWaves>(a.ix, job, sm, a.hash_log2, a.probes,
+  search_query<BITS, G, V, false, true, kTeamWaves>(a.ix, job, sm, a.hash_slots, a.probes,
                                                     a.expand, (int)(threadIdx.x & 63u));
 }
 
@@ -1120,7 +1268,7 @@ template <int BITS, int G, int V, bool MULTI>
 __global__ __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(batched_waves<BITS, V>()))) void batched_kernel(
     const StepHeader *__restrict__ hdr, const IndexView *__restrict__ subs,
-    unsigned int *__restrict__ counter, int32_t Lmax, int32_t hash_log2, int32_t probes,
+    unsigned int *__restrict__ counter, int32_t Lmax, int32_t hash_slots, int32_t probes,
     int32_t expand) {
   const int lane = threadIdx.x;
   const Lds sm = carve(Lmax);
@@ -1163,7 +1311,7 @@ __attribute__((amdgpu_waves_per_eu(batched_waves<BITS, V>()))) void batched_kern
     job.ids = hdr->ids + r.out_off + j * r.k;
     job.scores = hdr->scores + r.out_off + j * r.k;
     job.counters = hdr->counters ? hdr->counters + 2 * (int64_t)u : nullptr;
-    search_query<BITS, G, V, false, MULTI>(ix, job, sm, hash_log2, probes, expand, lane_q);
+    search_query<BITS, G, V, false, MULTI>(ix, job, sm, hash_slots, probes, expand, lane_q);
   }
 }
 
@@ -1185,7 +1333,7 @@ __global__ __launch_bounds__(64) void build_search_kernel(BuildSearchArgs a) {
   job.scores = nullptr;
   job.counters = a.counters ? a.counters + 2 * (size_t)b : nullptr;
   job.node = p;
-  search_query<BITS, G, V, true>(a.ix, job, carve(a.L), a.hash_log2, a.probes, 1, threadIdx.x);
+  search_query<BITS, G, V, true>(a.ix, job, carve(a.L), a.hash_slots, a.probes, 1, threadIdx.x);
   for (int r = threadIdx.x; r < a.ix.R; r += 64)
     gpw(job.ids)[a.L + r] = gp(a.ix.adj)[(size_t)p * (size_t)a.ix.R + r];
   if (a.stats && job.counters && threadIdx.x == 0) {  // the lane that wrote the counters
@@ -1218,10 +1366,10 @@ int launch_batched_t(const StepHeader *hdr, const IndexView *subs, unsigned int 
   if (counter) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
   if (vc.expand > 1)
     hipLaunchKernelGGL((batched_kernel<BITS, G, V, true>), dim3(grid), dim3(64), lds, s, hdr,
-                       subs, counter, Lmax, vc.log2h, vc.probes, vc.expand);
+                       subs, counter, Lmax, vc.slots, vc.probes, vc.expand);
   else
     hipLaunchKernelGGL((batched_kernel<BITS, G, V, false>), dim3(grid), dim3(64), lds, s, hdr,
-                       subs, counter, Lmax, vc.log2h, vc.probes, vc.expand);
+                       subs, counter, Lmax, vc.slots, vc.probes, vc.expand);
   LV_CHECK_LAUNCH();
   return LV_OK;
 }
@@ -1320,8 +1468,8 @@ IndexView make_view(const lv_index *ix) {
 
 int visited_config(const lv_search_params *params, VisitedCfg *cfg) {
   const int hs = params && params->hash_slots ? params->hash_slots : kDefaultHashSlots;
-  if (hs < 256 || hs > 65536 || (hs & (hs - 1)))
-    LV_FAIL(LV_EINVAL, "hash_slots must be a power of two in [256, 65536] (got %d)", hs);
+  if (hs < 256 || hs > 65536 || hs % 256)
+    LV_FAIL(LV_EINVAL, "hash_slots must be a multiple of 256 in [256, 65536] (got %d)", hs);
   const int pr = params ? params->probes : 0;
   if (pr < 0 || pr > 16) LV_FAIL(LV_EINVAL, "probes must be in [0, 16] (got %d)", pr);
   const int ex = params ? params->expand : 0;
@@ -1333,25 +1481,23 @@ int visited_config(const lv_search_params *params, VisitedCfg *cfg) {
     LV_FAIL(LV_EINVAL, "launch must be LV_LAUNCH_PER_QUERY, LV_LAUNCH_PERSISTENT or "
                        "LV_LAUNCH_TEAM (got %d)", la);
   cfg->team = la == LV_LAUNCH_TEAM;
-  int l = 0;
-  while ((1 << l) < hs) ++l;
-  cfg->log2h = l;
+  cfg->slots = hs;
   // small sets (occupancy matters): few probes; large sets: nearly exact
   cfg->probes = pr ? pr : (hs >= 4096 ? 8 : 2);
   return LV_OK;
 }
 
-size_t beam_lds_bytes(int L, int log2h) {
-  return (size_t)L * 12 + 64 * 12 + 4 * kMaxExpand + ((size_t)4 << log2h);
+size_t beam_lds_bytes(int L, int slots) {
+  return (size_t)L * 12 + 64 * 12 + 4 * kMaxExpand + (size_t)4 * (size_t)slots;
 }
 
-int check_lds(size_t lds, int L, int log2h) {
+int check_lds(size_t lds, int L, int slots) {
   int dev = 0, lds_max = 0;
   LV_CHECK_HIP(hipGetDevice(&dev));
   LV_CHECK_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   if (lds > (size_t)lds_max)
     LV_FAIL(LV_EINVAL, "window %d with %d hash slots needs %zu bytes of LDS (limit %d)", L,
-            1 << log2h, lds, lds_max);
+            slots, lds, lds_max);
   return LV_OK;
 }
 
@@ -1363,8 +1509,8 @@ int launch_beam(const lv_index *ix, const float *Q, const float *Qp, int64_t m, 
   if (rc != LV_OK) return rc;
   if (m == 0) return LV_OK;
   if (m > 0x7FFFFFFF) LV_FAIL(LV_EINVAL, "at most 2^31-1 queries per call");
-  const size_t lds = beam_lds_bytes(L, vc.log2h);
-  rc = check_lds(lds + (vc.team ? kTeamLdsBytes : 0), L, vc.log2h);
+  const size_t lds = beam_lds_bytes(L, vc.slots);
+  rc = check_lds(lds + (vc.team ? kTeamLdsBytes : 0), L, vc.slots);
   if (rc != LV_OK) return rc;
   PlainArgs a;
   a.ix = make_view(ix);
@@ -1376,7 +1522,7 @@ int launch_beam(const lv_index *ix, const float *Q, const float *Qp, int64_t m, 
   a.ids = ids;
   a.scores = scores;
   a.counters = counters;
-  a.hash_log2 = vc.log2h;
+  a.hash_slots = vc.slots;
   a.probes = vc.probes;
   a.expand = vc.expand;
   a.qp_stride = ix->qp_width;
@@ -1387,7 +1533,7 @@ int launch_beam(const lv_index *ix, const float *Q, const float *Qp, int64_t m, 
 int launch_batched(int bits, int group, int vbytes, const StepHeader *hdr,
                       const IndexView *subs, unsigned int *counter, int Lmax, VisitedCfg vc,
                       int grid, hipStream_t stream) {
-  const size_t lds = beam_lds_bytes(Lmax, vc.log2h);
+  const size_t lds = beam_lds_bytes(Lmax, vc.slots);
   BatchedLaunch f{hdr, subs, counter, Lmax, vc, lds, grid, stream};
   return dispatch(bits, group, vbytes, f);
 }
@@ -1395,14 +1541,14 @@ int launch_batched(int bits, int group, int vbytes, const StepHeader *hdr,
 int launch_build_search(int bits, int group, int vbytes, const BuildSearchArgs &a,
                         hipStream_t stream) {
   if (a.B <= 0) return LV_OK;
-  const size_t lds = beam_lds_bytes(a.L, a.hash_log2);
+  const size_t lds = beam_lds_bytes(a.L, a.hash_slots);
   BuildLaunch f{a, lds, stream};
   return dispatch(bits, group, vbytes, f);
 }
 
 int batched_occupancy(int bits, int group, int vbytes, int Lmax, VisitedCfg vc, int *blocks) {
-  const size_t lds = beam_lds_bytes(Lmax, vc.log2h);
-  int rc = check_lds(lds, Lmax, vc.log2h);
+  const size_t lds = beam_lds_bytes(Lmax, vc.slots);
+  int rc = check_lds(lds, Lmax, vc.slots);
   if (rc != LV_OK) return rc;
   Occupancy f{lds, vc.expand > 1, blocks};
   return dispatch(bits, group, vbytes, f);

@@ -82,7 +82,9 @@ def test_search_argument_validation_before_launch():
         rc = lib.lv_search_projected(h, FAKE, FAKE, m, k, L, FAKE, FAKE, None,
                                      ctypes.byref(prm), None)
         assert rc == lv.LV_EINVAL, (m, k, L)
-    for bad in (lv.SearchParams(1000, 0, 0),   # slots not a power of two
+    for bad in (lv.SearchParams(1000, 0, 0),   # slots not a multiple of 256
+                lv.SearchParams(128, 0, 0),    # too few slots
+                lv.SearchParams(65792, 0, 0),  # too many slots
                 lv.SearchParams(1024, 17, 0),  # too many probes
                 lv.SearchParams(1024, -1, 0),
                 lv.SearchParams(1024, 0, 0, 9),    # more expansions per step than allowed

@@ -165,7 +165,7 @@ def test_autotune_knobs_returns_a_valid_choice(lv, subs):
     ids = torch.zeros((1500,), dtype=torch.int32, device=DEV)
     sc = torch.zeros((1500,), dtype=torch.float32, device=DEV)
     best, ms = lv.lv_autotune_knobs(multi, 4, 256, 64, reqs, Q, ids, sc, reps=2)
-    assert best["hash_slots"] in (1024, 2048, 4096, 8192) and ms > 0
+    assert best["hash_slots"] in (1024, 1280, 1536, 2048, 4096, 8192) and ms > 0
     assert best["launch"] in (0, 1)
     multi.close()
 

@@ -103,10 +103,48 @@ def test_primary_score_equals_factored_form(tiny):
     wl, idx, Q, Qp = tiny
     ids = np.arange(50)
     qp = Qp[0].astype(np.float64)
+    qg = search.grid_query(qp)
     plain = search.primary_scores(idx, qp, ids)
-    fact = (idx.delta[ids].astype(np.float64) * (idx.codes[ids].astype(np.float64) @ qp)
-            + idx.lo[ids].astype(np.float64) * qp.sum() + idx.mu.astype(np.float64) @ qp)
+    fact = (idx.delta[ids].astype(np.float64) * (idx.codes[ids].astype(np.float64) @ qg)
+            + idx.lo[ids].astype(np.float64) * qg.sum() + idx.mu.astype(np.float64) @ qg)
     assert np.allclose(plain, fact, rtol=1e-12, atol=1e-12)
+    # on the grid, <q~, c> is an integer sum times 2^-s: exact in int64
+    s = 22 - int(np.frexp(np.abs(qp).max())[1])
+    Qi = np.rint(np.ldexp(qp, s)).astype(np.int64)
+    S = idx.codes[ids].astype(np.int64) @ Qi
+    assert np.array_equal(np.ldexp(S.astype(np.float64), -s),
+                          idx.codes[ids].astype(np.float64) @ qg)
+
+
+def test_grid_query_hand_worked():
+    """Largest component 3 = 0.75 * 2^2, so e = 2, s = 20: 3 stays; float32(0.1)
+    = 13421773 * 2^-27 becomes rint(104857.6015625) = 104858 steps of 2^-20;
+    -1e-9 is below half a step (rounds to zero).  Largest 1 = 0.5 * 2^1: s = 21,
+    and 2.5 and 3.5 steps of 2^-21 round to the even 2 and 4 steps."""
+    g = search.grid_query(np.array([3.0, np.float32(0.1), -1e-9, 0.0], np.float32))
+    assert g.tolist() == [3.0, 104858 * 2.0 ** -20, 0.0, 0.0]
+    g = search.grid_query(np.array([1.0, 2.5 * 2.0 ** -21, -3.5 * 2.0 ** -21], np.float32))
+    assert g.tolist() == [1.0, 2 * 2.0 ** -21, -4 * 2.0 ** -21]
+    assert search.grid_query(np.zeros(4, np.float32)).tolist() == [0.0] * 4
+
+
+def test_grid_query_properties():
+    """Multiples of 2^-s with at most 2^22 steps, within half a step (at most
+    2^-22 of the largest component) of the query, unchanged by a second
+    rounding, and scaled exactly with the query by powers of 2."""
+    rng = np.random.default_rng(5)
+    for t in range(200):
+        q = (rng.standard_normal(160) * 10.0 ** rng.uniform(-30, 30)).astype(np.float32)
+        q[rng.random(160) < 0.1] *= np.float32(1e-6)
+        g = search.grid_query(q)
+        q64 = q.astype(np.float64)
+        s = 22 - int(np.frexp(np.abs(q64).max())[1])
+        steps = np.ldexp(g, s)
+        assert np.array_equal(steps, np.rint(steps)) and np.abs(steps).max() <= 2 ** 22
+        assert np.all(np.abs(g - q64) <= np.ldexp(0.5, -s))
+        assert np.all(np.abs(g - q64) <= 2.0 ** -22 * np.abs(q64).max())
+        assert np.array_equal(search.grid_query(g), g)
+        assert np.array_equal(search.grid_query(q * np.float32(2.0 ** 7)), g * 2.0 ** 7)
 
 
 def test_parallel_search_matches_serial(tiny):
@@ -284,8 +322,11 @@ def test_two_level_full_window_equals_brute_force(tiny, bits):
     tidx, Y, mu = _two_level_index(tiny, bits)
     yhat = lvq.decode_two_level(tidx.codes, tidx.delta, tidx.lo, tidx.sec, tidx.sec_delta,
                                 tidx.sec_lo, mu)
+    y1 = lvq.decode(tidx.codes, tidx.delta, tidx.lo, mu).astype(np.float64)
     for i in range(3):
-        S = yhat @ Qp[i].astype(np.float64)
+        # first level on the query's grid, second level with the query as given
+        qp = Qp[i].astype(np.float64)
+        S = y1 @ search.grid_query(qp) + (yhat - y1) @ qp
         ids, sc = search.search_one(tidx, None, Qp[i], wl.k, tidx.N)
         order = np.lexsort((np.arange(tidx.N), -S))[:wl.k]
         assert ids.tolist() == order.tolist()
@@ -302,8 +343,12 @@ def test_two_level_scores_closer_to_the_reduced_inner_product(tiny):
     want = Y[ids].astype(np.float64) @ qp
     two = search.two_level_scores(tidx, qp, ids)
     one = search.primary_scores(tidx, qp, ids)
+    # the first level's part is taken on the query's grid (half a step per
+    # component at most)
+    y1 = lvq.decode(tidx.codes[ids], tidx.delta[ids], tidx.lo[ids], mu).astype(np.float64)
+    grid = np.abs(y1) @ np.abs(search.grid_query(qp) - qp)
     bound = (tidx.sec_delta[ids].astype(np.float64) / 2 + 1e-6 * tidx.delta[ids]) \
-        * np.abs(qp).sum()
+        * np.abs(qp).sum() + grid
     assert np.all(np.abs(two - want) <= bound + 1e-9)
     assert np.abs(two - want).max() < np.abs(one - want).max() / 20
 
