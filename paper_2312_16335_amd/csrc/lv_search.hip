@@ -409,11 +409,13 @@ __device__ __forceinline__ void score_batch(const IndexView &ix, const QCode<BIT
         acc = S * scale;
       }
       const int c = base + u * RPP + grp;
-      if (in_chunk) {
+      if (in_chunk) {  // cw0 is uniform: scalar branches, plain moves
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          if (w == cw0) dlw[u] = ch[u].w[w];
-          if (w == cw0 + 1) low[u] = ch[u].w[w];
+        for (int w = 0; w + 1 < NW; ++w) {
+          if (cw0 == w) {
+            dlw[u] = ch[u].w[w];
+            low[u] = ch[u].w[w + 1];
+          }
         }
       }
       if (gl == wl && c < nc) {
