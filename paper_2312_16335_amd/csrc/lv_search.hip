@@ -715,22 +715,23 @@ __device__ __forceinline__ void merge_batch(const Lds &sm, int nc, int L, int &n
   if (nsurv <= kFastMerge && nl <= 256) {
     // Few survivors (the common case once the window is full): a survivor
     // lands at (#window entries better) + (#kept survivors better), a
-    // window entry moves down by the kept survivors better than it.  The
-    // window is read into registers; survivors are broadcast one by one.
+    // window entry moves down by the kept survivors placed at or before it.
+    // The window is read into registers; survivors are broadcast one by one,
+    // and every per-survivor decision is a wave-wide mask (the compares'
+    // own lane masks, combined in scalar registers).
     const int nt = (nl + 63) >> 6;  // 64-entry chunks in use (uniform)
     double es[4];
-    uint32_t er[4];
+    uint32_t er[4], ei[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int e = lane + 64 * t;
       const bool ok = e < nl;
       es[t] = ok ? ls[e] : -INFINITY;
       er[t] = ok ? lid[e] : kSentinel;
+      ei[t] = er[t] & kIdMask;
     }
-    int sh[4] = {0, 0, 0, 0};  // kept survivors better than window entry t
+    uint64_t keepm = 0;  // lanes of the survivors kept
     int my_lb = 0, my_rank = 0;
-    bool my_keep = false;
-    int nkeep = 0;
     uint64_t rem = surv;
     while (rem) {  // uniform loop over survivors
       const int j = __ffsll((unsigned long long)rem) - 1;
@@ -742,28 +743,33 @@ __device__ __forceinline__ void merge_batch(const Lds &sm, int nc, int L, int &n
       uint64_t dm = 0;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        if (t < nt) {
-          const uint32_t idt = er[t] & kIdMask;
-          cnt += __popcll(__ballot(better(es[t], idt, cj, ij)));
-          dm |= __ballot(idt == ij);
-        }
+        if (t >= nt) break;  // uniform
+        const uint64_t gt = __ballot(es[t] > cj), eq = __ballot(es[t] == cj);
+        const uint64_t lt = __ballot(ei[t] < ij);
+        cnt += __popcll(gt | (eq & lt));
+        dm |= __ballot(ei[t] == ij);
       }
       bool keep = dm == 0;  // not already in the window
       if constexpr (DEDUP)  // nor kept earlier from this batch
-        keep = keep && __ballot(my_keep && bid == ij) == 0;
+        keep = keep && (keepm & __ballot(bid == ij)) == 0;
       if (keep) {
-        ++nkeep;
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          if (t < nt) sh[t] += (lane + 64 * t >= cnt) ? 1 : 0;
+        keepm |= 1ull << j;
         my_rank += (bid != kSentinel && better(cj, ij, bs, bid)) ? 1 : 0;
       }
-      if (lane == j) {
-        my_lb = cnt;
-        my_keep = keep;
+      my_lb = lane == j ? cnt : my_lb;
+    }
+    const int nkeep = __popcll(keepm);
+    if (nkeep == 0) return;
+    int sh[4] = {0, 0, 0, 0};  // kept survivors placed at or before window entry t
+    for (uint64_t km = keepm; km; km &= km - 1) {
+      const int lbj = __builtin_amdgcn_readlane(my_lb, __ffsll((unsigned long long)km) - 1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t >= nt) break;  // uniform
+        sh[t] += (lane + 64 * t >= lbj) ? 1 : 0;
       }
     }
-    if (nkeep == 0) return;
+    const bool my_keep = (keepm >> lane) & 1;
     // in place: the whole window was read into registers above
     double *ls_w = sm.ls();
 #pragma unroll
