@@ -996,7 +996,7 @@ def main():
         how = "given"
     else:
         knobs, _ = lv.lv_autotune_knobs(multi, nreq, m, L_star, reqs, Qd, ids_flat, scores_flat,
-                                        reps=2, expand=args.expand)
+                                        reps=6, expand=args.expand)
         hs, launch = knobs["hash_slots"], knobs["launch"]
         how = "chosen by the autotuner"
     launch_name = "persistent" if launch == lv.LV_LAUNCH_PERSISTENT else "per_query"
@@ -1366,7 +1366,7 @@ def ood_report(lv, torch, args, steps=10, in_flight=3, target=0.90, expand=3,
              torch.empty(m * k, dtype=torch.float32, device=dev)) for _ in range(in_flight)]
     if not hash_slots:  # visited-set size: the autotuner's choice, as for the main record
         knobs, _ = lv.lv_autotune_knobs(multi, len(reqs), m, L, reqs, Qd, outs[0][0], outs[0][1],
-                                        reps=2, expand=expand)
+                                        reps=6, expand=expand)
         hash_slots = knobs["hash_slots"]
     batch = lv.Batch(multi, max_requests=len(reqs), max_queries=m, max_L=L,
                      hash_slots=hash_slots, expand=expand)
