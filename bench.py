@@ -44,8 +44,8 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=None,
                     help="id-1m-768 (default); with --fit: ood-1m-512 (default)")
     ap.add_argument("--n", type=int, default=0, help="override database size (testing)")
@@ -258,7 +258,7 @@ def fit_report(lv, wl, n_s=100_000, m_test=1000, k=10):
 
 
 def multi_report(lv, torch, args, n_sub=64, pool=4096, learn=4096, n_req=1024,
-                 capacity=65536, target=0.90, L_max=512, in_flight=3):
+                 capacity=65536, target=0.90, L_max=512, in_flight=2):
     """The multi-index workload at full size.  Per sub-index s (sizes
     log-uniform in [1e4, 5e5], the id-1m-768 distribution with data seed
     4000 + s): LeanVec-ID fit on up to 100,000 vectors (host float64),
@@ -267,7 +267,7 @@ def multi_report(lv, torch, args, n_sub=64, pool=4096, learn=4096, n_req=1024,
     4,096 test and 4,096 learning queries with exact top-100 ids.  Windows L
     per (sub-index, k) from lv_autotune_window on the learning queries; the
     request stream (seed 401) is packed greedily into steps of at most
-    65,536 queries; the steps run back to back, three in flight, queries
+    65,536 queries; the steps run back to back, two in flight, queries
     resident.  Reported: whole-stream QPS (batched), the same requests as
     one plain search per request, and k-recall@k against the exact ids."""
     from dataclasses import replace
@@ -1056,10 +1056,10 @@ def main():
     serial_qps = m * args.steps / (total_ms / 1e3)
     kernel_ms = sum(a_.elapsed_time(b_) for a_, b_ in trav) / args.steps
 
-    # batched, pipelined: consecutive steps rotate over three streams (and three
+    # batched, pipelined: consecutive steps rotate over two streams (and two
     # output buffers), so a step's wavefronts start while earlier steps' slowest
     # queries finish; the timed region still spans exactly K whole steps
-    IN_FLIGHT = 3
+    IN_FLIGHT = 2  # steps in flight (the batch rotates four state sets: 2 divides 4)
     strs = [stream] + [torch.cuda.Stream() for _ in range(IN_FLIGHT - 1)]
     outs = [(ids_flat, scores_flat)] + [(torch.empty_like(ids_flat), torch.empty_like(scores_flat))
                                         for _ in range(IN_FLIGHT - 1)]
@@ -1200,7 +1200,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "N": wl.N, "D": wl.D, "d": wl.d, "lvq_bits": wl.bits,
                    "secondary": args.sec, "R": wl.R, "k": k, "queries": m, "L": L_star,
-                   "requests": nreq, "mode": "batched, 3 steps in flight",
+                   "requests": nreq, "mode": "batched, 2 steps in flight",
                    "visited_slots": hs, "launch": launch_name,
                    "expand": max(1, args.expand), "fit": fit_info},
         "recall_at_L": rec_star,
@@ -1237,7 +1237,7 @@ def main():
                                       "traversal graph on its launch stream",
                      "pipelined": {"launch_ms": launch_eff_ms, "achieved": achieved,
                                    "frac": achieved / HBM_PEAK_GBS,
-                                   "how": "three steps in flight: (last traversal end - first "
+                                   "how": "two steps in flight: (last traversal end - first "
                                           "traversal start) / K; the launches overlap, so "
                                           "this is the throughput per launch, not one "
                                           "launch's duration"}},
@@ -1260,7 +1260,7 @@ def main():
     print(json.dumps(out))
 
 
-def ood_report(lv, torch, args, steps=10, in_flight=3, target=0.90, expand=3,
+def ood_report(lv, torch, args, steps=40, in_flight=2, target=0.90, expand=3,
                hash_slots=0, cpu_sample=1000):
     """Compact run of the cross-modal workload (ood-1m-512: 1M x 512 database,
     10,000 out-of-distribution test queries): LeanVec-OOD fit (Algorithm 1, host
@@ -1269,7 +1269,7 @@ def ood_report(lv, torch, args, steps=10, in_flight=3, target=0.90, expand=3,
     float16 secondaries, the host-built graph (R = 64).  The smallest window
     reaching 10-recall@10 = 0.90 is found with the plain search, then batched
     steps over the uneven request stream run one after another (each launch's
-    own duration, for the roofline) and three in flight (the throughput).  The
+    own duration, for the roofline) and two in flight (the throughput).  The
     float64 oracle, with its own Frank-Wolfe fit and encoding, searches a sample
     of the queries at the same window for its recall."""
     from synth import gen

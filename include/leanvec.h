@@ -458,11 +458,13 @@ int lv_batch_destroy(lv_batch *batch);
  * Run one step on `stream`: validate and pack the requests on the host,
  * then launch the two captured graphs (table copy + grouped projection,
  * then counter reset + persistent traversal).  Asynchronous.  Steps rotate
- * through three sets of pinned table and device state; a set is reused three
+ * through four sets of pinned table and device state; a set is reused four
  * steps later, once the step that used it has finished (the host waits for
- * its table copy, `stream` waits for its traversal).  Up to three
+ * its table copy, `stream` waits for its traversal).  Up to four
  * consecutive steps issued on different streams therefore run concurrently;
- * their output buffers must then be distinct.
+ * their output buffers must then be distinct.  Rotate over 2 or 4 streams:
+ * the step that reuses a set is then on the stream of the step that used it
+ * (with 3 streams the reuse waits cross streams and stall the pipeline).
  *   Q:        device float32 [sum count][D]
  *   ids:      device uint32 [sum count * k] out; scores: device float32, same
  *   counters: device uint32 [sum count][2] out (expansions, scorings) or NULL
@@ -500,7 +502,7 @@ int lv_autotune_window(lv_multi *multi, int32_t sub, const float *Q, int64_t m,
 
 /*
  * Autotuner, performance part: for each visited-set size in {1024, 1280,
- * 1536, 2048, 4096, 8192} that fits, times `reps` rounds of three steps of the given
+ * 1536, 2048, 4096, 8192} that fits, times `reps` rounds of two steps of the given
  * requests in flight at once (on internal streams, the way consecutive steps
  * overlap in service) with the per-query launch, and returns the fastest in
  * best (these knobs never change results).  The persistent launch is not

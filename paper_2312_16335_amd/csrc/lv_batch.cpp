@@ -11,7 +11,9 @@
 // once when the caller issues them on different streams: later steps'
 // wavefronts then fill the compute units that the slowest queries of earlier
 // steps leave idle.  A set is reused kSets steps later, after the step that
-// last used it has finished (its stream is made to wait for that).
+// last used it has finished (its stream is made to wait for that); with a
+// number of streams that divides kSets that step ran on the same stream, so
+// the wait costs nothing.
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -26,7 +28,7 @@ struct lv_multi {
   int pw = 0;  // projected query width: d, or D with residual secondaries
 };
 
-constexpr int kSets = 3;
+constexpr int kSets = 4;
 
 struct lv_batch {
   lv_multi *multi = nullptr;
@@ -415,11 +417,11 @@ extern "C" int lv_autotune_knobs(lv_multi *multi, const lv_batch_caps *caps,
   if (nreq < 1 || nreq > caps->max_requests) LV_FAIL(LV_EINVAL, "bad request count");
   int64_t nout = 0;
   for (int i = 0; i < nreq; ++i) nout += (int64_t)reqs[i].count * reqs[i].k;
-  constexpr int kFlight = 3;
+  constexpr int kFlight = 2;  // steps in flight, as a server would run them (divides kSets)
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipStream_t st[kFlight] = {s, nullptr, nullptr};
-  uint32_t *xids[kFlight] = {ids, nullptr, nullptr};
-  float *xsc[kFlight] = {scores, nullptr, nullptr};
+  hipStream_t st[kFlight] = {s, nullptr};
+  uint32_t *xids[kFlight] = {ids, nullptr};
+  float *xsc[kFlight] = {scores, nullptr};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   auto cleanup = [&]() {
     for (int f = 1; f < kFlight; ++f) {
