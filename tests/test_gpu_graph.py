@@ -97,6 +97,26 @@ def test_build_equals_oracle(case):
         og.build(prim, order, entry, R, L, alphas, mb, stop_after=k)))
 
 
+def test_build_independent_of_visited_set_size():
+    """The construction searches forget ids differently with other visited-set
+    sizes (powers of two and other multiples of 256) but build the same graph."""
+    n, d, bits, R, L, mb, alphas = CASES[1]
+    prim, rec, order = _clustered(n, d, bits, seed=n + d)
+    entry = int(order[0])
+    recs = torch.from_numpy(rec).cuda()
+
+    def build(hs):
+        adj = torch.empty((n, R), dtype=torch.int32, device="cuda")
+        bp = lv.build_params(R, L, alphas, mb, 0, hash_slots=hs)
+        lv.lv_graph_build(recs, n, d, bits, order, entry, bp, adj)
+        torch.cuda.synchronize()
+        return adj.cpu().numpy()
+
+    ref = build(0)
+    for hs in (256, 1280, 2816):
+        assert np.array_equal(build(hs), ref), hs
+
+
 @pytest.mark.parametrize("stop_after", [1, 2, 5, 9, 12])
 def test_partial_builds_equal_oracle(stop_after):
     n, d, bits, R, L, mb = 700, 32, 8, 12, 24, 48

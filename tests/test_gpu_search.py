@@ -98,14 +98,19 @@ def test_search_parity_small(lv, small, k, L):
     assert np.array_equal(got_cnt[:, 1], want_cnt[:, 1])
 
 
-def test_small_visited_hash_changes_nothing(lv, small):
+@pytest.mark.parametrize("expand", [1, 3])
+def test_small_visited_hash_changes_nothing(lv, small, expand):
+    """Visited sets of any multiple of 256 slots (powers of two and others,
+    whose home slots come from the multiply-high range reduction) forget ids
+    differently but return the same ids, scores and expansions; only the
+    scorings of forgotten ids grow."""
     index, _ = gpu_index(lv, small)
-    ref = run_projected(lv, index, small, 10, 200, hash_slots=8192)
-    for hs in (256, 1024):
-        got = run_projected(lv, index, small, 10, 200, hash_slots=hs)
-        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
-        assert np.array_equal(got[2][:, 0], ref[2][:, 0])
-        assert np.all(got[2][:, 1] >= ref[2][:, 1])
+    ref = run_projected(lv, index, small, 10, 200, hash_slots=8192, expand=expand)
+    for hs in (256, 768, 1024, 1280, 1536, 2816):
+        got = run_projected(lv, index, small, 10, 200, hash_slots=hs, expand=expand)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), hs
+        assert np.array_equal(got[2][:, 0], ref[2][:, 0]), hs
+        assert np.all(got[2][:, 1] >= ref[2][:, 1]), hs
 
 
 def test_full_window_is_exact_knn(lv):
