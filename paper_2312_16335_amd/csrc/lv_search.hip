@@ -1266,11 +1266,11 @@ __global__ __launch_bounds__(64 * kTeamWaves) void team_kernel(PlainArgs a) {
 // run out; without one, workgroup b searches query b once (one workgroup per
 // query slot, scheduled by the hardware).  Requests are sorted by q_begin; a
 // query finds its request by binary search.
-// Waves per SIMD the register allocation aims at: 5 (at most 102 VGPRs)
-// for 8-bit records, 4 for 4-bit records, whose lanes hold twice as many
-// projected-query components.
+// Waves per SIMD the register allocation aims at: 5 (at most 102 VGPRs),
+// for 4-bit records too now that a lane's query components are held as
+// byte limbs (a few spills of per-query values, outside the search loops).
 template <int BITS, int V>
-constexpr int batched_waves() { return BITS == 8 ? 5 : 4; }
+constexpr int batched_waves() { return 5; }
 
 template <int BITS, int G, int V, bool MULTI>
 __global__ __launch_bounds__(64)
