@@ -17,10 +17,19 @@ struct GemmArgs {
   int32_t M, N, K;
   float alpha, beta;
   int32_t split = 0;  // 1: split-precision operands (hi + lo bfloat16), three passes
+  // optional second K segment: C = alpha * (op(A) op(B)^T + op(A2) op(B2)^T)
+  // + beta * C, A2 / B2 in the layouts of A / B, K2 columns (0: none)
+  const float *A2 = nullptr;
+  int64_t lda2 = 0;
+  const float *B2 = nullptr;
+  int64_t ldb2 = 0;
+  int32_t K2 = 0;
 };
 
 // C = alpha * op(A) op(B)^T + beta * C; a_kcont / b_kcont select whether
 // a(m, k) is A[m * lda + k] (true) or A[k * lda + m] (false), same for b(n, k).
+// A second K segment (K2 > 0) runs in the same launch on the tile kernels
+// and as a second product (beta = 1) on the others.
 // With a workspace (split_ws, split_floats floats), a product with few output
 // tiles and a long K is split over K: each part writes alpha times its
 // partial product to the workspace, and a second kernel adds the parts in a

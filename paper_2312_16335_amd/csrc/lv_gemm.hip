@@ -498,7 +498,9 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
-  const int nk_all = (g.K + TK - 1) / TK;
+  // steps of the first K segment, then of the second (A2, B2; none if K2 = 0)
+  const int nk1 = (g.K + TK - 1) / TK;
+  const int nk_all = nk1 + (g.K2 + TK - 1) / TK;
   const int t0 = (int)blockIdx.z * sps;
   const int nk = (t0 + sps < nk_all ? t0 + sps : nk_all) - t0;
   // two register sets: at step t the operands of step t + 1 (loaded during
@@ -506,8 +508,13 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int
   TileFrag<TBM, THREADS, AK> fa[2];
   TileFrag<TBN, THREADS, BKC> fb[2];
   auto load = [&](int t, int q) {
-    tload<TBM, THREADS, AK, FULL>(g.A, g.lda, g.M, g.K, m0, (t0 + t) * TK, fa[q], tid);
-    tload<TBN, THREADS, BKC, FULL>(g.B, g.ldb, g.N, g.K, n0, (t0 + t) * TK, fb[q], tid);
+    const int T = t0 + t;
+    const bool s2 = T >= nk1;  // uniform: the segment of this step
+    const int k = (s2 ? T - nk1 : T) * TK, kseg = s2 ? g.K2 : g.K;
+    tload<TBM, THREADS, AK, FULL>(s2 ? g.A2 : g.A, s2 ? g.lda2 : g.lda, g.M, kseg, m0, k, fa[q],
+                                  tid);
+    tload<TBN, THREADS, BKC, FULL>(s2 ? g.B2 : g.B, s2 ? g.ldb2 : g.ldb, g.N, kseg, n0, k, fb[q],
+                                   tid);
   };
   auto put = [&](int b, int q) {
     tstore<TBM, THREADS, AK, false>(fa[q], As + (b * NP) * SA, tid);
@@ -694,31 +701,54 @@ constexpr int kBigTileMinTiles = 128;
 int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *split_ws,
          size_t split_floats) {
   if (g.M <= 0 || g.N <= 0) return LV_OK;
+  const bool two = g.K2 > 0;  // a second K segment
+  // the two segments as separate products: C = alpha A B^T + beta C, then
+  // C += alpha A2 B2^T (the kernels other than the tile kernels)
+  auto two_launches = [&]() -> int {
+    GemmArgs g1 = g, g2 = g;
+    g1.A2 = g1.B2 = nullptr;
+    g1.K2 = 0;
+    g2.A = g.A2;
+    g2.lda = g.lda2;
+    g2.B = g.B2;
+    g2.ldb = g.ldb2;
+    g2.K = g.K2;
+    g2.beta = 1.f;
+    g2.A2 = g2.B2 = nullptr;
+    g2.K2 = 0;
+    int rc = gemm(g1, a_kcont, b_kcont, s, split_ws, split_floats);
+    return rc != LV_OK ? rc : gemm(g2, a_kcont, b_kcont, s, split_ws, split_floats);
+  };
   const dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
-  if (vec_ok(g.A, g.lda) && vec_ok(g.B, g.ldb)) {
+  if (vec_ok(g.A, g.lda) && vec_ok(g.B, g.ldb) &&
+      (!two || (vec_ok(g.A2, g.lda2) && vec_ok(g.B2, g.ldb2)))) {
     const bool split = g.split != 0;
+    const int tk_steps = (g.K + TK - 1) / TK + (g.K2 + TK - 1) / TK;  // tile kernel steps
+    const bool k_full = g.K % TK == 0 && g.K2 % TK == 0;
     const int big_tiles = ((g.M + kBigTile - 1) / kBigTile) * ((g.N + kBigTile - 1) / kBigTile);
     if (!split && big_tiles >= kBigTileMinTiles) {
       const dim3 gb((unsigned)((g.N + kBigTile - 1) / kBigTile),
                     (unsigned)((g.M + kBigTile - 1) / kBigTile), 1u);
-      const bool full = g.M % kBigTile == 0 && g.N % kBigTile == 0 && g.K % TK == 0;
-      TileLaunch<kBigTile, kBigTile, 2, 4> f{g, gb, (g.K + TK - 1) / TK > 0 ? (g.K + TK - 1) / TK : 1,
-                                          nullptr, s, full};
+      const bool full = g.M % kBigTile == 0 && g.N % kBigTile == 0 && k_full;
+      TileLaunch<kBigTile, kBigTile, 2, 4> f{g, gb, tk_steps > 0 ? tk_steps : 1, nullptr, s,
+                                          full};
       dispatch_layout(a_kcont, b_kcont, false, f);
       LV_CHECK_LAUNCH();
       return LV_OK;
     }
+    if (two && !split) return two_launches();  // the vector kernel has one segment
     // few output tiles and a long K: split K so that about 128 workgroups run
     const int tiles = (int)(grid.x * grid.y);
     const int step = split ? TK : VK;  // K per step of the kernel used
-    const int nk = (g.K + step - 1) / step;
+    const int nk = split ? tk_steps : (g.K + step - 1) / step;
+    const int ktot = g.K + g.K2;
     // (split precision: three products per step, so parts of at least 64 of K,
     // about 256 workgroups in all, and from K = 256 on)
     const int min_k = split ? 256 : 512, part_k = split ? 64 : 256, target = split ? 256 : 128;
     int parts = 1;
-    if (split_ws && tiles < 64 && g.K >= min_k) {
+    if (split_ws && tiles < 64 && ktot >= min_k) {
       parts = target / tiles;
-      if (parts > (g.K + part_k - 1) / part_k) parts = (g.K + part_k - 1) / part_k;
+      if (parts > (ktot + part_k - 1) / part_k) parts = (ktot + part_k - 1) / part_k;
       if (parts > kMaxSplit) parts = kMaxSplit;
       while (parts > 1 && (size_t)parts * g.M * g.N > split_floats) --parts;
     }
@@ -727,7 +757,7 @@ int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *sp
     float *part = parts > 1 ? split_ws : nullptr;
     const dim3 gz(grid.x, grid.y, (unsigned)parts);
     if (split) {  // both parts staged once per step
-      const bool full = g.M % BM == 0 && g.N % BN == 0 && g.K % TK == 0;
+      const bool full = g.M % BM == 0 && g.N % BN == 0 && k_full;
       TileLaunch<BM, BN, 2, 2> f{g, gz, sps, part, s, full};
       dispatch_layout(a_kcont, b_kcont, true, f);
     } else {
@@ -742,6 +772,7 @@ int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *sp
     LV_CHECK_LAUNCH();
     return LV_OK;
   }
+  if (two) return two_launches();
   ElemLaunch f{g, grid, s};
   dispatch_layout(a_kcont, b_kcont, g.split != 0, f);
   LV_CHECK_LAUNCH();

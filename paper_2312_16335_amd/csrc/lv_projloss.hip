@@ -16,8 +16,8 @@
 //   dB = -(2/P) (Rm^T G)^T Xb + 2 lam ((A K_Q A^T) B - A K_Q) K_X
 //
 // Every product is one launch of the bfloat16 matrix-core GEMM (float32
-// accumulation); Rm is formed as Qb Xb^T followed by a second product that
-// subtracts G H^T into the same buffer.  Rm is a small difference of two
+// accumulation); Rm is one product over K = D + d, [Qb | G] times
+// [Xb | -H]^T (H is kept negated for it).  Rm is a small difference of two
 // large products, and so are the trace part's M2 A - B K_X and
 // M1 B - A K_Q: the products that feed those differences (G, H, Qb Xb^T,
 // G H^T, B K_X, A K_Q, M1, M2, M2 A, M1 B) and the trace gradients' final
@@ -180,12 +180,19 @@ extern "C" int lv_projloss_fwd(const float *A, const float *B, const float *Qb, 
   lv::Ws w;
   lv::ws_floats(bq, bx, D, d, &w, static_cast<float *>(ws));
   using lv::GemmArgs;
-  // G = Qb A^T, H = Xb B^T
+  // G = Qb A^T, and H = Xb B^T kept negated (w.H = -H)
   LV_G(GemmArgs{Qb, D, A, D, w.G, d, bq, d, D, 1.f, 0.f, 1}, true, true, s);
-  LV_G(GemmArgs{Xb, D, B, D, w.H, d, bx, d, D, 1.f, 0.f, 1}, true, true, s);
-  // Rm = Qb Xb^T - G H^T
-  LV_G(GemmArgs{Qb, D, Xb, D, w.Rm, bx, bq, bx, D, 1.f, 0.f, 1}, true, true, s);
-  LV_G(GemmArgs{w.G, d, w.H, d, w.Rm, bx, bq, bx, d, -1.f, 1.f, 1}, true, true, s);
+  LV_G(GemmArgs{Xb, D, B, D, w.H, d, bx, d, D, -1.f, 0.f, 1}, true, true, s);
+  // Rm = Qb Xb^T - G H^T = Qb Xb^T + G (-H)^T: one product over K = D + d
+  {
+    GemmArgs r{Qb, D, Xb, D, w.Rm, bx, bq, bx, D, 1.f, 0.f, 1};
+    r.A2 = w.G;
+    r.lda2 = d;
+    r.B2 = w.H;
+    r.ldb2 = d;
+    r.K2 = d;
+    LV_G(r, true, true, s);
+  }
   const int with_trace = KQn != nullptr;
   hipLaunchKernelGGL(lv::dot_partials, dim3(lv::kRedBlocks), dim3(256), 0, s, w.Rm, w.Rm,
                      (int64_t)bq * bx, w.partial);
@@ -221,8 +228,8 @@ extern "C" int lv_projloss_bwd(const float *A, const float *B, const float *Qb, 
   lv::ws_floats(bq, bx, D, d, &w, static_cast<float *>(ws));
   using lv::GemmArgs;
   const float c = -2.f * grad_scale / (float)((double)bq * (double)bx);
-  // T = Rm H  (bq x d), S = Rm^T G (bx x d)
-  LV_G(GemmArgs{w.Rm, bx, w.H, d, w.T, d, bq, d, bx, 1.f, 0.f}, true, false, s);
+  // T = Rm H = -(Rm (-H))  (bq x d; w.H holds -H), S = Rm^T G (bx x d)
+  LV_G(GemmArgs{w.Rm, bx, w.H, d, w.T, d, bq, d, bx, -1.f, 0.f}, true, false, s);
   LV_G(GemmArgs{w.Rm, bx, w.G, d, w.S, d, bx, d, bq, 1.f, 0.f}, false, false, s);
   // dA = c T^T Qb, dB = c S^T Xb
   LV_G(GemmArgs{w.T, d, Qb, D, dA, D, d, D, bq, c, 0.f}, false, false, s);

@@ -231,6 +231,31 @@ def test_projloss_elementwise_against_float64(lv, block, case):
     assert abs(got[0] - (got[1] + lam * got[2])) <= 1e-6 * abs(got[0])
 
 
+# (bq, bx, D, d): partial tiles in every dimension and K of neither segment a
+# multiple of the K step (vector-load kernels); a row length not a multiple of
+# 4 (the element-wise kernel, the residual's two K segments as two products)
+@pytest.mark.parametrize("bq,bx,D,d", [(70, 196, 100, 12), (130, 260, 36, 20), (33, 70, 45, 13)])
+def test_projloss_ragged_shapes(lv, bq, bx, D, d):
+    """Loss and gradients of the pair part at shapes that are not multiples of
+    the tiles, against the float64 oracle within the bounds of `_bounds`."""
+    rng = np.random.default_rng(bq + bx + D + d)
+    Qb = rng.standard_normal((bq, D)).astype(np.float32)
+    Xb = rng.standard_normal((bx, D)).astype(np.float32)
+    A = (rng.standard_normal((d, D)) / np.sqrt(D)).astype(np.float32)
+    B = (A + 0.05 * rng.standard_normal((d, D)) / np.sqrt(D)).astype(np.float32)
+    got, dA, dB = _gpu_projloss(lv, A, B, Qb, Xb, None, None, 1.0)
+    gA, gB = opl.pair_grads(A, B, Qb, Xb)
+    pair = opl.pair_loss(A, B, Qb, Xb)
+    bA, bB = _bounds(A, B, Qb, Xb, None, None, 1.0)
+    err = {"pair": abs(got[1] - pair) / pair,
+           "dA/bound": float(np.max(np.abs(dA - gA) / bA)),
+           "dB/bound": float(np.max(np.abs(dB - gB) / bB))}
+    print((bq, bx, D, d), "errors vs float64:", err)
+    assert np.all(np.abs(dA - gA) <= bA), err
+    assert np.all(np.abs(dB - gB) <= bB), err
+    assert err["pair"] < 1e-4
+
+
 def test_autograd_function_matches_kernels(lv, block):
     from paper_2312_16335_amd.autograd import ProjLoss
 
