@@ -22,6 +22,8 @@
 // the product).  The relative error per operand falls from about 2^-9 to
 // about 2^-17, at three times the matrix-core work; products whose result
 // cancels (a difference of nearly equal products) need it.
+#include <algorithm>
+
 #include "lv_common.h"
 #include "lv_gemm.h"
 
@@ -34,6 +36,15 @@ typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 
 constexpr int BM = 128, BN = 128, BK = 32;
 constexpr int LDK = BK + 8;  // padded row (bf16 elements) against LDS bank conflicts
+
+// The second product of a pair run in one launch: workgroups with
+// blockIdx.z >= z1 compute it (z1 = gridDim.z: no second product).
+struct Second {
+  GemmArgs g;
+  int z1;
+  int sps;
+  float *part;
+};
 
 __device__ __forceinline__ uint16_t bf16_bits(float x) {
   uint32_t u = __float_as_uint(x);
@@ -305,15 +316,24 @@ __device__ __forceinline__ void vec_pass(const GemmArgs &g, uint16_t (*As)[BM * 
 
 // Split over K (grid z): part z covers steps [z * sps, (z + 1) * sps) and,
 // when `part` is set, writes alpha times its partial product to
-// part[z][M][N]; otherwise the whole K range goes to C.
+// part[z][M][N]; otherwise the whole K range goes to C.  Workgroups with
+// blockIdx.z >= sec.z1 compute the second product of a pair (its part
+// blockIdx.z - sec.z1); those past the output tiles of their product exit.
 template <bool AK, bool BKC, bool SPLIT>
-__global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g, int sps, float *part) {
+__global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g0, int sps0, float *part0,
+                                                       Second sec) {
   __shared__ __align__(16) uint16_t As[2][BM * VLD];
   __shared__ __align__(16) uint16_t Bs[2][BN * VLD];
+  const bool two = (int)blockIdx.z >= sec.z1;
+  const GemmArgs g = two ? sec.g : g0;
+  const int sps = two ? sec.sps : sps0;
+  float *const part = two ? sec.part : part0;
+  const int z = two ? (int)blockIdx.z - sec.z1 : (int)blockIdx.z;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  if (m0 >= g.M || n0 >= g.N) return;  // (whole workgroup)
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   f32x16 acc[2][2];
 #pragma unroll
@@ -324,7 +344,7 @@ __global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g, int sps, floa
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
   const int nk_all = (g.K + VK - 1) / VK;
-  const int t0 = (int)blockIdx.z * sps;
+  const int t0 = z * sps;
   const int nk = (t0 + sps < nk_all ? t0 + sps : nk_all) - t0;  // steps of this part
   vec_pass<AK, BKC, false, false>(g, As, Bs, m0, n0, wm, wn, t0, nk, tid, acc);
   if constexpr (SPLIT) {
@@ -332,7 +352,7 @@ __global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g, int sps, floa
     vec_pass<AK, BKC, true, false>(g, As, Bs, m0, n0, wm, wn, t0, nk, tid, acc);
   }
   const int r = lane & 31, kh = lane >> 5;
-  float *pz = part ? part + (int64_t)blockIdx.z * g.M * g.N : nullptr;
+  float *pz = part ? part + (int64_t)z * g.M * g.N : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -473,9 +493,10 @@ __device__ __forceinline__ void tstore(const TileFrag<ROWS, THREADS, KCONT> &f, 
   }
 }
 
+// (pairs of products and split over K as for gemm_vec_kernel)
 template <int TBM, int TBN, int WM, int WN, bool AK, bool BKC, bool SPLIT, bool FULL>
-__global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int sps,
-                                                                  float *part) {
+__global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g0, int sps0,
+                                                                  float *part0, Second sec) {
   constexpr int THREADS = 64 * WM * WN;
   constexpr int NP = SPLIT ? 2 : 1;   // operand parts staged per step
   constexpr int IM = TBM / WM / 32;   // MFMA tiles per wavefront along m
@@ -484,10 +505,16 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int
   __shared__ __align__(16) uint16_t tsm[2 * NP * (SA + SB)];
   uint16_t *As = tsm;                       // [2][NP][SA]
   uint16_t *Bs = tsm + 2 * NP * SA;         // [2][NP][SB]
+  const bool two = (int)blockIdx.z >= sec.z1;
+  const GemmArgs g = two ? sec.g : g0;
+  const int sps = two ? sec.sps : sps0;
+  float *const part = two ? sec.part : part0;
+  const int z = two ? (int)blockIdx.z - sec.z1 : (int)blockIdx.z;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
+  if (m0 >= g.M || n0 >= g.N) return;  // (whole workgroup)
   const int wm = (wave / WN) * (TBM / WM), wn = (wave % WN) * (TBN / WN);
   const int r = lane & 31, kh = lane >> 5;
   f32x16 acc[IM][JN];
@@ -498,10 +525,11 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
-  // steps of the first K segment, then of the second (A2, B2; none if K2 = 0)
+  // steps of the first K segment, then of the second (A2, B2; none if K2 = 0;
+  // split-precision instances only, the others take one segment)
   const int nk1 = (g.K + TK - 1) / TK;
-  const int nk_all = nk1 + (g.K2 + TK - 1) / TK;
-  const int t0 = (int)blockIdx.z * sps;
+  const int nk_all = nk1 + (SPLIT ? (g.K2 + TK - 1) / TK : 0);
+  const int t0 = z * sps;
   const int nk = (t0 + sps < nk_all ? t0 + sps : nk_all) - t0;
   // two register sets: at step t the operands of step t + 1 (loaded during
   // step t - 1) go to LDS while those of step t + 2 are in flight
@@ -509,12 +537,17 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int
   TileFrag<TBN, THREADS, BKC> fb[2];
   auto load = [&](int t, int q) {
     const int T = t0 + t;
-    const bool s2 = T >= nk1;  // uniform: the segment of this step
-    const int k = (s2 ? T - nk1 : T) * TK, kseg = s2 ? g.K2 : g.K;
-    tload<TBM, THREADS, AK, FULL>(s2 ? g.A2 : g.A, s2 ? g.lda2 : g.lda, g.M, kseg, m0, k, fa[q],
-                                  tid);
-    tload<TBN, THREADS, BKC, FULL>(s2 ? g.B2 : g.B, s2 ? g.ldb2 : g.ldb, g.N, kseg, n0, k, fb[q],
-                                   tid);
+    if constexpr (SPLIT) {
+      const bool s2 = T >= nk1;  // uniform: the segment of this step
+      const int k = (s2 ? T - nk1 : T) * TK, kseg = s2 ? g.K2 : g.K;
+      tload<TBM, THREADS, AK, FULL>(s2 ? g.A2 : g.A, s2 ? g.lda2 : g.lda, g.M, kseg, m0, k,
+                                    fa[q], tid);
+      tload<TBN, THREADS, BKC, FULL>(s2 ? g.B2 : g.B, s2 ? g.ldb2 : g.ldb, g.N, kseg, n0, k,
+                                     fb[q], tid);
+    } else {
+      tload<TBM, THREADS, AK, FULL>(g.A, g.lda, g.M, g.K, m0, T * TK, fa[q], tid);
+      tload<TBN, THREADS, BKC, FULL>(g.B, g.ldb, g.N, g.K, n0, T * TK, fb[q], tid);
+    }
   };
   auto put = [&](int b, int q) {
     tstore<TBM, THREADS, AK, false>(fa[q], As + (b * NP) * SA, tid);
@@ -586,7 +619,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int
     step(t + 1, 1);
   }
   if (t < nk) step(t, 0);
-  float *pz = part ? part + (int64_t)blockIdx.z * g.M * g.N : nullptr;
+  float *pz = part ? part + (int64_t)z * g.M * g.N : nullptr;
 #pragma unroll
   for (int i = 0; i < IM; ++i)
 #pragma unroll
@@ -608,9 +641,15 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g, int
     }
 }
 
-// C = sum over z of part[z] (in order z = 0, 1, ...) + beta * C.
-__global__ __launch_bounds__(256) void split_sum_kernel(const float *__restrict__ part, int nz,
-                                                        GemmArgs g) {
+// C = sum over z of part[z] (in order z = 0, 1, ...) + beta * C; grid row 1
+// does the same for a second product (part1, nz1, g1).
+__global__ __launch_bounds__(256) void split_sum_kernel(const float *__restrict__ part0, int nz0,
+                                                        GemmArgs g0, const float *part1, int nz1,
+                                                        GemmArgs g1) {
+  const bool two = blockIdx.y != 0;
+  const float *__restrict__ part = two ? part1 : part0;
+  const int nz = two ? nz1 : nz0;
+  const GemmArgs g = two ? g1 : g0;
   const int64_t mn = (int64_t)g.M * g.N;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < mn;
        i += (int64_t)gridDim.x * 256) {
@@ -629,9 +668,11 @@ struct VecLaunch {
   int sps;
   float *part;
   hipStream_t s;
+  Second sec;
   template <bool AK, bool BKC, bool SPLIT>
   void go() {
-    hipLaunchKernelGGL((gemm_vec_kernel<AK, BKC, SPLIT>), grid, dim3(256), 0, s, g, sps, part);
+    hipLaunchKernelGGL((gemm_vec_kernel<AK, BKC, SPLIT>), grid, dim3(256), 0, s, g, sps, part,
+                       sec);
   }
 };
 
@@ -643,6 +684,7 @@ struct TileLaunch {
   float *part;
   hipStream_t s;
   bool full;
+  Second sec;
   template <bool AK, bool BKC, bool SPLIT>
   void go() {
     // split precision runs on 128 x 128 tiles only (the large tile has no
@@ -650,10 +692,10 @@ struct TileLaunch {
     if constexpr (!SPLIT || TBM * TBN <= 128 * 128) {
       if (full)
         hipLaunchKernelGGL((gemm_tile_kernel<TBM, TBN, WM, WN, AK, BKC, SPLIT, true>), grid,
-                           dim3(64 * WM * WN), 0, s, g, sps, part);
+                           dim3(64 * WM * WN), 0, s, g, sps, part, sec);
       else
         hipLaunchKernelGGL((gemm_tile_kernel<TBM, TBN, WM, WN, AK, BKC, SPLIT, false>), grid,
-                           dim3(64 * WM * WN), 0, s, g, sps, part);
+                           dim3(64 * WM * WN), 0, s, g, sps, part, sec);
     }
   }
 };
@@ -698,6 +740,58 @@ size_t gemm_split_floats(int64_t M, int64_t N) { return (size_t)kMaxSplit * M * 
 constexpr int kBigTile = 256;
 constexpr int kBigTileMinTiles = 128;
 
+namespace {
+
+// How a product runs on the vector-load kernels (no big tile, one K segment
+// unless on the tile kernel): the tile grid and the split over K.
+struct Plan {
+  dim3 grid;  // x: tiles along N, y: along M
+  int parts, sps;
+  bool full;  // whole tiles and K steps (tile kernel)
+};
+
+Plan plan_small(const GemmArgs &g, size_t split_floats, bool have_ws) {
+  const bool split = g.split != 0;
+  Plan p;
+  p.grid = dim3((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
+  const int tk_steps = (g.K + TK - 1) / TK + (g.K2 + TK - 1) / TK;  // tile kernel steps
+  p.full = g.M % BM == 0 && g.N % BN == 0 && g.K % TK == 0 && g.K2 % TK == 0;
+  // few output tiles and a long K: split K so that about 128 workgroups run
+  const int tiles = (int)(p.grid.x * p.grid.y);
+  const int step = split ? TK : VK;  // K per step of the kernel used
+  const int nk = split ? tk_steps : (g.K + step - 1) / step;
+  const int ktot = g.K + g.K2;
+  // (split precision: three products per step, so parts of at least 64 of K,
+  // about 256 workgroups in all, and from K = 256 on)
+  const int min_k = split ? 256 : 512, part_k = split ? 64 : 256, target = split ? 256 : 128;
+  int parts = 1;
+  if (have_ws && tiles < 64 && ktot >= min_k) {
+    parts = target / tiles;
+    if (parts > (ktot + part_k - 1) / part_k) parts = (ktot + part_k - 1) / part_k;
+    if (parts > kMaxSplit) parts = kMaxSplit;
+    while (parts > 1 && (size_t)parts * g.M * g.N > split_floats) --parts;
+  }
+  p.sps = nk > 0 ? (nk + parts - 1) / parts : 1;  // steps per part
+  p.parts = nk > 0 ? (nk + p.sps - 1) / p.sps : 1;
+  return p;
+}
+
+bool vec_operands(const GemmArgs &g) {
+  return vec_ok(g.A, g.lda) && vec_ok(g.B, g.ldb) &&
+         (g.K2 <= 0 || (vec_ok(g.A2, g.lda2) && vec_ok(g.B2, g.ldb2)));
+}
+
+// The split sums of up to two products (n of them, part buffers and counts).
+void split_sums(int n, const float *p0, int nz0, const GemmArgs &g0, const float *p1, int nz1,
+                const GemmArgs &g1, hipStream_t s) {
+  const int64_t mn = std::max((int64_t)g0.M * g0.N, n > 1 ? (int64_t)g1.M * g1.N : 0);
+  const unsigned blocks = (unsigned)((mn + 255) / 256 < 2048 ? (mn + 255) / 256 : 2048);
+  hipLaunchKernelGGL(split_sum_kernel, dim3(blocks, (unsigned)n), dim3(256), 0, s, p0, nz0, g0,
+                     p1, nz1, g1);
+}
+
+}  // namespace
+
 int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *split_ws,
          size_t split_floats) {
   if (g.M <= 0 || g.N <= 0) return LV_OK;
@@ -720,9 +814,10 @@ int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *sp
     return rc != LV_OK ? rc : gemm(g2, a_kcont, b_kcont, s, split_ws, split_floats);
   };
   const dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
-  if (vec_ok(g.A, g.lda) && vec_ok(g.B, g.ldb) &&
-      (!two || (vec_ok(g.A2, g.lda2) && vec_ok(g.B2, g.ldb2)))) {
+  if (vec_operands(g)) {
     const bool split = g.split != 0;
+    // the second K segment runs in the split-precision tile kernel only
+    if (two && !split) return two_launches();
     const int tk_steps = (g.K + TK - 1) / TK + (g.K2 + TK - 1) / TK;  // tile kernel steps
     const bool k_full = g.K % TK == 0 && g.K2 % TK == 0;
     const int big_tiles = ((g.M + kBigTile - 1) / kBigTile) * ((g.N + kBigTile - 1) / kBigTile);
@@ -731,50 +826,70 @@ int gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, hipStream_t s, float *sp
                     (unsigned)((g.M + kBigTile - 1) / kBigTile), 1u);
       const bool full = g.M % kBigTile == 0 && g.N % kBigTile == 0 && k_full;
       TileLaunch<kBigTile, kBigTile, 2, 4> f{g, gb, tk_steps > 0 ? tk_steps : 1, nullptr, s,
-                                          full};
+                                          full, Second{g, 1, 0, nullptr}};
       dispatch_layout(a_kcont, b_kcont, false, f);
       LV_CHECK_LAUNCH();
       return LV_OK;
     }
-    if (two && !split) return two_launches();  // the vector kernel has one segment
-    // few output tiles and a long K: split K so that about 128 workgroups run
-    const int tiles = (int)(grid.x * grid.y);
-    const int step = split ? TK : VK;  // K per step of the kernel used
-    const int nk = split ? tk_steps : (g.K + step - 1) / step;
-    const int ktot = g.K + g.K2;
-    // (split precision: three products per step, so parts of at least 64 of K,
-    // about 256 workgroups in all, and from K = 256 on)
-    const int min_k = split ? 256 : 512, part_k = split ? 64 : 256, target = split ? 256 : 128;
-    int parts = 1;
-    if (split_ws && tiles < 64 && ktot >= min_k) {
-      parts = target / tiles;
-      if (parts > (ktot + part_k - 1) / part_k) parts = (ktot + part_k - 1) / part_k;
-      if (parts > kMaxSplit) parts = kMaxSplit;
-      while (parts > 1 && (size_t)parts * g.M * g.N > split_floats) --parts;
-    }
-    const int sps = nk > 0 ? (nk + parts - 1) / parts : 1;  // steps per part
-    parts = nk > 0 ? (nk + sps - 1) / sps : 1;
-    float *part = parts > 1 ? split_ws : nullptr;
-    const dim3 gz(grid.x, grid.y, (unsigned)parts);
+    const Plan p = plan_small(g, split_floats, split_ws != nullptr);
+    float *part = p.parts > 1 ? split_ws : nullptr;
+    const dim3 gz(p.grid.x, p.grid.y, (unsigned)p.parts);
+    const Second none{g, p.parts, 0, nullptr};
     if (split) {  // both parts staged once per step
-      const bool full = g.M % BM == 0 && g.N % BN == 0 && k_full;
-      TileLaunch<BM, BN, 2, 2> f{g, gz, sps, part, s, full};
+      TileLaunch<BM, BN, 2, 2> f{g, gz, p.sps, part, s, p.full, none};
       dispatch_layout(a_kcont, b_kcont, true, f);
     } else {
-      VecLaunch f{g, gz, sps, part, s};
+      VecLaunch f{g, gz, p.sps, part, s, none};
       dispatch_layout(a_kcont, b_kcont, false, f);
     }
-    if (part) {
-      const int64_t mn = (int64_t)g.M * g.N;
-      const unsigned blocks = (unsigned)((mn + 255) / 256 < 2048 ? (mn + 255) / 256 : 2048);
-      hipLaunchKernelGGL(split_sum_kernel, dim3(blocks), dim3(256), 0, s, part, parts, g);
-    }
+    if (part) split_sums(1, part, p.parts, g, nullptr, 0, g, s);
     LV_CHECK_LAUNCH();
     return LV_OK;
   }
   if (two) return two_launches();
   ElemLaunch f{g, grid, s};
   dispatch_layout(a_kcont, b_kcont, g.split != 0, f);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+
+int gemm_pair(const GemmArgs &g0, const GemmArgs &g1, bool a_kcont, bool b_kcont, hipStream_t s,
+              float *split_ws, size_t split_floats) {
+  // half of the workspace each (64-float aligned)
+  const size_t half = (split_floats / 2) & ~(size_t)63;
+  float *ws1 = split_ws ? split_ws + half : nullptr;
+  auto separate = [&]() -> int {
+    int rc = gemm(g0, a_kcont, b_kcont, s, split_ws, half);
+    return rc != LV_OK ? rc : gemm(g1, a_kcont, b_kcont, s, ws1, split_floats - half);
+  };
+  if (g0.M <= 0 || g0.N <= 0 || g1.M <= 0 || g1.N <= 0) return separate();
+  const bool split = g0.split != 0;
+  // one launch when both take the small-product path of the same kernel
+  const auto big = [](const GemmArgs &g) {
+    return ((g.M + kBigTile - 1) / kBigTile) * ((g.N + kBigTile - 1) / kBigTile) >=
+           kBigTileMinTiles;
+  };
+  if ((g1.split != 0) != split || !vec_operands(g0) || !vec_operands(g1) ||
+      (!split && (big(g0) || big(g1) || g0.K2 > 0 || g1.K2 > 0)))
+    return separate();
+  const Plan p0 = plan_small(g0, half, split_ws != nullptr);
+  const Plan p1 = plan_small(g1, split_floats - half, split_ws != nullptr);
+  float *part0 = p0.parts > 1 ? split_ws : nullptr;
+  float *part1 = p1.parts > 1 ? ws1 : nullptr;
+  const dim3 gz(std::max(p0.grid.x, p1.grid.x), std::max(p0.grid.y, p1.grid.y),
+                (unsigned)(p0.parts + p1.parts));
+  const Second sec{g1, p0.parts, p1.sps, part1};
+  if (split) {
+    TileLaunch<BM, BN, 2, 2> f{g0, gz, p0.sps, part0, s, p0.full && p1.full, sec};
+    dispatch_layout(a_kcont, b_kcont, true, f);
+  } else {
+    VecLaunch f{g0, gz, p0.sps, part0, s, sec};
+    dispatch_layout(a_kcont, b_kcont, false, f);
+  }
+  if (part0 && part1) split_sums(2, part0, p0.parts, g0, part1, p1.parts, g1, s);
+  else if (part0) split_sums(1, part0, p0.parts, g0, nullptr, 0, g0, s);
+  else if (part1) split_sums(1, part1, p1.parts, g1, nullptr, 0, g1, s);
   LV_CHECK_LAUNCH();
   return LV_OK;
 }

@@ -16,14 +16,18 @@
 //   dB = -(2/P) (Rm^T G)^T Xb + 2 lam ((A K_Q A^T) B - A K_Q) K_X
 //
 // Every product is one launch of the bfloat16 matrix-core GEMM (float32
-// accumulation); Rm is one product over K = D + d, [Qb | G] times
-// [Xb | -H]^T (H is kept negated for it).  Rm is a small difference of two
-// large products, and so are the trace part's M2 A - B K_X and
-// M1 B - A K_Q: the products that feed those differences (G, H, Qb Xb^T,
-// G H^T, B K_X, A K_Q, M1, M2, M2 A, M1 B) and the trace gradients' final
-// products take split-precision operands (hi + lo bfloat16, three matrix-core
-// passes), which brings the relative error of the gradients from about 1e-2
-// (plain bfloat16) to about 2e-4 at the refinement shape.  The pair-part
+// accumulation).  A difference of two products is one launch over two K
+// segments, with one factor kept negated in the workspace: Rm is
+// [Qb | G] [Xb | -H]^T (K = D + d), and the trace gradients, written with
+// U1 = B K_X and U2 = A K_Q as 2 lam (M2 U2 - U1 K_Q) and
+// 2 lam (M1 U1 - U2 K_X), are -2 lam [-M2 | U1] [U2 ; K_Q] (K = d + D) and
+// its mirror (M1 and M2 are both kept negated, which leaves <M1, M2>
+// unchanged).  Rm and the trace gradients are small differences of large
+// products: the products that feed them (G, H, Qb Xb^T, G H^T, B K_X, A K_Q,
+// M1, M2, and the trace gradients themselves) take split-precision operands
+// (hi + lo bfloat16, three matrix-core passes), which brings the relative
+// error of the gradients from about 1e-2 (plain bfloat16) to about 2e-4 at
+// the refinement shape.  The pair-part
 // products of the backward (Rm H, Rm^T G, and their products with Qb, Xb)
 // involve no cancellation and stay in plain bfloat16.  Sums of squares and inner products
 // use a fixed-order two-pass float64 reduction, so results are deterministic.
@@ -39,11 +43,21 @@ namespace {
 
 constexpr int kRedBlocks = 512;
 
-// partial[blockIdx.x] = sum over a grid-stride slice of a[i] * b[i] (float64)
-__global__ __launch_bounds__(256) void dot_partials(const float *__restrict__ a,
-                                                    const float *__restrict__ b, int64_t n,
-                                                    double *__restrict__ partial) {
+// Up to three inner products <a[j], b[j]> of n[j] floats, one per grid row.
+struct DotPairs {
+  const float *a[3];
+  const float *b[3];
+  int64_t n[3];
+};
+
+// partial[j * gridDim.x + blockIdx.x] = sum over a grid-stride slice of
+// a[j][i] * b[j][i] (float64), j = blockIdx.y
+__global__ __launch_bounds__(256) void dot_partials(DotPairs p, double *__restrict__ partial) {
   __shared__ double red[256];
+  const int j = blockIdx.y;
+  const float *__restrict__ a = p.a[j];
+  const float *__restrict__ b = p.b[j];
+  const int64_t n = p.n[j];
   double s = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     s += (double)a[i] * (double)b[i];
@@ -53,7 +67,7 @@ __global__ __launch_bounds__(256) void dot_partials(const float *__restrict__ a,
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = red[0];
 }
 
 // out[0] = total, out[1] = pair part, out[2] = trace part.  One workgroup of
@@ -81,13 +95,6 @@ __global__ __launch_bounds__(kRedBlocks) void finish_loss(const double *__restri
   out[2] = (float)tr;
 }
 
-__global__ __launch_bounds__(256) void sub_kernel(const float *__restrict__ a,
-                                                  const float *__restrict__ b, int64_t n,
-                                                  float *__restrict__ out) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    out[i] = a[i] - b[i];
-}
-
 __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p,
                                                    const float *__restrict__ g,
                                                    float *__restrict__ m, float *__restrict__ v,
@@ -106,7 +113,7 @@ __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p,
 
 // Workspace carve (floats, each region 64-float aligned).
 struct Ws {
-  float *G, *H, *Rm, *T, *S, *U1, *U2, *M1, *M2, *W;
+  float *G, *H, *Rm, *T, *S, *U1, *U2, *M1, *M2;
   float *SP;          // partial products of GEMMs split over K
   size_t sp_floats;
   double *partial;
@@ -131,10 +138,10 @@ size_t ws_floats(int64_t bq, int64_t bx, int64_t D, int64_t d, Ws *w, float *bas
   take(&t->U2, d * D);
   take(&t->M1, d * d);
   take(&t->M2, d * d);
-  take(&t->W, d * D);
   // the split products have at most max(b_q, b_x) x d or d x D outputs
+  // (pairs of them: twice that)
   const int64_t mn = std::max(std::max(bq, bx) * d, d * D);
-  t->sp_floats = gemm_split_floats(mn, 1);
+  t->sp_floats = 2 * gemm_split_floats(mn, 1);
   take(&t->SP, t->sp_floats);
   float *pp = nullptr;
   take(&pp, 2 * 3 * kRedBlocks);  // float64 partials
@@ -159,6 +166,13 @@ int check_args(const float *A, const float *B, const float *Qb, const float *Xb,
     if (rc_ != LV_OK) return rc_;                         \
   } while (0)
 
+// Two independent products of the same layouts in one launch.
+#define LV_G2(...)                                             \
+  do {                                                         \
+    int rc_ = ::lv::gemm_pair(__VA_ARGS__, w.SP, w.sp_floats); \
+    if (rc_ != LV_OK) return rc_;                              \
+  } while (0)
+
 }  // namespace
 }  // namespace lv
 
@@ -181,8 +195,8 @@ extern "C" int lv_projloss_fwd(const float *A, const float *B, const float *Qb, 
   lv::ws_floats(bq, bx, D, d, &w, static_cast<float *>(ws));
   using lv::GemmArgs;
   // G = Qb A^T, and H = Xb B^T kept negated (w.H = -H)
-  LV_G(GemmArgs{Qb, D, A, D, w.G, d, bq, d, D, 1.f, 0.f, 1}, true, true, s);
-  LV_G(GemmArgs{Xb, D, B, D, w.H, d, bx, d, D, -1.f, 0.f, 1}, true, true, s);
+  LV_G2(GemmArgs{Qb, D, A, D, w.G, d, bq, d, D, 1.f, 0.f, 1},
+        GemmArgs{Xb, D, B, D, w.H, d, bx, d, D, -1.f, 0.f, 1}, true, true, s);
   // Rm = Qb Xb^T - G H^T = Qb Xb^T + G (-H)^T: one product over K = D + d
   {
     GemmArgs r{Qb, D, Xb, D, w.Rm, bx, bq, bx, D, 1.f, 0.f, 1};
@@ -194,19 +208,18 @@ extern "C" int lv_projloss_fwd(const float *A, const float *B, const float *Qb, 
     LV_G(r, true, true, s);
   }
   const int with_trace = KQn != nullptr;
-  hipLaunchKernelGGL(lv::dot_partials, dim3(lv::kRedBlocks), dim3(256), 0, s, w.Rm, w.Rm,
-                     (int64_t)bq * bx, w.partial);
   if (with_trace) {
-    // U1 = B K_X, U2 = A K_Q (moments symmetric), M2 = U1 B^T, M1 = U2 A^T
-    LV_G(GemmArgs{B, D, KXn, D, w.U1, D, d, D, D, 1.f, 0.f, 1}, true, true, s);
-    LV_G(GemmArgs{A, D, KQn, D, w.U2, D, d, D, D, 1.f, 0.f, 1}, true, true, s);
-    LV_G(GemmArgs{w.U1, D, B, D, w.M2, d, d, d, D, 1.f, 0.f, 1}, true, true, s);
-    LV_G(GemmArgs{w.U2, D, A, D, w.M1, d, d, d, D, 1.f, 0.f, 1}, true, true, s);
-    hipLaunchKernelGGL(lv::dot_partials, dim3(lv::kRedBlocks), dim3(256), 0, s, w.M1, w.M2,
-                       (int64_t)d * d, w.partial + lv::kRedBlocks);
-    hipLaunchKernelGGL(lv::dot_partials, dim3(lv::kRedBlocks), dim3(256), 0, s, w.U2, w.U1,
-                       (int64_t)d * D, w.partial + 2 * lv::kRedBlocks);
+    // U1 = B K_X, U2 = A K_Q (moments symmetric); w.M2 = -U1 B^T, w.M1 = -U2 A^T
+    LV_G2(GemmArgs{B, D, KXn, D, w.U1, D, d, D, D, 1.f, 0.f, 1},
+          GemmArgs{A, D, KQn, D, w.U2, D, d, D, D, 1.f, 0.f, 1}, true, true, s);
+    LV_G2(GemmArgs{w.U1, D, B, D, w.M2, d, d, d, D, -1.f, 0.f, 1},
+          GemmArgs{w.U2, D, A, D, w.M1, d, d, d, D, -1.f, 0.f, 1}, true, true, s);
   }
+  // ||Rm||^2, then <M1, M2> and <U2, U1> (w.M1 and w.M2 both negated)
+  const lv::DotPairs dp{{w.Rm, w.M1, w.U2}, {w.Rm, w.M2, w.U1},
+                        {(int64_t)bq * bx, (int64_t)d * d, (int64_t)d * D}};
+  hipLaunchKernelGGL(lv::dot_partials, dim3(lv::kRedBlocks, with_trace ? 3u : 1u), dim3(256), 0,
+                     s, dp, w.partial);
   hipLaunchKernelGGL(lv::finish_loss, dim3(1), dim3(lv::kRedBlocks), 0, s, w.partial,
                      lv::kRedBlocks,
                      1.0 / ((double)bq * (double)bx), trace_const, lam, with_trace, loss);
@@ -232,20 +245,26 @@ extern "C" int lv_projloss_bwd(const float *A, const float *B, const float *Qb, 
   LV_G(GemmArgs{w.Rm, bx, w.H, d, w.T, d, bq, d, bx, -1.f, 0.f}, true, false, s);
   LV_G(GemmArgs{w.Rm, bx, w.G, d, w.S, d, bx, d, bq, 1.f, 0.f}, false, false, s);
   // dA = c T^T Qb, dB = c S^T Xb
-  LV_G(GemmArgs{w.T, d, Qb, D, dA, D, d, D, bq, c, 0.f}, false, false, s);
-  LV_G(GemmArgs{w.S, d, Xb, D, dB, D, d, D, bx, c, 0.f}, false, false, s);
+  LV_G2(GemmArgs{w.T, d, Qb, D, dA, D, d, D, bq, c, 0.f},
+        GemmArgs{w.S, d, Xb, D, dB, D, d, D, bx, c, 0.f}, false, false, s);
   if (KQn) {
     const float t = 2.f * lam * grad_scale;
-    const int64_t n = (int64_t)d * D;
-    const unsigned blocks = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
-    // dA += t (M2 A - U1) K_Q
-    LV_G(GemmArgs{w.M2, d, A, D, w.W, D, d, D, d, 1.f, 0.f, 1}, true, false, s);
-    hipLaunchKernelGGL(lv::sub_kernel, dim3(blocks), dim3(256), 0, s, w.W, w.U1, n, w.W);
-    LV_G(GemmArgs{w.W, D, KQn, D, dA, D, d, D, D, t, 1.f, 1}, true, true, s);
-    // dB += t (M1 B - U2) K_X
-    LV_G(GemmArgs{w.M1, d, B, D, w.W, D, d, D, d, 1.f, 0.f, 1}, true, false, s);
-    hipLaunchKernelGGL(lv::sub_kernel, dim3(blocks), dim3(256), 0, s, w.W, w.U2, n, w.W);
-    LV_G(GemmArgs{w.W, D, KXn, D, dB, D, d, D, D, t, 1.f, 1}, true, true, s);
+    // dA += t (M2 U2 - U1 K_Q) = -t ((-M2) U2 + U1 K_Q): K = d, then K = D
+    // (b(n, k) read as U2[k][n] and K_Q[k][n])
+    GemmArgs ga{w.M2, d, w.U2, D, dA, D, d, D, d, -t, 1.f, 1};
+    ga.A2 = w.U1;
+    ga.lda2 = D;
+    ga.B2 = KQn;
+    ga.ldb2 = D;
+    ga.K2 = D;
+    // dB += t (M1 U1 - U2 K_X) = -t ((-M1) U1 + U2 K_X)
+    GemmArgs gb{w.M1, d, w.U1, D, dB, D, d, D, d, -t, 1.f, 1};
+    gb.A2 = w.U2;
+    gb.lda2 = D;
+    gb.B2 = KXn;
+    gb.ldb2 = D;
+    gb.K2 = D;
+    LV_G2(ga, gb, true, false, s);
   }
   LV_CHECK_LAUNCH();
   return LV_OK;
