@@ -629,7 +629,15 @@ size_t lv_projloss_workspace_size(int32_t bq, int32_t bx, int32_t D, int32_t d);
  * K_Q/m, KXn = K_X/n (device float32 [D][D], symmetric; both NULL to drop
  * the trace part) with trace_const = tr(KQn KXn) supplied by the caller.
  * loss: device float32 [3] out = {total, pair part, trace part f}.
- * Leaves the intermediates lv_projloss_bwd needs in ws.
+ * Leaves the intermediates lv_projloss_bwd needs in ws (device buffer of
+ * lv_projloss_workspace_size bytes, 16-byte aligned, caller-owned).
+ * Stream-ordered on `stream`: independent products run on a second stream
+ * of the library's own (one per device, default priority), forked from
+ * `stream` and joined back to it with events before the call's last
+ * kernels, so the results are ready in `stream` order.  Calls from several
+ * host threads on one device share that second stream.  Errors: LV_EINVAL
+ * for bad sizes, NULL or unaligned pointers, a short workspace, or one of
+ * KQn / KXn NULL; LV_EDEVICE for a failed stream, event or launch.
  */
 int lv_projloss_fwd(const float *A, const float *B, const float *Qb, const float *Xb, int32_t bq,
                     int32_t bx, int32_t D, int32_t d, const float *KQn, const float *KXn,
@@ -640,7 +648,9 @@ int lv_projloss_fwd(const float *A, const float *B, const float *Qb, const float
  * Gradients of that loss times grad_scale (Eq. leanvec_gradients for the
  * trace part; the pair part by differentiating the squared residual):
  * dA, dB device float32 [d][D] out.  ws must hold the intermediates of the
- * preceding lv_projloss_fwd on the same arguments.
+ * preceding lv_projloss_fwd on the same arguments.  Streams and errors as
+ * for lv_projloss_fwd (the second stream is used with or without the trace
+ * part).
  */
 int lv_projloss_bwd(const float *A, const float *B, const float *Qb, const float *Xb, int32_t bq,
                     int32_t bx, int32_t D, int32_t d, const float *KQn, const float *KXn,

@@ -32,6 +32,7 @@
 // involve no cancellation and stay in plain bfloat16.  Sums of squares and inner products
 // use a fixed-order two-pass float64 reduction, so results are deterministic.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "lv_common.h"
@@ -50,17 +51,42 @@ struct DotPairs {
   int64_t n[3];
 };
 
+__device__ __forceinline__ double dot4(const float4 x, const float4 y) {
+  return (double)x.x * (double)y.x + (double)x.y * (double)y.y + (double)x.z * (double)y.z +
+         (double)x.w * (double)y.w;
+}
+
 // partial[j * gridDim.x + blockIdx.x] = sum over a grid-stride slice of
-// a[j][i] * b[j][i] (float64), j = blockIdx.y
+// a[j][i] * b[j][i] (float64), j = blockIdx.y.  Groups of four floats
+// (16-byte aligned arrays), four groups in flight per thread, the last
+// n % 4 elements by the first threads of block 0; a fixed order, so the
+// sums are deterministic.
 __global__ __launch_bounds__(256) void dot_partials(DotPairs p, double *__restrict__ partial) {
   __shared__ double red[256];
   const int j = blockIdx.y;
   const float *__restrict__ a = p.a[j];
   const float *__restrict__ b = p.b[j];
   const int64_t n = p.n[j];
+  const float4 *__restrict__ a4 = reinterpret_cast<const float4 *>(a);
+  const float4 *__restrict__ b4 = reinterpret_cast<const float4 *>(b);
+  const int64_t n4 = n >> 2, stride = (int64_t)gridDim.x * 256;
   double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    s += (double)a[i] * (double)b[i];
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * stride < n4; i += 4 * stride) {
+    float4 x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = a4[i + u * stride];
+      y[u] = b4[i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += dot4(x[u], y[u]);
+  }
+  for (; i < n4; i += stride) s += dot4(a4[i], b4[i]);
+  if (blockIdx.x == 0 && (int64_t)threadIdx.x < n - 4 * n4) {
+    const int64_t t = 4 * n4 + threadIdx.x;
+    s += (double)a[t] * (double)b[t];
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -115,6 +141,7 @@ __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p,
 struct Ws {
   float *G, *H, *Rm, *T, *S, *U1, *U2, *M1, *M2;
   float *SP;          // partial products of GEMMs split over K
+  float *SP2;         // the same for the products on the side stream
   size_t sp_floats;
   double *partial;
 };
@@ -143,6 +170,7 @@ size_t ws_floats(int64_t bq, int64_t bx, int64_t D, int64_t d, Ws *w, float *bas
   const int64_t mn = std::max(std::max(bq, bx) * d, d * D);
   t->sp_floats = 2 * gemm_split_floats(mn, 1);
   take(&t->SP, t->sp_floats);
+  take(&t->SP2, t->sp_floats);
   float *pp = nullptr;
   take(&pp, 2 * 3 * kRedBlocks);  // float64 partials
   if (w) w->partial = reinterpret_cast<double *>(pp);
@@ -153,8 +181,45 @@ int check_args(const float *A, const float *B, const float *Qb, const float *Xb,
                int32_t bx, int32_t D, int32_t d, void *ws, size_t ws_bytes) {
   if (bq < 1 || bx < 1 || D < 1 || d < 1 || d > D) LV_FAIL(LV_EINVAL, "bad sizes");
   if (!A || !B || !Qb || !Xb || !ws) LV_FAIL(LV_EINVAL, "NULL pointer");
+  if (reinterpret_cast<uintptr_t>(ws) & 15u) LV_FAIL(LV_EINVAL, "workspace not 16-byte aligned");
   const size_t need = ws_floats(bq, bx, D, d, nullptr, nullptr) * sizeof(float);
   if (ws_bytes < need) LV_FAIL(LV_EINVAL, "workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+  return LV_OK;
+}
+
+// A second stream per device for the loss's independent chains of
+// products, and the events that fork work onto it from the caller's stream
+// and join it back.  Each record and its wait are made under the lock, so
+// that calls from several host threads cannot mix up their events; work of
+// such calls on one device is serialised on the side stream.
+constexpr int kMaxDevices = 64;
+struct Side {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_side_mu;
+Side g_side[kMaxDevices];
+
+int side_stream(Side **out) {
+  int dev = 0;
+  LV_CHECK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) LV_FAIL(LV_EDEVICE, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  Side &sd = g_side[dev];
+  if (!sd.s) {
+    LV_CHECK_HIP(hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming));
+    LV_CHECK_HIP(hipEventCreateWithFlags(&sd.join, hipEventDisableTiming));
+    LV_CHECK_HIP(hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking));
+  }
+  *out = &sd;
+  return LV_OK;
+}
+
+// `to` waits for the work queued on `from` so far (event e).
+int stream_wait(hipEvent_t e, hipStream_t from, hipStream_t to) {
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  LV_CHECK_HIP(hipEventRecord(e, from));
+  LV_CHECK_HIP(hipStreamWaitEvent(to, e, 0));
   return LV_OK;
 }
 
@@ -171,6 +236,24 @@ int check_args(const float *A, const float *B, const float *Qb, const float *Xb,
   do {                                                         \
     int rc_ = ::lv::gemm_pair(__VA_ARGS__, w.SP, w.sp_floats); \
     if (rc_ != LV_OK) return rc_;                              \
+  } while (0)
+
+// The same on the side stream's split workspace.
+#define LV_G_SIDE(...)                                     \
+  do {                                                     \
+    int rc_ = ::lv::gemm(__VA_ARGS__, w.SP2, w.sp_floats); \
+    if (rc_ != LV_OK) return rc_;                          \
+  } while (0)
+#define LV_G2_SIDE(...)                                         \
+  do {                                                          \
+    int rc_ = ::lv::gemm_pair(__VA_ARGS__, w.SP2, w.sp_floats); \
+    if (rc_ != LV_OK) return rc_;                               \
+  } while (0)
+
+#define LV_TRY(expr)              \
+  do {                            \
+    int rc_ = (expr);             \
+    if (rc_ != LV_OK) return rc_; \
   } while (0)
 
 }  // namespace
@@ -194,6 +277,18 @@ extern "C" int lv_projloss_fwd(const float *A, const float *B, const float *Qb, 
   lv::Ws w;
   lv::ws_floats(bq, bx, D, d, &w, static_cast<float *>(ws));
   using lv::GemmArgs;
+  const int with_trace = KQn != nullptr;
+  lv::Side *side = nullptr;
+  if (with_trace) {
+    // on the side stream: U1 = B K_X, U2 = A K_Q (moments symmetric);
+    // w.M2 = -U1 B^T, w.M1 = -U2 A^T
+    LV_TRY(lv::side_stream(&side));
+    LV_TRY(lv::stream_wait(side->fork, s, side->s));
+    LV_G2_SIDE(GemmArgs{B, D, KXn, D, w.U1, D, d, D, D, 1.f, 0.f, 1},
+               GemmArgs{A, D, KQn, D, w.U2, D, d, D, D, 1.f, 0.f, 1}, true, true, side->s);
+    LV_G2_SIDE(GemmArgs{w.U1, D, B, D, w.M2, d, d, d, D, -1.f, 0.f, 1},
+               GemmArgs{w.U2, D, A, D, w.M1, d, d, d, D, -1.f, 0.f, 1}, true, true, side->s);
+  }
   // G = Qb A^T, and H = Xb B^T kept negated (w.H = -H)
   LV_G2(GemmArgs{Qb, D, A, D, w.G, d, bq, d, D, 1.f, 0.f, 1},
         GemmArgs{Xb, D, B, D, w.H, d, bx, d, D, -1.f, 0.f, 1}, true, true, s);
@@ -207,14 +302,7 @@ extern "C" int lv_projloss_fwd(const float *A, const float *B, const float *Qb, 
     r.K2 = d;
     LV_G(r, true, true, s);
   }
-  const int with_trace = KQn != nullptr;
-  if (with_trace) {
-    // U1 = B K_X, U2 = A K_Q (moments symmetric); w.M2 = -U1 B^T, w.M1 = -U2 A^T
-    LV_G2(GemmArgs{B, D, KXn, D, w.U1, D, d, D, D, 1.f, 0.f, 1},
-          GemmArgs{A, D, KQn, D, w.U2, D, d, D, D, 1.f, 0.f, 1}, true, true, s);
-    LV_G2(GemmArgs{w.U1, D, B, D, w.M2, d, d, d, D, -1.f, 0.f, 1},
-          GemmArgs{w.U2, D, A, D, w.M1, d, d, d, D, -1.f, 0.f, 1}, true, true, s);
-  }
+  if (side) LV_TRY(lv::stream_wait(side->join, side->s, s));
   // ||Rm||^2, then <M1, M2> and <U2, U1> (w.M1 and w.M2 both negated)
   const lv::DotPairs dp{{w.Rm, w.M1, w.U2}, {w.Rm, w.M2, w.U1},
                         {(int64_t)bq * bx, (int64_t)d * d, (int64_t)d * D}};
@@ -241,31 +329,37 @@ extern "C" int lv_projloss_bwd(const float *A, const float *B, const float *Qb, 
   lv::ws_floats(bq, bx, D, d, &w, static_cast<float *>(ws));
   using lv::GemmArgs;
   const float c = -2.f * grad_scale / (float)((double)bq * (double)bx);
-  // T = Rm H = -(Rm (-H))  (bq x d; w.H holds -H), S = Rm^T G (bx x d)
-  LV_G(GemmArgs{w.Rm, bx, w.H, d, w.T, d, bq, d, bx, -1.f, 0.f}, true, false, s);
-  LV_G(GemmArgs{w.Rm, bx, w.G, d, w.S, d, bx, d, bq, 1.f, 0.f}, false, false, s);
-  // dA = c T^T Qb, dB = c S^T Xb
-  LV_G2(GemmArgs{w.T, d, Qb, D, dA, D, d, D, bq, c, 0.f},
-        GemmArgs{w.S, d, Xb, D, dB, D, d, D, bx, c, 0.f}, false, false, s);
-  if (KQn) {
+  lv::Side *side = nullptr;
+  LV_TRY(lv::side_stream(&side));
+  LV_TRY(lv::stream_wait(side->fork, s, side->s));
+  if (KQn) {  // on the side stream, first: the trace part of dA and dB
     const float t = 2.f * lam * grad_scale;
-    // dA += t (M2 U2 - U1 K_Q) = -t ((-M2) U2 + U1 K_Q): K = d, then K = D
+    // dA = t (M2 U2 - U1 K_Q) = -t ((-M2) U2 + U1 K_Q): K = d, then K = D
     // (b(n, k) read as U2[k][n] and K_Q[k][n])
-    GemmArgs ga{w.M2, d, w.U2, D, dA, D, d, D, d, -t, 1.f, 1};
+    GemmArgs ga{w.M2, d, w.U2, D, dA, D, d, D, d, -t, 0.f, 1};
     ga.A2 = w.U1;
     ga.lda2 = D;
     ga.B2 = KQn;
     ga.ldb2 = D;
     ga.K2 = D;
-    // dB += t (M1 U1 - U2 K_X) = -t ((-M1) U1 + U2 K_X)
-    GemmArgs gb{w.M1, d, w.U1, D, dB, D, d, D, d, -t, 1.f, 1};
+    // dB = t (M1 U1 - U2 K_X) = -t ((-M1) U1 + U2 K_X)
+    GemmArgs gb{w.M1, d, w.U1, D, dB, D, d, D, d, -t, 0.f, 1};
     gb.A2 = w.U2;
     gb.lda2 = D;
     gb.B2 = KXn;
     gb.ldb2 = D;
     gb.K2 = D;
-    LV_G2(ga, gb, true, false, s);
+    LV_G2_SIDE(ga, gb, true, false, side->s);
   }
+  // S = Rm^T G (bx x d) on the side stream, T = Rm H = -(Rm (-H)) (bq x d;
+  // w.H holds -H) on the caller's
+  LV_G_SIDE(GemmArgs{w.Rm, bx, w.G, d, w.S, d, bx, d, bq, 1.f, 0.f}, false, false, side->s);
+  LV_G(GemmArgs{w.Rm, bx, w.H, d, w.T, d, bq, d, bx, -1.f, 0.f}, true, false, s);
+  LV_TRY(lv::stream_wait(side->join, side->s, s));
+  // dA (+)= c T^T Qb, dB (+)= c S^T Xb (added to the trace part if any)
+  const float beta = KQn ? 1.f : 0.f;
+  LV_G2(GemmArgs{w.T, d, Qb, D, dA, D, d, D, bq, c, beta},
+        GemmArgs{w.S, d, Xb, D, dB, D, d, D, bx, c, beta}, false, false, s);
   LV_CHECK_LAUNCH();
   return LV_OK;
 }

@@ -256,6 +256,40 @@ def test_projloss_ragged_shapes(lv, bq, bx, D, d):
     assert err["pair"] < 1e-4
 
 
+def test_projloss_on_a_caller_stream_is_bit_identical(lv, block):
+    """The loss forks its independent products onto a second stream of its
+    own and joins it back: on a stream of the caller's, with a long kernel
+    queued before it that rewrites the inputs, the results must equal those
+    on the default stream bit for bit (a missing wait would read the old
+    inputs or a half-computed intermediate)."""
+    A, B, Qb, Xb, KQ, KX = block
+    d, D = A.shape
+    tc = float(np.trace(KQ @ KX))
+    ref = _gpu_projloss(lv, A, B, Qb, Xb, KQ, KX, 1.0)
+    ws = torch.empty(lv.lv_projloss_workspace_size(len(Qb), len(Xb), D, d), dtype=torch.uint8,
+                     device=DEV)
+    loss = torch.empty(3, device=DEV)
+    dA, dB = torch.empty((d, D), device=DEV), torch.empty((d, D), device=DEV)
+    At, Bt, Qt, Xt, KQt, KXt = (t(v) for v in (A, B, Qb, Xb, KQ, KX))
+    Az, Bz = torch.zeros_like(At), torch.zeros_like(Bt)
+    big = torch.randn((4096, 4096), device=DEV)
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        for _ in range(3):  # keep the stream busy before the inputs are written
+            big = big @ big
+            big = big / big.norm()
+        Az.copy_(At)
+        Bz.copy_(Bt)
+        lv.lv_projloss_fwd(Az, Bz, Qt, Xt, loss, ws, KQt, KXt, tc, 1.0)
+        lv.lv_projloss_bwd(Az, Bz, Qt, Xt, dA, dB, ws, KQt, KXt, 1.0, 1.0)
+    st.synchronize()
+    got = (loss.cpu().numpy().astype(np.float64), dA.cpu().numpy().astype(np.float64),
+           dB.cpu().numpy().astype(np.float64))
+    for g, r in zip(got, ref):
+        assert np.array_equal(g, r)
+
+
 def test_autograd_function_matches_kernels(lv, block):
     from paper_2312_16335_amd.autograd import ProjLoss
 
