@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ood", action="store_true",
                     help="skip the cross-modal workload's sub-record (ood-1m-512)")
+    ap.add_argument("--no-mfma", action="store_true",
+                    help="skip the matrix-core kernels' sub-record (projections, refinement "
+                         "step, GEMM; the same figures as --mfma)")
     ap.add_argument("--sec", choices=("f16", "lvq8", "resid", "level2"), default="f16",
                     help="secondary vectors: float16 (the benchmark configuration), LVQ-8, "
                          "float16 residual coordinates only (D - d per vector), or the 8-bit "
@@ -1181,6 +1184,13 @@ def main():
         index.close()
         torch.cuda.empty_cache()
         ood = ood_report(lv, torch, args)
+    mfma = None
+    if (not args.no_mfma and wl.name == "id-1m-768" and not args.n and args.sec == "f16"
+            and not args.bits):
+        # the matrix-core kernels (database and query projections, one refinement
+        # step of the differentiable projection, a large GEMM) as a sub-record
+        torch.cuda.empty_cache()
+        mfma = mfma_report(lv, torch)
 
     out = {
         "metric": ("QPS at 10-recall@10=0.90 (1M x 768, d=160), batched vs plain; HBM GB/s"
@@ -1256,6 +1266,7 @@ def main():
         "traversal_compare": variant,
         "small_batches": small_batches,
         "ood": ood,
+        "mfma": mfma,
     }
     print(json.dumps(out))
 
