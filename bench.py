@@ -552,7 +552,8 @@ def mfma_report(lv, torch, reps=10):
     """Matrix-core kernels on synthetic operands of the workloads' shapes: the
     database projection (1M x 768 -> 160) and the query projection (10,000
     queries), one refinement step (forward + backward, b_q = 1024, b_x = 4096,
-    D = 768, d = 128, with the trace term) and one 8192^3 GEMM.  Flops are the
+    D = 768, d = 128, with the trace term) and one 8192^3 GEMM (float32
+    operands rounded when staged, and bfloat16 operands in memory).  Flops are the
     products' own (2 M N K each); bytes are the projections' operands and outputs."""
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev)
@@ -651,6 +652,12 @@ def mfma_report(lv, torch, reps=10):
     Gc = torch.empty((n, n), device=dev)
     ms = timed(lambda: lv.lv_gemm(Ga, Gb, Gc, n, n, n))
     out["gemm_8192"] = entry(ms, 2.0 * n ** 3)
+    # the same product with the operands held as bfloat16 (converted once,
+    # outside the timed region): half the bytes staged per flop
+    Ha, Hb = Ga.to(torch.bfloat16), Gb.to(torch.bfloat16)
+    del Ga, Gb
+    ms = timed(lambda: lv.lv_gemm_bf16(Ha, Hb, Gc, n, n, n))
+    out["gemm_8192_bf16_operands"] = entry(ms, 2.0 * n ** 3)
     return out
 
 

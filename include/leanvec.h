@@ -614,6 +614,22 @@ int lv_gemm_split(const float *A, int32_t a_kcont, int64_t lda, const float *B,
                   int32_t K, float alpha, float beta, void *workspace, size_t workspace_bytes,
                   void *stream);
 
+/*
+ * The same matrix-core product (the projections' arithmetic: bfloat16
+ * operands, float32 accumulation) for operands already held as bfloat16,
+ * as a caller converts them once for many products:
+ *   C[m][n] = alpha * sum_k A[m][k] B[n][k] + beta * C[m][n]
+ * A: device bfloat16 bits [M][lda], B: device bfloat16 bits [N][ldb] (both
+ * k-contiguous rows), C: device float32 [M][ldc]; beta = 0 does not read C.
+ * Runs on 256 x 256 output tiles (meant for large products; no split over
+ * K, no workspace).  Errors: LV_EINVAL for negative sizes, NULL pointers,
+ * leading dimensions below K (A, B) or N (C), and rows of A or B that are
+ * not 16-byte aligned (pointers aligned, lda and ldb multiples of 8).
+ */
+int lv_gemm_bf16(const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, float *C,
+                 int64_t ldc, int32_t M, int32_t N, int32_t K, float alpha, float beta,
+                 void *stream);
+
 /* Workspace bytes with which lv_gemm may split an M x N product the most. */
 size_t lv_gemm_workspace_size(int32_t M, int32_t N);
 

@@ -122,6 +122,8 @@ _SIGS = {
     "lv_gemm_split": (_c_i32, [_vp, _c_i32, _c_i64, _vp, _c_i32, _c_i64, _vp, _c_i64, _c_i32,
                                _c_i32, _c_i32, ctypes.c_float, ctypes.c_float, _vp,
                                ctypes.c_size_t, _vp]),
+    "lv_gemm_bf16": (_c_i32, [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_i32, _c_i32, _c_i32,
+                              ctypes.c_float, ctypes.c_float, _vp]),
     "lv_gemm_workspace_size": (ctypes.c_size_t, [_c_i32, _c_i32]),
     "lv_projloss_workspace_size": (ctypes.c_size_t, [_c_i32, _c_i32, _c_i32, _c_i32]),
     "lv_projloss_fwd": (_c_i32, [_vp, _vp, _vp, _vp, _c_i32, _c_i32, _c_i32, _c_i32, _vp, _vp,
@@ -692,6 +694,25 @@ def lv_gemm(A, B, C, M, N, K, a_kcont=True, b_kcont=True, lda=None, ldb=None, ld
     _check(fn(_dev(A, torch.float32), int(a_kcont), lda, _dev(B, torch.float32), int(b_kcont),
               ldb, _dev(C, torch.float32), ldc, M, N, K, alpha, beta, ws, ws_bytes,
               _stream(stream)))
+
+
+def lv_gemm_bf16(A, B, C, M, N, K, lda=None, ldb=None, ldc=None, alpha=1.0, beta=0.0,
+                 stream=None):
+    """C = alpha A B^T + beta C with A [M][lda], B [N][ldb] bfloat16 (k-contiguous
+    rows; torch.bfloat16 or their int16 bits) and C float32 (lv_gemm_bf16)."""
+    import torch
+
+    lda = lda if lda is not None else K
+    ldb = ldb if ldb is not None else K
+    ldc = ldc if ldc is not None else N
+    for t, what in ((A, "A"), (B, "B")):
+        if t.dtype not in (torch.bfloat16, torch.int16):
+            raise TypeError(f"{what} must hold bfloat16 (or its int16 bits), got {t.dtype}")
+    _need(A, (M - 1) * lda + K if M > 0 else 0, "A")
+    _need(B, (N - 1) * ldb + K if N > 0 else 0, "B")
+    _need(C, (M - 1) * ldc + N if M > 0 else 0, "C")
+    _check(load().lv_gemm_bf16(_dev(A), lda, _dev(B), ldb, _dev(C, torch.float32), ldc, M, N, K,
+                               alpha, beta, _stream(stream)))
 
 
 def lv_gemm_workspace_size(M, N) -> int:

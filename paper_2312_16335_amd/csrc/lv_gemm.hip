@@ -23,6 +23,7 @@
 // about 2^-17, at three times the matrix-core work; products whose result
 // cancels (a difference of nearly equal products) need it.
 #include <algorithm>
+#include <type_traits>
 
 #include "lv_common.h"
 #include "lv_gemm.h"
@@ -399,6 +400,48 @@ struct TileFrag {
   float4 v[kPer];
 };
 
+// bfloat16 operands in memory (k-contiguous): 16-byte pieces of 8 k per
+// thread, unit u = row u / 4, k 8 (u % 4) (the float32 path's units).
+template <int ROWS, int THREADS>
+struct TileFrag16 {
+  static constexpr int kPer = ROWS * TK / 8 / THREADS;
+  u32x4 v[kPer];
+};
+
+template <int ROWS, int THREADS, bool FULL>
+__device__ __forceinline__ void tload16(const uint16_t *__restrict__ X, int64_t ld, int rows,
+                                        int kdim, int r0, int k0, TileFrag16<ROWS, THREADS> &f,
+                                        int tid) {
+#pragma unroll
+  for (int j = 0; j < TileFrag16<ROWS, THREADS>::kPer; ++j) {
+    const int u = tid + THREADS * j;
+    const int gr = r0 + (u >> 2), gk = k0 + 8 * (u & 3);
+    if (FULL || (gr < rows && gk + 7 < kdim)) {
+      f.v[j] = *reinterpret_cast<const u32x4 *>(X + (int64_t)gr * ld + gk);
+    } else {  // edge: element by element, zeros past the matrix
+      uint32_t w[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t lo = gr < rows && gk + 2 * e < kdim ? X[(int64_t)gr * ld + gk + 2 * e] : 0u;
+        const uint32_t hi =
+            gr < rows && gk + 2 * e + 1 < kdim ? X[(int64_t)gr * ld + gk + 2 * e + 1] : 0u;
+        w[e] = lo | (hi << 16);
+      }
+      f.v[j] = u32x4{w[0], w[1], w[2], w[3]};
+    }
+  }
+}
+
+template <int ROWS, int THREADS>
+__device__ __forceinline__ void tstore16(const TileFrag16<ROWS, THREADS> &f, uint16_t *S,
+                                         int tid) {
+#pragma unroll
+  for (int j = 0; j < TileFrag16<ROWS, THREADS>::kPer; ++j) {
+    const int u = tid + THREADS * j;
+    *reinterpret_cast<u32x4 *>(S + tswz(u >> 2, u & 3)) = f.v[j];
+  }
+}
+
 // Global -> registers.  k-contiguous: unit u (row u / 4, k 8 (u % 4) ..), two
 // pieces per unit, so four consecutive threads read one row's 128 bytes.
 // m-contiguous: unit u (k rows 2 kp and 2 kp + 1, m 4 mq ..), two pieces.
@@ -494,9 +537,12 @@ __device__ __forceinline__ void tstore(const TileFrag<ROWS, THREADS, KCONT> &f, 
 }
 
 // (pairs of products and split over K as for gemm_vec_kernel)
-template <int TBM, int TBN, int WM, int WN, bool AK, bool BKC, bool SPLIT, bool FULL>
+// BF: A and B hold bfloat16 bits (k-contiguous, no split precision)
+template <int TBM, int TBN, int WM, int WN, bool AK, bool BKC, bool SPLIT, bool FULL,
+          bool BF = false>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g0, int sps0,
                                                                   float *part0, Second sec) {
+  static_assert(!BF || (AK && BKC && !SPLIT), "bfloat16 operands: k-contiguous, one part");
   constexpr int THREADS = 64 * WM * WN;
   constexpr int NP = SPLIT ? 2 : 1;   // operand parts staged per step
   constexpr int IM = TBM / WM / 32;   // MFMA tiles per wavefront along m
@@ -533,11 +579,18 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g0, in
   const int nk = (t0 + sps < nk_all ? t0 + sps : nk_all) - t0;
   // two register sets: at step t the operands of step t + 1 (loaded during
   // step t - 1) go to LDS while those of step t + 2 are in flight
-  TileFrag<TBM, THREADS, AK> fa[2];
-  TileFrag<TBN, THREADS, BKC> fb[2];
+  using FragA = std::conditional_t<BF, TileFrag16<TBM, THREADS>, TileFrag<TBM, THREADS, AK>>;
+  using FragB = std::conditional_t<BF, TileFrag16<TBN, THREADS>, TileFrag<TBN, THREADS, BKC>>;
+  FragA fa[2];
+  FragB fb[2];
   auto load = [&](int t, int q) {
     const int T = t0 + t;
-    if constexpr (SPLIT) {
+    if constexpr (BF) {
+      tload16<TBM, THREADS, FULL>(reinterpret_cast<const uint16_t *>(g.A), g.lda, g.M, g.K, m0,
+                                  T * TK, fa[q], tid);
+      tload16<TBN, THREADS, FULL>(reinterpret_cast<const uint16_t *>(g.B), g.ldb, g.N, g.K, n0,
+                                  T * TK, fb[q], tid);
+    } else if constexpr (SPLIT) {
       const bool s2 = T >= nk1;  // uniform: the segment of this step
       const int k = (s2 ? T - nk1 : T) * TK, kseg = s2 ? g.K2 : g.K;
       tload<TBM, THREADS, AK, FULL>(s2 ? g.A2 : g.A, s2 ? g.lda2 : g.lda, g.M, kseg, m0, k,
@@ -550,11 +603,16 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_tile_kernel(GemmArgs g0, in
     }
   };
   auto put = [&](int b, int q) {
-    tstore<TBM, THREADS, AK, false>(fa[q], As + (b * NP) * SA, tid);
-    tstore<TBN, THREADS, BKC, false>(fb[q], Bs + (b * NP) * SB, tid);
-    if constexpr (SPLIT) {
-      tstore<TBM, THREADS, AK, true>(fa[q], As + (b * NP + 1) * SA, tid);
-      tstore<TBN, THREADS, BKC, true>(fb[q], Bs + (b * NP + 1) * SB, tid);
+    if constexpr (BF) {
+      tstore16<TBM, THREADS>(fa[q], As + b * SA, tid);
+      tstore16<TBN, THREADS>(fb[q], Bs + b * SB, tid);
+    } else {
+      tstore<TBM, THREADS, AK, false>(fa[q], As + (b * NP) * SA, tid);
+      tstore<TBN, THREADS, BKC, false>(fb[q], Bs + (b * NP) * SB, tid);
+      if constexpr (SPLIT) {
+        tstore<TBM, THREADS, AK, true>(fa[q], As + (b * NP + 1) * SA, tid);
+        tstore<TBN, THREADS, BKC, true>(fb[q], Bs + (b * NP + 1) * SB, tid);
+      }
     }
   };
   auto compute = [&](int cur) {
@@ -930,6 +988,46 @@ extern "C" int lv_gemm_split(const float *A, int32_t a_kcont, int64_t lda, const
                              size_t workspace_bytes, void *stream) {
   return gemm_entry(A, a_kcont, lda, B, b_kcont, ldb, C, ldc, M, N, K, alpha, beta, workspace,
                     workspace_bytes, stream, 1);
+}
+
+namespace lv {
+namespace {
+
+int gemm_bf16(const GemmArgs &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return LV_OK;
+  const dim3 gb((unsigned)((g.N + kBigTile - 1) / kBigTile),
+                (unsigned)((g.M + kBigTile - 1) / kBigTile), 1u);
+  const int steps = (g.K + TK - 1) / TK;
+  const bool full = g.M % kBigTile == 0 && g.N % kBigTile == 0 && g.K % TK == 0;
+  const Second none{g, 1, 0, nullptr};
+  if (full)
+    hipLaunchKernelGGL((gemm_tile_kernel<kBigTile, kBigTile, 2, 4, true, true, false, true, true>),
+                       gb, dim3(512), 0, s, g, steps > 0 ? steps : 1, nullptr, none);
+  else
+    hipLaunchKernelGGL((gemm_tile_kernel<kBigTile, kBigTile, 2, 4, true, true, false, false, true>),
+                       gb, dim3(512), 0, s, g, steps > 0 ? steps : 1, nullptr, none);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+}  // namespace
+}  // namespace lv
+
+extern "C" int lv_gemm_bf16(const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb,
+                            float *C, int64_t ldc, int32_t M, int32_t N, int32_t K, float alpha,
+                            float beta, void *stream) {
+  lv::clear_error();
+  if (M < 0 || N < 0 || K < 0) LV_FAIL(LV_EINVAL, "negative size");
+  if ((int64_t)M * N == 0) return LV_OK;
+  if (!C || (K > 0 && (!A || !B))) LV_FAIL(LV_EINVAL, "NULL pointer");
+  if (ldc < N || lda < K || ldb < K) LV_FAIL(LV_EINVAL, "leading dimension too small");
+  if (lda % 8 != 0 || ldb % 8 != 0 || (reinterpret_cast<uintptr_t>(A) & 15u) ||
+      (reinterpret_cast<uintptr_t>(B) & 15u))
+    LV_FAIL(LV_EINVAL, "A and B need 16-byte aligned rows (pointers aligned, lda and ldb "
+                       "multiples of 8)");
+  lv::GemmArgs g{reinterpret_cast<const float *>(A), lda, reinterpret_cast<const float *>(B),
+                 ldb, C, ldc, M, N, K, alpha, beta, 0};
+  return lv::gemm_bf16(g, static_cast<hipStream_t>(stream));
 }
 
 extern "C" size_t lv_gemm_workspace_size(int32_t M, int32_t N) {

@@ -453,6 +453,13 @@ def test_binding_checks_buffer_sizes_before_any_call():
         lv.lv_gemm(z(64), z(64), z(63), 8, 8, 8)
     with pytest.raises(ValueError):   # B read with ldb = 16: (8 - 1) * 16 + 8 elements
         lv.lv_gemm(z(64), z(64), z(64), 8, 8, 8, ldb=16)
+    bf = torch.bfloat16
+    with pytest.raises(TypeError):    # bfloat16 operands only
+        lv.lv_gemm_bf16(z(64), z(64, dt=bf), z(64), 8, 8, 8)
+    with pytest.raises(ValueError):   # A [8][8] needs 64 elements
+        lv.lv_gemm_bf16(z(63, dt=bf), z(64, dt=bf), z(64), 8, 8, 8)
+    with pytest.raises(ValueError):   # C [8][8] needs 64 elements
+        lv.lv_gemm_bf16(z(64, dt=bf), z(64, dt=bf), z(63), 8, 8, 8)
     Dr, dr, bq, bx = 16, 4, 5, 7
     pws = z(lv.lv_projloss_workspace_size(bq, bx, Dr, dr), dt=u8)
     A, B, Qb, Xb = z(dr, Dr), z(dr, Dr), z(bq, Dr), z(bx, Dr)

@@ -125,6 +125,40 @@ def test_gemm_split_precision_is_exact_on_wide_integers(lv, M, N, K, wide, ak, b
     assert not np.array_equal(P.cpu().numpy().astype(np.float64), a @ b.T)
 
 
+# bfloat16 operands in memory: whole 256 x 256 tiles, ragged m, n and k edges
+# (element-wise edge loads), a row stride past K, exact on small integers
+@pytest.mark.parametrize("M,N,K,ld", [(512, 768, 256, None), (300, 520, 100, 104),
+                                      (1, 7, 5, 8), (257, 255, 33, 48), (1024, 1024, 1024, None)])
+def test_gemm_bf16_exact_on_small_integers(lv, M, N, K, ld):
+    rng = np.random.default_rng(M + 3 * N + 7 * K)
+    lda = ldb = ld if ld is not None else K
+    a = rng.integers(-8, 9, size=(M, K)).astype(np.float32)
+    b = rng.integers(-8, 9, size=(N, K)).astype(np.float32)
+    c0 = rng.integers(-3, 4, size=(M, N)).astype(np.float32)
+    A = torch.zeros((M, lda), dtype=torch.bfloat16, device=DEV)
+    B = torch.zeros((N, ldb), dtype=torch.bfloat16, device=DEV)
+    A[:, :K] = t(a).to(torch.bfloat16)
+    B[:, :K] = t(b).to(torch.bfloat16)
+    if lda > K:  # values past K in a row must not enter the product
+        A[:, K:] = 1e4
+        B[:, K:] = -1e4
+    C = t(c0)
+    lv.lv_gemm_bf16(A, B, C, M, N, K, lda=lda, ldb=ldb, alpha=2.0, beta=-1.0)
+    torch.cuda.synchronize()
+    want = 2.0 * a.astype(np.float64) @ b.astype(np.float64).T - c0
+    assert np.array_equal(C.cpu().numpy().astype(np.float64), want)
+
+
+def test_gemm_bf16_rejects_unaligned_rows(lv):
+    A = torch.zeros((16, 12), dtype=torch.bfloat16, device=DEV)
+    B = torch.zeros((16, 16), dtype=torch.bfloat16, device=DEV)
+    C = torch.zeros((16, 16), device=DEV)
+    with pytest.raises(lv.LVError):  # lda = 12 is not a multiple of 8
+        lv.lv_gemm_bf16(A, B, C, 16, 16, 12, lda=12, ldb=16)
+    with pytest.raises(lv.LVError):  # A one element past an aligned start
+        lv.lv_gemm_bf16(A.view(-1)[1:], B, C, 15, 16, 8, lda=8, ldb=16)
+
+
 @pytest.fixture(scope="module")
 def block():
     wl = gen.WORKLOADS["ood-1m-768"].scaled(N=8192, m_test=2048)
