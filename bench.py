@@ -1519,9 +1519,16 @@ def cpu_model_name():
     try:
         out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
                              text=True, timeout=20).stdout
+        f = {}
         for line in out.splitlines():
-            if line.strip().startswith("Model name:"):
-                return line.split(":", 1)[1].strip()
+            k, _, v = line.partition(":")
+            f.setdefault(k.strip(), v.strip())
+        if f.get("Model name"):
+            # the name a virtual machine reports can be short ("AMD EPYC"): the
+            # family, model and stepping numbers identify the part
+            ids = ", ".join(f"{k.lower()} {f[k]}" for k in ("CPU family", "Model", "Stepping")
+                            if f.get(k))
+            return f["Model name"] + (f" ({ids})" if ids else "")
     except (OSError, subprocess.SubprocessError):
         pass
     try:
