@@ -724,7 +724,7 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on exactly one GPU; "
                                    "--gpus %d is not supported (query or database sharding "
-                                   "across GPUs is described in DESIGN.md, not built)" % args.gpus}))
+                                   "across GPUs is a design only, not built)" % args.gpus}))
         sys.exit(2)
     import torch
 
