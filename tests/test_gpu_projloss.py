@@ -149,6 +149,26 @@ def test_gemm_bf16_exact_on_small_integers(lv, M, N, K, ld):
     assert np.array_equal(C.cpu().numpy().astype(np.float64), want)
 
 
+@pytest.mark.parametrize("M,N,K", [(4096, 2048, 256), (3000, 2900, 70)])
+def test_gemm_bf16_equals_float32_operands_bit_for_bit(lv, M, N, K):
+    """Products with at least 128 tiles of 256 x 256 take the large-tile kernel
+    in both entry points: on values that bfloat16 holds exactly, the float32
+    operands round to the same bfloat16 and each output gets the same MFMA
+    sequence, so lv_gemm_bf16 must equal lv_gemm bit for bit (random values,
+    not integers: any staging or layout slip changes the sums)."""
+    g = torch.Generator(device=DEV)
+    g.manual_seed(M + N + K)
+    lda = ldb = (K + 7) // 8 * 8
+    Ab = torch.randn((M, lda), device=DEV, generator=g).to(torch.bfloat16)
+    Bb = torch.randn((N, ldb), device=DEV, generator=g).to(torch.bfloat16)
+    C16 = torch.empty((M, N), device=DEV)
+    C32 = torch.empty((M, N), device=DEV)
+    lv.lv_gemm_bf16(Ab, Bb, C16, M, N, K, lda=lda, ldb=ldb)
+    lv.lv_gemm(Ab.float(), Bb.float(), C32, M, N, K, lda=lda, ldb=ldb)
+    torch.cuda.synchronize()
+    assert torch.equal(C16, C32)
+
+
 def test_gemm_bf16_rejects_unaligned_rows(lv):
     A = torch.zeros((16, 12), dtype=torch.bfloat16, device=DEV)
     B = torch.zeros((16, 16), dtype=torch.bfloat16, device=DEV)
