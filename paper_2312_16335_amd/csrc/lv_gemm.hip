@@ -8,12 +8,16 @@
 // vector loads.  Tile 128 x 128 per 256-thread workgroup, each wavefront a
 // 64 x 64 quadrant (2 x 2 tiles of 32 x 32x16 MFMAs), two LDS buffers.
 //
-// Two kernels: when both operands allow 16-byte loads (aligned pointers,
+// Kernels: when both operands allow 16-byte loads (aligned pointers,
 // leading dimensions multiples of 4 floats), gemm_vec_kernel walks K in
 // steps of 64 and keeps the next tile's float32 operands in registers while
 // the current tile is multiplied (one barrier per step), with float4 loads
-// for both operand layouts; otherwise gemm_kernel stages element by element
-// in steps of 32.
+// for both operand layouts; gemm_tile_kernel (below) takes large products on
+// 256 x 256 tiles and the split-precision ones; otherwise gemm_kernel stages
+// element by element in steps of 32.  The vector and tile kernels also serve
+// two independent products in one launch (gemm_pair), the split-precision
+// tile kernel a second K segment (C = A B^T + A2 B2^T), and the large tile
+// operands already held as bfloat16 (lv_gemm_bf16).
 //
 // Split precision (GemmArgs::split): each float32 operand x is written as
 // hi + lo with hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in
@@ -377,9 +381,9 @@ __global__ __launch_bounds__(256) void gemm_vec_kernel(GemmArgs g0, int sps0, fl
 
 // ---- tiled kernel: TBM x TBN output tile per workgroup of WM x WN
 // wavefronts (each a (TBM / WM) x (TBN / WN) block of 32 x 32 MFMA tiles),
-// K steps of TK, two LDS buffers and one barrier per step, and the float32
-// operands of the next two steps in flight in registers while the current
-// step's products run.  Whole tiles (FULL: M, N multiples of the tile and K
+// K steps of TK, two LDS buffers and one barrier per step, and the operands
+// of the next two steps in flight in registers (float32, or bfloat16 with
+// BF) while the current step's products run.  Whole tiles (FULL: M, N multiples of the tile and K
 // of TK) load with plain 16-byte loads and no edge tests.
 // SPLIT: both parts of every operand (hi, lo) are staged in the same step
 // and each fragment pair takes the three products hi*hi, hi*lo, lo*hi, so

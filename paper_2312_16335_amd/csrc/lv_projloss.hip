@@ -15,9 +15,13 @@
 //   dA = -(2/P) (Rm H)^T Qb + 2 lam ((B K_X B^T) A - B K_X) K_Q
 //   dB = -(2/P) (Rm^T G)^T Xb + 2 lam ((A K_Q A^T) B - A K_Q) K_X
 //
-// Every product is one launch of the bfloat16 matrix-core GEMM (float32
-// accumulation).  A difference of two products is one launch over two K
-// segments, with one factor kept negated in the workspace: Rm is
+// Products run on the bfloat16 matrix-core GEMM (float32 accumulation);
+// two independent products of the same operand layouts share one launch
+// (gemm_pair), and the trace term's products (forward) and the trace
+// gradients and S (backward) run on a second stream of the library's, forked
+// from the caller's stream and joined back with events.  A difference of two
+// products is one launch over two K segments, with one factor kept negated
+// in the workspace: Rm is
 // [Qb | G] [Xb | -H]^T (K = D + d), and the trace gradients, written with
 // U1 = B K_X and U2 = A K_Q as 2 lam (M2 U2 - U1 K_Q) and
 // 2 lam (M1 U1 - U2 K_X), are -2 lam [-M2 | U1] [U2 ; K_Q] (K = d + D) and
