@@ -621,6 +621,16 @@ def mfma_report(lv, torch, reps=10):
     trace = 2.0 * (2 * d2 * D2 * D2 + 2 * d2 * d2 * D2) * 2
     out["refinement_step"] = dict(b_q=bq, b_x=bx, D=D2, d=d2,
                                   **entry(timed(step), pair_f + pair_b + trace))
+    # the same step captured once in a HIP graph (its second stream included)
+    # and replayed: the host's launch work leaves the loop
+    gstream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gstream):
+        step()
+    torch.cuda.synchronize()
+    out["refinement_step_graph"] = dict(b_q=bq, b_x=bx, D=D2, d=d2,
+                                        **entry(timed(graph.replay), pair_f + pair_b + trace))
+    del graph
     # the float64 oracle beside them (host cores): projection + LVQ-8 encoding of
     # a 20,000-row sample, and one refinement step (loss and gradients)
     from oracle import fit as ofit

@@ -344,6 +344,42 @@ def test_projloss_on_a_caller_stream_is_bit_identical(lv, block):
         assert np.array_equal(g, r)
 
 
+def test_projloss_graph_replays_are_bit_identical(lv, block):
+    """The forward and backward captured in one HIP graph (the library's
+    second stream joins the capture through its events) and replayed three
+    times, with eager work and synchronisations between the replays and the
+    outputs cleared before each: every replay equals the eager results."""
+    A, B, Qb, Xb, KQ, KX = block
+    d, D = A.shape
+    tc = float(np.trace(KQ @ KX))
+    ws = torch.empty(lv.lv_projloss_workspace_size(len(Qb), len(Xb), D, d), dtype=torch.uint8,
+                     device=DEV)
+    loss = torch.empty(3, device=DEV)
+    dA, dB = torch.empty((d, D), device=DEV), torch.empty((d, D), device=DEV)
+    At, Bt, Qt, Xt, KQt, KXt = (t(v) for v in (A, B, Qb, Xb, KQ, KX))
+
+    def step():
+        lv.lv_projloss_fwd(At, Bt, Qt, Xt, loss, ws, KQt, KXt, tc, 1.0)
+        lv.lv_projloss_bwd(At, Bt, Qt, Xt, dA, dB, ws, KQt, KXt, 1.0, 1.0)
+
+    step()  # eager (also creates the second stream outside the capture)
+    torch.cuda.synchronize()
+    ref = (loss.clone(), dA.clone(), dB.clone())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=torch.cuda.Stream()):
+        step()
+    torch.cuda.synchronize()
+    for i in range(3):
+        loss.fill_(float("nan"))
+        dA.fill_(float("nan"))
+        dB.fill_(float("nan"))
+        x = torch.randn((512, 512), device=DEV)
+        (x @ x).sum().item()  # eager work between the replays
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(loss, ref[0]) and torch.equal(dA, ref[1]) and torch.equal(dB, ref[2]), i
+
+
 def test_autograd_function_matches_kernels(lv, block):
     from paper_2312_16335_amd.autograd import ProjLoss
 
